@@ -1,0 +1,104 @@
+"""Seeded synthetic workloads shaped like the laser-electron collisions of arXiv 2511.08929.
+
+This module only draws initial particle states and states field / step parameters.  It
+holds none of the QED method's arithmetic, and it is shared by the oracle tests, the GPU
+parity tests and the benchmark.  All randomness comes from ``numpy.random.Generator``
+(PCG64) seeded per workload.
+
+Units: time in 1/omega_r, length in c/omega_r, momentum in m c, fields in m c omega_r / e,
+with omega_r the angular frequency of a lambda = 0.8 um laser.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+
+# physical constants (CODATA 2018)
+HC_EV_NM = 1239.841984332
+MEC2_EV = 510998.95
+C_LIGHT = 299792458.0
+LAMBDA_UM = 0.8
+EPS_R = HC_EV_NM / (LAMBDA_UM * 1000.0) / MEC2_EV      # hbar omega_r / (m c^2)
+OMEGA_R = 2.0 * math.pi * C_LIGHT / (LAMBDA_UM * 1e-6)  # rad/s
+
+FIELD_UNIFORM, FIELD_PLANE_LP = 0, 1
+
+
+@dataclass
+class Workload:
+    name: str
+    n: int                      # primary electrons
+    steps: int
+    dt: float
+    seed: int
+    field_kind: int
+    E0: tuple = (0.0, 0.0, 0.0)
+    B0: tuple = (0.0, 0.0, 0.0)
+    a0: float = 0.0
+    phase_len: float = 0.0
+    track: tuple = (True, True, True)   # which position components matter
+    pair: bool = False
+    k_retire: float = 0.0               # photon energy (m c^2) below which chi_gamma < chi_min always
+    x: np.ndarray = field(default=None, repr=False)
+    p: np.ndarray = field(default=None, repr=False)
+    s: np.ndarray = field(default=None, repr=False)
+    extra: dict = field(default_factory=dict)
+
+
+def c1(n: int = 10_000, seed: int = 1, steps: int = 1000) -> Workload:
+    """Test-particle case: gamma0 = 2000 along +x, spins +y, uniform B_z with chi_e = 1,
+    no E, dt = 1/100 of the relativistic gyro period, no pair production."""
+    gamma0 = 2000.0
+    pmag = math.sqrt(gamma0 * gamma0 - 1.0)
+    Bz = 1.0 / (EPS_R * pmag)                 # chi_e = eps_r |p x B| = 1
+    period = 2.0 * math.pi * gamma0 / Bz      # omega_c = B / gamma in these units
+    x = np.zeros((3, n))
+    p = np.zeros((3, n)); p[0] = pmag
+    s = np.zeros((3, n)); s[1] = 1.0
+    return Workload("c1_test_particle_uniform_B", n, steps, 0.01 * period, seed, FIELD_UNIFORM,
+                    B0=(0.0, 0.0, Bz), track=(False, False, False), pair=False, k_retire=0.0,
+                    x=x, p=p, s=s, extra=dict(gamma0=gamma0, Bz=Bz, gyro_period=period))
+
+
+def sin2_phase_len(fwhm_fs: float) -> float:
+    """Total length (in laser phase) of a sin^2 field envelope whose intensity FWHM is fwhm_fs."""
+    th = math.asin(2.0 ** -0.25)               # sin^4 = 1/2
+    return OMEGA_R * fwhm_fs * 1e-15 / (1.0 - 2.0 * th / math.pi)
+
+
+def c2(n: int = 1_000_000, seed: int = 2, steps: int = 3000, a0: float = 100.0,
+       gamma_mean: float = 4000.0, gamma_spread: float = 0.05) -> Workload:
+    """Head-on collision: gamma0 ~ N(4000, 5 %), 1 mrad Gaussian angular spread, spins +/-y
+    with equal probability, LP plane wave along -x with a0 = 100, sin^2 envelope of 30 fs
+    intensity FWHM, dt = lambda/(100 c), 3000 steps, both QED channels on."""
+    rng = np.random.default_rng(seed)
+    gam = rng.normal(gamma_mean, gamma_spread * gamma_mean, n)
+    gam = np.maximum(gam, 2.0)
+    ty = rng.normal(0.0, 1e-3, n)
+    tz = rng.normal(0.0, 1e-3, n)
+    d = np.stack([np.ones(n), ty, tz])
+    d /= np.linalg.norm(d, axis=0)
+    p = d * np.sqrt(gam * gam - 1.0)
+    sgn = np.where(rng.random(n) < 0.5, 1.0, -1.0)
+    s = np.zeros((3, n)); s[1] = sgn
+    x = np.zeros((3, n)); x[0] = rng.uniform(-2.0 * math.pi, 0.0, n)
+    chi_g_min = 0.05
+    return Workload("c2_head_on_lp_a0_100", n, steps, 2.0 * math.pi / 100.0, seed, FIELD_PLANE_LP,
+                    a0=a0, phase_len=sin2_phase_len(30.0), track=(True, False, False), pair=True,
+                    k_retire=chi_g_min / (2.0 * a0 * EPS_R), x=x, p=p, s=s)
+
+
+def subsample(w: Workload, idx) -> Workload:
+    """The same workload restricted to the given primary-electron indices (for oracle samples)."""
+    import copy
+    v = copy.copy(w)
+    v.x, v.p, v.s = w.x[:, idx].copy(), w.p[:, idx].copy(), w.s[:, idx].copy()
+    v.n = v.p.shape[1]
+    return v
+
+
+def random_unit_vectors(rng, n):
+    v = rng.normal(size=(3, n))
+    return v / np.linalg.norm(v, axis=0)
