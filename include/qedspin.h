@@ -1,0 +1,199 @@
+/*
+ * qedspin.h -- C ABI of the MI355X (gfx950) implementation of the spin- and
+ * polarization-resolved strong-field QED particle step of Qian, Seipt, Vranic,
+ * Grismayer, Ridgers and Thomas, "A Fully Spin and Polarization Resolved Strong Field
+ * QED Algorithm for Particle-in-Cell Codes" (arXiv 2511.08929).
+ *
+ * The step, per electron or positron (NLC section and its flow chart): Lorentz push and
+ * T-BMT spin rotation; chi_e and the rest-frame basis (eps, beta, k) (basis section);
+ * the spin-weighted emission rate from the spin-up / spin-down rate tables; a
+ * Philox4x32-10 draw against W dt; on emission the photon energy from the spin-up or
+ * spin-down inverse CDF, recoil, collapse of the lepton spin onto its quantization axis
+ * and of the photon Stokes vector onto its polarization axis, stored as a P-vector
+ * (photon-polarization section); without emission the no-transition spin update
+ * (non-transition section).  Per photon (NBW section): ballistic move, chi_gamma, the
+ * Stokes vector decoded from the P-vector in the local basis, the xi3-weighted pair rate,
+ * the pair's momentum split, correlated electron / positron spins, or the no-pair
+ * polarization update.
+ *
+ * Units: time in 1/omega_r, length in c/omega_r, momenta in m c, fields in
+ * m c omega_r / e; eps_r = hbar omega_r / (m c^2).  Spin and P-vectors are lab-frame
+ * 3-vectors.
+ *
+ * Conventions that hold for every entry point:
+ *  - All particle pointers are DEVICE pointers owned by the caller; arrays are SoA, one
+ *    array per component, element type double (QED_F64 tables) or float (QED_F32 tables).
+ *  - Counts live on the device (int64).  Kernels process [0, *d_count) and append at
+ *    *d_count; appends never write at or beyond `capacity`: the excess is dropped and
+ *    counted in qed_counters.n_capacity_overflow.
+ *  - Calls only enqueue work on the given stream and return; the status reports host-side
+ *    argument checks and launch errors.  Device-side conditions go to qed_counters
+ *    (device memory, caller-owned, accumulated, never reset by the library).
+ *  - No call allocates device memory except qed_init_tables; scratch memory is the
+ *    caller-provided workspace of at least qed_workspace_size() bytes.
+ *  - Appends are order-preserving: new photons in increasing emitter index, new pairs in
+ *    increasing photon index, so results are bitwise reproducible run to run.
+ *  - Random numbers: Philox4x32-10 keyed by the 64-bit seed, counter
+ *    (id low, id high, step, channel).  Lepton id = (species << 62) | index; photon id =
+ *    2^63 | (parent species << 61) | ((parent index mod 2^37) << 24) | (step mod 2^24).
+ */
+#ifndef QEDSPIN_H
+#define QEDSPIN_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ihipStream_t *qed_stream;   /* a hipStream_t (NULL = default stream) */
+
+typedef enum {
+    QED_OK = 0,
+    QED_ERR_INVALID = -1,     /* bad argument (NULL pointer, size, precision mismatch ...) */
+    QED_ERR_HIP = -2,         /* a HIP runtime call or kernel launch failed */
+    QED_ERR_CAPACITY = -3,    /* workspace too small */
+    QED_ERR_UNSUPPORTED = -4  /* unknown field model or flag combination */
+} qed_status;
+
+typedef enum { QED_F64 = 0, QED_F32 = 1 } qed_precision;
+
+/* Physics switches (the paper's per-effect toggles used in its verification runs). */
+enum {
+    QED_PUSH = 1u << 0,        /* Lorentz (Boris) push inside qed_emit before the QED step */
+    QED_TBMT = 1u << 1,        /* T-BMT spin rotation in the push */
+    QED_EMIT = 1u << 2,        /* nonlinear Compton emission */
+    QED_RECOIL = 1u << 3,      /* p <- (1 - lambda) p on emission */
+    QED_SPIN = 1u << 4,        /* lepton spin collapse on emission */
+    QED_NOEMIT = 1u << 5,      /* no-transition spin update of non-emitters */
+    QED_PHOTON_POL = 1u << 6,  /* photon Stokes collapse (else unpolarized photons) */
+    QED_MEAN = 1u << 7,        /* mean-value mode: s_f = g/w, xi = F(s_f=0)/w, pair spins j/w0 */
+    QED_PAIR = 1u << 8,        /* nonlinear Breit-Wheeler pair creation */
+    QED_NOPAIR = 1u << 9,      /* no-transition polarization update of surviving photons */
+    QED_PAIR_SPIN = 1u << 10   /* correlated pair spins (else unpolarized pairs) */
+};
+
+/* Field models evaluated at each particle. */
+enum {
+    QED_FIELD_UNIFORM = 0,     /* E = E0, B = B0 */
+    QED_FIELD_PLANE_LP = 1     /* E0, B0 plus a linearly polarized wave along -x:
+                                  E_y = a0 g(phi) cos(phi), B_z = -E_y, phi = t + x,
+                                  g = sin^2(pi phi / phase_len) on [0, phase_len] (1 if phase_len = 0) */
+};
+
+/* Rate / inverse-CDF table grid: nodes uniform in ln chi and in rho = ln(r/(1-r)).
+   Index 0 = nonlinear Compton (chi_e), 1 = Breit-Wheeler (chi_gamma). */
+typedef struct {
+    int    n_chi[2];
+    double lnchi0[2];
+    double dlnchi[2];
+    int    n_rho;
+    double rho0, drho;
+} qed_table_grid;
+
+typedef struct {
+    qed_table_grid grid;
+    qed_precision  precision;   /* element type of every particle array used with these tables */
+} qed_table_params;
+
+typedef struct qed_tables_s *qed_tables;   /* opaque, library-owned device tables */
+
+typedef struct {
+    int64_t  capacity;          /* elements allocated in every array */
+    int64_t *d_count;           /* device: live leptons; appends go here */
+    int      species;           /* 0 = electron (charge -1), 1 = positron (+1) */
+    void    *x[3];              /* position components; x[i] may be NULL if the field model
+                                   does not depend on coordinate i (then it is not advanced) */
+    void    *p[3];              /* momentum / (m c) */
+    void    *s[3];              /* spin vector, |s| <= 1 */
+} qed_leptons;
+
+typedef struct {
+    int64_t   capacity;
+    int64_t  *d_count;          /* device: photons stored (dead slots included) */
+    int64_t  *d_count_prev;     /* device: photons that qed_pair steps; qed_pair sets it to
+                                   *d_count when it finishes, so photons born later in the same
+                                   step wait for the next one */
+    void     *x[3];             /* may be NULL as for leptons */
+    void     *k[3];             /* momentum hbar k / (m c) */
+    void     *P[3];             /* P-vector (photon-polarization section) */
+    uint64_t *id;               /* 0 marks a dead slot (decayed, retired or never stored) */
+} qed_photons;
+
+typedef struct {
+    int    kind;
+    double E0[3], B0[3];
+    double a0, phase_len;
+} qed_fields;
+
+typedef struct {
+    double   t;                 /* time at the start of the step */
+    double   dt;
+    double   a_e;               /* anomalous magnetic moment in T-BMT */
+    double   eps_r;
+    double   chi_e_min, chi_e_max;  /* no QED below min; lookups clamped above max */
+    double   chi_g_min, chi_g_max;
+    double   k_retire;          /* photons with |k| below this are stored as dead slots / retired */
+    int64_t  step;              /* Philox counter word */
+    uint64_t seed;              /* Philox key */
+    uint32_t flags;
+} qed_step_params;
+
+typedef struct {                /* device-resident, accumulated */
+    unsigned long long n_emit, n_pair, n_prob_clamped, n_chi_clamped, n_norm_clamped,
+                       n_capacity_overflow, n_retired, n_pad;
+} qed_counters;
+
+/* Build the rate tables ln int_0^1 w dlam (spin-down, spin-up; xi3 = -1, +1) and inverse-CDF
+   tables nu = ln(lam/(1-lam)) at rho = ln(r/(1-r)) on the given grid, by quadrature on the GPU
+   (NLC section: rate and ICDF tabulated only for s_beta = -1, +1; NBW section: only for
+   xi3 = -1, +1).  Allocates device memory; synchronizes the stream.  Returns QED_ERR_INVALID
+   for a NULL pointer or a grid with fewer than 4 nodes per axis. */
+qed_status qed_init_tables(const qed_table_params *params, qed_stream stream, qed_tables *out);
+
+/* Release the tables (device memory).  Safe on NULL. */
+qed_status qed_free_tables(qed_tables tables);
+
+/* Copy the FP64 tables to host memory (layout [4 channels][n_chi][...], channels NLC-down,
+   NLC-up, NBW-minus, NBW-plus).  Sizes in elements are returned when the pointers are NULL. */
+qed_status qed_tables_download(qed_tables tables, double *lnrate, int64_t *n_lnrate,
+                               double *nu, int64_t *n_nu);
+
+/* Bytes of workspace qed_emit / qed_pair / qed_compact need for sets of up to
+   max_particles elements (leptons or photons, whichever is larger). */
+size_t qed_workspace_size(int64_t max_particles);
+
+/* Lorentz (Boris) push with fields at (x, t), T-BMT rotation (if QED_TBMT), then
+   x += v dt, for leptons [0, *d_count).  In place. */
+qed_status qed_push_spin(const qed_leptons *leptons, const qed_fields *fields,
+                         const qed_step_params *params, qed_tables tables, qed_stream stream);
+
+/* NLC step for leptons [0, *d_count): with QED_PUSH, first the push of qed_push_spin with
+   fields at t; then QED with fields at t + dt.  Emitted photons are appended to `photons`
+   (dead slots, id = 0, for photons below k_retire).  In place on the leptons. */
+qed_status qed_emit(qed_tables tables, const qed_leptons *leptons, const qed_fields *fields,
+                    const qed_step_params *params, const qed_photons *photons,
+                    qed_counters *d_counters, void *workspace, size_t workspace_bytes,
+                    qed_stream stream);
+
+/* NBW step for photons [0, *d_count_prev): x += khat dt, fields at t + dt; pairs appended to
+   `electrons` and `positrons` (same index in both for one pair); decayed photons become dead
+   slots; survivors get the no-pair update.  Photons below k_retire are retired (dead slot).
+   Sets *d_count_prev = *d_count on completion. */
+qed_status qed_pair(qed_tables tables, const qed_photons *photons, const qed_fields *fields,
+                    const qed_step_params *params, const qed_leptons *electrons,
+                    const qed_leptons *positrons, qed_counters *d_counters, void *workspace,
+                    size_t workspace_bytes, qed_stream stream);
+
+/* Order-preserving removal of dead photon slots (id == 0); updates *d_count and
+   *d_count_prev.  The workspace must hold qed_workspace_size(capacity) bytes plus one photon
+   record per slot: see qed_compact_workspace_size. */
+size_t qed_compact_workspace_size(const qed_photons *photons, qed_precision precision);
+qed_status qed_compact(const qed_photons *photons, qed_precision precision, void *workspace,
+                       size_t workspace_bytes, qed_stream stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

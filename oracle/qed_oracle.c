@@ -883,6 +883,7 @@ int orc_photon_qed_one(const orc_tables *T, const orc_params *prm, uint64_t id,
 {
     uint32_t fl = prm->flags;
     int near = 0;
+    if (!(fl & ORC_F_PAIR)) return 0;
     double eh[3], bh[3], kh[3];
     double chi = orc_basis(0, prm->eps_r, E, B, k, eh, bh, kh);
     if (!(chi >= prm->chi_g_min)) return 0;

@@ -1,0 +1,309 @@
+"""MI355X (gfx950) spin- and polarization-resolved strong-field QED particle step.
+
+Thin Python binding of the C ABI in ``include/qedspin.h`` (``libqedspin.so``): argument
+marshalling only.  Every step of the method runs in the HIP kernels of ``csrc/``; PyTorch
+provides device memory and streams.  The product path has no CPU fallback: if the library
+is not built, or no GPU is present, calls raise.
+
+Names follow the C ABI: qed_init_tables, qed_free_tables, qed_tables_download,
+qed_workspace_size, qed_push_spin, qed_emit, qed_pair, qed_compact_workspace_size,
+qed_compact.  ``LeptonBuffers`` / ``PhotonBuffers`` hold SoA torch tensors and build the
+ABI views; ``sim.Simulation`` strings the calls into time steps.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import math
+from pathlib import Path
+
+PKG = Path(__file__).resolve().parent
+LIB_PATH = PKG / "libqedspin.so"
+
+ALPHA = 7.2973525693e-3
+
+QED_OK, QED_ERR_INVALID, QED_ERR_HIP, QED_ERR_CAPACITY, QED_ERR_UNSUPPORTED = 0, -1, -2, -3, -4
+QED_F64, QED_F32 = 0, 1
+QED_PUSH, QED_TBMT, QED_EMIT, QED_RECOIL = 1 << 0, 1 << 1, 1 << 2, 1 << 3
+QED_SPIN, QED_NOEMIT, QED_PHOTON_POL, QED_MEAN = 1 << 4, 1 << 5, 1 << 6, 1 << 7
+QED_PAIR, QED_NOPAIR, QED_PAIR_SPIN = 1 << 8, 1 << 9, 1 << 10
+QED_ALL = (QED_PUSH | QED_TBMT | QED_EMIT | QED_RECOIL | QED_SPIN | QED_NOEMIT | QED_PHOTON_POL
+           | QED_PAIR | QED_NOPAIR | QED_PAIR_SPIN)
+QED_FIELD_UNIFORM, QED_FIELD_PLANE_LP = 0, 1
+
+ABI_SYMBOLS = ("qed_init_tables", "qed_free_tables", "qed_tables_download", "qed_workspace_size",
+               "qed_push_spin", "qed_emit", "qed_pair", "qed_compact_workspace_size", "qed_compact")
+
+
+class QedError(RuntimeError):
+    pass
+
+
+# ------------------------------------------------------------------ ABI structs
+class TableGrid(C.Structure):
+    _fields_ = [("n_chi", C.c_int * 2), ("lnchi0", C.c_double * 2), ("dlnchi", C.c_double * 2),
+                ("n_rho", C.c_int), ("rho0", C.c_double), ("drho", C.c_double)]
+
+
+class TableParams(C.Structure):
+    _fields_ = [("grid", TableGrid), ("precision", C.c_int)]
+
+
+class Leptons(C.Structure):
+    _fields_ = [("capacity", C.c_int64), ("d_count", C.c_void_p), ("species", C.c_int),
+                ("x", C.c_void_p * 3), ("p", C.c_void_p * 3), ("s", C.c_void_p * 3)]
+
+
+class Photons(C.Structure):
+    _fields_ = [("capacity", C.c_int64), ("d_count", C.c_void_p), ("d_count_prev", C.c_void_p),
+                ("x", C.c_void_p * 3), ("k", C.c_void_p * 3), ("P", C.c_void_p * 3), ("id", C.c_void_p)]
+
+
+class Fields(C.Structure):
+    _fields_ = [("kind", C.c_int), ("E0", C.c_double * 3), ("B0", C.c_double * 3),
+                ("a0", C.c_double), ("phase_len", C.c_double)]
+
+
+class StepParams(C.Structure):
+    _fields_ = [("t", C.c_double), ("dt", C.c_double), ("a_e", C.c_double), ("eps_r", C.c_double),
+                ("chi_e_min", C.c_double), ("chi_e_max", C.c_double), ("chi_g_min", C.c_double),
+                ("chi_g_max", C.c_double), ("k_retire", C.c_double), ("step", C.c_int64),
+                ("seed", C.c_uint64), ("flags", C.c_uint32)]
+
+
+COUNTER_NAMES = ("n_emit", "n_pair", "n_prob_clamped", "n_chi_clamped", "n_norm_clamped",
+                 "n_capacity_overflow", "n_retired", "n_pad")
+
+_lib = None
+
+
+def lib():
+    """Load libqedspin.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not LIB_PATH.exists():
+            raise QedError(f"{LIB_PATH} is missing: build it with paper_2511_08929_amd/build.py "
+                           "(there is no CPU fallback)")
+        L = C.CDLL(str(LIB_PATH))
+        P, vp, i64, sz = C.POINTER, C.c_void_p, C.c_int64, C.c_size_t
+        L.qed_init_tables.argtypes = [P(TableParams), vp, P(vp)]
+        L.qed_free_tables.argtypes = [vp]
+        L.qed_tables_download.argtypes = [vp, vp, P(i64), vp, P(i64)]
+        L.qed_workspace_size.argtypes = [i64]; L.qed_workspace_size.restype = sz
+        L.qed_push_spin.argtypes = [P(Leptons), P(Fields), P(StepParams), vp, vp]
+        L.qed_emit.argtypes = [vp, P(Leptons), P(Fields), P(StepParams), P(Photons), vp, vp, sz, vp]
+        L.qed_pair.argtypes = [vp, P(Photons), P(Fields), P(StepParams), P(Leptons), P(Leptons), vp, vp, sz, vp]
+        L.qed_compact_workspace_size.argtypes = [P(Photons), C.c_int]; L.qed_compact_workspace_size.restype = sz
+        L.qed_compact.argtypes = [P(Photons), C.c_int, vp, sz, vp]
+        for name in ABI_SYMBOLS:
+            if name not in ("qed_workspace_size", "qed_compact_workspace_size"):
+                getattr(L, name).restype = C.c_int
+        _lib = L
+    return _lib
+
+
+def _check(status, what):
+    if status != QED_OK:
+        raise QedError(f"{what} failed with status {status}")
+
+
+def _stream_ptr(stream=None):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr()) if t is not None else C.c_void_p(0)
+
+
+# ------------------------------------------------------------------ table grid
+def contract_grid(n_chi_per_decade=32, n_rho=256, rho_max=37.5, nlc_range=(1e-3, 1e2),
+                  nbw_chi_min=0.05, nbw_decades=3.3125):
+    """The table grid of the method contract: nodes uniform in ln chi and in rho = logit r."""
+    h = math.log(10.0) / n_chi_per_decade
+    n_nlc = int(round(math.log(nlc_range[1] / nlc_range[0]) / h)) + 1
+    n_nbw = int(round(nbw_decades * n_chi_per_decade)) + 1
+    return dict(n_chi=(n_nlc, n_nbw), lnchi0=(math.log(nlc_range[0]), math.log(nbw_chi_min)),
+                dlnchi=(h, h), n_rho=n_rho, rho0=-rho_max, drho=2.0 * rho_max / (n_rho - 1))
+
+
+# ------------------------------------------------------------------ ABI wrappers
+class Tables:
+    """Owner of a qed_tables handle (qed_init_tables / qed_free_tables)."""
+
+    def __init__(self, grid=None, precision=QED_F64, stream=None):
+        g = grid or contract_grid()
+        p = TableParams()
+        p.grid.n_chi[0], p.grid.n_chi[1] = g["n_chi"]
+        p.grid.lnchi0[0], p.grid.lnchi0[1] = g["lnchi0"]
+        p.grid.dlnchi[0], p.grid.dlnchi[1] = g["dlnchi"]
+        p.grid.n_rho, p.grid.rho0, p.grid.drho = g["n_rho"], g["rho0"], g["drho"]
+        p.precision = precision
+        self.grid, self.precision = g, precision
+        h = C.c_void_p()
+        _check(lib().qed_init_tables(C.byref(p), _stream_ptr(stream), C.byref(h)), "qed_init_tables")
+        self.handle = h
+
+    def download(self):
+        import numpy as np
+        nr, nv = C.c_int64(), C.c_int64()
+        _check(lib().qed_tables_download(self.handle, None, C.byref(nr), None, C.byref(nv)), "qed_tables_download")
+        lnrate, nu = np.zeros(nr.value), np.zeros(nv.value)
+        _check(lib().qed_tables_download(self.handle, lnrate.ctypes.data, None, nu.ctypes.data, None),
+               "qed_tables_download")
+        return lnrate, nu
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().qed_free_tables(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def qed_workspace_size(max_particles):
+    return int(lib().qed_workspace_size(int(max_particles)))
+
+
+class LeptonBuffers:
+    """Device SoA storage for one lepton species (torch tensors) and its ABI view."""
+
+    def __init__(self, species, capacity, dtype, device="cuda", track=(True, True, True)):
+        import torch
+        self.species, self.capacity, self.dtype = species, int(capacity), dtype
+        self.x = [torch.zeros(capacity, dtype=dtype, device=device) if t else None for t in track]
+        self.p = [torch.zeros(capacity, dtype=dtype, device=device) for _ in range(3)]
+        self.s = [torch.zeros(capacity, dtype=dtype, device=device) for _ in range(3)]
+        self.count = torch.zeros(1, dtype=torch.int64, device=device)
+
+    def load(self, x, p, s):
+        import torch
+        n = p.shape[1]
+        assert n <= self.capacity
+        for i in range(3):
+            if self.x[i] is not None:
+                self.x[i][:n] = torch.as_tensor(x[i], dtype=self.dtype)
+            self.p[i][:n] = torch.as_tensor(p[i], dtype=self.dtype)
+            self.s[i][:n] = torch.as_tensor(s[i], dtype=self.dtype)
+        self.count.fill_(n)
+
+    def view(self):
+        v = Leptons()
+        v.capacity, v.d_count, v.species = self.capacity, self.count.data_ptr(), self.species
+        for i in range(3):
+            v.x[i] = self.x[i].data_ptr() if self.x[i] is not None else None
+            v.p[i] = self.p[i].data_ptr()
+            v.s[i] = self.s[i].data_ptr()
+        return v
+
+    def n(self):
+        return int(self.count.item())
+
+    def arrays(self):
+        import numpy as np
+        n = self.n()
+        x = np.stack([(a[:n].double().cpu().numpy() if a is not None else np.zeros(n)) for a in self.x])
+        return (x, np.stack([a[:n].double().cpu().numpy() for a in self.p]),
+                np.stack([a[:n].double().cpu().numpy() for a in self.s]))
+
+
+class PhotonBuffers:
+    def __init__(self, capacity, dtype, device="cuda", track=(True, True, True)):
+        import torch
+        self.capacity, self.dtype = int(capacity), dtype
+        self.x = [torch.zeros(capacity, dtype=dtype, device=device) if t else None for t in track]
+        self.k = [torch.zeros(capacity, dtype=dtype, device=device) for _ in range(3)]
+        self.P = [torch.zeros(capacity, dtype=dtype, device=device) for _ in range(3)]
+        self.id = torch.zeros(capacity, dtype=torch.int64, device=device)
+        self.count = torch.zeros(1, dtype=torch.int64, device=device)
+        self.count_prev = torch.zeros(1, dtype=torch.int64, device=device)
+
+    def view(self):
+        v = Photons()
+        v.capacity, v.d_count, v.d_count_prev = self.capacity, self.count.data_ptr(), self.count_prev.data_ptr()
+        for i in range(3):
+            v.x[i] = self.x[i].data_ptr() if self.x[i] is not None else None
+            v.k[i] = self.k[i].data_ptr()
+            v.P[i] = self.P[i].data_ptr()
+        v.id = self.id.data_ptr()
+        return v
+
+    def n(self):
+        return int(self.count.item())
+
+    def arrays(self):
+        import numpy as np
+        n = self.n()
+        x = np.stack([(a[:n].double().cpu().numpy() if a is not None else np.zeros(n)) for a in self.x])
+        return (x, np.stack([a[:n].double().cpu().numpy() for a in self.k]),
+                np.stack([a[:n].double().cpu().numpy() for a in self.P]),
+                self.id[:n].cpu().numpy().view(np.uint64))
+
+
+def make_fields(kind=QED_FIELD_UNIFORM, E0=(0, 0, 0), B0=(0, 0, 0), a0=0.0, phase_len=0.0):
+    f = Fields()
+    f.kind = kind
+    for i in range(3):
+        f.E0[i], f.B0[i] = E0[i], B0[i]
+    f.a0, f.phase_len = a0, phase_len
+    return f
+
+
+def make_step(dt, eps_r, step=0, t=0.0, seed=1, flags=QED_ALL, a_e=ALPHA / (2 * math.pi), chi_e_min=1e-3,
+              chi_e_max=1e2, chi_g_min=0.05, chi_g_max=1e2, k_retire=0.0):
+    p = StepParams()
+    p.t, p.dt, p.a_e, p.eps_r = t, dt, a_e, eps_r
+    p.chi_e_min, p.chi_e_max, p.chi_g_min, p.chi_g_max, p.k_retire = chi_e_min, chi_e_max, chi_g_min, chi_g_max, k_retire
+    p.step, p.seed, p.flags = step, seed, flags
+    return p
+
+
+def qed_push_spin(leptons: LeptonBuffers, fields, step, tables: Tables, stream=None):
+    v = leptons.view()
+    _check(lib().qed_push_spin(C.byref(v), C.byref(fields), C.byref(step), tables.handle, _stream_ptr(stream)),
+           "qed_push_spin")
+
+
+def qed_emit(tables: Tables, leptons: LeptonBuffers, fields, step, photons: PhotonBuffers, counters, workspace,
+             stream=None):
+    lv, pv = leptons.view(), photons.view()
+    _check(lib().qed_emit(tables.handle, C.byref(lv), C.byref(fields), C.byref(step), C.byref(pv), _ptr(counters),
+                          _ptr(workspace), workspace.numel() * workspace.element_size(), _stream_ptr(stream)),
+           "qed_emit")
+
+
+def qed_pair(tables: Tables, photons: PhotonBuffers, fields, step, electrons: LeptonBuffers,
+             positrons: LeptonBuffers, counters, workspace, stream=None):
+    gv, ev, pv = photons.view(), electrons.view(), positrons.view()
+    _check(lib().qed_pair(tables.handle, C.byref(gv), C.byref(fields), C.byref(step), C.byref(ev), C.byref(pv),
+                          _ptr(counters), _ptr(workspace), workspace.numel() * workspace.element_size(),
+                          _stream_ptr(stream)), "qed_pair")
+
+
+def qed_compact_workspace_size(photons: PhotonBuffers, precision):
+    v = photons.view()
+    return int(lib().qed_compact_workspace_size(C.byref(v), precision))
+
+
+def qed_compact(photons: PhotonBuffers, precision, workspace, stream=None):
+    v = photons.view()
+    _check(lib().qed_compact(C.byref(v), precision, _ptr(workspace), workspace.numel() * workspace.element_size(),
+                             _stream_ptr(stream)), "qed_compact")
+
+
+def new_counters(device="cuda"):
+    import torch
+    return torch.zeros(len(COUNTER_NAMES), dtype=torch.int64, device=device)
+
+
+def counters_dict(ctr):
+    return {n: int(v) for n, v in zip(COUNTER_NAMES, ctr.cpu().tolist())}
+
+
+def new_workspace(nbytes, device="cuda"):
+    import torch
+    return torch.empty(int(nbytes), dtype=torch.uint8, device=device)

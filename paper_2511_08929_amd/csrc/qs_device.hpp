@@ -1,0 +1,348 @@
+// qs_device.hpp -- device math of the spin- and polarization-resolved QED step (gfx950).
+//
+// Precision policy: particle state and bulk arithmetic in R (float or double); FP64 islands
+// for chi (cancellation in p0 E + p x B for co-propagating geometry), for the inverse-CDF
+// interpolation and lambda = 1/(1+exp(-nu)) (small-photon-energy tail), and for the Bessel
+// functions K_1/3, K_2/3, IntK_1/3 of the emitters.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace qs {
+
+constexpr double kAlpha = 7.2973525693e-3;
+constexpr double kPi = 3.14159265358979323846;
+
+// physics switches (values of the C ABI enum)
+enum : uint32_t {
+    F_PUSH = 1u << 0, F_TBMT = 1u << 1, F_EMIT = 1u << 2, F_RECOIL = 1u << 3, F_SPIN = 1u << 4,
+    F_NOEMIT = 1u << 5, F_PHOTON_POL = 1u << 6, F_MEAN = 1u << 7, F_PAIR = 1u << 8,
+    F_NOPAIR = 1u << 9, F_PAIR_SPIN = 1u << 10
+};
+
+// ------------------------------------------------------------------ small vectors
+template <class R> struct V3 { R x, y, z; };
+
+template <class R> __device__ __forceinline__ V3<R> v3(R a, R b, R c) { return V3<R>{a, b, c}; }
+template <class R> __device__ __forceinline__ V3<R> operator+(V3<R> a, V3<R> b) { return {a.x + b.x, a.y + b.y, a.z + b.z}; }
+template <class R> __device__ __forceinline__ V3<R> operator-(V3<R> a, V3<R> b) { return {a.x - b.x, a.y - b.y, a.z - b.z}; }
+template <class R> __device__ __forceinline__ V3<R> operator*(R s, V3<R> a) { return {s * a.x, s * a.y, s * a.z}; }
+template <class R> __device__ __forceinline__ R dot(V3<R> a, V3<R> b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
+template <class R> __device__ __forceinline__ V3<R> cross(V3<R> a, V3<R> b)
+{
+    return {a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x};
+}
+template <class D, class S> __device__ __forceinline__ V3<D> cvt(V3<S> a) { return {(D)a.x, (D)a.y, (D)a.z}; }
+
+__device__ __forceinline__ float rsqrt_r(float v) { return 1.0f / sqrtf(v); }
+__device__ __forceinline__ double rsqrt_r(double v) { return 1.0 / sqrt(v); }
+__device__ __forceinline__ float sqrt_r(float v) { return sqrtf(v); }
+__device__ __forceinline__ double sqrt_r(double v) { return sqrt(v); }
+__device__ __forceinline__ float exp_r(float v) { return expf(v); }
+__device__ __forceinline__ double exp_r(double v) { return exp(v); }
+__device__ __forceinline__ float log_r(float v) { return logf(v); }
+__device__ __forceinline__ double log_r(double v) { return log(v); }
+
+// ------------------------------------------------------------------ Philox4x32-10
+// Salmon, Moraes, Dror, Shaw (SC'11): 10 rounds of two 32x32 -> 64 multiplies with
+// Weyl-sequence key bumps.
+__device__ __forceinline__ uint4 philox4x32_10(uint4 c, uint32_t k0, uint32_t k1)
+{
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint32_t lo0 = 0xD2511F53u * c.x, hi0 = __umulhi(0xD2511F53u, c.x);
+        const uint32_t lo1 = 0xCD9E8D57u * c.z, hi1 = __umulhi(0xCD9E8D57u, c.z);
+        c = make_uint4(hi1 ^ c.y ^ k0, lo1, hi0 ^ c.w ^ k1, lo0);
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    return c;
+}
+
+__device__ __forceinline__ uint4 philox_block(uint64_t seed, uint64_t id, int64_t step, uint32_t channel)
+{
+    return philox4x32_10(make_uint4((uint32_t)id, (uint32_t)(id >> 32), (uint32_t)step, channel),
+                         (uint32_t)seed, (uint32_t)(seed >> 32));
+}
+
+// 53-bit uniform in (0,1): m = 27 high bits of hi : 26 high bits of lo, u = (m + 1/2) 2^-53
+__device__ __forceinline__ double u01_53(uint32_t hi, uint32_t lo)
+{
+    const uint64_t m = ((uint64_t)(hi >> 5) << 26) | (uint64_t)(lo >> 6);
+    return ((double)m + 0.5) * 0x1p-53;
+}
+// 24-bit uniform in (0,1), exactly representable in float: (2 (hi >> 9) + 1) 2^-24
+__device__ __forceinline__ float u01_24(uint32_t hi) { return (float)(2u * (hi >> 9) + 1u) * 0x1p-24f; }
+
+template <class R> struct Unif;
+template <> struct Unif<double> {
+    static __device__ __forceinline__ void two(uint4 w, double &a, double &b) { a = u01_53(w.x, w.y); b = u01_53(w.z, w.w); }
+};
+template <> struct Unif<float> {
+    static __device__ __forceinline__ void two(uint4 w, float &a, float &b) { a = u01_24(w.x); b = u01_24(w.z); }
+};
+
+__device__ __forceinline__ uint64_t lepton_id(int species, int64_t index) { return ((uint64_t)species << 62) | (uint64_t)index; }
+__device__ __forceinline__ uint64_t photon_id(int species, int64_t index, int64_t step)
+{
+    return (1ull << 63) | ((uint64_t)species << 61) | (((uint64_t)index & ((1ull << 37) - 1)) << 24) |
+           ((uint64_t)step & 0xFFFFFFull);
+}
+
+// ------------------------------------------------------------------ Bessel triple (FP64)
+// K_nu(x) = int_0^inf e^{-x cosh t} cosh(nu t) dt, IntK_1/3(x) = int_0^inf e^{-x cosh t} cosh(t/3)/cosh(t) dt,
+// by the trapezoidal rule in t, which converges geometrically for these integrands (analytic
+// in the strip |Im t| < pi/2): step 0.2 (error ~ e^{-pi^2/0.2}) and 0.6/sqrt(x) for large x,
+// where the integrand is a narrow Gaussian of width 1/sqrt(x).  Returned scaled by e^{+x}:
+// o = e^x (K_1/3, K_2/3, IntK_1/3).  Zero beyond x = 700.
+struct Bessel3 { double k13, k23, ik; };
+
+__device__ inline Bessel3 bessel3_scaled(double x)
+{
+    Bessel3 o{0.0, 0.0, 0.0};
+    if (!(x < 700.0)) return o;
+    const double h = fmin(0.2, 0.6 / sqrt(x));
+    double s13 = 0.5, s23 = 0.5, sik = 0.5;     // t = 0 node, half weight
+    for (int j = 1; j < 4096; ++j) {
+        const double t = j * h;
+        const double sh = sinh(0.5 * t);
+        const double chm1 = 2.0 * sh * sh;          // cosh t - 1
+        const double e = exp(-x * chm1);            // e^{-x cosh t} e^{x}
+        const double z = exp(t * (1.0 / 3.0)), zi = 1.0 / z;
+        const double c1 = 0.5 * (z + zi), c2 = 0.5 * (z * z + zi * zi);
+        s13 += e * c1;
+        s23 += e * c2;
+        sik += e * c1 / (1.0 + chm1);
+        if (x * chm1 > 44.0 && x * (1.0 + chm1) > 44.0) break;
+    }
+    o.k13 = h * s13;
+    o.k23 = h * s23;
+    o.ik = h * sik;
+    return o;
+}
+
+// ------------------------------------------------------------------ fields
+struct FieldDev {
+    int kind;
+    double E0[3], B0[3];
+    double a0, phase_len;
+};
+
+// E and B at position x (only x[0] enters the plane wave) and time t.
+template <class R> __device__ __forceinline__ void eval_fields(const FieldDev &f, double x0, double t, V3<R> &E, V3<R> &B);
+
+template <> __device__ __forceinline__ void eval_fields<double>(const FieldDev &f, double x0, double t, V3<double> &E, V3<double> &B)
+{
+    E = {f.E0[0], f.E0[1], f.E0[2]};
+    B = {f.B0[0], f.B0[1], f.B0[2]};
+    if (f.kind == 1) {
+        const double phi = t + x0;
+        double g = 1.0;
+        if (f.phase_len > 0.0) {
+            if (phi < 0.0 || phi > f.phase_len) g = 0.0;
+            else { const double sn = sin(kPi * phi / f.phase_len); g = sn * sn; }
+        }
+        const double ey = f.a0 * g * cos(phi);
+        E.y += ey;
+        B.z -= ey;
+    }
+}
+
+// single precision: the phase is formed and reduced modulo 2 pi in FP64, the trig in FP32
+template <> __device__ __forceinline__ void eval_fields<float>(const FieldDev &f, double x0, double t, V3<float> &E, V3<float> &B)
+{
+    E = {(float)f.E0[0], (float)f.E0[1], (float)f.E0[2]};
+    B = {(float)f.B0[0], (float)f.B0[1], (float)f.B0[2]};
+    if (f.kind == 1) {
+        const double phi = t + x0;
+        float g = 1.0f;
+        if (f.phase_len > 0.0) {
+            if (phi < 0.0 || phi > f.phase_len) g = 0.0f;
+            else {
+                const double a = phi / f.phase_len;                 // in [0, 1]
+                const float sn = sinf((float)(kPi * a));
+                g = sn * sn;
+            }
+        }
+        const double red = phi - 2.0 * kPi * rint(phi * (0.5 / kPi));
+        const float ey = (float)f.a0 * g * cosf((float)red);
+        E.y += ey;
+        B.z -= ey;
+    }
+}
+
+// ------------------------------------------------------------------ push (Boris + T-BMT)
+// Cayley rotation v <- v + (v + v x t) x 2t/(1+t^2): exact rotation by 2 atan|t| about t.
+template <class R> __device__ __forceinline__ V3<R> cayley(V3<R> v, V3<R> t)
+{
+    const R f = (R)2 / ((R)1 + dot(t, t));
+    const V3<R> vp = v + cross(v, t);
+    return v + cross(vp, f * t);
+}
+
+// Boris momentum update with fields at the old position; T-BMT with the standard E-term
+// coefficient a + 1/(gamma+1), the Boris mid-step gamma and beta = (u- + u+)/(2 gamma);
+// returns the displacement p/gamma dt with the new momentum.
+template <class R>
+__device__ __forceinline__ V3<R> push(int q, R a_e, V3<R> E, V3<R> B, R dt, bool tbmt, V3<R> &p, V3<R> &s)
+{
+    const R hq = (R)0.5 * (R)q * dt;
+    const V3<R> um = p + hq * E;
+    const R gm = sqrt_r((R)1 + dot(um, um));
+    const V3<R> up = cayley(um, (hq / gm) * B);
+    if (tbmt) {
+        const V3<R> be = ((R)0.5 / gm) * (um + up);
+        const V3<R> bxE = cross(be, E);
+        const R bB = dot(be, B);
+        const V3<R> Om = (R)(-q) * ((a_e + (R)1 / gm) * B - (a_e * gm / (gm + (R)1) * bB) * be -
+                                    (a_e + (R)1 / (gm + (R)1)) * bxE);
+        s = cayley(s, ((R)(-0.5) * dt) * Om);
+    }
+    p = up + hq * E;
+    const R g = sqrt_r((R)1 + dot(p, p));
+    return (dt / g) * p;
+}
+
+// ------------------------------------------------------------------ basis and chi
+// chi = eps_r sqrt((p0 E + p x B)^2 - (p.E)^2) in FP64 (p0 = gamma for leptons, |k| for photons);
+// khat = p/|p|; eps = unit(sgn (E + v x B) perpendicular to khat), sgn = -q (q = -1 for e-
+// and photons, +1 for e+); beta = khat x eps (right-handed triad).  chi = 0 when the
+// transverse force vanishes.
+template <class R> struct Basis { V3<R> e, b, k; };
+
+template <class R>
+__device__ __forceinline__ double basis_chi(int charge, double eps_r, V3<R> p, double p0, V3<R> E, V3<R> B, Basis<R> &out)
+{
+    const V3<double> pd = cvt<double>(p), Ed = cvt<double>(E), Bd = cvt<double>(B);
+    const V3<double> F = p0 * Ed + cross(pd, Bd);
+    const double pE = dot(pd, Ed);
+    const double rad = dot(F, F) - pE * pE;
+    const double pn2 = dot(pd, pd);
+    // transverse part of F (FP64), then unit vectors in R
+    const V3<double> Ft = F - (dot(F, pd) / pn2) * pd;
+    const double ft2 = dot(Ft, Ft);
+    const R ipn = rsqrt_r((R)pn2);
+    out.k = ipn * p;
+    if (!(ft2 > 0.0)) {
+        out.e = {0, 0, 0};
+        out.b = {0, 0, 0};
+        return 0.0;
+    }
+    const R sgn = charge > 0 ? (R)-1 : (R)1;
+    out.e = (sgn * rsqrt_r((R)ft2)) * cvt<R>(Ft);
+    out.b = cross(out.k, out.e);
+    return eps_r * sqrt(rad > 0.0 ? rad : 0.0);
+}
+
+// ------------------------------------------------------------------ table interpolation
+// 4-point Lagrange weights on nodes v0 + i h, i = 0..n-1 (one-sided at the ends).
+template <class R> __device__ __forceinline__ int lagrange4(R v, R v0, R h, int n, R L[4])
+{
+    R s = (v - v0) / h;
+    s = s < (R)0 ? (R)0 : s;
+    s = s > (R)(n - 1) ? (R)(n - 1) : s;
+    int i = (int)floor(s) - 1;
+    i = i < 0 ? 0 : (i > n - 4 ? n - 4 : i);
+    const R t = s - (R)i;
+    const R a = t - (R)1, b = t - (R)2, c = t - (R)3;
+    L[0] = -(a * b * c) / (R)6;
+    L[1] = (t * b * c) / (R)2;
+    L[2] = -(t * a * c) / (R)2;
+    L[3] = (t * a * b) / (R)6;
+    return i;
+}
+
+// ------------------------------------------------------------------ P-vector <-> Stokes
+// Encode xi (emission-basis Stokes, xi3 linear along eps, xi2 circular) as P = d [sqrt(1-xi2^2)
+// (cos dth eps + sin dth beta) + xi2 k], dth = atan2(xi1, xi3)/2, for unit xi scaled by d = |xi|.
+template <class R> __device__ __forceinline__ V3<R> stokes_to_P(R x1, R x2, R x3, const Basis<R> &bs)
+{
+    const R d = sqrt_r(x1 * x1 + x2 * x2 + x3 * x3);
+    if (!(d > (R)0)) return {0, 0, 0};
+    const R id = (R)1 / d;
+    const R u1 = x1 * id, u2 = x2 * id, u3 = x3 * id;
+    const R dth = (R)0.5 * atan2(u1, u3);
+    R tr = (R)1 - u2 * u2;
+    tr = sqrt_r(tr > (R)0 ? tr : (R)0);
+    const R ce = d * tr * cos(dth), cb = d * tr * sin(dth), ck = d * u2;
+    return ce * bs.e + cb * bs.b + ck * bs.k;
+}
+
+template <class R> __device__ __forceinline__ void P_to_stokes(V3<R> P, const Basis<R> &bs, R &x1, R &x2, R &x3)
+{
+    const R d2 = dot(P, P);
+    if (!(d2 > (R)0)) { x1 = x2 = x3 = 0; return; }
+    const R d = sqrt_r(d2), id = (R)1 / d;
+    const R p1 = dot(P, bs.e) * id, p2 = dot(P, bs.b) * id, pk = dot(P, bs.k) * id;
+    const R rr = p1 * p1 + p2 * p2;
+    if (rr > (R)0) {
+        const R ir = rsqrt_r(rr);
+        x1 = d * (R)2 * p1 * p2 * ir;
+        x3 = d * (p1 * p1 - p2 * p2) * ir;
+    } else {
+        x1 = x3 = 0;
+    }
+    x2 = d * pk;
+}
+
+// ------------------------------------------------------------------ spectra
+// Bessel values normalized by K_2/3 (ratios are all the collapse needs):
+// K1 = K_1/3/K_2/3, I = IntK_1/3/K_2/3 at u' (NLC) or u~' (NBW).
+template <class R> struct SpecPt { R lam, oml, u, K1, I; };
+
+// NLC (appendix, Bessel forms), a = s_i and b = s_f in (eps, beta, k) components.
+// w = -I + kappa K2 + lam a_beta K1; g = u K1 beta + (-I + 2 K2) a + lam u (-I + K2) a_k k.
+template <class R> __device__ __forceinline__ R nlc_w(const SpecPt<R> &q, R ab)
+{
+    const R kap = (R)1 / q.oml + q.oml;
+    return -q.I + kap + q.lam * ab * q.K1;
+}
+template <class R> __device__ __forceinline__ V3<R> nlc_g(const SpecPt<R> &q, V3<R> a)
+{
+    const R c = -q.I + (R)2;
+    return {c * a.x, q.u * q.K1 + c * a.y, c * a.z + q.lam * q.u * (-q.I + (R)1) * a.z};
+}
+// F = (F1, F2, F3) for initial a and final b (diagonal, circular, linear-along-eps components)
+template <class R> __device__ __forceinline__ V3<R> nlc_F(const SpecPt<R> &q, V3<R> a, V3<R> b)
+{
+    const R lam = q.lam, u = q.u, I = q.I, K1 = q.K1;
+    const R kap = (R)1 / q.oml + q.oml, kapt = (R)1 / q.oml - q.oml;
+    const R ck = b.x * a.y - b.y * a.x;           // (s_f x s_i) . k
+    const R ce = b.y * a.z - b.z * a.y;           // (s_f x s_i) . eps
+    const R hlu = (R)0.5 * lam * u;
+    V3<R> F;
+    F.x = -K1 * (u * a.x + lam * b.x) - hlu * I * (b.x * a.y + b.y * a.x) + (R)0.5 * kapt * ck;
+    F.y = (R)0.5 * kapt * K1 * ce - (lam * I - kapt) * a.z - (u * I - kapt) * b.z + hlu * K1 * (b.z * a.y + b.y * a.z);
+    F.z = (R)1 + (u * a.y + lam * b.y) * K1 - hlu * I * (b.x * a.x - b.y * a.y) + (R)0.5 * kap * dot(b, a) - hlu * b.z * a.z;
+    return F;
+}
+
+// NBW (appendix, Bessel forms) with the plus sign of the last term of G3 (as in its Airy form);
+// e = s_e, p = s_p components; returns G0 and G = (G1, G2, G3).
+template <class R> __device__ __forceinline__ R nbw_G(const SpecPt<R> &q, V3<R> e, V3<R> p, V3<R> &G)
+{
+    const R lam = q.lam, oml = q.oml, I = q.I, K1 = q.K1;
+    const R il = (R)1 / lam, io = (R)1 / oml;
+    const R ut = il + io, rho = oml * il + lam * io, rhot = oml * il - lam * io;
+    const R pe = dot(p, e);
+    const R ck = p.x * e.y - p.y * e.x;           // (s_p x s_e) . k
+    const R ce = p.y * e.z - p.z * e.y;           // (s_p x s_e) . eps
+    const R G0 = I + rho + e.y * K1 * io - p.y * K1 * il + (I - (R)2) * pe + (rho * I - (rho - (R)2)) * p.z * e.z;
+    G.x = K1 * (e.x * il - p.x * io) - (R)0.5 * ut * I * (p.x * e.y + p.y * e.x) + (R)0.5 * rhot * ck;
+    G.y = -(R)0.5 * ut * K1 * ce + (I * io + rhot) * e.z + (I * il - rhot) * p.z - (R)0.5 * rhot * K1 * (p.z * e.y + p.y * e.z);
+    G.z = -(R)1 + (-e.y * il + p.y * io) * K1 - (R)0.5 * ut * I * (p.x * e.x - p.y * e.y) + (R)0.5 * rho * pe +
+          ((R)1 - (R)0.5 * rho) * p.z * e.z;
+    return G0;
+}
+// w0 and the spin vectors j_e, j_p (marginals of G over the other lepton's spin)
+template <class R> __device__ __forceinline__ R nbw_j(const SpecPt<R> &q, V3<R> xi, V3<R> &je, V3<R> &jp)
+{
+    const R lam = q.lam, oml = q.oml, I = q.I, K1 = q.K1;
+    const R il = (R)1 / lam, io = (R)1 / oml;
+    const R rho = oml * il + lam * io, rhot = oml * il - lam * io;
+    je = {xi.x * K1 * il, (io - xi.z * il) * K1, xi.y * (I * io + rhot)};
+    jp = {-xi.x * K1 * io, (-il + xi.z * io) * K1, xi.y * (I * il - rhot)};
+    return I + rho - xi.z;
+}
+
+}  // namespace qs

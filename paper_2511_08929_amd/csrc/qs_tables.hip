@@ -1,0 +1,298 @@
+// qs_tables.hip -- GPU construction of the rate and inverse-CDF tables (qed_init_tables).
+//
+// The NLC section tabulates the emission rate and the inverse CDF of the photon spectrum only
+// for the initial spin along / against the rest-frame B (s_beta = +1 / -1); the NBW section
+// does the same for photons with xi3 = +1 / -1.  Each table entry is computed here by
+// quadrature of the spectrum in nu = ln(lam/(1-lam)) (dlam = lam (1-lam) dnu), where the
+// integrand is smooth and decays at both ends:
+//   rate   ln int_0^1 w dlam;
+//   ICDF   nu(rho) with CDF(lam(nu)) = r, rho = ln(r/(1-r)), solved by Newton's method on
+//          ln(cumulative) with a bisection safeguard, from the left for r <= 1/2 and on the
+//          complementary CDF from the right for r > 1/2 so both tails keep full precision.
+// Below nu = -60 the NLC spectrum follows its small-lambda law
+//   int_0^lam w = 3 Gamma(2/3) (3 chi)^(2/3) lam^(1/3) - (pi/sqrt 3) lam   (relative remainder < 1e-26).
+// Quadrature: 12-point Gauss-Legendre panels of width 1/2 in nu (the density is analytic in
+// the strip |Im nu| < pi/2, so each panel is exact to rounding); Bessel functions by the
+// trapezoidal rule of qs_device.hpp.
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <vector>
+
+#include "qs_internal.hpp"
+
+namespace {
+
+constexpr int kNQ = 12;
+constexpr double kPanel = 0.5;
+constexpr double kNuLo = -60.0;
+constexpr int kMaxPanels = 320;
+
+struct GL12 { double x[kNQ], w[kNQ]; };
+
+struct BuildArgs {
+    int n_chi[2];
+    double lnchi0[2], dlnchi[2];
+    int n_rho;
+    double rho0, drho;
+    int off_rate[4];
+    int64_t off_nu[4];
+};
+
+// Legendre nodes and weights on [-1, 1] by Newton's method on P_n (host)
+GL12 legendre_nodes()
+{
+    GL12 g;
+    const int n = kNQ;
+    for (int i = 0; i < n; ++i) {
+        double x = cos(M_PI * (4.0 * i + 3.0) / (4.0 * n + 2.0));
+        double dp = 1.0;
+        for (int it = 0; it < 50; ++it) {
+            double p0 = 1.0, p1 = x;
+            for (int k = 2; k <= n; ++k) {
+                const double p2 = ((2.0 * k - 1.0) * x * p1 - (k - 1.0) * p0) / k;
+                p0 = p1;
+                p1 = p2;
+            }
+            dp = n * (x * p1 - p0) / (x * x - 1.0);
+            const double dx = p1 / dp;
+            x -= dx;
+            if (fabs(dx) < 1e-16) break;
+        }
+        double p0 = 1.0, p1 = x;
+        for (int k = 2; k <= n; ++k) {
+            const double p2 = ((2.0 * k - 1.0) * x * p1 - (k - 1.0) * p0) / k;
+            p0 = p1;
+            p1 = p2;
+        }
+        dp = n * (x * p1 - p0) / (x * x - 1.0);
+        g.x[i] = x;
+        g.w[i] = 2.0 / ((1.0 - x * x) * dp * dp);
+    }
+    return g;
+}
+
+__device__ __forceinline__ double kPi_over_sqrt3() { return qs::kPi / sqrt(3.0); }
+
+// spectrum density in nu for channel ch (un-normalized): w lam (1-lam)
+__device__ double density(int ch, double chi, double nu)
+{
+    const double lam = 1.0 / (1.0 + exp(-nu)), oml = 1.0 / (1.0 + exp(nu));
+    if (ch < 2) {
+        const double up = 2.0 * exp(nu) / (3.0 * chi);
+        if (!(up < 700.0)) return 0.0;
+        const qs::Bessel3 b = qs::bessel3_scaled(up);
+        const double kap = 1.0 / oml + oml;
+        const double w = -b.ik + kap * b.k23 + (ch == 1 ? lam : -lam) * b.k13;
+        return exp(-up) * w * lam * oml;
+    } else {
+        const double ut = 1.0 / lam + 1.0 / oml;
+        const double up = 2.0 * ut / (3.0 * chi);
+        if (!(up < 700.0)) return 0.0;
+        const qs::Bessel3 b = qs::bessel3_scaled(up);
+        const double rho = oml / lam + lam / oml;
+        const double w0 = b.ik + rho * b.k23 - (ch == 3 ? 1.0 : -1.0) * b.k23;
+        return exp(-up) * w0 * lam * oml;
+    }
+}
+
+__device__ double gl_integral(const GL12 &g, int ch, double chi, double a, double b)
+{
+    if (!(b > a)) return 0.0;
+    const double mid = 0.5 * (a + b), half = 0.5 * (b - a);
+    double s = 0.0;
+    for (int i = 0; i < kNQ; ++i) s += g.w[i] * density(ch, chi, mid + half * g.x[i]);
+    return half * s;
+}
+
+// Newton on ln(cum(nu)) - ln(target) inside [lo, hi].
+// side > 0: cum = base + int_lo^nu f (increasing); side < 0: cum = base + int_nu^hi f (decreasing).
+__device__ double solve_root(const GL12 &g, int ch, double chi, int side, double base, double pint,
+                             double lo, double hi, double target)
+{
+    const double c_lo = side > 0 ? base : base + pint;
+    const double c_hi = side > 0 ? base + pint : base;
+    const double lt = log(target);
+    const double l_lo = log(fmax(c_lo, 1e-300)), l_hi = log(fmax(c_hi, 1e-300));
+    double a = lo, b = hi;
+    double nu = (l_hi != l_lo) ? lo + (hi - lo) * (lt - l_lo) / (l_hi - l_lo) : 0.5 * (lo + hi);
+    if (!(nu > a && nu < b)) nu = 0.5 * (a + b);
+    for (int it = 0; it < 80; ++it) {
+        const double cum = side > 0 ? base + gl_integral(g, ch, chi, lo, nu) : base + gl_integral(g, ch, chi, nu, hi);
+        const double r = log(cum) - lt;
+        const double f = density(ch, chi, nu);
+        const double step = f > 0.0 ? r * cum / (side > 0 ? f : -f) : 0.0;
+        if (fabs(r) < 1e-15) {
+            if (nu - step > a && nu - step < b) nu -= step;
+            break;
+        }
+        if ((side > 0) == (r > 0.0)) b = nu; else a = nu;
+        double nn = nu - step;
+        if (!(f > 0.0) || !(nn > a && nn < b)) nn = 0.5 * (a + b);
+        if (fabs(nn - nu) <= 2e-16 * fmax(1.0, fabs(nu)) || (b - a) <= 2e-16 * fmax(1.0, fabs(nu))) {
+            nu = nn;
+            break;
+        }
+        nu = nn;
+    }
+    return nu;
+}
+
+__global__ void __launch_bounds__(256) k_build_tables(BuildArgs A, GL12 g, double *lnrate, double *nu_out)
+{
+    __shared__ double pint[kMaxPanels], left[kMaxPanels + 1], right[kMaxPanels + 1];
+    __shared__ double s_total, s_tail;
+    __shared__ int s_np;
+    int task = blockIdx.x, ch, i;
+    if (task < 2 * A.n_chi[0]) { ch = task / A.n_chi[0]; i = task % A.n_chi[0]; }
+    else { const int t2 = task - 2 * A.n_chi[0]; ch = 2 + t2 / A.n_chi[1]; i = t2 % A.n_chi[1]; }
+    const int grp = ch < 2 ? 0 : 1;
+    const double chi = exp(A.lnchi0[grp] + i * A.dlnchi[grp]);
+    double a0, b1;
+    if (ch < 2) { a0 = kNuLo; b1 = log(1.5 * chi * 700.0); }
+    else {
+        const double c = 0.75 * chi * 700.0 - 1.0;
+        const double m = c > 1.0 ? acosh(c) : 0.0;
+        a0 = -m; b1 = m;
+    }
+    int np = (int)ceil((b1 - a0) / kPanel);
+    np = np < 1 ? 1 : (np > kMaxPanels ? kMaxPanels : np);
+    for (int p = threadIdx.x; p < np; p += blockDim.x)
+        pint[p] = gl_integral(g, ch, chi, a0 + p * kPanel, fmin(a0 + (p + 1) * kPanel, b1));
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double tail = 0.0;
+        if (ch < 2) {
+            const double lam0 = 1.0 / (1.0 + exp(-a0));
+            tail = 3.0 * tgamma(2.0 / 3.0) * pow(3.0 * chi, 2.0 / 3.0) * cbrt(lam0) - kPi_over_sqrt3() * lam0;
+        }
+        left[0] = tail;
+        for (int p = 0; p < np; ++p) left[p + 1] = left[p] + pint[p];
+        right[np] = 0.0;
+        for (int p = np - 1; p >= 0; --p) right[p] = right[p + 1] + pint[p];
+        s_total = tail + right[0];
+        s_tail = tail;
+        s_np = np;
+        lnrate[A.off_rate[ch] + i] = log(s_total);
+    }
+    __syncthreads();
+    const double total = s_total, tail = s_tail;
+    np = s_np;
+    double *row = nu_out + A.off_nu[ch] + (int64_t)i * A.n_rho;
+    for (int j = threadIdx.x; j < A.n_rho; j += blockDim.x) {
+        const double rho = A.rho0 + j * A.drho;
+        double nu;
+        if (rho <= 0.0) {
+            const double target = total / (1.0 + exp(-rho));
+            if (ch < 2 && target <= tail) {
+                const double Ac = 3.0 * tgamma(2.0 / 3.0) * pow(3.0 * chi, 2.0 / 3.0), Bc = kPi_over_sqrt3();
+                double y = target / Ac;
+                for (int it = 0; it < 4; ++it) y -= (Ac * y - Bc * y * y * y - target) / (Ac - 3.0 * Bc * y * y);
+                nu = 3.0 * log(y) - log1p(-y * y * y);
+            } else {
+                int lo = 0, hi = np;
+                while (hi - lo > 1) { const int m = (lo + hi) >> 1; if (left[m] <= target) lo = m; else hi = m; }
+                nu = solve_root(g, ch, chi, +1, left[lo], pint[lo], a0 + lo * kPanel, fmin(a0 + (lo + 1) * kPanel, b1), target);
+            }
+        } else {
+            const double target = total / (1.0 + exp(rho));
+            int lo = 0, hi = np;
+            while (hi - lo > 1) { const int m = (lo + hi) >> 1; if (right[m] > target) lo = m; else hi = m; }
+            nu = solve_root(g, ch, chi, -1, right[lo + 1], pint[lo], a0 + lo * kPanel, fmin(a0 + (lo + 1) * kPanel, b1), target);
+        }
+        row[j] = nu;
+    }
+}
+
+__global__ void k_to_float(const double *src, float *dst, int n)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) dst[i] = (float)src[i];
+}
+
+}  // namespace
+
+extern "C" qed_status qed_init_tables(const qed_table_params *params, qed_stream stream, qed_tables *out)
+{
+    if (!params || !out) return QED_ERR_INVALID;
+    const qed_table_grid &G = params->grid;
+    if (G.n_chi[0] < 4 || G.n_chi[1] < 4 || G.n_rho < 4 || !(G.dlnchi[0] > 0) || !(G.dlnchi[1] > 0) ||
+        !(G.drho > 0))
+        return QED_ERR_INVALID;
+    if (params->precision != QED_F64 && params->precision != QED_F32) return QED_ERR_INVALID;
+    hipStream_t st = (hipStream_t)stream;
+    qed_tables T = (qed_tables)calloc(1, sizeof(qed_tables_s));
+    if (!T) return QED_ERR_INVALID;
+    T->params = *params;
+    BuildArgs A;
+    int r = 0;
+    int64_t v = 0;
+    for (int c = 0; c < 4; ++c) {
+        const int n = G.n_chi[c < 2 ? 0 : 1];
+        A.off_rate[c] = r;
+        A.off_nu[c] = v;
+        T->dev.off_rate[c] = r;
+        T->dev.off_nu[c] = v;
+        r += n;
+        v += (int64_t)n * G.n_rho;
+    }
+    for (int k = 0; k < 2; ++k) {
+        A.n_chi[k] = G.n_chi[k];
+        A.lnchi0[k] = G.lnchi0[k];
+        A.dlnchi[k] = G.dlnchi[k];
+    }
+    A.n_rho = G.n_rho;
+    A.rho0 = G.rho0;
+    A.drho = G.drho;
+    T->n_rate = r;
+    T->n_nu = v;
+    if (hipMalloc(&T->d_lnrate, sizeof(double) * r) != hipSuccess ||
+        hipMalloc(&T->d_lnrate32, sizeof(float) * r) != hipSuccess ||
+        hipMalloc(&T->d_nu, sizeof(double) * v) != hipSuccess) {
+        qed_free_tables(T);
+        return QED_ERR_HIP;
+    }
+    const GL12 g = legendre_nodes();
+    const int ntask = 2 * G.n_chi[0] + 2 * G.n_chi[1];
+    hipLaunchKernelGGL(k_build_tables, dim3(ntask), dim3(256), 0, st, A, g, T->d_lnrate, T->d_nu);
+    hipLaunchKernelGGL(k_to_float, dim3((r + 255) / 256), dim3(256), 0, st, T->d_lnrate, T->d_lnrate32, r);
+    if (hipGetLastError() != hipSuccess || hipStreamSynchronize(st) != hipSuccess) {
+        qed_free_tables(T);
+        return QED_ERR_HIP;
+    }
+    TablesDev &D = T->dev;
+    for (int k = 0; k < 2; ++k) {
+        D.n_chi[k] = G.n_chi[k];
+        D.lnchi0[k] = G.lnchi0[k];
+        D.dlnchi[k] = G.dlnchi[k];
+    }
+    D.n_rho = G.n_rho;
+    D.rho0 = G.rho0;
+    D.drho = G.drho;
+    D.lnrate = T->d_lnrate;
+    D.lnrate32 = T->d_lnrate32;
+    D.nu = T->d_nu;
+    *out = T;
+    return QED_OK;
+}
+
+extern "C" qed_status qed_free_tables(qed_tables T)
+{
+    if (!T) return QED_OK;
+    if (T->d_lnrate) (void)hipFree(T->d_lnrate);
+    if (T->d_lnrate32) (void)hipFree(T->d_lnrate32);
+    if (T->d_nu) (void)hipFree(T->d_nu);
+    free(T);
+    return QED_OK;
+}
+
+extern "C" qed_status qed_tables_download(qed_tables T, double *lnrate, int64_t *n_lnrate, double *nu, int64_t *n_nu)
+{
+    if (!T) return QED_ERR_INVALID;
+    if (n_lnrate) *n_lnrate = T->n_rate;
+    if (n_nu) *n_nu = T->n_nu;
+    if (lnrate) QS_CHECK(hipMemcpy(lnrate, T->d_lnrate, sizeof(double) * T->n_rate, hipMemcpyDeviceToHost));
+    if (nu) QS_CHECK(hipMemcpy(nu, T->d_nu, sizeof(double) * T->n_nu, hipMemcpyDeviceToHost));
+    return QED_OK;
+}

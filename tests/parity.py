@@ -1,0 +1,104 @@
+"""Helpers of the GPU parity tests: run the oracle on the same seeded inputs with the same step
+order as the HIP driver, and compare particle by particle.  Imports the oracle (test side only)."""
+from __future__ import annotations
+
+import numpy as np
+
+import oracle
+
+
+def oracle_run(tables, w, steps, flags, *, cap_e=None, cap_p=None, cap_g=None, u24=False, near_tol=1e-10,
+               index=None, seed=None, k_retire=None, t0=0.0, nthreads=16, x=None, p=None, s=None,
+               fields=None, step0=0):
+    """Run the oracle for `steps` steps of workload `w` (optionally a subset with original indices
+    `index`).  Returns dict of oracle sets, counters and accumulated near-tie flags."""
+    x = w.x if x is None else x
+    p = w.p if p is None else p
+    s = w.s if s is None else s
+    n = p.shape[1]
+    cap_e = cap_e or n
+    cap_p = cap_p or max(1, cap_e - n)
+    cap_g = cap_g or 1
+    E = oracle.LeptonSet(0, cap_e, track=w.track)
+    E.set(x, p, s, index=index)
+    P = oracle.LeptonSet(1, cap_p, track=w.track)
+    G = oracle.PhotonSet(cap_g, track=w.track)
+    F = fields or oracle.make_fields(w.field_kind, E0=w.E0, B0=w.B0, a0=w.a0, phase_len=w.phase_len)
+    ctr = oracle.Counters()
+    near_e = np.zeros(cap_e, dtype=bool)
+    near_p = np.zeros(cap_p, dtype=bool)
+    near_g = np.zeros(cap_g, dtype=bool)
+    pair = bool(flags & oracle.F_PAIR)
+    for k in range(step0, step0 + steps):
+        prm = oracle.make_params(w.dt, oracle_eps(), step=k, t=t0 + k * w.dt,
+                                 seed=w.seed if seed is None else seed, flags=flags,
+                                 k_retire=w.k_retire if k_retire is None else k_retire, near_tol=near_tol, u24=u24)
+        oracle.lepton_step(tables, prm, F, E, G, ctr, nthreads)
+        near_e |= E.near.astype(bool)
+        if pair:
+            oracle.lepton_step(tables, prm, F, P, G, ctr, nthreads)
+            near_p |= P.near.astype(bool)
+            oracle.photon_step(tables, prm, F, G, E, P, ctr, nthreads)
+            near_g |= G.near.astype(bool)
+    return dict(E=E, P=P, G=G, ctr=ctr.as_dict(), near_e=near_e[:E.n], near_p=near_p[:P.n], near_g=near_g[:G.n])
+
+
+def oracle_eps():
+    import synth
+    return synth.EPS_R
+
+
+def rel_vec_err(a, b, floor=1e-300):
+    """per-column |a - b| / max(|b|, floor) for (3, n) arrays"""
+    return np.linalg.norm(a - b, axis=0) / np.maximum(np.linalg.norm(b, axis=0), floor)
+
+
+def compare_leptons(gpu, orc, exclude, rtol_p, atol_s, rtol_x=None, what=""):
+    xg, pg, sg = gpu
+    xo, po, so = orc
+    assert pg.shape == po.shape, f"{what}: count {pg.shape[1]} vs oracle {po.shape[1]}"
+    keep = ~exclude
+    ep = rel_vec_err(pg[:, keep], po[:, keep])
+    es = np.linalg.norm(sg[:, keep] - so[:, keep], axis=0)
+    worst = dict(p=float(ep.max(initial=0)), s=float(es.max(initial=0)))
+    assert worst["p"] <= rtol_p, f"{what}: momentum rel err {worst['p']:.3e} (argmax {int(np.argmax(ep))})"
+    assert worst["s"] <= atol_s, f"{what}: spin err {worst['s']:.3e} (argmax {int(np.argmax(es))})"
+    if rtol_x is not None:
+        ex = np.abs(xg[:, keep] - xo[:, keep]).max(axis=0) / np.maximum(np.abs(xo[:, keep]).max(axis=0), 1.0)
+        worst["x"] = float(ex.max(initial=0))
+        assert worst["x"] <= rtol_x, f"{what}: position err {worst['x']:.3e}"
+    return worst
+
+
+def photon_parent(ids):
+    ids = ids.astype(np.uint64)
+    return ((ids >> np.uint64(61)) & np.uint64(3)).astype(np.int64), \
+        ((ids >> np.uint64(24)) & np.uint64((1 << 37) - 1)).astype(np.int64)
+
+
+def compare_photons(gpu, orc, excluded_parents, rtol_k, atol_P, what="", near_photons=None):
+    """Match live photons by id; ids absent on one side must belong to excluded parents."""
+    xg, kg, Pg, idg = gpu
+    xo, ko, Po, ido = orc
+    lg, lo = idg != 0, ido != 0
+    ig, io = idg[lg], ido[lo]
+    assert len(np.unique(ig)) == ig.size and len(np.unique(io)) == io.size, f"{what}: duplicate ids"
+    common, cg, co = np.intersect1d(ig, io, return_indices=True)
+    only = np.setxor1d(ig, io)
+    if only.size:
+        sp, pi = photon_parent(only)
+        bad = [(int(a), int(b)) for a, b in zip(sp, pi) if (int(a), int(b)) not in excluded_parents]
+        assert not bad, f"{what}: {only.size} unmatched photons, e.g. parents {bad[:5]}"
+    sp, pi = photon_parent(common)
+    keep = np.array([(int(a), int(b)) not in excluded_parents for a, b in zip(sp, pi)], dtype=bool)
+    if near_photons is not None:
+        keep &= ~np.isin(common, near_photons)
+    kgs, kos = kg[:, lg][:, cg][:, keep], ko[:, lo][:, co][:, keep]
+    Pgs, Pos = Pg[:, lg][:, cg][:, keep], Po[:, lo][:, co][:, keep]
+    ek = rel_vec_err(kgs, kos)
+    eP = np.linalg.norm(Pgs - Pos, axis=0)
+    worst = dict(k=float(ek.max(initial=0)), P=float(eP.max(initial=0)), matched=int(keep.sum()),
+                 unmatched=int(only.size))
+    assert worst["k"] <= rtol_k, f"{what}: photon momentum rel err {worst['k']:.3e}"
+    assert worst["P"] <= atol_P, f"{what}: photon P-vector err {worst['P']:.3e}"
+    return worst

@@ -1,0 +1,295 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle, particle by particle, on the
+same seeded inputs and Philox counters.
+
+Tolerances (written here, derived in the design notes): FP64 path 1e-12 relative on momenta,
+1e-12 absolute on spins and P-vectors (|s|, |P| <= 1); FP32 path 1e-5.  Decisions are compared
+exactly except for particles whose uniform draw fell within a relative 1e-10 (FP64) / 1e-5
+(FP32) of a threshold (reported by the oracle); their count is asserted to be tiny and reported.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from parity import compare_leptons, compare_photons, oracle_run, photon_parent, rel_vec_err
+
+pytestmark = pytest.mark.gpu
+EPS = synth.EPS_R
+
+
+@pytest.fixture(scope="module")
+def q():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("GPU test run without a GPU")
+    import paper_2511_08929_amd as q
+    q.lib()
+    return q
+
+
+@pytest.fixture(scope="module")
+def gtab64(q):
+    return q.Tables(precision=q.QED_F64)
+
+
+@pytest.fixture(scope="module")
+def gtab32(q):
+    return q.Tables(precision=q.QED_F32)
+
+
+def _sim(q, tab, w, cap_e, cap_p, cap_g, flags, seed=None, k_retire=None, fields=None):
+    from paper_2511_08929_amd.sim import Simulation
+    f = fields or q.make_fields(w.field_kind, E0=w.E0, B0=w.B0, a0=w.a0, phase_len=w.phase_len)
+    return Simulation(tab, cap_e=cap_e, cap_p=cap_p, cap_g=cap_g, track=w.track, fields=f, dt=w.dt, eps_r=EPS,
+                      seed=w.seed if seed is None else seed, flags=flags,
+                      k_retire=w.k_retire if k_retire is None else k_retire)
+
+
+def _random_leptons(n, seed, gmin=300.0, gmax=8000.0, mixed=True):
+    rng = np.random.default_rng(seed)
+    d = synth.random_unit_vectors(rng, n)
+    g = np.exp(rng.uniform(math.log(gmin), math.log(gmax), n))
+    p = d * np.sqrt(g * g - 1)
+    s = synth.random_unit_vectors(rng, n)
+    if mixed:
+        s *= np.where(rng.random(n) < 0.2, rng.uniform(0, 1, n), 1.0)
+    x = np.stack([rng.uniform(0, 200, n), rng.uniform(-5, 5, n), rng.uniform(-5, 5, n)])
+    return x, p, s
+
+
+def _workload_uniform(n, dt, B0=(0.0, 0.0, 160.0), E0=(0.0, 40.0, 0.0), seed=21):
+    w = synth.Workload("random_leptons_uniform_field", n, 1, dt, seed, synth.FIELD_UNIFORM, E0=E0, B0=B0,
+                       track=(True, True, True))
+    w.x, w.p, w.s = _random_leptons(n, seed)
+    return w
+
+
+# ------------------------------------------------------------------ tables
+def test_tables_match_oracle(gtab64, otables):
+    lnrate, nu = gtab64.download()
+    assert lnrate.shape == otables._lnrate.shape and nu.shape == otables._nu.shape
+    d_rate = np.abs(lnrate - otables._lnrate).max()
+    d_nu = (np.abs(nu - otables._nu) / np.maximum(1.0, np.abs(otables._nu))).max()
+    print(f"table parity: max |d ln rate| = {d_rate:.2e}, max rel |d nu| = {d_nu:.2e}")
+    assert d_rate < 1e-13
+    assert d_nu < 1e-12
+
+
+# ------------------------------------------------------------------ single steps, FP64
+@pytest.mark.parametrize("field", ["uniform", "plane"])
+def test_lepton_step_fp64(q, gtab64, otables, field):
+    n = 1000                                  # ragged: not a multiple of 64
+    w = _workload_uniform(n, dt=0.5)
+    if field == "plane":
+        w.field_kind, w.a0, w.phase_len, w.E0, w.B0 = synth.FIELD_PLANE_LP, 300.0, 400.0, (0, 0, 0), (0, 0, 0)
+        w.dt = 0.2
+    flags = q.QED_ALL & ~q.QED_PAIR
+    sim = _sim(q, gtab64, w, n, 1, 2 * n, flags, k_retire=0.0)
+    sim.e.load(w.x, w.p, w.s)
+    sim.step()
+    ref = oracle_run(otables, w, 1, flags, cap_g=2 * n, k_retire=0.0)
+    assert ref["ctr"]["n_emit"] > 100
+    ex = ref["near_e"]
+    assert ex.sum() <= 2
+    print("near ties", int(ex.sum()), "counters", q.counters_dict(sim.ctr), ref["ctr"])
+    compare_leptons(sim.e.arrays(), ref["E"].arrays(), ex, 1e-12, 1e-12, rtol_x=1e-12, what="leptons")
+    excl = {(0, int(i)) for i in np.nonzero(ex)[0]}
+    compare_photons(sim.g.arrays(), ref["G"].arrays(), excl, 1e-12, 1e-12, what="photons")
+    c = q.counters_dict(sim.ctr)
+    assert c["n_emit"] == ref["ctr"]["n_emit"] and c["n_prob_clamped"] == ref["ctr"]["n_prob_clamped"]
+
+
+def _photon_inputs(n, seed, chi_target=2.0):
+    rng = np.random.default_rng(seed)
+    d = synth.random_unit_vectors(rng, n)
+    k0 = np.exp(rng.uniform(math.log(2e3), math.log(2e4), n))
+    k = d * k0
+    P = synth.random_unit_vectors(rng, n) * np.where(rng.random(n) < 0.3, rng.uniform(0, 1, n), 1.0)
+    x = np.stack([rng.uniform(0, 10, n), rng.uniform(0, 10, n), rng.uniform(0, 10, n)])
+    ids = (np.uint64(1) << np.uint64(63)) | (np.arange(n, dtype=np.uint64) << np.uint64(24)) | np.uint64(3)
+    return x, k, P, ids
+
+
+def test_photon_step_fp64(q, gtab64, otables):
+    n = 1500
+    x, k, P, ids = _photon_inputs(n, 31)
+    B0 = (0.0, 0.0, 2.0 / (EPS * 1e4))             # chi_gamma ~ 2 |k_perp| / 1e4
+    w = synth.Workload("photons_uniform_B", 0, 1, 0.05, 4, synth.FIELD_UNIFORM, B0=B0, track=(True, True, True))
+    flags = q.QED_ALL
+    sim = _sim(q, gtab64, w, 2 * n, 2 * n, n, flags, k_retire=0.0)
+    import torch
+    for i in range(3):
+        sim.g.x[i][:n] = torch.as_tensor(x[i]); sim.g.k[i][:n] = torch.as_tensor(k[i])
+        sim.g.P[i][:n] = torch.as_tensor(P[i])
+    sim.g.id[:n] = torch.as_tensor(ids.view(np.int64))
+    sim.g.count.fill_(n); sim.g.count_prev.fill_(n)
+    sp = sim.step_params(0)
+    q.qed_pair(gtab64, sim.g, sim.fields, sp, sim.e, sim.p, sim.ctr, sim.ws)
+    # oracle
+    G = oracle.PhotonSet(n, track=w.track)
+    for i in range(3):
+        G.x[i][:n], G.k[i][:n], G.P[i][:n] = x[i], k[i], P[i]
+    G.id[:n] = ids; G.n = G.n_prev = n
+    Le, Lp = oracle.LeptonSet(0, 2 * n), oracle.LeptonSet(1, 2 * n)
+    ctr = oracle.Counters()
+    prm = oracle.make_params(w.dt, EPS, step=0, seed=w.seed, flags=flags, near_tol=1e-10)
+    oracle.photon_step(otables, prm, oracle.make_fields(w.field_kind, B0=B0), G, Le, Lp, ctr)
+    print("pairs", ctr.n_pair, "near", int(G.near[:n].sum()), q.counters_dict(sim.ctr))
+    assert ctr.n_pair > 100 and int(G.near[:n].sum()) == 0
+    assert sim.g.count_prev.item() == sim.g.count.item() == n
+    xg, kg, Pg, idg = sim.g.arrays()
+    np.testing.assert_array_equal(idg, G.id[:n])                      # same decays (dead slots)
+    live = idg != 0
+    assert np.linalg.norm(Pg[:, live] - np.stack(G.P)[:, :n][:, live], axis=0).max() < 1e-12
+    assert np.abs(xg - np.stack(G.x)[:, :n]).max() < 1e-12 * 20
+    compare_leptons(sim.e.arrays(), Le.arrays(), np.zeros(Le.n, bool), 1e-12, 1e-12, rtol_x=1e-12, what="electrons")
+    compare_leptons(sim.p.arrays(), Lp.arrays(), np.zeros(Lp.n, bool), 1e-12, 1e-12, rtol_x=1e-12, what="positrons")
+    assert q.counters_dict(sim.ctr)["n_pair"] == ctr.n_pair
+
+
+# ------------------------------------------------------------------ whole runs, FP64
+def test_c1_run_fp64(q, gtab64, otables):
+    """Test-particle workload (gamma0 = 2000, chi = 1, W dt ~ 0.95 and > 1 once cooled), all
+    1000 steps, 2048 electrons, every particle and photon compared."""
+    w = synth.c1(n=2048)
+    flags = q.QED_ALL & ~q.QED_PAIR
+    cap_g = w.n * w.steps
+    sim = _sim(q, gtab64, w, w.n, 1, cap_g, flags)
+    sim.e.load(w.x, w.p, w.s)
+    for _ in range(w.steps):
+        sim.step()
+    ref = oracle_run(otables, w, w.steps, flags, cap_g=cap_g)
+    ex = ref["near_e"]
+    print("near-tie particles", int(ex.sum()), "counters", q.counters_dict(sim.ctr), ref["ctr"])
+    assert ex.sum() <= 2
+    worst = compare_leptons(sim.e.arrays(), ref["E"].arrays(), ex, 1e-12, 1e-12, what="c1 leptons")
+    excl = {(0, int(i)) for i in np.nonzero(ex)[0]}
+    wp = compare_photons(sim.g.arrays(), ref["G"].arrays(), excl, 1e-12, 1e-12, what="c1 photons")
+    print("worst", worst, wp)
+    assert wp["matched"] > 1_000_000
+
+
+def test_c1_full_size_sampled(q, gtab64, otables):
+    """Full 10^4-electron, 1000-step run on the GPU; the oracle recomputes 128 sampled electrons
+    (with their original Philox ids) and their photons."""
+    w = synth.c1()
+    flags = q.QED_ALL & ~q.QED_PAIR
+    cap_g = w.n * w.steps
+    sim = _sim(q, gtab64, w, w.n, 1, cap_g, flags)
+    sim.e.load(w.x, w.p, w.s)
+    for _ in range(w.steps):
+        sim.step()
+    idx = np.sort(np.random.default_rng(99).choice(w.n, 128, replace=False))
+    sub = synth.subsample(w, idx)
+    ref = oracle_run(otables, sub, w.steps, flags, cap_g=128 * w.steps, index=idx)
+    x, p, s = sim.e.arrays()
+    compare_leptons((x[:, idx], p[:, idx], s[:, idx]), ref["E"].arrays(), ref["near_e"], 1e-12, 1e-12, what="sampled")
+    xg, kg, Pg, idg = sim.g.arrays()
+    sp, par = photon_parent(idg)
+    mine = np.isin(par, idx) & (idg != 0)
+    compare_photons((xg[:, mine], kg[:, mine], Pg[:, mine], idg[mine]), ref["G"].arrays(),
+                    {(0, int(i)) for i in idx[ref["near_e"]]}, 1e-12, 1e-12, what="sampled photons")
+
+
+def test_c2_small_run_fp64(q, gtab64, otables):
+    """Head-on collision workload at 400 electrons through the whole pulse (1700 steps), both
+    channels: every lepton, pair-born lepton and photon compared."""
+    w = synth.subsample(synth.c2(), np.arange(400))
+    w.steps = 1700
+    flags = q.QED_ALL
+    cap_g, cap_p = 60_000, 2_000
+    sim = _sim(q, gtab64, w, w.n + cap_p, cap_p, cap_g, flags)
+    sim.e.load(w.x, w.p, w.s)
+    for k in range(w.steps):
+        sim.step()
+        if k % 200 == 199:
+            sim.compact()
+    ref = oracle_run(otables, w, w.steps, flags, cap_e=w.n + cap_p, cap_p=cap_p, cap_g=cap_g)
+    c = q.counters_dict(sim.ctr)
+    print("gpu counters", c, "oracle", ref["ctr"], "near", int(ref["near_e"].sum()), int(ref["near_g"].sum()))
+    assert ref["near_e"].sum() == 0 and ref["near_g"].sum() == 0
+    assert c["n_emit"] == ref["ctr"]["n_emit"] and c["n_pair"] == ref["ctr"]["n_pair"]
+    compare_leptons(sim.e.arrays(), ref["E"].arrays(), np.zeros(ref["E"].n, bool), 1e-12, 1e-12, rtol_x=1e-12,
+                    what="c2 electrons")
+    compare_leptons(sim.p.arrays(), ref["P"].arrays(), np.zeros(ref["P"].n, bool), 1e-12, 1e-12, rtol_x=1e-12,
+                    what="c2 positrons")
+    compare_photons(sim.g.arrays(), ref["G"].arrays(), set(), 1e-12, 1e-12, what="c2 photons")
+
+
+# ------------------------------------------------------------------ single precision
+def test_lepton_and_photon_step_fp32(q, gtab32, otables):
+    n = 1000
+    w = _workload_uniform(n, dt=0.5)
+    w.x, w.p, w.s = (a.astype(np.float32).astype(np.float64) for a in (w.x, w.p, w.s))
+    flags = q.QED_ALL & ~q.QED_PAIR
+    sim = _sim(q, gtab32, w, n, 1, 2 * n, flags, k_retire=0.0)
+    sim.e.load(w.x, w.p, w.s)
+    sim.step()
+    ref = oracle_run(otables, w, 1, flags, cap_g=2 * n, k_retire=0.0, u24=True, near_tol=1e-5)
+    ex = ref["near_e"]
+    print("fp32 near-tie fraction", ex.mean())
+    assert ex.mean() < 0.01
+    compare_leptons(sim.e.arrays(), ref["E"].arrays(), ex, 1e-5, 1e-5, what="fp32 leptons")
+    compare_photons(sim.g.arrays(), ref["G"].arrays(), {(0, int(i)) for i in np.nonzero(ex)[0]}, 1e-5, 1e-5,
+                    what="fp32 photons")
+
+
+# ------------------------------------------------------------------ bookkeeping edge cases
+def test_capacity_overflow_and_empty(q, gtab64, otables):
+    import torch
+    n = 700
+    w = _workload_uniform(n, dt=0.5)
+    flags = q.QED_ALL & ~q.QED_PAIR
+    sim = _sim(q, gtab64, w, n, 1, 300, flags, k_retire=0.0)
+    guard = q.PhotonBuffers(300 + 64, sim.dtype, track=w.track)      # 64 guard slots past the capacity
+    guard.capacity = 300
+    sim.g = guard
+    sim.e.load(w.x, w.p, w.s)
+    sim.step()
+    c = q.counters_dict(sim.ctr)
+    assert sim.g.n() == 300 and c["n_capacity_overflow"] == c["n_emit"] - 300 > 0
+    for arrs in (sim.g.k, sim.g.P):
+        for a in arrs:
+            assert torch.all(a[300:] == 0)
+    assert torch.all(sim.g.id[300:] == 0)
+    # empty lepton set and empty photon set: nothing happens, nothing faults
+    sim.e.count.fill_(0)
+    sim.flags = q.QED_ALL
+    sim.step()
+    assert sim.g.n() == 300
+    torch.cuda.synchronize()
+
+
+def test_compaction_preserves_order(q, gtab64):
+    import torch
+    w = synth.c1(n=640)
+    flags = q.QED_ALL & ~q.QED_PAIR
+    sim = _sim(q, gtab64, w, w.n, 1, 640 * 5, flags, k_retire=30.0)
+    sim.e.load(w.x, w.p, w.s)
+    for _ in range(5):
+        sim.step()
+    x0, k0, P0, id0 = sim.g.arrays()
+    live = id0 != 0
+    assert 0 < live.sum() < id0.size
+    sim.compact()
+    x1, k1, P1, id1 = sim.g.arrays()
+    assert sim.g.count_prev.item() == live.sum()
+    np.testing.assert_array_equal(id1, id0[live])
+    np.testing.assert_array_equal(k1, k0[:, live])
+    np.testing.assert_array_equal(P1, P0[:, live])
+
+
+def test_bitwise_reproducible(q, gtab64):
+    w = synth.subsample(synth.c2(), np.arange(3000))
+    out = []
+    for _ in range(2):
+        sim = _sim(q, gtab64, w, w.n + 4000, 4000, 200_000, q.QED_ALL)
+        sim.e.load(w.x, w.p, w.s)
+        for _ in range(900):
+            sim.step()
+        out.append((sim.e.arrays(), sim.g.arrays(), q.counters_dict(sim.ctr)))
+    for a, b in zip(out[0][0] + out[0][1], out[1][0] + out[1][1]):
+        np.testing.assert_array_equal(a, b)
+    assert out[0][2] == out[1][2]
