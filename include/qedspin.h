@@ -142,8 +142,17 @@ typedef struct {
 
 typedef struct {                /* device-resident, accumulated */
     unsigned long long n_emit, n_pair, n_prob_clamped, n_chi_clamped, n_norm_clamped,
-                       n_capacity_overflow, n_retired, n_pad;
+                       n_capacity_overflow, n_retired,
+                       n_lepton_steps,   /* leptons stepped by qed_emit */
+                       n_photon_steps,   /* live photons stepped by qed_pair */
+                       n_photon_qed;     /* of those, photons with chi_gamma >= chi_g_min (full NBW step) */
 } qed_counters;
+
+typedef struct {
+    const char *name;           /* kernel name (library-owned string) */
+    long long   calls;
+    double      total_ms;       /* sum of launch durations measured with HIP events on the launch stream */
+} qed_kernel_time;
 
 /* Build the rate tables ln int_0^1 w dlam (spin-down, spin-up; xi3 = -1, +1) and inverse-CDF
    tables nu = ln(lam/(1-lam)) at rho = ln(r/(1-r)) on the given grid, by quadrature on the GPU
@@ -151,6 +160,10 @@ typedef struct {                /* device-resident, accumulated */
    xi3 = -1, +1).  Allocates device memory; synchronizes the stream.  Returns QED_ERR_INVALID
    for a NULL pointer or a grid with fewer than 4 nodes per axis. */
 qed_status qed_init_tables(const qed_table_params *params, qed_stream stream, qed_tables *out);
+
+/* Text of the HIP error behind the most recent QED_ERR_HIP returned on this thread
+   ("" if none).  The string is owned by the library. */
+const char *qed_last_error(void);
 
 /* Release the tables (device memory).  Safe on NULL. */
 qed_status qed_free_tables(qed_tables tables);
@@ -192,6 +205,13 @@ qed_status qed_pair(qed_tables tables, const qed_photons *photons, const qed_fie
 size_t qed_compact_workspace_size(const qed_photons *photons, qed_precision precision);
 qed_status qed_compact(const qed_photons *photons, qed_precision precision, void *workspace,
                        size_t workspace_bytes, qed_stream stream);
+
+/* Kernel timing for measurement tools: qed_profile_start clears the record and brackets every
+   subsequent launch with HIP events on its stream; qed_profile_stop synchronizes on them, writes
+   up to max_entries per-kernel totals and the number of kernels seen, and stops recording.
+   Process-wide and not thread-safe. */
+qed_status qed_profile_start(void);
+qed_status qed_profile_stop(qed_kernel_time *out, int max_entries, int *n_entries);
 
 #ifdef __cplusplus
 }

@@ -366,7 +366,8 @@ static double nlc_tail(double chi, double lam)
 
 typedef struct {
     int ch; double chi;
-    int np; double a0, h, b_end;
+    int np; double a0, b_end;
+    double *edge_nu;        /* panel boundaries, np + 1 */
     double *left, *right;   /* cumulative integrals at panel edges */
     double tail, total;
 } cdf_ctx;
@@ -378,34 +379,50 @@ static double gl_panel(int ch, double chi, double a, double b)
     return half * s;
 }
 
+/* Integration range in nu and the local decay rate |d u'/d nu| of the density's e^{-u'} factor.
+   The range stops where u' exceeds its smallest value by 80 (the mass beyond is < e^-80 of
+   the total); panel widths keep |d u'/d nu| * width <= 2 so every panel is smooth. */
 static void nu_range(int ch, double chi, double *a, double *b)
 {
     if (ch < 2) {
-        /* u' = 2 e^nu / (3 chi) reaches the Bessel cut-off at nu = ln(1.5 chi x_max) */
+        /* u' = 2 e^nu / (3 chi) */
         *a = NLC_NU_LO;
-        *b = log(1.5 * chi * BESSEL_XMAX);
+        *b = log(1.5 * chi * 80.0);
     } else {
-        /* u~' = 2 (2 + 2 cosh nu)/(3 chi) reaches the cut-off at cosh nu = 0.75 chi x_max - 1 */
-        double c = 0.75 * chi * BESSEL_XMAX - 1.0;
-        double m = c > 1.0 ? acosh(c) : 0.0;
+        /* u~' = 4 (1 + cosh nu) / (3 chi), smallest 8 / (3 chi) at nu = 0 */
+        double c = 1.0 + 0.75 * chi * 80.0;
+        double m = acosh(c);
         *a = -m; *b = m;
     }
+}
+
+static double decay_rate(int ch, double chi, double nu)
+{
+    if (ch < 2) return 2.0 * exp(nu) / (3.0 * chi);
+    return 4.0 * fabs(sinh(nu)) / (3.0 * chi);
 }
 
 static void cdf_build(cdf_ctx *C, int ch, double chi)
 {
     C->ch = ch; C->chi = chi;
     nu_range(ch, chi, &C->a0, &C->b_end);
-    C->h = 1.0;
-    C->np = (int)ceil((C->b_end - C->a0) / C->h);
-    if (C->np < 1) C->np = 1;
+    int cap = 64;
+    C->edge_nu = (double *)malloc(sizeof(double) * cap);
+    C->np = 0;
+    double a = C->a0;
+    C->edge_nu[0] = a;
+    while (a < C->b_end) {
+        double w = 1.0;
+        while (w > 1.0 / 1024.0 && w * fmax(decay_rate(ch, chi, a), decay_rate(ch, chi, a + w)) > 2.0) w *= 0.5;
+        double b = fmin(a + w, C->b_end);
+        if (C->np + 2 > cap) { cap *= 2; C->edge_nu = (double *)realloc(C->edge_nu, sizeof(double) * cap); }
+        C->edge_nu[++C->np] = b;
+        a = b;
+    }
     C->left = (double *)malloc(sizeof(double) * (C->np + 1));
     C->right = (double *)malloc(sizeof(double) * (C->np + 1));
     double *pint = (double *)malloc(sizeof(double) * C->np);
-    for (int k = 0; k < C->np; ++k) {
-        double a = C->a0 + k * C->h, b = fmin(C->a0 + (k + 1) * C->h, C->b_end);
-        pint[k] = gl_panel(ch, chi, a, b);
-    }
+    for (int k = 0; k < C->np; ++k) pint[k] = gl_panel(ch, chi, C->edge_nu[k], C->edge_nu[k + 1]);
     C->tail = 0.0;
     if (ch < 2) { double l, o; lam_from_nu(C->a0, &l, &o); C->tail = nlc_tail(chi, l); }
     C->left[0] = C->tail;
@@ -416,9 +433,17 @@ static void cdf_build(cdf_ctx *C, int ch, double chi)
     free(pint);
 }
 
-static void cdf_free(cdf_ctx *C) { free(C->left); free(C->right); }
+static void cdf_free(cdf_ctx *C) { free(C->edge_nu); free(C->left); free(C->right); }
 
-static double edge(const cdf_ctx *C, int k) { return fmin(C->a0 + k * C->h, C->b_end); }
+static double edge(const cdf_ctx *C, int k) { return C->edge_nu[k]; }
+
+/* panel containing nu (a0 <= nu < b_end) */
+static int panel_of(const cdf_ctx *C, double nu)
+{
+    int lo = 0, hi = C->np;
+    while (hi - lo > 1) { int m = (lo + hi) / 2; if (C->edge_nu[m] <= nu) lo = m; else hi = m; }
+    return lo;
+}
 
 /* integral of the density over [a, b] inside one panel */
 static double partial(const cdf_ctx *C, double a, double b)
@@ -444,8 +469,7 @@ double orc_cdf(int ch, double chi, double lam)
     if (nu <= C.a0) r = (ch < 2) ? nlc_tail(chi, lam) / C.total : 0.0;
     else if (nu >= C.b_end) r = 1.0;
     else {
-        int k = (int)floor((nu - C.a0) / C.h);
-        if (k >= C.np) k = C.np - 1;
+        int k = panel_of(&C, nu);
         r = (C.left[k] + partial(&C, edge(&C, k), nu)) / C.total;
     }
     cdf_free(&C);
@@ -460,8 +484,7 @@ double orc_ccdf(int ch, double chi, double lam)
     if (nu >= C.b_end) r = 0.0;
     else if (nu <= C.a0) r = 1.0 - ((ch < 2) ? nlc_tail(chi, lam) / C.total : 0.0);
     else {
-        int k = (int)floor((nu - C.a0) / C.h);
-        if (k >= C.np) k = C.np - 1;
+        int k = panel_of(&C, nu);
         r = (C.right[k + 1] + partial(&C, nu, edge(&C, k + 1))) / C.total;
     }
     cdf_free(&C);
@@ -979,6 +1002,7 @@ static void add_counters(orc_counters *d, const orc_counters *s)
     d->n_chi_clamped += s->n_chi_clamped; d->n_norm_clamped += s->n_norm_clamped;
     d->n_capacity_overflow += s->n_capacity_overflow; d->n_retired += s->n_retired;
     d->n_near_threshold += s->n_near_threshold;
+    d->n_lepton_steps += s->n_lepton_steps; d->n_photon_steps += s->n_photon_steps;
 }
 
 int orc_lepton_step(const orc_tables *T, const orc_params *prm, const orc_fields *f,
@@ -998,6 +1022,7 @@ int orc_lepton_step(const orc_tables *T, const orc_params *prm, const orc_fields
         orc_counters loc = {0};
 #pragma omp for schedule(static)
         for (int64_t j = 0; j < n; ++j) {
+            loc.n_lepton_steps++;
             double x[3] = {getx(L->x, 0, j), getx(L->x, 1, j), getx(L->x, 2, j)};
             double p[3] = {L->p[0][j], L->p[1][j], L->p[2][j]};
             double s[3] = {L->s[0][j], L->s[1][j], L->s[2][j]};
@@ -1071,7 +1096,10 @@ int orc_photon_step(const orc_tables *T, const orc_params *prm, const orc_fields
                 x[i] = getx(G->x, i, j) + k[i] / k0 * prm->dt;
                 if (G->x[i]) G->x[i][j] = x[i];
             }
-            if (k0 < prm->k_retire) { G->id[j] = 0; loc.n_retired++; continue; }
+            loc.n_photon_steps++;
+            int behind = f->kind == ORC_FIELD_PLANE_LP && f->phase_len > 0.0 &&
+                         prm->t + prm->dt + x[0] > f->phase_len;
+            if (k0 < prm->k_retire || behind) { G->id[j] = 0; loc.n_retired++; continue; }
             double E[3], B[3];
             orc_fields_eval(f, x, prm->t + prm->dt, E, B);
             double P[3] = {G->P[0][j], G->P[1][j], G->P[2][j]};

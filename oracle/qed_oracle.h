@@ -113,7 +113,7 @@ typedef struct {
 
 typedef struct {
     int64_t n_emit, n_pair, n_prob_clamped, n_chi_clamped, n_norm_clamped,
-            n_capacity_overflow, n_retired, n_near_threshold;
+            n_capacity_overflow, n_retired, n_near_threshold, n_lepton_steps, n_photon_steps;
 } orc_counters;
 
 /* Lorentz (Boris) push + T-BMT rotation + position advance for one lepton. */
@@ -123,7 +123,9 @@ void orc_push_one(int charge, double a_e, const double E[3], const double B[3], 
 /* One whole lepton step (push with fields at t, QED with fields at t+dt) over L. */
 int orc_lepton_step(const orc_tables *T, const orc_params *prm, const orc_fields *f,
                     orc_leptons *L, orc_photons *G, orc_counters *ctr, int nthreads);
-/* One photon step over photons [0, G->n_prev); afterwards n_prev = n. */
+/* One photon step over photons [0, G->n_prev); afterwards n_prev = n.  A photon is retired
+   (dead slot) when |k| < k_retire or, for the plane-wave field with an envelope, when its
+   phase t + x is past the pulse's trailing end (the phase of a photon never decreases). */
 int orc_photon_step(const orc_tables *T, const orc_params *prm, const orc_fields *f,
                     orc_photons *G, orc_leptons *Le, orc_leptons *Lp, orc_counters *ctr,
                     int nthreads);

@@ -30,8 +30,9 @@ QED_ALL = (QED_PUSH | QED_TBMT | QED_EMIT | QED_RECOIL | QED_SPIN | QED_NOEMIT |
            | QED_PAIR | QED_NOPAIR | QED_PAIR_SPIN)
 QED_FIELD_UNIFORM, QED_FIELD_PLANE_LP = 0, 1
 
-ABI_SYMBOLS = ("qed_init_tables", "qed_free_tables", "qed_tables_download", "qed_workspace_size",
-               "qed_push_spin", "qed_emit", "qed_pair", "qed_compact_workspace_size", "qed_compact")
+ABI_SYMBOLS = ("qed_init_tables", "qed_last_error", "qed_free_tables", "qed_tables_download", "qed_workspace_size",
+               "qed_push_spin", "qed_emit", "qed_pair", "qed_compact_workspace_size", "qed_compact",
+               "qed_profile_start", "qed_profile_stop")
 
 
 class QedError(RuntimeError):
@@ -71,7 +72,11 @@ class StepParams(C.Structure):
 
 
 COUNTER_NAMES = ("n_emit", "n_pair", "n_prob_clamped", "n_chi_clamped", "n_norm_clamped",
-                 "n_capacity_overflow", "n_retired", "n_pad")
+                 "n_capacity_overflow", "n_retired", "n_lepton_steps", "n_photon_steps", "n_photon_qed")
+
+
+class KernelTime(C.Structure):
+    _fields_ = [("name", C.c_char_p), ("calls", C.c_longlong), ("total_ms", C.c_double)]
 
 _lib = None
 
@@ -83,10 +88,15 @@ def lib():
         if not LIB_PATH.exists():
             raise QedError(f"{LIB_PATH} is missing: build it with paper_2511_08929_amd/build.py "
                            "(there is no CPU fallback)")
+        # torch's HIP runtime must be the one resident in the process: it is loaded under the
+        # same soname, so libqedspin.so then binds to it instead of a second copy
+        import torch  # noqa: F401
         L = C.CDLL(str(LIB_PATH))
         P, vp, i64, sz = C.POINTER, C.c_void_p, C.c_int64, C.c_size_t
         L.qed_init_tables.argtypes = [P(TableParams), vp, P(vp)]
         L.qed_free_tables.argtypes = [vp]
+        L.qed_last_error.argtypes = []
+        L.qed_last_error.restype = C.c_char_p
         L.qed_tables_download.argtypes = [vp, vp, P(i64), vp, P(i64)]
         L.qed_workspace_size.argtypes = [i64]; L.qed_workspace_size.restype = sz
         L.qed_push_spin.argtypes = [P(Leptons), P(Fields), P(StepParams), vp, vp]
@@ -94,8 +104,10 @@ def lib():
         L.qed_pair.argtypes = [vp, P(Photons), P(Fields), P(StepParams), P(Leptons), P(Leptons), vp, vp, sz, vp]
         L.qed_compact_workspace_size.argtypes = [P(Photons), C.c_int]; L.qed_compact_workspace_size.restype = sz
         L.qed_compact.argtypes = [P(Photons), C.c_int, vp, sz, vp]
+        L.qed_profile_start.argtypes = []
+        L.qed_profile_stop.argtypes = [P(KernelTime), C.c_int, P(C.c_int)]
         for name in ABI_SYMBOLS:
-            if name not in ("qed_workspace_size", "qed_compact_workspace_size"):
+            if name not in ("qed_workspace_size", "qed_compact_workspace_size", "qed_last_error"):
                 getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -103,7 +115,8 @@ def lib():
 
 def _check(status, what):
     if status != QED_OK:
-        raise QedError(f"{what} failed with status {status}")
+        detail = lib().qed_last_error().decode() if status == QED_ERR_HIP else ""
+        raise QedError(f"{what} failed with status {status} {detail}")
 
 
 def _stream_ptr(stream=None):
@@ -192,12 +205,15 @@ class LeptonBuffers:
         self.count.fill_(n)
 
     def view(self):
+        if getattr(self, "_view", None) is not None and self._view.capacity == self.capacity:
+            return self._view
         v = Leptons()
         v.capacity, v.d_count, v.species = self.capacity, self.count.data_ptr(), self.species
         for i in range(3):
             v.x[i] = self.x[i].data_ptr() if self.x[i] is not None else None
             v.p[i] = self.p[i].data_ptr()
             v.s[i] = self.s[i].data_ptr()
+        self._view = v
         return v
 
     def n(self):
@@ -223,6 +239,8 @@ class PhotonBuffers:
         self.count_prev = torch.zeros(1, dtype=torch.int64, device=device)
 
     def view(self):
+        if getattr(self, "_view", None) is not None and self._view.capacity == self.capacity:
+            return self._view
         v = Photons()
         v.capacity, v.d_count, v.d_count_prev = self.capacity, self.count.data_ptr(), self.count_prev.data_ptr()
         for i in range(3):
@@ -230,6 +248,7 @@ class PhotonBuffers:
             v.k[i] = self.k[i].data_ptr()
             v.P[i] = self.P[i].data_ptr()
         v.id = self.id.data_ptr()
+        self._view = v
         return v
 
     def n(self):
@@ -307,3 +326,15 @@ def counters_dict(ctr):
 def new_workspace(nbytes, device="cuda"):
     import torch
     return torch.empty(int(nbytes), dtype=torch.uint8, device=device)
+
+
+def qed_profile_start():
+    _check(lib().qed_profile_start(), "qed_profile_start")
+
+
+def qed_profile_stop():
+    """{kernel name: (calls, total ms)} of the launches since qed_profile_start."""
+    buf = (KernelTime * 32)()
+    n = C.c_int()
+    _check(lib().qed_profile_stop(buf, 32, C.byref(n)), "qed_profile_stop")
+    return {buf[i].name.decode(): (int(buf[i].calls), float(buf[i].total_ms)) for i in range(min(n.value, 32))}

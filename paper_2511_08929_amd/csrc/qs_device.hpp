@@ -121,6 +121,39 @@ __device__ inline Bessel3 bessel3_scaled(double x)
     return o;
 }
 
+// Ratios K_1/3 / K_2/3 and IntK_1/3 / K_2/3 at x: all the spin and polarization collapse needs.
+// Double: from the FP64 trapezoid above.  Single: the same rule in FP32 with step 0.4 (error
+// ~e^{-pi^2/0.4} = 2e-11) or 1/sqrt(x), truncated at e^{-22} (2.8e-10 of the peak term).
+template <class R> __device__ __forceinline__ void bessel_ratios(double x, R &K1, R &I);
+
+template <> __device__ __forceinline__ void bessel_ratios<double>(double x, double &K1, double &I)
+{
+    const Bessel3 b = bessel3_scaled(x);
+    K1 = b.k13 / b.k23;
+    I = b.ik / b.k23;
+}
+
+template <> __device__ __forceinline__ void bessel_ratios<float>(double xd, float &K1, float &I)
+{
+    const float x = fmaxf((float)xd, 1e-30f);
+    const float h = fminf(0.4f, rsqrtf(x));
+    float s13 = 0.5f, s23 = 0.5f, sik = 0.5f;
+    for (int j = 1; j < 4096; ++j) {
+        const float t = j * h;
+        const float sh = sinhf(0.5f * t);
+        const float chm1 = 2.0f * sh * sh;
+        const float e = expf(-x * chm1);
+        const float z = expf(t * (1.0f / 3.0f)), zi = 1.0f / z;
+        const float c1 = 0.5f * (z + zi), c2 = 0.5f * (z * z + zi * zi);
+        s13 += e * c1;
+        s23 += e * c2;
+        sik += e * c1 / (1.0f + chm1);
+        if (x * chm1 > 22.0f && x * (1.0f + chm1) > 22.0f) break;
+    }
+    K1 = s13 / s23;
+    I = sik / s23;
+}
+
 // ------------------------------------------------------------------ fields
 struct FieldDev {
     int kind;
@@ -259,13 +292,23 @@ template <class R> __device__ __forceinline__ V3<R> stokes_to_P(R x1, R x2, R x3
 {
     const R d = sqrt_r(x1 * x1 + x2 * x2 + x3 * x3);
     if (!(d > (R)0)) return {0, 0, 0};
-    const R id = (R)1 / d;
-    const R u1 = x1 * id, u2 = x2 * id, u3 = x3 * id;
-    const R dth = (R)0.5 * atan2(u1, u3);
-    R tr = (R)1 - u2 * u2;
-    tr = sqrt_r(tr > (R)0 ? tr : (R)0);
-    const R ce = d * tr * cos(dth), cb = d * tr * sin(dth), ck = d * u2;
-    return ce * bs.e + cb * bs.b + ck * bs.k;
+    // transverse part: length sqrt(x1^2 + x3^2), at half the Stokes angle 2 dth = atan2(x1, x3),
+    // from the half-angle formulas (cos dth >= 0 on the principal branch); the cancelling
+    // square root is avoided by dividing by the larger of the two
+    const R tr = sqrt_r(x1 * x1 + x3 * x3);
+    R c = (R)1, sn = (R)0;
+    if (tr > (R)0) {
+        const R cth = x3 / tr, sth = x1 / tr;
+        if (cth >= (R)0) {
+            c = sqrt_r((R)0.5 * ((R)1 + cth));
+            sn = sth / ((R)2 * c);
+        } else {
+            sn = sqrt_r((R)0.5 * ((R)1 - cth));
+            sn = sth < (R)0 ? -sn : sn;
+            c = sth / ((R)2 * sn);
+        }
+    }
+    return (tr * c) * bs.e + (tr * sn) * bs.b + x2 * bs.k;
 }
 
 template <class R> __device__ __forceinline__ void P_to_stokes(V3<R> P, const Basis<R> &bs, R &x1, R &x2, R &x3)

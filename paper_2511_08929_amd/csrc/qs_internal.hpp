@@ -29,8 +29,37 @@ struct qed_tables_s {
     int64_t n_rate, n_nu;
 };
 
-#define QS_CHECK(expr)                                 \
-    do {                                               \
-        hipError_t e_ = (expr);                        \
-        if (e_ != hipSuccess) return QED_ERR_HIP;      \
+// Record the error text of a failed HIP call for qed_last_error() and map it to QED_ERR_HIP.
+qed_status qs_fail(hipError_t e, const char *where);
+// Clear a stale error left in HIP's per-thread last-error slot by earlier, unrelated calls.
+inline void qs_clear_error() { (void)hipGetLastError(); }
+// Status after a sequence of launches.
+inline qed_status qs_launch_status(const char *where)
+{
+    const hipError_t e = hipGetLastError();
+    return e == hipSuccess ? QED_OK : qs_fail(e, where);
+}
+
+#define QS_CHECK(expr)                                   \
+    do {                                                 \
+        hipError_t e_ = (expr);                          \
+        if (e_ != hipSuccess) return qs_fail(e_, #expr); \
+    } while (0)
+
+// ---------------------------------------------------------------- kernel timing
+// With profiling on (qed_profile_start), every launch is bracketed by two HIP events recorded on
+// the launch stream; qed_profile_stop synchronizes and reports per-kernel calls and time.
+enum QsKernel {
+    K_TABLES = 0, K_PUSH, K_LEPTON_MAIN, K_EMIT_PROCESS, K_PHOTON_MAIN, K_PAIR_PROCESS, K_MASK_REDUCE, K_BOOK,
+    K_MASK_EXPAND, K_SET_PREV, K_ALIVE_MASK, K_GATHER, K_SCATTER_BACK, K_NKERNELS
+};
+extern bool g_qs_profiling;
+void qs_prof_begin(int kid, hipStream_t st);
+void qs_prof_end(int kid, hipStream_t st);
+
+#define QS_LAUNCH(kid, kernel, grid, block, lds, stream, ...)                        \
+    do {                                                                            \
+        if (g_qs_profiling) qs_prof_begin(kid, stream);                             \
+        hipLaunchKernelGGL(kernel, grid, block, lds, stream, __VA_ARGS__);          \
+        if (g_qs_profiling) qs_prof_end(kid, stream);                               \
     } while (0)

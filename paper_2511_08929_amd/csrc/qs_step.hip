@@ -23,8 +23,6 @@ namespace {
 using namespace qs;
 
 constexpr int kBlock = 256;
-constexpr int kChunksPerThread = 8;
-constexpr int kChunksPerBlock = kBlock * kChunksPerThread;   // mask words per reduce/expand block
 constexpr int kMaxGrid = 2048;                               // 256 CUs x 8 resident blocks
 
 template <class R> struct LepDev {
@@ -49,12 +47,14 @@ struct StepDev {
     uint32_t flags;
 };
 
-enum { C_EMIT = 0, C_PAIR, C_PROB, C_CHI, C_NORM, C_OVER, C_RETIRED, C_PAD };
+enum { C_EMIT = 0, C_PAIR, C_PROB, C_CHI, C_NORM, C_OVER, C_RETIRED, C_LSTEP, C_GSTEP, C_GQED, kNCtr };
 
 struct WS {
     uint64_t *mask;      // [2][nchunks]: transition, branch (up / plus)
-    uint32_t *bsum;      // [nblocks]
-    int64_t *book;       // [8]: base0, total, base1, n_fit
+    uint32_t *bcnt;      // [kMaxGrid]: transitions per block of the streaming pass
+    uint32_t *boff;      // [kMaxGrid]: their exclusive prefix sums
+    int64_t *book;       // [8]: base0, total, base1, n_fit, n processed, block range
+    uint32_t *bctr;      // [kMaxGrid][kNCtr]: per-block counts of the streaming pass
     uint32_t *idx;       // [max particles]
 };
 
@@ -64,12 +64,13 @@ inline size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 WS carve(void *ws, int64_t cap, int64_t *nchunks_out)
 {
     const int64_t nch = cdiv(cap > 0 ? cap : 1, 64);
-    const int64_t nblk = cdiv(nch, kChunksPerBlock);
     char *b = (char *)ws;
     WS w;
     w.mask = (uint64_t *)b; b += align256(sizeof(uint64_t) * 2 * nch);
-    w.bsum = (uint32_t *)b; b += align256(sizeof(uint32_t) * nblk);
+    w.bcnt = (uint32_t *)b; b += align256(sizeof(uint32_t) * kMaxGrid);
+    w.boff = (uint32_t *)b; b += align256(sizeof(uint32_t) * kMaxGrid);
     w.book = (int64_t *)b;  b += align256(sizeof(int64_t) * 8);
+    w.bctr = (uint32_t *)b; b += align256(sizeof(uint32_t) * kMaxGrid * kNCtr);
     w.idx = (uint32_t *)b;
     *nchunks_out = nch;
     return w;
@@ -135,11 +136,46 @@ template <class R> __device__ __forceinline__ void stx(R *const a[3], int64_t i,
     if (a[2]) a[2][i] = v.z;
 }
 
+// Contiguous partition of [0, n) over the grid of a streaming pass: block b owns
+// [b B, (b+1) B) with B a multiple of 64, so each 64-particle mask word belongs to one block and
+// the per-block transition counts are the scan input in particle order.
+__host__ __device__ __forceinline__ int64_t block_len(int64_t n, int64_t nblk)
+{
+    return ((cdiv(n, nblk > 0 ? nblk : 1) + 63) / 64) * 64;
+}
+
+// per-block totals of the streaming pass's counts and of its transitions, written (not
+// atomically added) to the workspace; the bookkeeping kernel reduces them
+__device__ __forceinline__ void block_counts(uint32_t *bctr, uint32_t *bcnt, const unsigned (&v)[kNCtr], unsigned ntrans)
+{
+    __shared__ unsigned red[kBlock / 64][kNCtr + 1];
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+    for (int c = 0; c < kNCtr; ++c) {
+        unsigned t = v[c];
+        for (int o = 32; o > 0; o >>= 1) t += __shfl_xor(t, o);
+        if (lane == 0) red[wid][c] = t;
+    }
+    if (lane == 0) red[wid][kNCtr] = ntrans;      // lane 0 holds its wave's transition count
+    __syncthreads();
+    if (threadIdx.x <= kNCtr) {
+        unsigned t = 0;
+        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) t += red[w][threadIdx.x];
+        if (threadIdx.x < kNCtr) bctr[blockIdx.x * kNCtr + threadIdx.x] = t;
+        else bcnt[blockIdx.x] = t;
+    }
+}
+
 __device__ __forceinline__ void wave_add(unsigned long long *ctr, int slot, unsigned v)
 {
     // reduce over the wave, one atomic per wave
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
     if ((threadIdx.x & 63) == 0 && v) atomicAdd(ctr + slot, (unsigned long long)v);
+}
+
+template <class R> __device__ __forceinline__ bool zero_field(V3<R> E, V3<R> B)
+{
+    return E.x == (R)0 && E.y == (R)0 && E.z == (R)0 && B.x == (R)0 && B.y == (R)0 && B.z == (R)0;
 }
 
 // ------------------------------------------------------------------ lepton QED: decision part
@@ -158,6 +194,12 @@ __device__ __forceinline__ LDecide<R> lepton_decide(const StepDev &S, const Tabl
                                                     int64_t index, V3<R> p, V3<R> s, V3<R> E, V3<R> B)
 {
     LDecide<R> d;
+    d.clamped_chi = false;
+    if (zero_field(E, B)) {           // outside the pulse: no QED, skip the FP64 island
+        d.active = false;
+        d.chi = 0.0;
+        return d;
+    }
     const int q = species == 0 ? -1 : 1;
     const double gam = sqrt(1.0 + dot(cvt<double>(p), cvt<double>(p)));
     d.chi = basis_chi(q, S.eps_r, p, gam, E, B, d.bs);
@@ -200,20 +242,22 @@ __global__ void __launch_bounds__(kBlock) k_push(LepDev<R> L, FieldDev F, StepDe
 
 template <class R>
 __global__ void __launch_bounds__(kBlock) k_lepton_main(LepDev<R> L, FieldDev F, StepDev S, TablesDev T,
-                                                        uint64_t *mask, int64_t nchunks, unsigned long long *ctr)
+                                                        uint64_t *mask, int64_t nchunks, uint32_t *bctr, uint32_t *bcnt)
 {
     extern __shared__ unsigned char smem_raw[];
     R *lds = reinterpret_cast<R *>(smem_raw);
     stage_rates<R>(T, 0, lds);
     const int64_t n = *L.count;
+    const int64_t B = block_len(n, gridDim.x);
+    const int64_t start = (int64_t)blockIdx.x * B, end = start + B < n ? start + B : n;
     const int q = L.species == 0 ? -1 : 1;
     const int lane = threadIdx.x & 63;
-    unsigned c_prob = 0, c_chi = 0, c_norm = 0;
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t base = (int64_t)blockIdx.x * blockDim.x + (threadIdx.x & ~63); base < n; base += stride) {
+    unsigned c_prob = 0, c_chi = 0, c_norm = 0, c_step = 0, ntrans = 0;
+    for (int64_t base = start + (threadIdx.x & ~63); base < end; base += blockDim.x) {
         const int64_t i = base + lane;
         bool emit = false, up = false;
-        if (i < n) {
+        if (i < end) {
+            ++c_step;
             V3<R> x = ldx(L.x, i), p = ld3(L.p, i), s = ld3(L.s, i);
             V3<R> E, B;
             if (S.flags & F_PUSH) {
@@ -253,11 +297,12 @@ __global__ void __launch_bounds__(kBlock) k_lepton_main(LepDev<R> L, FieldDev F,
         if (lane == 0) {
             mask[base >> 6] = m;
             mask[nchunks + (base >> 6)] = mu;
+            ntrans += __popcll(m);
         }
     }
-    wave_add(ctr, C_PROB, c_prob);
-    wave_add(ctr, C_CHI, c_chi);
-    wave_add(ctr, C_NORM, c_norm);
+    unsigned v[kNCtr] = {};
+    v[C_PROB] = c_prob; v[C_CHI] = c_chi; v[C_NORM] = c_norm; v[C_LSTEP] = c_step;
+    block_counts(bctr, bcnt, v, ntrans);
 }
 
 // emitter processing: lambda from the selected inverse CDF, recoil, spin collapse, Stokes
@@ -288,10 +333,9 @@ __global__ void __launch_bounds__(kBlock) k_emit_process(LepDev<R> L, PhoDev<R> 
         const V3<R> k = (R)lam_d * p;
         R r3, r4;
         Unif<R>::two(philox_block(S.seed, lepton_id(L.species, i), S.step, 1u), r3, r4);
-        const Bessel3 bz = bessel3_scaled(2.0 * u_d / (3.0 * d.chi));
         SpecPt<R> qp;
         qp.lam = (R)lam_d; qp.oml = (R)oml_d; qp.u = (R)u_d;
-        qp.K1 = (R)(bz.k13 / bz.k23); qp.I = (R)(bz.ik / bz.k23);
+        bessel_ratios<R>(2.0 * u_d / (3.0 * d.chi), qp.K1, qp.I);
         const V3<R> si = {dot(s, d.bs.e), dot(s, d.bs.b), dot(s, d.bs.k)};
         const R w = nlc_w(qp, si.y);
         const V3<R> g = nlc_g(qp, si);
@@ -352,6 +396,12 @@ __device__ __forceinline__ PDecide<R> photon_decide(const StepDev &S, const Tabl
                                                     V3<R> k, double k0, V3<R> P, V3<R> E, V3<R> B)
 {
     PDecide<R> d;
+    d.clamped_chi = false;
+    if (zero_field(E, B)) {
+        d.active = false;
+        d.chi = 0.0;
+        return d;
+    }
     d.chi = basis_chi(0, S.eps_r, k, k0, E, B, d.bs);
     d.active = d.chi >= S.chi_g_min;
     d.clamped_chi = d.chi > S.chi_g_max;
@@ -374,27 +424,33 @@ __device__ __forceinline__ PDecide<R> photon_decide(const StepDev &S, const Tabl
 
 template <class R>
 __global__ void __launch_bounds__(kBlock) k_photon_main(PhoDev<R> G, FieldDev F, StepDev S, TablesDev T, uint64_t *mask,
-                                                        int64_t nchunks, unsigned long long *ctr)
+                                                        int64_t nchunks, uint32_t *bctr, uint32_t *bcnt)
 {
     extern __shared__ unsigned char smem_raw[];
     R *lds = reinterpret_cast<R *>(smem_raw);
     stage_rates<R>(T, 1, lds);
     const int64_t n = *G.count_prev;
+    const int64_t B = block_len(n, gridDim.x);
+    const int64_t start = (int64_t)blockIdx.x * B, end = start + B < n ? start + B : n;
     const int lane = threadIdx.x & 63;
-    unsigned c_chi = 0, c_norm = 0, c_ret = 0, c_prob = 0;
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t base = (int64_t)blockIdx.x * blockDim.x + (threadIdx.x & ~63); base < n; base += stride) {
+    unsigned c_chi = 0, c_norm = 0, c_ret = 0, c_prob = 0, c_step = 0, c_qed = 0, ntrans = 0;
+    for (int64_t base = start + (threadIdx.x & ~63); base < end; base += blockDim.x) {
         const int64_t i = base + lane;
         bool pair = false, plus = false;
-        if (i < n) {
+        if (i < end) {
             const uint64_t id = G.id[i];
             if (id != 0) {
+                ++c_step;
                 const V3<R> k = ld3(G.k, i);
-                const double k0 = sqrt(dot(cvt<double>(k), cvt<double>(k)));
+                const R k0r = sqrt_r(dot(k, k));
+                const double k0 = (double)k0r;
                 V3<R> x = ldx(G.x, i);
-                x = x + (R)(S.dt / k0) * k;
+                x = x + ((R)S.dt / k0r) * k;
                 stx(G.x, i, x);
-                if (k0 < S.k_retire) {
+                // retirement: too soft to ever reach chi_min, or behind the trailing edge of the
+                // plane-wave pulse (the phase t + x of a photon never decreases)
+                const bool behind = F.kind == 1 && F.phase_len > 0.0 && S.t + S.dt + (double)x.x > F.phase_len;
+                if (k0 < S.k_retire || behind) {
                     G.id[i] = 0;
                     ++c_ret;
                 } else if (S.flags & F_PAIR) {
@@ -403,6 +459,7 @@ __global__ void __launch_bounds__(kBlock) k_photon_main(PhoDev<R> G, FieldDev F,
                     V3<R> P = ld3(G.P, i);
                     const PDecide<R> d = photon_decide<R>(S, T, lds, id, k, k0, P, E, B);
                     if (d.active) {
+                        ++c_qed;
                         c_chi += d.clamped_chi;
                         if (d.P <= (R)1 && !(d.r1 < d.P)) {
                             if (S.flags & F_NOPAIR) {
@@ -432,12 +489,13 @@ __global__ void __launch_bounds__(kBlock) k_photon_main(PhoDev<R> G, FieldDev F,
         if (lane == 0) {
             mask[base >> 6] = m;
             mask[nchunks + (base >> 6)] = mp;
+            ntrans += __popcll(m);
         }
     }
-    wave_add(ctr, C_CHI, c_chi);
-    wave_add(ctr, C_NORM, c_norm);
-    wave_add(ctr, C_RETIRED, c_ret);
-    wave_add(ctr, C_PROB, c_prob);
+    unsigned v[kNCtr] = {};
+    v[C_PROB] = c_prob; v[C_CHI] = c_chi; v[C_NORM] = c_norm; v[C_RETIRED] = c_ret; v[C_GSTEP] = c_step;
+    v[C_GQED] = c_qed;
+    block_counts(bctr, bcnt, v, ntrans);
 }
 
 // pair processing: lambda~ from the selected inverse CDF, momenta, correlated spins
@@ -455,7 +513,7 @@ __global__ void __launch_bounds__(kBlock) k_pair_process(PhoDev<R> G, LepDev<R> 
         const int64_t i = idx[j];
         const uint64_t id = G.id[i];
         const V3<R> k = ld3(G.k, i), x = ldx(G.x, i), P = ld3(G.P, i);
-        const double k0 = sqrt(dot(cvt<double>(k), cvt<double>(k)));
+        const double k0 = (double)sqrt_r(dot(k, k));
         V3<R> E, B;
         eval_fields<R>(F, (double)x.x, S.t + S.dt, E, B);
         const PDecide<R> d = photon_decide<R>(S, T, lds, id, k, k0, P, E, B);
@@ -466,10 +524,9 @@ __global__ void __launch_bounds__(kBlock) k_pair_process(PhoDev<R> G, LepDev<R> 
         const V3<R> pp = (R)lam_d * k, pe = (R)oml_d * k;
         V3<R> ec = {0, 0, 0}, pc = {0, 0, 0};
         if (S.flags & F_PAIR_SPIN) {
-            const Bessel3 bz = bessel3_scaled(2.0 * (1.0 / lam_d + 1.0 / oml_d) / (3.0 * d.chi));
             SpecPt<R> qp;
             qp.lam = (R)lam_d; qp.oml = (R)oml_d; qp.u = (R)0;
-            qp.K1 = (R)(bz.k13 / bz.k23); qp.I = (R)(bz.ik / bz.k23);
+            bessel_ratios<R>(2.0 * (1.0 / lam_d + 1.0 / oml_d) / (3.0 * d.chi), qp.K1, qp.I);
             const V3<R> xi = {d.x1, d.x2, d.x3};
             V3<R> je, jp;
             const R w0 = nbw_j(qp, xi, je, jp);
@@ -514,50 +571,69 @@ __global__ void __launch_bounds__(kBlock) k_pair_process(PhoDev<R> G, LepDev<R> 
 }
 
 // ------------------------------------------------------------------ kernels: scan / compaction
-__device__ __forceinline__ uint32_t block_sum(uint32_t v, uint32_t *sh)
-{
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
-    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
-    __syncthreads();
-    uint32_t t = 0;
-    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) t += sh[w];
-    __syncthreads();
-    return t;
-}
+// Bookkeeping (one block): exclusive scan of the per-block transition counts, totals of the
+// streaming pass's counters, append bases, capacity clamp, device-side counts.
+// mode 0: photon append (emission); 1: pair append to two lepton sets (and count_prev of the
+// photons <- count); 2: compaction.  `count` is the particle count the streaming pass used.
+constexpr int kBookThreads = 1024;
 
-// per-block popcount sums of the transition masks
-__global__ void __launch_bounds__(kBlock) k_mask_reduce(const uint64_t *mask, const int64_t *count, uint32_t *bsum)
+__global__ void __launch_bounds__(kBookThreads) k_book(const uint32_t *bcnt, uint32_t *boff, const int64_t *count, int nblk,
+                                                       int64_t *book, int mode, int64_t *cnt0, int64_t cap0, int64_t *cnt1,
+                                                       int64_t cap1, int64_t *cnt_prev, const int64_t *cnt_src,
+                                                       unsigned long long *ctr, const uint32_t *bctr)
 {
-    __shared__ uint32_t sh[kBlock / 64];
-    const int64_t nch = cdiv(*count, 64);
-    const int64_t c0 = (int64_t)blockIdx.x * kChunksPerBlock + threadIdx.x * kChunksPerThread;
-    uint32_t v = 0;
+    __shared__ uint32_t wsum[kBookThreads / 64];
+    __shared__ unsigned long long csum[kBookThreads / 64][kNCtr];
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    const int64_t n = *count;
+    // exclusive scan of bcnt[0, nblk): two entries per thread
+    const int i0 = 2 * tid;
+    const uint32_t a0 = i0 < nblk ? bcnt[i0] : 0u, a1 = i0 + 1 < nblk ? bcnt[i0 + 1] : 0u;
+    const uint32_t tsum = a0 + a1;
+    uint32_t incl = tsum;
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t y = __shfl_up(incl, o);
+        if (lane >= o) incl += y;
+    }
+    if (lane == 63) wsum[wid] = incl;
+    // counters: thread t sums blocks t, t + 1024 (kMaxGrid = 2048)
+    unsigned long long c[kNCtr];
 #pragma unroll
-    for (int m = 0; m < kChunksPerThread; ++m)
-        if (c0 + m < nch) v += __popcll(mask[c0 + m]);
-    const uint32_t t = block_sum(v, sh);
-    if (threadIdx.x == 0) bsum[blockIdx.x] = t;
-}
-
-// bookkeeping: total transitions, append bases, capacity clamp, device counts, counters.
-// mode 0: photon append (emission); 1: pair append to two lepton sets; 2: compaction.
-__global__ void __launch_bounds__(kBlock) k_book(const uint32_t *bsum, const int64_t *count, int64_t *book, int mode,
-                                                 int64_t *cnt0, int64_t cap0, int64_t *cnt1, int64_t cap1,
-                                                 int64_t *cnt_prev, unsigned long long *ctr)
-{
-    __shared__ uint32_t sh[kBlock / 64];
-    const int64_t nblk = cdiv(cdiv(*count, 64), kChunksPerBlock);
-    uint64_t acc = 0;
-    for (int64_t b = threadIdx.x; b < nblk; b += blockDim.x) acc += bsum[b];
-    // 64-bit block sum via two 32-bit halves is unnecessary: counts stay below 2^32 per call
-    const uint32_t total = block_sum((uint32_t)acc, sh);
-    if (threadIdx.x != 0) return;
+    for (int k = 0; k < kNCtr; ++k) c[k] = 0ull;
+    if (bctr) {
+        for (int bb = tid; bb < nblk; bb += kBookThreads)
+#pragma unroll
+            for (int k = 0; k < kNCtr; ++k) c[k] += bctr[bb * kNCtr + k];
+    }
+#pragma unroll
+    for (int k = 0; k < kNCtr; ++k) {
+        unsigned long long t = c[k];
+        for (int o = 32; o > 0; o >>= 1) t += __shfl_xor(t, o);
+        if (lane == 0) csum[wid][k] = t;
+    }
+    __syncthreads();
+    uint32_t woff = 0, total = 0;
+    for (int w = 0; w < kBookThreads / 64; ++w) {
+        if (w < wid) woff += wsum[w];
+        total += wsum[w];
+    }
+    const uint32_t ex = woff + incl - tsum;
+    if (i0 < nblk) boff[i0] = ex;
+    if (i0 + 1 < nblk) boff[i0 + 1] = ex + a0;
+    if (ctr && bctr && tid < kNCtr) {
+        unsigned long long t = 0;
+        for (int w = 0; w < kBookThreads / 64; ++w) t += csum[w][tid];
+        if (t) atomicAdd(ctr + tid, t);
+    }
+    if (tid != 0) return;
+    book[4] = n;
+    book[5] = block_len(n, nblk);
     if (mode == 0) {
-        const int64_t base = *cnt0;
-        const int64_t room = cap0 - base > 0 ? cap0 - base : 0;
+        const int64_t base = cnt0 ? *cnt0 : 0;
+        const int64_t room = cnt0 && cap0 - base > 0 ? cap0 - base : 0;
         const int64_t nfit = (int64_t)total < room ? (int64_t)total : room;
         book[0] = base; book[1] = total; book[2] = 0; book[3] = nfit;
-        *cnt0 = base + nfit;
+        if (cnt0) *cnt0 = base + nfit;
         if (ctr) {
             atomicAdd(ctr + C_EMIT, (unsigned long long)total);
             if (total > nfit) atomicAdd(ctr + C_OVER, (unsigned long long)(total - nfit));
@@ -577,64 +653,73 @@ __global__ void __launch_bounds__(kBlock) k_book(const uint32_t *bsum, const int
     } else {
         book[0] = 0; book[1] = total; book[2] = 0; book[3] = total;
     }
-    if (cnt_prev) *cnt_prev = mode == 2 ? (int64_t)total : *cnt_prev;
+    if (cnt_prev) *cnt_prev = mode == 2 ? (int64_t)total : *cnt_src;
 }
 
-// ascending list of the indices whose transition bit is set
-__global__ void __launch_bounds__(kBlock) k_mask_expand(const uint64_t *mask, const int64_t *count, const uint32_t *bsum,
+// ascending list of the indices whose transition bit is set; block b expands the mask words of
+// the particle range block b of the streaming pass owned, starting at rank boff[b]
+__global__ void __launch_bounds__(kBlock) k_mask_expand(const uint64_t *mask, const uint32_t *boff, const int64_t *book,
                                                         uint32_t *idx)
 {
-    __shared__ uint32_t sh[kBlock / 64];
     __shared__ uint32_t wtot[kBlock / 64];
-    const int64_t nch = cdiv(*count, 64);
-    const int64_t blk0 = (int64_t)blockIdx.x * kChunksPerBlock;
-    if (blk0 >= nch) return;
-    // exclusive prefix of the preceding blocks
-    uint64_t pre = 0;
-    for (int64_t b = threadIdx.x; b < (int64_t)blockIdx.x; b += blockDim.x) pre += bsum[b];
-    const uint32_t prefix = block_sum((uint32_t)pre, sh);
-    // this thread's chunks and their popcounts
-    const int64_t c0 = blk0 + threadIdx.x * kChunksPerThread;
-    uint64_t m[kChunksPerThread];
-    uint32_t tsum = 0;
-#pragma unroll
-    for (int k = 0; k < kChunksPerThread; ++k) {
-        m[k] = (c0 + k < nch) ? mask[c0 + k] : 0ull;
-        tsum += __popcll(m[k]);
-    }
-    // block-wide exclusive scan of tsum: wave scan with shuffles, then wave totals
+    const int64_t n = book[4], B = book[5];
+    const int64_t start = (int64_t)blockIdx.x * B;
+    if (start >= n) return;
+    const int64_t end = start + B < n ? start + B : n;
+    const int64_t c0 = start >> 6, c1 = cdiv(end, 64);
+    uint32_t rank0 = boff[blockIdx.x];
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    uint32_t incl = tsum;
-    for (int o = 1; o < 64; o <<= 1) {
-        const uint32_t y = __shfl_up(incl, o);
-        if (lane >= o) incl += y;
-    }
-    if (lane == 63) wtot[wid] = incl;
-    __syncthreads();
-    uint32_t woff = 0;
-    for (int w = 0; w < wid; ++w) woff += wtot[w];
-    uint32_t rank = prefix + woff + incl - tsum;
-#pragma unroll
-    for (int k = 0; k < kChunksPerThread; ++k) {
-        uint64_t bits = m[k];
+    for (int64_t tile = c0; tile < c1; tile += kBlock) {
+        const int64_t c = tile + threadIdx.x;
+        const uint64_t m = c < c1 ? mask[c] : 0ull;
+        const uint32_t pc = __popcll(m);
+        uint32_t incl = pc;
+        for (int o = 1; o < 64; o <<= 1) {
+            const uint32_t y = __shfl_up(incl, o);
+            if (lane >= o) incl += y;
+        }
+        if (lane == 63) wtot[wid] = incl;
+        __syncthreads();
+        uint32_t woff = 0, ttot = 0;
+        for (int w = 0; w < kBlock / 64; ++w) {
+            if (w < wid) woff += wtot[w];
+            ttot += wtot[w];
+        }
+        uint32_t rank = rank0 + woff + incl - pc;
+        uint64_t bits = m;
         while (bits) {
             const int b = __ffsll((long long)bits) - 1;
-            idx[rank++] = (uint32_t)((c0 + k) * 64 + b);
+            idx[rank++] = (uint32_t)(c * 64 + b);
             bits &= bits - 1;
         }
+        rank0 += ttot;
+        __syncthreads();
     }
 }
 
 template <class R>
-__global__ void __launch_bounds__(kBlock) k_alive_mask(PhoDev<R> G, uint64_t *mask)
+__global__ void __launch_bounds__(kBlock) k_alive_mask(PhoDev<R> G, uint64_t *mask, uint32_t *bcnt)
 {
+    __shared__ unsigned red[kBlock / 64];
     const int64_t n = *G.count;
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t base = (int64_t)blockIdx.x * blockDim.x + (threadIdx.x & ~63); base < n; base += stride) {
+    const int64_t B = block_len(n, gridDim.x);
+    const int64_t start = (int64_t)blockIdx.x * B, end = start + B < n ? start + B : n;
+    unsigned ntrans = 0;
+    for (int64_t base = start + (threadIdx.x & ~63); base < end; base += blockDim.x) {
         const int64_t i = base + (threadIdx.x & 63);
-        const bool alive = i < n && G.id[i] != 0;
+        const bool alive = i < end && G.id[i] != 0;
         const uint64_t m = __ballot(alive);
-        if ((threadIdx.x & 63) == 0) mask[base >> 6] = m;
+        if ((threadIdx.x & 63) == 0) {
+            mask[base >> 6] = m;
+            ntrans += __popcll(m);
+        }
+    }
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = ntrans;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned t = 0;
+        for (int w = 0; w < kBlock / 64; ++w) t += red[w];
+        bcnt[blockIdx.x] = t;
     }
 }
 
@@ -691,6 +776,10 @@ template <class R> LepDev<R> lep_dev(const qed_leptons *L)
 template <class R> PhoDev<R> pho_dev(const qed_photons *G)
 {
     PhoDev<R> d;
+    if (!G) {                     // emission disabled: a view with no room, never written
+        memset(&d, 0, sizeof(d));
+        return d;
+    }
     d.cap = G->capacity;
     d.count = G->d_count;
     d.count_prev = G->d_count_prev;
@@ -733,7 +822,6 @@ int grid_for(int64_t n)
     return (int)(g < kMaxGrid ? g : kMaxGrid);
 }
 
-int scan_blocks(int64_t cap) { return (int)cdiv(cdiv(cap > 0 ? cap : 1, 64), kChunksPerBlock); }
 
 bool leptons_ok(const qed_leptons *L)
 {
@@ -766,20 +854,18 @@ qed_status emit_impl(qed_tables T, const qed_leptons *L, const qed_fields *f, co
     unsigned long long *c = (unsigned long long *)ctr;
     const size_t lds_nlc = sizeof(R) * 2 * T->dev.n_chi[0];
     const int g = grid_for(L->capacity);
-    hipLaunchKernelGGL(k_lepton_main<R>, dim3(g), dim3(kBlock), lds_nlc, st, ld, fd, sd, T->dev, w.mask, nch, c);
-    if (!(p->flags & QED_EMIT)) return hipGetLastError() == hipSuccess ? QED_OK : QED_ERR_HIP;
-    const PhoDev<R> gd = pho_dev<R>(G);
-    const int nb = scan_blocks(L->capacity);
-    hipLaunchKernelGGL(k_mask_reduce, dim3(nb), dim3(kBlock), 0, st, w.mask, L->d_count, w.bsum);
-    hipLaunchKernelGGL(k_book, dim3(1), dim3(kBlock), 0, st, w.bsum, L->d_count, w.book, 0, G->d_count, G->capacity,
-                       (int64_t *)nullptr, (int64_t)0, (int64_t *)nullptr, c);
-    hipLaunchKernelGGL(k_mask_expand, dim3(nb), dim3(kBlock), 0, st, w.mask, L->d_count, w.bsum, w.idx);
-    hipLaunchKernelGGL(k_emit_process<R>, dim3(g), dim3(kBlock), lds_nlc, st, ld, gd, fd, sd, T->dev, w.mask, nch, w.idx,
+    QS_LAUNCH(K_LEPTON_MAIN, k_lepton_main<R>, dim3(g), dim3(kBlock), lds_nlc, st, ld, fd, sd, T->dev, w.mask, nch, w.bctr,
+              w.bcnt);
+    const PhoDev<R> gd = pho_dev<R>((p->flags & QED_EMIT) ? G : nullptr);
+    QS_LAUNCH(K_BOOK, k_book, dim3(1), dim3(kBookThreads), 0, st, (const uint32_t *)w.bcnt, w.boff, L->d_count, g, w.book,
+              0, gd.count, gd.cap, (int64_t *)nullptr, (int64_t)0, (int64_t *)nullptr, (const int64_t *)nullptr, c,
+              (const uint32_t *)w.bctr);
+    QS_LAUNCH(K_MASK_EXPAND, k_mask_expand, dim3(g), dim3(kBlock), 0, st, (const uint64_t *)w.mask, (const uint32_t *)w.boff,
+              (const int64_t *)w.book, w.idx);
+    QS_LAUNCH(K_EMIT_PROCESS, k_emit_process<R>, dim3(g), dim3(kBlock), lds_nlc, st, ld, gd, fd, sd, T->dev, w.mask, nch, w.idx,
                        w.book, c);
-    return hipGetLastError() == hipSuccess ? QED_OK : QED_ERR_HIP;
+    return qs_launch_status(__func__);
 }
-
-__global__ void k_set_prev(const int64_t *count, int64_t *prev) { *prev = *count; }
 
 template <class R>
 qed_status pair_impl(qed_tables T, const qed_photons *G, const qed_fields *f, const qed_step_params *p,
@@ -794,17 +880,17 @@ qed_status pair_impl(qed_tables T, const qed_photons *G, const qed_fields *f, co
     unsigned long long *c = (unsigned long long *)ctr;
     const size_t lds_nbw = sizeof(R) * 2 * T->dev.n_chi[1];
     const int g = grid_for(G->capacity);
-    const int nb = scan_blocks(G->capacity);
-    hipLaunchKernelGGL(k_photon_main<R>, dim3(g), dim3(kBlock), lds_nbw, st, gd, fd, sd, T->dev, w.mask, nch, c);
-    hipLaunchKernelGGL(k_mask_reduce, dim3(nb), dim3(kBlock), 0, st, w.mask, G->d_count_prev, w.bsum);
-    // book reads *d_count_prev for the block count before it overwrites it
-    hipLaunchKernelGGL(k_book, dim3(1), dim3(kBlock), 0, st, w.bsum, G->d_count_prev, w.book, 1, Le->d_count,
-                       Le->capacity, Lp->d_count, Lp->capacity, (int64_t *)nullptr, c);
-    hipLaunchKernelGGL(k_mask_expand, dim3(nb), dim3(kBlock), 0, st, w.mask, G->d_count_prev, w.bsum, w.idx);
-    hipLaunchKernelGGL(k_pair_process<R>, dim3(g), dim3(kBlock), lds_nbw, st, gd, lep_dev<R>(Le), lep_dev<R>(Lp), fd, sd,
+    QS_LAUNCH(K_PHOTON_MAIN, k_photon_main<R>, dim3(g), dim3(kBlock), lds_nbw, st, gd, fd, sd, T->dev, w.mask, nch, w.bctr,
+              w.bcnt);
+    // book reads *d_count_prev (the count just stepped) before setting it to *d_count
+    QS_LAUNCH(K_BOOK, k_book, dim3(1), dim3(kBookThreads), 0, st, (const uint32_t *)w.bcnt, w.boff, G->d_count_prev, g,
+              w.book, 1, Le->d_count, Le->capacity, Lp->d_count, Lp->capacity, G->d_count_prev,
+              (const int64_t *)G->d_count, c, (const uint32_t *)w.bctr);
+    QS_LAUNCH(K_MASK_EXPAND, k_mask_expand, dim3(g), dim3(kBlock), 0, st, (const uint64_t *)w.mask, (const uint32_t *)w.boff,
+              (const int64_t *)w.book, w.idx);
+    QS_LAUNCH(K_PAIR_PROCESS, k_pair_process<R>, dim3(g), dim3(kBlock), lds_nbw, st, gd, lep_dev<R>(Le), lep_dev<R>(Lp), fd, sd,
                        T->dev, w.mask, nch, w.idx, w.book);
-    hipLaunchKernelGGL(k_set_prev, dim3(1), dim3(1), 0, st, G->d_count, G->d_count_prev);
-    return hipGetLastError() == hipSuccess ? QED_OK : QED_ERR_HIP;
+    return qs_launch_status(__func__);
 }
 
 }  // namespace
@@ -814,9 +900,8 @@ extern "C" size_t qed_workspace_size(int64_t max_particles)
 {
     const int64_t cap = max_particles > 0 ? max_particles : 1;
     const int64_t nch = cdiv(cap, 64);
-    const int64_t nblk = cdiv(nch, kChunksPerBlock);
-    return align256(sizeof(uint64_t) * 2 * nch) + align256(sizeof(uint32_t) * nblk) + align256(sizeof(int64_t) * 8) +
-           align256(sizeof(uint32_t) * cap);
+    return align256(sizeof(uint64_t) * 2 * nch) + 2 * align256(sizeof(uint32_t) * kMaxGrid) +
+           align256(sizeof(int64_t) * 8) + align256(sizeof(uint32_t) * kMaxGrid * kNCtr) + align256(sizeof(uint32_t) * cap);
 }
 
 extern "C" qed_status qed_push_spin(const qed_leptons *L, const qed_fields *f, const qed_step_params *p, qed_tables T,
@@ -824,14 +909,15 @@ extern "C" qed_status qed_push_spin(const qed_leptons *L, const qed_fields *f, c
 {
     if (!T || !leptons_ok(L) || !p || !fields_ok(f)) return QED_ERR_INVALID;
     hipStream_t st = (hipStream_t)stream;
+    qs_clear_error();
     const FieldDev fd = field_dev(f);
     const StepDev sd = step_dev(p);
     const int g = grid_for(L->capacity);
     if (T->params.precision == QED_F64)
-        hipLaunchKernelGGL(k_push<double>, dim3(g), dim3(kBlock), 0, st, lep_dev<double>(L), fd, sd);
+        QS_LAUNCH(K_PUSH, k_push<double>, dim3(g), dim3(kBlock), 0, st, lep_dev<double>(L), fd, sd);
     else
-        hipLaunchKernelGGL(k_push<float>, dim3(g), dim3(kBlock), 0, st, lep_dev<float>(L), fd, sd);
-    return hipGetLastError() == hipSuccess ? QED_OK : QED_ERR_HIP;
+        QS_LAUNCH(K_PUSH, k_push<float>, dim3(g), dim3(kBlock), 0, st, lep_dev<float>(L), fd, sd);
+    return qs_launch_status(__func__);
 }
 
 extern "C" qed_status qed_emit(qed_tables T, const qed_leptons *L, const qed_fields *f, const qed_step_params *p,
@@ -842,6 +928,7 @@ extern "C" qed_status qed_emit(qed_tables T, const qed_leptons *L, const qed_fie
     if (!(p->dt > 0.0) || !(p->eps_r > 0.0)) return QED_ERR_INVALID;
     if (ws_bytes < qed_workspace_size(L->capacity)) return QED_ERR_CAPACITY;
     hipStream_t st = (hipStream_t)stream;
+    qs_clear_error();
     if (T->params.precision == QED_F64) return emit_impl<double>(T, L, f, p, G, ctr, ws, ws_bytes, st);
     return emit_impl<float>(T, L, f, p, G, ctr, ws, ws_bytes, st);
 }
@@ -855,6 +942,7 @@ extern "C" qed_status qed_pair(qed_tables T, const qed_photons *G, const qed_fie
     if (!(p->dt > 0.0) || !(p->eps_r > 0.0)) return QED_ERR_INVALID;
     if (ws_bytes < qed_workspace_size(G->capacity)) return QED_ERR_CAPACITY;
     hipStream_t st = (hipStream_t)stream;
+    qs_clear_error();
     if (T->params.precision == QED_F64) return pair_impl<double>(T, G, f, p, Le, Lp, ctr, ws, ws_bytes, st);
     return pair_impl<float>(T, G, f, p, Le, Lp, ctr, ws, ws_bytes, st);
 }
@@ -884,15 +972,16 @@ template <class R> static qed_status compact_impl(const qed_photons *G, void *ws
     for (int c = 0; c < 3; ++c) { S.P[c] = (R *)b; b += align256(sizeof(R) * cap); }
     S.id = (uint64_t *)b;
     const PhoDev<R> gd = pho_dev<R>(G);
-    const int g = grid_for(G->capacity), nb = scan_blocks(G->capacity);
-    hipLaunchKernelGGL(k_alive_mask<R>, dim3(g), dim3(kBlock), 0, st, gd, w.mask);
-    hipLaunchKernelGGL(k_mask_reduce, dim3(nb), dim3(kBlock), 0, st, w.mask, G->d_count, w.bsum);
-    hipLaunchKernelGGL(k_book, dim3(1), dim3(kBlock), 0, st, w.bsum, G->d_count, w.book, 2, (int64_t *)nullptr,
-                       (int64_t)0, (int64_t *)nullptr, (int64_t)0, G->d_count_prev, (unsigned long long *)nullptr);
-    hipLaunchKernelGGL(k_mask_expand, dim3(nb), dim3(kBlock), 0, st, w.mask, G->d_count, w.bsum, w.idx);
-    hipLaunchKernelGGL(k_gather<R>, dim3(g), dim3(kBlock), 0, st, gd, S, w.idx, w.book);
-    hipLaunchKernelGGL(k_scatter_back<R>, dim3(g), dim3(kBlock), 0, st, gd, S, w.book);
-    return hipGetLastError() == hipSuccess ? QED_OK : QED_ERR_HIP;
+    const int g = grid_for(G->capacity);
+    QS_LAUNCH(K_ALIVE_MASK, k_alive_mask<R>, dim3(g), dim3(kBlock), 0, st, gd, w.mask, w.bcnt);
+    QS_LAUNCH(K_BOOK, k_book, dim3(1), dim3(kBookThreads), 0, st, (const uint32_t *)w.bcnt, w.boff, G->d_count, g, w.book,
+              2, (int64_t *)nullptr, (int64_t)0, (int64_t *)nullptr, (int64_t)0, G->d_count_prev,
+              (const int64_t *)nullptr, (unsigned long long *)nullptr, (const uint32_t *)nullptr);
+    QS_LAUNCH(K_MASK_EXPAND, k_mask_expand, dim3(g), dim3(kBlock), 0, st, (const uint64_t *)w.mask, (const uint32_t *)w.boff,
+              (const int64_t *)w.book, w.idx);
+    QS_LAUNCH(K_GATHER, k_gather<R>, dim3(g), dim3(kBlock), 0, st, gd, S, w.idx, w.book);
+    QS_LAUNCH(K_SCATTER_BACK, k_scatter_back<R>, dim3(g), dim3(kBlock), 0, st, gd, S, w.book);
+    return qs_launch_status(__func__);
 }
 
 extern "C" qed_status qed_compact(const qed_photons *G, qed_precision prec, void *ws, size_t ws_bytes, qed_stream stream)
@@ -901,6 +990,7 @@ extern "C" qed_status qed_compact(const qed_photons *G, qed_precision prec, void
     if (prec != QED_F64 && prec != QED_F32) return QED_ERR_INVALID;
     if (ws_bytes < qed_compact_workspace_size(G, prec)) return QED_ERR_CAPACITY;
     hipStream_t st = (hipStream_t)stream;
+    qs_clear_error();
     if (prec == QED_F64) return compact_impl<double>(G, ws, st);
     return compact_impl<float>(G, ws, st);
 }

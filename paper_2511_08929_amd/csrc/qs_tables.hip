@@ -11,10 +11,12 @@
 //          complementary CDF from the right for r > 1/2 so both tails keep full precision.
 // Below nu = -60 the NLC spectrum follows its small-lambda law
 //   int_0^lam w = 3 Gamma(2/3) (3 chi)^(2/3) lam^(1/3) - (pi/sqrt 3) lam   (relative remainder < 1e-26).
-// Quadrature: 12-point Gauss-Legendre panels of width 1/2 in nu (the density is analytic in
-// the strip |Im nu| < pi/2, so each panel is exact to rounding); Bessel functions by the
-// trapezoidal rule of qs_device.hpp.
+// Quadrature: 12-point Gauss-Legendre panels in nu, at most 1/2 wide and narrow enough that
+// the density's exponential factor e^{-u'} changes by at most e per panel (the density is
+// analytic in the strip |Im nu| < pi/2, so each panel is exact to rounding); the range ends
+// where u' exceeds its minimum by 90.  Bessel functions by the trapezoidal rule of qs_device.hpp.
 #include <math.h>
+#include <stdio.h>
 #include <stdlib.h>
 #include <string.h>
 
@@ -25,9 +27,8 @@
 namespace {
 
 constexpr int kNQ = 12;
-constexpr double kPanel = 0.5;
 constexpr double kNuLo = -60.0;
-constexpr int kMaxPanels = 320;
+constexpr int kMaxPanels = 512;
 
 struct GL12 { double x[kNQ], w[kNQ]; };
 
@@ -139,9 +140,16 @@ __device__ double solve_root(const GL12 &g, int ch, double chi, int side, double
     return nu;
 }
 
+// decay rate |d u'/d nu| of the density's e^{-u'} factor: NLC u' = 2 e^nu/(3 chi),
+// NBW u~' = 4 (1 + cosh nu)/(3 chi)
+__device__ __forceinline__ double decay(int ch, double chi, double nu)
+{
+    return ch < 2 ? 2.0 * exp(nu) / (3.0 * chi) : 4.0 * fabs(sinh(nu)) / (3.0 * chi);
+}
+
 __global__ void __launch_bounds__(256) k_build_tables(BuildArgs A, GL12 g, double *lnrate, double *nu_out)
 {
-    __shared__ double pint[kMaxPanels], left[kMaxPanels + 1], right[kMaxPanels + 1];
+    __shared__ double pint[kMaxPanels], left[kMaxPanels + 1], right[kMaxPanels + 1], edge[kMaxPanels + 1];
     __shared__ double s_total, s_tail;
     __shared__ int s_np;
     int task = blockIdx.x, ch, i;
@@ -149,17 +157,30 @@ __global__ void __launch_bounds__(256) k_build_tables(BuildArgs A, GL12 g, doubl
     else { const int t2 = task - 2 * A.n_chi[0]; ch = 2 + t2 / A.n_chi[1]; i = t2 % A.n_chi[1]; }
     const int grp = ch < 2 ? 0 : 1;
     const double chi = exp(A.lnchi0[grp] + i * A.dlnchi[grp]);
+    // range: up to where u' exceeds its minimum by 90 (the mass beyond is < e^-90 of the total)
     double a0, b1;
-    if (ch < 2) { a0 = kNuLo; b1 = log(1.5 * chi * 700.0); }
+    if (ch < 2) { a0 = kNuLo; b1 = log(1.5 * chi * 90.0); }
     else {
-        const double c = 0.75 * chi * 700.0 - 1.0;
-        const double m = c > 1.0 ? acosh(c) : 0.0;
+        const double m = acosh(1.0 + 0.75 * chi * 90.0);
         a0 = -m; b1 = m;
     }
-    int np = (int)ceil((b1 - a0) / kPanel);
-    np = np < 1 ? 1 : (np > kMaxPanels ? kMaxPanels : np);
-    for (int p = threadIdx.x; p < np; p += blockDim.x)
-        pint[p] = gl_integral(g, ch, chi, a0 + p * kPanel, fmin(a0 + (p + 1) * kPanel, b1));
+    // panels no wider than 1/2 with |d u'/d nu| * width <= 1 (built by one thread)
+    if (threadIdx.x == 0) {
+        int np = 0;
+        double a = a0;
+        edge[0] = a;
+        while (a < b1 && np < kMaxPanels) {
+            double w = 0.5;
+            while (w > 1.0 / 4096.0 && w * fmax(decay(ch, chi, a), decay(ch, chi, a + w)) > 1.0) w *= 0.5;
+            const double b = np == kMaxPanels - 1 ? b1 : fmin(a + w, b1);
+            edge[++np] = b;
+            a = b;
+        }
+        s_np = np;
+    }
+    __syncthreads();
+    int np = s_np;
+    for (int p = threadIdx.x; p < np; p += blockDim.x) pint[p] = gl_integral(g, ch, chi, edge[p], edge[p + 1]);
     __syncthreads();
     if (threadIdx.x == 0) {
         double tail = 0.0;
@@ -193,13 +214,13 @@ __global__ void __launch_bounds__(256) k_build_tables(BuildArgs A, GL12 g, doubl
             } else {
                 int lo = 0, hi = np;
                 while (hi - lo > 1) { const int m = (lo + hi) >> 1; if (left[m] <= target) lo = m; else hi = m; }
-                nu = solve_root(g, ch, chi, +1, left[lo], pint[lo], a0 + lo * kPanel, fmin(a0 + (lo + 1) * kPanel, b1), target);
+                nu = solve_root(g, ch, chi, +1, left[lo], pint[lo], edge[lo], edge[lo + 1], target);
             }
         } else {
             const double target = total / (1.0 + exp(rho));
             int lo = 0, hi = np;
             while (hi - lo > 1) { const int m = (lo + hi) >> 1; if (right[m] > target) lo = m; else hi = m; }
-            nu = solve_root(g, ch, chi, -1, right[lo + 1], pint[lo], a0 + lo * kPanel, fmin(a0 + (lo + 1) * kPanel, b1), target);
+            nu = solve_root(g, ch, chi, -1, right[lo + 1], pint[lo], edge[lo], edge[lo + 1], target);
         }
         row[j] = nu;
     }
@@ -213,6 +234,16 @@ __global__ void k_to_float(const double *src, float *dst, int n)
 
 }  // namespace
 
+static thread_local char g_last_error[256];
+
+qed_status qs_fail(hipError_t e, const char *where)
+{
+    snprintf(g_last_error, sizeof(g_last_error), "%s: %s", where, hipGetErrorString(e));
+    return QED_ERR_HIP;
+}
+
+extern "C" const char *qed_last_error(void) { return g_last_error; }
+
 extern "C" qed_status qed_init_tables(const qed_table_params *params, qed_stream stream, qed_tables *out)
 {
     if (!params || !out) return QED_ERR_INVALID;
@@ -222,6 +253,7 @@ extern "C" qed_status qed_init_tables(const qed_table_params *params, qed_stream
         return QED_ERR_INVALID;
     if (params->precision != QED_F64 && params->precision != QED_F32) return QED_ERR_INVALID;
     hipStream_t st = (hipStream_t)stream;
+    qs_clear_error();
     qed_tables T = (qed_tables)calloc(1, sizeof(qed_tables_s));
     if (!T) return QED_ERR_INVALID;
     T->params = *params;
@@ -247,19 +279,22 @@ extern "C" qed_status qed_init_tables(const qed_table_params *params, qed_stream
     A.drho = G.drho;
     T->n_rate = r;
     T->n_nu = v;
-    if (hipMalloc(&T->d_lnrate, sizeof(double) * r) != hipSuccess ||
-        hipMalloc(&T->d_lnrate32, sizeof(float) * r) != hipSuccess ||
-        hipMalloc(&T->d_nu, sizeof(double) * v) != hipSuccess) {
+    hipError_t e = hipMalloc(&T->d_lnrate, sizeof(double) * r);
+    if (e == hipSuccess) e = hipMalloc(&T->d_lnrate32, sizeof(float) * r);
+    if (e == hipSuccess) e = hipMalloc(&T->d_nu, sizeof(double) * v);
+    if (e != hipSuccess) {
         qed_free_tables(T);
-        return QED_ERR_HIP;
+        return qs_fail(e, "hipMalloc (tables)");
     }
     const GL12 g = legendre_nodes();
     const int ntask = 2 * G.n_chi[0] + 2 * G.n_chi[1];
-    hipLaunchKernelGGL(k_build_tables, dim3(ntask), dim3(256), 0, st, A, g, T->d_lnrate, T->d_nu);
-    hipLaunchKernelGGL(k_to_float, dim3((r + 255) / 256), dim3(256), 0, st, T->d_lnrate, T->d_lnrate32, r);
-    if (hipGetLastError() != hipSuccess || hipStreamSynchronize(st) != hipSuccess) {
+    QS_LAUNCH(K_TABLES, k_build_tables, dim3(ntask), dim3(256), 0, st, A, g, T->d_lnrate, T->d_nu);
+    QS_LAUNCH(K_TABLES, k_to_float, dim3((r + 255) / 256), dim3(256), 0, st, T->d_lnrate, T->d_lnrate32, r);
+    e = hipGetLastError();
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) {
         qed_free_tables(T);
-        return QED_ERR_HIP;
+        return qs_fail(e, "table build kernels");
     }
     TablesDev &D = T->dev;
     for (int k = 0; k < 2; ++k) {

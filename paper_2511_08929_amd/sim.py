@@ -32,6 +32,7 @@ class Simulation:
         self.k_retire, self.t0, self.a_e = k_retire, t0, a_e
         self.chi = (chi_e_min, chi_e_max, chi_g_min, chi_g_max)
         self.n = 0
+        self._sp = None
 
     def step_params(self, n):
         return make_step(self.dt, self.eps_r, step=n, t=self.t0 + n * self.dt, seed=self.seed, flags=self.flags,
@@ -39,7 +40,10 @@ class Simulation:
                          chi_g_max=self.chi[3], k_retire=self.k_retire)
 
     def step(self, stream=None):
-        sp = self.step_params(self.n)
+        sp = self._sp
+        if sp is None:
+            sp = self._sp = self.step_params(self.n)
+        sp.step, sp.t, sp.flags = self.n, self.t0 + self.n * self.dt, self.flags
         qed_emit(self.tables, self.e, self.fields, sp, self.g, self.ctr, self.ws, stream)
         if self.flags & QED_PAIR:
             qed_emit(self.tables, self.p, self.fields, sp, self.g, self.ctr, self.ws, stream)

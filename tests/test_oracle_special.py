@@ -224,3 +224,27 @@ def test_tables_interpolation_error(otables):
         worst_rate = max(worst_rate, abs(otables.lnrate(ch, lnchi) - ex))
     assert worst_nu < 2e-3
     assert worst_rate < 1e-4
+
+
+@pytest.mark.parametrize("ch,chi", [(2, 0.0537), (3, 0.3), (3, 5.0), (0, 1e-3), (1, 0.05), (0, 10.0), (1, 100.0)])
+def test_icdf_tails_vs_independent_quadrature(ch, chi):
+    """Tail probabilities at the extreme table nodes (rho = +-37.5, |r - 0 or 1| ~ 5e-17), where
+    the density falls by ~e^50 per unit nu, against scipy's adaptive quadrature of the
+    density between the root and a point far in the tail."""
+    tot = oracle.rate_integral(ch, chi)
+    f = lambda v: oracle.density_nu(ch, chi, v)
+    for rho in (-37.5, -30.0, 30.0, 37.5):
+        nu = oracle.icdf_nu(ch, chi, rho)
+        if rho > 0:
+            pts = np.linspace(nu, nu + 8.0, 200)
+            target = special.expit(-rho)
+        else:
+            if ch < 2 and nu < -60:
+                continue          # below nu = -60 the small-lambda law (pinned separately) is used
+            pts = np.linspace(nu - 8.0 if ch >= 2 else -60.0, nu, 200)
+            target = special.expit(rho)
+        val = sum(integrate.quad(f, a, b, epsabs=0, epsrel=1e-13, limit=300)[0] for a, b in zip(pts[:-1], pts[1:]))
+        if rho < 0 and ch < 2:
+            lam0 = special.expit(-60.0)
+            val += 3 * special.gamma(2 / 3) * (3 * chi) ** (2 / 3) * lam0 ** (1 / 3) - math.pi / math.sqrt(3) * lam0
+        assert abs(val / tot / target - 1) < 1e-12, (rho, val / tot / target - 1)
