@@ -138,6 +138,9 @@ typedef struct {
     int64_t  step;              /* Philox counter word */
     uint64_t seed;              /* Philox key */
     uint32_t flags;
+    const int64_t *d_clock;     /* optional device step offset c (NULL = 0): the launch uses step + c and
+                                   t + c dt, so one recorded sequence of calls (a HIP graph) can be
+                                   replayed every step; advance it with qed_clock_advance */
 } qed_step_params;
 
 typedef struct {                /* device-resident, accumulated */
@@ -205,6 +208,9 @@ qed_status qed_pair(qed_tables tables, const qed_photons *photons, const qed_fie
 size_t qed_compact_workspace_size(const qed_photons *photons, qed_precision precision);
 qed_status qed_compact(const qed_photons *photons, qed_precision precision, void *workspace,
                        size_t workspace_bytes, qed_stream stream);
+
+/* *d_clock += 1 on the stream (one-thread kernel), for replayed step sequences. */
+qed_status qed_clock_advance(int64_t *d_clock, qed_stream stream);
 
 /* Kernel timing for measurement tools: qed_profile_start clears the record and brackets every
    subsequent launch with HIP events on its stream; qed_profile_stop synchronizes on them, writes

@@ -32,7 +32,7 @@ QED_FIELD_UNIFORM, QED_FIELD_PLANE_LP = 0, 1
 
 ABI_SYMBOLS = ("qed_init_tables", "qed_last_error", "qed_free_tables", "qed_tables_download", "qed_workspace_size",
                "qed_push_spin", "qed_emit", "qed_pair", "qed_compact_workspace_size", "qed_compact",
-               "qed_profile_start", "qed_profile_stop")
+               "qed_profile_start", "qed_profile_stop", "qed_clock_advance")
 
 
 class QedError(RuntimeError):
@@ -68,7 +68,7 @@ class StepParams(C.Structure):
     _fields_ = [("t", C.c_double), ("dt", C.c_double), ("a_e", C.c_double), ("eps_r", C.c_double),
                 ("chi_e_min", C.c_double), ("chi_e_max", C.c_double), ("chi_g_min", C.c_double),
                 ("chi_g_max", C.c_double), ("k_retire", C.c_double), ("step", C.c_int64),
-                ("seed", C.c_uint64), ("flags", C.c_uint32)]
+                ("seed", C.c_uint64), ("flags", C.c_uint32), ("d_clock", C.c_void_p)]
 
 
 COUNTER_NAMES = ("n_emit", "n_pair", "n_prob_clamped", "n_chi_clamped", "n_norm_clamped",
@@ -104,6 +104,7 @@ def lib():
         L.qed_pair.argtypes = [vp, P(Photons), P(Fields), P(StepParams), P(Leptons), P(Leptons), vp, vp, sz, vp]
         L.qed_compact_workspace_size.argtypes = [P(Photons), C.c_int]; L.qed_compact_workspace_size.restype = sz
         L.qed_compact.argtypes = [P(Photons), C.c_int, vp, sz, vp]
+        L.qed_clock_advance.argtypes = [vp, vp]
         L.qed_profile_start.argtypes = []
         L.qed_profile_stop.argtypes = [P(KernelTime), C.c_int, P(C.c_int)]
         for name in ABI_SYMBOLS:
@@ -338,3 +339,7 @@ def qed_profile_stop():
     n = C.c_int()
     _check(lib().qed_profile_stop(buf, 32, C.byref(n)), "qed_profile_stop")
     return {buf[i].name.decode(): (int(buf[i].calls), float(buf[i].total_ms)) for i in range(min(n.value, 32))}
+
+
+def qed_clock_advance(clock, stream=None):
+    _check(lib().qed_clock_advance(_ptr(clock), _stream_ptr(stream)), "qed_clock_advance")

@@ -89,31 +89,40 @@ __device__ __forceinline__ uint64_t photon_id(int species, int64_t index, int64_
            ((uint64_t)step & 0xFFFFFFull);
 }
 
-// ------------------------------------------------------------------ Bessel triple (FP64)
+// ------------------------------------------------------------------ Bessel functions
 // K_nu(x) = int_0^inf e^{-x cosh t} cosh(nu t) dt, IntK_1/3(x) = int_0^inf e^{-x cosh t} cosh(t/3)/cosh(t) dt,
-// by the trapezoidal rule in t, which converges geometrically for these integrands (analytic
-// in the strip |Im t| < pi/2): step 0.2 (error ~ e^{-pi^2/0.2}) and 0.6/sqrt(x) for large x,
-// where the integrand is a narrow Gaussian of width 1/sqrt(x).  Returned scaled by e^{+x}:
-// o = e^x (K_1/3, K_2/3, IntK_1/3).  Zero beyond x = 700.
+// by the trapezoidal rule in t, which converges geometrically for these integrands (analytic in
+// the strip |Im t| < pi/2): error ~ e^{-pi^2/h} for step h, and e^{-2 pi^2/(h^2 x)} for large x
+// where the integrand is a Gaussian of width 1/sqrt(x), hence h = min(h0, c/sqrt(x)).  The
+// node values cosh t - 1, cosh(t/3), cosh(2t/3), cosh(t/3)/cosh t are tabulated once per step
+// size (qed_init_tables), so a node costs one exponential.  Values are returned scaled by e^{+x}.
+//
+// FP64 tables: h = 0.2 / 2^k, k = 0..4 (x <= 9, 36, 144, 576, 2304), 1024 nodes at k = 0 and 64
+// above, 4 doubles per node; terms stop below e^{-44} of the first.  FP32 tables: h = 0.4, 0.1,
+// 0.025 (x <= 6.25, 100, 1600), 256 and 64 nodes, one float4 per node; terms stop below e^{-22}.
+constexpr int kBn64Levels = 5, kBn64N0 = 1024, kBn64N = 64;
+constexpr int kBn32Levels = 3, kBn32N0 = 256, kBn32N = 64;
+constexpr int kBn64Nodes = kBn64N0 + (kBn64Levels - 1) * kBn64N;
+constexpr int kBn32Nodes = kBn32N0 + (kBn32Levels - 1) * kBn32N;
+
 struct Bessel3 { double k13, k23, ik; };
 
-__device__ inline Bessel3 bessel3_scaled(double x)
+__device__ inline Bessel3 bessel3_scaled(double x, const double *nodes)
 {
     Bessel3 o{0.0, 0.0, 0.0};
     if (!(x < 700.0)) return o;
-    const double h = fmin(0.2, 0.6 / sqrt(x));
+    const int k = x <= 9.0 ? 0 : (x <= 36.0 ? 1 : (x <= 144.0 ? 2 : (x <= 576.0 ? 3 : 4)));
+    const double h = 0.2 / (double)(1 << k);
+    const int off = k == 0 ? 0 : kBn64N0 + (k - 1) * kBn64N, nn = k == 0 ? kBn64N0 : kBn64N;
+    const double2 *q = reinterpret_cast<const double2 *>(nodes) + 2 * off;
     double s13 = 0.5, s23 = 0.5, sik = 0.5;     // t = 0 node, half weight
-    for (int j = 1; j < 4096; ++j) {
-        const double t = j * h;
-        const double sh = sinh(0.5 * t);
-        const double chm1 = 2.0 * sh * sh;          // cosh t - 1
-        const double e = exp(-x * chm1);            // e^{-x cosh t} e^{x}
-        const double z = exp(t * (1.0 / 3.0)), zi = 1.0 / z;
-        const double c1 = 0.5 * (z + zi), c2 = 0.5 * (z * z + zi * zi);
-        s13 += e * c1;
-        s23 += e * c2;
-        sik += e * c1 / (1.0 + chm1);
-        if (x * chm1 > 44.0 && x * (1.0 + chm1) > 44.0) break;
+    for (int j = 1; j < nn; ++j) {
+        const double2 a = q[2 * j], b = q[2 * j + 1];   // (cosh t - 1, cosh t/3), (cosh 2t/3, cosh t/3 / cosh t)
+        const double e = exp(-x * a.x);
+        s13 += e * a.y;
+        s23 += e * b.x;
+        sik += e * b.y;
+        if (x * a.x > 44.0 && x * (1.0 + a.x) > 44.0) break;
     }
     o.k13 = h * s13;
     o.k23 = h * s23;
@@ -122,35 +131,31 @@ __device__ inline Bessel3 bessel3_scaled(double x)
 }
 
 // Ratios K_1/3 / K_2/3 and IntK_1/3 / K_2/3 at x: all the spin and polarization collapse needs.
-// Double: from the FP64 trapezoid above.  Single: the same rule in FP32 with step 0.4 (error
-// ~e^{-pi^2/0.4} = 2e-11) or 1/sqrt(x), truncated at e^{-22} (2.8e-10 of the peak term).
-template <class R> __device__ __forceinline__ void bessel_ratios(double x, R &K1, R &I);
+template <class R> __device__ __forceinline__ void bessel_ratios(double x, const void *nodes, R &K1, R &I);
 
-template <> __device__ __forceinline__ void bessel_ratios<double>(double x, double &K1, double &I)
+template <> __device__ __forceinline__ void bessel_ratios<double>(double x, const void *nodes, double &K1, double &I)
 {
-    const Bessel3 b = bessel3_scaled(x);
+    const Bessel3 b = bessel3_scaled(x, (const double *)nodes);
     K1 = b.k13 / b.k23;
     I = b.ik / b.k23;
 }
 
-template <> __device__ __forceinline__ void bessel_ratios<float>(double xd, float &K1, float &I)
+template <> __device__ __forceinline__ void bessel_ratios<float>(double xd, const void *nodes, float &K1, float &I)
 {
     const float x = fmaxf((float)xd, 1e-30f);
-    const float h = fminf(0.4f, rsqrtf(x));
+    const int k = x <= 6.25f ? 0 : (x <= 100.0f ? 1 : 2);
+    const int off = k == 0 ? 0 : kBn32N0 + (k - 1) * kBn32N, nn = k == 0 ? kBn32N0 : kBn32N;
+    const float4 *q = reinterpret_cast<const float4 *>(nodes) + off;
     float s13 = 0.5f, s23 = 0.5f, sik = 0.5f;
-    for (int j = 1; j < 4096; ++j) {
-        const float t = j * h;
-        const float sh = sinhf(0.5f * t);
-        const float chm1 = 2.0f * sh * sh;
-        const float e = expf(-x * chm1);
-        const float z = expf(t * (1.0f / 3.0f)), zi = 1.0f / z;
-        const float c1 = 0.5f * (z + zi), c2 = 0.5f * (z * z + zi * zi);
-        s13 += e * c1;
-        s23 += e * c2;
-        sik += e * c1 / (1.0f + chm1);
-        if (x * chm1 > 22.0f && x * (1.0f + chm1) > 22.0f) break;
+    for (int j = 1; j < nn; ++j) {
+        const float4 a = q[j];                          // cosh t - 1, cosh t/3, cosh 2t/3, ratio
+        const float e = expf(-x * a.x);
+        s13 += e * a.y;
+        s23 += e * a.z;
+        sik += e * a.w;
+        if (x * a.x > 22.0f && x * (1.0f + a.x) > 22.0f) break;
     }
-    K1 = s13 / s23;
+    K1 = s13 / s23;       // the step h cancels in the ratios
     I = sik / s23;
 }
 
@@ -159,6 +164,7 @@ struct FieldDev {
     int kind;
     double E0[3], B0[3];
     double a0, phase_len;
+    double inv_phase_len;      // 1 / phase_len (0 without envelope)
 };
 
 // E and B at position x (only x[0] enters the plane wave) and time t.
@@ -172,8 +178,9 @@ template <> __device__ __forceinline__ void eval_fields<double>(const FieldDev &
         const double phi = t + x0;
         double g = 1.0;
         if (f.phase_len > 0.0) {
-            if (phi < 0.0 || phi > f.phase_len) g = 0.0;
-            else { const double sn = sin(kPi * phi / f.phase_len); g = sn * sn; }
+            if (phi < 0.0 || phi > f.phase_len) return;      // outside the pulse
+            const double sn = sin(kPi * phi * f.inv_phase_len);
+            g = sn * sn;
         }
         const double ey = f.a0 * g * cos(phi);
         E.y += ey;
@@ -181,7 +188,8 @@ template <> __device__ __forceinline__ void eval_fields<double>(const FieldDev &
     }
 }
 
-// single precision: the phase is formed and reduced modulo 2 pi in FP64, the trig in FP32
+// single precision: the phase is formed and reduced to revolutions in FP64; the sine and
+// cosine of the reduced argument use the hardware instructions (|argument| <= 1 revolution)
 template <> __device__ __forceinline__ void eval_fields<float>(const FieldDev &f, double x0, double t, V3<float> &E, V3<float> &B)
 {
     E = {(float)f.E0[0], (float)f.E0[1], (float)f.E0[2]};
@@ -190,15 +198,14 @@ template <> __device__ __forceinline__ void eval_fields<float>(const FieldDev &f
         const double phi = t + x0;
         float g = 1.0f;
         if (f.phase_len > 0.0) {
-            if (phi < 0.0 || phi > f.phase_len) g = 0.0f;
-            else {
-                const double a = phi / f.phase_len;                 // in [0, 1]
-                const float sn = sinf((float)(kPi * a));
-                g = sn * sn;
-            }
+            if (phi < 0.0 || phi > f.phase_len) return;
+            const float a = (float)(phi * f.inv_phase_len);          // in [0, 1]: half a revolution of sin(pi a)
+            const float sn = __builtin_amdgcn_sinf(0.5f * a);         // sin(2 pi r), r in revolutions
+            g = sn * sn;
         }
-        const double red = phi - 2.0 * kPi * rint(phi * (0.5 / kPi));
-        const float ey = (float)f.a0 * g * cosf((float)red);
+        const double rev = phi * (0.5 / kPi);
+        const float red = (float)(rev - rint(rev));                    // in [-1/2, 1/2] revolutions
+        const float ey = (float)f.a0 * g * __builtin_amdgcn_cosf(red);
         E.y += ey;
         B.z -= ey;
     }
@@ -246,16 +253,16 @@ template <class R> struct Basis { V3<R> e, b, k; };
 template <class R>
 __device__ __forceinline__ double basis_chi(int charge, double eps_r, V3<R> p, double p0, V3<R> E, V3<R> B, Basis<R> &out)
 {
+    // FP64: the cancellation-prone F = p0 E + p x B and the invariant (p0 E + p x B)^2 - (p.E)^2
     const V3<double> pd = cvt<double>(p), Ed = cvt<double>(E), Bd = cvt<double>(B);
     const V3<double> F = p0 * Ed + cross(pd, Bd);
     const double pE = dot(pd, Ed);
     const double rad = dot(F, F) - pE * pE;
-    const double pn2 = dot(pd, pd);
-    // transverse part of F (FP64), then unit vectors in R
-    const V3<double> Ft = F - (dot(F, pd) / pn2) * pd;
+    // directions in R: khat, the part of F transverse to khat, eps, beta
+    out.k = rsqrt_r(dot(p, p)) * p;
+    const V3<double> kd = cvt<double>(out.k);
+    const V3<double> Ft = F - dot(F, kd) * kd;
     const double ft2 = dot(Ft, Ft);
-    const R ipn = rsqrt_r((R)pn2);
-    out.k = ipn * p;
     if (!(ft2 > 0.0)) {
         out.e = {0, 0, 0};
         out.b = {0, 0, 0};
@@ -264,7 +271,7 @@ __device__ __forceinline__ double basis_chi(int charge, double eps_r, V3<R> p, d
     const R sgn = charge > 0 ? (R)-1 : (R)1;
     out.e = (sgn * rsqrt_r((R)ft2)) * cvt<R>(Ft);
     out.b = cross(out.k, out.e);
-    return eps_r * sqrt(rad > 0.0 ? rad : 0.0);
+    return eps_r * (double)sqrt_r((R)(rad > 0.0 ? rad : 0.0));
 }
 
 // ------------------------------------------------------------------ table interpolation

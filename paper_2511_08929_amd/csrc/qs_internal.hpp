@@ -16,6 +16,8 @@ struct TablesDev {
     const double *lnrate;     // [sum n_chi(channel)]
     const float *lnrate32;
     const double *nu;         // [sum n_chi(channel) * n_rho]
+    const double *bn64;       // trapezoid nodes of the Bessel functions, FP64 levels
+    const float *bn32;        // FP32 levels
     int off_rate[4];
     int64_t off_nu[4];
 };
@@ -26,6 +28,8 @@ struct qed_tables_s {
     double *d_lnrate;
     float *d_lnrate32;
     double *d_nu;
+    double *d_bn64;
+    float *d_bn32;
     int64_t n_rate, n_nu;
 };
 

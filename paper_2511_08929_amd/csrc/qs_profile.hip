@@ -18,7 +18,7 @@ std::vector<hipEvent_t> g_pool;
 hipEvent_t g_open = nullptr;
 
 const char *const kNames[K_NKERNELS] = {"table_build", "push", "lepton_main", "emit_process", "photon_main",
-                                        "pair_process", "mask_reduce", "book", "mask_expand", "set_prev",
+                                        "pair_process", "mask_reduce", "book", "expand", "clock",
                                         "alive_mask", "gather", "scatter_back"};
 
 hipEvent_t take()

@@ -45,14 +45,25 @@ struct StepDev {
     int64_t step;
     uint64_t seed;
     uint32_t flags;
+    const int64_t *clock;      // optional device step offset (replayable launches)
 };
+
+// step index and time of this launch: params.step + *clock and params.t + *clock dt
+__device__ __forceinline__ StepDev localize(StepDev S)
+{
+    if (S.clock) {
+        const int64_t off = *S.clock;
+        S.step += off;
+        S.t += (double)off * S.dt;
+    }
+    return S;
+}
 
 enum { C_EMIT = 0, C_PAIR, C_PROB, C_CHI, C_NORM, C_OVER, C_RETIRED, C_LSTEP, C_GSTEP, C_GQED, kNCtr };
 
 struct WS {
     uint64_t *mask;      // [2][nchunks]: transition, branch (up / plus)
     uint32_t *bcnt;      // [kMaxGrid]: transitions per block of the streaming pass
-    uint32_t *boff;      // [kMaxGrid]: their exclusive prefix sums
     int64_t *book;       // [8]: base0, total, base1, n_fit, n processed, block range
     uint32_t *bctr;      // [kMaxGrid][kNCtr]: per-block counts of the streaming pass
     uint32_t *idx;       // [max particles]
@@ -68,7 +79,6 @@ WS carve(void *ws, int64_t cap, int64_t *nchunks_out)
     WS w;
     w.mask = (uint64_t *)b; b += align256(sizeof(uint64_t) * 2 * nch);
     w.bcnt = (uint32_t *)b; b += align256(sizeof(uint32_t) * kMaxGrid);
-    w.boff = (uint32_t *)b; b += align256(sizeof(uint32_t) * kMaxGrid);
     w.book = (int64_t *)b;  b += align256(sizeof(int64_t) * 8);
     w.bctr = (uint32_t *)b; b += align256(sizeof(uint32_t) * kMaxGrid * kNCtr);
     w.idx = (uint32_t *)b;
@@ -80,6 +90,11 @@ WS carve(void *ws, int64_t cap, int64_t *nchunks_out)
 template <class R> __device__ __forceinline__ const R *rate_src(const TablesDev &T);
 template <> __device__ __forceinline__ const double *rate_src<double>(const TablesDev &T) { return T.lnrate; }
 template <> __device__ __forceinline__ const float *rate_src<float>(const TablesDev &T) { return T.lnrate32; }
+
+template <class R> __device__ __forceinline__ const void *bn_of(const TablesDev &T)
+{
+    return sizeof(R) == 8 ? (const void *)T.bn64 : (const void *)T.bn32;
+}
 
 // stage the two rate rows of one process (NLC: channels 0,1; NBW: 2,3) into LDS
 template <class R> __device__ __forceinline__ int stage_rates(const TablesDev &T, int grp, R *lds)
@@ -225,8 +240,9 @@ __device__ __forceinline__ LDecide<R> lepton_decide(const StepDev &S, const Tabl
 
 // ------------------------------------------------------------------ kernels: leptons
 template <class R>
-__global__ void __launch_bounds__(kBlock) k_push(LepDev<R> L, FieldDev F, StepDev S)
+__global__ void __launch_bounds__(kBlock) k_push(LepDev<R> L, FieldDev F, StepDev S0)
 {
+    const StepDev S = localize(S0);
     const int64_t n = *L.count;
     const int q = L.species == 0 ? -1 : 1;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
@@ -241,9 +257,10 @@ __global__ void __launch_bounds__(kBlock) k_push(LepDev<R> L, FieldDev F, StepDe
 }
 
 template <class R>
-__global__ void __launch_bounds__(kBlock) k_lepton_main(LepDev<R> L, FieldDev F, StepDev S, TablesDev T,
+__global__ void __launch_bounds__(kBlock) k_lepton_main(LepDev<R> L, FieldDev F, StepDev S0, TablesDev T,
                                                         uint64_t *mask, int64_t nchunks, uint32_t *bctr, uint32_t *bcnt)
 {
+    const StepDev S = localize(S0);
     extern __shared__ unsigned char smem_raw[];
     R *lds = reinterpret_cast<R *>(smem_raw);
     stage_rates<R>(T, 0, lds);
@@ -308,10 +325,11 @@ __global__ void __launch_bounds__(kBlock) k_lepton_main(LepDev<R> L, FieldDev F,
 // emitter processing: lambda from the selected inverse CDF, recoil, spin collapse, Stokes
 // collapse, P-vector, photon append (NLC section, steps after the decision)
 template <class R>
-__global__ void __launch_bounds__(kBlock) k_emit_process(LepDev<R> L, PhoDev<R> G, FieldDev F, StepDev S, TablesDev T,
+__global__ void __launch_bounds__(kBlock) k_emit_process(LepDev<R> L, PhoDev<R> G, FieldDev F, StepDev S0, TablesDev T,
                                                          const uint64_t *mask, int64_t nchunks, const uint32_t *idx,
                                                          const int64_t *book, unsigned long long *ctr)
 {
+    const StepDev S = localize(S0);
     extern __shared__ unsigned char smem_raw[];
     R *lds = reinterpret_cast<R *>(smem_raw);
     stage_rates<R>(T, 0, lds);
@@ -335,7 +353,7 @@ __global__ void __launch_bounds__(kBlock) k_emit_process(LepDev<R> L, PhoDev<R> 
         Unif<R>::two(philox_block(S.seed, lepton_id(L.species, i), S.step, 1u), r3, r4);
         SpecPt<R> qp;
         qp.lam = (R)lam_d; qp.oml = (R)oml_d; qp.u = (R)u_d;
-        bessel_ratios<R>(2.0 * u_d / (3.0 * d.chi), qp.K1, qp.I);
+        bessel_ratios<R>(2.0 * u_d / (3.0 * d.chi), bn_of<R>(T), qp.K1, qp.I);
         const V3<R> si = {dot(s, d.bs.e), dot(s, d.bs.b), dot(s, d.bs.k)};
         const R w = nlc_w(qp, si.y);
         const V3<R> g = nlc_g(qp, si);
@@ -423,9 +441,10 @@ __device__ __forceinline__ PDecide<R> photon_decide(const StepDev &S, const Tabl
 }
 
 template <class R>
-__global__ void __launch_bounds__(kBlock) k_photon_main(PhoDev<R> G, FieldDev F, StepDev S, TablesDev T, uint64_t *mask,
+__global__ void __launch_bounds__(kBlock) k_photon_main(PhoDev<R> G, FieldDev F, StepDev S0, TablesDev T, uint64_t *mask,
                                                         int64_t nchunks, uint32_t *bctr, uint32_t *bcnt)
 {
+    const StepDev S = localize(S0);
     extern __shared__ unsigned char smem_raw[];
     R *lds = reinterpret_cast<R *>(smem_raw);
     stage_rates<R>(T, 1, lds);
@@ -501,13 +520,16 @@ __global__ void __launch_bounds__(kBlock) k_photon_main(PhoDev<R> G, FieldDev F,
 // pair processing: lambda~ from the selected inverse CDF, momenta, correlated spins
 // (NBW section), appends at base + rank in both lepton sets, decayed photon -> dead slot
 template <class R>
-__global__ void __launch_bounds__(kBlock) k_pair_process(PhoDev<R> G, LepDev<R> Le, LepDev<R> Lp, FieldDev F, StepDev S,
+__global__ void __launch_bounds__(kBlock) k_pair_process(PhoDev<R> G, LepDev<R> Le, LepDev<R> Lp, FieldDev F, StepDev S0,
                                                          TablesDev T, const uint64_t *mask, int64_t nchunks,
                                                          const uint32_t *idx, const int64_t *book)
 {
+    const StepDev S = localize(S0);
     extern __shared__ unsigned char smem_raw[];
     R *lds = reinterpret_cast<R *>(smem_raw);
     stage_rates<R>(T, 1, lds);
+    // photons born later in this step wait for the next one: the next pair step covers all stored now
+    if (blockIdx.x == 0 && threadIdx.x == 0) *G.count_prev = *G.count;
     const int64_t total = book[1], be = book[0], bp = book[2], nfit = book[3];
     for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < total; j += (int64_t)gridDim.x * blockDim.x) {
         const int64_t i = idx[j];
@@ -526,7 +548,7 @@ __global__ void __launch_bounds__(kBlock) k_pair_process(PhoDev<R> G, LepDev<R> 
         if (S.flags & F_PAIR_SPIN) {
             SpecPt<R> qp;
             qp.lam = (R)lam_d; qp.oml = (R)oml_d; qp.u = (R)0;
-            bessel_ratios<R>(2.0 * (1.0 / lam_d + 1.0 / oml_d) / (3.0 * d.chi), qp.K1, qp.I);
+            bessel_ratios<R>(2.0 * (1.0 / lam_d + 1.0 / oml_d) / (3.0 * d.chi), bn_of<R>(T), qp.K1, qp.I);
             const V3<R> xi = {d.x1, d.x2, d.x3};
             V3<R> je, jp;
             const R w0 = nbw_j(qp, xi, je, jp);
@@ -571,104 +593,82 @@ __global__ void __launch_bounds__(kBlock) k_pair_process(PhoDev<R> G, LepDev<R> 
 }
 
 // ------------------------------------------------------------------ kernels: scan / compaction
-// Bookkeeping (one block): exclusive scan of the per-block transition counts, totals of the
-// streaming pass's counters, append bases, capacity clamp, device-side counts.
-// mode 0: photon append (emission); 1: pair append to two lepton sets (and count_prev of the
-// photons <- count); 2: compaction.  `count` is the particle count the streaming pass used.
-constexpr int kBookThreads = 1024;
-
-__global__ void __launch_bounds__(kBookThreads) k_book(const uint32_t *bcnt, uint32_t *boff, const int64_t *count, int nblk,
-                                                       int64_t *book, int mode, int64_t *cnt0, int64_t cap0, int64_t *cnt1,
-                                                       int64_t cap1, int64_t *cnt_prev, const int64_t *cnt_src,
-                                                       unsigned long long *ctr, const uint32_t *bctr)
-{
-    __shared__ uint32_t wsum[kBookThreads / 64];
-    __shared__ unsigned long long csum[kBookThreads / 64][kNCtr];
-    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
-    const int64_t n = *count;
-    // exclusive scan of bcnt[0, nblk): two entries per thread
-    const int i0 = 2 * tid;
-    const uint32_t a0 = i0 < nblk ? bcnt[i0] : 0u, a1 = i0 + 1 < nblk ? bcnt[i0 + 1] : 0u;
-    const uint32_t tsum = a0 + a1;
-    uint32_t incl = tsum;
-    for (int o = 1; o < 64; o <<= 1) {
-        const uint32_t y = __shfl_up(incl, o);
-        if (lane >= o) incl += y;
-    }
-    if (lane == 63) wsum[wid] = incl;
-    // counters: thread t sums blocks t, t + 1024 (kMaxGrid = 2048)
-    unsigned long long c[kNCtr];
-#pragma unroll
-    for (int k = 0; k < kNCtr; ++k) c[k] = 0ull;
-    if (bctr) {
-        for (int bb = tid; bb < nblk; bb += kBookThreads)
-#pragma unroll
-            for (int k = 0; k < kNCtr; ++k) c[k] += bctr[bb * kNCtr + k];
-    }
-#pragma unroll
-    for (int k = 0; k < kNCtr; ++k) {
-        unsigned long long t = c[k];
-        for (int o = 32; o > 0; o >>= 1) t += __shfl_xor(t, o);
-        if (lane == 0) csum[wid][k] = t;
-    }
-    __syncthreads();
-    uint32_t woff = 0, total = 0;
-    for (int w = 0; w < kBookThreads / 64; ++w) {
-        if (w < wid) woff += wsum[w];
-        total += wsum[w];
-    }
-    const uint32_t ex = woff + incl - tsum;
-    if (i0 < nblk) boff[i0] = ex;
-    if (i0 + 1 < nblk) boff[i0 + 1] = ex + a0;
-    if (ctr && bctr && tid < kNCtr) {
-        unsigned long long t = 0;
-        for (int w = 0; w < kBookThreads / 64; ++w) t += csum[w][tid];
-        if (t) atomicAdd(ctr + tid, t);
-    }
-    if (tid != 0) return;
-    book[4] = n;
-    book[5] = block_len(n, nblk);
-    if (mode == 0) {
-        const int64_t base = cnt0 ? *cnt0 : 0;
-        const int64_t room = cnt0 && cap0 - base > 0 ? cap0 - base : 0;
-        const int64_t nfit = (int64_t)total < room ? (int64_t)total : room;
-        book[0] = base; book[1] = total; book[2] = 0; book[3] = nfit;
-        if (cnt0) *cnt0 = base + nfit;
-        if (ctr) {
-            atomicAdd(ctr + C_EMIT, (unsigned long long)total);
-            if (total > nfit) atomicAdd(ctr + C_OVER, (unsigned long long)(total - nfit));
-        }
-    } else if (mode == 1) {
-        const int64_t be = *cnt0, bp = *cnt1;
-        int64_t room = cap0 - be < cap1 - bp ? cap0 - be : cap1 - bp;
-        room = room > 0 ? room : 0;
-        const int64_t nfit = (int64_t)total < room ? (int64_t)total : room;
-        book[0] = be; book[1] = total; book[2] = bp; book[3] = nfit;
-        *cnt0 = be + nfit;
-        *cnt1 = bp + nfit;
-        if (ctr) {
-            atomicAdd(ctr + C_PAIR, (unsigned long long)total);
-            if (total > nfit) atomicAdd(ctr + C_OVER, (unsigned long long)(total - nfit));
-        }
-    } else {
-        book[0] = 0; book[1] = total; book[2] = 0; book[3] = total;
-    }
-    if (cnt_prev) *cnt_prev = mode == 2 ? (int64_t)total : *cnt_src;
-}
-
-// ascending list of the indices whose transition bit is set; block b expands the mask words of
-// the particle range block b of the streaming pass owned, starting at rank boff[b]
-__global__ void __launch_bounds__(kBlock) k_mask_expand(const uint64_t *mask, const uint32_t *boff, const int64_t *book,
-                                                        uint32_t *idx)
+// Scan + bookkeeping + expansion in one launch over the streaming pass's grid.
+// Block b sums the transition counts of the blocks before it (its rank offset) and writes the
+// ascending indices of the transitioning particles of the range it owned in the streaming pass.
+// Block 0 also does the bookkeeping: total, append bases, capacity clamp, device counts:
+//   mode 0  photon append (emission)      cnt0 = photons
+//   mode 1  pair append to two lepton sets (cnt0 = electrons, cnt1 = positrons)
+//   mode 2  compaction (cnt_prev = survivors; the photon count is set by the copy-back)
+// and every 32nd block adds the streaming pass's per-block counters of 32 blocks to ctr.
+// `count` is the particle count the streaming pass used; it is not modified here.
+__global__ void __launch_bounds__(kBlock) k_expand(const uint64_t *mask, const uint32_t *bcnt, const int64_t *count,
+                                                   int64_t *book, int mode, int64_t *cnt0, int64_t cap0, int64_t *cnt1,
+                                                   int64_t cap1, int64_t *cnt_prev, unsigned long long *ctr,
+                                                   const uint32_t *bctr, uint32_t *idx)
 {
     __shared__ uint32_t wtot[kBlock / 64];
-    const int64_t n = book[4], B = book[5];
-    const int64_t start = (int64_t)blockIdx.x * B;
+    __shared__ unsigned long long wc[kBlock / 64];
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    const int nblk = gridDim.x, b = blockIdx.x;
+    const int64_t n = *count;
+    // rank offset of this block and (block 0) the total
+    uint32_t pre = 0, all = 0;
+    for (int k = threadIdx.x; k < nblk; k += kBlock) {
+        const uint32_t v = bcnt[k];
+        all += v;
+        if (k < b) pre += v;
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        pre += __shfl_xor(pre, o);
+        all += __shfl_xor(all, o);
+    }
+    if (lane == 0) { wtot[wid] = pre; wc[wid] = all; }
+    __syncthreads();
+    uint32_t rank0 = 0, total = 0;
+    for (int w = 0; w < kBlock / 64; ++w) { rank0 += wtot[w]; total += (uint32_t)wc[w]; }
+    __syncthreads();
+    // counters of the streaming pass: in blocks b = 0, 32, 64, ..., thread c adds counter c of 32 blocks
+    if (ctr && bctr && (b & 31) == 0 && threadIdx.x < kNCtr) {
+        const int hi = b + 32 < nblk ? b + 32 : nblk;
+        unsigned long long t = 0;
+        for (int k = b; k < hi; ++k) t += bctr[k * kNCtr + threadIdx.x];
+        if (t) atomicAdd(ctr + threadIdx.x, t);
+    }
+    if (b == 0 && threadIdx.x == 0) {
+        if (mode == 0) {
+            const int64_t base = cnt0 ? *cnt0 : 0;
+            const int64_t room = cnt0 && cap0 - base > 0 ? cap0 - base : 0;
+            const int64_t nfit = (int64_t)total < room ? (int64_t)total : room;
+            book[0] = base; book[1] = total; book[2] = 0; book[3] = nfit;
+            if (cnt0) *cnt0 = base + nfit;
+            if (ctr) {
+                atomicAdd(ctr + C_EMIT, (unsigned long long)total);
+                if (total > nfit) atomicAdd(ctr + C_OVER, (unsigned long long)(total - nfit));
+            }
+        } else if (mode == 1) {
+            const int64_t be = *cnt0, bp = *cnt1;
+            int64_t room = cap0 - be < cap1 - bp ? cap0 - be : cap1 - bp;
+            room = room > 0 ? room : 0;
+            const int64_t nfit = (int64_t)total < room ? (int64_t)total : room;
+            book[0] = be; book[1] = total; book[2] = bp; book[3] = nfit;
+            *cnt0 = be + nfit;
+            *cnt1 = bp + nfit;
+            if (ctr) {
+                atomicAdd(ctr + C_PAIR, (unsigned long long)total);
+                if (total > nfit) atomicAdd(ctr + C_OVER, (unsigned long long)(total - nfit));
+            }
+        } else {
+            book[0] = 0; book[1] = total; book[2] = 0; book[3] = total;
+            if (cnt_prev) *cnt_prev = (int64_t)total;
+        }
+    }
+    // expansion of this block's mask words
+    const int64_t B = block_len(n, nblk);
+    const int64_t start = (int64_t)b * B;
     if (start >= n) return;
     const int64_t end = start + B < n ? start + B : n;
     const int64_t c0 = start >> 6, c1 = cdiv(end, 64);
-    uint32_t rank0 = boff[blockIdx.x];
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     for (int64_t tile = c0; tile < c1; tile += kBlock) {
         const int64_t c = tile + threadIdx.x;
         const uint64_t m = c < c1 ? mask[c] : 0ull;
@@ -688,8 +688,8 @@ __global__ void __launch_bounds__(kBlock) k_mask_expand(const uint64_t *mask, co
         uint32_t rank = rank0 + woff + incl - pc;
         uint64_t bits = m;
         while (bits) {
-            const int b = __ffsll((long long)bits) - 1;
-            idx[rank++] = (uint32_t)(c * 64 + b);
+            const int bit = __ffsll((long long)bits) - 1;
+            idx[rank++] = (uint32_t)(c * 64 + bit);
             bits &= bits - 1;
         }
         rank0 += ttot;
@@ -802,6 +802,7 @@ FieldDev field_dev(const qed_fields *f)
     }
     d.a0 = f->a0;
     d.phase_len = f->phase_len;
+    d.inv_phase_len = f->phase_len > 0.0 ? 1.0 / f->phase_len : 0.0;
     return d;
 }
 
@@ -813,6 +814,7 @@ StepDev step_dev(const qed_step_params *p)
     s.k_retire = p->k_retire;
     s.Kc = kAlpha / (sqrt(3.0) * kPi * p->eps_r);
     s.step = p->step; s.seed = p->seed; s.flags = p->flags;
+    s.clock = p->d_clock;
     return s;
 }
 
@@ -857,11 +859,9 @@ qed_status emit_impl(qed_tables T, const qed_leptons *L, const qed_fields *f, co
     QS_LAUNCH(K_LEPTON_MAIN, k_lepton_main<R>, dim3(g), dim3(kBlock), lds_nlc, st, ld, fd, sd, T->dev, w.mask, nch, w.bctr,
               w.bcnt);
     const PhoDev<R> gd = pho_dev<R>((p->flags & QED_EMIT) ? G : nullptr);
-    QS_LAUNCH(K_BOOK, k_book, dim3(1), dim3(kBookThreads), 0, st, (const uint32_t *)w.bcnt, w.boff, L->d_count, g, w.book,
-              0, gd.count, gd.cap, (int64_t *)nullptr, (int64_t)0, (int64_t *)nullptr, (const int64_t *)nullptr, c,
-              (const uint32_t *)w.bctr);
-    QS_LAUNCH(K_MASK_EXPAND, k_mask_expand, dim3(g), dim3(kBlock), 0, st, (const uint64_t *)w.mask, (const uint32_t *)w.boff,
-              (const int64_t *)w.book, w.idx);
+    QS_LAUNCH(K_MASK_EXPAND, k_expand, dim3(g), dim3(kBlock), 0, st, (const uint64_t *)w.mask, (const uint32_t *)w.bcnt,
+              (const int64_t *)L->d_count, w.book, 0, gd.count, gd.cap, (int64_t *)nullptr, (int64_t)0,
+              (int64_t *)nullptr, c, (const uint32_t *)w.bctr, w.idx);
     QS_LAUNCH(K_EMIT_PROCESS, k_emit_process<R>, dim3(g), dim3(kBlock), lds_nlc, st, ld, gd, fd, sd, T->dev, w.mask, nch, w.idx,
                        w.book, c);
     return qs_launch_status(__func__);
@@ -882,12 +882,9 @@ qed_status pair_impl(qed_tables T, const qed_photons *G, const qed_fields *f, co
     const int g = grid_for(G->capacity);
     QS_LAUNCH(K_PHOTON_MAIN, k_photon_main<R>, dim3(g), dim3(kBlock), lds_nbw, st, gd, fd, sd, T->dev, w.mask, nch, w.bctr,
               w.bcnt);
-    // book reads *d_count_prev (the count just stepped) before setting it to *d_count
-    QS_LAUNCH(K_BOOK, k_book, dim3(1), dim3(kBookThreads), 0, st, (const uint32_t *)w.bcnt, w.boff, G->d_count_prev, g,
-              w.book, 1, Le->d_count, Le->capacity, Lp->d_count, Lp->capacity, G->d_count_prev,
-              (const int64_t *)G->d_count, c, (const uint32_t *)w.bctr);
-    QS_LAUNCH(K_MASK_EXPAND, k_mask_expand, dim3(g), dim3(kBlock), 0, st, (const uint64_t *)w.mask, (const uint32_t *)w.boff,
-              (const int64_t *)w.book, w.idx);
+    QS_LAUNCH(K_MASK_EXPAND, k_expand, dim3(g), dim3(kBlock), 0, st, (const uint64_t *)w.mask, (const uint32_t *)w.bcnt,
+              (const int64_t *)G->d_count_prev, w.book, 1, Le->d_count, Le->capacity, Lp->d_count, Lp->capacity,
+              (int64_t *)nullptr, c, (const uint32_t *)w.bctr, w.idx);
     QS_LAUNCH(K_PAIR_PROCESS, k_pair_process<R>, dim3(g), dim3(kBlock), lds_nbw, st, gd, lep_dev<R>(Le), lep_dev<R>(Lp), fd, sd,
                        T->dev, w.mask, nch, w.idx, w.book);
     return qs_launch_status(__func__);
@@ -900,7 +897,7 @@ extern "C" size_t qed_workspace_size(int64_t max_particles)
 {
     const int64_t cap = max_particles > 0 ? max_particles : 1;
     const int64_t nch = cdiv(cap, 64);
-    return align256(sizeof(uint64_t) * 2 * nch) + 2 * align256(sizeof(uint32_t) * kMaxGrid) +
+    return align256(sizeof(uint64_t) * 2 * nch) + align256(sizeof(uint32_t) * kMaxGrid) +
            align256(sizeof(int64_t) * 8) + align256(sizeof(uint32_t) * kMaxGrid * kNCtr) + align256(sizeof(uint32_t) * cap);
 }
 
@@ -947,6 +944,17 @@ extern "C" qed_status qed_pair(qed_tables T, const qed_photons *G, const qed_fie
     return pair_impl<float>(T, G, f, p, Le, Lp, ctr, ws, ws_bytes, st);
 }
 
+__global__ void k_clock_advance(int64_t *clock) { *clock += 1; }
+
+extern "C" qed_status qed_clock_advance(int64_t *d_clock, qed_stream stream)
+{
+    if (!d_clock) return QED_ERR_INVALID;
+    hipStream_t st = (hipStream_t)stream;
+    qs_clear_error();
+    QS_LAUNCH(K_SET_PREV, k_clock_advance, dim3(1), dim3(1), 0, st, d_clock);
+    return qs_launch_status(__func__);
+}
+
 extern "C" size_t qed_compact_workspace_size(const qed_photons *G, qed_precision prec)
 {
     if (!G) return 0;
@@ -974,11 +982,9 @@ template <class R> static qed_status compact_impl(const qed_photons *G, void *ws
     const PhoDev<R> gd = pho_dev<R>(G);
     const int g = grid_for(G->capacity);
     QS_LAUNCH(K_ALIVE_MASK, k_alive_mask<R>, dim3(g), dim3(kBlock), 0, st, gd, w.mask, w.bcnt);
-    QS_LAUNCH(K_BOOK, k_book, dim3(1), dim3(kBookThreads), 0, st, (const uint32_t *)w.bcnt, w.boff, G->d_count, g, w.book,
-              2, (int64_t *)nullptr, (int64_t)0, (int64_t *)nullptr, (int64_t)0, G->d_count_prev,
-              (const int64_t *)nullptr, (unsigned long long *)nullptr, (const uint32_t *)nullptr);
-    QS_LAUNCH(K_MASK_EXPAND, k_mask_expand, dim3(g), dim3(kBlock), 0, st, (const uint64_t *)w.mask, (const uint32_t *)w.boff,
-              (const int64_t *)w.book, w.idx);
+    QS_LAUNCH(K_MASK_EXPAND, k_expand, dim3(g), dim3(kBlock), 0, st, (const uint64_t *)w.mask, (const uint32_t *)w.bcnt,
+              (const int64_t *)G->d_count, w.book, 2, (int64_t *)nullptr, (int64_t)0, (int64_t *)nullptr, (int64_t)0,
+              G->d_count_prev, (unsigned long long *)nullptr, (const uint32_t *)nullptr, w.idx);
     QS_LAUNCH(K_GATHER, k_gather<R>, dim3(g), dim3(kBlock), 0, st, gd, S, w.idx, w.book);
     QS_LAUNCH(K_SCATTER_BACK, k_scatter_back<R>, dim3(g), dim3(kBlock), 0, st, gd, S, w.book);
     return qs_launch_status(__func__);

@@ -76,14 +76,43 @@ GL12 legendre_nodes()
 
 __device__ __forceinline__ double kPi_over_sqrt3() { return qs::kPi / sqrt(3.0); }
 
+// trapezoid node tables of qs_device.hpp (host, FP64 libm): per node cosh t - 1, cosh(t/3),
+// cosh(2t/3), cosh(t/3)/cosh t at t = j h
+void fill_nodes(std::vector<double> &n64, std::vector<float> &n32)
+{
+    n64.assign(4 * qs::kBn64Nodes, 0.0);
+    for (int k = 0; k < qs::kBn64Levels; ++k) {
+        const int off = k == 0 ? 0 : qs::kBn64N0 + (k - 1) * qs::kBn64N, nn = k == 0 ? qs::kBn64N0 : qs::kBn64N;
+        const double h = 0.2 / (double)(1 << k);
+        for (int j = 0; j < nn; ++j) {
+            const double t = j * h, sh = sinh(0.5 * t);
+            const double chm1 = 2.0 * sh * sh, c1 = cosh(t / 3.0);
+            double *q = &n64[4 * (off + j)];
+            q[0] = chm1; q[1] = c1; q[2] = cosh(2.0 * t / 3.0); q[3] = c1 / (1.0 + chm1);
+        }
+    }
+    n32.assign(4 * qs::kBn32Nodes, 0.0f);
+    const double h32[qs::kBn32Levels] = {0.4, 0.1, 0.025};
+    for (int k = 0; k < qs::kBn32Levels; ++k) {
+        const int off = k == 0 ? 0 : qs::kBn32N0 + (k - 1) * qs::kBn32N, nn = k == 0 ? qs::kBn32N0 : qs::kBn32N;
+        for (int j = 0; j < nn; ++j) {
+            const double t = j * h32[k], sh = sinh(0.5 * t);
+            const double chm1 = 2.0 * sh * sh, c1 = cosh(t / 3.0);
+            float *q = &n32[4 * (off + j)];
+            q[0] = (float)fmin(chm1, 1e38); q[1] = (float)c1; q[2] = (float)cosh(2.0 * t / 3.0);
+            q[3] = (float)(c1 / (1.0 + chm1));
+        }
+    }
+}
+
 // spectrum density in nu for channel ch (un-normalized): w lam (1-lam)
-__device__ double density(int ch, double chi, double nu)
+__device__ double density(int ch, double chi, double nu, const double *bn)
 {
     const double lam = 1.0 / (1.0 + exp(-nu)), oml = 1.0 / (1.0 + exp(nu));
     if (ch < 2) {
         const double up = 2.0 * exp(nu) / (3.0 * chi);
         if (!(up < 700.0)) return 0.0;
-        const qs::Bessel3 b = qs::bessel3_scaled(up);
+        const qs::Bessel3 b = qs::bessel3_scaled(up, bn);
         const double kap = 1.0 / oml + oml;
         const double w = -b.ik + kap * b.k23 + (ch == 1 ? lam : -lam) * b.k13;
         return exp(-up) * w * lam * oml;
@@ -91,26 +120,26 @@ __device__ double density(int ch, double chi, double nu)
         const double ut = 1.0 / lam + 1.0 / oml;
         const double up = 2.0 * ut / (3.0 * chi);
         if (!(up < 700.0)) return 0.0;
-        const qs::Bessel3 b = qs::bessel3_scaled(up);
+        const qs::Bessel3 b = qs::bessel3_scaled(up, bn);
         const double rho = oml / lam + lam / oml;
         const double w0 = b.ik + rho * b.k23 - (ch == 3 ? 1.0 : -1.0) * b.k23;
         return exp(-up) * w0 * lam * oml;
     }
 }
 
-__device__ double gl_integral(const GL12 &g, int ch, double chi, double a, double b)
+__device__ double gl_integral(const GL12 &g, int ch, double chi, double a, double b, const double *bn)
 {
     if (!(b > a)) return 0.0;
     const double mid = 0.5 * (a + b), half = 0.5 * (b - a);
     double s = 0.0;
-    for (int i = 0; i < kNQ; ++i) s += g.w[i] * density(ch, chi, mid + half * g.x[i]);
+    for (int i = 0; i < kNQ; ++i) s += g.w[i] * density(ch, chi, mid + half * g.x[i], bn);
     return half * s;
 }
 
 // Newton on ln(cum(nu)) - ln(target) inside [lo, hi].
 // side > 0: cum = base + int_lo^nu f (increasing); side < 0: cum = base + int_nu^hi f (decreasing).
 __device__ double solve_root(const GL12 &g, int ch, double chi, int side, double base, double pint,
-                             double lo, double hi, double target)
+                             double lo, double hi, double target, const double *bn)
 {
     const double c_lo = side > 0 ? base : base + pint;
     const double c_hi = side > 0 ? base + pint : base;
@@ -120,9 +149,9 @@ __device__ double solve_root(const GL12 &g, int ch, double chi, int side, double
     double nu = (l_hi != l_lo) ? lo + (hi - lo) * (lt - l_lo) / (l_hi - l_lo) : 0.5 * (lo + hi);
     if (!(nu > a && nu < b)) nu = 0.5 * (a + b);
     for (int it = 0; it < 80; ++it) {
-        const double cum = side > 0 ? base + gl_integral(g, ch, chi, lo, nu) : base + gl_integral(g, ch, chi, nu, hi);
+        const double cum = side > 0 ? base + gl_integral(g, ch, chi, lo, nu, bn) : base + gl_integral(g, ch, chi, nu, hi, bn);
         const double r = log(cum) - lt;
-        const double f = density(ch, chi, nu);
+        const double f = density(ch, chi, nu, bn);
         const double step = f > 0.0 ? r * cum / (side > 0 ? f : -f) : 0.0;
         if (fabs(r) < 1e-15) {
             if (nu - step > a && nu - step < b) nu -= step;
@@ -147,7 +176,8 @@ __device__ __forceinline__ double decay(int ch, double chi, double nu)
     return ch < 2 ? 2.0 * exp(nu) / (3.0 * chi) : 4.0 * fabs(sinh(nu)) / (3.0 * chi);
 }
 
-__global__ void __launch_bounds__(256) k_build_tables(BuildArgs A, GL12 g, double *lnrate, double *nu_out)
+__global__ void __launch_bounds__(256) k_build_tables(BuildArgs A, GL12 g, double *lnrate, double *nu_out,
+                                                      const double *bn)
 {
     __shared__ double pint[kMaxPanels], left[kMaxPanels + 1], right[kMaxPanels + 1], edge[kMaxPanels + 1];
     __shared__ double s_total, s_tail;
@@ -180,7 +210,7 @@ __global__ void __launch_bounds__(256) k_build_tables(BuildArgs A, GL12 g, doubl
     }
     __syncthreads();
     int np = s_np;
-    for (int p = threadIdx.x; p < np; p += blockDim.x) pint[p] = gl_integral(g, ch, chi, edge[p], edge[p + 1]);
+    for (int p = threadIdx.x; p < np; p += blockDim.x) pint[p] = gl_integral(g, ch, chi, edge[p], edge[p + 1], bn);
     __syncthreads();
     if (threadIdx.x == 0) {
         double tail = 0.0;
@@ -214,13 +244,13 @@ __global__ void __launch_bounds__(256) k_build_tables(BuildArgs A, GL12 g, doubl
             } else {
                 int lo = 0, hi = np;
                 while (hi - lo > 1) { const int m = (lo + hi) >> 1; if (left[m] <= target) lo = m; else hi = m; }
-                nu = solve_root(g, ch, chi, +1, left[lo], pint[lo], edge[lo], edge[lo + 1], target);
+                nu = solve_root(g, ch, chi, +1, left[lo], pint[lo], edge[lo], edge[lo + 1], target, bn);
             }
         } else {
             const double target = total / (1.0 + exp(rho));
             int lo = 0, hi = np;
             while (hi - lo > 1) { const int m = (lo + hi) >> 1; if (right[m] > target) lo = m; else hi = m; }
-            nu = solve_root(g, ch, chi, -1, right[lo + 1], pint[lo], edge[lo], edge[lo + 1], target);
+            nu = solve_root(g, ch, chi, -1, right[lo + 1], pint[lo], edge[lo], edge[lo + 1], target, bn);
         }
         row[j] = nu;
     }
@@ -279,16 +309,24 @@ extern "C" qed_status qed_init_tables(const qed_table_params *params, qed_stream
     A.drho = G.drho;
     T->n_rate = r;
     T->n_nu = v;
+    std::vector<double> n64;
+    std::vector<float> n32;
+    fill_nodes(n64, n32);
     hipError_t e = hipMalloc(&T->d_lnrate, sizeof(double) * r);
     if (e == hipSuccess) e = hipMalloc(&T->d_lnrate32, sizeof(float) * r);
     if (e == hipSuccess) e = hipMalloc(&T->d_nu, sizeof(double) * v);
+    if (e == hipSuccess) e = hipMalloc(&T->d_bn64, sizeof(double) * n64.size());
+    if (e == hipSuccess) e = hipMalloc(&T->d_bn32, sizeof(float) * n32.size());
+    if (e == hipSuccess) e = hipMemcpyAsync(T->d_bn64, n64.data(), sizeof(double) * n64.size(), hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(T->d_bn32, n32.data(), sizeof(float) * n32.size(), hipMemcpyHostToDevice, st);
     if (e != hipSuccess) {
         qed_free_tables(T);
-        return qs_fail(e, "hipMalloc (tables)");
+        return qs_fail(e, "hipMalloc / upload (tables)");
     }
     const GL12 g = legendre_nodes();
     const int ntask = 2 * G.n_chi[0] + 2 * G.n_chi[1];
-    QS_LAUNCH(K_TABLES, k_build_tables, dim3(ntask), dim3(256), 0, st, A, g, T->d_lnrate, T->d_nu);
+    QS_LAUNCH(K_TABLES, k_build_tables, dim3(ntask), dim3(256), 0, st, A, g, T->d_lnrate, T->d_nu,
+              (const double *)T->d_bn64);
     QS_LAUNCH(K_TABLES, k_to_float, dim3((r + 255) / 256), dim3(256), 0, st, T->d_lnrate, T->d_lnrate32, r);
     e = hipGetLastError();
     if (e == hipSuccess) e = hipStreamSynchronize(st);
@@ -308,6 +346,8 @@ extern "C" qed_status qed_init_tables(const qed_table_params *params, qed_stream
     D.lnrate = T->d_lnrate;
     D.lnrate32 = T->d_lnrate32;
     D.nu = T->d_nu;
+    D.bn64 = T->d_bn64;
+    D.bn32 = T->d_bn32;
     *out = T;
     return QED_OK;
 }
@@ -318,6 +358,8 @@ extern "C" qed_status qed_free_tables(qed_tables T)
     if (T->d_lnrate) (void)hipFree(T->d_lnrate);
     if (T->d_lnrate32) (void)hipFree(T->d_lnrate32);
     if (T->d_nu) (void)hipFree(T->d_nu);
+    if (T->d_bn64) (void)hipFree(T->d_bn64);
+    if (T->d_bn32) (void)hipFree(T->d_bn32);
     free(T);
     return QED_OK;
 }

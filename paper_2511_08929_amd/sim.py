@@ -1,22 +1,24 @@
 """Time-step driver over the C ABI: one step = qed_emit (push + NLC) for electrons, then for
 positrons, then qed_pair (NBW) for the photons born in earlier steps; qed_compact on demand.
 
-All counts stay on the device; a step enqueues without host synchronization, so a sequence of
-steps can be captured in a HIP graph.
+All counts stay on the device; a step enqueues without host synchronization.  With
+``device_clock=True`` the step index and time come from a device counter that the step itself
+advances (qed_clock_advance), so the same sequence of launches is valid at every step and can be
+captured once in a HIP graph and replayed (``capture`` / ``replay``).
 """
 from __future__ import annotations
 
 import math
 
-from . import (ALPHA, QED_F32, QED_F64, QED_PAIR, LeptonBuffers, PhotonBuffers, Tables, make_fields, make_step,
-               new_counters, new_workspace, qed_compact, qed_compact_workspace_size, qed_emit, qed_pair,
-               qed_workspace_size)
+from . import (ALPHA, QED_F64, QED_PAIR, LeptonBuffers, PhotonBuffers, Tables, make_fields, make_step,
+               new_counters, new_workspace, qed_clock_advance, qed_compact, qed_compact_workspace_size, qed_emit,
+               qed_pair, qed_workspace_size)
 
 
 class Simulation:
     def __init__(self, tables: Tables, *, cap_e, cap_p, cap_g, track, fields, dt, eps_r, seed, flags,
                  k_retire=0.0, t0=0.0, a_e=ALPHA / (2 * math.pi), chi_e_min=1e-3, chi_e_max=1e2, chi_g_min=0.05,
-                 chi_g_max=1e2, device="cuda"):
+                 chi_g_max=1e2, device="cuda", device_clock=False):
         import torch
         self.tables = tables
         self.dtype = torch.float64 if tables.precision == QED_F64 else torch.float32
@@ -33,22 +35,62 @@ class Simulation:
         self.chi = (chi_e_min, chi_e_max, chi_g_min, chi_g_max)
         self.n = 0
         self._sp = None
+        self.clock = torch.zeros(1, dtype=torch.int64, device=device) if device_clock else None
 
     def step_params(self, n):
         return make_step(self.dt, self.eps_r, step=n, t=self.t0 + n * self.dt, seed=self.seed, flags=self.flags,
                          a_e=self.a_e, chi_e_min=self.chi[0], chi_e_max=self.chi[1], chi_g_min=self.chi[2],
                          chi_g_max=self.chi[3], k_retire=self.k_retire)
 
-    def step(self, stream=None):
+    def _params(self):
         sp = self._sp
         if sp is None:
-            sp = self._sp = self.step_params(self.n)
-        sp.step, sp.t, sp.flags = self.n, self.t0 + self.n * self.dt, self.flags
+            sp = self._sp = self.step_params(0)
+        if self.clock is not None:
+            # step = 0 + *clock, t = t0 + *clock dt on the device
+            sp.step, sp.t, sp.d_clock = 0, self.t0, self.clock.data_ptr()
+        else:
+            sp.step, sp.t, sp.d_clock = self.n, self.t0 + self.n * self.dt, None
+        sp.flags = self.flags
+        return sp
+
+    def _enqueue_step(self, stream=None):
+        sp = self._params()
         qed_emit(self.tables, self.e, self.fields, sp, self.g, self.ctr, self.ws, stream)
         if self.flags & QED_PAIR:
             qed_emit(self.tables, self.p, self.fields, sp, self.g, self.ctr, self.ws, stream)
             qed_pair(self.tables, self.g, self.fields, sp, self.e, self.p, self.ctr, self.ws, stream)
+        if self.clock is not None:
+            qed_clock_advance(self.clock, stream)
+
+    def step(self, stream=None):
+        if self.clock is not None and self.n == 0:
+            self.clock.fill_(0)
+        self._enqueue_step(stream)
         self.n += 1
 
     def compact(self, stream=None):
         qed_compact(self.g, self.tables.precision, self.ws, stream)
+
+    def capture(self, nsteps, compact_at_end=True):
+        """Record `nsteps` steps (and a compaction) into a HIP graph; needs device_clock=True.
+        The graph reads every count, the step and the time from device memory, so it can be
+        replayed from any state."""
+        import torch
+        assert self.clock is not None, "graph capture needs the device clock"
+        torch.cuda.synchronize()
+        self.clock.fill_(self.n)
+        torch.cuda.synchronize()
+        graph = torch.cuda.CUDAGraph()
+        side = torch.cuda.Stream()
+        with torch.cuda.graph(graph, stream=side):
+            for _ in range(nsteps):
+                self._enqueue_step()
+            if compact_at_end:
+                self.compact()
+        graph.steps = nsteps
+        return graph
+
+    def replay(self, graph):
+        graph.replay()
+        self.n += graph.steps

@@ -302,3 +302,33 @@ def test_bitwise_reproducible(q, gtab64):
     for a, b in zip(out[0][0] + out[0][1], out[1][0] + out[1][1]):
         np.testing.assert_array_equal(a, b)
     assert out[0][2] == out[1][2]
+
+
+def test_graph_replay_matches_eager(q, gtab64):
+    """A captured period (steps + compaction, step and time from the device clock) replayed
+    several times, with eager work and synchronizations between replays, equals the eager run
+    bit for bit after every replay."""
+    import torch
+    w = synth.subsample(synth.c2(), np.arange(2000))
+    period = 25
+    a = _sim(q, gtab64, w, w.n + 3000, 3000, 150_000, q.QED_ALL)
+    b = _sim(q, gtab64, w, w.n + 3000, 3000, 150_000, q.QED_ALL)
+    b.clock = torch.zeros(1, dtype=torch.int64, device="cuda")   # b reads step and time from the device
+    a.e.load(w.x, w.p, w.s)
+    b.e.load(w.x, w.p, w.s)
+    for _ in range(700):                     # reach the pulse, eagerly on both
+        a.step(); b.step()
+        if a.n % period == 0:
+            a.compact(); b.compact()
+    g = b.capture(period)
+    for rep in range(6):
+        for _ in range(period):
+            a.step()
+        a.compact()
+        b.replay(g)
+        torch.cuda.synchronize()
+        _ = b.e.count.item() + a.e.count.item()          # eager host work between replays
+        for x, y in zip(a.e.arrays() + a.g.arrays() + a.p.arrays(), b.e.arrays() + b.g.arrays() + b.p.arrays()):
+            np.testing.assert_array_equal(x, y)
+        assert q.counters_dict(a.ctr) == q.counters_dict(b.ctr), rep
+    assert a.n == b.n and q.counters_dict(a.ctr)["n_emit"] > 0
