@@ -36,12 +36,11 @@ def log(*a):
 
 def bytes_per_unit(es, tracked_x=1):
     """Algorithmic HBM bytes per lepton-step and per photon-step (element size es):
-    lepton: read and write x (tracked components), p[3], s[3];
-    photon: read id, k[3], x; write x; with chi_gamma >= chi_min also read and write P[3]."""
+    lepton: read and write the tracked x components, p[3], s[3];
+    photon: read id, k[3], P[3], x; write x and P[3]."""
     lep = 2 * es * (tracked_x + 6)
-    pho_base = 8 + es * 3 + 2 * es * tracked_x
-    pho_qed = 2 * es * 3
-    return lep, pho_base, pho_qed
+    pho = 8 + es * (6 + tracked_x) + es * (3 + tracked_x)
+    return lep, pho
 
 
 def run_gpu(q, prec, w, steps, warmup, compact_every, profile, graph=True):
@@ -90,6 +89,48 @@ def run_gpu(q, prec, w, steps, warmup, compact_every, profile, graph=True):
     return dict(wall=wall, ctr=ctr, ktimes=ktimes, n_photons=sim.g.n(), n_e=sim.e.n(), n_p=sim.p.n())
 
 
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "photon_main_head_on_1e6_fp32_hbm_traffic.md")
+
+
+def kernel_source_hash():
+    """sha256 over the HIP sources; HBM counters taken on other sources do not describe these kernels"""
+    import hashlib
+    h = hashlib.sha256()
+    d = os.path.join(ROOT, "paper_2511_08929_amd", "csrc")
+    for f in sorted(os.listdir(d)):
+        if f.endswith((".hip", ".hpp", ".h")):
+            with open(os.path.join(d, f), "rb") as fh:
+                h.update(f.encode() + b"\0" + fh.read())
+    return h.hexdigest()
+
+
+def load_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed counter summary (FETCH_SIZE and WRITE_SIZE
+    passes scaled by the copy-kernel factors), or None if absent or taken on other sources."""
+    try:
+        text = open(TRAFFIC_FILE).read()
+        blob = json.loads(text.split("```json", 1)[1].split("```", 1)[0])
+    except (OSError, IndexError, ValueError):
+        return None
+    if blob.get("kernel") != kernel or blob.get("source_sha256") != kernel_source_hash():
+        return None
+    return blob.get("traffic_bytes_per_launch")
+
+
+def probe(q, w, steps, compact_every):
+    """Counter-collection run: a plain elementwise kernel over 256 MiB in and 256 MiB out (the
+    calibration of FETCH_SIZE / WRITE_SIZE), then the single-precision path eagerly."""
+    import torch
+    a = torch.ones(1 << 26, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        torch.neg(a, out=b)
+    torch.cuda.synchronize()
+    del a, b
+    r = run_gpu(q, q.QED_F32, w, steps, 0, compact_every, profile=False, graph=False)
+    log(f"probe: {steps} steps in {r['wall']:.2f} s, counters {r['ctr']}")
+
+
 def cpu_baseline(n_sample, steps, nthreads):
     import oracle
     sys.path.insert(0, os.path.join(ROOT, "tests"))
@@ -117,6 +158,8 @@ def main():
     ap.add_argument("--no-fp64", action="store_true", help="skip timing the FP64 path")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=3000)
+    ap.add_argument("--probe", action="store_true",
+                    help="profiler run: copy calibration + the FP32 path, eager, no JSON line")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this build measures one GPU; multi-GPU runs are out of scope (the path shards by "
@@ -130,6 +173,9 @@ def main():
         sys.exit(1)
     w = synth.c2(n=args.n)
     log(f"workload {w.name}: n={w.n} steps={args.steps} warmup={args.warmup}")
+    if args.probe:
+        probe(q, w, args.steps, args.compact_every)
+        return
 
     # timed run: graph replays (no per-launch host work); kernel timing in a separate eager run
     r32 = run_gpu(q, q.QED_F32, w, args.steps, args.warmup, args.compact_every, profile=False, graph=True)
@@ -142,15 +188,14 @@ def main():
     log(f"fp32 (eager, events): {rk['wall']:.3f} s; kernel times {rk['ktimes']}")
 
     # roofline of the dominant kernel (largest total time), from the HIP-event timings
-    lep_b, pho_b, pho_q = bytes_per_unit(4)
-    bytes_of = {"lepton_main": ck["n_lepton_steps"] * lep_b,
-                "photon_main": ck["n_photon_steps"] * pho_b + ck["n_photon_qed"] * pho_q}
+    lep_b, pho_b = bytes_per_unit(4)
+    bytes_of = {"lepton_main": ck["n_lepton_steps"] * lep_b, "photon_main": ck["n_photon_steps"] * pho_b}
     kt = {k: v for k, v in rk["ktimes"].items() if k in bytes_of}
     dom = max(kt, key=lambda k: kt[k][1])
     calls, ms = kt[dom]
     achieved = bytes_of[dom] / (ms * 1e-3) / 1e9
     roof = dict(bound="hbm", kernel=dom, achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
-                frac=round(achieved / HBM_PEAK_GBS, 4), traffic=None,
+                frac=round(achieved / HBM_PEAK_GBS, 4), traffic=load_traffic(dom),
                 avg_launch_us=round(ms * 1e3 / calls, 2), launches=calls,
                 bytes_per_launch=round(bytes_of[dom] / calls),
                 kernel_ms={k: round(v[1], 3) for k, v in rk["ktimes"].items()})

@@ -14,6 +14,8 @@ SOURCES = ["qs_tables.hip", "qs_step.hip", "qs_profile.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC", "-shared",
+         # FP32 division and square root by the hardware approximations (FP64 is unaffected)
+         "-fno-hip-fp32-correctly-rounded-divide-sqrt",
          # keep packed FP32 instructions out of the generated code
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-Wall", "-Wno-unused-function", "-Wno-unused-variable"]

@@ -21,6 +21,12 @@ enum : uint32_t {
 };
 
 // ------------------------------------------------------------------ small vectors
+// A renormalization of |s| or |xi| is counted when the excess over 1 of the squared norm is
+// above rounding noise of the precision: 1e-12 in FP64, 1e-6 (about 8 ulp) in FP32.
+template <class R> __device__ __forceinline__ constexpr R norm_count_tol();
+template <> __device__ __forceinline__ constexpr double norm_count_tol<double>() { return 1e-12; }
+template <> __device__ __forceinline__ constexpr float norm_count_tol<float>() { return 1e-6f; }
+
 template <class R> struct V3 { R x, y, z; };
 
 template <class R> __device__ __forceinline__ V3<R> v3(R a, R b, R c) { return V3<R>{a, b, c}; }
@@ -34,14 +40,22 @@ template <class R> __device__ __forceinline__ V3<R> cross(V3<R> a, V3<R> b)
 }
 template <class D, class S> __device__ __forceinline__ V3<D> cvt(V3<S> a) { return {(D)a.x, (D)a.y, (D)a.z}; }
 
-__device__ __forceinline__ float rsqrt_r(float v) { return 1.0f / sqrtf(v); }
+// Single precision uses the hardware approximations (about 1 ulp): v_rsq, v_sqrt, v_rcp, v_exp
+// (base 2) and v_log (base 2).  Double precision uses the correctly rounded library forms.
+__device__ __forceinline__ float rsqrt_r(float v) { return __builtin_amdgcn_rsqf(v); }
 __device__ __forceinline__ double rsqrt_r(double v) { return 1.0 / sqrt(v); }
-__device__ __forceinline__ float sqrt_r(float v) { return sqrtf(v); }
+__device__ __forceinline__ float sqrt_r(float v) { return __builtin_amdgcn_sqrtf(v); }
 __device__ __forceinline__ double sqrt_r(double v) { return sqrt(v); }
-__device__ __forceinline__ float exp_r(float v) { return expf(v); }
+__device__ __forceinline__ float rcp_r(float v) { return __builtin_amdgcn_rcpf(v); }
+__device__ __forceinline__ double rcp_r(double v) { return 1.0 / v; }
+__device__ __forceinline__ float exp_r(float v) { return __builtin_amdgcn_exp2f(v * 1.44269504088896341f); }
 __device__ __forceinline__ double exp_r(double v) { return exp(v); }
-__device__ __forceinline__ float log_r(float v) { return logf(v); }
+__device__ __forceinline__ float log_r(float v) { return __builtin_amdgcn_logf(v) * 0.693147180559945309f; }
 __device__ __forceinline__ double log_r(double v) { return log(v); }
+// num / den of two FP64 values, rounded to R: exact division in FP64, v_rcp in FP32
+template <class R> __device__ __forceinline__ R ratio_r(double num, double den);
+template <> __device__ __forceinline__ double ratio_r<double>(double num, double den) { return num / den; }
+template <> __device__ __forceinline__ float ratio_r<float>(double num, double den) { return (float)num * rcp_r((float)den); }
 
 // ------------------------------------------------------------------ Philox4x32-10
 // Salmon, Moraes, Dror, Shaw (SC'11): 10 rounds of two 32x32 -> 64 multiplies with
@@ -50,9 +64,9 @@ __device__ __forceinline__ uint4 philox4x32_10(uint4 c, uint32_t k0, uint32_t k1
 {
 #pragma unroll
     for (int r = 0; r < 10; ++r) {
-        const uint32_t lo0 = 0xD2511F53u * c.x, hi0 = __umulhi(0xD2511F53u, c.x);
-        const uint32_t lo1 = 0xCD9E8D57u * c.z, hi1 = __umulhi(0xCD9E8D57u, c.z);
-        c = make_uint4(hi1 ^ c.y ^ k0, lo1, hi0 ^ c.w ^ k1, lo0);
+        // one 32x32 -> 64-bit product per multiplier gives both halves
+        const uint64_t m0 = (uint64_t)0xD2511F53u * c.x, m1 = (uint64_t)0xCD9E8D57u * c.z;
+        c = make_uint4((uint32_t)(m1 >> 32) ^ c.y ^ k0, (uint32_t)m1, (uint32_t)(m0 >> 32) ^ c.w ^ k1, (uint32_t)m0);
         k0 += 0x9E3779B9u;
         k1 += 0xBB67AE85u;
     }

@@ -225,7 +225,7 @@ __device__ __forceinline__ LDecide<R> lepton_decide(const StepDev &S, const Tabl
     const int n = T.n_chi[0];
     const R lnchi = log_r((R)d.chi);
     const R x0 = (R)T.lnchi0[0], h = (R)T.dlnchi[0];
-    const R Ce = (R)(S.Kc / gam);
+    const R Ce = ratio_r<R>(S.Kc, gam);
     d.Wdn = Ce * exp_r(rate_lookup(lds, lnchi, x0, h, n));
     d.Wup = Ce * exp_r(rate_lookup(lds + n, lnchi, x0, h, n));
     const R sb = dot(s, d.bs.b);
@@ -295,7 +295,7 @@ __global__ void __launch_bounds__(kBlock) k_lepton_main(LepDev<R> L, FieldDev F,
                             const R n2 = dot(s, s);
                             if (n2 > (R)1) {
                                 s = rsqrt_r(n2) * s;
-                                c_norm += n2 > (R)1 + (R)1e-12;
+                                c_norm += n2 > (R)1 + norm_count_tol<R>();
                             }
                         }
                     } else {
@@ -428,7 +428,7 @@ __device__ __forceinline__ PDecide<R> photon_decide(const StepDev &S, const Tabl
     const int n = T.n_chi[1];
     const R lnchi = log_r((R)d.chi);
     const R x0 = (R)T.lnchi0[1], h = (R)T.dlnchi[1];
-    const R Cg = (R)(S.Kc / k0);
+    const R Cg = ratio_r<R>(S.Kc, k0);
     d.Wm = Cg * exp_r(rate_lookup(lds, lnchi, x0, h, n));
     d.Wp = Cg * exp_r(rate_lookup(lds + n, lnchi, x0, h, n));
     P_to_stokes(P, d.bs, d.x1, d.x2, d.x3);
@@ -440,6 +440,21 @@ __device__ __forceinline__ PDecide<R> photon_decide(const StepDev &S, const Tabl
     return d;
 }
 
+// Photons whose FP32 bound eps_r k0 (|E| + |B|) >= |F_perp| eps_r = chi cannot reach chi_min skip
+// the QED part.  The bound carries a relative margin far above FP32 rounding, so every photon
+// with chi >= chi_min (FP64) is a candidate.
+template <class R> __device__ __forceinline__ bool photon_candidate(const StepDev &S, R k0, V3<R> E, V3<R> B)
+{
+    const R bound = (R)S.eps_r * k0 * (sqrt_r(dot(E, E)) + sqrt_r(dot(B, B)));
+    return bound * (R)1.001 >= (R)S.chi_g_min;
+}
+
+// Photon streaming pass.  The block walks its contiguous range in tiles of kPhoTile slots.
+// Phase 1 (every slot): advance x, retire, evaluate the fields, queue the candidates in LDS.
+// Phase 2 (queued slots only, all lanes busy): chi in FP64, rates, draw, no-pair update, and
+// the transition bits, OR-ed into the tile's mask words in LDS and stored once per tile.
+constexpr int kPhoTile = 1024;
+
 template <class R>
 __global__ void __launch_bounds__(kBlock) k_photon_main(PhoDev<R> G, FieldDev F, StepDev S0, TablesDev T, uint64_t *mask,
                                                         int64_t nchunks, uint32_t *bctr, uint32_t *bcnt)
@@ -447,73 +462,113 @@ __global__ void __launch_bounds__(kBlock) k_photon_main(PhoDev<R> G, FieldDev F,
     const StepDev S = localize(S0);
     extern __shared__ unsigned char smem_raw[];
     R *lds = reinterpret_cast<R *>(smem_raw);
+    __shared__ uint32_t q_idx[kPhoTile];
+    __shared__ R q_x[kPhoTile];
+    __shared__ unsigned long long q_bits[2][kPhoTile / 64];
+    __shared__ uint32_t q_n;
     stage_rates<R>(T, 1, lds);
     const int64_t n = *G.count_prev;
     const int64_t B = block_len(n, gridDim.x);
     const int64_t start = (int64_t)blockIdx.x * B, end = start + B < n ? start + B : n;
     const int lane = threadIdx.x & 63;
+    const bool qed = (S.flags & F_PAIR) != 0;
     unsigned c_chi = 0, c_norm = 0, c_ret = 0, c_prob = 0, c_step = 0, c_qed = 0, ntrans = 0;
-    for (int64_t base = start + (threadIdx.x & ~63); base < end; base += blockDim.x) {
-        const int64_t i = base + lane;
-        bool pair = false, plus = false;
-        if (i < end) {
-            const uint64_t id = G.id[i];
-            if (id != 0) {
-                ++c_step;
-                const V3<R> k = ld3(G.k, i);
-                const R k0r = sqrt_r(dot(k, k));
-                const double k0 = (double)k0r;
-                V3<R> x = ldx(G.x, i);
-                x = x + ((R)S.dt / k0r) * k;
-                stx(G.x, i, x);
-                // retirement: too soft to ever reach chi_min, or behind the trailing edge of the
-                // plane-wave pulse (the phase t + x of a photon never decreases)
-                const bool behind = F.kind == 1 && F.phase_len > 0.0 && S.t + S.dt + (double)x.x > F.phase_len;
-                if (k0 < S.k_retire || behind) {
-                    G.id[i] = 0;
-                    ++c_ret;
-                } else if (S.flags & F_PAIR) {
-                    V3<R> E, B;
-                    eval_fields<R>(F, (double)x.x, S.t + S.dt, E, B);
-                    V3<R> P = ld3(G.P, i);
-                    const PDecide<R> d = photon_decide<R>(S, T, lds, id, k, k0, P, E, B);
-                    if (d.active) {
-                        ++c_qed;
-                        c_chi += d.clamped_chi;
-                        if (d.P <= (R)1 && !(d.r1 < d.P)) {
-                            if (S.flags & F_NOPAIR) {
-                                const R dt = (R)S.dt;
-                                const R Wbar = (R)0.5 * (d.Wp + d.Wm), dW = (R)0.5 * (d.Wp - d.Wm);
-                                const R inv = (R)1 / ((R)1 - d.P);
-                                const R f = ((R)1 - Wbar * dt) * inv;
-                                V3<R> xn = {d.x1 * f, d.x2 * f, (d.x3 * ((R)1 - Wbar * dt) - dW * dt) * inv};
-                                const R n2 = dot(xn, xn);
-                                if (n2 > (R)1) {
-                                    xn = rsqrt_r(n2) * xn;
-                                    c_norm += n2 > (R)1 + (R)1e-12;
-                                }
-                                st3(G.P, i, stokes_to_P(xn.x, xn.y, xn.z, d.bs));
-                            }
-                        } else {
-                            pair = true;
-                            c_prob += d.P > (R)1;
-                            const R thr = d.P <= (R)1 ? d.a : d.a / d.P;
-                            plus = !(d.r1 < thr);
-                        }
+    for (int64_t tile = start; tile < end; tile += kPhoTile) {
+        const int64_t tend = tile + kPhoTile < end ? tile + kPhoTile : end;
+        if (threadIdx.x < kPhoTile / 64) { q_bits[0][threadIdx.x] = 0ull; q_bits[1][threadIdx.x] = 0ull; }
+        if (threadIdx.x == 0) q_n = 0;
+        __syncthreads();
+        // phase 1
+        for (int64_t base = tile + (threadIdx.x & ~63); base < tend; base += blockDim.x) {
+            const int64_t i = base + lane;
+            bool cand = false;
+            R xq = (R)0;
+            if (i < tend) {
+                const uint64_t id = G.id[i];
+                if (id != 0) {
+                    ++c_step;
+                    const V3<R> k = ld3(G.k, i);
+                    const R k0r = sqrt_r(dot(k, k));
+                    V3<R> x = ldx(G.x, i);
+                    x = x + ((R)S.dt / k0r) * k;
+                    stx(G.x, i, x);
+                    // retirement: too soft to ever reach chi_min, or behind the trailing edge of the
+                    // plane-wave pulse (the phase t + x of a photon never decreases)
+                    const bool behind = F.kind == 1 && F.phase_len > 0.0 && S.t + S.dt + (double)x.x > F.phase_len;
+                    if ((double)k0r < S.k_retire || behind) {
+                        G.id[i] = 0;
+                        ++c_ret;
+                    } else if (qed) {
+                        V3<R> E, Bf;
+                        eval_fields<R>(F, (double)x.x, S.t + S.dt, E, Bf);
+                        cand = photon_candidate<R>(S, k0r, E, Bf);
+                        xq = x.x;
                     }
                 }
             }
+            const uint64_t m = __ballot(cand);
+            uint32_t wbase = 0;
+            if (lane == 0 && m) wbase = atomicAdd(&q_n, (uint32_t)__popcll(m));
+            wbase = __shfl(wbase, 0);
+            if (cand) {
+                const uint32_t r = wbase + (uint32_t)__popcll(m & ((1ull << lane) - 1ull));
+                q_idx[r] = (uint32_t)(i - tile);
+                q_x[r] = xq;
+            }
         }
-        const uint64_t m = __ballot(pair), mp = __ballot(plus);
-        if (lane == 0) {
-            mask[base >> 6] = m;
-            mask[nchunks + (base >> 6)] = mp;
+        __syncthreads();
+        // phase 2
+        const uint32_t nq = q_n;
+        for (uint32_t j = threadIdx.x; j < nq; j += blockDim.x) {
+            const uint32_t o = q_idx[j];
+            const int64_t i = tile + o;
+            const uint64_t id = G.id[i];
+            const V3<R> k = ld3(G.k, i);
+            const double k0 = (double)sqrt_r(dot(k, k));
+            V3<R> E, Bf;
+            eval_fields<R>(F, (double)q_x[j], S.t + S.dt, E, Bf);
+            const V3<R> P = ld3(G.P, i);
+            const PDecide<R> d = photon_decide<R>(S, T, lds, id, k, k0, P, E, Bf);
+            if (!d.active) continue;
+            ++c_qed;
+            c_chi += d.clamped_chi;
+            if (d.P <= (R)1 && !(d.r1 < d.P)) {
+                if (S.flags & F_NOPAIR) {
+                    const R dt = (R)S.dt;
+                    const R Wbar = (R)0.5 * (d.Wp + d.Wm), dW = (R)0.5 * (d.Wp - d.Wm);
+                    const R inv = (R)1 / ((R)1 - d.P);
+                    const R f = ((R)1 - Wbar * dt) * inv;
+                    V3<R> xn = {d.x1 * f, d.x2 * f, (d.x3 * ((R)1 - Wbar * dt) - dW * dt) * inv};
+                    const R n2 = dot(xn, xn);
+                    if (n2 > (R)1) {
+                        xn = rsqrt_r(n2) * xn;
+                        c_norm += n2 > (R)1 + norm_count_tol<R>();
+                    }
+                    st3(G.P, i, stokes_to_P(xn.x, xn.y, xn.z, d.bs));
+                }
+            } else {
+                c_prob += d.P > (R)1;
+                const R thr = d.P <= (R)1 ? d.a : d.a / d.P;
+                const unsigned long long bit = 1ull << (o & 63);
+                atomicOr(&q_bits[0][o >> 6], bit);
+                if (!(d.r1 < thr)) atomicOr(&q_bits[1][o >> 6], bit);
+            }
+        }
+        __syncthreads();
+        const int nw = (int)cdiv(tend - tile, 64);
+        if (threadIdx.x < nw) {
+            const uint64_t m = q_bits[0][threadIdx.x];
+            mask[(tile >> 6) + threadIdx.x] = m;
+            mask[nchunks + (tile >> 6) + threadIdx.x] = q_bits[1][threadIdx.x];
             ntrans += __popcll(m);
         }
+        __syncthreads();
     }
     unsigned v[kNCtr] = {};
     v[C_PROB] = c_prob; v[C_CHI] = c_chi; v[C_NORM] = c_norm; v[C_RETIRED] = c_ret; v[C_GSTEP] = c_step;
     v[C_GQED] = c_qed;
+    // block_counts takes lane 0's transition count per wave: reduce the tile-word counts first
+    for (int o = 32; o > 0; o >>= 1) ntrans += __shfl_xor(ntrans, o);
     block_counts(bctr, bcnt, v, ntrans);
 }
 

@@ -119,21 +119,29 @@ def _photon_inputs(n, seed, chi_target=2.0):
     return x, k, P, ids
 
 
-def test_photon_step_fp64(q, gtab64, otables):
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_photon_step(q, gtab64, gtab32, otables, prec):
+    """One NBW step of 1500 photons of random direction in a uniform B (about a third below
+    chi_min): decays, surviving polarization, positions and the pair products."""
+    import torch
+    fp32 = prec == "fp32"
+    tab = gtab32 if fp32 else gtab64
+    tol = 1e-5 if fp32 else 1e-12
     n = 1500
     x, k, P, ids = _photon_inputs(n, 31)
+    if fp32:
+        x, k, P = (a.astype(np.float32).astype(np.float64) for a in (x, k, P))
     B0 = (0.0, 0.0, 2.0 / (EPS * 1e4))             # chi_gamma ~ 2 |k_perp| / 1e4
     w = synth.Workload("photons_uniform_B", 0, 1, 20.0, 4, synth.FIELD_UNIFORM, B0=B0, track=(True, True, True))
     flags = q.QED_ALL
-    sim = _sim(q, gtab64, w, 2 * n, 2 * n, n, flags, k_retire=0.0)
-    import torch
+    sim = _sim(q, tab, w, 2 * n, 2 * n, n, flags, k_retire=0.0)
     for i in range(3):
         sim.g.x[i][:n] = torch.as_tensor(x[i]); sim.g.k[i][:n] = torch.as_tensor(k[i])
         sim.g.P[i][:n] = torch.as_tensor(P[i])
     sim.g.id[:n] = torch.as_tensor(ids.view(np.int64))
     sim.g.count.fill_(n); sim.g.count_prev.fill_(n)
     sp = sim.step_params(0)
-    q.qed_pair(gtab64, sim.g, sim.fields, sp, sim.e, sim.p, sim.ctr, sim.ws)
+    q.qed_pair(tab, sim.g, sim.fields, sp, sim.e, sim.p, sim.ctr, sim.ws)
     # oracle
     G = oracle.PhotonSet(n, track=w.track)
     for i in range(3):
@@ -141,19 +149,20 @@ def test_photon_step_fp64(q, gtab64, otables):
     G.id[:n] = ids; G.n = G.n_prev = n
     Le, Lp = oracle.LeptonSet(0, 2 * n), oracle.LeptonSet(1, 2 * n)
     ctr = oracle.Counters()
-    prm = oracle.make_params(w.dt, EPS, step=0, seed=w.seed, flags=flags, near_tol=1e-10)
+    prm = oracle.make_params(w.dt, EPS, step=0, seed=w.seed, flags=flags, near_tol=1e-5 if fp32 else 1e-10, u24=fp32)
     oracle.photon_step(otables, prm, oracle.make_fields(w.field_kind, B0=B0), G, Le, Lp, ctr)
-    print("pairs", ctr.n_pair, "near", int(G.near[:n].sum()), q.counters_dict(sim.ctr))
-    assert ctr.n_pair > 100 and int(G.near[:n].sum()) == 0
+    near = G.near[:n].astype(bool)
+    print(prec, "pairs", ctr.n_pair, "near", int(near.sum()), q.counters_dict(sim.ctr))
+    assert ctr.n_pair > 100 and int(near.sum()) == 0      # this seed has no decision within the tolerance
     assert sim.g.count_prev.item() == sim.g.count.item() == n
     xg, kg, Pg, idg = sim.g.arrays()
     np.testing.assert_array_equal(idg, G.id[:n])                      # same decays (dead slots)
     live = idg != 0
     from parity import director_err
-    assert director_err(Pg[:, live], np.stack(G.P)[:, :n][:, live], kg[:, live]).max() < 1e-12
-    assert np.abs(xg - np.stack(G.x)[:, :n]).max() < 1e-12 * 40
-    compare_leptons(sim.e.arrays(), Le.arrays(), np.zeros(Le.n, bool), 1e-12, 1e-12, rtol_x=1e-12, what="electrons")
-    compare_leptons(sim.p.arrays(), Lp.arrays(), np.zeros(Lp.n, bool), 1e-12, 1e-12, rtol_x=1e-12, what="positrons")
+    assert director_err(Pg[:, live], np.stack(G.P)[:, :n][:, live], kg[:, live]).max() < tol
+    assert np.abs(xg - np.stack(G.x)[:, :n]).max() < tol * 40
+    compare_leptons(sim.e.arrays(), Le.arrays(), np.zeros(Le.n, bool), tol, tol, rtol_x=tol, what="electrons")
+    compare_leptons(sim.p.arrays(), Lp.arrays(), np.zeros(Lp.n, bool), tol, tol, rtol_x=tol, what="positrons")
     assert q.counters_dict(sim.ctr)["n_pair"] == ctr.n_pair
 
 
