@@ -219,6 +219,54 @@ qed_status qed_clock_advance(int64_t *d_clock, qed_stream stream);
 qed_status qed_profile_start(void);
 qed_status qed_profile_stop(qed_kernel_time *out, int max_entries, int *n_entries);
 
+/* ---------------------------------------------------------------------------------------
+   Whole steps of one or many independent instances (collisions) in two launches.
+
+   One step of an instance is the paper's per-step sequence (NLC section flow chart for the
+   leptons, NBW section for the photons): qed_emit for the electrons, qed_emit for the
+   positrons, qed_pair for the photons stored before the step, then the step clock advances.
+   qed_plan_step produces the same particles, bit for bit, for every instance at once: one
+   streaming launch over all particle sets (each set owns a contiguous range of blocks) and one
+   launch that processes the emitters and the decaying photons.  Appends keep the per-species
+   order (photons of electrons, then of positrons, in emitter order; pairs in photon order). */
+typedef struct {
+    qed_leptons     electrons;   /* species 0 */
+    qed_leptons     positrons;   /* species 1; stepped (and filled by pairs) only with QED_PAIR */
+    qed_photons     photons;     /* filled with QED_EMIT; stepped with QED_PAIR */
+    qed_fields      fields;
+    qed_step_params params;      /* step and t at clock 0; d_clock is required: each
+                                    qed_plan_step uses step + *d_clock, t + *d_clock dt and
+                                    then adds 1 to *d_clock */
+    qed_counters   *d_counters;  /* device, accumulated per instance */
+} qed_instance;
+
+typedef struct {
+    int particles_per_block;     /* blocks of a set = ceil(capacity / this), default 256 */
+    int max_blocks_per_set;      /* cap on the blocks of one set, default 2048 */
+} qed_plan_config;
+
+typedef struct qed_plan_s *qed_plan;   /* opaque, library-owned */
+
+/* Copy the instance descriptions (pointers, capacities, fields, parameters) to the device and
+   allocate the plan's scratch: two mask planes of one bit per particle slot, per-block counts
+   and per-set bookkeeping.  Allocates device memory and synchronizes the device; afterwards the
+   arrays and counters named here must stay allocated and keep their addresses.  config may be
+   NULL.  QED_ERR_INVALID for a NULL pointer, an inconsistent set (species, missing arrays,
+   dt or eps_r <= 0, no d_clock or d_counters) or more than 2^24 blocks. */
+qed_status qed_plan_create(qed_tables tables, int n_instances, const qed_instance *instances,
+                           const qed_plan_config *config, qed_plan *out);
+
+/* One step of every instance, enqueued on the stream without host synchronization; no
+   allocation, no memset, so it can be captured in a HIP graph and replayed.  Steps of one plan
+   must not overlap (they share its scratch). */
+qed_status qed_plan_step(qed_plan plan, qed_stream stream);
+
+/* Blocks in the plan's grid (0 for NULL). */
+int64_t qed_plan_blocks(qed_plan plan);
+
+/* Synchronize the device and release the plan.  Safe on NULL. */
+qed_status qed_plan_destroy(qed_plan plan);
+
 #ifdef __cplusplus
 }
 #endif

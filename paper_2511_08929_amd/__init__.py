@@ -32,7 +32,8 @@ QED_FIELD_UNIFORM, QED_FIELD_PLANE_LP = 0, 1
 
 ABI_SYMBOLS = ("qed_init_tables", "qed_last_error", "qed_free_tables", "qed_tables_download", "qed_workspace_size",
                "qed_push_spin", "qed_emit", "qed_pair", "qed_compact_workspace_size", "qed_compact",
-               "qed_profile_start", "qed_profile_stop", "qed_clock_advance")
+               "qed_profile_start", "qed_profile_stop", "qed_clock_advance", "qed_plan_create", "qed_plan_step",
+               "qed_plan_blocks", "qed_plan_destroy")
 
 
 class QedError(RuntimeError):
@@ -75,6 +76,15 @@ COUNTER_NAMES = ("n_emit", "n_pair", "n_prob_clamped", "n_chi_clamped", "n_norm_
                  "n_capacity_overflow", "n_retired", "n_lepton_steps", "n_photon_steps", "n_photon_qed")
 
 
+class Instance(C.Structure):
+    _fields_ = [("electrons", Leptons), ("positrons", Leptons), ("photons", Photons), ("fields", Fields),
+                ("params", StepParams), ("d_counters", C.c_void_p)]
+
+
+class PlanConfig(C.Structure):
+    _fields_ = [("particles_per_block", C.c_int), ("max_blocks_per_set", C.c_int)]
+
+
 class KernelTime(C.Structure):
     _fields_ = [("name", C.c_char_p), ("calls", C.c_longlong), ("total_ms", C.c_double)]
 
@@ -105,10 +115,14 @@ def lib():
         L.qed_compact_workspace_size.argtypes = [P(Photons), C.c_int]; L.qed_compact_workspace_size.restype = sz
         L.qed_compact.argtypes = [P(Photons), C.c_int, vp, sz, vp]
         L.qed_clock_advance.argtypes = [vp, vp]
+        L.qed_plan_create.argtypes = [vp, C.c_int, P(Instance), P(PlanConfig), P(vp)]
+        L.qed_plan_step.argtypes = [vp, vp]
+        L.qed_plan_blocks.argtypes = [vp]; L.qed_plan_blocks.restype = i64
+        L.qed_plan_destroy.argtypes = [vp]
         L.qed_profile_start.argtypes = []
         L.qed_profile_stop.argtypes = [P(KernelTime), C.c_int, P(C.c_int)]
         for name in ABI_SYMBOLS:
-            if name not in ("qed_workspace_size", "qed_compact_workspace_size", "qed_last_error"):
+            if name not in ("qed_workspace_size", "qed_compact_workspace_size", "qed_last_error", "qed_plan_blocks"):
                 getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -343,3 +357,42 @@ def qed_profile_stop():
 
 def qed_clock_advance(clock, stream=None):
     _check(lib().qed_clock_advance(_ptr(clock), _stream_ptr(stream)), "qed_clock_advance")
+
+
+class Plan:
+    """qed_plan over instances given as (electrons, positrons, photons, fields, step params, counters).
+    The buffers must stay alive (and unmoved) for the plan's lifetime; step params need d_clock."""
+
+    def __init__(self, tables: Tables, instances, particles_per_block=0, max_blocks_per_set=0):
+        n = len(instances)
+        arr = (Instance * n)()
+        self._keep = []
+        for j, (e, p, g, fields, step, ctr) in enumerate(instances):
+            if not step.d_clock:
+                raise QedError("a plan needs step params with d_clock")
+            arr[j].electrons = e.view()
+            arr[j].positrons = p.view()
+            arr[j].photons = g.view()
+            arr[j].fields = fields
+            arr[j].params = step
+            arr[j].d_counters = ctr.data_ptr()
+            self._keep.append((e, p, g, ctr))
+        cfg = PlanConfig(particles_per_block, max_blocks_per_set)
+        h = C.c_void_p()
+        _check(lib().qed_plan_create(tables.handle, n, arr, C.byref(cfg), C.byref(h)), "qed_plan_create")
+        self.handle = h
+        self.blocks = int(lib().qed_plan_blocks(h))
+
+    def step(self, stream=None):
+        _check(lib().qed_plan_step(self.handle, _stream_ptr(stream)), "qed_plan_step")
+
+    def close(self):
+        if self.handle:
+            lib().qed_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

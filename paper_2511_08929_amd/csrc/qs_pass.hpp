@@ -1,0 +1,677 @@
+// qs_pass.hpp -- device views of the particle sets, the decision parts of the two channels and
+// the per-particle bodies of the streaming and processing passes, shared by the per-species
+// entry points (qs_step.hip) and the merged multi-instance step (qs_plan.hip).
+#pragma once
+#include <math.h>
+#include <stdint.h>
+#include <string.h>
+
+#include "qs_internal.hpp"
+
+namespace qs {
+
+constexpr int kBlock = 256;
+constexpr int kMaxGrid = 2048;                               // 256 CUs x 8 resident blocks
+
+template <class R> struct LepDev {
+    int64_t cap;
+    int64_t *count;
+    int species;
+    R *x[3], *p[3], *s[3];
+};
+
+template <class R> struct PhoDev {
+    int64_t cap;
+    int64_t *count, *count_prev;
+    R *x[3], *k[3], *P[3];
+    uint64_t *id;
+};
+
+struct StepDev {
+    double t, dt, a_e, eps_r, chi_e_min, chi_e_max, chi_g_min, chi_g_max, k_retire;
+    double Kc;                 // alpha / (sqrt3 pi eps_r): rate prefactor times gamma (or |k|)
+    int64_t step;
+    uint64_t seed;
+    uint32_t flags;
+    const int64_t *clock;      // optional device step offset (replayable launches)
+};
+
+// step index and time of this launch: params.step + *clock and params.t + *clock dt
+__device__ __forceinline__ StepDev localize(StepDev S)
+{
+    if (S.clock) {
+        const int64_t off = *S.clock;
+        S.step += off;
+        S.t += (double)off * S.dt;
+    }
+    return S;
+}
+
+enum { C_EMIT = 0, C_PAIR, C_PROB, C_CHI, C_NORM, C_OVER, C_RETIRED, C_LSTEP, C_GSTEP, C_GQED, kNCtr };
+
+struct WS {
+    uint64_t *mask;      // [2][nchunks]: transition, branch (up / plus)
+    uint32_t *bcnt;      // [kMaxGrid]: transitions per block of the streaming pass
+    int64_t *book;       // [8]: base0, total, base1, n_fit, n processed, block range
+    uint32_t *bctr;      // [kMaxGrid][kNCtr]: per-block counts of the streaming pass
+    uint32_t *idx;       // [max particles]
+};
+
+__host__ __device__ inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
+inline size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+inline WS carve(void *ws, int64_t cap, int64_t *nchunks_out)
+{
+    const int64_t nch = cdiv(cap > 0 ? cap : 1, 64);
+    char *b = (char *)ws;
+    WS w;
+    w.mask = (uint64_t *)b; b += align256(sizeof(uint64_t) * 2 * nch);
+    w.bcnt = (uint32_t *)b; b += align256(sizeof(uint32_t) * kMaxGrid);
+    w.book = (int64_t *)b;  b += align256(sizeof(int64_t) * 8);
+    w.bctr = (uint32_t *)b; b += align256(sizeof(uint32_t) * kMaxGrid * kNCtr);
+    w.idx = (uint32_t *)b;
+    *nchunks_out = nch;
+    return w;
+}
+
+// ------------------------------------------------------------------ device helpers
+template <class R> __device__ __forceinline__ const R *rate_src(const TablesDev &T);
+template <> __device__ __forceinline__ const double *rate_src<double>(const TablesDev &T) { return T.lnrate; }
+template <> __device__ __forceinline__ const float *rate_src<float>(const TablesDev &T) { return T.lnrate32; }
+
+template <class R> __device__ __forceinline__ const void *bn_of(const TablesDev &T)
+{
+    return sizeof(R) == 8 ? (const void *)T.bn64 : (const void *)T.bn32;
+}
+
+// stage the two rate rows of one process (NLC: channels 0,1; NBW: 2,3) into LDS
+template <class R> __device__ __forceinline__ int stage_rates(const TablesDev &T, int grp, R *lds)
+{
+    const int n = T.n_chi[grp];
+    const R *src = rate_src<R>(T) + T.off_rate[2 * grp];
+    for (int j = threadIdx.x; j < 2 * n; j += blockDim.x) lds[j] = src[j];
+    __syncthreads();
+    return n;
+}
+
+template <class R> __device__ __forceinline__ R rate_lookup(const R *row, R lnchi, R x0, R h, int n)
+{
+    R L[4];
+    const int i = lagrange4(lnchi, x0, h, n, L);
+    return L[0] * row[i] + L[1] * row[i + 1] + L[2] * row[i + 2] + L[3] * row[i + 3];
+}
+
+// inverse CDF (FP64 island): nu at (ln chi, rho) for channel ch
+__device__ __forceinline__ double icdf_nu(const TablesDev &T, int ch, double lnchi, double rho)
+{
+    const int grp = ch < 2 ? 0 : 1;
+    double Lc[4], Lr[4];
+    const int i0 = lagrange4(lnchi, T.lnchi0[grp], T.dlnchi[grp], T.n_chi[grp], Lc);
+    const int j0 = lagrange4(rho, T.rho0, T.drho, T.n_rho, Lr);
+    const double *base = T.nu + T.off_nu[ch] + (int64_t)i0 * T.n_rho + j0;
+    double acc = 0.0;
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+        const double *r = base + (int64_t)a * T.n_rho;
+        acc += Lc[a] * (Lr[0] * r[0] + Lr[1] * r[1] + Lr[2] * r[2] + Lr[3] * r[3]);
+    }
+    return acc;
+}
+
+template <class R> __device__ __forceinline__ V3<R> ld3(R *const a[3], int64_t i)
+{
+    return {a[0][i], a[1][i], a[2][i]};
+}
+template <class R> __device__ __forceinline__ void st3(R *const a[3], int64_t i, V3<R> v)
+{
+    a[0][i] = v.x;
+    a[1][i] = v.y;
+    a[2][i] = v.z;
+}
+template <class R> __device__ __forceinline__ V3<R> ldx(R *const a[3], int64_t i)
+{
+    return {a[0] ? a[0][i] : (R)0, a[1] ? a[1][i] : (R)0, a[2] ? a[2][i] : (R)0};
+}
+template <class R> __device__ __forceinline__ void stx(R *const a[3], int64_t i, V3<R> v)
+{
+    if (a[0]) a[0][i] = v.x;
+    if (a[1]) a[1][i] = v.y;
+    if (a[2]) a[2][i] = v.z;
+}
+
+// Contiguous partition of [0, n) over the grid of a streaming pass: block b owns
+// [b B, (b+1) B) with B a multiple of 64, so each 64-particle mask word belongs to one block and
+// the per-block transition counts are the scan input in particle order.
+__host__ __device__ __forceinline__ int64_t block_len(int64_t n, int64_t nblk)
+{
+    return ((cdiv(n, nblk > 0 ? nblk : 1) + 63) / 64) * 64;
+}
+
+// Block totals of the per-thread counts v[0..kNCtr) and of the transition count v[kNCtr]:
+// on return tot[c] holds the block's sum (shared, valid after the barrier inside).
+__device__ __forceinline__ void block_sum(unsigned (&v)[kNCtr + 1], unsigned (&tot)[kNCtr + 1])
+{
+    __shared__ unsigned red[kBlock / 64][kNCtr + 1];
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+    for (int c = 0; c <= kNCtr; ++c) {
+        unsigned t = v[c];
+        for (int o = 32; o > 0; o >>= 1) t += __shfl_xor(t, o);
+        if (lane == 0) red[wid][c] = t;
+    }
+    __syncthreads();
+    if (threadIdx.x <= kNCtr) {
+        unsigned t = 0;
+        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) t += red[w][threadIdx.x];
+        tot[threadIdx.x] = t;
+    }
+    __syncthreads();
+}
+
+__device__ __forceinline__ void wave_add(unsigned long long *ctr, int slot, unsigned v)
+{
+    // reduce over the wave, one atomic per wave
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    if ((threadIdx.x & 63) == 0 && v) atomicAdd(ctr + slot, (unsigned long long)v);
+}
+
+template <class R> __device__ __forceinline__ bool zero_field(V3<R> E, V3<R> B)
+{
+    return E.x == (R)0 && E.y == (R)0 && E.z == (R)0 && B.x == (R)0 && B.y == (R)0 && B.z == (R)0;
+}
+
+// ------------------------------------------------------------------ lepton QED: decision part
+// Everything up to and including the emit / no-emit decision (NLC section: chi_e, beta, the
+// spin-weighted rate W = W_up (1+s.beta)/2 + W_down (1-s.beta)/2, the draw r1 < W dt).
+template <class R> struct LDecide {
+    double chi;        // clamped for lookups
+    Basis<R> bs;
+    R Wdn, Wup, a, P, r1, r2;
+    bool active;       // chi >= chi_min
+    bool clamped_chi;
+};
+
+template <class R>
+__device__ __forceinline__ LDecide<R> lepton_decide(const StepDev &S, const TablesDev &T, const R *lds, int species,
+                                                    int64_t index, V3<R> p, V3<R> s, V3<R> E, V3<R> B)
+{
+    LDecide<R> d;
+    d.clamped_chi = false;
+    if (zero_field(E, B)) {           // outside the pulse: no QED, skip the FP64 island
+        d.active = false;
+        d.chi = 0.0;
+        return d;
+    }
+    const int q = species == 0 ? -1 : 1;
+    const double gam = sqrt(1.0 + dot(cvt<double>(p), cvt<double>(p)));
+    d.chi = basis_chi(q, S.eps_r, p, gam, E, B, d.bs);
+    d.active = d.chi >= S.chi_e_min;
+    d.clamped_chi = d.chi > S.chi_e_max;
+    if (d.clamped_chi) d.chi = S.chi_e_max;
+    if (!d.active) return d;
+    const int n = T.n_chi[0];
+    const R lnchi = log_r((R)d.chi);
+    const R x0 = (R)T.lnchi0[0], h = (R)T.dlnchi[0];
+    const R Ce = ratio_r<R>(S.Kc, gam);
+    d.Wdn = Ce * exp_r(rate_lookup(lds, lnchi, x0, h, n));
+    d.Wup = Ce * exp_r(rate_lookup(lds + n, lnchi, x0, h, n));
+    const R sb = dot(s, d.bs.b);
+    const R dt = (R)S.dt;
+    d.a = d.Wdn * (R)0.5 * ((R)1 - sb) * dt;
+    const R b = d.Wup * (R)0.5 * ((R)1 + sb) * dt;
+    d.P = d.a + b;
+    const uint4 w = philox_block(S.seed, lepton_id(species, index), S.step, 0u);
+    Unif<R>::two(w, d.r1, d.r2);
+    return d;
+}
+
+// ------------------------------------------------------------------ photons: decision part
+template <class R> struct PDecide {
+    double chi;
+    Basis<R> bs;
+    R Wm, Wp, a, P, r1, r2, x1, x2, x3;
+    bool active, clamped_chi;
+};
+
+template <class R>
+__device__ __forceinline__ PDecide<R> photon_decide(const StepDev &S, const TablesDev &T, const R *lds, uint64_t id,
+                                                    V3<R> k, double k0, V3<R> P, V3<R> E, V3<R> B)
+{
+    PDecide<R> d;
+    d.clamped_chi = false;
+    if (zero_field(E, B)) {
+        d.active = false;
+        d.chi = 0.0;
+        return d;
+    }
+    d.chi = basis_chi(0, S.eps_r, k, k0, E, B, d.bs);
+    d.active = d.chi >= S.chi_g_min;
+    d.clamped_chi = d.chi > S.chi_g_max;
+    if (d.clamped_chi) d.chi = S.chi_g_max;
+    if (!d.active) return d;
+    const int n = T.n_chi[1];
+    const R lnchi = log_r((R)d.chi);
+    const R x0 = (R)T.lnchi0[1], h = (R)T.dlnchi[1];
+    const R Cg = ratio_r<R>(S.Kc, k0);
+    d.Wm = Cg * exp_r(rate_lookup(lds, lnchi, x0, h, n));
+    d.Wp = Cg * exp_r(rate_lookup(lds + n, lnchi, x0, h, n));
+    P_to_stokes(P, d.bs, d.x1, d.x2, d.x3);
+    const R dt = (R)S.dt;
+    d.a = d.Wm * (R)0.5 * ((R)1 - d.x3) * dt;
+    const R b = d.Wp * (R)0.5 * ((R)1 + d.x3) * dt;
+    d.P = d.a + b;
+    Unif<R>::two(philox_block(S.seed, id, S.step, 2u), d.r1, d.r2);
+    return d;
+}
+
+// Photons whose FP32 bound eps_r k0 (|E| + |B|) >= |F_perp| eps_r = chi cannot reach chi_min skip
+// the QED part.  The bound carries a relative margin far above FP32 rounding, so every photon
+// with chi >= chi_min (FP64) is a candidate.
+template <class R> __device__ __forceinline__ bool photon_candidate(const StepDev &S, R k0, V3<R> E, V3<R> B)
+{
+    const R bound = (R)S.eps_r * k0 * (sqrt_r(dot(E, E)) + sqrt_r(dot(B, B)));
+    return bound * (R)1.001 >= (R)S.chi_g_min;
+}
+
+
+// ------------------------------------------------------------------ per-particle work
+// The bodies below are shared by the per-species entry points and the merged step.
+
+struct LCount { unsigned prob = 0, chi = 0, norm = 0, step = 0, trans = 0; };
+
+// Main pass, one lepton: Boris push and T-BMT rotation with the fields at t, the fields at
+// t + dt, chi and the decision (NLC section); a non-emitter gets the no-transition spin update
+// (non-transition section).  Stores x, p, s.
+template <class R>
+__device__ __forceinline__ void lepton_item(const LepDev<R> &L, const FieldDev &F, const StepDev &S, const TablesDev &T,
+                                            const R *lds, int64_t i, bool &emit, bool &up, LCount &c)
+{
+    const int q = L.species == 0 ? -1 : 1;
+    ++c.step;
+    V3<R> x = ldx(L.x, i), p = ld3(L.p, i), s = ld3(L.s, i);
+    V3<R> E, B;
+    if (S.flags & F_PUSH) {
+        eval_fields<R>(F, (double)x.x, S.t, E, B);
+        x = x + push<R>(q, (R)S.a_e, E, B, (R)S.dt, (S.flags & F_TBMT) != 0, p, s);
+    }
+    if (S.flags & F_EMIT) {
+        eval_fields<R>(F, (double)x.x, S.t + S.dt, E, B);
+        const LDecide<R> d = lepton_decide<R>(S, T, lds, L.species, i, p, s, E, B);
+        if (d.active) {
+            c.chi += d.clamped_chi;
+            if (d.P <= (R)1 && !(d.r1 < d.P)) {
+                if (S.flags & F_NOEMIT) {
+                    const R dt = (R)S.dt;
+                    const R Wbar = (R)0.5 * (d.Wup + d.Wdn), dW = (R)0.5 * (d.Wup - d.Wdn);
+                    const R inv = (R)1 / ((R)1 - d.P);
+                    s = inv * (((R)1 - Wbar * dt) * s - (dW * dt) * d.bs.b);
+                    const R n2 = dot(s, s);
+                    if (n2 > (R)1) {
+                        s = rsqrt_r(n2) * s;
+                        c.norm += n2 > (R)1 + norm_count_tol<R>();
+                    }
+                }
+            } else {
+                emit = true;
+                c.prob += d.P > (R)1;
+                const R thr = d.P <= (R)1 ? d.a : d.a / d.P;
+                up = !(d.r1 < thr);
+            }
+        }
+    }
+    stx(L.x, i, x);
+    st3(L.p, i, p);
+    st3(L.s, i, s);
+}
+
+// Main pass over the lepton range [start, end) (start a multiple of 64): the wave's decisions
+// and branch choices go to mask[w] and mask[nchunks + w] of its 64-particle word w.
+template <class R>
+__device__ __forceinline__ void lepton_range(const LepDev<R> &L, const FieldDev &F, const StepDev &S, const TablesDev &T,
+                                             const R *lds, int64_t start, int64_t end, uint64_t *mask, int64_t nchunks,
+                                             LCount &c)
+{
+    const int lane = threadIdx.x & 63;
+    for (int64_t base = start + (threadIdx.x & ~63); base < end; base += blockDim.x) {
+        const int64_t i = base + lane;
+        bool emit = false, up = false;
+        if (i < end) lepton_item<R>(L, F, S, T, lds, i, emit, up, c);
+        const uint64_t m = __ballot(emit), mu = __ballot(up);
+        if (lane == 0) {
+            mask[base >> 6] = m;
+            mask[nchunks + (base >> 6)] = mu;
+            c.trans += __popcll(m);
+        }
+    }
+}
+
+// Emitter processing (NLC section, after the decision): lambda from the selected inverse CDF,
+// recoil, spin collapse, Stokes collapse, P-vector; the photon goes to slot `slot` (< 0: no room).
+template <class R>
+__device__ __forceinline__ void emit_item(const LepDev<R> &L, const PhoDev<R> &G, const FieldDev &F, const StepDev &S,
+                                          const TablesDev &T, const R *lds, int64_t i, bool up, int64_t slot,
+                                          unsigned &c_ret)
+{
+    const V3<R> x = ldx(L.x, i);
+    V3<R> p = ld3(L.p, i), s = ld3(L.s, i);
+    V3<R> E, B;
+    eval_fields<R>(F, (double)x.x, S.t + S.dt, E, B);
+    const LDecide<R> d = lepton_decide<R>(S, T, lds, L.species, i, p, s, E, B);
+    const double r2 = (double)d.r2;
+    const double rho = log(r2) - log1p(-r2);
+    const double nu = icdf_nu(T, up ? 1 : 0, log(d.chi), rho);
+    const double lam_d = 1.0 / (1.0 + exp(-nu)), oml_d = 1.0 / (1.0 + exp(nu));
+    const double u_d = lam_d / oml_d;
+    const V3<R> k = (R)lam_d * p;
+    R r3, r4;
+    Unif<R>::two(philox_block(S.seed, lepton_id(L.species, i), S.step, 1u), r3, r4);
+    SpecPt<R> qp;
+    qp.lam = (R)lam_d; qp.oml = (R)oml_d; qp.u = (R)u_d;
+    bessel_ratios<R>(2.0 * u_d / (3.0 * d.chi), bn_of<R>(T), qp.K1, qp.I);
+    const V3<R> si = {dot(s, d.bs.e), dot(s, d.bs.b), dot(s, d.bs.k)};
+    const R w = nlc_w(qp, si.y);
+    const V3<R> g = nlc_g(qp, si);
+    V3<R> sf = si;
+    if (S.flags & F_SPIN) {
+        if (S.flags & F_MEAN) sf = ((R)1 / w) * g;
+        else {
+            const R gn = sqrt_r(dot(g, g));
+            const V3<R> Sq = gn > (R)0 ? ((R)1 / gn) * g : v3<R>(0, 1, 0);
+            const R thr3 = (w - gn) / ((R)2 * w);
+            sf = (r3 < thr3 ? (R)-1 : (R)1) * Sq;
+        }
+    }
+    V3<R> xi = {0, 0, 0};
+    if (S.flags & F_PHOTON_POL) {
+        if (S.flags & F_MEAN) xi = ((R)1 / w) * nlc_F(qp, si, v3<R>(0, 0, 0));
+        else {
+            const V3<R> Fv = nlc_F(qp, si, sf);
+            const R F0 = w + dot(sf, g);
+            const R Fn = sqrt_r(dot(Fv, Fv));
+            if (Fn > (R)0) {
+                const R thr4 = (F0 - Fn) / ((R)2 * F0);
+                xi = ((r4 < thr4 ? (R)-1 : (R)1) / Fn) * Fv;
+            }
+        }
+    }
+    const V3<R> Pv = stokes_to_P(xi.x, xi.y, xi.z, d.bs);
+    if (S.flags & F_RECOIL) p = (R)oml_d * p;
+    if (S.flags & F_SPIN) s = sf.x * d.bs.e + sf.y * d.bs.b + sf.z * d.bs.k;
+    st3(L.p, i, p);
+    st3(L.s, i, s);
+    if (slot >= 0) {
+        if (sqrt(dot(cvt<double>(k), cvt<double>(k))) < S.k_retire) {
+            G.id[slot] = 0;
+            ++c_ret;
+        } else {
+            G.id[slot] = photon_id(L.species, i, S.step);
+            stx(G.x, slot, x);
+            st3(G.k, slot, k);
+            st3(G.P, slot, Pv);
+        }
+    }
+}
+
+struct GCount { unsigned chi = 0, norm = 0, ret = 0, prob = 0, step = 0, qed = 0, trans = 0; };
+
+// Photon streaming pass, one tile of at most kPhoTile slots starting at `tile` (a multiple of 64).
+// Phase 1 (every slot): advance x, retire, evaluate the fields, queue the chi candidates in LDS.
+// Phase 2 (queued slots only, so the QED part runs on full waves): chi in FP64, rates, draw,
+// no-pair update, and the transition bits, OR-ed into the tile's mask words in LDS and stored
+// once: decisions at mask[w], branch (plus) at mask[nchunks + w].
+constexpr int kPhoTile = 1024;
+
+template <class R> struct PhoQueue {
+    uint32_t idx[kPhoTile];
+    R x[kPhoTile];
+    unsigned long long bits[2][kPhoTile / 64];
+    uint32_t n;
+};
+
+template <class R>
+__device__ __forceinline__ void photon_tile(const PhoDev<R> &G, const FieldDev &F, const StepDev &S, const TablesDev &T,
+                                            const R *lds, PhoQueue<R> &Q, int64_t tile, int64_t tend, uint64_t *mask,
+                                            int64_t nchunks, GCount &c)
+{
+    const int lane = threadIdx.x & 63;
+    const bool qed = (S.flags & F_PAIR) != 0;
+    if (threadIdx.x < kPhoTile / 64) { Q.bits[0][threadIdx.x] = 0ull; Q.bits[1][threadIdx.x] = 0ull; }
+    if (threadIdx.x == 0) Q.n = 0;
+    __syncthreads();
+    for (int64_t base = tile + (threadIdx.x & ~63); base < tend; base += blockDim.x) {
+        const int64_t i = base + lane;
+        bool cand = false;
+        R xq = (R)0;
+        if (i < tend) {
+            const uint64_t id = G.id[i];
+            if (id != 0) {
+                ++c.step;
+                const V3<R> k = ld3(G.k, i);
+                const R k0r = sqrt_r(dot(k, k));
+                V3<R> x = ldx(G.x, i);
+                x = x + ((R)S.dt / k0r) * k;
+                stx(G.x, i, x);
+                // retirement: too soft to ever reach chi_min, or behind the trailing edge of the
+                // plane-wave pulse (the phase t + x of a photon never decreases)
+                const bool behind = F.kind == 1 && F.phase_len > 0.0 && S.t + S.dt + (double)x.x > F.phase_len;
+                if ((double)k0r < S.k_retire || behind) {
+                    G.id[i] = 0;
+                    ++c.ret;
+                } else if (qed) {
+                    V3<R> E, Bf;
+                    eval_fields<R>(F, (double)x.x, S.t + S.dt, E, Bf);
+                    cand = photon_candidate<R>(S, k0r, E, Bf);
+                    xq = x.x;
+                }
+            }
+        }
+        const uint64_t m = __ballot(cand);
+        uint32_t wbase = 0;
+        if (lane == 0 && m) wbase = atomicAdd(&Q.n, (uint32_t)__popcll(m));
+        wbase = __shfl(wbase, 0);
+        if (cand) {
+            const uint32_t r = wbase + (uint32_t)__popcll(m & ((1ull << lane) - 1ull));
+            Q.idx[r] = (uint32_t)(i - tile);
+            Q.x[r] = xq;
+        }
+    }
+    __syncthreads();
+    const uint32_t nq = Q.n;
+    for (uint32_t j = threadIdx.x; j < nq; j += blockDim.x) {
+        const uint32_t o = Q.idx[j];
+        const int64_t i = tile + o;
+        const uint64_t id = G.id[i];
+        const V3<R> k = ld3(G.k, i);
+        const double k0 = (double)sqrt_r(dot(k, k));
+        V3<R> E, Bf;
+        eval_fields<R>(F, (double)Q.x[j], S.t + S.dt, E, Bf);
+        const V3<R> P = ld3(G.P, i);
+        const PDecide<R> d = photon_decide<R>(S, T, lds, id, k, k0, P, E, Bf);
+        if (!d.active) continue;
+        ++c.qed;
+        c.chi += d.clamped_chi;
+        if (d.P <= (R)1 && !(d.r1 < d.P)) {
+            if (S.flags & F_NOPAIR) {
+                const R dt = (R)S.dt;
+                const R Wbar = (R)0.5 * (d.Wp + d.Wm), dW = (R)0.5 * (d.Wp - d.Wm);
+                const R inv = (R)1 / ((R)1 - d.P);
+                const R f = ((R)1 - Wbar * dt) * inv;
+                V3<R> xn = {d.x1 * f, d.x2 * f, (d.x3 * ((R)1 - Wbar * dt) - dW * dt) * inv};
+                const R n2 = dot(xn, xn);
+                if (n2 > (R)1) {
+                    xn = rsqrt_r(n2) * xn;
+                    c.norm += n2 > (R)1 + norm_count_tol<R>();
+                }
+                st3(G.P, i, stokes_to_P(xn.x, xn.y, xn.z, d.bs));
+            }
+        } else {
+            c.prob += d.P > (R)1;
+            const R thr = d.P <= (R)1 ? d.a : d.a / d.P;
+            const unsigned long long bit = 1ull << (o & 63);
+            atomicOr(&Q.bits[0][o >> 6], bit);
+            if (!(d.r1 < thr)) atomicOr(&Q.bits[1][o >> 6], bit);
+        }
+    }
+    __syncthreads();
+    const int nw = (int)cdiv(tend - tile, 64);
+    if (threadIdx.x < nw) {
+        const uint64_t m = Q.bits[0][threadIdx.x];
+        mask[(tile >> 6) + threadIdx.x] = m;
+        mask[nchunks + (tile >> 6) + threadIdx.x] = Q.bits[1][threadIdx.x];
+        c.trans += __popcll(m);
+    }
+    __syncthreads();
+}
+
+// Pair processing (NBW section, after the decision): lambda~ from the selected inverse CDF,
+// momenta, correlated spins; the pair goes to slots se (electrons) and sp (positrons) when
+// se >= 0; the photon becomes a dead slot.
+template <class R>
+__device__ __forceinline__ void pair_item(const PhoDev<R> &G, const LepDev<R> &Le, const LepDev<R> &Lp, const FieldDev &F,
+                                          const StepDev &S, const TablesDev &T, const R *lds, int64_t i, bool plus,
+                                          int64_t se, int64_t sp)
+{
+    const uint64_t id = G.id[i];
+    const V3<R> k = ld3(G.k, i), x = ldx(G.x, i), P = ld3(G.P, i);
+    const double k0 = (double)sqrt_r(dot(k, k));
+    V3<R> E, B;
+    eval_fields<R>(F, (double)x.x, S.t + S.dt, E, B);
+    const PDecide<R> d = photon_decide<R>(S, T, lds, id, k, k0, P, E, B);
+    const double r2 = (double)d.r2;
+    const double nu = icdf_nu(T, plus ? 3 : 2, log(d.chi), log(r2) - log1p(-r2));
+    const double lam_d = 1.0 / (1.0 + exp(-nu)), oml_d = 1.0 / (1.0 + exp(nu));
+    const V3<R> pp = (R)lam_d * k, pe = (R)oml_d * k;
+    V3<R> ec = {0, 0, 0}, pc = {0, 0, 0};
+    if (S.flags & F_PAIR_SPIN) {
+        SpecPt<R> qp;
+        qp.lam = (R)lam_d; qp.oml = (R)oml_d; qp.u = (R)0;
+        bessel_ratios<R>(2.0 * (1.0 / lam_d + 1.0 / oml_d) / (3.0 * d.chi), bn_of<R>(T), qp.K1, qp.I);
+        const V3<R> xi = {d.x1, d.x2, d.x3};
+        V3<R> je, jp;
+        const R w0 = nbw_j(qp, xi, je, jp);
+        if (S.flags & F_MEAN) {
+            ec = ((R)1 / w0) * je;
+            pc = ((R)1 / w0) * jp;
+        } else {
+            R r3, r3b;
+            Unif<R>::two(philox_block(S.seed, id, S.step, 3u), r3, r3b);
+            const R jen = sqrt_r(dot(je, je)), jpn = sqrt_r(dot(jp, jp));
+            const V3<R> Se = jen > (R)0 ? ((R)1 / jen) * je : v3<R>(0, 1, 0);
+            const V3<R> Sp = jpn > (R)0 ? ((R)1 / jpn) * jp : v3<R>(0, 1, 0);
+            // outcomes (positron, electron): (down,down), (down,up), (up,down), (up,up)
+            const R inv4 = (R)1 / ((R)4 * w0);
+            R cum = 0;
+            int pick = 3;
+#pragma unroll
+            for (int o = 0; o < 3; ++o) {
+                const R spn = o < 2 ? (R)-1 : (R)1, sen = (o & 1) ? (R)1 : (R)-1;
+                V3<R> Gv;
+                const R G0 = nbw_G(qp, sen * Se, spn * Sp, Gv);
+                cum += (G0 + dot(xi, Gv)) * inv4;
+                if (pick == 3 && r3 < cum) pick = o;
+            }
+            const R spn = pick < 2 ? (R)-1 : (R)1, sen = (pick & 1) ? (R)1 : (R)-1;
+            ec = sen * Se;
+            pc = spn * Sp;
+        }
+    }
+    G.id[i] = 0;
+    if (se >= 0) {
+        const V3<R> se_lab = ec.x * d.bs.e + ec.y * d.bs.b + ec.z * d.bs.k;
+        const V3<R> sp_lab = pc.x * d.bs.e + pc.y * d.bs.b + pc.z * d.bs.k;
+        stx(Le.x, se, x);
+        st3(Le.p, se, pe);
+        st3(Le.s, se, se_lab);
+        stx(Lp.x, sp, x);
+        st3(Lp.p, sp, pp);
+        st3(Lp.s, sp, sp_lab);
+    }
+}
+
+// ------------------------------------------------------------------ host-side views
+template <class R> LepDev<R> lep_dev(const qed_leptons *L)
+{
+    LepDev<R> d;
+    d.cap = L->capacity;
+    d.count = L->d_count;
+    d.species = L->species;
+    for (int c = 0; c < 3; ++c) {
+        d.x[c] = (R *)L->x[c];
+        d.p[c] = (R *)L->p[c];
+        d.s[c] = (R *)L->s[c];
+    }
+    return d;
+}
+
+template <class R> PhoDev<R> pho_dev(const qed_photons *G)
+{
+    PhoDev<R> d;
+    if (!G) {                     // emission disabled: a view with no room, never written
+        memset(&d, 0, sizeof(d));
+        return d;
+    }
+    d.cap = G->capacity;
+    d.count = G->d_count;
+    d.count_prev = G->d_count_prev;
+    for (int c = 0; c < 3; ++c) {
+        d.x[c] = (R *)G->x[c];
+        d.k[c] = (R *)G->k[c];
+        d.P[c] = (R *)G->P[c];
+    }
+    d.id = G->id;
+    return d;
+}
+
+inline FieldDev field_dev(const qed_fields *f)
+{
+    FieldDev d;
+    d.kind = f->kind;
+    for (int c = 0; c < 3; ++c) {
+        d.E0[c] = f->E0[c];
+        d.B0[c] = f->B0[c];
+    }
+    d.a0 = f->a0;
+    d.phase_len = f->phase_len;
+    d.inv_phase_len = f->phase_len > 0.0 ? 1.0 / f->phase_len : 0.0;
+    return d;
+}
+
+inline StepDev step_dev(const qed_step_params *p)
+{
+    StepDev s;
+    s.t = p->t; s.dt = p->dt; s.a_e = p->a_e; s.eps_r = p->eps_r;
+    s.chi_e_min = p->chi_e_min; s.chi_e_max = p->chi_e_max; s.chi_g_min = p->chi_g_min; s.chi_g_max = p->chi_g_max;
+    s.k_retire = p->k_retire;
+    s.Kc = kAlpha / (sqrt(3.0) * kPi * p->eps_r);
+    s.step = p->step; s.seed = p->seed; s.flags = p->flags;
+    s.clock = p->d_clock;
+    return s;
+}
+
+inline int grid_for(int64_t n)
+{
+    const int64_t g = cdiv(n > 0 ? n : 1, kBlock);
+    return (int)(g < kMaxGrid ? g : kMaxGrid);
+}
+
+
+inline bool leptons_ok(const qed_leptons *L)
+{
+    if (!L || !L->d_count || L->capacity < 0 || L->capacity >= (int64_t)1 << 32) return false;
+    if (L->species != 0 && L->species != 1) return false;
+    for (int c = 0; c < 3; ++c)
+        if (!L->p[c] || !L->s[c]) return false;
+    return true;
+}
+
+inline bool photons_ok(const qed_photons *G)
+{
+    if (!G || !G->d_count || !G->d_count_prev || !G->id || G->capacity < 0 || G->capacity >= (int64_t)1 << 32) return false;
+    for (int c = 0; c < 3; ++c)
+        if (!G->k[c] || !G->P[c]) return false;
+    return true;
+}
+
+inline bool fields_ok(const qed_fields *f) { return f && (f->kind == QED_FIELD_UNIFORM || f->kind == QED_FIELD_PLANE_LP); }
+
+}  // namespace qs

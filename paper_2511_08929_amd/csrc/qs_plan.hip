@@ -1,0 +1,435 @@
+// qs_plan.hip -- one whole step (NLC for electrons and positrons, NBW for photons) of any number
+// of independent instances in two launches: qed_plan_create / qed_plan_step / qed_plan_destroy.
+//
+// A plan splits every particle set of every instance into a contiguous range of blocks of one
+// grid ("segments": electrons, positrons, photons of instance 0, then of instance 1, ...).
+//   main     block b streams its share of its segment (lepton push + decision + no-emission
+//            update, or the two-phase photon pass) and writes its transition count; the last
+//            block to finish (completion counter, no waiting) scans the counts of all blocks in
+//            grid order and does each instance's bookkeeping: append bases, capacity clamp,
+//            device counts, event counters, and the step clock;
+//   process  block b expands its own mask words into an ordered list in LDS and processes its
+//            transitions, writing photons (or pairs) at the instance's base + the rank.
+// The appends keep the order of the per-species calls: photons of electrons, then of
+// positrons, in emitter order; pairs in photon order.  So a plan step gives the same particles,
+// bit for bit, as qed_emit(electrons), qed_emit(positrons), qed_pair, qed_clock_advance.
+#include <vector>
+
+#include "qs_pass.hpp"
+
+namespace {
+using namespace qs;
+
+template <class R> struct InstDev {
+    LepDev<R> E, P;
+    PhoDev<R> G;
+    FieldDev F;
+    StepDev S;
+    unsigned long long *ctr;
+    int se, sp, sg;            // segment indices (-1: set not stepped)
+};
+
+struct SegDev {
+    int kind;                  // 0 electrons, 1 positrons, 2 photons
+    int inst;
+    int b0, nb;                // block range
+    int64_t mask_off, nchunks; // decision plane at mask + mask_off, branch plane nchunks words later
+};
+
+// written by the last block of the main pass, read by the process pass
+struct SegBook {
+    int64_t n_main;            // particles the main pass covered
+    int64_t base, base2;       // append base (photons; pairs: electrons, positrons)
+    int64_t total, nfit;       // transitions, of which stored
+};
+
+struct PlanDev {
+    const SegDev *seg;
+    int nseg, nblk, ninst;
+    uint64_t *mask;
+    uint32_t *bcnt;            // [nblk]
+    uint32_t *gpre;            // [nblk + 1] exclusive prefix of bcnt in grid order
+    SegBook *sbook;            // [nseg]
+    int64_t *clock_used;       // [ninst] step clock of the last main pass
+    unsigned *done;            // completion counter (0 between launches)
+};
+
+__device__ __forceinline__ int seg_of(const SegDev *seg, int nseg, int b)
+{
+    int lo = 0, hi = nseg - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (seg[mid].b0 <= b) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+__device__ __forceinline__ int64_t seg_total(const PlanDev &P, int sj)
+{
+    // read back what other threads of this block just stored, past the vector L1
+    if (sj < 0) return 0;
+    const uint32_t hi = __hip_atomic_load(P.gpre + P.seg[sj].b0 + P.seg[sj].nb, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const uint32_t lo = __hip_atomic_load(P.gpre + P.seg[sj].b0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return (int64_t)hi - (int64_t)lo;
+}
+
+// last block: scan of the block counts, then per-instance bookkeeping (one thread per instance)
+template <class R> __device__ void plan_book(const InstDev<R> *inst, const PlanDev &P)
+{
+    __shared__ uint32_t wsum[kBlock / 64];
+    __shared__ uint32_t carry;
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    if (threadIdx.x == 0) carry = 0;
+    __syncthreads();
+    for (int t0 = 0; t0 < P.nblk; t0 += kBlock) {
+        const int b = t0 + threadIdx.x;
+        const uint32_t v = b < P.nblk ? __hip_atomic_load(P.bcnt + b, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0u;
+        uint32_t incl = v;
+        for (int o = 1; o < 64; o <<= 1) {
+            const uint32_t y = __shfl_up(incl, o);
+            if (lane >= o) incl += y;
+        }
+        if (lane == 63) wsum[wid] = incl;
+        __syncthreads();
+        uint32_t off = carry;
+        for (int w = 0; w < wid; ++w) off += wsum[w];
+        if (b < P.nblk) P.gpre[b] = off + incl - v;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            uint32_t t = 0;
+            for (int w = 0; w < kBlock / 64; ++w) t += wsum[w];
+            carry += t;
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) P.gpre[P.nblk] = carry;
+    __threadfence();
+    __syncthreads();
+    for (int i = threadIdx.x; i < P.ninst; i += blockDim.x) {
+        const InstDev<R> &I = inst[i];
+        unsigned long long *ctr = I.ctr;
+        const int64_t te = seg_total(P, I.se), tp = seg_total(P, I.sp), tg = seg_total(P, I.sg);
+        const int64_t ne = *I.E.count;
+        const int64_t np = I.sp >= 0 ? *I.P.count : 0;
+        // emission: photons of electrons, then of positrons
+        int64_t over = 0;
+        if (I.G.count) {
+            const int64_t gb = *I.G.count;
+            const int64_t room = I.G.cap - gb > 0 ? I.G.cap - gb : 0;
+            const int64_t nfe = te < room ? te : room;
+            const int64_t nfp = tp < room - nfe ? tp : room - nfe;
+            *I.G.count = gb + nfe + nfp;
+            P.sbook[I.se] = SegBook{ne, gb, 0, te, nfe};
+            if (I.sp >= 0) P.sbook[I.sp] = SegBook{np, gb + nfe, 0, tp, nfp};
+            over += (te - nfe) + (tp - nfp);
+            if (te + tp) atomicAdd(ctr + C_EMIT, (unsigned long long)(te + tp));
+        } else {
+            P.sbook[I.se] = SegBook{ne, 0, 0, te, 0};
+        }
+        // pairs of the photons stepped in this pass, appended after the leptons stepped in it
+        if (I.sg >= 0) {
+            const int64_t ng = *I.G.count_prev;
+            int64_t room = I.E.cap - ne < I.P.cap - np ? I.E.cap - ne : I.P.cap - np;
+            room = room > 0 ? room : 0;
+            const int64_t nfg = tg < room ? tg : room;
+            *I.E.count = ne + nfg;
+            *I.P.count = np + nfg;
+            P.sbook[I.sg] = SegBook{ng, ne, np, tg, nfg};
+            over += tg - nfg;
+            if (tg) atomicAdd(ctr + C_PAIR, (unsigned long long)tg);
+            // photons born in this step wait for the next one
+            *I.G.count_prev = *I.G.count;
+        }
+        if (over) atomicAdd(ctr + C_OVER, (unsigned long long)over);
+        if (I.S.clock) {
+            int64_t *clk = const_cast<int64_t *>(I.S.clock);
+            P.clock_used[i] = *clk;
+            *clk += 1;
+        } else {
+            P.clock_used[i] = 0;
+        }
+    }
+    if (threadIdx.x == 0) *P.done = 0u;
+}
+
+template <class R>
+__global__ void __launch_bounds__(kBlock) k_plan_main(const InstDev<R> *inst, PlanDev P, TablesDev T)
+{
+    extern __shared__ unsigned char smem_raw[];
+    R *lds = reinterpret_cast<R *>(smem_raw);
+    __shared__ PhoQueue<R> Q;
+    __shared__ unsigned tot[kNCtr + 1];
+    __shared__ int last;
+    const int b = blockIdx.x;
+    const int sj = seg_of(P.seg, P.nseg, b);
+    const SegDev sg = P.seg[sj];
+    const InstDev<R> &I = inst[sg.inst];
+    const StepDev S = localize(I.S);
+    uint64_t *mask = P.mask + sg.mask_off;
+    unsigned v[kNCtr + 1] = {};
+    if (sg.kind < 2) {
+        const LepDev<R> &L = sg.kind == 0 ? I.E : I.P;
+        stage_rates<R>(T, 0, lds);
+        const int64_t n = *L.count;
+        const int64_t B = block_len(n, sg.nb);
+        const int64_t start = (int64_t)(b - sg.b0) * B, end = start + B < n ? start + B : n;
+        LCount c;
+        lepton_range<R>(L, I.F, S, T, lds, start, end, mask, sg.nchunks, c);
+        v[C_PROB] = c.prob; v[C_CHI] = c.chi; v[C_NORM] = c.norm; v[C_LSTEP] = c.step; v[kNCtr] = c.trans;
+    } else {
+        stage_rates<R>(T, 1, lds);
+        const int64_t n = *I.G.count_prev;
+        const int64_t B = block_len(n, sg.nb);
+        const int64_t start = (int64_t)(b - sg.b0) * B, end = start + B < n ? start + B : n;
+        GCount c;
+        for (int64_t tile = start; tile < end; tile += kPhoTile)
+            photon_tile<R>(I.G, I.F, S, T, lds, Q, tile, tile + kPhoTile < end ? tile + kPhoTile : end, mask, sg.nchunks, c);
+        v[C_PROB] = c.prob; v[C_CHI] = c.chi; v[C_NORM] = c.norm; v[C_RETIRED] = c.ret; v[C_GSTEP] = c.step;
+        v[C_GQED] = c.qed; v[kNCtr] = c.trans;
+    }
+    block_sum(v, tot);
+    if (threadIdx.x < kNCtr && tot[threadIdx.x]) atomicAdd(I.ctr + threadIdx.x, (unsigned long long)tot[threadIdx.x]);
+    if (threadIdx.x == kNCtr) P.bcnt[b] = tot[kNCtr];
+    // completion counter: the block that finishes last sees every other block's count
+    __threadfence();
+    __syncthreads();
+    if (threadIdx.x == 0) last = atomicAdd(P.done, 1u) == (unsigned)(gridDim.x - 1);
+    __syncthreads();
+    if (!last) return;
+    __threadfence();
+    plan_book<R>(inst, P);
+}
+
+constexpr int kExpandWords = 64;   // mask words expanded per round of the process pass (4096 slots)
+
+template <class R>
+__global__ void __launch_bounds__(kBlock) k_plan_process(const InstDev<R> *inst, PlanDev P, TablesDev T)
+{
+    extern __shared__ unsigned char smem_raw[];
+    R *lds = reinterpret_cast<R *>(smem_raw);
+    __shared__ uint16_t list[kExpandWords * 64];
+    __shared__ uint32_t nlist;
+    const int b = blockIdx.x;
+    if (P.gpre[b + 1] == P.gpre[b]) return;           // no transition in this block's range
+    const int sj = seg_of(P.seg, P.nseg, b);
+    const SegDev sg = P.seg[sj];
+    const InstDev<R> &I = inst[sg.inst];
+    StepDev S = I.S;
+    S.step += P.clock_used[sg.inst];
+    S.t += (double)P.clock_used[sg.inst] * S.dt;
+    const SegBook bk = P.sbook[sj];
+    stage_rates<R>(T, sg.kind < 2 ? 0 : 1, lds);
+    const uint64_t *mask = P.mask + sg.mask_off;
+    const int64_t n = bk.n_main;
+    const int64_t B = block_len(n, sg.nb);
+    const int64_t start = (int64_t)(b - sg.b0) * B, end = start + B < n ? start + B : n;
+    int64_t rank0 = (int64_t)P.gpre[b] - (int64_t)P.gpre[sg.b0];
+    const int lane = threadIdx.x & 63;
+    unsigned c_ret = 0;
+    for (int64_t c0 = start >> 6; c0 < cdiv(end, 64); c0 += kExpandWords) {
+        const int64_t c1 = c0 + kExpandWords < cdiv(end, 64) ? c0 + kExpandWords : cdiv(end, 64);
+        // wave 0: one mask word per lane, positions by an inclusive scan of the popcounts
+        if (threadIdx.x < 64) {
+            const int64_t c = c0 + lane;
+            const uint64_t m = c < c1 ? mask[c] : 0ull;
+            const uint32_t pc = __popcll(m);
+            uint32_t incl = pc;
+            for (int o = 1; o < 64; o <<= 1) {
+                const uint32_t y = __shfl_up(incl, o);
+                if (lane >= o) incl += y;
+            }
+            uint32_t pos = incl - pc;
+            uint64_t bits = m;
+            while (bits) {
+                const int bit = __ffsll((long long)bits) - 1;
+                list[pos++] = (uint16_t)(lane * 64 + bit);
+                bits &= bits - 1;
+            }
+            if (lane == 63) nlist = incl;
+        }
+        __syncthreads();
+        const uint32_t nl = nlist;
+        for (uint32_t j = threadIdx.x; j < nl; j += blockDim.x) {
+            const int64_t i = c0 * 64 + list[j];
+            const int64_t r = rank0 + j;
+            const bool br = (mask[sg.nchunks + (i >> 6)] >> (i & 63)) & 1ull;
+            if (sg.kind < 2) {
+                const LepDev<R> &L = sg.kind == 0 ? I.E : I.P;
+                emit_item<R>(L, I.G, I.F, S, T, lds, i, br, r < bk.nfit ? bk.base + r : -1, c_ret);
+            } else {
+                pair_item<R>(I.G, I.E, I.P, I.F, S, T, lds, i, br, r < bk.nfit ? bk.base + r : -1, bk.base2 + r);
+            }
+        }
+        rank0 += nl;
+        __syncthreads();
+    }
+    wave_add(I.ctr, C_RETIRED, c_ret);
+}
+
+}  // namespace
+
+struct qed_plan_s {
+    qed_tables T;
+    int ninst, nseg, nblk;
+    void *d_inst;
+    SegDev *d_seg;
+    uint64_t *d_mask;
+    uint32_t *d_bcnt, *d_gpre;
+    SegBook *d_sbook;
+    int64_t *d_clock_used;
+    unsigned *d_done;
+    size_t lds;
+};
+
+namespace {
+
+template <class R> InstDev<R> inst_dev(const qed_instance *in)
+{
+    InstDev<R> d;
+    memset(&d, 0, sizeof(d));
+    d.E = lep_dev<R>(&in->electrons);
+    d.P = lep_dev<R>(&in->positrons);
+    d.G = pho_dev<R>((in->params.flags & (QED_EMIT | QED_PAIR)) ? &in->photons : nullptr);
+    d.F = field_dev(&in->fields);
+    d.S = step_dev(&in->params);
+    d.ctr = (unsigned long long *)in->d_counters;
+    d.se = d.sp = d.sg = -1;
+    return d;
+}
+
+void plan_free(qed_plan p)
+{
+    if (!p) return;
+    (void)hipFree(p->d_inst);
+    (void)hipFree(p->d_seg);
+    (void)hipFree(p->d_mask);
+    (void)hipFree(p->d_bcnt);
+    (void)hipFree(p->d_gpre);
+    (void)hipFree(p->d_sbook);
+    (void)hipFree(p->d_clock_used);
+    (void)hipFree(p->d_done);
+    delete p;
+}
+
+template <class R>
+qed_status plan_create(qed_tables T, int n, const qed_instance *in, int ppb, int maxb, qed_plan *out)
+{
+    std::vector<InstDev<R>> inst(n);
+    std::vector<SegDev> seg;
+    int64_t nblk = 0, mask_words = 0;
+    auto add = [&](int kind, int i, int64_t cap) {
+        SegDev s;
+        s.kind = kind;
+        s.inst = i;
+        const int64_t want = cdiv(cap > 0 ? cap : 1, ppb);
+        s.nb = (int)(want < maxb ? want : maxb);
+        s.b0 = (int)nblk;
+        s.nchunks = cdiv(cap > 0 ? cap : 1, 64);
+        s.mask_off = mask_words;
+        nblk += s.nb;
+        mask_words += 2 * s.nchunks;
+        seg.push_back(s);
+        return (int)seg.size() - 1;
+    };
+    for (int i = 0; i < n; ++i) {
+        inst[i] = inst_dev<R>(&in[i]);
+        inst[i].se = add(0, i, in[i].electrons.capacity);
+        if (in[i].params.flags & QED_PAIR) {
+            inst[i].sp = add(1, i, in[i].positrons.capacity);
+            inst[i].sg = add(2, i, in[i].photons.capacity);
+        }
+    }
+    if (nblk > (1 << 24)) return QED_ERR_INVALID;
+    qed_plan p = new qed_plan_s();
+    memset(p, 0, sizeof(*p));
+    p->T = T;
+    p->ninst = n;
+    p->nseg = (int)seg.size();
+    p->nblk = (int)nblk;
+    p->lds = sizeof(R) * 2 * (T->dev.n_chi[0] > T->dev.n_chi[1] ? T->dev.n_chi[0] : T->dev.n_chi[1]);
+    hipError_t e = hipMalloc(&p->d_inst, sizeof(InstDev<R>) * n);
+    if (e == hipSuccess) e = hipMalloc((void **)&p->d_seg, sizeof(SegDev) * seg.size());
+    if (e == hipSuccess) e = hipMalloc((void **)&p->d_mask, sizeof(uint64_t) * mask_words);
+    if (e == hipSuccess) e = hipMalloc((void **)&p->d_bcnt, sizeof(uint32_t) * nblk);
+    if (e == hipSuccess) e = hipMalloc((void **)&p->d_gpre, sizeof(uint32_t) * (nblk + 1));
+    if (e == hipSuccess) e = hipMalloc((void **)&p->d_sbook, sizeof(SegBook) * seg.size());
+    if (e == hipSuccess) e = hipMalloc((void **)&p->d_clock_used, sizeof(int64_t) * n);
+    if (e == hipSuccess) e = hipMalloc((void **)&p->d_done, sizeof(unsigned));
+    if (e == hipSuccess) e = hipMemcpy(p->d_inst, inst.data(), sizeof(InstDev<R>) * n, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(p->d_seg, seg.data(), sizeof(SegDev) * seg.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemset(p->d_done, 0, sizeof(unsigned));
+    if (e == hipSuccess) e = hipMemset(p->d_gpre, 0, sizeof(uint32_t) * (nblk + 1));
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    if (e != hipSuccess) {
+        plan_free(p);
+        return qs_fail(e, "qed_plan_create");
+    }
+    *out = p;
+    return QED_OK;
+}
+
+template <class R> qed_status plan_step(qed_plan p, hipStream_t st)
+{
+    PlanDev P;
+    P.seg = p->d_seg;
+    P.nseg = p->nseg;
+    P.nblk = p->nblk;
+    P.ninst = p->ninst;
+    P.mask = p->d_mask;
+    P.bcnt = p->d_bcnt;
+    P.gpre = p->d_gpre;
+    P.sbook = p->d_sbook;
+    P.clock_used = p->d_clock_used;
+    P.done = p->d_done;
+    const InstDev<R> *inst = (const InstDev<R> *)p->d_inst;
+    QS_LAUNCH(K_PLAN_MAIN, k_plan_main<R>, dim3(p->nblk), dim3(kBlock), p->lds, st, inst, P, p->T->dev);
+    QS_LAUNCH(K_PLAN_PROCESS, k_plan_process<R>, dim3(p->nblk), dim3(kBlock), p->lds, st, inst, P, p->T->dev);
+    return qs_launch_status("qed_plan_step");
+}
+
+bool instance_ok(const qed_instance *in)
+{
+    const uint32_t fl = in->params.flags;
+    if (!leptons_ok(&in->electrons) || in->electrons.species != 0) return false;
+    if (!fields_ok(&in->fields) || !in->d_counters || !in->params.d_clock) return false;
+    if (!(in->params.dt > 0.0) || !(in->params.eps_r > 0.0)) return false;
+    if ((fl & (QED_EMIT | QED_PAIR)) && !photons_ok(&in->photons)) return false;
+    if ((fl & QED_PAIR) && (!leptons_ok(&in->positrons) || in->positrons.species != 1)) return false;
+    return true;
+}
+
+}  // namespace
+
+extern "C" qed_status qed_plan_create(qed_tables T, int n_instances, const qed_instance *instances,
+                                      const qed_plan_config *config, qed_plan *out)
+{
+    if (!T || !out || n_instances <= 0 || !instances) return QED_ERR_INVALID;
+    *out = nullptr;
+    for (int i = 0; i < n_instances; ++i)
+        if (!instance_ok(&instances[i])) return QED_ERR_INVALID;
+    const int ppb = config && config->particles_per_block > 0 ? config->particles_per_block : kBlock;
+    const int maxb = config && config->max_blocks_per_set > 0 ? config->max_blocks_per_set : kMaxGrid;
+    qs_clear_error();
+    if (T->params.precision == QED_F64) return plan_create<double>(T, n_instances, instances, ppb, maxb, out);
+    return plan_create<float>(T, n_instances, instances, ppb, maxb, out);
+}
+
+extern "C" qed_status qed_plan_step(qed_plan plan, qed_stream stream)
+{
+    if (!plan) return QED_ERR_INVALID;
+    qs_clear_error();
+    if (plan->T->params.precision == QED_F64) return plan_step<double>(plan, (hipStream_t)stream);
+    return plan_step<float>(plan, (hipStream_t)stream);
+}
+
+extern "C" int64_t qed_plan_blocks(qed_plan plan) { return plan ? plan->nblk : 0; }
+
+extern "C" qed_status qed_plan_destroy(qed_plan plan)
+{
+    if (plan) {
+        (void)hipDeviceSynchronize();
+        plan_free(plan);
+    }
+    return QED_OK;
+}

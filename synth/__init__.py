@@ -90,6 +90,31 @@ def c2(n: int = 1_000_000, seed: int = 2, steps: int = 3000, a0: float = 100.0,
                     k_retire=chi_g_min / (2.0 * a0 * EPS_R), x=x, p=p, s=s)
 
 
+def c5(n_instances: int = 64, seed: int = 5, steps: int = 2000, n_min: float = 1e4, n_max: float = 1e7,
+       scale: float = 1.0) -> list:
+    """Batched ensembles: independent head-on collisions shaped like c2, except per instance
+    N ~ LogUniform[n_min, n_max] (times `scale`), a0 ~ U[20, 200], gamma0 ~ U[500, 1e4] with
+    a 5 % spread, and spin polarization degree d ~ U[0, 1] along a random axis n perpendicular
+    to x: every electron is pure, +n with probability (1 + d)/2, else -n.  2000 steps."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for j in range(n_instances):
+        n = max(1, int(round(scale * math.exp(rng.uniform(math.log(n_min), math.log(n_max))))))
+        a0 = rng.uniform(20.0, 200.0)
+        g0 = rng.uniform(500.0, 1e4)
+        w = c2(n=n, seed=int(rng.integers(1 << 62)), steps=steps, a0=a0, gamma_mean=g0)
+        r = np.random.default_rng(int(rng.integers(1 << 62)))
+        ang = r.uniform(0.0, 2.0 * math.pi)
+        axis = np.array([0.0, math.cos(ang), math.sin(ang)])
+        d = r.uniform(0.0, 1.0)
+        sgn = np.where(r.random(n) < 0.5 * (1.0 + d), 1.0, -1.0)
+        w.s = axis[:, None] * sgn[None, :]
+        w.name = f"c5_instance_{j}"
+        w.extra = dict(a0=a0, gamma0=g0, pol_degree=d, pol_axis=axis)
+        out.append(w)
+    return out
+
+
 def subsample(w: Workload, idx) -> Workload:
     """The same workload restricted to the given primary-electron indices (for oracle samples)."""
     import copy

@@ -12,7 +12,7 @@ HEADER = ROOT / "include" / "qedspin.h"
 
 def declared_symbols():
     text = HEADER.read_text()
-    return sorted(set(re.findall(r"^\s*(?:qed_status|size_t|const char \*)\s*(qed_\w+)\s*\(", text, flags=re.M)))
+    return sorted(set(re.findall(r"^\s*(?:qed_status|size_t|int64_t|const char \*)\s*(qed_\w+)\s*\(", text, flags=re.M)))
 
 
 def test_header_declares_the_boundary():

@@ -1,0 +1,139 @@
+"""Merged and batched steps (qed_plan_step) against the per-species calls, bit for bit.
+
+A plan step of an instance is defined as qed_emit(electrons), qed_emit(positrons),
+qed_pair(photons), clock + 1; the per-species calls are themselves checked against the oracle
+in test_gpu_parity.  So equality here, particle by particle and counter by counter, carries the
+oracle parity over to the plan path.
+"""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+import synth
+
+pytestmark = pytest.mark.gpu
+
+EPS = synth.EPS_R
+
+
+@pytest.fixture(scope="module")
+def q():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2511_08929_amd as q
+    return q
+
+
+@pytest.fixture(scope="module")
+def tabs(q):
+    return {"fp64": q.Tables(precision=q.QED_F64), "fp32": q.Tables(precision=q.QED_F32)}
+
+
+def _sim(q, tab, w, merged, cap_e, cap_p, cap_g, flags=None, ppb=0):
+    from paper_2511_08929_amd.sim import Simulation
+    f = q.make_fields(w.field_kind, E0=w.E0, B0=w.B0, a0=w.a0, phase_len=w.phase_len)
+    sim = Simulation(tab, cap_e=cap_e, cap_p=cap_p, cap_g=cap_g, track=w.track, fields=f, dt=w.dt, eps_r=EPS,
+                     seed=w.seed, flags=q.QED_ALL if flags is None else flags, k_retire=w.k_retire,
+                     device_clock=True, merged=merged, particles_per_block=ppb)
+    sim.e.load(w.x, w.p, w.s)
+    return sim
+
+
+def _state(q, sim):
+    return sim.e.arrays() + sim.p.arrays() + sim.g.arrays() + (q.counters_dict(sim.ctr),)
+
+
+def _assert_same(a, b, what):
+    assert len(a) == len(b)
+    for j, (x, y) in enumerate(zip(a, b)):
+        if isinstance(x, dict):
+            assert x == y, f"{what}: counters {x} vs {y}"
+        else:
+            assert x.shape == y.shape, f"{what}: array {j} shape {x.shape} vs {y.shape}"
+            np.testing.assert_array_equal(x, y, err_msg=f"{what}: array {j}")
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_plan_equals_per_species_head_on(q, tabs, prec):
+    """2000 electrons of the head-on collision through the pulse (emission, pairs, retirement,
+    compaction every 25 steps), checked at five points."""
+    import torch
+    w = synth.subsample(synth.c2(), np.arange(2000))
+    a = _sim(q, tabs[prec], w, False, w.n + 3000, 3000, 150_000)
+    b = _sim(q, tabs[prec], w, True, w.n + 3000, 3000, 150_000)
+    for k in range(1, 1001):
+        a.step(); b.step()
+        if k % 25 == 0:
+            a.compact(); b.compact()
+        if k % 200 == 0:
+            torch.cuda.synchronize()
+            _assert_same(_state(q, a), _state(q, b), f"{prec} step {k}")
+    c = q.counters_dict(b.ctr)
+    print(prec, c)
+    assert c["n_emit"] > 10_000 and c["n_pair"] > 0 and c["n_retired"] > 0
+    assert int(a.clock.item()) == int(b.clock.item()) == 1000
+
+
+def test_plan_equals_per_species_dense_emission(q, tabs):
+    """Test-particle case (about 95 % emitters per step, no pairs): every block of the process
+    pass has a full list; small blocks (64 particles each) and a photon store that overflows."""
+    w = synth.c1(n=3000)
+    flags = q.QED_ALL & ~q.QED_PAIR
+    a = _sim(q, tabs["fp64"], w, False, w.n, 1, 40_000, flags)
+    b = _sim(q, tabs["fp64"], w, True, w.n, 1, 40_000, flags, ppb=64)
+    assert b.plan is None
+    for _ in range(16):
+        a.step(); b.step()
+    assert b.plan.blocks == 3000 // 64 + 1
+    _assert_same(_state(q, a), _state(q, b), "c1")
+    c = q.counters_dict(b.ctr)
+    assert c["n_capacity_overflow"] > 0 and b.g.n() == 40_000
+
+
+def test_plan_batched_instances(q, tabs):
+    """Three instances of different sizes, fields and seeds in one plan, each equal to its own
+    per-species run; then the same plan captured in a HIP graph and replayed, with eager work
+    between the replays, equal to further per-species steps after every replay."""
+    import torch
+    from paper_2511_08929_amd.sim import Batch
+    ws = synth.c5(n_instances=3, seed=11, n_min=300, n_max=3000)
+    tab = tabs["fp32"]
+    specs = []
+    for w in ws:
+        specs.append(dict(cap_e=w.n * 2 + 2000, cap_p=w.n + 2000, cap_g=80 * w.n + 20_000, track=w.track,
+                          fields=dict(kind=w.field_kind, a0=w.a0, phase_len=w.phase_len), dt=w.dt, eps_r=EPS,
+                          seed=w.seed, flags=q.QED_ALL, k_retire=w.k_retire))
+    bat = Batch(tab, specs, particles_per_block=128)
+    for w, inst in zip(ws, bat.inst):
+        inst["e"].load(w.x, w.p, w.s)
+    ref = [_sim(q, tab, w, False, s["cap_e"], s["cap_p"], s["cap_g"]) for w, s in zip(ws, specs)]
+
+    def check(what):
+        torch.cuda.synchronize()
+        for j, (r, inst) in enumerate(zip(ref, bat.inst)):
+            got = inst["e"].arrays() + inst["p"].arrays() + inst["g"].arrays() + (q.counters_dict(inst["ctr"]),)
+            _assert_same(_state(q, r), got, f"{what} instance {j}")
+
+    for k in range(1, 601):
+        bat.step()
+        for r in ref:
+            r.step()
+        if k % 50 == 0:
+            bat.compact()
+            for r in ref:
+                r.compact()
+    check("eager")
+    g = bat.capture(50)
+    for rep in range(4):
+        bat.replay(g)
+        for r in ref:
+            for _ in range(50):
+                r.step()
+            r.compact()
+        torch.cuda.synchronize()
+        check(f"replay {rep}")
+    tot = [q.counters_dict(i["ctr"]) for i in bat.inst]
+    print(tot)
+    assert sum(t["n_emit"] for t in tot) > 1000
