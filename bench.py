@@ -43,9 +43,10 @@ def bytes_per_unit(es, tracked_x=1):
     return lep, pho
 
 
-def run_gpu(q, prec, w, steps, warmup, compact_every, profile, graph=True):
+def run_gpu(q, prec, w, steps, warmup, compact_every, profile, graph=True, merged=True):
     """Time `steps` steps from the initial state.  With graph=True each run of `compact_every`
-    steps plus the compaction is one captured HIP graph (recorded before the timed region)."""
+    steps plus the compaction is one captured HIP graph (recorded before the timed region).
+    merged=True runs each step as one qed_plan_step (streaming + processing launch)."""
     import torch
     from paper_2511_08929_amd.sim import Simulation
     tab = q.Tables(precision=prec)
@@ -55,7 +56,8 @@ def run_gpu(q, prec, w, steps, warmup, compact_every, profile, graph=True):
 
     def fresh():
         sim = Simulation(tab, cap_e=w.n + cap_p, cap_p=cap_p, cap_g=cap_g, track=w.track, fields=fields, dt=w.dt,
-                         eps_r=synth.EPS_R, seed=w.seed, flags=q.QED_ALL, k_retire=w.k_retire, device_clock=graph)
+                         eps_r=synth.EPS_R, seed=w.seed, flags=q.QED_ALL, k_retire=w.k_retire, device_clock=graph,
+                         merged=merged)
         sim.e.load(w.x, w.p, w.s)
         return sim
 
@@ -89,7 +91,7 @@ def run_gpu(q, prec, w, steps, warmup, compact_every, profile, graph=True):
     return dict(wall=wall, ctr=ctr, ktimes=ktimes, n_photons=sim.g.n(), n_e=sim.e.n(), n_p=sim.p.n())
 
 
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "photon_main_head_on_1e6_fp32_hbm_traffic.md")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "plan_photon_head_on_1e6_fp32_hbm_traffic.md")
 
 
 def kernel_source_hash():
@@ -189,7 +191,8 @@ def main():
 
     # roofline of the dominant kernel (largest total time), from the HIP-event timings
     lep_b, pho_b = bytes_per_unit(4)
-    bytes_of = {"lepton_main": ck["n_lepton_steps"] * lep_b, "photon_main": ck["n_photon_steps"] * pho_b}
+    bytes_of = {"lepton_main": ck["n_lepton_steps"] * lep_b, "photon_main": ck["n_photon_steps"] * pho_b,
+                "plan_lepton": ck["n_lepton_steps"] * lep_b, "plan_photon": ck["n_photon_steps"] * pho_b}
     kt = {k: v for k, v in rk["ktimes"].items() if k in bytes_of}
     dom = max(kt, key=lambda k: kt[k][1])
     calls, ms = kt[dom]

@@ -1,15 +1,23 @@
 // qs_plan.hip -- one whole step (NLC for electrons and positrons, NBW for photons) of any number
-// of independent instances in two launches: qed_plan_create / qed_plan_step / qed_plan_destroy.
+// of independent instances in five launches: qed_plan_create / qed_plan_step / qed_plan_destroy.
 //
 // A plan splits every particle set of every instance into a contiguous range of blocks of one
-// grid ("segments": electrons, positrons, photons of instance 0, then of instance 1, ...).
+// block index space ("segments": the electrons and positrons of every instance, then the photons
+// of every instance).
 //   main     block b streams its share of its segment (lepton push + decision + no-emission
-//            update, or the two-phase photon pass) and writes its transition count; the last
-//            block to finish (completion counter, no waiting) scans the counts of all blocks in
-//            grid order and does each instance's bookkeeping: append bases, capacity clamp,
-//            device counts, event counters, and the step clock;
+//            update, or the two-phase photon pass) and writes its transition count and event
+//            counts (plain stores); leptons and photons are two launches, each with its own
+//            register allocation;
+//   book     block 0 scans the transition counts of all blocks in index order and does each
+//            instance's bookkeeping: append bases, capacity clamp, device counts, the step
+//            clock; the other blocks add the event counts of 64 main blocks each to the
+//            instances' counters;
 //   process  block b expands its own mask words into an ordered list in LDS and processes its
-//            transitions, writing photons (or pairs) at the instance's base + the rank.
+//            transitions, writing photons (or pairs) at the instance's base + the rank (again
+//            one launch for the lepton blocks and one for the photon blocks).
+// No block waits for another and no fence orders blocks: every hand-over is a launch boundary
+// on the stream.  (On this chip the L2 is per XCD, so a device-scope release or acquire fence
+// inside a kernel writes back or invalidates a whole L2.)
 // The appends keep the order of the per-species calls: photons of electrons, then of
 // positrons, in emitter order; pairs in photon order.  So a plan step gives the same particles,
 // bit for bit, as qed_emit(electrons), qed_emit(positrons), qed_pair, qed_clock_advance.
@@ -36,7 +44,7 @@ struct SegDev {
     int64_t mask_off, nchunks; // decision plane at mask + mask_off, branch plane nchunks words later
 };
 
-// written by the last block of the main pass, read by the process pass
+// written by the bookkeeping block, read by the process pass
 struct SegBook {
     int64_t n_main;            // particles the main pass covered
     int64_t base, base2;       // append base (photons; pairs: electrons, positrons)
@@ -48,10 +56,10 @@ struct PlanDev {
     int nseg, nblk, ninst;
     uint64_t *mask;
     uint32_t *bcnt;            // [nblk]
+    uint32_t *bctr;            // [nblk][kNCtr] event counts of each main block
     uint32_t *gpre;            // [nblk + 1] exclusive prefix of bcnt in grid order
     SegBook *sbook;            // [nseg]
     int64_t *clock_used;       // [ninst] step clock of the last main pass
-    unsigned *done;            // completion counter (0 between launches)
 };
 
 __device__ __forceinline__ int seg_of(const SegDev *seg, int nseg, int b)
@@ -74,37 +82,64 @@ __device__ __forceinline__ int64_t seg_total(const PlanDev &P, int sj)
     return (int64_t)hi - (int64_t)lo;
 }
 
-// last block: scan of the block counts, then per-instance bookkeeping (one thread per instance)
-template <class R> __device__ void plan_book(const InstDev<R> *inst, const PlanDev &P)
+constexpr int kCtrGroup = 64;   // main blocks whose event counts one bookkeeping block adds up
+
+// Block 0: scan of the transition counts of all main blocks, then per-instance bookkeeping (one
+// thread per instance).  Block 1 + g: event counts of main blocks [64 g, 64 g + 64) added to
+// their instances' counters (one atomic per counter and run of blocks of one instance).
+template <class R>
+__global__ void __launch_bounds__(kBlock) k_plan_book(const InstDev<R> *inst, PlanDev P)
 {
-    __shared__ uint32_t wsum[kBlock / 64];
-    __shared__ uint32_t carry;
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    if (threadIdx.x == 0) carry = 0;
-    __syncthreads();
-    for (int t0 = 0; t0 < P.nblk; t0 += kBlock) {
-        const int b = t0 + threadIdx.x;
-        const uint32_t v = b < P.nblk ? __hip_atomic_load(P.bcnt + b, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0u;
-        uint32_t incl = v;
-        for (int o = 1; o < 64; o <<= 1) {
-            const uint32_t y = __shfl_up(incl, o);
-            if (lane >= o) incl += y;
-        }
-        if (lane == 63) wsum[wid] = incl;
-        __syncthreads();
-        uint32_t off = carry;
-        for (int w = 0; w < wid; ++w) off += wsum[w];
-        if (b < P.nblk) P.gpre[b] = off + incl - v;
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            uint32_t t = 0;
-            for (int w = 0; w < kBlock / 64; ++w) t += wsum[w];
-            carry += t;
+    if (blockIdx.x > 0) {
+        __shared__ uint32_t cnt[kCtrGroup][kNCtr];
+        __shared__ int iid[kCtrGroup];
+        const int b0 = (blockIdx.x - 1) * kCtrGroup;
+        const int gsz = P.nblk - b0 < kCtrGroup ? P.nblk - b0 : kCtrGroup;
+        if ((int)threadIdx.x < gsz) {
+            const int b = b0 + threadIdx.x;
+            iid[threadIdx.x] = P.seg[seg_of(P.seg, P.nseg, b)].inst;
+            for (int c = 0; c < kNCtr; ++c) cnt[threadIdx.x][c] = P.bctr[(int64_t)b * kNCtr + c];
         }
         __syncthreads();
+        if (threadIdx.x < kNCtr) {
+            const int c = threadIdx.x;
+            unsigned long long acc = 0;
+            int cur = iid[0];
+            for (int t = 0; t < gsz; ++t) {
+                if (iid[t] != cur) {
+                    if (acc) atomicAdd(inst[cur].ctr + c, acc);
+                    cur = iid[t];
+                    acc = 0;
+                }
+                acc += cnt[t][c];
+            }
+            if (acc) atomicAdd(inst[cur].ctr + c, acc);
+        }
+        return;
     }
-    if (threadIdx.x == 0) P.gpre[P.nblk] = carry;
-    __threadfence();
+    // thread t owns the contiguous run [t m, t m + m) of block counts: all loads in flight at once,
+    // a serial sum, one block-wide scan of the 256 run totals, then the run's prefixes
+    __shared__ uint32_t wsum[kBlock / 64];
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    const int m = (int)cdiv(P.nblk, kBlock);
+    const int lo = threadIdx.x * m, hi = lo + m < P.nblk ? lo + m : P.nblk;
+    uint32_t run = 0;
+    for (int b = lo; b < hi; ++b) run += P.bcnt[b];
+    uint32_t incl = run;
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t y = __shfl_up(incl, o);
+        if (lane >= o) incl += y;
+    }
+    if (lane == 63) wsum[wid] = incl;
+    __syncthreads();
+    uint32_t off = incl - run;
+    for (int w = 0; w < wid; ++w) off += wsum[w];
+    for (int b = lo; b < hi; ++b) {
+        const uint32_t v = P.bcnt[b];
+        P.gpre[b] = off;
+        off += v;
+    }
+    if (threadIdx.x == kBlock - 1) P.gpre[P.nblk] = off;
     __syncthreads();
     for (int i = threadIdx.x; i < P.ninst; i += blockDim.x) {
         const InstDev<R> &I = inst[i];
@@ -150,76 +185,75 @@ template <class R> __device__ void plan_book(const InstDev<R> *inst, const PlanD
             P.clock_used[i] = 0;
         }
     }
-    if (threadIdx.x == 0) *P.done = 0u;
 }
 
-template <class R>
-__global__ void __launch_bounds__(kBlock) k_plan_main(const InstDev<R> *inst, PlanDev P, TablesDev T)
+// The streaming pass runs as two launches with their own register allocation: PHO = 0 over the
+// lepton segments (blocks [0, nblk_lep)), PHO = 1 over the photon segments (the rest).
+template <class R, int PHO>
+__global__ void __launch_bounds__(kBlock) k_plan_main(const InstDev<R> *inst, PlanDev P, TablesDev T, int b_first)
 {
     extern __shared__ unsigned char smem_raw[];
     R *lds = reinterpret_cast<R *>(smem_raw);
     __shared__ PhoQueue<R> Q;
     __shared__ unsigned tot[kNCtr + 1];
-    __shared__ int last;
-    const int b = blockIdx.x;
+    const int b = b_first + blockIdx.x;
     const int sj = seg_of(P.seg, P.nseg, b);
     const SegDev sg = P.seg[sj];
-    const InstDev<R> &I = inst[sg.inst];
-    const StepDev S = localize(I.S);
+    // local copies of the instance's views: the particle stores below may not alias them, so
+    // they stay in registers instead of being re-read from global memory after every store
+    const InstDev<R> *Ip = inst + sg.inst;
+    const StepDev S = localize(Ip->S);
+    const FieldDev F = Ip->F;
     uint64_t *mask = P.mask + sg.mask_off;
     unsigned v[kNCtr + 1] = {};
-    if (sg.kind < 2) {
-        const LepDev<R> &L = sg.kind == 0 ? I.E : I.P;
+    if (!PHO) {
+        const LepDev<R> L = sg.kind == 0 ? Ip->E : Ip->P;
         stage_rates<R>(T, 0, lds);
         const int64_t n = *L.count;
         const int64_t B = block_len(n, sg.nb);
         const int64_t start = (int64_t)(b - sg.b0) * B, end = start + B < n ? start + B : n;
         LCount c;
-        lepton_range<R>(L, I.F, S, T, lds, start, end, mask, sg.nchunks, c);
+        lepton_range<R>(L, F, S, T, lds, start, end, mask, sg.nchunks, c);
         v[C_PROB] = c.prob; v[C_CHI] = c.chi; v[C_NORM] = c.norm; v[C_LSTEP] = c.step; v[kNCtr] = c.trans;
     } else {
+        const PhoDev<R> G = Ip->G;
         stage_rates<R>(T, 1, lds);
-        const int64_t n = *I.G.count_prev;
+        const int64_t n = *G.count_prev;
         const int64_t B = block_len(n, sg.nb);
         const int64_t start = (int64_t)(b - sg.b0) * B, end = start + B < n ? start + B : n;
         GCount c;
         for (int64_t tile = start; tile < end; tile += kPhoTile)
-            photon_tile<R>(I.G, I.F, S, T, lds, Q, tile, tile + kPhoTile < end ? tile + kPhoTile : end, mask, sg.nchunks, c);
+            photon_tile<R>(G, F, S, T, lds, Q, tile, tile + kPhoTile < end ? tile + kPhoTile : end, mask, sg.nchunks, c);
         v[C_PROB] = c.prob; v[C_CHI] = c.chi; v[C_NORM] = c.norm; v[C_RETIRED] = c.ret; v[C_GSTEP] = c.step;
         v[C_GQED] = c.qed; v[kNCtr] = c.trans;
     }
     block_sum(v, tot);
-    if (threadIdx.x < kNCtr && tot[threadIdx.x]) atomicAdd(I.ctr + threadIdx.x, (unsigned long long)tot[threadIdx.x]);
-    if (threadIdx.x == kNCtr) P.bcnt[b] = tot[kNCtr];
-    // completion counter: the block that finishes last sees every other block's count
-    __threadfence();
-    __syncthreads();
-    if (threadIdx.x == 0) last = atomicAdd(P.done, 1u) == (unsigned)(gridDim.x - 1);
-    __syncthreads();
-    if (!last) return;
-    __threadfence();
-    plan_book<R>(inst, P);
+    if (threadIdx.x < kNCtr) P.bctr[(int64_t)b * kNCtr + threadIdx.x] = tot[threadIdx.x];
+    else if (threadIdx.x == kNCtr) P.bcnt[b] = tot[kNCtr];
 }
 
 constexpr int kExpandWords = 64;   // mask words expanded per round of the process pass (4096 slots)
 
-template <class R>
-__global__ void __launch_bounds__(kBlock) k_plan_process(const InstDev<R> *inst, PlanDev P, TablesDev T)
+template <class R, int PHO>
+__global__ void __launch_bounds__(kBlock) k_plan_process(const InstDev<R> *inst, PlanDev P, TablesDev T, int b_first)
 {
     extern __shared__ unsigned char smem_raw[];
     R *lds = reinterpret_cast<R *>(smem_raw);
     __shared__ uint16_t list[kExpandWords * 64];
     __shared__ uint32_t nlist;
-    const int b = blockIdx.x;
+    const int b = b_first + blockIdx.x;
     if (P.gpre[b + 1] == P.gpre[b]) return;           // no transition in this block's range
     const int sj = seg_of(P.seg, P.nseg, b);
     const SegDev sg = P.seg[sj];
-    const InstDev<R> &I = inst[sg.inst];
-    StepDev S = I.S;
+    const InstDev<R> *Ip = inst + sg.inst;
+    StepDev S = Ip->S;
     S.step += P.clock_used[sg.inst];
     S.t += (double)P.clock_used[sg.inst] * S.dt;
+    const FieldDev F = Ip->F;
+    const LepDev<R> E = Ip->E, Pp = Ip->P;
+    const PhoDev<R> G = Ip->G;
     const SegBook bk = P.sbook[sj];
-    stage_rates<R>(T, sg.kind < 2 ? 0 : 1, lds);
+    stage_rates<R>(T, PHO, lds);
     const uint64_t *mask = P.mask + sg.mask_off;
     const int64_t n = bk.n_main;
     const int64_t B = block_len(n, sg.nb);
@@ -254,31 +288,29 @@ __global__ void __launch_bounds__(kBlock) k_plan_process(const InstDev<R> *inst,
             const int64_t i = c0 * 64 + list[j];
             const int64_t r = rank0 + j;
             const bool br = (mask[sg.nchunks + (i >> 6)] >> (i & 63)) & 1ull;
-            if (sg.kind < 2) {
-                const LepDev<R> &L = sg.kind == 0 ? I.E : I.P;
-                emit_item<R>(L, I.G, I.F, S, T, lds, i, br, r < bk.nfit ? bk.base + r : -1, c_ret);
-            } else {
-                pair_item<R>(I.G, I.E, I.P, I.F, S, T, lds, i, br, r < bk.nfit ? bk.base + r : -1, bk.base2 + r);
-            }
+            if (!PHO)
+                emit_item<R>(sg.kind == 0 ? E : Pp, G, F, S, T, lds, i, br, r < bk.nfit ? bk.base + r : -1, c_ret);
+            else
+                pair_item<R>(G, E, Pp, F, S, T, lds, i, br, r < bk.nfit ? bk.base + r : -1, bk.base2 + r);
         }
         rank0 += nl;
         __syncthreads();
     }
-    wave_add(I.ctr, C_RETIRED, c_ret);
+    wave_add(Ip->ctr, C_RETIRED, c_ret);
 }
 
 }  // namespace
 
 struct qed_plan_s {
     qed_tables T;
-    int ninst, nseg, nblk;
+    int ninst, nseg, nblk, nblk_lep;
     void *d_inst;
     SegDev *d_seg;
     uint64_t *d_mask;
     uint32_t *d_bcnt, *d_gpre;
     SegBook *d_sbook;
     int64_t *d_clock_used;
-    unsigned *d_done;
+    uint32_t *d_bctr;
     size_t lds;
 };
 
@@ -308,7 +340,7 @@ void plan_free(qed_plan p)
     (void)hipFree(p->d_gpre);
     (void)hipFree(p->d_sbook);
     (void)hipFree(p->d_clock_used);
-    (void)hipFree(p->d_done);
+    (void)hipFree(p->d_bctr);
     delete p;
 }
 
@@ -332,14 +364,15 @@ qed_status plan_create(qed_tables T, int n, const qed_instance *in, int ppb, int
         seg.push_back(s);
         return (int)seg.size() - 1;
     };
+    // lepton segments of every instance first (first launch), then the photon segments
     for (int i = 0; i < n; ++i) {
         inst[i] = inst_dev<R>(&in[i]);
         inst[i].se = add(0, i, in[i].electrons.capacity);
-        if (in[i].params.flags & QED_PAIR) {
-            inst[i].sp = add(1, i, in[i].positrons.capacity);
-            inst[i].sg = add(2, i, in[i].photons.capacity);
-        }
+        if (in[i].params.flags & QED_PAIR) inst[i].sp = add(1, i, in[i].positrons.capacity);
     }
+    const int64_t nblk_lep = nblk;
+    for (int i = 0; i < n; ++i)
+        if (in[i].params.flags & QED_PAIR) inst[i].sg = add(2, i, in[i].photons.capacity);
     if (nblk > (1 << 24)) return QED_ERR_INVALID;
     qed_plan p = new qed_plan_s();
     memset(p, 0, sizeof(*p));
@@ -347,6 +380,7 @@ qed_status plan_create(qed_tables T, int n, const qed_instance *in, int ppb, int
     p->ninst = n;
     p->nseg = (int)seg.size();
     p->nblk = (int)nblk;
+    p->nblk_lep = (int)nblk_lep;
     p->lds = sizeof(R) * 2 * (T->dev.n_chi[0] > T->dev.n_chi[1] ? T->dev.n_chi[0] : T->dev.n_chi[1]);
     hipError_t e = hipMalloc(&p->d_inst, sizeof(InstDev<R>) * n);
     if (e == hipSuccess) e = hipMalloc((void **)&p->d_seg, sizeof(SegDev) * seg.size());
@@ -355,10 +389,9 @@ qed_status plan_create(qed_tables T, int n, const qed_instance *in, int ppb, int
     if (e == hipSuccess) e = hipMalloc((void **)&p->d_gpre, sizeof(uint32_t) * (nblk + 1));
     if (e == hipSuccess) e = hipMalloc((void **)&p->d_sbook, sizeof(SegBook) * seg.size());
     if (e == hipSuccess) e = hipMalloc((void **)&p->d_clock_used, sizeof(int64_t) * n);
-    if (e == hipSuccess) e = hipMalloc((void **)&p->d_done, sizeof(unsigned));
+    if (e == hipSuccess) e = hipMalloc((void **)&p->d_bctr, sizeof(uint32_t) * kNCtr * nblk);
     if (e == hipSuccess) e = hipMemcpy(p->d_inst, inst.data(), sizeof(InstDev<R>) * n, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(p->d_seg, seg.data(), sizeof(SegDev) * seg.size(), hipMemcpyHostToDevice);
-    if (e == hipSuccess) e = hipMemset(p->d_done, 0, sizeof(unsigned));
     if (e == hipSuccess) e = hipMemset(p->d_gpre, 0, sizeof(uint32_t) * (nblk + 1));
     if (e == hipSuccess) e = hipDeviceSynchronize();
     if (e != hipSuccess) {
@@ -381,10 +414,20 @@ template <class R> qed_status plan_step(qed_plan p, hipStream_t st)
     P.gpre = p->d_gpre;
     P.sbook = p->d_sbook;
     P.clock_used = p->d_clock_used;
-    P.done = p->d_done;
+    P.bctr = p->d_bctr;
     const InstDev<R> *inst = (const InstDev<R> *)p->d_inst;
-    QS_LAUNCH(K_PLAN_MAIN, k_plan_main<R>, dim3(p->nblk), dim3(kBlock), p->lds, st, inst, P, p->T->dev);
-    QS_LAUNCH(K_PLAN_PROCESS, k_plan_process<R>, dim3(p->nblk), dim3(kBlock), p->lds, st, inst, P, p->T->dev);
+    if (p->nblk_lep > 0)
+        QS_LAUNCH(K_PLAN_LEPTON, (k_plan_main<R, 0>), dim3(p->nblk_lep), dim3(kBlock), p->lds, st, inst, P, p->T->dev, 0);
+    if (p->nblk > p->nblk_lep)
+        QS_LAUNCH(K_PLAN_PHOTON, (k_plan_main<R, 1>), dim3(p->nblk - p->nblk_lep), dim3(kBlock), p->lds, st, inst, P,
+                  p->T->dev, p->nblk_lep);
+    QS_LAUNCH(K_BOOK, k_plan_book<R>, dim3(1 + (int)cdiv(p->nblk, kCtrGroup)), dim3(kBlock), 0, st, inst, P);
+    if (p->nblk_lep > 0)
+        QS_LAUNCH(K_PLAN_PROCESS, (k_plan_process<R, 0>), dim3(p->nblk_lep), dim3(kBlock), p->lds, st, inst, P,
+                  p->T->dev, 0);
+    if (p->nblk > p->nblk_lep)
+        QS_LAUNCH(K_PLAN_PROCESS, (k_plan_process<R, 1>), dim3(p->nblk - p->nblk_lep), dim3(kBlock), p->lds, st, inst,
+                  P, p->T->dev, p->nblk_lep);
     return qs_launch_status("qed_plan_step");
 }
 
