@@ -12,6 +12,8 @@
  *      for electrons and photons, +1 for positrons; beta = khat x eps (right-handed).
  *      The printed spectra are non-negative for every pure state only in this
  *      handedness; the orientation makes electrons polarize against the rest-frame B.
+ *      For photons (NBW) the electron-line convention rests on the crossing symmetry of
+ *      the outgoing-electron term; beyond positivity that orientation is parity unpinned.
  *  R2  Last term of G3 (NBW appendix, Bessel form) taken with a plus sign, as in the
  *      Airy form of the same equation.
  *  R3  Both branches of the spin-up/down inverse-CDF selection in the NLC section print

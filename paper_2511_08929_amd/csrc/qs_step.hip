@@ -1,18 +1,18 @@
-// qs_step.hip -- the per-particle QED step on gfx950: qed_push_spin, qed_emit, qed_pair,
-// qed_compact.
+// qs_step.hip -- the per-species entry points qed_push_spin, qed_emit, qed_pair, and the photon
+// compaction qed_compact.
 //
 // Each transition step runs as
 //   main     one streaming pass over the particle SoA (coalesced loads/stores, rate tables in
 //            LDS): push, chi, basis, rates, Philox draw, decision, no-transition update; the
-//            wave's 64 decisions and branch choices are ballot'ed into two 64-bit mask words;
-//   reduce   per-block popcount sums of the mask words;
-//   book     one block: total, append bases, capacity clamp, counters, device-side counts;
-//   expand   per-block prefix + block scan of the mask popcounts -> dense, ascending list of
-//            the transitioning particles' indices;
-//   process  one thread per transitioning particle (dense, no divergence from the ~97 % that
-//            do not transition): inverse-CDF sampling, Bessel functions, spin / Stokes collapse,
-//            appends at base + rank.
-// Everything is keyed on device-resident counts, so a step enqueues without host sync.
+//            wave's 64 decisions and branch choices are ballot'ed into two 64-bit mask words,
+//            each block writes its transition and event counts;
+//   expand   per-block prefix of the block counts (block 0 also does the bookkeeping: total,
+//            append bases, capacity clamp, counters, device counts) and expansion of the block's
+//            mask words into a dense, ascending list of the transitioning particles;
+//   process  one thread per transitioning particle: inverse-CDF sampling, Bessel functions,
+//            spin / Stokes collapse, appends at base + rank.
+// Everything is keyed on device-resident counts, so a step enqueues without host sync.  The
+// per-particle bodies are shared with the merged step (qs_plan.hip) through qs_pass.hpp.
 #include "qs_pass.hpp"
 
 namespace {
