@@ -71,7 +71,10 @@ enum {
     QED_MEAN = 1u << 7,        /* mean-value mode: s_f = g/w, xi = F(s_f=0)/w, pair spins j/w0 */
     QED_PAIR = 1u << 8,        /* nonlinear Breit-Wheeler pair creation */
     QED_NOPAIR = 1u << 9,      /* no-transition polarization update of surviving photons */
-    QED_PAIR_SPIN = 1u << 10   /* correlated pair spins (else unpolarized pairs) */
+    QED_PAIR_SPIN = 1u << 10,  /* correlated pair spins (else unpolarized pairs) */
+    QED_OPTICAL_DEPTH = 1u << 11 /* emission decided by the optical depth (decision-making overview):
+                                  tau += W dt in FP64, emission when tau >= tau* = -ln(1 - u), u from
+                                  Philox channel 4; the leptons' tau / tau_target arrays are required */
 };
 
 /* Field models evaluated at each particle. */
@@ -107,6 +110,9 @@ typedef struct {
                                    does not depend on coordinate i (then it is not advanced) */
     void    *p[3];              /* momentum / (m c) */
     void    *s[3];              /* spin vector, |s| <= 1 */
+    double  *tau, *tau_target;  /* optical depth and its target, FP64 in both precisions (NULL unless
+                                   QED_OPTICAL_DEPTH); a target <= 0 is drawn at the particle's next step;
+                                   pair-born leptons start at 0, 0 */
 } qed_leptons;
 
 typedef struct {

@@ -33,6 +33,7 @@ NLC_DOWN, NLC_UP, NBW_MINUS, NBW_PLUS = 0, 1, 2, 3
 F_PUSH, F_TBMT, F_EMIT, F_RECOIL = 1 << 0, 1 << 1, 1 << 2, 1 << 3
 F_SPIN, F_NOEMIT, F_PHOTON_POL, F_MEAN = 1 << 4, 1 << 5, 1 << 6, 1 << 7
 F_PAIR, F_NOPAIR, F_PAIR_SPIN = 1 << 8, 1 << 9, 1 << 10
+F_TAU = 1 << 11
 F_ALL = (F_PUSH | F_TBMT | F_EMIT | F_RECOIL | F_SPIN | F_NOEMIT | F_PHOTON_POL
          | F_PAIR | F_NOPAIR | F_PAIR_SPIN)
 
@@ -82,7 +83,7 @@ DP = C.POINTER(C.c_double)
 class Leptons(C.Structure):
     _fields_ = [("n", C.c_int64), ("cap", C.c_int64), ("species", C.c_int),
                 ("x", DP * 3), ("p", DP * 3), ("s", DP * 3), ("near", C.POINTER(C.c_uint8)),
-                ("index", C.POINTER(C.c_int64))]
+                ("index", C.POINTER(C.c_int64)), ("tau", DP), ("tau_target", DP)]
 
 
 class Photons(C.Structure):
@@ -134,7 +135,7 @@ def lib():
                                       C.POINTER(Counters), i]
         L.orc_compact.argtypes = [C.POINTER(Photons)]
         L.orc_lepton_qed_one.argtypes = [C.POINTER(Tables), C.POINTER(Params), i, C.c_int64, DP, DP, DP,
-                                         DP, DP, DP, DP, C.POINTER(u64), C.POINTER(Counters)]
+                                         DP, DP, DP, DP, C.POINTER(u64), DP, C.POINTER(Counters)]
         L.orc_lepton_qed_one.restype = i
         L.orc_photon_qed_one.argtypes = [C.POINTER(Tables), C.POINTER(Params), u64, DP, DP, DP, DP,
                                          DP, DP, DP, DP, C.POINTER(Counters)]
@@ -335,13 +336,15 @@ class OracleTables:
 class LeptonSet:
     """SoA lepton storage (float64) with a capacity; x components may be absent."""
 
-    def __init__(self, species, cap, track=(True, True, True)):
+    def __init__(self, species, cap, track=(True, True, True), tau=False):
         self.species, self.cap, self.n = species, int(cap), 0
         self.x = [np.zeros(cap) if t else None for t in track]
         self.p = [np.zeros(cap) for _ in range(3)]
         self.s = [np.zeros(cap) for _ in range(3)]
         self.near = np.zeros(cap, dtype=np.uint8)
         self.index = None
+        self.tau = np.zeros(cap) if tau else None           # optical depth and its target
+        self.tau_target = np.zeros(cap) if tau else None
 
     def set(self, x, p, s, index=None):
         n = p.shape[1]
@@ -366,6 +369,8 @@ class LeptonSet:
         L.near = self.near.ctypes.data_as(C.POINTER(C.c_uint8))
         L.index = (self.index.ctypes.data_as(C.POINTER(C.c_int64)) if self.index is not None
                    else C.POINTER(C.c_int64)())
+        L.tau = self.tau.ctypes.data_as(DP) if self.tau is not None else DP()
+        L.tau_target = self.tau_target.ctypes.data_as(DP) if self.tau_target is not None else DP()
         return L
 
     def arrays(self):
@@ -452,15 +457,17 @@ def compact(G: PhotonSet):
     G.pull(Gs)
 
 
-def lepton_qed_one(tables, params, species, index, E, B, x, p, s):
+def lepton_qed_one(tables, params, species, index, E, B, x, p, s, tau2=None):
+    """tau2: optional [tau, tau*] (optical-depth decision), updated in place"""
     E, pE = _v(E); B, pB = _v(B); x, px = _v(x)
     p = np.array(p, dtype=np.float64); s = np.array(s, dtype=np.float64)
     k, P = np.zeros(3), np.zeros(3)
     pid = C.c_uint64()
     ctr = Counters()
+    pt = tau2.ctypes.data_as(DP) if tau2 is not None else DP()
     r = lib().orc_lepton_qed_one(C.byref(tables.struct), C.byref(params), species, index, pE, pB, px,
                                  p.ctypes.data_as(DP), s.ctypes.data_as(DP), k.ctypes.data_as(DP),
-                                 P.ctypes.data_as(DP), C.byref(pid), C.byref(ctr))
+                                 P.ctypes.data_as(DP), C.byref(pid), pt, C.byref(ctr))
     return r, p, s, k, P, pid.value, ctr.as_dict()
 
 

@@ -29,6 +29,12 @@
  *  R8  Photon-polarization collapse picks +/- Xi (the section writes s_f where xi is meant).
  *  R9  T-BMT with the standard E-term coefficient (a + 1/(gamma+1)); Cayley rotation with
  *      the Boris mid-step gamma, so that g = 2 keeps the spin-momentum angle.
+ *  R10 Optical-depth decision (the alternative of the decision-making overview): tau grows by
+ *      the spin-weighted W dt each step, in FP64; emission when tau >= tau*, with tau* =
+ *      -ln(1 - u) drawn from Philox channel 4 (53-bit words 0,1 when no target is set yet,
+ *      words 2,3 after an emission, when tau restarts at 0).  The up/down branch is then
+ *      r1 < a/P with the step's r1; without emission the no-transition update is the same as
+ *      with the per-step draw, applied only while W dt < 1 (otherwise skipped and counted).
  */
 #include "qed_oracle.h"
 
@@ -795,12 +801,27 @@ static uint64_t photon_id(int species, int64_t index, int64_t step)
            | ((uint64_t)step & 0xFFFFFFull);
 }
 
+/* no-transition spin update (non-transition section), renormalised if it leaves |s| > 1 (R6) */
+static void no_emission_update(double s[3], const double bh[3], double Wbar, double dW, double dt, double P,
+                               orc_counters *ctr)
+{
+    double den = 1.0 - P;
+    for (int i = 0; i < 3; ++i) s[i] = (s[i] * (1.0 - Wbar * dt) - dW * dt * bh[i]) / den;
+    double n2 = dot3(s, s);
+    if (n2 > 1.0) {
+        double n = sqrt(n2);
+        for (int i = 0; i < 3; ++i) s[i] /= n;
+        if (n2 > 1.0 + 1e-12) ctr->n_norm_clamped++;
+    }
+}
+
 /* returns 1 if a photon was emitted (k_out, P_out, id_out valid), 0 otherwise;
-   bit 1 of the return value flags a near tie of one of the decisions. */
+   bit 1 of the return value flags a near tie of one of the decisions.  tau2 = {tau, tau*}
+   of the lepton, updated in place, with ORC_F_TAU (may be NULL otherwise). */
 int orc_lepton_qed_one(const orc_tables *T, const orc_params *prm, int species, int64_t index,
                        const double E[3], const double B[3], const double x[3],
                        double p[3], double s[3], double k_out[3], double P_out[3],
-                       uint64_t *id_out, orc_counters *ctr)
+                       uint64_t *id_out, double tau2[2], orc_counters *ctr)
 {
     (void)x;
     uint32_t fl = prm->flags;
@@ -824,24 +845,39 @@ int orc_lepton_qed_one(const orc_tables *T, const orc_params *prm, int species, 
     uint64_t id = lepton_id(species, index);
     double r1, r2;
     uniforms2(prm, id, 0, &r1, &r2);
-    if (P <= 1.0 && near_tie(r1, P, prm->near_tol)) near = 1;
-    if (P <= 1.0 && !(r1 < P)) {
-        if (fl & ORC_F_NOEMIT) {
-            double Wbar = 0.5 * (Wup + Wdn), dW = 0.5 * (Wup - Wdn);
-            double den = 1.0 - P;
-            for (int i = 0; i < 3; ++i) s[i] = (s[i] * (1.0 - Wbar * dt) - dW * dt * bh[i]) / den;
-            double n2 = dot3(s, s);
-            if (n2 > 1.0) {
-                double n = sqrt(n2);
-                for (int i = 0; i < 3; ++i) s[i] /= n;
-                if (n2 > 1.0 + 1e-12) ctr->n_norm_clamped++;
+    double Wbar = 0.5 * (Wup + Wdn), dW = 0.5 * (Wup - Wdn);
+    double thr;
+    if ((fl & ORC_F_TAU) && tau2) {
+        /* optical depth (R10) */
+        uint32_t w4[4];
+        philox_block(prm->seed, id, prm->step, 4u, w4);
+        double target = tau2[1];
+        if (!(target > 0.0)) target = -log1p(-orc_u01_53(w4[0], w4[1]));
+        double tn = tau2[0] + P;
+        if (near_tie(tn, target, prm->near_tol)) near = 1;
+        if (!(tn >= target)) {
+            tau2[0] = tn;
+            tau2[1] = target;
+            if (fl & ORC_F_NOEMIT) {
+                if (P < 1.0) no_emission_update(s, bh, Wbar, dW, dt, P, ctr);
+                else ctr->n_prob_clamped++;
             }
+            return near << 1;
         }
-        return near << 1;
+        tau2[0] = 0.0;
+        tau2[1] = -log1p(-orc_u01_53(w4[2], w4[3]));
+        thr = a / P;
+    } else {
+        /* per-step draw */
+        if (P <= 1.0 && near_tie(r1, P, prm->near_tol)) near = 1;
+        if (P <= 1.0 && !(r1 < P)) {
+            if (fl & ORC_F_NOEMIT) no_emission_update(s, bh, Wbar, dW, dt, P, ctr);
+            return near << 1;
+        }
+        if (P > 1.0) ctr->n_prob_clamped++;
+        /* branch: down table iff r1 < a (or r1 < a/P when the probability is clamped) */
+        thr = (P <= 1.0) ? a : a / P;
     }
-    if (P > 1.0) ctr->n_prob_clamped++;
-    /* branch: down table iff r1 < a (or r1 < a/P when the probability is clamped) */
-    double thr = (P <= 1.0) ? a : a / P;
     if (near_tie(r1, thr, prm->near_tol)) near = 1;
     int up = !(r1 < thr);
     double rho = log(r2) - log1p(-r2);
@@ -1035,8 +1071,11 @@ int orc_lepton_step(const orc_tables *T, const orc_params *prm, const orc_fields
             }
             orc_fields_eval(f, x, prm->t + prm->dt, E, B);
             int64_t idx = L->index ? L->index[j] : j;
+            double tau2[2] = {L->tau ? L->tau[j] : 0.0, L->tau_target ? L->tau_target[j] : 0.0};
+            int mode_b = (prm->flags & ORC_F_TAU) && L->tau && L->tau_target;
             int r = orc_lepton_qed_one(T, prm, L->species, idx, E, B, x, p, s, kb + 6 * j, kb + 6 * j + 3,
-                                       ib + j, &loc);
+                                       ib + j, mode_b ? tau2 : NULL, &loc);
+            if (mode_b) { L->tau[j] = tau2[0]; L->tau_target[j] = tau2[1]; }
             emitted[j] = (char)(r & 1);
             if (r & 2) loc.n_near_threshold++;
             if (L->near) L->near[j] = (uint8_t)((r >> 1) & 1);
@@ -1122,6 +1161,11 @@ int orc_photon_step(const orc_tables *T, const orc_params *prm, const orc_fields
         int64_t me = Le->n++, mp = Lp->n++;
         if (Le->index) Le->index[me] = me;
         if (Lp->index) Lp->index[mp] = mp;
+        /* new leptons start with no optical depth and no target (drawn at their first step) */
+        if (Le->tau) Le->tau[me] = 0.0;
+        if (Le->tau_target) Le->tau_target[me] = 0.0;
+        if (Lp->tau) Lp->tau[mp] = 0.0;
+        if (Lp->tau_target) Lp->tau_target[mp] = 0.0;
         for (int i = 0; i < 3; ++i) {
             double xv = getx(G->x, i, j);
             if (Le->x[i]) Le->x[i][me] = xv;

@@ -82,7 +82,8 @@ void orc_fields_eval(const orc_fields *f, const double x[3], double t, double E[
 enum {
     ORC_F_PUSH = 1u << 0, ORC_F_TBMT = 1u << 1, ORC_F_EMIT = 1u << 2, ORC_F_RECOIL = 1u << 3,
     ORC_F_SPIN = 1u << 4, ORC_F_NOEMIT = 1u << 5, ORC_F_PHOTON_POL = 1u << 6, ORC_F_MEAN = 1u << 7,
-    ORC_F_PAIR = 1u << 8, ORC_F_NOPAIR = 1u << 9, ORC_F_PAIR_SPIN = 1u << 10
+    ORC_F_PAIR = 1u << 8, ORC_F_NOPAIR = 1u << 9, ORC_F_PAIR_SPIN = 1u << 10,
+    ORC_F_TAU = 1u << 11     /* emission decided by the optical depth instead of the per-step draw */
 };
 
 typedef struct {
@@ -102,6 +103,7 @@ typedef struct {
     double *x[3], *p[3], *s[3];   /* x[i] may be NULL: coordinate not tracked (taken as 0) */
     uint8_t *near;          /* optional: set to 1 when a decision of this particle was a near tie */
     int64_t *index;         /* optional: index that names particle j in its full set (default j) */
+    double  *tau, *tau_target;  /* optical depth and its target (ORC_F_TAU only); target 0 = not drawn */
 } orc_leptons;
 
 typedef struct {
@@ -136,7 +138,7 @@ void orc_compact(orc_photons *G);
 int orc_lepton_qed_one(const orc_tables *T, const orc_params *prm, int species, int64_t index,
                        const double E[3], const double B[3], const double x[3],
                        double p[3], double s[3], double k_out[3], double P_out[3],
-                       uint64_t *id_out, orc_counters *ctr);
+                       uint64_t *id_out, double tau2[2], orc_counters *ctr);
 int orc_photon_qed_one(const orc_tables *T, const orc_params *prm, uint64_t id,
                        const double E[3], const double B[3], const double k[3], double P[3],
                        double pe[3], double se[3], double pp[3], double sp[3], orc_counters *ctr);

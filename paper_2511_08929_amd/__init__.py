@@ -26,6 +26,7 @@ QED_F64, QED_F32 = 0, 1
 QED_PUSH, QED_TBMT, QED_EMIT, QED_RECOIL = 1 << 0, 1 << 1, 1 << 2, 1 << 3
 QED_SPIN, QED_NOEMIT, QED_PHOTON_POL, QED_MEAN = 1 << 4, 1 << 5, 1 << 6, 1 << 7
 QED_PAIR, QED_NOPAIR, QED_PAIR_SPIN = 1 << 8, 1 << 9, 1 << 10
+QED_OPTICAL_DEPTH = 1 << 11
 QED_ALL = (QED_PUSH | QED_TBMT | QED_EMIT | QED_RECOIL | QED_SPIN | QED_NOEMIT | QED_PHOTON_POL
            | QED_PAIR | QED_NOPAIR | QED_PAIR_SPIN)
 QED_FIELD_UNIFORM, QED_FIELD_PLANE_LP = 0, 1
@@ -52,7 +53,8 @@ class TableParams(C.Structure):
 
 class Leptons(C.Structure):
     _fields_ = [("capacity", C.c_int64), ("d_count", C.c_void_p), ("species", C.c_int),
-                ("x", C.c_void_p * 3), ("p", C.c_void_p * 3), ("s", C.c_void_p * 3)]
+                ("x", C.c_void_p * 3), ("p", C.c_void_p * 3), ("s", C.c_void_p * 3),
+                ("tau", C.c_void_p), ("tau_target", C.c_void_p)]
 
 
 class Photons(C.Structure):
@@ -200,13 +202,16 @@ def qed_workspace_size(max_particles):
 class LeptonBuffers:
     """Device SoA storage for one lepton species (torch tensors) and its ABI view."""
 
-    def __init__(self, species, capacity, dtype, device="cuda", track=(True, True, True)):
+    def __init__(self, species, capacity, dtype, device="cuda", track=(True, True, True), tau=False):
         import torch
         self.species, self.capacity, self.dtype = species, int(capacity), dtype
         self.x = [torch.zeros(capacity, dtype=dtype, device=device) if t else None for t in track]
         self.p = [torch.zeros(capacity, dtype=dtype, device=device) for _ in range(3)]
         self.s = [torch.zeros(capacity, dtype=dtype, device=device) for _ in range(3)]
         self.count = torch.zeros(1, dtype=torch.int64, device=device)
+        # optical depth and its target (FP64 in both precisions), for QED_OPTICAL_DEPTH
+        self.tau = torch.zeros(capacity, dtype=torch.float64, device=device) if tau else None
+        self.tau_target = torch.zeros(capacity, dtype=torch.float64, device=device) if tau else None
 
     def load(self, x, p, s):
         import torch
@@ -228,6 +233,8 @@ class LeptonBuffers:
             v.x[i] = self.x[i].data_ptr() if self.x[i] is not None else None
             v.p[i] = self.p[i].data_ptr()
             v.s[i] = self.s[i].data_ptr()
+        v.tau = self.tau.data_ptr() if self.tau is not None else None
+        v.tau_target = self.tau_target.data_ptr() if self.tau_target is not None else None
         self._view = v
         return v
 
@@ -240,6 +247,10 @@ class LeptonBuffers:
         x = np.stack([(a[:n].double().cpu().numpy() if a is not None else np.zeros(n)) for a in self.x])
         return (x, np.stack([a[:n].double().cpu().numpy() for a in self.p]),
                 np.stack([a[:n].double().cpu().numpy() for a in self.s]))
+
+    def tau_arrays(self):
+        n = self.n()
+        return self.tau[:n].cpu().numpy(), self.tau_target[:n].cpu().numpy()
 
 
 class PhotonBuffers:

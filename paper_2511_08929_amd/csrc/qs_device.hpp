@@ -17,7 +17,7 @@ constexpr double kPi = 3.14159265358979323846;
 enum : uint32_t {
     F_PUSH = 1u << 0, F_TBMT = 1u << 1, F_EMIT = 1u << 2, F_RECOIL = 1u << 3, F_SPIN = 1u << 4,
     F_NOEMIT = 1u << 5, F_PHOTON_POL = 1u << 6, F_MEAN = 1u << 7, F_PAIR = 1u << 8,
-    F_NOPAIR = 1u << 9, F_PAIR_SPIN = 1u << 10
+    F_NOPAIR = 1u << 9, F_PAIR_SPIN = 1u << 10, F_TAU = 1u << 11
 };
 
 // ------------------------------------------------------------------ small vectors

@@ -18,6 +18,7 @@ template <class R> struct LepDev {
     int64_t *count;
     int species;
     R *x[3], *p[3], *s[3];
+    double *tau, *tau_t;       // optical depth and its target (FP64 in both precisions), or NULL
 };
 
 template <class R> struct PhoDev {
@@ -299,23 +300,43 @@ __device__ __forceinline__ void lepton_item(const LepDev<R> &L, const FieldDev &
         const LDecide<R> d = lepton_decide<R>(S, T, lds, L.species, i, p, s, E, B);
         if (d.active) {
             c.chi += d.clamped_chi;
-            if (d.P <= (R)1 && !(d.r1 < d.P)) {
-                if (S.flags & F_NOEMIT) {
-                    const R dt = (R)S.dt;
-                    const R Wbar = (R)0.5 * (d.Wup + d.Wdn), dW = (R)0.5 * (d.Wup - d.Wdn);
-                    const R inv = (R)1 / ((R)1 - d.P);
-                    s = inv * (((R)1 - Wbar * dt) * s - (dW * dt) * d.bs.b);
-                    const R n2 = dot(s, s);
-                    if (n2 > (R)1) {
-                        s = rsqrt_r(n2) * s;
-                        c.norm += n2 > (R)1 + norm_count_tol<R>();
-                    }
+            bool noemit_update = false;
+            if ((S.flags & F_TAU) && L.tau) {
+                // optical depth in FP64: tau += W dt; emission at tau >= tau*, tau* = -ln(1 - u)
+                // from channel 4 (words 0,1 if no target is set yet, words 2,3 after an emission)
+                const uint4 w4 = philox_block(S.seed, lepton_id(L.species, i), S.step, 4u);
+                double target = L.tau_t[i];
+                if (!(target > 0.0)) target = -log1p(-u01_53(w4.x, w4.y));
+                const double tn = L.tau[i] + (double)d.P;
+                if (tn >= target) {
+                    L.tau[i] = 0.0;
+                    L.tau_t[i] = -log1p(-u01_53(w4.z, w4.w));
+                    emit = true;
+                    up = !(d.r1 < d.a / d.P);
+                } else {
+                    L.tau[i] = tn;
+                    L.tau_t[i] = target;
+                    if (d.P < (R)1) noemit_update = true;
+                    else if (S.flags & F_NOEMIT) ++c.prob;
                 }
+            } else if (d.P <= (R)1 && !(d.r1 < d.P)) {
+                noemit_update = true;
             } else {
                 emit = true;
                 c.prob += d.P > (R)1;
                 const R thr = d.P <= (R)1 ? d.a : d.a / d.P;
                 up = !(d.r1 < thr);
+            }
+            if (noemit_update && (S.flags & F_NOEMIT)) {
+                const R dt = (R)S.dt;
+                const R Wbar = (R)0.5 * (d.Wup + d.Wdn), dW = (R)0.5 * (d.Wup - d.Wdn);
+                const R inv = (R)1 / ((R)1 - d.P);
+                s = inv * (((R)1 - Wbar * dt) * s - (dW * dt) * d.bs.b);
+                const R n2 = dot(s, s);
+                if (n2 > (R)1) {
+                    s = rsqrt_r(n2) * s;
+                    c.norm += n2 > (R)1 + norm_count_tol<R>();
+                }
             }
         }
     }
@@ -577,6 +598,9 @@ __device__ __forceinline__ void pair_item(const PhoDev<R> &G, const LepDev<R> &L
     }
     G.id[i] = 0;
     if (se >= 0) {
+        // new leptons start with no optical depth and no target (drawn at their first step)
+        if (Le.tau) { Le.tau[se] = 0.0; Le.tau_t[se] = 0.0; }
+        if (Lp.tau) { Lp.tau[sp] = 0.0; Lp.tau_t[sp] = 0.0; }
         const V3<R> se_lab = ec.x * d.bs.e + ec.y * d.bs.b + ec.z * d.bs.k;
         const V3<R> sp_lab = pc.x * d.bs.e + pc.y * d.bs.b + pc.z * d.bs.k;
         stx(Le.x, se, x);
@@ -600,6 +624,8 @@ template <class R> LepDev<R> lep_dev(const qed_leptons *L)
         d.p[c] = (R *)L->p[c];
         d.s[c] = (R *)L->s[c];
     }
+    d.tau = L->tau;
+    d.tau_t = L->tau_target;
     return d;
 }
 
@@ -662,6 +688,12 @@ inline bool leptons_ok(const qed_leptons *L)
     for (int c = 0; c < 3; ++c)
         if (!L->p[c] || !L->s[c]) return false;
     return true;
+}
+
+// the optical-depth decision needs both FP64 arrays
+inline bool tau_ok(const qed_leptons *L, uint32_t flags)
+{
+    return !(flags & QED_OPTICAL_DEPTH) || (L->tau && L->tau_target);
 }
 
 inline bool photons_ok(const qed_photons *G)

@@ -22,12 +22,13 @@ from . import (ALPHA, QED_F64, QED_PAIR, LeptonBuffers, PhotonBuffers, Plan, Tab
 class Simulation:
     def __init__(self, tables: Tables, *, cap_e, cap_p, cap_g, track, fields, dt, eps_r, seed, flags,
                  k_retire=0.0, t0=0.0, a_e=ALPHA / (2 * math.pi), chi_e_min=1e-3, chi_e_max=1e2, chi_g_min=0.05,
-                 chi_g_max=1e2, device="cuda", device_clock=False, merged=False, particles_per_block=0):
+                 chi_g_max=1e2, device="cuda", device_clock=False, merged=False, particles_per_block=0,
+                 optical_depth=False):
         import torch
         self.tables = tables
         self.dtype = torch.float64 if tables.precision == QED_F64 else torch.float32
-        self.e = LeptonBuffers(0, cap_e, self.dtype, device, track)
-        self.p = LeptonBuffers(1, cap_p, self.dtype, device, track)
+        self.e = LeptonBuffers(0, cap_e, self.dtype, device, track, tau=optical_depth)
+        self.p = LeptonBuffers(1, cap_p, self.dtype, device, track, tau=optical_depth)
         self.g = PhotonBuffers(cap_g, self.dtype, device, track)
         self.ctr = new_counters(device)
         nbytes = max(qed_workspace_size(max(cap_e, cap_p, cap_g)),

@@ -9,7 +9,7 @@ import oracle
 
 def oracle_run(tables, w, steps, flags, *, cap_e=None, cap_p=None, cap_g=None, u24=False, near_tol=1e-10,
                index=None, seed=None, k_retire=None, t0=0.0, nthreads=16, x=None, p=None, s=None,
-               fields=None, step0=0):
+               fields=None, step0=0, tau=False):
     """Run the oracle for `steps` steps of workload `w` (optionally a subset with original indices
     `index`).  Returns dict of oracle sets, counters and accumulated near-tie flags."""
     x = w.x if x is None else x
@@ -19,9 +19,9 @@ def oracle_run(tables, w, steps, flags, *, cap_e=None, cap_p=None, cap_g=None, u
     cap_e = cap_e or n
     cap_p = cap_p or max(1, cap_e - n)
     cap_g = cap_g or 1
-    E = oracle.LeptonSet(0, cap_e, track=w.track)
+    E = oracle.LeptonSet(0, cap_e, track=w.track, tau=tau)
     E.set(x, p, s, index=index)
-    P = oracle.LeptonSet(1, cap_p, track=w.track)
+    P = oracle.LeptonSet(1, cap_p, track=w.track, tau=tau)
     G = oracle.PhotonSet(cap_g, track=w.track)
     F = fields or oracle.make_fields(w.field_kind, E0=w.E0, B0=w.B0, a0=w.a0, phase_len=w.phase_len)
     ctr = oracle.Counters()
@@ -53,7 +53,9 @@ def rel_vec_err(a, b, floor=1e-300):
     return np.linalg.norm(a - b, axis=0) / np.maximum(np.linalg.norm(b, axis=0), floor)
 
 
-def compare_leptons(gpu, orc, exclude, rtol_p, atol_s, rtol_x=None, what=""):
+def compare_leptons(gpu, orc, exclude, rtol_p, atol_s, rtol_x=None, what="", events=None):
+    """events: number of spin collapses behind the compared spins (default: one per particle);
+    the ill-conditioned collapse axis allows one spin in 1e5 collapses above atol_s."""
     xg, pg, sg = gpu
     xo, po, so = orc
     assert pg.shape == po.shape, f"{what}: count {pg.shape[1]} vs oracle {po.shape[1]}"
@@ -65,7 +67,8 @@ def compare_leptons(gpu, orc, exclude, rtol_p, atol_s, rtol_x=None, what=""):
                  s_over_tol=int((es > atol_s).sum()))
     assert worst["p"] <= rtol_p, f"{what}: momentum rel err {worst['p']:.3e} (argmax {int(np.argmax(ep))})"
     # the spin axis g/|g| of the collapse has the same conditioning as the photon axis
-    assert worst["s_over_tol"] <= max(1, es.size // 100_000) and worst["s"] <= 1e3 * atol_s, \
+    allowed = max(1, (es.size if events is None else events) // 100_000)
+    assert worst["s_over_tol"] <= allowed and worst["s"] <= 1e3 * atol_s, \
         f"{what}: spin err {worst['s']:.3e} (argmax {int(np.argmax(es))}, {worst['s_over_tol']} over tol)"
     if rtol_x is not None:
         ex = np.abs(xg[:, keep] - xo[:, keep]).max(axis=0) / np.maximum(np.abs(xo[:, keep]).max(axis=0), 1.0)
@@ -88,8 +91,9 @@ def photon_parent(ids):
         ((ids >> np.uint64(24)) & np.uint64((1 << 37) - 1)).astype(np.int64)
 
 
-def compare_photons(gpu, orc, excluded_parents, rtol_k, atol_P, what="", near_photons=None):
-    """Match live photons by id; ids absent on one side must belong to excluded parents."""
+def compare_photons(gpu, orc, excluded_parents, rtol_k, atol_P, what="", near_photons=None, outlier_rate=1e-5):
+    """Match live photons by id; ids absent on one side must belong to excluded parents.
+    outlier_rate: fraction of photons allowed above atol_P (ill-conditioned polarization axis)."""
     xg, kg, Pg, idg = gpu
     xo, ko, Po, ido = orc
     lg, lo = idg != 0, ido != 0
@@ -114,8 +118,8 @@ def compare_photons(gpu, orc, excluded_parents, rtol_k, atol_P, what="", near_ph
                  P_999999=float(np.quantile(eP, 0.999999)) if eP.size else 0.0)
     assert worst["k"] <= rtol_k, f"{what}: photon momentum rel err {worst['k']:.3e}"
     # The polarization axis F/|F| is ill-conditioned where the photon's polarization degree
-    # |F|/F0 is small (axis error ~ eps F0/|F|): at most 1 photon in 1e5 may exceed atol_P,
-    # and none may exceed 1e3 atol_P.
-    assert worst["P_over_tol"] <= max(1, eP.size // 100_000) and worst["P"] <= 1e3 * atol_P, \
+    # |F|/F0 is small (axis error ~ eps F0/|F|): at most a fraction outlier_rate (default 1e-5)
+    # of the photons may exceed atol_P, and none may exceed 1e3 atol_P.
+    assert worst["P_over_tol"] <= max(1, int(eP.size * outlier_rate)) and worst["P"] <= 1e3 * atol_P, \
         f"{what}: photon P-vector err {worst['P']:.3e} ({worst['P_over_tol']} over {atol_P:.1e})"
     return worst

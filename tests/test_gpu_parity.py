@@ -46,12 +46,12 @@ def gtab32(q):
     return q.Tables(precision=q.QED_F32)
 
 
-def _sim(q, tab, w, cap_e, cap_p, cap_g, flags, seed=None, k_retire=None, fields=None):
+def _sim(q, tab, w, cap_e, cap_p, cap_g, flags, seed=None, k_retire=None, fields=None, tau=False):
     from paper_2511_08929_amd.sim import Simulation
     f = fields or q.make_fields(w.field_kind, E0=w.E0, B0=w.B0, a0=w.a0, phase_len=w.phase_len)
     return Simulation(tab, cap_e=cap_e, cap_p=cap_p, cap_g=cap_g, track=w.track, fields=f, dt=w.dt, eps_r=EPS,
                       seed=w.seed if seed is None else seed, flags=flags,
-                      k_retire=w.k_retire if k_retire is None else k_retire)
+                      k_retire=w.k_retire if k_retire is None else k_retire, optical_depth=tau)
 
 
 def _random_leptons(n, seed, gmin=300.0, gmax=8000.0, mixed=True):
@@ -234,6 +234,54 @@ def test_c2_small_run_fp64(q, gtab64, otables):
     compare_leptons(sim.p.arrays(), ref["P"].arrays(), np.zeros(ref["P"].n, bool), tol_k(w.steps), tol_k(w.steps),
                     rtol_x=tol_k(w.steps), what="c2 positrons")
     print(compare_photons(sim.g.arrays(), ref["G"].arrays(), set(), tol_k(w.steps), tol_k(w.steps), what="c2 photons"))
+
+
+def test_optical_depth_runs_fp64(q, gtab64, otables):
+    """Optical-depth decision (FP64 tau, targets from Philox channel 4): the test-particle
+    workload for 300 steps and the head-on collision (both channels, pair-born leptons start
+    with no target) for 1200 steps; leptons, optical depths and photons compared."""
+    # test particle
+    w = synth.c1(n=1024)
+    flags = (q.QED_ALL & ~q.QED_PAIR) | q.QED_OPTICAL_DEPTH
+    steps = 300
+    sim = _sim(q, gtab64, w, w.n, 1, w.n * steps, flags, tau=True)
+    sim.e.load(w.x, w.p, w.s)
+    for _ in range(steps):
+        sim.step()
+    ref = oracle_run(otables, w, steps, flags, cap_g=w.n * steps, tau=True)
+    ex = ref["near_e"]
+    assert ex.sum() == 0
+    compare_leptons(sim.e.arrays(), ref["E"].arrays(), ex, tol_k(steps), tol_k(steps), what="tau c1 leptons",
+                    events=ref["ctr"]["n_emit"])
+    tg, tsg = sim.e.tau_arrays()
+    E = ref["E"]
+    assert np.abs(tg - E.tau[:E.n]).max() < 1e-12 * steps and np.abs(tsg - E.tau_target[:E.n]).max() < 1e-12
+    # without a draw per step the leptons spend more steps under the no-emission update, so more
+    # photons come from partially polarized parents, whose polarization axis is worse conditioned
+    wp = compare_photons(sim.g.arrays(), ref["G"].arrays(), set(), tol_k(steps), tol_k(steps), what="tau c1 photons",
+                         outlier_rate=1e-4)
+    print("tau c1 photons", wp)
+    assert q.counters_dict(sim.ctr)["n_emit"] == ref["ctr"]["n_emit"] > 0
+    # head-on collision
+    w = synth.subsample(synth.c2(), np.arange(300))
+    steps = 1200
+    flags = q.QED_ALL | q.QED_OPTICAL_DEPTH
+    sim = _sim(q, gtab64, w, w.n + 2000, 2000, 100_000, flags, tau=True)
+    sim.e.load(w.x, w.p, w.s)
+    for k in range(steps):
+        sim.step()
+        if (k + 1) % 200 == 0:
+            sim.compact()
+    ref = oracle_run(otables, w, steps, flags, cap_e=w.n + 2000, cap_p=2000, cap_g=100_000, tau=True)
+    assert ref["near_e"].sum() == 0 and ref["ctr"]["n_pair"] > 0, ref["ctr"]
+    compare_leptons(sim.e.arrays(), ref["E"].arrays(), np.zeros(ref["E"].n, bool), tol_k(steps), tol_k(steps),
+                    rtol_x=tol_k(steps), what="tau c2 electrons")
+    compare_leptons(sim.p.arrays(), ref["P"].arrays(), np.zeros(ref["P"].n, bool), tol_k(steps), tol_k(steps),
+                    rtol_x=tol_k(steps), what="tau c2 positrons")
+    for L, O in ((sim.e, ref["E"]), (sim.p, ref["P"])):
+        tg, tsg = L.tau_arrays()
+        assert np.abs(tg - O.tau[:O.n]).max() < 1e-12 * steps and np.abs(tsg - O.tau_target[:O.n]).max() < 1e-12
+    compare_photons(sim.g.arrays(), ref["G"].arrays(), set(), tol_k(steps), tol_k(steps), what="tau c2 photons")
 
 
 # ------------------------------------------------------------------ single precision

@@ -31,12 +31,12 @@ def tabs(q):
     return {"fp64": q.Tables(precision=q.QED_F64), "fp32": q.Tables(precision=q.QED_F32)}
 
 
-def _sim(q, tab, w, merged, cap_e, cap_p, cap_g, flags=None, ppb=0):
+def _sim(q, tab, w, merged, cap_e, cap_p, cap_g, flags=None, ppb=0, tau=False):
     from paper_2511_08929_amd.sim import Simulation
     f = q.make_fields(w.field_kind, E0=w.E0, B0=w.B0, a0=w.a0, phase_len=w.phase_len)
     sim = Simulation(tab, cap_e=cap_e, cap_p=cap_p, cap_g=cap_g, track=w.track, fields=f, dt=w.dt, eps_r=EPS,
                      seed=w.seed, flags=q.QED_ALL if flags is None else flags, k_retire=w.k_retire,
-                     device_clock=True, merged=merged, particles_per_block=ppb)
+                     device_clock=True, merged=merged, particles_per_block=ppb, optical_depth=tau)
     sim.e.load(w.x, w.p, w.s)
     return sim
 
@@ -74,6 +74,24 @@ def test_plan_equals_per_species_head_on(q, tabs, prec):
     print(prec, c)
     assert c["n_emit"] > 10_000 and c["n_pair"] > 0 and c["n_retired"] > 0
     assert int(a.clock.item()) == int(b.clock.item()) == 1000
+
+
+def test_plan_equals_per_species_optical_depth(q, tabs):
+    """Optical-depth decision in the merged step: 1500 electrons of the head-on collision, FP32,
+    tau and targets compared too."""
+    import torch
+    w = synth.subsample(synth.c2(), np.arange(1500))
+    flags = q.QED_ALL | q.QED_OPTICAL_DEPTH
+    a = _sim(q, tabs["fp32"], w, False, w.n + 3000, 3000, 120_000, flags, tau=True)
+    b = _sim(q, tabs["fp32"], w, True, w.n + 3000, 3000, 120_000, flags, tau=True)
+    for k in range(1, 1001):
+        a.step(); b.step()
+        if k % 50 == 0:
+            a.compact(); b.compact()
+    torch.cuda.synchronize()
+    _assert_same(_state(q, a) + a.e.tau_arrays() + a.p.tau_arrays(),
+                 _state(q, b) + b.e.tau_arrays() + b.p.tau_arrays(), "optical depth")
+    assert q.counters_dict(b.ctr)["n_pair"] > 0
 
 
 def test_plan_equals_per_species_dense_emission(q, tabs):

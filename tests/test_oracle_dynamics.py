@@ -322,3 +322,40 @@ def test_array_step_bookkeeping(otables):
     oracle.compact(G2)
     assert G2.n == live.size and G2.n_prev == live.size
     np.testing.assert_array_equal(G2.id[:G2.n], live)
+
+
+def test_optical_depth_decision_is_memoryless(otables):
+    """Optical-depth decision with a constant rate (recoil off, unpolarized electrons that stay
+    unpolarized, chi = 1 held by a pure B): tau restarts at 0 after each emission, so an emission in
+    a step is Bernoulli with probability 1 - exp(-W dt), independent of the past; the per-step
+    draw gives W dt.  W from scipy quadrature of scipy's Bessel functions."""
+    import os
+    import sys
+    sys.path.insert(0, os.path.dirname(__file__))
+    from test_oracle_special import _scipy_nlc_rate
+    w = synth.c1(n=20_000)
+    gamma = w.extra["gamma0"]
+    P = CE(gamma) * 0.5 * (_scipy_nlc_rate(1.0, 1.0) + _scipy_nlc_rate(1.0, -1.0)) * w.dt
+    base = oracle.F_PUSH | oracle.F_TBMT | oracle.F_EMIT
+    F = oracle.make_fields(w.field_kind, B0=w.B0)
+    for mode, expect in ((oracle.F_TAU, 1.0 - math.exp(-P)), (0, P)):
+        L = oracle.LeptonSet(0, w.n, track=w.track, tau=True)
+        L.set(w.x, w.p, np.zeros_like(w.s))
+        G = oracle.PhotonSet(w.n, track=w.track)
+        hist = []
+        for k in range(8):
+            prm = oracle.make_params(w.dt, EPS, step=k, t=k * w.dt, seed=5, flags=base | mode)
+            G.n = 0
+            oracle.lepton_step(otables, prm, F, L, G, oracle.Counters())
+            par = (G.id[:G.n] >> np.uint64(24)) & np.uint64((1 << 37) - 1)
+            e = np.zeros(w.n, bool)
+            e[par.astype(np.int64)] = True
+            hist.append(e)
+        h = np.array(hist)
+        sigma = math.sqrt(expect * (1 - expect) / h.size)
+        assert abs(h.mean() - expect) < 5 * sigma, (mode, h.mean(), expect)
+        if mode:
+            # independence of consecutive steps
+            both = (h[1:] & h[:-1]).mean()
+            assert abs(both - expect ** 2) < 5 * math.sqrt(expect ** 2 * (1 - expect ** 2) / h[1:].size)
+            assert np.all(L.tau[:w.n] >= 0) and np.all(L.tau_target[:w.n] > 0)
