@@ -246,9 +246,15 @@ typedef struct {
     qed_counters   *d_counters;  /* device, accumulated per instance */
 } qed_instance;
 
+typedef struct qed_surrogate_s *qed_surrogate;   /* opaque, library-owned; see below */
+
 typedef struct {
     int particles_per_block;     /* blocks of a set = ceil(capacity / this), default 256 */
     int max_blocks_per_set;      /* cap on the blocks of one set, default 2048 */
+    qed_surrogate icdf_nlc;      /* learned inverse CDF for the emission energy (NULL: tables); */
+    qed_surrogate icdf_nbw;      /* ... for the pair split.  Only with QED_F32 tables, and built on
+                                    the same tables (else QED_ERR_UNSUPPORTED / QED_ERR_INVALID).
+                                    The plan keeps a scratch of 16 bytes per particle slot. */
 } qed_plan_config;
 
 typedef struct qed_plan_s *qed_plan;   /* opaque, library-owned */
@@ -272,6 +278,50 @@ int64_t qed_plan_blocks(qed_plan plan);
 
 /* Synchronize the device and release the plan.  Safe on NULL. */
 qed_status qed_plan_destroy(qed_plan plan);
+
+/* ---------------------------------------------------------------------------------------
+   Learned inverse CDF.  The NLCS and NBW implementation sections tabulate the inverse CDF of
+   the photon (pair) energy only for the two spin (xi3) channels, because the full dependence
+   is too large to tabulate.  A surrogate is a small network nu(ln chi, rho, c), c = -1 / +1
+   (NLC: spin down / up; NBW: xi3 = -1 / +1), that stands in for the two tables of one process:
+   inputs u = (ln chi - m)/h (m, h: centre and half-width of the table's ln chi range),
+   v = rho/17 (rho = ln(r/(1-r)) of a 24-bit uniform, |rho| <= 16.64), c; four hidden layers of
+   64 SiLU units; output nu = 20 y.  12801 parameters in the flat order W1 (3x64, row = input),
+   b1, W2 (64x64, row = input unit), b2, W3, b3, W4, b4, W5 (64), b5.  Evaluation runs the 64x64
+   layers on the matrix cores in BF16 with FP32 accumulation (BF16 weights); the tables remain
+   the fallback and the judge of its error. */
+int64_t qed_surrogate_n_params(void);
+
+/* Allocate a surrogate for process 0 (NLC) or 1 (NBW) of these tables, parameters initialized
+   from Philox channel 7 with `seed` (uniform, variance 2 / fan-in).  Synchronizes the device. */
+qed_status qed_surrogate_create(qed_tables tables, int process, uint64_t seed, qed_surrogate *out);
+
+/* Normalization constants {m, h, rho scale, nu scale} (host array of 4). */
+qed_status qed_surrogate_norm(qed_surrogate s, float *out4);
+
+/* `steps` Adam steps (lr; betas 0.9, 0.999) on the mean squared error of y against nu/20, each
+   on 4 x 256 x tiles_per_wave x 16 fresh samples drawn from Philox channel 6: ln chi uniform over
+   the table range, rho half the time uniform over [-17, 17] and half the time logit(r) of a
+   uniform r (as in the sampling), c = +-1; targets nu from the tables.  d_loss (device,
+   `steps` floats, may be NULL) receives each step's mean squared error. */
+qed_status qed_surrogate_train(qed_surrogate s, int steps, int tiles_per_wave, float lr, float *d_loss,
+                               qed_stream stream);
+
+/* Gradient of sum_i (y_i - nu_i/20)^2 over n given samples (device: d_x[n][3] = ln chi, rho, c;
+   d_nu[n]) with respect to the parameters: d_grad[12801], then the sum of squares in
+   d_grad[12801].  n <= 16384.  For checks of the training kernels. */
+qed_status qed_surrogate_gradient(qed_surrogate s, const float *d_x, const float *d_nu, int64_t n,
+                                  float *d_grad, qed_stream stream);
+
+/* nu for n samples d_x[n][3] = (ln chi, rho, c) (device) into d_nu[n]. */
+qed_status qed_surrogate_eval(qed_surrogate s, const float *d_x, int64_t n, float *d_nu, qed_stream stream);
+
+/* Copy the FP32 parameters out of / into the surrogate (device arrays of 12801 floats). */
+qed_status qed_surrogate_get_params(qed_surrogate s, float *d_params, qed_stream stream);
+qed_status qed_surrogate_set_params(qed_surrogate s, const float *d_params, qed_stream stream);
+
+/* Synchronize the device and release the surrogate.  Safe on NULL. */
+qed_status qed_surrogate_destroy(qed_surrogate s);
 
 #ifdef __cplusplus
 }

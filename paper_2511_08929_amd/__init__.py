@@ -34,7 +34,9 @@ QED_FIELD_UNIFORM, QED_FIELD_PLANE_LP = 0, 1
 ABI_SYMBOLS = ("qed_init_tables", "qed_last_error", "qed_free_tables", "qed_tables_download", "qed_workspace_size",
                "qed_push_spin", "qed_emit", "qed_pair", "qed_compact_workspace_size", "qed_compact",
                "qed_profile_start", "qed_profile_stop", "qed_clock_advance", "qed_plan_create", "qed_plan_step",
-               "qed_plan_blocks", "qed_plan_destroy")
+               "qed_plan_blocks", "qed_plan_destroy", "qed_surrogate_n_params", "qed_surrogate_create",
+               "qed_surrogate_norm", "qed_surrogate_train", "qed_surrogate_gradient", "qed_surrogate_eval",
+               "qed_surrogate_get_params", "qed_surrogate_set_params", "qed_surrogate_destroy")
 
 
 class QedError(RuntimeError):
@@ -84,7 +86,8 @@ class Instance(C.Structure):
 
 
 class PlanConfig(C.Structure):
-    _fields_ = [("particles_per_block", C.c_int), ("max_blocks_per_set", C.c_int)]
+    _fields_ = [("particles_per_block", C.c_int), ("max_blocks_per_set", C.c_int), ("icdf_nlc", C.c_void_p),
+                ("icdf_nbw", C.c_void_p)]
 
 
 class KernelTime(C.Structure):
@@ -121,10 +124,21 @@ def lib():
         L.qed_plan_step.argtypes = [vp, vp]
         L.qed_plan_blocks.argtypes = [vp]; L.qed_plan_blocks.restype = i64
         L.qed_plan_destroy.argtypes = [vp]
+        f = C.c_float
+        L.qed_surrogate_n_params.argtypes = []; L.qed_surrogate_n_params.restype = i64
+        L.qed_surrogate_create.argtypes = [vp, C.c_int, C.c_uint64, P(vp)]
+        L.qed_surrogate_norm.argtypes = [vp, P(f)]
+        L.qed_surrogate_train.argtypes = [vp, C.c_int, C.c_int, f, vp, vp]
+        L.qed_surrogate_gradient.argtypes = [vp, vp, vp, i64, vp, vp]
+        L.qed_surrogate_eval.argtypes = [vp, vp, i64, vp, vp]
+        L.qed_surrogate_get_params.argtypes = [vp, vp, vp]
+        L.qed_surrogate_set_params.argtypes = [vp, vp, vp]
+        L.qed_surrogate_destroy.argtypes = [vp]
         L.qed_profile_start.argtypes = []
         L.qed_profile_stop.argtypes = [P(KernelTime), C.c_int, P(C.c_int)]
         for name in ABI_SYMBOLS:
-            if name not in ("qed_workspace_size", "qed_compact_workspace_size", "qed_last_error", "qed_plan_blocks"):
+            if name not in ("qed_workspace_size", "qed_compact_workspace_size", "qed_last_error", "qed_plan_blocks",
+                            "qed_surrogate_n_params"):
                 getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -374,7 +388,7 @@ class Plan:
     """qed_plan over instances given as (electrons, positrons, photons, fields, step params, counters).
     The buffers must stay alive (and unmoved) for the plan's lifetime; step params need d_clock."""
 
-    def __init__(self, tables: Tables, instances, particles_per_block=0, max_blocks_per_set=0):
+    def __init__(self, tables: Tables, instances, particles_per_block=0, max_blocks_per_set=0, surrogates=(None, None)):
         n = len(instances)
         arr = (Instance * n)()
         self._keep = []
@@ -388,7 +402,10 @@ class Plan:
             arr[j].params = step
             arr[j].d_counters = ctr.data_ptr()
             self._keep.append((e, p, g, ctr))
-        cfg = PlanConfig(particles_per_block, max_blocks_per_set)
+        cfg = PlanConfig(particles_per_block, max_blocks_per_set,
+                         surrogates[0].handle if surrogates[0] is not None else None,
+                         surrogates[1].handle if surrogates[1] is not None else None)
+        self._keep.append(surrogates)
         h = C.c_void_p()
         _check(lib().qed_plan_create(tables.handle, n, arr, C.byref(cfg), C.byref(h)), "qed_plan_create")
         self.handle = h
@@ -400,6 +417,70 @@ class Plan:
     def close(self):
         if self.handle:
             lib().qed_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Surrogate:
+    """qed_surrogate: the learned inverse CDF of one process (0 = NLC, 1 = NBW)."""
+
+    def __init__(self, tables: Tables, process, seed=1):
+        h = C.c_void_p()
+        _check(lib().qed_surrogate_create(tables.handle, process, seed, C.byref(h)), "qed_surrogate_create")
+        self.handle, self.tables, self.process = h, tables, process
+        self.n_params = int(lib().qed_surrogate_n_params())
+
+    def norm(self):
+        out = (C.c_float * 4)()
+        _check(lib().qed_surrogate_norm(self.handle, out), "qed_surrogate_norm")
+        return tuple(float(v) for v in out)
+
+    def train(self, steps, tiles_per_wave=2, lr=1e-3, stream=None):
+        """run `steps` Adam steps; returns the per-step mean squared errors (device tensor)"""
+        import torch
+        loss = torch.zeros(max(steps, 1), dtype=torch.float32, device="cuda")
+        _check(lib().qed_surrogate_train(self.handle, steps, tiles_per_wave, lr, _ptr(loss), _stream_ptr(stream)),
+               "qed_surrogate_train")
+        return loss[:steps]
+
+    def fit(self, schedule=((2e-3, 3000), (5e-4, 3000), (1e-4, 2000)), tiles_per_wave=1, stream=None):
+        """the standard training: Adam at piecewise-constant learning rates; returns the losses"""
+        import torch
+        return torch.cat([self.train(n, tiles_per_wave, lr, stream) for lr, n in schedule])
+
+    def gradient(self, x, nu, stream=None):
+        """gradient of sum (y - nu/20)^2 over the samples (x: (n, 3) float32 device, nu: (n,)); the
+        returned tensor has n_params + 1 entries, the last one the sum of squares"""
+        import torch
+        g = torch.zeros(self.n_params + 1, dtype=torch.float32, device="cuda")
+        _check(lib().qed_surrogate_gradient(self.handle, _ptr(x), _ptr(nu), x.shape[0], _ptr(g), _stream_ptr(stream)),
+               "qed_surrogate_gradient")
+        return g
+
+    def eval(self, x, stream=None):
+        import torch
+        nu = torch.empty(x.shape[0], dtype=torch.float32, device="cuda")
+        _check(lib().qed_surrogate_eval(self.handle, _ptr(x), x.shape[0], _ptr(nu), _stream_ptr(stream)),
+               "qed_surrogate_eval")
+        return nu
+
+    def get_params(self, stream=None):
+        import torch
+        p = torch.empty(self.n_params, dtype=torch.float32, device="cuda")
+        _check(lib().qed_surrogate_get_params(self.handle, _ptr(p), _stream_ptr(stream)), "qed_surrogate_get_params")
+        return p
+
+    def set_params(self, p, stream=None):
+        _check(lib().qed_surrogate_set_params(self.handle, _ptr(p), _stream_ptr(stream)), "qed_surrogate_set_params")
+
+    def close(self):
+        if self.handle:
+            lib().qed_surrogate_destroy(self.handle)
             self.handle = None
 
     def __del__(self):

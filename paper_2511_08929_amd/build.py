@@ -10,7 +10,7 @@ PKG = Path(__file__).resolve().parent
 CSRC = PKG / "csrc"
 INCLUDE = PKG.parent / "include"
 LIB = PKG / "libqedspin.so"
-SOURCES = ["qs_tables.hip", "qs_step.hip", "qs_plan.hip", "qs_profile.hip"]
+SOURCES = ["qs_tables.hip", "qs_step.hip", "qs_plan.hip", "qs_mlp.hip", "qs_profile.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC", "-shared",

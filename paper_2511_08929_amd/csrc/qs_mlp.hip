@@ -1,0 +1,389 @@
+// qs_mlp.hip -- training and evaluation of the learned inverse CDF (qed_surrogate_*).
+//
+// Training data come from the library's own inverse-CDF tables (FP64 interpolation, the same
+// lookup the table path uses): every step draws fresh samples (ln chi, rho, c) from Philox
+// channel 6 (ln chi uniform; rho half uniform, half distributed as in the sampling) and fits
+// y = nu/out_s by mean squared error with Adam.  The tables stay the fallback
+// and the judge of the network's error.
+//   k_mlp_grad   forward + backward of 16-row tiles per wave on the matrix cores; parameter
+//                gradients summed per block in LDS, written per block
+//   k_mlp_adam   sums the block gradients, Adam update of the FP32 master, BF16 copy
+//   k_mlp_image  BF16 copy of W2..W4 rearranged as MFMA B operands
+//   k_mlp_eval   nu for given (ln chi, rho, c)
+#include <math.h>
+#include <stdint.h>
+
+#include <vector>
+
+#include "qs_mlp.hpp"
+
+namespace {
+using namespace qs;
+using namespace qs::mlp;
+
+constexpr int kMlpBlock = 256;          // 4 waves
+constexpr int kGradGrid = 256;          // blocks of a training step
+constexpr int kAcc = kNP + 1;           // per-block record: gradient, then the summed squared error
+
+// normalized inputs (u, v, c) and target y of sample `id` of training step `step`
+__device__ inline void draw_sample(const MlpDev &M, const TablesDev &T, int proc, uint64_t seed, uint64_t id,
+                                   int64_t step, float xo[3], float &yo)
+{
+    // ln chi uniform over the table range; rho half the time uniform over its range, half the time
+    // rho = logit(r) of a uniform r, as in the sampling itself
+    const uint4 w = philox_block(seed, id, step, 6u);
+    const float u = 2.0f * u01_24(w.x) - 1.0f;
+    const float c = (w.z & 1u) ? 1.0f : -1.0f;
+    const double lnchi = (double)M.in_m + (double)M.in_h * (double)u;
+    const double r = (double)u01_24(w.y);
+    double rho = (w.z & 2u) ? log(r) - log1p(-r) : (double)M.rho_s * (2.0 * r - 1.0);
+    const float v = (float)(rho / (double)M.rho_s);
+    const double nu = icdf_nu(T, 2 * proc + (c > 0.0f ? 1 : 0), lnchi, rho);
+    xo[0] = u; xo[1] = v; xo[2] = c;
+    yo = (float)(nu / (double)M.out_s);
+}
+
+__device__ inline void normalize(const MlpDev &M, const float *xr, float xo[3])
+{
+    xo[0] = (xr[0] - M.in_m) / M.in_h;
+    xo[1] = xr[1] / M.rho_s;
+    xo[2] = xr[2] > 0.0f ? 1.0f : -1.0f;
+}
+
+// One training step's gradients.  xs/ys given (n samples, raw ln chi, rho, c and target nu):
+// the gradient of sum_i (y_i - nu_i/out_s)^2 over them; otherwise samples drawn from the tables.
+__global__ void __launch_bounds__(kMlpBlock) k_mlp_grad(MlpDev M, TablesDev T, int proc, const float *xs, const float *ys,
+                                                        int64_t n, uint64_t seed, int64_t step, int tiles_per_wave,
+                                                        float *acc_out)
+{
+    __shared__ float G[kAcc];
+    __shared__ MlpWave Wv[kMlpBlock / 64];
+    __shared__ float yt[kMlpBlock / 64][16];
+    __shared__ int ok[kMlpBlock / 64][16];
+    for (int i = threadIdx.x; i < kAcc; i += blockDim.x) G[i] = 0.0f;
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63, r = l & 15;
+    MlpWave &W = Wv[w];
+    __syncthreads();
+    for (int t = 0; t < tiles_per_wave; ++t) {
+        const int64_t tile = ((int64_t)blockIdx.x * (kMlpBlock / 64) + w) * tiles_per_wave + t;
+        if (l < 16) {
+            const int64_t id = tile * 16 + l;
+            float xo[3] = {0.0f, 0.0f, 1.0f}, yo = 0.0f;
+            int valid = 1;
+            if (xs) {
+                valid = id < n;
+                if (valid) {
+                    normalize(M, xs + 3 * id, xo);
+                    yo = ys[id] / M.out_s;
+                }
+            } else {
+                draw_sample(M, T, proc, seed, (uint64_t)id, step, xo, yo);
+            }
+            W.x[l][0] = xo[0]; W.x[l][1] = xo[1]; W.x[l][2] = xo[2];
+            yt[w][l] = yo;
+            ok[w][l] = valid;
+        }
+        __syncthreads();
+        const float y = mlp_forward(M, W);
+        const float e = ok[w][r] ? y - yt[w][r] : 0.0f;
+        if (l < 16) {
+            const float s = row_sum16(e * e);
+            if (l == 0) atomicAdd(&G[kNP], s);
+        }
+        mlp_backward(M, W, 2.0f * e, G);
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < kAcc; i += blockDim.x) acc_out[(int64_t)blockIdx.x * kAcc + i] = G[i];
+}
+
+// sum of the block records (gradient and squared error) into out[kAcc]
+__global__ void k_mlp_sum(const float *acc, int nblk, float *out)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= kAcc) return;
+    float s = 0.0f;
+    for (int b = 0; b < nblk; ++b) s += acc[(int64_t)b * kAcc + i];
+    out[i] = s;
+}
+
+// Adam (Kingma and Ba) on the mean gradient; loss[step] = mean squared error of the batch
+__global__ void k_mlp_adam(float *p, float *m1, float *m2, const float *acc, int nblk, float inv_count, float lr, int t,
+                           unsigned short *wt, float *loss)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i > kNP) return;
+    float g = 0.0f;
+    for (int b = 0; b < nblk; ++b) g += acc[(int64_t)b * kAcc + i];
+    g *= inv_count;
+    if (i == kNP) {
+        if (loss) loss[0] = g;
+        return;
+    }
+    const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
+    const float a = b1 * m1[i] + (1.0f - b1) * g, v = b2 * m2[i] + (1.0f - b2) * g * g;
+    m1[i] = a;
+    m2[i] = v;
+    const float ah = a / (1.0f - powf(b1, (float)t)), vh = v / (1.0f - powf(b2, (float)t));
+    const float x = p[i] - lr * ah / (sqrtf(vh) + eps);
+    p[i] = x;
+    wt[i] = f2bf(x);
+}
+
+__global__ void k_mlp_to_bf16(const float *p, unsigned short *wt)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < kNP) wt[i] = f2bf(p[i]);
+}
+
+// img[(L-2)*1024 + (kb*4 + nb)*64 + lane][j] = W_L[k = kb*16 + 4(lane/16) + j][n = nb*16 + lane%16]
+__global__ void k_mlp_image(const unsigned short *wt, bf16x4 *img)
+{
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= kImg) return;
+    const int L = 2 + e / 1024, kbnb = (e % 1024) / 64, lane = e % 64;
+    const int kb = kbnb / 4, nb = kbnb % 4;
+    bf16x4 v;
+    for (int j = 0; j < 4; ++j)
+        v[j] = (short)wt[kW(L) + (kb * 16 + 4 * (lane / 16) + j) * kH + nb * 16 + (lane % 16)];
+    img[e] = v;
+}
+
+// nu for n samples given as raw (ln chi, rho, c); every wave takes 16-row tiles, block-uniformly
+__global__ void __launch_bounds__(kMlpBlock) k_mlp_eval(MlpDev M, const float *xs, int64_t n, float *nu)
+{
+    __shared__ MlpWave Wv[kMlpBlock / 64];
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+    MlpWave &W = Wv[w];
+    const int64_t ntiles = cdiv(n, 16);
+    for (int64_t t0 = (int64_t)blockIdx.x * (kMlpBlock / 64); t0 < ntiles; t0 += (int64_t)gridDim.x * (kMlpBlock / 64)) {
+        const int64_t tile = t0 + w;
+        const int64_t id = tile * 16 + (l & 15);
+        if (l < 16) {
+            float xo[3] = {0.0f, 0.0f, 1.0f};
+            if (id < n) normalize(M, xs + 3 * id, xo);
+            W.x[l][0] = xo[0]; W.x[l][1] = xo[1]; W.x[l][2] = xo[2];
+        }
+        __syncthreads();
+        const float y = mlp_forward(M, W);
+        if (l < 16 && id < n) nu[id] = M.out_s * y;
+        __syncthreads();
+    }
+}
+
+// nu for the samples with global ranks [gpre[b_lo], gpre[b_hi]) (bounds read on the device)
+__global__ void __launch_bounds__(kMlpBlock) k_mlp_eval_ranks(MlpDev M, const float *xs, const uint32_t *gpre, int b_lo,
+                                                              int b_hi, float *nu)
+{
+    __shared__ MlpWave Wv[kMlpBlock / 64];
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+    MlpWave &W = Wv[w];
+    const int64_t lo = gpre[b_lo], hi = gpre[b_hi];
+    const int64_t ntiles = cdiv(hi - lo, 16);
+    for (int64_t t0 = (int64_t)blockIdx.x * (kMlpBlock / 64); t0 < ntiles; t0 += (int64_t)gridDim.x * (kMlpBlock / 64)) {
+        const int64_t id = lo + (t0 + w) * 16 + (l & 15);
+        if (l < 16) {
+            float xo[3] = {0.0f, 0.0f, 1.0f};
+            if (id < hi) normalize(M, xs + 3 * id, xo);
+            W.x[l][0] = xo[0]; W.x[l][1] = xo[1]; W.x[l][2] = xo[2];
+        }
+        __syncthreads();
+        const float y = mlp_forward(M, W);
+        if (l < 16 && id < hi) nu[id] = M.out_s * y;
+        __syncthreads();
+    }
+}
+
+}  // namespace
+
+struct qed_surrogate_s {
+    qed_tables T;
+    int proc;
+    uint64_t seed;
+    int64_t steps_done;
+    float *p, *m1, *m2, *acc, *loss_tmp;
+    unsigned short *wt;
+    bf16x4 *img;
+    float in_m, in_h, rho_s, out_s;
+};
+
+namespace {
+MlpDev mlp_dev(const qed_surrogate_s *s)
+{
+    MlpDev M;
+    M.p = s->p;
+    M.wt = s->wt;
+    M.img = s->img;
+    M.in_m = s->in_m; M.in_h = s->in_h; M.rho_s = s->rho_s; M.out_s = s->out_s;
+    return M;
+}
+
+qed_status refresh_bf16(qed_surrogate s, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_mlp_to_bf16, dim3((kNP + 255) / 256), dim3(256), 0, st, (const float *)s->p, s->wt);
+    hipLaunchKernelGGL(k_mlp_image, dim3((kImg + 255) / 256), dim3(256), 0, st, (const unsigned short *)s->wt, s->img);
+    return qs_launch_status("surrogate parameters");
+}
+
+void surrogate_free(qed_surrogate s)
+{
+    if (!s) return;
+    (void)hipFree(s->p); (void)hipFree(s->m1); (void)hipFree(s->m2); (void)hipFree(s->acc);
+    (void)hipFree(s->loss_tmp); (void)hipFree(s->wt); (void)hipFree(s->img);
+    delete s;
+}
+}  // namespace
+
+// device view for the step kernels (qs_plan.hip)
+MlpDev qs_surrogate_view(const qed_surrogate_s *s) { return mlp_dev(s); }
+int qs_surrogate_process(const qed_surrogate_s *s) { return s->proc; }
+const qed_tables_s *qs_surrogate_tables(const qed_surrogate_s *s) { return s->T; }
+
+// the learned nu of the transitions with global ranks [gpre[b_lo], gpre[b_hi]) of a plan step
+void qs_surrogate_eval_ranks(const qed_surrogate_s *s, const float *xs, const uint32_t *gpre, int b_lo, int b_hi,
+                             float *nu, hipStream_t st)
+{
+    QS_LAUNCH(K_SURROGATE, k_mlp_eval_ranks, dim3(1024), dim3(kMlpBlock), 0, st, mlp_dev(s), xs, gpre, b_lo, b_hi, nu);
+}
+
+extern "C" int64_t qed_surrogate_n_params(void) { return kNP; }
+
+extern "C" qed_status qed_surrogate_create(qed_tables T, int process, uint64_t seed, qed_surrogate *out)
+{
+    if (!T || !out || (process != 0 && process != 1)) return QED_ERR_INVALID;
+    *out = nullptr;
+    qs_clear_error();
+    qed_surrogate s = new qed_surrogate_s();
+    memset(s, 0, sizeof(*s));
+    s->T = T;
+    s->proc = process;
+    s->seed = seed;
+    const qed_table_grid &g = T->params.grid;
+    const double lo = g.lnchi0[process], hi = g.lnchi0[process] + (g.n_chi[process] - 1) * g.dlnchi[process];
+    s->in_m = (float)(0.5 * (lo + hi));
+    s->in_h = (float)(0.5 * (hi - lo));
+    s->rho_s = 17.0f;        // 24-bit uniforms: |rho| <= ln(2^24) = 16.64
+    s->out_s = 20.0f;
+    // He-style initialization from Philox channel 7 (uniform with the variance 2 / fan_in)
+    std::vector<float> p(kNP, 0.0f);
+    auto fill = [&](int off, int fan_in, int count) {
+        const float a = sqrtf(6.0f / (float)fan_in);
+        uint32_t w[4];
+        for (int i = 0; i < count; i += 4) {
+            // host Philox: same definition as the device one
+            uint32_t c0 = (uint32_t)(off + i), c1 = 0u, c2 = 0u, c3 = 7u, k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
+            for (int rr = 0; rr < 10; ++rr) {
+                const uint64_t m0 = (uint64_t)0xD2511F53u * c0, m1 = (uint64_t)0xCD9E8D57u * c2;
+                const uint32_t n0 = (uint32_t)(m1 >> 32) ^ c1 ^ k0, n2 = (uint32_t)(m0 >> 32) ^ c3 ^ k1;
+                c0 = n0; c1 = (uint32_t)m1; c2 = n2; c3 = (uint32_t)m0;
+                k0 += 0x9E3779B9u; k1 += 0xBB67AE85u;
+            }
+            w[0] = c0; w[1] = c1; w[2] = c2; w[3] = c3;
+            for (int j = 0; j < 4 && i + j < count; ++j)
+                p[off + i + j] = a * (2.0f * ((float)(w[j] >> 8) + 0.5f) * 0x1p-24f - 1.0f);
+        }
+    };
+    fill(kW1, 3, 3 * kH);
+    for (int L = 2; L <= 4; ++L) fill(kW(L), kH, kH * kH);
+    fill(kW5, kH, kH);
+    hipError_t e = hipMalloc((void **)&s->p, sizeof(float) * kNP);
+    if (e == hipSuccess) e = hipMalloc((void **)&s->m1, sizeof(float) * kNP);
+    if (e == hipSuccess) e = hipMalloc((void **)&s->m2, sizeof(float) * kNP);
+    if (e == hipSuccess) e = hipMalloc((void **)&s->acc, sizeof(float) * kAcc * kGradGrid);
+    if (e == hipSuccess) e = hipMalloc((void **)&s->loss_tmp, sizeof(float) * kAcc);
+    if (e == hipSuccess) e = hipMalloc((void **)&s->wt, sizeof(unsigned short) * kNP);
+    if (e == hipSuccess) e = hipMalloc((void **)&s->img, sizeof(bf16x4) * kImg);
+    if (e == hipSuccess) e = hipMemcpy(s->p, p.data(), sizeof(float) * kNP, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemset(s->m1, 0, sizeof(float) * kNP);
+    if (e == hipSuccess) e = hipMemset(s->m2, 0, sizeof(float) * kNP);
+    if (e != hipSuccess) {
+        surrogate_free(s);
+        return qs_fail(e, "qed_surrogate_create");
+    }
+    qed_status st = refresh_bf16(s, nullptr);
+    if (st == QED_OK && (e = hipDeviceSynchronize()) != hipSuccess) st = qs_fail(e, "qed_surrogate_create");
+    if (st != QED_OK) {
+        surrogate_free(s);
+        return st;
+    }
+    *out = s;
+    return QED_OK;
+}
+
+extern "C" qed_status qed_surrogate_norm(qed_surrogate s, float *out4)
+{
+    if (!s || !out4) return QED_ERR_INVALID;
+    out4[0] = s->in_m; out4[1] = s->in_h; out4[2] = s->rho_s; out4[3] = s->out_s;
+    return QED_OK;
+}
+
+extern "C" qed_status qed_surrogate_train(qed_surrogate s, int steps, int tiles_per_wave, float lr, float *d_loss,
+                                          qed_stream stream)
+{
+    if (!s || steps < 0 || tiles_per_wave <= 0 || !(lr > 0.0f)) return QED_ERR_INVALID;
+    hipStream_t st = (hipStream_t)stream;
+    qs_clear_error();
+    const MlpDev M = mlp_dev(s);
+    const float inv = 1.0f / (float)((int64_t)kGradGrid * (kMlpBlock / 64) * tiles_per_wave * 16);
+    for (int k = 0; k < steps; ++k) {
+        const int64_t t = ++s->steps_done;
+        hipLaunchKernelGGL(k_mlp_grad, dim3(kGradGrid), dim3(kMlpBlock), 0, st, M, s->T->dev, s->proc, (const float *)nullptr,
+                           (const float *)nullptr, (int64_t)0, s->seed, t, tiles_per_wave, s->acc);
+        hipLaunchKernelGGL(k_mlp_adam, dim3((kAcc + 255) / 256), dim3(256), 0, st, s->p, s->m1, s->m2, (const float *)s->acc,
+                           kGradGrid, inv, lr, (int)t, s->wt, d_loss ? d_loss + k : (float *)nullptr);
+        hipLaunchKernelGGL(k_mlp_image, dim3((kImg + 255) / 256), dim3(256), 0, st, (const unsigned short *)s->wt, s->img);
+    }
+    return qs_launch_status("qed_surrogate_train");
+}
+
+extern "C" qed_status qed_surrogate_gradient(qed_surrogate s, const float *d_x, const float *d_nu, int64_t n,
+                                             float *d_grad, qed_stream stream)
+{
+    if (!s || !d_x || !d_nu || !d_grad || n <= 0) return QED_ERR_INVALID;
+    hipStream_t st = (hipStream_t)stream;
+    qs_clear_error();
+    const int64_t tiles = cdiv(n, 16);
+    const int64_t blocks = cdiv(tiles, kMlpBlock / 64);
+    if (blocks > kGradGrid) return QED_ERR_CAPACITY;
+    hipLaunchKernelGGL(k_mlp_grad, dim3((int)blocks), dim3(kMlpBlock), 0, st, mlp_dev(s), s->T->dev, s->proc, d_x, d_nu, n,
+                       s->seed, (int64_t)0, 1, s->acc);
+    hipLaunchKernelGGL(k_mlp_sum, dim3((kAcc + 255) / 256), dim3(256), 0, st, (const float *)s->acc, (int)blocks, d_grad);
+    return qs_launch_status("qed_surrogate_gradient");
+}
+
+extern "C" qed_status qed_surrogate_eval(qed_surrogate s, const float *d_x, int64_t n, float *d_nu, qed_stream stream)
+{
+    if (!s || !d_x || !d_nu || n < 0) return QED_ERR_INVALID;
+    if (n == 0) return QED_OK;
+    hipStream_t st = (hipStream_t)stream;
+    qs_clear_error();
+    const int64_t blocks = cdiv(cdiv(n, 16), kMlpBlock / 64);
+    hipLaunchKernelGGL(k_mlp_eval, dim3((int)(blocks < 4096 ? blocks : 4096)), dim3(kMlpBlock), 0, st, mlp_dev(s), d_x, n,
+                       d_nu);
+    return qs_launch_status("qed_surrogate_eval");
+}
+
+extern "C" qed_status qed_surrogate_get_params(qed_surrogate s, float *d_params, qed_stream stream)
+{
+    if (!s || !d_params) return QED_ERR_INVALID;
+    qs_clear_error();
+    QS_CHECK(hipMemcpyAsync(d_params, s->p, sizeof(float) * kNP, hipMemcpyDeviceToDevice, (hipStream_t)stream));
+    return QED_OK;
+}
+
+extern "C" qed_status qed_surrogate_set_params(qed_surrogate s, const float *d_params, qed_stream stream)
+{
+    if (!s || !d_params) return QED_ERR_INVALID;
+    hipStream_t st = (hipStream_t)stream;
+    qs_clear_error();
+    QS_CHECK(hipMemcpyAsync(s->p, d_params, sizeof(float) * kNP, hipMemcpyDeviceToDevice, st));
+    return refresh_bf16(s, st);
+}
+
+extern "C" qed_status qed_surrogate_destroy(qed_surrogate s)
+{
+    if (s) {
+        (void)hipDeviceSynchronize();
+        surrogate_free(s);
+    }
+    return QED_OK;
+}

@@ -368,10 +368,12 @@ __device__ __forceinline__ void lepton_range(const LepDev<R> &L, const FieldDev 
 
 // Emitter processing (NLC section, after the decision): lambda from the selected inverse CDF,
 // recoil, spin collapse, Stokes collapse, P-vector; the photon goes to slot `slot` (< 0: no room).
+// With x_out set, only the inputs of the inverse CDF (ln chi, rho, channel sign) are written there;
+// with nu_in set, nu is taken from it instead of the table (learned inverse CDF).
 template <class R>
 __device__ __forceinline__ void emit_item(const LepDev<R> &L, const PhoDev<R> &G, const FieldDev &F, const StepDev &S,
                                           const TablesDev &T, const R *lds, int64_t i, bool up, int64_t slot,
-                                          unsigned &c_ret)
+                                          unsigned &c_ret, const float *nu_in = nullptr, float *x_out = nullptr)
 {
     const V3<R> x = ldx(L.x, i);
     V3<R> p = ld3(L.p, i), s = ld3(L.s, i);
@@ -380,7 +382,13 @@ __device__ __forceinline__ void emit_item(const LepDev<R> &L, const PhoDev<R> &G
     const LDecide<R> d = lepton_decide<R>(S, T, lds, L.species, i, p, s, E, B);
     const double r2 = (double)d.r2;
     const double rho = log(r2) - log1p(-r2);
-    const double nu = icdf_nu(T, up ? 1 : 0, log(d.chi), rho);
+    if (x_out) {
+        x_out[0] = (float)log(d.chi);
+        x_out[1] = (float)rho;
+        x_out[2] = up ? 1.0f : -1.0f;
+        return;
+    }
+    const double nu = nu_in ? (double)*nu_in : icdf_nu(T, up ? 1 : 0, log(d.chi), rho);
     const double lam_d = 1.0 / (1.0 + exp(-nu)), oml_d = 1.0 / (1.0 + exp(nu));
     const double u_d = lam_d / oml_d;
     const V3<R> k = (R)lam_d * p;
@@ -550,7 +558,7 @@ __device__ __forceinline__ void photon_tile(const PhoDev<R> &G, const FieldDev &
 template <class R>
 __device__ __forceinline__ void pair_item(const PhoDev<R> &G, const LepDev<R> &Le, const LepDev<R> &Lp, const FieldDev &F,
                                           const StepDev &S, const TablesDev &T, const R *lds, int64_t i, bool plus,
-                                          int64_t se, int64_t sp)
+                                          int64_t se, int64_t sp, const float *nu_in = nullptr, float *x_out = nullptr)
 {
     const uint64_t id = G.id[i];
     const V3<R> k = ld3(G.k, i), x = ldx(G.x, i), P = ld3(G.P, i);
@@ -559,7 +567,14 @@ __device__ __forceinline__ void pair_item(const PhoDev<R> &G, const LepDev<R> &L
     eval_fields<R>(F, (double)x.x, S.t + S.dt, E, B);
     const PDecide<R> d = photon_decide<R>(S, T, lds, id, k, k0, P, E, B);
     const double r2 = (double)d.r2;
-    const double nu = icdf_nu(T, plus ? 3 : 2, log(d.chi), log(r2) - log1p(-r2));
+    const double rho = log(r2) - log1p(-r2);
+    if (x_out) {
+        x_out[0] = (float)log(d.chi);
+        x_out[1] = (float)rho;
+        x_out[2] = plus ? 1.0f : -1.0f;
+        return;
+    }
+    const double nu = nu_in ? (double)*nu_in : icdf_nu(T, plus ? 3 : 2, log(d.chi), rho);
     const double lam_d = 1.0 / (1.0 + exp(-nu)), oml_d = 1.0 / (1.0 + exp(nu));
     const V3<R> pp = (R)lam_d * k, pe = (R)oml_d * k;
     V3<R> ec = {0, 0, 0}, pc = {0, 0, 0};

@@ -23,7 +23,7 @@
 // bit for bit, as qed_emit(electrons), qed_emit(positrons), qed_pair, qed_clock_advance.
 #include <vector>
 
-#include "qs_pass.hpp"
+#include "qs_mlp.hpp"
 
 namespace {
 using namespace qs;
@@ -60,6 +60,7 @@ struct PlanDev {
     uint32_t *gpre;            // [nblk + 1] exclusive prefix of bcnt in grid order
     SegBook *sbook;            // [nseg]
     int64_t *clock_used;       // [ninst] step clock of the last main pass
+    float *sx, *snu;           // learned inverse CDF: inputs [3] and nu per global transition rank
 };
 
 __device__ __forceinline__ int seg_of(const SegDev *seg, int nseg, int b)
@@ -234,8 +235,11 @@ __global__ void __launch_bounds__(kBlock) k_plan_main(const InstDev<R> *inst, Pl
 
 constexpr int kExpandWords = 64;   // mask words expanded per round of the process pass (4096 slots)
 
+// mode 0: tables; 1: write the inverse-CDF inputs of every transition (learned inverse CDF);
+// 2: finish the transitions with the learned nu
 template <class R, int PHO>
-__global__ void __launch_bounds__(kBlock) k_plan_process(const InstDev<R> *inst, PlanDev P, TablesDev T, int b_first)
+__global__ void __launch_bounds__(kBlock) k_plan_process(const InstDev<R> *inst, PlanDev P, TablesDev T, int b_first,
+                                                         int mode)
 {
     extern __shared__ unsigned char smem_raw[];
     R *lds = reinterpret_cast<R *>(smem_raw);
@@ -287,11 +291,15 @@ __global__ void __launch_bounds__(kBlock) k_plan_process(const InstDev<R> *inst,
         for (uint32_t j = threadIdx.x; j < nl; j += blockDim.x) {
             const int64_t i = c0 * 64 + list[j];
             const int64_t r = rank0 + j;
+            const int64_t gr = (int64_t)P.gpre[sg.b0] + r;            // global transition rank
             const bool br = (mask[sg.nchunks + (i >> 6)] >> (i & 63)) & 1ull;
+            const float *nu_in = mode == 2 ? P.snu + gr : nullptr;
+            float *x_out = mode == 1 ? P.sx + 3 * gr : nullptr;
             if (!PHO)
-                emit_item<R>(sg.kind == 0 ? E : Pp, G, F, S, T, lds, i, br, r < bk.nfit ? bk.base + r : -1, c_ret);
+                emit_item<R>(sg.kind == 0 ? E : Pp, G, F, S, T, lds, i, br, r < bk.nfit ? bk.base + r : -1, c_ret, nu_in,
+                             x_out);
             else
-                pair_item<R>(G, E, Pp, F, S, T, lds, i, br, r < bk.nfit ? bk.base + r : -1, bk.base2 + r);
+                pair_item<R>(G, E, Pp, F, S, T, lds, i, br, r < bk.nfit ? bk.base + r : -1, bk.base2 + r, nu_in, x_out);
         }
         rank0 += nl;
         __syncthreads();
@@ -311,6 +319,8 @@ struct qed_plan_s {
     SegBook *d_sbook;
     int64_t *d_clock_used;
     uint32_t *d_bctr;
+    float *d_sx, *d_snu;
+    qed_surrogate sur[2];      // learned inverse CDF per process (NULL: tables)
     size_t lds;
 };
 
@@ -341,11 +351,14 @@ void plan_free(qed_plan p)
     (void)hipFree(p->d_sbook);
     (void)hipFree(p->d_clock_used);
     (void)hipFree(p->d_bctr);
+    (void)hipFree(p->d_sx);
+    (void)hipFree(p->d_snu);
     delete p;
 }
 
 template <class R>
-qed_status plan_create(qed_tables T, int n, const qed_instance *in, int ppb, int maxb, qed_plan *out)
+qed_status plan_create(qed_tables T, int n, const qed_instance *in, int ppb, int maxb, qed_surrogate s_nlc,
+                       qed_surrogate s_nbw, qed_plan *out)
 {
     std::vector<InstDev<R>> inst(n);
     std::vector<SegDev> seg;
@@ -390,6 +403,15 @@ qed_status plan_create(qed_tables T, int n, const qed_instance *in, int ppb, int
     if (e == hipSuccess) e = hipMalloc((void **)&p->d_sbook, sizeof(SegBook) * seg.size());
     if (e == hipSuccess) e = hipMalloc((void **)&p->d_clock_used, sizeof(int64_t) * n);
     if (e == hipSuccess) e = hipMalloc((void **)&p->d_bctr, sizeof(uint32_t) * kNCtr * nblk);
+    p->sur[0] = s_nlc;
+    p->sur[1] = s_nbw;
+    if (s_nlc || s_nbw) {
+        // one record per possible transition: every slot of every set
+        int64_t slots = 0;
+        for (const SegDev &sg : seg) slots += sg.nchunks * 64;
+        if (e == hipSuccess) e = hipMalloc((void **)&p->d_sx, sizeof(float) * 3 * slots);
+        if (e == hipSuccess) e = hipMalloc((void **)&p->d_snu, sizeof(float) * slots);
+    }
     if (e == hipSuccess) e = hipMemcpy(p->d_inst, inst.data(), sizeof(InstDev<R>) * n, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(p->d_seg, seg.data(), sizeof(SegDev) * seg.size(), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemset(p->d_gpre, 0, sizeof(uint32_t) * (nblk + 1));
@@ -415,6 +437,8 @@ template <class R> qed_status plan_step(qed_plan p, hipStream_t st)
     P.sbook = p->d_sbook;
     P.clock_used = p->d_clock_used;
     P.bctr = p->d_bctr;
+    P.sx = p->d_sx;
+    P.snu = p->d_snu;
     const InstDev<R> *inst = (const InstDev<R> *)p->d_inst;
     if (p->nblk_lep > 0)
         QS_LAUNCH(K_PLAN_LEPTON, (k_plan_main<R, 0>), dim3(p->nblk_lep), dim3(kBlock), p->lds, st, inst, P, p->T->dev, 0);
@@ -422,12 +446,23 @@ template <class R> qed_status plan_step(qed_plan p, hipStream_t st)
         QS_LAUNCH(K_PLAN_PHOTON, (k_plan_main<R, 1>), dim3(p->nblk - p->nblk_lep), dim3(kBlock), p->lds, st, inst, P,
                   p->T->dev, p->nblk_lep);
     QS_LAUNCH(K_BOOK, k_plan_book<R>, dim3(1 + (int)cdiv(p->nblk, kCtrGroup)), dim3(kBlock), 0, st, inst, P);
-    if (p->nblk_lep > 0)
-        QS_LAUNCH(K_PLAN_PROCESS, (k_plan_process<R, 0>), dim3(p->nblk_lep), dim3(kBlock), p->lds, st, inst, P,
-                  p->T->dev, 0);
-    if (p->nblk > p->nblk_lep)
-        QS_LAUNCH(K_PLAN_PROCESS, (k_plan_process<R, 1>), dim3(p->nblk - p->nblk_lep), dim3(kBlock), p->lds, st, inst,
-                  P, p->T->dev, p->nblk_lep);
+    // processing: with a learned inverse CDF, a first pass writes its inputs, the network runs on
+    // the dense list of transitions, and a second pass finishes them with its nu
+    const bool sl = p->sur[0] != nullptr, sp = p->sur[1] != nullptr;
+    const bool has_l = p->nblk_lep > 0, has_g = p->nblk > p->nblk_lep;
+    const int nl = p->nblk_lep, ng = p->nblk - p->nblk_lep;
+    if (has_l)
+        QS_LAUNCH(K_PLAN_PROCESS, (k_plan_process<R, 0>), dim3(nl), dim3(kBlock), p->lds, st, inst, P, p->T->dev, 0,
+                  sl ? 1 : 0);
+    if (has_g)
+        QS_LAUNCH(K_PLAN_PROCESS, (k_plan_process<R, 1>), dim3(ng), dim3(kBlock), p->lds, st, inst, P, p->T->dev, nl,
+                  sp ? 1 : 0);
+    if (has_l && sl) qs_surrogate_eval_ranks(p->sur[0], P.sx, P.gpre, 0, nl, P.snu, st);
+    if (has_g && sp) qs_surrogate_eval_ranks(p->sur[1], P.sx, P.gpre, nl, p->nblk, P.snu, st);
+    if (has_l && sl)
+        QS_LAUNCH(K_PLAN_PROCESS, (k_plan_process<R, 0>), dim3(nl), dim3(kBlock), p->lds, st, inst, P, p->T->dev, 0, 2);
+    if (has_g && sp)
+        QS_LAUNCH(K_PLAN_PROCESS, (k_plan_process<R, 1>), dim3(ng), dim3(kBlock), p->lds, st, inst, P, p->T->dev, nl, 2);
     return qs_launch_status("qed_plan_step");
 }
 
@@ -454,9 +489,14 @@ extern "C" qed_status qed_plan_create(qed_tables T, int n_instances, const qed_i
         if (!instance_ok(&instances[i])) return QED_ERR_INVALID;
     const int ppb = config && config->particles_per_block > 0 ? config->particles_per_block : kBlock;
     const int maxb = config && config->max_blocks_per_set > 0 ? config->max_blocks_per_set : kMaxGrid;
+    qed_surrogate sn = config ? config->icdf_nlc : nullptr, sb = config ? config->icdf_nbw : nullptr;
+    // the networks are trained for 24-bit uniforms (single precision) on these tables' ranges
+    if ((sn || sb) && T->params.precision != QED_F32) return QED_ERR_UNSUPPORTED;
+    if (sn && (qs_surrogate_process(sn) != 0 || qs_surrogate_tables(sn) != T)) return QED_ERR_INVALID;
+    if (sb && (qs_surrogate_process(sb) != 1 || qs_surrogate_tables(sb) != T)) return QED_ERR_INVALID;
     qs_clear_error();
-    if (T->params.precision == QED_F64) return plan_create<double>(T, n_instances, instances, ppb, maxb, out);
-    return plan_create<float>(T, n_instances, instances, ppb, maxb, out);
+    if (T->params.precision == QED_F64) return plan_create<double>(T, n_instances, instances, ppb, maxb, sn, sb, out);
+    return plan_create<float>(T, n_instances, instances, ppb, maxb, sn, sb, out);
 }
 
 extern "C" qed_status qed_plan_step(qed_plan plan, qed_stream stream)

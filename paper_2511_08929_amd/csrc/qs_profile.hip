@@ -19,7 +19,7 @@ hipEvent_t g_open = nullptr;
 
 const char *const kNames[K_NKERNELS] = {"table_build", "push", "lepton_main", "emit_process", "photon_main",
                                         "pair_process", "mask_reduce", "book", "expand", "clock",
-                                        "alive_mask", "gather", "scatter_back", "plan_lepton", "plan_photon", "plan_process"};
+                                        "alive_mask", "gather", "scatter_back", "plan_lepton", "plan_photon", "plan_process", "surrogate"};
 
 hipEvent_t take()
 {

@@ -23,7 +23,7 @@ class Simulation:
     def __init__(self, tables: Tables, *, cap_e, cap_p, cap_g, track, fields, dt, eps_r, seed, flags,
                  k_retire=0.0, t0=0.0, a_e=ALPHA / (2 * math.pi), chi_e_min=1e-3, chi_e_max=1e2, chi_g_min=0.05,
                  chi_g_max=1e2, device="cuda", device_clock=False, merged=False, particles_per_block=0,
-                 optical_depth=False):
+                 optical_depth=False, surrogates=(None, None)):
         import torch
         self.tables = tables
         self.dtype = torch.float64 if tables.precision == QED_F64 else torch.float32
@@ -40,8 +40,10 @@ class Simulation:
         self.chi = (chi_e_min, chi_e_max, chi_g_min, chi_g_max)
         self.n = 0
         self._sp = None
+        merged = merged or any(x is not None for x in surrogates)     # the learned inverse CDF runs in plans
         self.clock = torch.zeros(1, dtype=torch.int64, device=device) if (device_clock or merged) else None
         self.merged, self.ppb = merged, particles_per_block
+        self.surrogates = surrogates
         self.plan = None
 
     def step_params(self, n):
@@ -64,7 +66,7 @@ class Simulation:
     def _ensure_plan(self):
         if self.merged and self.plan is None:
             self.plan = Plan(self.tables, [(self.e, self.p, self.g, self.fields, self._params(), self.ctr)],
-                             particles_per_block=self.ppb)
+                             particles_per_block=self.ppb, surrogates=self.surrogates)
 
     def _enqueue_step(self, stream=None):
         if self.merged:

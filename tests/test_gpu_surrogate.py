@@ -1,0 +1,172 @@
+"""The learned inverse CDF (qed_surrogate_*): the GPU training kernels' gradients against the FP64
+reference network (oracle/mlp.py, itself pinned by finite differences), the trained network's
+error against the inverse-CDF tables it stands in for, its memory against theirs, and the merged
+step with it (same decisions, photon energies within the stated error, replayable in a graph)."""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import mlp
+
+pytestmark = pytest.mark.gpu
+
+EPS = synth.EPS_R
+
+
+@pytest.fixture(scope="module")
+def q():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2511_08929_amd as q
+    return q
+
+
+@pytest.fixture(scope="module")
+def t32(q):
+    return q.Tables(precision=q.QED_F32)
+
+
+@pytest.fixture(scope="module")
+def trained(q, t32):
+    out = {}
+    for proc in (0, 1):
+        s = q.Surrogate(t32, proc, seed=1)
+        loss = s.fit().cpu().numpy()
+        out[proc] = (s, loss)
+    return out
+
+
+def _bf16(a):
+    u = np.asarray(a, np.float32).view(np.uint32).astype(np.uint64)
+    u = ((u + 0x7FFF + ((u >> 16) & 1)) >> 16) << 16
+    return u.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+def _inputs(q, s, n, seed, rho_max=16.0):
+    import torch
+    m, h, rs, os_ = s.norm()
+    rng = np.random.default_rng(seed)
+    x = np.column_stack([m + h * rng.uniform(-1, 1, n), rng.uniform(-rho_max, rho_max, n), rng.choice([-1.0, 1.0], n)])
+    return torch.tensor(x, dtype=torch.float32, device="cuda").contiguous()
+
+
+@pytest.mark.parametrize("proc", [0, 1])
+def test_surrogate_gradient_matches_fp64_reference(q, t32, proc):
+    import torch
+    s = q.Surrogate(t32, proc, seed=5)
+    m, h, rs, os_ = s.norm()
+    n = 4096
+    x = _inputs(q, s, n, 2)
+    nu = np.random.default_rng(3).normal(0.0, 10.0, n).astype(np.float32)
+    g = s.gradient(x, torch.tensor(nu, device="cuda")).cpu().numpy().astype(np.float64)
+    theta = _bf16(s.get_params().cpu().numpy())            # the network runs on BF16 weights
+    xf = x.cpu().numpy()
+    X = np.column_stack([(xf[:, 0] - np.float32(m)) / np.float32(h), xf[:, 1] / np.float32(rs), xf[:, 2]])
+    L, go = mlp.loss_and_grad(theta, X.astype(np.float64), nu.astype(np.float64) / os_)
+    o = 0
+    for name, shp in mlp.SHAPES:
+        k = int(np.prod(shp))
+        a, b = g[o:o + k], go[o:o + k]
+        o += k
+        rel = np.linalg.norm(a - b) / np.linalg.norm(b)
+        assert rel < 5e-3, (name, rel)
+    assert abs(g[-1] / L - 1) < 1e-3
+
+
+@pytest.mark.parametrize("proc", [0, 1])
+def test_surrogate_error_and_memory(q, t32, trained, otables, proc):
+    """Error of the trained network against the inverse-CDF tables over the sampled range, and its
+    size (BF16 parameters) against the two FP64 tables of the process."""
+    s, loss = trained[proc]
+    assert loss[-1] < loss[0] / 1e3
+    n = 20_000
+    x = _inputs(q, s, n, 7, rho_max=16.6)
+    nus = s.eval(x).cpu().numpy().astype(np.float64)
+    xf = x.cpu().numpy().astype(np.float64)
+    ref = np.array([otables.nu(2 * proc + (1 if c > 0 else 0), a, b) for a, b, c in xf])
+    d = nus - ref
+    lam_s, lam_r = 1 / (1 + np.exp(-nus)), 1 / (1 + np.exp(-ref))
+    rel = np.abs(lam_s - lam_r) / lam_r
+    rms = float(np.sqrt(np.mean(d * d)))
+    print(f"process {proc}: rms |dnu| {rms:.3g}, max {np.abs(d).max():.3g}, "
+          f"lambda rel err median {np.median(rel):.3g} p99 {np.quantile(rel, 0.99):.3g}, final mse {loss[-1]:.3g}")
+    assert rms < 0.1 and np.median(rel) < 0.04
+    n_chi = (161, 107)[proc]
+    table_bytes = 2 * n_chi * 256 * 8
+    net_bytes = s.n_params * 2
+    print(f"process {proc}: network {net_bytes} B (BF16) vs tables {table_bytes} B (FP64): {table_bytes / net_bytes:.1f}x")
+    assert table_bytes / net_bytes > 15
+
+
+def test_merged_step_with_surrogate(q, t32, trained):
+    """Head-on collision, 4000 electrons, FP32: one step from the same state gives the same
+    decisions with and without the network and photon energies within its stated error; the
+    surrogate plan replayed in a HIP graph equals its eager steps."""
+    import torch
+    from paper_2511_08929_amd.sim import Simulation
+    w = synth.subsample(synth.c2(), np.arange(4000))
+    w.k_retire = 0.0                           # keep every photon, soft ones included
+    f = q.make_fields(w.field_kind, a0=w.a0, phase_len=w.phase_len)
+    sur = (trained[0][0], trained[1][0])
+
+    def mk(use):
+        sim = Simulation(t32, cap_e=w.n + 3000, cap_p=3000, cap_g=400_000, track=w.track, fields=f, dt=w.dt,
+                         eps_r=EPS, seed=w.seed, flags=q.QED_ALL, k_retire=w.k_retire, device_clock=True,
+                         merged=True, surrogates=sur if use else (None, None))
+        sim.e.load(w.x, w.p, w.s)
+        return sim
+
+    a, b = mk(False), mk(True)
+    for k in range(700):                       # into the pulse, eagerly, same state on both
+        a.step()
+        if (k + 1) % 50 == 0:
+            a.compact()
+    for L, M in ((a.e, b.e), (a.p, b.p)):
+        for i in range(3):
+            M.p[i].copy_(L.p[i]); M.s[i].copy_(L.s[i])
+            if L.x[i] is not None:
+                M.x[i].copy_(L.x[i])
+        M.count.copy_(L.count)
+    for i in range(3):
+        b.g.k[i].copy_(a.g.k[i]); b.g.P[i].copy_(a.g.P[i])
+        if a.g.x[i] is not None:
+            b.g.x[i].copy_(a.g.x[i])
+    b.g.id.copy_(a.g.id); b.g.count.copy_(a.g.count); b.g.count_prev.copy_(a.g.count_prev)
+    b.clock.copy_(a.clock); b.n = a.n
+    n0 = a.g.n()
+    a.step(); b.step()
+    torch.cuda.synchronize()
+    ida, idb = a.g.id[n0:a.g.n()].cpu().numpy(), b.g.id[n0:b.g.n()].cpu().numpy()
+    assert ida.shape == idb.shape                              # same emitters: same slots
+    # a photon born below the retirement energy is stored as a dead slot (id 0): near that
+    # energy the network's lambda may decide differently
+    both = (ida != 0) & (idb != 0)
+    np.testing.assert_array_equal(ida[both], idb[both])
+    assert ((ida != 0) != (idb != 0)).mean() < 0.05
+    ka = np.stack([a.g.k[i][n0:a.g.n()].double().cpu().numpy() for i in range(3)])
+    kb = np.stack([b.g.k[i][n0:b.g.n()].double().cpu().numpy() for i in range(3)])
+    live = both
+    rel = np.linalg.norm(kb[:, live] - ka[:, live], axis=0) / np.linalg.norm(ka[:, live], axis=0)
+    print(f"one step: {live.sum()} photons, energy rel err median {np.median(rel):.3g} p99 {np.quantile(rel, 0.99):.3g}")
+    assert live.sum() > 200 and np.median(rel) < 0.04
+    # graph replay of the surrogate plan equals its eager steps
+    c = mk(True)
+    for k in range(650):
+        c.step()
+        if (k + 1) % 50 == 0:
+            c.compact()
+    d = mk(True)
+    for k in range(600):
+        d.step()
+        if (k + 1) % 50 == 0:
+            d.compact()
+    g = d.capture(50)
+    d.replay(g)
+    torch.cuda.synchronize()
+    for x, y in zip(c.e.arrays() + c.g.arrays(), d.e.arrays() + d.g.arrays()):
+        np.testing.assert_array_equal(x, y)
