@@ -43,13 +43,12 @@ def bytes_per_unit(es, tracked_x=1):
     return lep, pho
 
 
-def run_gpu(q, prec, w, steps, warmup, compact_every, profile, graph=True, merged=True):
+def run_gpu(q, tab, w, steps, warmup, compact_every, profile, graph=True, merged=True, surrogates=(None, None)):
     """Time `steps` steps from the initial state.  With graph=True each run of `compact_every`
     steps plus the compaction is one captured HIP graph (recorded before the timed region).
-    merged=True runs each step as one qed_plan_step (streaming + processing launch)."""
+    merged=True runs each step as one qed_plan_step; surrogates: learned inverse CDFs (NLC, NBW)."""
     import torch
     from paper_2511_08929_amd.sim import Simulation
-    tab = q.Tables(precision=prec)
     cap_p = max(1000, w.n // 5)
     cap_g = max(100_000, 30 * w.n)
     fields = q.make_fields(w.field_kind, a0=w.a0, phase_len=w.phase_len)
@@ -57,7 +56,7 @@ def run_gpu(q, prec, w, steps, warmup, compact_every, profile, graph=True, merge
     def fresh():
         sim = Simulation(tab, cap_e=w.n + cap_p, cap_p=cap_p, cap_g=cap_g, track=w.track, fields=fields, dt=w.dt,
                          eps_r=synth.EPS_R, seed=w.seed, flags=q.QED_ALL, k_retire=w.k_retire, device_clock=graph,
-                         merged=merged)
+                         merged=merged, surrogates=surrogates)
         sim.e.load(w.x, w.p, w.s)
         return sim
 
@@ -119,6 +118,86 @@ def load_traffic(kernel):
     return blob.get("traffic_bytes_per_launch")
 
 
+def spectra(q, tab, w, steps, surrogates=(None, None)):
+    """Every photon emitted in `steps` steps of workload w (no retirement, no compaction: dead
+    slots keep their momentum and P-vector) and the electrons' final spins."""
+    import torch
+    from paper_2511_08929_amd.sim import Simulation
+    fields = q.make_fields(w.field_kind, a0=w.a0, phase_len=w.phase_len)
+    sim = Simulation(tab, cap_e=w.n * 2 + 1000, cap_p=w.n + 1000, cap_g=120 * w.n, track=w.track, fields=fields,
+                     dt=w.dt, eps_r=synth.EPS_R, seed=w.seed, flags=q.QED_ALL, k_retire=0.0, device_clock=True,
+                     merged=True, surrogates=surrogates)
+    sim.e.load(w.x, w.p, w.s)
+    for _ in range(steps):
+        sim.step()
+    torch.cuda.synchronize()
+    n = sim.g.n()
+    k = torch.stack([c[:n].double() for c in sim.g.k]).norm(dim=0).cpu().numpy()
+    P = torch.stack([c[:n].double() for c in sim.g.P]).cpu().numpy()
+    kh = torch.stack([c[:n].double() for c in sim.g.k]).cpu().numpy() / np.maximum(k, 1e-300)
+    xi2 = np.sum(P * kh, axis=0)                       # circular Stokes parameter (P along k)
+    lin = P[1] ** 2 - P[2] ** 2                          # linear polarization along the laser E (y) vs B (z)
+    s = torch.stack([c[:w.n].double() for c in sim.e.s]).cpu().numpy()
+    c = q.counters_dict(sim.ctr)
+    assert c["n_capacity_overflow"] == 0, c
+    return dict(k=k, xi2=xi2, lin=lin, s_mean=s.mean(axis=1), ctr=c)
+
+
+def spectrum_error(ref, got, bins_per_decade=8, min_count=10_000):
+    """per-bin relative error of the photon-energy spectrum (8 bins per decade) over bins holding at
+    least min_count photons; per bin, the change of the photons' mean linear polarization along the
+    laser field (P_y^2 - P_z^2) and mean circular polarization (P . k/|k|); the change of the
+    electrons' mean spin vector"""
+    lo, hi = np.log10(max(ref["k"].min(), 1e-3)), np.log10(ref["k"].max())
+    edges = 10 ** np.arange(np.floor(lo * bins_per_decade) / bins_per_decade, hi + 1 / bins_per_decade,
+                            1 / bins_per_decade)
+    nr, _ = np.histogram(ref["k"], edges)
+    ng, _ = np.histogram(got["k"], edges)
+    ok = nr >= min_count
+    rel = np.abs(ng[ok] / nr[ok] - 1)
+    stat = 1 / np.sqrt(nr[ok])
+    dlin, dcirc = [], []
+    for a, b_ in zip(edges[:-1][ok], edges[1:][ok]):
+        sr, sg = (ref["k"] >= a) & (ref["k"] < b_), (got["k"] >= a) & (got["k"] < b_)
+        dlin.append(abs(got["lin"][sg].mean() - ref["lin"][sr].mean()))
+        dcirc.append(abs(got["xi2"][sg].mean() - ref["xi2"][sr].mean()))
+    return dict(bins=int(ok.sum()), spectrum_max_rel=round(float(rel.max()), 5),
+                spectrum_mean_rel=round(float(rel.mean()), 5), spectrum_stat_1sigma=round(float(stat.max()), 5),
+                linear_pol_max_abs=round(float(max(dlin)), 5), circular_pol_max_abs=round(float(max(dcirc)), 5),
+                spin_mean_abs=round(float(np.abs(got["s_mean"] - ref["s_mean"]).max()), 6),
+                photons_ref=int(ref["k"].size), photons=int(got["k"].size))
+
+
+def run_batched(q, tab, ws, steps, compact_every, ppb, graph=True):
+    """C5-shaped ensembles in one plan; returns wall time and the summed counters"""
+    import torch
+    from paper_2511_08929_amd.sim import Batch
+    specs = [dict(cap_e=w.n + max(1000, w.n // 5), cap_p=max(1000, w.n // 5), cap_g=max(100_000, 40 * w.n),
+                  track=w.track, fields=dict(kind=w.field_kind, a0=w.a0, phase_len=w.phase_len), dt=w.dt,
+                  eps_r=synth.EPS_R, seed=w.seed, flags=q.QED_ALL, k_retire=w.k_retire) for w in ws]
+    bat = Batch(tab, specs, particles_per_block=ppb)
+    for w, inst in zip(ws, bat.inst):
+        inst["e"].load(w.x, w.p, w.s)
+    g = bat.capture(compact_every) if graph else None
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    done = 0
+    while g is not None and done + compact_every <= steps:
+        bat.replay(g)
+        done += compact_every
+    for _ in range(steps - done):
+        bat.step()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    tot = {}
+    for inst in bat.inst:
+        for k, v in q.counters_dict(inst["ctr"]).items():
+            tot[k] = tot.get(k, 0) + v
+    del bat, g
+    torch.cuda.empty_cache()
+    return dict(wall=wall, ctr=tot)
+
+
 def probe(q, w, steps, compact_every):
     """Counter-collection run: a plain elementwise kernel over 256 MiB in and 256 MiB out (the
     calibration of FETCH_SIZE / WRITE_SIZE), then the single-precision path eagerly."""
@@ -129,7 +208,7 @@ def probe(q, w, steps, compact_every):
         torch.neg(a, out=b)
     torch.cuda.synchronize()
     del a, b
-    r = run_gpu(q, q.QED_F32, w, steps, 0, compact_every, profile=False, graph=False)
+    r = run_gpu(q, q.Tables(precision=q.QED_F32), w, steps, 0, compact_every, profile=False, graph=False)
     log(f"probe: {steps} steps in {r['wall']:.2f} s, counters {r['ctr']}")
 
 
@@ -150,6 +229,62 @@ def cpu_baseline(n_sample, steps, nthreads):
                        f"({c['n_lepton_steps']} lepton-steps + {c['n_photon_steps']} photon-steps in {dt:.1f} s)")
 
 
+def extras(q, args, w, t32, t64, out, v32, v64):
+    """learned inverse CDF (throughput and error), batched ensembles (autotuned block shape),
+    and the stated error of the single-precision paths against the FP64 path"""
+    import torch
+    # learned inverse CDF
+    t0 = time.perf_counter()
+    sn, sb = q.Surrogate(t32, 0, seed=1), q.Surrogate(t32, 1, seed=2)
+    ln, lb = sn.fit(), sb.fit()
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    rs = run_gpu(q, t32, w, args.steps, args.warmup, args.compact_every, profile=False, graph=True, surrogates=(sn, sb))
+    cs = rs["ctr"]
+    vs = (cs["n_lepton_steps"] + cs["n_photon_steps"]) / rs["wall"]
+    log(f"fp32 + learned inverse CDF (graph): {rs['wall']:.3f} s, {vs:.4g}/s (training {t_train:.2f} s)")
+    sur = {"value": round(vs, 1), "unit": "particle-QED-steps/s", "train_s": round(t_train, 3),
+           "final_mse": [round(float(ln[-1]), 8), round(float(lb[-1]), 8)],
+           "network_bytes_bf16": sn.n_params * 2}
+    if v64:
+        sur["speedup_vs_fp64"] = round(vs / v64, 3)
+    # stated error: spectra and polarization of the single-precision paths against the FP64 path
+    wsub = synth.subsample(w, np.arange(min(w.n, 100_000)))
+    steps_e = min(args.steps, 2000)
+    ref = spectra(q, t64, wsub, steps_e)
+    e32 = spectrum_error(ref, spectra(q, t32, wsub, steps_e))
+    esu = spectrum_error(ref, spectra(q, t32, wsub, steps_e, surrogates=(sn, sb)))
+    log(f"error vs fp64: fp32 {e32}; learned inverse CDF {esu}")
+    sur["error_vs_fp64"] = esu
+    out["fp32_error_vs_fp64"] = e32
+    out["error_workload"] = f"first {wsub.n} electrons of the same collision, {steps_e} steps, every photon kept"
+    out["surrogate"] = sur
+    del sn, sb
+    torch.cuda.empty_cache()
+    # batched ensembles: 64 instances, block shape chosen by timing 300 steps of each candidate
+    ws = synth.c5(scale=args.batched_scale)
+    steps_b = 2000
+    cand = {}
+    for ppb in (256, 512, 1024, 2048):
+        r = run_batched(q, t32, ws, 300, args.compact_every, ppb)
+        cand[ppb] = r["wall"]
+    best = min(cand, key=cand.get)
+    rb = run_batched(q, t32, ws, steps_b, args.compact_every, best)
+    cb = rb["ctr"]
+    vb = (cb["n_lepton_steps"] + cb["n_photon_steps"]) / rb["wall"]
+    rb64 = run_batched(q, t64, ws, steps_b, args.compact_every, best)
+    cb64 = rb64["ctr"]
+    vb64 = (cb64["n_lepton_steps"] + cb64["n_photon_steps"]) / rb64["wall"]
+    log(f"batched: {len(ws)} instances, {sum(x.n for x in ws)} electrons, particles/block {best} "
+        f"(candidates {cand}): fp32 {vb:.4g}/s, fp64 {vb64:.4g}/s")
+    out["batched"] = {"value": round(vb, 1), "unit": "particle-QED-steps/s", "instances": len(ws),
+                      "electrons": int(sum(x.n for x in ws)), "steps": steps_b,
+                      "recipe": f"64 head-on collisions, N ~ LogUniform[1e4, 1e7] x {args.batched_scale}, "
+                                "a0 ~ U[20, 200], gamma0 ~ U[500, 1e4], spin degree ~ U[0, 1]",
+                      "particles_per_block": best, "tuning_s_per_300_steps": {str(k): round(v, 4) for k, v in cand.items()},
+                      "fp64_value": round(vb64, 1), "speedup_vs_fp64": round(vb / vb64, 3)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -160,6 +295,10 @@ def main():
     ap.add_argument("--no-fp64", action="store_true", help="skip timing the FP64 path")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=3000)
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the learned-inverse-CDF, batched and spectral-error measurements")
+    ap.add_argument("--batched-scale", type=float, default=0.05,
+                    help="particle counts of the 64 batched ensembles relative to the full recipe")
     ap.add_argument("--probe", action="store_true",
                     help="profiler run: copy calibration + the FP32 path, eager, no JSON line")
     args = ap.parse_args()
@@ -179,13 +318,14 @@ def main():
         probe(q, w, args.steps, args.compact_every)
         return
 
+    t32, t64 = q.Tables(precision=q.QED_F32), q.Tables(precision=q.QED_F64)
     # timed run: graph replays (no per-launch host work); kernel timing in a separate eager run
-    r32 = run_gpu(q, q.QED_F32, w, args.steps, args.warmup, args.compact_every, profile=False, graph=True)
+    r32 = run_gpu(q, t32, w, args.steps, args.warmup, args.compact_every, profile=False, graph=True)
     c = r32["ctr"]
     work = c["n_lepton_steps"] + c["n_photon_steps"]
     value = work / r32["wall"]
     log(f"fp32 (graph): {r32['wall']:.3f} s, {work} particle-steps, {value:.4g}/s, counters {c}")
-    rk = run_gpu(q, q.QED_F32, w, args.steps, 0, args.compact_every, profile=True, graph=False)
+    rk = run_gpu(q, t32, w, args.steps, 0, args.compact_every, profile=True, graph=False)
     ck = rk["ctr"]
     log(f"fp32 (eager, events): {rk['wall']:.3f} s; kernel times {rk['ktimes']}")
 
@@ -216,12 +356,15 @@ def main():
                     "photons_emitted": c["n_emit"], "pairs": c["n_pair"]}}
 
     if not args.no_fp64:
-        r64 = run_gpu(q, q.QED_F64, w, args.steps, 0, args.compact_every, profile=False, graph=True)
+        r64 = run_gpu(q, t64, w, args.steps, 0, args.compact_every, profile=False, graph=True)
         c64 = r64["ctr"]
         v64 = (c64["n_lepton_steps"] + c64["n_photon_steps"]) / r64["wall"]
         log(f"fp64: {r64['wall']:.3f} s, {v64:.4g}/s")
         out["fp64_value"] = round(v64, 1)
         out["speedup_fp32_vs_fp64"] = round(value / v64, 3)
+
+    if not args.no_extras:
+        extras(q, args, w, t32, t64, out, value, out.get("fp64_value"))
 
     if not args.no_cpu_baseline:
         nthreads = min(16, os.cpu_count() or 1)
