@@ -43,7 +43,7 @@ def bytes_per_unit(es, tracked_x=1):
     return lep, pho
 
 
-def run_gpu(q, tab, w, steps, warmup, compact_every, profile, graph=True, merged=True, surrogates=(None, None)):
+def run_gpu(q, tab, w, steps, warmup, compact_every, profile, graph=True, merged=True, surrogates=(None, None), ppb=0):
     """Time `steps` steps from the initial state.  With graph=True each run of `compact_every`
     steps plus the compaction is one captured HIP graph (recorded before the timed region).
     merged=True runs each step as one qed_plan_step; surrogates: learned inverse CDFs (NLC, NBW)."""
@@ -56,7 +56,7 @@ def run_gpu(q, tab, w, steps, warmup, compact_every, profile, graph=True, merged
     def fresh():
         sim = Simulation(tab, cap_e=w.n + cap_p, cap_p=cap_p, cap_g=cap_g, track=w.track, fields=fields, dt=w.dt,
                          eps_r=synth.EPS_R, seed=w.seed, flags=q.QED_ALL, k_retire=w.k_retire, device_clock=graph,
-                         merged=merged, surrogates=surrogates)
+                         merged=merged, surrogates=surrogates, particles_per_block=ppb)
         sim.e.load(w.x, w.p, w.s)
         return sim
 
@@ -198,7 +198,7 @@ def run_batched(q, tab, ws, steps, compact_every, ppb, graph=True):
     return dict(wall=wall, ctr=tot)
 
 
-def probe(q, w, steps, compact_every):
+def probe(q, w, steps, compact_every, ppb=0):
     """Counter-collection run: a plain elementwise kernel over 256 MiB in and 256 MiB out (the
     calibration of FETCH_SIZE / WRITE_SIZE), then the single-precision path eagerly."""
     import torch
@@ -208,7 +208,7 @@ def probe(q, w, steps, compact_every):
         torch.neg(a, out=b)
     torch.cuda.synchronize()
     del a, b
-    r = run_gpu(q, q.Tables(precision=q.QED_F32), w, steps, 0, compact_every, profile=False, graph=False)
+    r = run_gpu(q, q.Tables(precision=q.QED_F32), w, steps, 0, compact_every, profile=False, graph=False, ppb=ppb)
     log(f"probe: {steps} steps in {r['wall']:.2f} s, counters {r['ctr']}")
 
 
@@ -239,7 +239,8 @@ def extras(q, args, w, t32, t64, out, v32, v64):
     ln, lb = sn.fit(), sb.fit()
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t0
-    rs = run_gpu(q, t32, w, args.steps, args.warmup, args.compact_every, profile=False, graph=True, surrogates=(sn, sb))
+    rs = run_gpu(q, t32, w, args.steps, args.warmup, args.compact_every, profile=False, graph=True, surrogates=(sn, sb),
+                 ppb=args.ppb)
     cs = rs["ctr"]
     vs = (cs["n_lepton_steps"] + cs["n_photon_steps"]) / rs["wall"]
     log(f"fp32 + learned inverse CDF (graph): {rs['wall']:.3f} s, {vs:.4g}/s (training {t_train:.2f} s)")
@@ -299,6 +300,7 @@ def main():
                     help="skip the learned-inverse-CDF, batched and spectral-error measurements")
     ap.add_argument("--batched-scale", type=float, default=0.05,
                     help="particle counts of the 64 batched ensembles relative to the full recipe")
+    ap.add_argument("--ppb", type=int, default=0, help="particles per block of the plan in --probe runs (0: 256)")
     ap.add_argument("--probe", action="store_true",
                     help="profiler run: copy calibration + the FP32 path, eager, no JSON line")
     args = ap.parse_args()
@@ -315,17 +317,25 @@ def main():
     w = synth.c2(n=args.n)
     log(f"workload {w.name}: n={w.n} steps={args.steps} warmup={args.warmup}")
     if args.probe:
-        probe(q, w, args.steps, args.compact_every)
+        probe(q, w, args.steps, args.compact_every, args.ppb)
         return
 
     t32, t64 = q.Tables(precision=q.QED_F32), q.Tables(precision=q.QED_F64)
+    # block shape of the plan: particles per block chosen by timing the first 600 steps of each
+    # candidate (graph replays), before the timed region
+    tune = {}
+    for ppb in (256, 512, 1024, 2048, 4096):
+        tune[ppb] = run_gpu(q, t32, w, 600, 0, args.compact_every, profile=False, graph=True, ppb=ppb)["wall"]
+    ppb = min(tune, key=tune.get)
+    log(f"particles per block {ppb} (600-step times {tune})")
+    args.ppb = ppb
     # timed run: graph replays (no per-launch host work); kernel timing in a separate eager run
-    r32 = run_gpu(q, t32, w, args.steps, args.warmup, args.compact_every, profile=False, graph=True)
+    r32 = run_gpu(q, t32, w, args.steps, args.warmup, args.compact_every, profile=False, graph=True, ppb=ppb)
     c = r32["ctr"]
     work = c["n_lepton_steps"] + c["n_photon_steps"]
     value = work / r32["wall"]
     log(f"fp32 (graph): {r32['wall']:.3f} s, {work} particle-steps, {value:.4g}/s, counters {c}")
-    rk = run_gpu(q, t32, w, args.steps, 0, args.compact_every, profile=True, graph=False)
+    rk = run_gpu(q, t32, w, args.steps, 0, args.compact_every, profile=True, graph=False, ppb=ppb)
     ck = rk["ctr"]
     log(f"fp32 (eager, events): {rk['wall']:.3f} s; kernel times {rk['ktimes']}")
 
@@ -352,11 +362,12 @@ def main():
                       "time_steps": args.steps, "precision": "FP32 bulk + FP64 islands",
                       "channels": "NLC + NBW, spin and polarization resolved"},
            "roofline": roof,
+           "tuning": {"particles_per_block": ppb, "s_per_600_steps": {str(k): round(v, 4) for k, v in tune.items()}},
            "work": {"lepton_steps": c["n_lepton_steps"], "photon_steps": c["n_photon_steps"],
                     "photons_emitted": c["n_emit"], "pairs": c["n_pair"]}}
 
     if not args.no_fp64:
-        r64 = run_gpu(q, t64, w, args.steps, 0, args.compact_every, profile=False, graph=True)
+        r64 = run_gpu(q, t64, w, args.steps, 0, args.compact_every, profile=False, graph=True, ppb=ppb)
         c64 = r64["ctr"]
         v64 = (c64["n_lepton_steps"] + c64["n_photon_steps"]) / r64["wall"]
         log(f"fp64: {r64['wall']:.3f} s, {v64:.4g}/s")

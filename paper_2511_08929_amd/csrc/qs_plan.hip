@@ -125,7 +125,15 @@ __global__ void __launch_bounds__(kBlock) k_plan_book(const InstDev<R> *inst, Pl
     const int m = (int)cdiv(P.nblk, kBlock);
     const int lo = threadIdx.x * m, hi = lo + m < P.nblk ? lo + m : P.nblk;
     uint32_t run = 0;
-    for (int b = lo; b < hi; ++b) run += P.bcnt[b];
+    int b = lo;
+    for (; b + 8 <= hi; b += 8) {              // eight independent loads in flight
+        uint32_t v[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) v[j] = P.bcnt[b + j];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) run += v[j];
+    }
+    for (; b < hi; ++b) run += P.bcnt[b];
     uint32_t incl = run;
     for (int o = 1; o < 64; o <<= 1) {
         const uint32_t y = __shfl_up(incl, o);
@@ -135,9 +143,9 @@ __global__ void __launch_bounds__(kBlock) k_plan_book(const InstDev<R> *inst, Pl
     __syncthreads();
     uint32_t off = incl - run;
     for (int w = 0; w < wid; ++w) off += wsum[w];
-    for (int b = lo; b < hi; ++b) {
-        const uint32_t v = P.bcnt[b];
-        P.gpre[b] = off;
+    for (int bb = lo; bb < hi; ++bb) {
+        const uint32_t v = P.bcnt[bb];
+        P.gpre[bb] = off;
         off += v;
     }
     if (threadIdx.x == kBlock - 1) P.gpre[P.nblk] = off;
