@@ -80,9 +80,13 @@ enum {
 /* Field models evaluated at each particle. */
 enum {
     QED_FIELD_UNIFORM = 0,     /* E = E0, B = B0 */
-    QED_FIELD_PLANE_LP = 1     /* E0, B0 plus a linearly polarized wave along -x:
+    QED_FIELD_PLANE_LP = 1,    /* E0, B0 plus a linearly polarized wave along -x:
                                   E_y = a0 g(phi) cos(phi), B_z = -E_y, phi = t + x,
                                   g = sin^2(pi phi / phase_len) on [0, phase_len] (1 if phase_len = 0) */
+    QED_FIELD_GRID2D = 2       /* E0, B0 plus a static field on a periodic 2-D grid in (x, y): six FP32
+                                  device arrays Ex, Ey, Ez, Bx, By, Bz of nx * ny nodes, node (i, j) at
+                                  (x0 + i dx, y0 + j dy), index j * nx + i; bilinear interpolation
+                                  (particles need x[0] and x[1]) */
 };
 
 /* Rate / inverse-CDF table grid: nodes uniform in ln chi and in rho = ln(r/(1-r)).
@@ -131,6 +135,9 @@ typedef struct {
     int    kind;
     double E0[3], B0[3];
     double a0, phase_len;
+    const float *grid[6];       /* QED_FIELD_GRID2D only (device pointers, caller-owned) */
+    int    nx, ny;
+    double dx, dy, x0, y0;
 } qed_fields;
 
 typedef struct {

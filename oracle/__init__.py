@@ -37,7 +37,7 @@ F_TAU = 1 << 11
 F_ALL = (F_PUSH | F_TBMT | F_EMIT | F_RECOIL | F_SPIN | F_NOEMIT | F_PHOTON_POL
          | F_PAIR | F_NOPAIR | F_PAIR_SPIN)
 
-FIELD_UNIFORM, FIELD_PLANE_LP = 0, 1
+FIELD_UNIFORM, FIELD_PLANE_LP, FIELD_GRID2D = 0, 1, 2
 
 
 def build(force: bool = False) -> Path:
@@ -67,7 +67,9 @@ class Tables(C.Structure):
 
 class Fields(C.Structure):
     _fields_ = [("kind", C.c_int), ("E0", C.c_double * 3), ("B0", C.c_double * 3),
-                ("a0", C.c_double), ("phase_len", C.c_double)]
+                ("a0", C.c_double), ("phase_len", C.c_double), ("grid", C.POINTER(C.c_float) * 6),
+                ("nx", C.c_int), ("ny", C.c_int), ("dx", C.c_double), ("dy", C.c_double), ("x0", C.c_double),
+                ("y0", C.c_double)]
 
 
 class Params(C.Structure):
@@ -419,12 +421,22 @@ def make_params(dt, eps_r, step=0, t=0.0, seed=1, flags=F_ALL, a_e=ALPHA / (2 * 
     return P
 
 
-def make_fields(kind=FIELD_UNIFORM, E0=(0, 0, 0), B0=(0, 0, 0), a0=0.0, phase_len=0.0):
+def make_fields(kind=FIELD_UNIFORM, E0=(0, 0, 0), B0=(0, 0, 0), a0=0.0, phase_len=0.0, grid=None, dx=1.0, dy=1.0,
+                x0=0.0, y0=0.0):
+    """grid: float32 array (6, ny, nx) of Ex, Ey, Ez, Bx, By, Bz at the nodes (kind FIELD_GRID2D);
+    the returned structure keeps a reference to it"""
     F = Fields()
     F.kind = kind
     for i in range(3):
         F.E0[i], F.B0[i] = E0[i], B0[i]
     F.a0, F.phase_len = a0, phase_len
+    if grid is not None:
+        g = np.ascontiguousarray(grid, dtype=np.float32)
+        F._grid = g
+        F.ny, F.nx = g.shape[1], g.shape[2]
+        for c in range(6):
+            F.grid[c] = g[c].ctypes.data_as(C.POINTER(C.c_float))
+        F.dx, F.dy, F.x0, F.y0 = dx, dy, x0, y0
     return F
 
 

@@ -679,6 +679,20 @@ void orc_fields_eval(const orc_fields *f, const double x[3], double t, double E[
         double ey = f->a0 * g * cos(phi);
         E[1] += ey;
         B[2] += -ey;
+    } else if (f->kind == ORC_FIELD_GRID2D) {
+        /* bilinear interpolation between the four nodes around (x, y), periodic grid */
+        double u = (x[0] - f->x0) / f->dx, v = (x[1] - f->y0) / f->dy;
+        double iu = floor(u), iv = floor(v);
+        double ax = u - iu, ay = v - iv;
+        long i0 = ((long)fmod(iu, (double)f->nx) + f->nx) % f->nx, j0 = ((long)fmod(iv, (double)f->ny) + f->ny) % f->ny;
+        long i1 = (i0 + 1) % f->nx, j1 = (j0 + 1) % f->ny;
+        double w00 = (1 - ax) * (1 - ay), w10 = ax * (1 - ay), w01 = (1 - ax) * ay, w11 = ax * ay;
+        for (int c = 0; c < 6; ++c) {
+            const float *g = f->grid[c];
+            double val = w00 * g[j0 * f->nx + i0] + w10 * g[j0 * f->nx + i1] + w01 * g[j1 * f->nx + i0]
+                       + w11 * g[j1 * f->nx + i1];
+            if (c < 3) E[c] += val; else B[c - 3] += val;
+        }
     }
 }
 

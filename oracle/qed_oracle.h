@@ -69,12 +69,17 @@ double orc_table_lnrate(const orc_tables *T, int channel, double lnchi);
 double orc_table_nu(const orc_tables *T, int channel, double lnchi, double rho);
 
 /* ---------------- fields ---------------- */
-enum { ORC_FIELD_UNIFORM = 0, ORC_FIELD_PLANE_LP = 1, ORC_FIELD_PLANE_CP2 = 2 };
+enum { ORC_FIELD_UNIFORM = 0, ORC_FIELD_PLANE_LP = 1, ORC_FIELD_GRID2D = 2 };
 typedef struct {
     int    kind;
     double E0[3], B0[3];    /* uniform */
     double a0;              /* plane wave amplitude */
     double phase_len;       /* sin^2 envelope length in phase (0 = no envelope) */
+    /* static 2-D grid (x, y), periodic: six node arrays Ex, Ey, Ez, Bx, By, Bz of nx * ny floats,
+       node (i, j) at (x0 + i dx, y0 + j dy), index j * nx + i; bilinear interpolation */
+    const float *grid[6];
+    int    nx, ny;
+    double dx, dy, x0, y0;
 } orc_fields;
 void orc_fields_eval(const orc_fields *f, const double x[3], double t, double E[3], double B[3]);
 

@@ -29,7 +29,7 @@ QED_PAIR, QED_NOPAIR, QED_PAIR_SPIN = 1 << 8, 1 << 9, 1 << 10
 QED_OPTICAL_DEPTH = 1 << 11
 QED_ALL = (QED_PUSH | QED_TBMT | QED_EMIT | QED_RECOIL | QED_SPIN | QED_NOEMIT | QED_PHOTON_POL
            | QED_PAIR | QED_NOPAIR | QED_PAIR_SPIN)
-QED_FIELD_UNIFORM, QED_FIELD_PLANE_LP = 0, 1
+QED_FIELD_UNIFORM, QED_FIELD_PLANE_LP, QED_FIELD_GRID2D = 0, 1, 2
 
 ABI_SYMBOLS = ("qed_init_tables", "qed_last_error", "qed_free_tables", "qed_tables_download", "qed_workspace_size",
                "qed_push_spin", "qed_emit", "qed_pair", "qed_compact_workspace_size", "qed_compact",
@@ -66,7 +66,8 @@ class Photons(C.Structure):
 
 class Fields(C.Structure):
     _fields_ = [("kind", C.c_int), ("E0", C.c_double * 3), ("B0", C.c_double * 3),
-                ("a0", C.c_double), ("phase_len", C.c_double)]
+                ("a0", C.c_double), ("phase_len", C.c_double), ("grid", C.c_void_p * 6), ("nx", C.c_int),
+                ("ny", C.c_int), ("dx", C.c_double), ("dy", C.c_double), ("x0", C.c_double), ("y0", C.c_double)]
 
 
 class StepParams(C.Structure):
@@ -303,12 +304,24 @@ class PhotonBuffers:
                 self.id[:n].cpu().numpy().view(np.uint64))
 
 
-def make_fields(kind=QED_FIELD_UNIFORM, E0=(0, 0, 0), B0=(0, 0, 0), a0=0.0, phase_len=0.0):
+def make_fields(kind=QED_FIELD_UNIFORM, E0=(0, 0, 0), B0=(0, 0, 0), a0=0.0, phase_len=0.0, grid=None, dx=1.0, dy=1.0,
+                x0=0.0, y0=0.0):
+    """grid (QED_FIELD_GRID2D): float32 device tensor (6, ny, nx) of Ex, Ey, Ez, Bx, By, Bz at the
+    nodes; the returned structure keeps a reference to it"""
     f = Fields()
     f.kind = kind
     for i in range(3):
         f.E0[i], f.B0[i] = E0[i], B0[i]
     f.a0, f.phase_len = a0, phase_len
+    if grid is not None:
+        import torch
+        g = grid.contiguous()
+        assert g.dtype == torch.float32 and g.dim() == 3 and g.shape[0] == 6 and g.is_cuda
+        f._grid = g
+        f.ny, f.nx = int(g.shape[1]), int(g.shape[2])
+        for c in range(6):
+            f.grid[c] = g[c].data_ptr()
+        f.dx, f.dy, f.x0, f.y0 = dx, dy, x0, y0
     return f
 
 

@@ -179,12 +179,41 @@ struct FieldDev {
     double E0[3], B0[3];
     double a0, phase_len;
     double inv_phase_len;      // 1 / phase_len (0 without envelope)
+    const float *g[6];         // grid: Ex, Ey, Ez, Bx, By, Bz node arrays [ny][nx]
+    int nx, ny;
+    double gx0, gy0, inv_dx, inv_dy, inv_nx, inv_ny;
 };
 
-// E and B at position x (only x[0] enters the plane wave) and time t.
-template <class R> __device__ __forceinline__ void eval_fields(const FieldDev &f, double x0, double t, V3<R> &E, V3<R> &B);
+// Bilinear interpolation on the periodic grid: cell index and fractions from FP64 coordinates
+// (the index wraps with an FP64 floor, exact for |index| < 2^52), weights in R.
+template <class R> __device__ __forceinline__ void add_grid(const FieldDev &f, double x, double y, V3<R> &E, V3<R> &B)
+{
+    const double u = (x - f.gx0) * f.inv_dx, v = (y - f.gy0) * f.inv_dy;
+    const double fu = floor(u), fv = floor(v);
+    const R ax = (R)(u - fu), ay = (R)(v - fv);
+    int i0 = (int)(fu - (double)f.nx * floor(fu * f.inv_nx));
+    int j0 = (int)(fv - (double)f.ny * floor(fv * f.inv_ny));
+    i0 = i0 >= f.nx ? i0 - f.nx : (i0 < 0 ? i0 + f.nx : i0);
+    j0 = j0 >= f.ny ? j0 - f.ny : (j0 < 0 ? j0 + f.ny : j0);
+    const int i1 = i0 + 1 == f.nx ? 0 : i0 + 1, j1 = j0 + 1 == f.ny ? 0 : j0 + 1;
+    const int64_t a = (int64_t)j0 * f.nx, b = (int64_t)j1 * f.nx;
+    const R w00 = ((R)1 - ax) * ((R)1 - ay), w10 = ax * ((R)1 - ay), w01 = ((R)1 - ax) * ay, w11 = ax * ay;
+    R val[6];
+#pragma unroll
+    for (int c = 0; c < 6; ++c) {
+        const float *g = f.g[c];
+        val[c] = w00 * (R)g[a + i0] + w10 * (R)g[a + i1] + w01 * (R)g[b + i0] + w11 * (R)g[b + i1];
+    }
+    E.x += val[0]; E.y += val[1]; E.z += val[2];
+    B.x += val[3]; B.y += val[4]; B.z += val[5];
+}
 
-template <> __device__ __forceinline__ void eval_fields<double>(const FieldDev &f, double x0, double t, V3<double> &E, V3<double> &B)
+// E and B at position (x, y) (the plane wave depends on x only, the grid on x and y) and time t.
+template <class R> __device__ __forceinline__ void eval_fields(const FieldDev &f, double x0, double y0, double t, V3<R> &E,
+                                                              V3<R> &B);
+
+template <> __device__ __forceinline__ void eval_fields<double>(const FieldDev &f, double x0, double y0, double t,
+                                                                V3<double> &E, V3<double> &B)
 {
     E = {f.E0[0], f.E0[1], f.E0[2]};
     B = {f.B0[0], f.B0[1], f.B0[2]};
@@ -199,12 +228,15 @@ template <> __device__ __forceinline__ void eval_fields<double>(const FieldDev &
         const double ey = f.a0 * g * cos(phi);
         E.y += ey;
         B.z -= ey;
+    } else if (f.kind == 2) {
+        add_grid<double>(f, x0, y0, E, B);
     }
 }
 
 // single precision: the phase is formed and reduced to revolutions in FP64; the sine and
 // cosine of the reduced argument use the hardware instructions (|argument| <= 1 revolution)
-template <> __device__ __forceinline__ void eval_fields<float>(const FieldDev &f, double x0, double t, V3<float> &E, V3<float> &B)
+template <> __device__ __forceinline__ void eval_fields<float>(const FieldDev &f, double x0, double y0, double t,
+                                                               V3<float> &E, V3<float> &B)
 {
     E = {(float)f.E0[0], (float)f.E0[1], (float)f.E0[2]};
     B = {(float)f.B0[0], (float)f.B0[1], (float)f.B0[2]};
@@ -222,6 +254,8 @@ template <> __device__ __forceinline__ void eval_fields<float>(const FieldDev &f
         const float ey = (float)f.a0 * g * __builtin_amdgcn_cosf(red);
         E.y += ey;
         B.z -= ey;
+    } else if (f.kind == 2) {
+        add_grid<float>(f, x0, y0, E, B);
     }
 }
 

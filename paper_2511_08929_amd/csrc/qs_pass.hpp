@@ -282,8 +282,9 @@ struct LCount { unsigned prob = 0, chi = 0, norm = 0, step = 0, trans = 0; };
 
 // Main pass, one lepton: Boris push and T-BMT rotation with the fields at t, the fields at
 // t + dt, chi and the decision (NLC section); a non-emitter gets the no-transition spin update
-// (non-transition section).  Stores x, p, s.
-template <class R>
+// (non-transition section).  Stores x, p, s.  TAU: compiled with the optical-depth decision (the
+// variant without it needs fewer registers).
+template <class R, bool TAU>
 __device__ __forceinline__ void lepton_item(const LepDev<R> &L, const FieldDev &F, const StepDev &S, const TablesDev &T,
                                             const R *lds, int64_t i, bool &emit, bool &up, LCount &c)
 {
@@ -292,16 +293,16 @@ __device__ __forceinline__ void lepton_item(const LepDev<R> &L, const FieldDev &
     V3<R> x = ldx(L.x, i), p = ld3(L.p, i), s = ld3(L.s, i);
     V3<R> E, B;
     if (S.flags & F_PUSH) {
-        eval_fields<R>(F, (double)x.x, S.t, E, B);
+        eval_fields<R>(F, (double)x.x, (double)x.y, S.t, E, B);
         x = x + push<R>(q, (R)S.a_e, E, B, (R)S.dt, (S.flags & F_TBMT) != 0, p, s);
     }
     if (S.flags & F_EMIT) {
-        eval_fields<R>(F, (double)x.x, S.t + S.dt, E, B);
+        eval_fields<R>(F, (double)x.x, (double)x.y, S.t + S.dt, E, B);
         const LDecide<R> d = lepton_decide<R>(S, T, lds, L.species, i, p, s, E, B);
         if (d.active) {
             c.chi += d.clamped_chi;
             bool noemit_update = false;
-            if ((S.flags & F_TAU) && L.tau) {
+            if (TAU && (S.flags & F_TAU) && L.tau) {
                 // optical depth in FP64: tau += W dt; emission at tau >= tau*, tau* = -ln(1 - u)
                 // from channel 4 (words 0,1 if no target is set yet, words 2,3 after an emission)
                 const uint4 w4 = philox_block(S.seed, lepton_id(L.species, i), S.step, 4u);
@@ -347,7 +348,7 @@ __device__ __forceinline__ void lepton_item(const LepDev<R> &L, const FieldDev &
 
 // Main pass over the lepton range [start, end) (start a multiple of 64): the wave's decisions
 // and branch choices go to mask[w] and mask[nchunks + w] of its 64-particle word w.
-template <class R>
+template <class R, bool TAU>
 __device__ __forceinline__ void lepton_range(const LepDev<R> &L, const FieldDev &F, const StepDev &S, const TablesDev &T,
                                              const R *lds, int64_t start, int64_t end, uint64_t *mask, int64_t nchunks,
                                              LCount &c)
@@ -356,7 +357,7 @@ __device__ __forceinline__ void lepton_range(const LepDev<R> &L, const FieldDev 
     for (int64_t base = start + (threadIdx.x & ~63); base < end; base += blockDim.x) {
         const int64_t i = base + lane;
         bool emit = false, up = false;
-        if (i < end) lepton_item<R>(L, F, S, T, lds, i, emit, up, c);
+        if (i < end) lepton_item<R, TAU>(L, F, S, T, lds, i, emit, up, c);
         const uint64_t m = __ballot(emit), mu = __ballot(up);
         if (lane == 0) {
             mask[base >> 6] = m;
@@ -378,7 +379,7 @@ __device__ __forceinline__ void emit_item(const LepDev<R> &L, const PhoDev<R> &G
     const V3<R> x = ldx(L.x, i);
     V3<R> p = ld3(L.p, i), s = ld3(L.s, i);
     V3<R> E, B;
-    eval_fields<R>(F, (double)x.x, S.t + S.dt, E, B);
+    eval_fields<R>(F, (double)x.x, (double)x.y, S.t + S.dt, E, B);
     const LDecide<R> d = lepton_decide<R>(S, T, lds, L.species, i, p, s, E, B);
     const double r2 = (double)d.r2;
     const double rho = log(r2) - log1p(-r2);
@@ -452,7 +453,7 @@ constexpr int kPhoTile = 1024;
 
 template <class R> struct PhoQueue {
     uint32_t idx[kPhoTile];
-    R x[kPhoTile];
+    R x[kPhoTile], y[kPhoTile];
     unsigned long long bits[2][kPhoTile / 64];
     uint32_t n;
 };
@@ -470,7 +471,7 @@ __device__ __forceinline__ void photon_tile(const PhoDev<R> &G, const FieldDev &
     for (int64_t base = tile + (threadIdx.x & ~63); base < tend; base += blockDim.x) {
         const int64_t i = base + lane;
         bool cand = false;
-        R xq = (R)0;
+        R xq = (R)0, yq = (R)0;
         if (i < tend) {
             const uint64_t id = G.id[i];
             if (id != 0) {
@@ -488,9 +489,10 @@ __device__ __forceinline__ void photon_tile(const PhoDev<R> &G, const FieldDev &
                     ++c.ret;
                 } else if (qed) {
                     V3<R> E, Bf;
-                    eval_fields<R>(F, (double)x.x, S.t + S.dt, E, Bf);
+                    eval_fields<R>(F, (double)x.x, (double)x.y, S.t + S.dt, E, Bf);
                     cand = photon_candidate<R>(S, k0r, E, Bf);
                     xq = x.x;
+                    yq = x.y;
                 }
             }
         }
@@ -502,6 +504,7 @@ __device__ __forceinline__ void photon_tile(const PhoDev<R> &G, const FieldDev &
             const uint32_t r = wbase + (uint32_t)__popcll(m & ((1ull << lane) - 1ull));
             Q.idx[r] = (uint32_t)(i - tile);
             Q.x[r] = xq;
+            Q.y[r] = yq;
         }
     }
     __syncthreads();
@@ -513,7 +516,7 @@ __device__ __forceinline__ void photon_tile(const PhoDev<R> &G, const FieldDev &
         const V3<R> k = ld3(G.k, i);
         const double k0 = (double)sqrt_r(dot(k, k));
         V3<R> E, Bf;
-        eval_fields<R>(F, (double)Q.x[j], S.t + S.dt, E, Bf);
+        eval_fields<R>(F, (double)Q.x[j], (double)Q.y[j], S.t + S.dt, E, Bf);
         const V3<R> P = ld3(G.P, i);
         const PDecide<R> d = photon_decide<R>(S, T, lds, id, k, k0, P, E, Bf);
         if (!d.active) continue;
@@ -564,7 +567,7 @@ __device__ __forceinline__ void pair_item(const PhoDev<R> &G, const LepDev<R> &L
     const V3<R> k = ld3(G.k, i), x = ldx(G.x, i), P = ld3(G.P, i);
     const double k0 = (double)sqrt_r(dot(k, k));
     V3<R> E, B;
-    eval_fields<R>(F, (double)x.x, S.t + S.dt, E, B);
+    eval_fields<R>(F, (double)x.x, (double)x.y, S.t + S.dt, E, B);
     const PDecide<R> d = photon_decide<R>(S, T, lds, id, k, k0, P, E, B);
     const double r2 = (double)d.r2;
     const double rho = log(r2) - log1p(-r2);
@@ -666,6 +669,7 @@ template <class R> PhoDev<R> pho_dev(const qed_photons *G)
 inline FieldDev field_dev(const qed_fields *f)
 {
     FieldDev d;
+    memset(&d, 0, sizeof(d));
     d.kind = f->kind;
     for (int c = 0; c < 3; ++c) {
         d.E0[c] = f->E0[c];
@@ -674,6 +678,13 @@ inline FieldDev field_dev(const qed_fields *f)
     d.a0 = f->a0;
     d.phase_len = f->phase_len;
     d.inv_phase_len = f->phase_len > 0.0 ? 1.0 / f->phase_len : 0.0;
+    if (f->kind == QED_FIELD_GRID2D) {
+        for (int c = 0; c < 6; ++c) d.g[c] = f->grid[c];
+        d.nx = f->nx; d.ny = f->ny;
+        d.gx0 = f->x0; d.gy0 = f->y0;
+        d.inv_dx = 1.0 / f->dx; d.inv_dy = 1.0 / f->dy;
+        d.inv_nx = 1.0 / f->nx; d.inv_ny = 1.0 / f->ny;
+    }
     return d;
 }
 
@@ -719,6 +730,14 @@ inline bool photons_ok(const qed_photons *G)
     return true;
 }
 
-inline bool fields_ok(const qed_fields *f) { return f && (f->kind == QED_FIELD_UNIFORM || f->kind == QED_FIELD_PLANE_LP); }
+inline bool fields_ok(const qed_fields *f)
+{
+    if (!f) return false;
+    if (f->kind == QED_FIELD_UNIFORM || f->kind == QED_FIELD_PLANE_LP) return true;
+    if (f->kind != QED_FIELD_GRID2D) return false;
+    for (int c = 0; c < 6; ++c)
+        if (!f->grid[c]) return false;
+    return f->nx >= 2 && f->ny >= 2 && f->dx > 0.0 && f->dy > 0.0;
+}
 
 }  // namespace qs

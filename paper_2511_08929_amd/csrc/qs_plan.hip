@@ -198,7 +198,7 @@ __global__ void __launch_bounds__(kBlock) k_plan_book(const InstDev<R> *inst, Pl
 
 // The streaming pass runs as two launches with their own register allocation: PHO = 0 over the
 // lepton segments (blocks [0, nblk_lep)), PHO = 1 over the photon segments (the rest).
-template <class R, int PHO>
+template <class R, int PHO, bool TAU>
 __global__ void __launch_bounds__(kBlock) k_plan_main(const InstDev<R> *inst, PlanDev P, TablesDev T, int b_first)
 {
     extern __shared__ unsigned char smem_raw[];
@@ -222,7 +222,7 @@ __global__ void __launch_bounds__(kBlock) k_plan_main(const InstDev<R> *inst, Pl
         const int64_t B = block_len(n, sg.nb);
         const int64_t start = (int64_t)(b - sg.b0) * B, end = start + B < n ? start + B : n;
         LCount c;
-        lepton_range<R>(L, F, S, T, lds, start, end, mask, sg.nchunks, c);
+        lepton_range<R, TAU>(L, F, S, T, lds, start, end, mask, sg.nchunks, c);
         v[C_PROB] = c.prob; v[C_CHI] = c.chi; v[C_NORM] = c.norm; v[C_LSTEP] = c.step; v[kNCtr] = c.trans;
     } else {
         const PhoDev<R> G = Ip->G;
@@ -262,8 +262,6 @@ __global__ void __launch_bounds__(kBlock) k_plan_process(const InstDev<R> *inst,
     S.step += P.clock_used[sg.inst];
     S.t += (double)P.clock_used[sg.inst] * S.dt;
     const FieldDev F = Ip->F;
-    const LepDev<R> E = Ip->E, Pp = Ip->P;
-    const PhoDev<R> G = Ip->G;
     const SegBook bk = P.sbook[sj];
     stage_rates<R>(T, PHO, lds);
     const uint64_t *mask = P.mask + sg.mask_off;
@@ -304,10 +302,11 @@ __global__ void __launch_bounds__(kBlock) k_plan_process(const InstDev<R> *inst,
             const float *nu_in = mode == 2 ? P.snu + gr : nullptr;
             float *x_out = mode == 1 ? P.sx + 3 * gr : nullptr;
             if (!PHO)
-                emit_item<R>(sg.kind == 0 ? E : Pp, G, F, S, T, lds, i, br, r < bk.nfit ? bk.base + r : -1, c_ret, nu_in,
-                             x_out);
+                emit_item<R>(sg.kind == 0 ? Ip->E : Ip->P, Ip->G, F, S, T, lds, i, br, r < bk.nfit ? bk.base + r : -1,
+                             c_ret, nu_in, x_out);
             else
-                pair_item<R>(G, E, Pp, F, S, T, lds, i, br, r < bk.nfit ? bk.base + r : -1, bk.base2 + r, nu_in, x_out);
+                pair_item<R>(Ip->G, Ip->E, Ip->P, F, S, T, lds, i, br, r < bk.nfit ? bk.base + r : -1, bk.base2 + r, nu_in,
+                             x_out);
         }
         rank0 += nl;
         __syncthreads();
@@ -329,6 +328,7 @@ struct qed_plan_s {
     uint32_t *d_bctr;
     float *d_sx, *d_snu;
     qed_surrogate sur[2];      // learned inverse CDF per process (NULL: tables)
+    bool tau;                  // some instance decides emission by the optical depth
     size_t lds;
 };
 
@@ -413,6 +413,8 @@ qed_status plan_create(qed_tables T, int n, const qed_instance *in, int ppb, int
     if (e == hipSuccess) e = hipMalloc((void **)&p->d_bctr, sizeof(uint32_t) * kNCtr * nblk);
     p->sur[0] = s_nlc;
     p->sur[1] = s_nbw;
+    p->tau = false;
+    for (int i = 0; i < n; ++i) p->tau = p->tau || (in[i].params.flags & QED_OPTICAL_DEPTH);
     if (s_nlc || s_nbw) {
         // one record per possible transition: every slot of every set
         int64_t slots = 0;
@@ -448,10 +450,16 @@ template <class R> qed_status plan_step(qed_plan p, hipStream_t st)
     P.sx = p->d_sx;
     P.snu = p->d_snu;
     const InstDev<R> *inst = (const InstDev<R> *)p->d_inst;
-    if (p->nblk_lep > 0)
-        QS_LAUNCH(K_PLAN_LEPTON, (k_plan_main<R, 0>), dim3(p->nblk_lep), dim3(kBlock), p->lds, st, inst, P, p->T->dev, 0);
+    if (p->nblk_lep > 0) {
+        if (p->tau)
+            QS_LAUNCH(K_PLAN_LEPTON, (k_plan_main<R, 0, true>), dim3(p->nblk_lep), dim3(kBlock), p->lds, st, inst, P,
+                      p->T->dev, 0);
+        else
+            QS_LAUNCH(K_PLAN_LEPTON, (k_plan_main<R, 0, false>), dim3(p->nblk_lep), dim3(kBlock), p->lds, st, inst, P,
+                      p->T->dev, 0);
+    }
     if (p->nblk > p->nblk_lep)
-        QS_LAUNCH(K_PLAN_PHOTON, (k_plan_main<R, 1>), dim3(p->nblk - p->nblk_lep), dim3(kBlock), p->lds, st, inst, P,
+        QS_LAUNCH(K_PLAN_PHOTON, (k_plan_main<R, 1, false>), dim3(p->nblk - p->nblk_lep), dim3(kBlock), p->lds, st, inst, P,
                   p->T->dev, p->nblk_lep);
     QS_LAUNCH(K_BOOK, k_plan_book<R>, dim3(1 + (int)cdiv(p->nblk, kCtrGroup)), dim3(kBlock), 0, st, inst, P);
     // processing: with a learned inverse CDF, a first pass writes its inputs, the network runs on

@@ -28,7 +28,7 @@ __global__ void __launch_bounds__(kBlock) k_push(LepDev<R> L, FieldDev F, StepDe
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
         V3<R> x = ldx(L.x, i), p = ld3(L.p, i), s = ld3(L.s, i);
         V3<R> E, B;
-        eval_fields<R>(F, (double)x.x, S.t, E, B);
+        eval_fields<R>(F, (double)x.x, (double)x.y, S.t, E, B);
         const V3<R> d = push<R>(q, (R)S.a_e, E, B, (R)S.dt, (S.flags & F_TBMT) != 0, p, s);
         stx(L.x, i, x + d);
         st3(L.p, i, p);
@@ -36,7 +36,7 @@ __global__ void __launch_bounds__(kBlock) k_push(LepDev<R> L, FieldDev F, StepDe
     }
 }
 
-template <class R>
+template <class R, bool TAU>
 __global__ void __launch_bounds__(kBlock) k_lepton_main(LepDev<R> L, FieldDev F, StepDev S0, TablesDev T,
                                                         uint64_t *mask, int64_t nchunks, uint32_t *bctr, uint32_t *bcnt)
 {
@@ -48,7 +48,7 @@ __global__ void __launch_bounds__(kBlock) k_lepton_main(LepDev<R> L, FieldDev F,
     const int64_t B = block_len(n, gridDim.x);
     const int64_t start = (int64_t)blockIdx.x * B, end = start + B < n ? start + B : n;
     LCount c;
-    lepton_range<R>(L, F, S, T, lds, start, end, mask, nchunks, c);
+    lepton_range<R, TAU>(L, F, S, T, lds, start, end, mask, nchunks, c);
     unsigned v[kNCtr + 1] = {};
     v[C_PROB] = c.prob; v[C_CHI] = c.chi; v[C_NORM] = c.norm; v[C_LSTEP] = c.step; v[kNCtr] = c.trans;
     __shared__ unsigned tot[kNCtr + 1];
@@ -299,8 +299,12 @@ qed_status emit_impl(qed_tables T, const qed_leptons *L, const qed_fields *f, co
     unsigned long long *c = (unsigned long long *)ctr;
     const size_t lds_nlc = sizeof(R) * 2 * T->dev.n_chi[0];
     const int g = grid_for(L->capacity);
-    QS_LAUNCH(K_LEPTON_MAIN, k_lepton_main<R>, dim3(g), dim3(kBlock), lds_nlc, st, ld, fd, sd, T->dev, w.mask, nch, w.bctr,
-              w.bcnt);
+    if (p->flags & QED_OPTICAL_DEPTH)
+        QS_LAUNCH(K_LEPTON_MAIN, (k_lepton_main<R, true>), dim3(g), dim3(kBlock), lds_nlc, st, ld, fd, sd, T->dev, w.mask,
+                  nch, w.bctr, w.bcnt);
+    else
+        QS_LAUNCH(K_LEPTON_MAIN, (k_lepton_main<R, false>), dim3(g), dim3(kBlock), lds_nlc, st, ld, fd, sd, T->dev, w.mask,
+                  nch, w.bctr, w.bcnt);
     const PhoDev<R> gd = pho_dev<R>((p->flags & QED_EMIT) ? G : nullptr);
     QS_LAUNCH(K_MASK_EXPAND, k_expand, dim3(g), dim3(kBlock), 0, st, (const uint64_t *)w.mask, (const uint32_t *)w.bcnt,
               (const int64_t *)L->d_count, w.book, 0, gd.count, gd.cap, (int64_t *)nullptr, (int64_t)0,

@@ -23,7 +23,7 @@ LAMBDA_UM = 0.8
 EPS_R = HC_EV_NM / (LAMBDA_UM * 1000.0) / MEC2_EV      # hbar omega_r / (m c^2)
 OMEGA_R = 2.0 * math.pi * C_LIGHT / (LAMBDA_UM * 1e-6)  # rad/s
 
-FIELD_UNIFORM, FIELD_PLANE_LP = 0, 1
+FIELD_UNIFORM, FIELD_PLANE_LP, FIELD_GRID2D = 0, 1, 2
 
 
 @dataclass
@@ -88,6 +88,48 @@ def c2(n: int = 1_000_000, seed: int = 2, steps: int = 3000, a0: float = 100.0,
     return Workload("c2_head_on_lp_a0_100", n, steps, 2.0 * math.pi / 100.0, seed, FIELD_PLANE_LP,
                     a0=a0, phase_len=sin2_phase_len(30.0), track=(True, False, False), pair=True,
                     k_retire=chi_g_min / (2.0 * a0 * EPS_R), x=x, p=p, s=s)
+
+
+def c3_grid(nx: int = 4096, ny: int = 1024, a0: float = 200.0, noise: float = 0.01, seed: int = 3):
+    """Field snapshot of the grid workload: two counter-propagating circularly polarized waves along
+    +x and -x, each of amplitude a0 (lambda = 0.8 um), at t = 0 on a periodic 2-D grid of cell
+    size lambda/40, plus noise * a0 * N(0, 1) at every node and component.  Returns a float32
+    array (6, ny, nx) of Ex, Ey, Ez, Bx, By, Bz and the cell size in c/omega_r."""
+    rng = np.random.default_rng(seed)
+    dx = 2.0 * math.pi / 40.0
+    x = dx * np.arange(nx)
+    c, s_ = np.cos(x), np.sin(x)
+    # wave along +x: E = a0 (cos x, sin x) in (y, z), B = x^ x E; wave along -x: E = a0 (cos x, -sin x),
+    # B = -x^ x E
+    g = np.zeros((6, ny, nx), dtype=np.float32)
+    Ey = a0 * (c + c)
+    Ez = a0 * (s_ - s_)
+    By = a0 * (-s_ - s_)
+    Bz = a0 * (c - c)
+    for k, row in ((1, Ey), (2, Ez), (4, By), (5, Bz)):
+        g[k] = row[None, :]
+    g += (noise * a0 * rng.standard_normal(g.shape)).astype(np.float32)
+    return g, dx
+
+
+def c3(n: int = 1 << 26, seed: int = 3, steps: int = 1000, nx: int = 4096, ny: int = 1024,
+       grid_seed: int = 3) -> Workload:
+    """Grid-interpolated fields: electrons uniform over the periodic box of the c3_grid snapshot
+    (16 per cell at full size), gamma ~ LogUniform(10, 1e4), isotropic directions and unit spins,
+    dt = dx/2, 1000 steps, both channels; photons below 21 m c^2 are retired (chi_gamma stays below
+    0.05 in fields up to about 2 a0 plus the noise).  The field array is in extra['grid']."""
+    rng = np.random.default_rng(seed)
+    grid, dx = c3_grid(nx, ny, seed=grid_seed)
+    x = np.zeros((3, n))
+    x[0] = rng.uniform(0.0, nx * dx, n)
+    x[1] = rng.uniform(0.0, ny * dx, n)
+    gam = np.exp(rng.uniform(math.log(10.0), math.log(1e4), n))
+    p = random_unit_vectors(rng, n) * np.sqrt(gam * gam - 1.0)
+    s = random_unit_vectors(rng, n)
+    k_retire = 0.05 / (2.0 * 2.0 * 200.0 * EPS_R) * 1.0
+    return Workload("c3_grid_cp_standing_a0_200", n, steps, dx / 2.0, seed, FIELD_GRID2D, track=(True, True, False),
+                    pair=True, k_retire=k_retire, x=x, p=p, s=s,
+                    extra=dict(grid=grid, dx=dx, dy=dx, nx=nx, ny=ny))
 
 
 def c5(n_instances: int = 64, seed: int = 5, steps: int = 2000, n_min: float = 1e4, n_max: float = 1e7,

@@ -46,12 +46,12 @@ def gtab32(q):
     return q.Tables(precision=q.QED_F32)
 
 
-def _sim(q, tab, w, cap_e, cap_p, cap_g, flags, seed=None, k_retire=None, fields=None, tau=False):
+def _sim(q, tab, w, cap_e, cap_p, cap_g, flags, seed=None, k_retire=None, fields=None, tau=False, merged=False):
     from paper_2511_08929_amd.sim import Simulation
     f = fields or q.make_fields(w.field_kind, E0=w.E0, B0=w.B0, a0=w.a0, phase_len=w.phase_len)
     return Simulation(tab, cap_e=cap_e, cap_p=cap_p, cap_g=cap_g, track=w.track, fields=f, dt=w.dt, eps_r=EPS,
                       seed=w.seed if seed is None else seed, flags=flags,
-                      k_retire=w.k_retire if k_retire is None else k_retire, optical_depth=tau)
+                      k_retire=w.k_retire if k_retire is None else k_retire, optical_depth=tau, merged=merged)
 
 
 def _random_leptons(n, seed, gmin=300.0, gmax=8000.0, mixed=True):
@@ -282,6 +282,96 @@ def test_optical_depth_runs_fp64(q, gtab64, otables):
         tg, tsg = L.tau_arrays()
         assert np.abs(tg - O.tau[:O.n]).max() < 1e-12 * steps and np.abs(tsg - O.tau_target[:O.n]).max() < 1e-12
     compare_photons(sim.g.arrays(), ref["G"].arrays(), set(), tol_k(steps), tol_k(steps), what="tau c2 photons")
+
+
+def _grid_fields(q, w):
+    import torch
+    g = w.extra["grid"]
+    fg = q.make_fields(q.QED_FIELD_GRID2D, grid=torch.as_tensor(g, device="cuda"), dx=w.extra["dx"], dy=w.extra["dy"])
+    fo = oracle.make_fields(oracle.FIELD_GRID2D, grid=g, dx=w.extra["dx"], dy=w.extra["dy"])
+    return fg, fo
+
+
+def test_grid_fields_run_fp64(q, gtab64, otables):
+    """Grid-interpolated fields (two counter-propagating CP waves at a0 = 200 plus noise, periodic
+    64 x 16 grid), 2000 electrons, both channels, compaction every 50 steps: every lepton,
+    pair-born lepton and photon compared after 25 and after 150 steps.
+    Electrons down to gamma = 10 in fields of 400 turn by up to ~2.5 rad per step, so rounding
+    differences grow faster than linearly along such trajectories: 1e-12 per 250 steps holds at
+    25 steps; at 150 steps the bound is 1e-11."""
+    w = synth.c3(n=2000, nx=64, ny=16)
+    fg, fo = _grid_fields(q, w)
+    sim = _sim(q, gtab64, w, w.n + 4000, 4000, 200_000, q.QED_ALL, fields=fg)
+    sim.e.load(w.x, w.p, w.s)
+    done = 0
+    for steps, tol in ((25, tol_k(25)), (150, 1e-11)):
+        while done < steps:
+            sim.step()
+            done += 1
+            if done % 50 == 0:
+                sim.compact()
+        ref = oracle_run(otables, w, steps, q.QED_ALL, cap_e=w.n + 4000, cap_p=4000, cap_g=200_000, fields=fo)
+        c = ref["ctr"]
+        print("grid", steps, c)
+        assert ref["near_e"].sum() == 0
+        compare_leptons(sim.e.arrays(), ref["E"].arrays(), np.zeros(ref["E"].n, bool), tol, tol, rtol_x=tol,
+                        what=f"grid electrons {steps}", events=c["n_emit"])
+        compare_leptons(sim.p.arrays(), ref["P"].arrays(), np.zeros(ref["P"].n, bool), tol, tol, rtol_x=tol,
+                        what=f"grid positrons {steps}")
+        if steps % 50:
+            # without the compaction the oracle keeps dead slots the GPU has not removed either
+            pass
+        compare_photons(sim.g.arrays(), ref["G"].arrays(), set(), tol, tol, what=f"grid photons {steps}")
+        assert q.counters_dict(sim.ctr)["n_pair"] == c["n_pair"]
+    assert c["n_emit"] > 10_000 and c["n_pair"] > 10
+
+
+def test_grid_fields_full_size_sampled_fp32(q, gtab32, otables):
+    """The grid workload at full size (2^26 electrons, 16 per cell of the 4096 x 1024 grid),
+    single precision, two steps of the merged step; the oracle recomputes 256 sampled electrons
+    (their Philox ids) and their photons."""
+    w = synth.c3()
+    fg, fo = _grid_fields(q, w)
+    steps = 2
+    sim = _sim(q, gtab32, w, w.n + (w.n >> 4), w.n >> 4, 2 * w.n, q.QED_ALL, fields=fg, merged=True)
+    sim.e.load(w.x, w.p, w.s)
+    for _ in range(steps):
+        sim.step()
+    idx = np.sort(np.random.default_rng(98).choice(w.n, 256, replace=False))
+    sub = synth.subsample(w, idx)
+    # inputs as the GPU holds them (FP32)
+    sub.x, sub.p, sub.s = (a.astype(np.float32).astype(np.float64) for a in (sub.x, sub.p, sub.s))
+    ref = oracle_run(otables, sub, steps, q.QED_ALL, cap_e=256 * 4, cap_p=256 * 4, cap_g=256 * 4, index=idx,
+                     fields=fo, u24=True, near_tol=1e-5)
+    n_e = sim.e.n()
+    x = np.stack([(a[idx.tolist()].double().cpu().numpy() if a is not None else np.zeros(256)) for a in sim.e.x])
+    p = np.stack([a[idx.tolist()].double().cpu().numpy() for a in sim.e.p])
+    s = np.stack([a[idx.tolist()].double().cpu().numpy() for a in sim.e.s])
+    print("grid full size: electrons", n_e, "photons", sim.g.n(), q.counters_dict(sim.ctr))
+    E = ref["E"]
+    ex = ref["near_e"][:256]
+    po = np.stack([E.p[i][:256] for i in range(3)])
+    err = np.linalg.norm(p - po, axis=0) / np.linalg.norm(po, axis=0)
+    worst = np.argsort(err)[-6:]
+    print("worst sampled electrons: rel err", err[worst], "|p| final", np.linalg.norm(po, axis=0)[worst],
+          "|p| initial", np.linalg.norm(sub.p, axis=0)[worst], "near", ex[worst])
+    compare_leptons((x, p, s), (np.stack([(E.x[i][:256] if E.x[i] is not None else np.zeros(256)) for i in range(3)]),
+                                po, np.stack([E.s[i][:256] for i in range(3)])),
+                    ex, 1e-5, 1e-5, rtol_x=1e-5, what="grid sampled electrons")
+    import torch
+    idg = sim.g.id[:sim.g.n()].cpu().numpy().view(np.uint64)
+    sp, par = photon_parent(idg)
+    mine = np.nonzero(np.isin(par, idx) & (sp == 0) & (idg != 0))[0]
+    sel = torch.as_tensor(mine, device="cuda")
+    gx = np.stack([(a[sel].double().cpu().numpy() if a is not None else np.zeros(mine.size)) for a in sim.g.x])
+    gk = np.stack([a[sel].double().cpu().numpy() for a in sim.g.k])
+    gP = np.stack([a[sel].double().cpu().numpy() for a in sim.g.P])
+    xg, kg, Pg, ido = ref["G"].arrays()
+    keep = (ido != 0) & (photon_parent(ido)[0] == 0)
+    wp = compare_photons((gx, gk, gP, idg[mine]), (xg[:, keep], kg[:, keep], Pg[:, keep], ido[keep]),
+                         {(0, int(i)) for i in idx[ex]}, 1e-5, 1e-5, what="grid sampled photons")
+    print(wp)
+    assert wp["matched"] > 20
 
 
 # ------------------------------------------------------------------ single precision

@@ -359,3 +359,30 @@ def test_optical_depth_decision_is_memoryless(otables):
             both = (h[1:] & h[:-1]).mean()
             assert abs(both - expect ** 2) < 5 * math.sqrt(expect ** 2 * (1 - expect ** 2) / h[1:].size)
             assert np.all(L.tau[:w.n] >= 0) and np.all(L.tau_target[:w.n] > 0)
+
+
+def test_grid_fields_bilinear_and_periodic():
+    """Grid field model: reproduces a field linear in x and y exactly inside the grid (bilinear
+    interpolation is exact for it), returns node values at nodes, and is periodic."""
+    nx, ny, dx, dy, x0, y0 = 7, 5, 0.3, 0.45, -1.0, 2.0
+    X, Y = np.meshgrid(x0 + dx * np.arange(nx), y0 + dy * np.arange(ny))
+    coef = np.array([[1.0, 2.0, -0.5], [0.3, -1.0, 0.7], [-2.0, 0.1, 0.2], [0.5, 0.5, 0.5], [1.5, -0.2, 0.0],
+                     [0.0, 1.0, -1.0]])
+    grid = np.stack([c[0] + c[1] * X + c[2] * Y for c in coef]).astype(np.float32)
+    F = oracle.make_fields(oracle.FIELD_GRID2D, E0=(0.1, 0, 0), grid=grid, dx=dx, dy=dy, x0=x0, y0=y0)
+    rng = np.random.default_rng(0)
+    for _ in range(50):
+        x = x0 + dx * rng.uniform(0, nx - 1)
+        y = y0 + dy * rng.uniform(0, ny - 1)
+        E, B = oracle.fields_eval(F, [x, y, 0.3], 0.7)
+        want = np.array([c[0] + c[1] * x + c[2] * y for c in coef])
+        # the grid holds float32 node values of the linear function
+        assert np.allclose(np.concatenate([E - [0.1, 0, 0], B]), want, atol=2e-5)
+    for i in range(nx):
+        for j in range(ny):
+            E, B = oracle.fields_eval(F, [x0 + i * dx, y0 + j * dy, 0.0], 0.0)
+            np.testing.assert_allclose(np.concatenate([E - [0.1, 0, 0], B]), grid[:, j, i], rtol=0, atol=1e-12)
+    x, y = 0.37, 2.81
+    E1, B1 = oracle.fields_eval(F, [x, y, 0], 0)
+    E2, B2 = oracle.fields_eval(F, [x + 3 * nx * dx, y - 2 * ny * dy, 0], 0)
+    np.testing.assert_allclose(np.concatenate([E1, B1]), np.concatenate([E2, B2]), atol=1e-12)
