@@ -9,9 +9,11 @@ import oracle
 
 def oracle_run(tables, w, steps, flags, *, cap_e=None, cap_p=None, cap_g=None, u24=False, near_tol=1e-10,
                index=None, seed=None, k_retire=None, t0=0.0, nthreads=16, x=None, p=None, s=None,
-               fields=None, step0=0, tau=False):
+               fields=None, step0=0, tau=False, round32=False):
     """Run the oracle for `steps` steps of workload `w` (optionally a subset with original indices
-    `index`).  Returns dict of oracle sets, counters and accumulated near-tie flags."""
+    `index`).  Returns dict of oracle sets, counters and accumulated near-tie flags.
+    round32: round the stored particle state (x, p, s, k, P) to FP32 after every step, as the
+    single-precision path stores it, so that a comparison measures one step's arithmetic."""
     x = w.x if x is None else x
     p = w.p if p is None else p
     s = w.s if s is None else s
@@ -40,6 +42,14 @@ def oracle_run(tables, w, steps, flags, *, cap_e=None, cap_p=None, cap_g=None, u
             near_p |= P.near.astype(bool)
             oracle.photon_step(tables, prm, F, G, E, P, ctr, nthreads)
             near_g |= G.near.astype(bool)
+        if round32:
+            for S_ in (E, P):
+                for arr in list(S_.x) + list(S_.p) + list(S_.s):
+                    if arr is not None:
+                        arr[:] = arr.astype(np.float32)
+            for arr in list(G.x) + list(G.k) + list(G.P):
+                if arr is not None:
+                    arr[:] = arr.astype(np.float32)
     return dict(E=E, P=P, G=G, ctr=ctr.as_dict(), near_e=near_e[:E.n], near_p=near_p[:P.n], near_g=near_g[:G.n])
 
 
@@ -53,9 +63,11 @@ def rel_vec_err(a, b, floor=1e-300):
     return np.linalg.norm(a - b, axis=0) / np.maximum(np.linalg.norm(b, axis=0), floor)
 
 
-def compare_leptons(gpu, orc, exclude, rtol_p, atol_s, rtol_x=None, what="", events=None):
+def compare_leptons(gpu, orc, exclude, rtol_p, atol_s, rtol_x=None, what="", events=None, outlier_rate=1e-5):
     """events: number of spin collapses behind the compared spins (default: one per particle);
-    the ill-conditioned collapse axis allows one spin in 1e5 collapses above atol_s."""
+    the ill-conditioned collapse axis allows a fraction outlier_rate of them above atol_s (1e-5 in
+    FP64; in FP32, whose rounding is 1e9 times larger, axes with conditioning above ~100 exceed
+    1e-5, so single-precision checks pass 1e-2)."""
     xg, pg, sg = gpu
     xo, po, so = orc
     assert pg.shape == po.shape, f"{what}: count {pg.shape[1]} vs oracle {po.shape[1]}"
@@ -67,7 +79,7 @@ def compare_leptons(gpu, orc, exclude, rtol_p, atol_s, rtol_x=None, what="", eve
                  s_over_tol=int((es > atol_s).sum()))
     assert worst["p"] <= rtol_p, f"{what}: momentum rel err {worst['p']:.3e} (argmax {int(np.argmax(ep))})"
     # the spin axis g/|g| of the collapse has the same conditioning as the photon axis
-    allowed = max(1, (es.size if events is None else events) // 100_000)
+    allowed = max(1, int((es.size if events is None else events) * outlier_rate))
     assert worst["s_over_tol"] <= allowed and worst["s"] <= 1e3 * atol_s, \
         f"{what}: spin err {worst['s']:.3e} (argmax {int(np.argmax(es))}, {worst['s_over_tol']} over tol)"
     if rtol_x is not None:
@@ -115,6 +127,8 @@ def compare_photons(gpu, orc, excluded_parents, rtol_k, atol_P, what="", near_ph
     eP = director_err(Pgs, Pos, kos)
     worst = dict(k=float(ek.max(initial=0)), P=float(eP.max(initial=0)), matched=int(keep.sum()),
                  unmatched=int(only.size), P_over_tol=int((eP > atol_P).sum()),
+                 P_median=float(np.median(eP)) if eP.size else 0.0,
+                 P_90=float(np.quantile(eP, 0.9)) if eP.size else 0.0,
                  P_999999=float(np.quantile(eP, 0.999999)) if eP.size else 0.0)
     assert worst["k"] <= rtol_k, f"{what}: photon momentum rel err {worst['k']:.3e}"
     # The polarization axis F/|F| is ill-conditioned where the photon's polarization degree
