@@ -262,6 +262,7 @@ typedef struct {
     qed_surrogate icdf_nbw;      /* ... for the pair split.  Only with QED_F32 tables, and built on
                                     the same tables (else QED_ERR_UNSUPPORTED / QED_ERR_INVALID).
                                     The plan keeps a scratch of 16 bytes per particle slot. */
+    int process_group;           /* streaming blocks whose transitions one block processes, default 4 */
 } qed_plan_config;
 
 typedef struct qed_plan_s *qed_plan;   /* opaque, library-owned */

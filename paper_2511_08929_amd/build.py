@@ -16,6 +16,10 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC", "-shared",
          # FP32 division and square root by the hardware approximations (FP64 is unaffected)
          "-fno-hip-fp32-correctly-rounded-divide-sqrt",
+         # fused multiply-add only where one source expression has the form a*b+c: the same
+         # function inlined into different kernels then rounds the same way, so the per-species
+         # calls and the merged step agree bit for bit
+         "-ffp-contract=on",
          # keep packed FP32 instructions out of the generated code
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-Wall", "-Wno-unused-function", "-Wno-unused-variable"]

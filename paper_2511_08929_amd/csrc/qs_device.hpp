@@ -209,11 +209,12 @@ template <class R> __device__ __forceinline__ void add_grid(const FieldDev &f, d
 }
 
 // E and B at position (x, y) (the plane wave depends on x only, the grid on x and y) and time t.
-template <class R> __device__ __forceinline__ void eval_fields(const FieldDev &f, double x0, double y0, double t, V3<R> &E,
-                                                              V3<R> &B);
+// GRID: compiled with the grid model (kernels without it keep fewer registers live).
+template <class R, bool GRID> struct FieldEval;
 
-template <> __device__ __forceinline__ void eval_fields<double>(const FieldDev &f, double x0, double y0, double t,
-                                                                V3<double> &E, V3<double> &B)
+template <bool GRID> struct FieldEval<double, GRID> {
+static __device__ __forceinline__ void eval(const FieldDev &f, double x0, double y0, double t, V3<double> &E,
+                                            V3<double> &B)
 {
     E = {f.E0[0], f.E0[1], f.E0[2]};
     B = {f.B0[0], f.B0[1], f.B0[2]};
@@ -228,15 +229,17 @@ template <> __device__ __forceinline__ void eval_fields<double>(const FieldDev &
         const double ey = f.a0 * g * cos(phi);
         E.y += ey;
         B.z -= ey;
-    } else if (f.kind == 2) {
+    } else if (GRID && f.kind == 2) {
         add_grid<double>(f, x0, y0, E, B);
     }
 }
+};
 
 // single precision: the phase is formed and reduced to revolutions in FP64; the sine and
 // cosine of the reduced argument use the hardware instructions (|argument| <= 1 revolution)
-template <> __device__ __forceinline__ void eval_fields<float>(const FieldDev &f, double x0, double y0, double t,
-                                                               V3<float> &E, V3<float> &B)
+template <bool GRID> struct FieldEval<float, GRID> {
+static __device__ __forceinline__ void eval(const FieldDev &f, double x0, double y0, double t, V3<float> &E,
+                                            V3<float> &B)
 {
     E = {(float)f.E0[0], (float)f.E0[1], (float)f.E0[2]};
     B = {(float)f.B0[0], (float)f.B0[1], (float)f.B0[2]};
@@ -254,9 +257,16 @@ template <> __device__ __forceinline__ void eval_fields<float>(const FieldDev &f
         const float ey = (float)f.a0 * g * __builtin_amdgcn_cosf(red);
         E.y += ey;
         B.z -= ey;
-    } else if (f.kind == 2) {
+    } else if (GRID && f.kind == 2) {
         add_grid<float>(f, x0, y0, E, B);
     }
+}
+};
+
+template <class R, bool GRID = true>
+__device__ __forceinline__ void eval_fields(const FieldDev &f, double x0, double y0, double t, V3<R> &E, V3<R> &B)
+{
+    FieldEval<R, GRID>::eval(f, x0, y0, t, E, B);
 }
 
 // ------------------------------------------------------------------ push (Boris + T-BMT)

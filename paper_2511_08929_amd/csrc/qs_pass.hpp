@@ -284,7 +284,7 @@ struct LCount { unsigned prob = 0, chi = 0, norm = 0, step = 0, trans = 0; };
 // t + dt, chi and the decision (NLC section); a non-emitter gets the no-transition spin update
 // (non-transition section).  Stores x, p, s.  TAU: compiled with the optical-depth decision (the
 // variant without it needs fewer registers).
-template <class R, bool TAU>
+template <class R, bool TAU, bool GRID>
 __device__ __forceinline__ void lepton_item(const LepDev<R> &L, const FieldDev &F, const StepDev &S, const TablesDev &T,
                                             const R *lds, int64_t i, bool &emit, bool &up, LCount &c)
 {
@@ -293,11 +293,11 @@ __device__ __forceinline__ void lepton_item(const LepDev<R> &L, const FieldDev &
     V3<R> x = ldx(L.x, i), p = ld3(L.p, i), s = ld3(L.s, i);
     V3<R> E, B;
     if (S.flags & F_PUSH) {
-        eval_fields<R>(F, (double)x.x, (double)x.y, S.t, E, B);
+        eval_fields<R, GRID>(F, (double)x.x, (double)x.y, S.t, E, B);
         x = x + push<R>(q, (R)S.a_e, E, B, (R)S.dt, (S.flags & F_TBMT) != 0, p, s);
     }
     if (S.flags & F_EMIT) {
-        eval_fields<R>(F, (double)x.x, (double)x.y, S.t + S.dt, E, B);
+        eval_fields<R, GRID>(F, (double)x.x, (double)x.y, S.t + S.dt, E, B);
         const LDecide<R> d = lepton_decide<R>(S, T, lds, L.species, i, p, s, E, B);
         if (d.active) {
             c.chi += d.clamped_chi;
@@ -348,7 +348,7 @@ __device__ __forceinline__ void lepton_item(const LepDev<R> &L, const FieldDev &
 
 // Main pass over the lepton range [start, end) (start a multiple of 64): the wave's decisions
 // and branch choices go to mask[w] and mask[nchunks + w] of its 64-particle word w.
-template <class R, bool TAU>
+template <class R, bool TAU, bool GRID>
 __device__ __forceinline__ void lepton_range(const LepDev<R> &L, const FieldDev &F, const StepDev &S, const TablesDev &T,
                                              const R *lds, int64_t start, int64_t end, uint64_t *mask, int64_t nchunks,
                                              LCount &c)
@@ -357,7 +357,7 @@ __device__ __forceinline__ void lepton_range(const LepDev<R> &L, const FieldDev 
     for (int64_t base = start + (threadIdx.x & ~63); base < end; base += blockDim.x) {
         const int64_t i = base + lane;
         bool emit = false, up = false;
-        if (i < end) lepton_item<R, TAU>(L, F, S, T, lds, i, emit, up, c);
+        if (i < end) lepton_item<R, TAU, GRID>(L, F, S, T, lds, i, emit, up, c);
         const uint64_t m = __ballot(emit), mu = __ballot(up);
         if (lane == 0) {
             mask[base >> 6] = m;
@@ -371,7 +371,7 @@ __device__ __forceinline__ void lepton_range(const LepDev<R> &L, const FieldDev 
 // recoil, spin collapse, Stokes collapse, P-vector; the photon goes to slot `slot` (< 0: no room).
 // With x_out set, only the inputs of the inverse CDF (ln chi, rho, channel sign) are written there;
 // with nu_in set, nu is taken from it instead of the table (learned inverse CDF).
-template <class R>
+template <class R, bool GRID>
 __device__ __forceinline__ void emit_item(const LepDev<R> &L, const PhoDev<R> &G, const FieldDev &F, const StepDev &S,
                                           const TablesDev &T, const R *lds, int64_t i, bool up, int64_t slot,
                                           unsigned &c_ret, const float *nu_in = nullptr, float *x_out = nullptr)
@@ -379,7 +379,7 @@ __device__ __forceinline__ void emit_item(const LepDev<R> &L, const PhoDev<R> &G
     const V3<R> x = ldx(L.x, i);
     V3<R> p = ld3(L.p, i), s = ld3(L.s, i);
     V3<R> E, B;
-    eval_fields<R>(F, (double)x.x, (double)x.y, S.t + S.dt, E, B);
+    eval_fields<R, GRID>(F, (double)x.x, (double)x.y, S.t + S.dt, E, B);
     const LDecide<R> d = lepton_decide<R>(S, T, lds, L.species, i, p, s, E, B);
     const double r2 = (double)d.r2;
     const double rho = log(r2) - log1p(-r2);
@@ -458,7 +458,7 @@ template <class R> struct PhoQueue {
     uint32_t n;
 };
 
-template <class R>
+template <class R, bool GRID>
 __device__ __forceinline__ void photon_tile(const PhoDev<R> &G, const FieldDev &F, const StepDev &S, const TablesDev &T,
                                             const R *lds, PhoQueue<R> &Q, int64_t tile, int64_t tend, uint64_t *mask,
                                             int64_t nchunks, GCount &c)
@@ -489,10 +489,10 @@ __device__ __forceinline__ void photon_tile(const PhoDev<R> &G, const FieldDev &
                     ++c.ret;
                 } else if (qed) {
                     V3<R> E, Bf;
-                    eval_fields<R>(F, (double)x.x, (double)x.y, S.t + S.dt, E, Bf);
+                    eval_fields<R, GRID>(F, (double)x.x, (double)x.y, S.t + S.dt, E, Bf);
                     cand = photon_candidate<R>(S, k0r, E, Bf);
                     xq = x.x;
-                    yq = x.y;
+                    if (GRID) yq = x.y;
                 }
             }
         }
@@ -504,7 +504,7 @@ __device__ __forceinline__ void photon_tile(const PhoDev<R> &G, const FieldDev &
             const uint32_t r = wbase + (uint32_t)__popcll(m & ((1ull << lane) - 1ull));
             Q.idx[r] = (uint32_t)(i - tile);
             Q.x[r] = xq;
-            Q.y[r] = yq;
+            if (GRID) Q.y[r] = yq;
         }
     }
     __syncthreads();
@@ -516,7 +516,7 @@ __device__ __forceinline__ void photon_tile(const PhoDev<R> &G, const FieldDev &
         const V3<R> k = ld3(G.k, i);
         const double k0 = (double)sqrt_r(dot(k, k));
         V3<R> E, Bf;
-        eval_fields<R>(F, (double)Q.x[j], (double)Q.y[j], S.t + S.dt, E, Bf);
+        eval_fields<R, GRID>(F, (double)Q.x[j], GRID ? (double)Q.y[j] : 0.0, S.t + S.dt, E, Bf);
         const V3<R> P = ld3(G.P, i);
         const PDecide<R> d = photon_decide<R>(S, T, lds, id, k, k0, P, E, Bf);
         if (!d.active) continue;
@@ -558,7 +558,7 @@ __device__ __forceinline__ void photon_tile(const PhoDev<R> &G, const FieldDev &
 // Pair processing (NBW section, after the decision): lambda~ from the selected inverse CDF,
 // momenta, correlated spins; the pair goes to slots se (electrons) and sp (positrons) when
 // se >= 0; the photon becomes a dead slot.
-template <class R>
+template <class R, bool GRID>
 __device__ __forceinline__ void pair_item(const PhoDev<R> &G, const LepDev<R> &Le, const LepDev<R> &Lp, const FieldDev &F,
                                           const StepDev &S, const TablesDev &T, const R *lds, int64_t i, bool plus,
                                           int64_t se, int64_t sp, const float *nu_in = nullptr, float *x_out = nullptr)
@@ -567,7 +567,7 @@ __device__ __forceinline__ void pair_item(const PhoDev<R> &G, const LepDev<R> &L
     const V3<R> k = ld3(G.k, i), x = ldx(G.x, i), P = ld3(G.P, i);
     const double k0 = (double)sqrt_r(dot(k, k));
     V3<R> E, B;
-    eval_fields<R>(F, (double)x.x, (double)x.y, S.t + S.dt, E, B);
+    eval_fields<R, GRID>(F, (double)x.x, (double)x.y, S.t + S.dt, E, B);
     const PDecide<R> d = photon_decide<R>(S, T, lds, id, k, k0, P, E, B);
     const double r2 = (double)d.r2;
     const double rho = log(r2) - log1p(-r2);

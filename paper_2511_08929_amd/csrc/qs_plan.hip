@@ -40,7 +40,8 @@ template <class R> struct InstDev {
 struct SegDev {
     int kind;                  // 0 electrons, 1 positrons, 2 photons
     int inst;
-    int b0, nb;                // block range
+    int b0, nb;                // block range of the streaming pass
+    int pb0, npb;              // block range of the processing pass (one block per `group` streaming blocks)
     int64_t mask_off, nchunks; // decision plane at mask + mask_off, branch plane nchunks words later
 };
 
@@ -54,6 +55,7 @@ struct SegBook {
 struct PlanDev {
     const SegDev *seg;
     int nseg, nblk, ninst;
+    int group;                 // streaming blocks per processing block
     uint64_t *mask;
     uint32_t *bcnt;            // [nblk]
     uint32_t *bctr;            // [nblk][kNCtr] event counts of each main block
@@ -69,6 +71,17 @@ __device__ __forceinline__ int seg_of(const SegDev *seg, int nseg, int b)
     while (lo < hi) {
         const int mid = (lo + hi + 1) >> 1;
         if (seg[mid].b0 <= b) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+__device__ __forceinline__ int seg_of_pb(const SegDev *seg, int nseg, int pb)
+{
+    int lo = 0, hi = nseg - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (seg[mid].pb0 <= pb) lo = mid;
         else hi = mid - 1;
     }
     return lo;
@@ -151,29 +164,36 @@ __global__ void __launch_bounds__(kBlock) k_plan_book(const InstDev<R> *inst, Pl
     if (threadIdx.x == kBlock - 1) P.gpre[P.nblk] = off;
     __syncthreads();
     for (int i = threadIdx.x; i < P.ninst; i += blockDim.x) {
+        // every load first (they do not depend on each other), then the arithmetic and the stores
         const InstDev<R> &I = inst[i];
         unsigned long long *ctr = I.ctr;
+        const bool has_g = I.G.count != nullptr, pair = I.sg >= 0;
         const int64_t te = seg_total(P, I.se), tp = seg_total(P, I.sp), tg = seg_total(P, I.sg);
         const int64_t ne = *I.E.count;
         const int64_t np = I.sp >= 0 ? *I.P.count : 0;
-        // emission: photons of electrons, then of positrons
+        const int64_t gb = has_g ? *I.G.count : 0;
+        const int64_t ng = pair ? *I.G.count_prev : 0;
+        int64_t *clk = const_cast<int64_t *>(I.S.clock);
+        const int64_t clock = clk ? *clk : 0;
         int64_t over = 0;
-        if (I.G.count) {
-            const int64_t gb = *I.G.count;
+        // emission: photons of electrons, then of positrons
+        if (has_g) {
             const int64_t room = I.G.cap - gb > 0 ? I.G.cap - gb : 0;
             const int64_t nfe = te < room ? te : room;
             const int64_t nfp = tp < room - nfe ? tp : room - nfe;
-            *I.G.count = gb + nfe + nfp;
+            const int64_t gnew = gb + nfe + nfp;
+            *I.G.count = gnew;
             P.sbook[I.se] = SegBook{ne, gb, 0, te, nfe};
             if (I.sp >= 0) P.sbook[I.sp] = SegBook{np, gb + nfe, 0, tp, nfp};
             over += (te - nfe) + (tp - nfp);
             if (te + tp) atomicAdd(ctr + C_EMIT, (unsigned long long)(te + tp));
+            // photons born in this step wait for the next one
+            if (pair) *I.G.count_prev = gnew;
         } else {
             P.sbook[I.se] = SegBook{ne, 0, 0, te, 0};
         }
         // pairs of the photons stepped in this pass, appended after the leptons stepped in it
-        if (I.sg >= 0) {
-            const int64_t ng = *I.G.count_prev;
+        if (pair) {
             int64_t room = I.E.cap - ne < I.P.cap - np ? I.E.cap - ne : I.P.cap - np;
             room = room > 0 ? room : 0;
             const int64_t nfg = tg < room ? tg : room;
@@ -182,24 +202,17 @@ __global__ void __launch_bounds__(kBlock) k_plan_book(const InstDev<R> *inst, Pl
             P.sbook[I.sg] = SegBook{ng, ne, np, tg, nfg};
             over += tg - nfg;
             if (tg) atomicAdd(ctr + C_PAIR, (unsigned long long)tg);
-            // photons born in this step wait for the next one
-            *I.G.count_prev = *I.G.count;
         }
         if (over) atomicAdd(ctr + C_OVER, (unsigned long long)over);
-        if (I.S.clock) {
-            int64_t *clk = const_cast<int64_t *>(I.S.clock);
-            P.clock_used[i] = *clk;
-            *clk += 1;
-        } else {
-            P.clock_used[i] = 0;
-        }
+        P.clock_used[i] = clock;
+        if (clk) *clk = clock + 1;
     }
 }
 
 // The streaming pass runs as two launches with their own register allocation: PHO = 0 over the
 // lepton segments (blocks [0, nblk_lep)), PHO = 1 over the photon segments (the rest).
-template <class R, int PHO, bool TAU>
-__global__ void __launch_bounds__(kBlock) k_plan_main(const InstDev<R> *inst, PlanDev P, TablesDev T, int b_first)
+template <class R, int PHO, bool TAU, bool GRID>
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 ? 4 : 1))) k_plan_main(const InstDev<R> *inst, PlanDev P, TablesDev T, int b_first)
 {
     extern __shared__ unsigned char smem_raw[];
     R *lds = reinterpret_cast<R *>(smem_raw);
@@ -222,7 +235,7 @@ __global__ void __launch_bounds__(kBlock) k_plan_main(const InstDev<R> *inst, Pl
         const int64_t B = block_len(n, sg.nb);
         const int64_t start = (int64_t)(b - sg.b0) * B, end = start + B < n ? start + B : n;
         LCount c;
-        lepton_range<R, TAU>(L, F, S, T, lds, start, end, mask, sg.nchunks, c);
+        lepton_range<R, TAU, GRID>(L, F, S, T, lds, start, end, mask, sg.nchunks, c);
         v[C_PROB] = c.prob; v[C_CHI] = c.chi; v[C_NORM] = c.norm; v[C_LSTEP] = c.step; v[kNCtr] = c.trans;
     } else {
         const PhoDev<R> G = Ip->G;
@@ -232,7 +245,8 @@ __global__ void __launch_bounds__(kBlock) k_plan_main(const InstDev<R> *inst, Pl
         const int64_t start = (int64_t)(b - sg.b0) * B, end = start + B < n ? start + B : n;
         GCount c;
         for (int64_t tile = start; tile < end; tile += kPhoTile)
-            photon_tile<R>(G, F, S, T, lds, Q, tile, tile + kPhoTile < end ? tile + kPhoTile : end, mask, sg.nchunks, c);
+            photon_tile<R, GRID>(G, F, S, T, lds, Q, tile, tile + kPhoTile < end ? tile + kPhoTile : end, mask, sg.nchunks,
+                                 c);
         v[C_PROB] = c.prob; v[C_CHI] = c.chi; v[C_NORM] = c.norm; v[C_RETIRED] = c.ret; v[C_GSTEP] = c.step;
         v[C_GQED] = c.qed; v[kNCtr] = c.trans;
     }
@@ -243,9 +257,10 @@ __global__ void __launch_bounds__(kBlock) k_plan_main(const InstDev<R> *inst, Pl
 
 constexpr int kExpandWords = 64;   // mask words expanded per round of the process pass (4096 slots)
 
-// mode 0: tables; 1: write the inverse-CDF inputs of every transition (learned inverse CDF);
-// 2: finish the transitions with the learned nu
-template <class R, int PHO>
+// One launch over the processing blocks of every set (lepton sets first, then photons); the
+// channel follows the block's set.  mode 0: tables; 1: write the inverse-CDF inputs of every
+// transition (learned inverse CDF); 2: finish the transitions with the learned nu.
+template <class R, bool GRID>
 __global__ void __launch_bounds__(kBlock) k_plan_process(const InstDev<R> *inst, PlanDev P, TablesDev T, int b_first,
                                                          int mode)
 {
@@ -253,22 +268,27 @@ __global__ void __launch_bounds__(kBlock) k_plan_process(const InstDev<R> *inst,
     R *lds = reinterpret_cast<R *>(smem_raw);
     __shared__ uint16_t list[kExpandWords * 64];
     __shared__ uint32_t nlist;
-    const int b = b_first + blockIdx.x;
-    if (P.gpre[b + 1] == P.gpre[b]) return;           // no transition in this block's range
-    const int sj = seg_of(P.seg, P.nseg, b);
+    // this block covers the streaming blocks [mb0, mb1) of one segment: a contiguous slot range
+    const int pb = b_first + blockIdx.x;
+    const int sj = seg_of_pb(P.seg, P.nseg, pb);
     const SegDev sg = P.seg[sj];
+    const int mb0 = sg.b0 + (pb - sg.pb0) * P.group;
+    const int mb1 = mb0 + P.group < sg.b0 + sg.nb ? mb0 + P.group : sg.b0 + sg.nb;
+    if (P.gpre[mb1] == P.gpre[mb0]) return;           // no transition in this range
     const InstDev<R> *Ip = inst + sg.inst;
     StepDev S = Ip->S;
     S.step += P.clock_used[sg.inst];
     S.t += (double)P.clock_used[sg.inst] * S.dt;
     const FieldDev F = Ip->F;
     const SegBook bk = P.sbook[sj];
+    const int PHO = sg.kind == 2;
     stage_rates<R>(T, PHO, lds);
     const uint64_t *mask = P.mask + sg.mask_off;
     const int64_t n = bk.n_main;
     const int64_t B = block_len(n, sg.nb);
-    const int64_t start = (int64_t)(b - sg.b0) * B, end = start + B < n ? start + B : n;
-    int64_t rank0 = (int64_t)P.gpre[b] - (int64_t)P.gpre[sg.b0];
+    const int64_t start = (int64_t)(mb0 - sg.b0) * B;
+    const int64_t end = (int64_t)(mb1 - sg.b0) * B < n ? (int64_t)(mb1 - sg.b0) * B : n;
+    int64_t rank0 = (int64_t)P.gpre[mb0] - (int64_t)P.gpre[sg.b0];
     const int lane = threadIdx.x & 63;
     unsigned c_ret = 0;
     for (int64_t c0 = start >> 6; c0 < cdiv(end, 64); c0 += kExpandWords) {
@@ -302,10 +322,10 @@ __global__ void __launch_bounds__(kBlock) k_plan_process(const InstDev<R> *inst,
             const float *nu_in = mode == 2 ? P.snu + gr : nullptr;
             float *x_out = mode == 1 ? P.sx + 3 * gr : nullptr;
             if (!PHO)
-                emit_item<R>(sg.kind == 0 ? Ip->E : Ip->P, Ip->G, F, S, T, lds, i, br, r < bk.nfit ? bk.base + r : -1,
+                emit_item<R, GRID>(sg.kind == 0 ? Ip->E : Ip->P, Ip->G, F, S, T, lds, i, br, r < bk.nfit ? bk.base + r : -1,
                              c_ret, nu_in, x_out);
             else
-                pair_item<R>(Ip->G, Ip->E, Ip->P, F, S, T, lds, i, br, r < bk.nfit ? bk.base + r : -1, bk.base2 + r, nu_in,
+                pair_item<R, GRID>(Ip->G, Ip->E, Ip->P, F, S, T, lds, i, br, r < bk.nfit ? bk.base + r : -1, bk.base2 + r, nu_in,
                              x_out);
         }
         rank0 += nl;
@@ -318,7 +338,7 @@ __global__ void __launch_bounds__(kBlock) k_plan_process(const InstDev<R> *inst,
 
 struct qed_plan_s {
     qed_tables T;
-    int ninst, nseg, nblk, nblk_lep;
+    int ninst, nseg, nblk, nblk_lep, npb, npb_lep, group;
     void *d_inst;
     SegDev *d_seg;
     uint64_t *d_mask;
@@ -329,6 +349,7 @@ struct qed_plan_s {
     float *d_sx, *d_snu;
     qed_surrogate sur[2];      // learned inverse CDF per process (NULL: tables)
     bool tau;                  // some instance decides emission by the optical depth
+    bool grid;                 // some instance uses the grid field model
     size_t lds;
 };
 
@@ -365,12 +386,13 @@ void plan_free(qed_plan p)
 }
 
 template <class R>
-qed_status plan_create(qed_tables T, int n, const qed_instance *in, int ppb, int maxb, qed_surrogate s_nlc,
+qed_status plan_create(qed_tables T, int n, const qed_instance *in, int ppb, int maxb, int group, qed_surrogate s_nlc,
                        qed_surrogate s_nbw, qed_plan *out)
 {
     std::vector<InstDev<R>> inst(n);
     std::vector<SegDev> seg;
     int64_t nblk = 0, mask_words = 0;
+    int64_t npb = 0;
     auto add = [&](int kind, int i, int64_t cap) {
         SegDev s;
         s.kind = kind;
@@ -378,6 +400,9 @@ qed_status plan_create(qed_tables T, int n, const qed_instance *in, int ppb, int
         const int64_t want = cdiv(cap > 0 ? cap : 1, ppb);
         s.nb = (int)(want < maxb ? want : maxb);
         s.b0 = (int)nblk;
+        s.npb = (int)cdiv(s.nb, group);
+        s.pb0 = (int)npb;
+        npb += s.npb;
         s.nchunks = cdiv(cap > 0 ? cap : 1, 64);
         s.mask_off = mask_words;
         nblk += s.nb;
@@ -391,7 +416,7 @@ qed_status plan_create(qed_tables T, int n, const qed_instance *in, int ppb, int
         inst[i].se = add(0, i, in[i].electrons.capacity);
         if (in[i].params.flags & QED_PAIR) inst[i].sp = add(1, i, in[i].positrons.capacity);
     }
-    const int64_t nblk_lep = nblk;
+    const int64_t nblk_lep = nblk, npb_lep = npb;
     for (int i = 0; i < n; ++i)
         if (in[i].params.flags & QED_PAIR) inst[i].sg = add(2, i, in[i].photons.capacity);
     if (nblk > (1 << 24)) return QED_ERR_INVALID;
@@ -402,6 +427,9 @@ qed_status plan_create(qed_tables T, int n, const qed_instance *in, int ppb, int
     p->nseg = (int)seg.size();
     p->nblk = (int)nblk;
     p->nblk_lep = (int)nblk_lep;
+    p->npb = (int)npb;
+    p->npb_lep = (int)npb_lep;
+    p->group = group;
     p->lds = sizeof(R) * 2 * (T->dev.n_chi[0] > T->dev.n_chi[1] ? T->dev.n_chi[0] : T->dev.n_chi[1]);
     hipError_t e = hipMalloc(&p->d_inst, sizeof(InstDev<R>) * n);
     if (e == hipSuccess) e = hipMalloc((void **)&p->d_seg, sizeof(SegDev) * seg.size());
@@ -414,7 +442,11 @@ qed_status plan_create(qed_tables T, int n, const qed_instance *in, int ppb, int
     p->sur[0] = s_nlc;
     p->sur[1] = s_nbw;
     p->tau = false;
-    for (int i = 0; i < n; ++i) p->tau = p->tau || (in[i].params.flags & QED_OPTICAL_DEPTH);
+    p->grid = false;
+    for (int i = 0; i < n; ++i) {
+        p->tau = p->tau || (in[i].params.flags & QED_OPTICAL_DEPTH);
+        p->grid = p->grid || in[i].fields.kind == QED_FIELD_GRID2D;
+    }
     if (s_nlc || s_nbw) {
         // one record per possible transition: every slot of every set
         int64_t slots = 0;
@@ -440,6 +472,7 @@ template <class R> qed_status plan_step(qed_plan p, hipStream_t st)
     P.seg = p->d_seg;
     P.nseg = p->nseg;
     P.nblk = p->nblk;
+    P.group = p->group;
     P.ninst = p->ninst;
     P.mask = p->d_mask;
     P.bcnt = p->d_bcnt;
@@ -452,33 +485,53 @@ template <class R> qed_status plan_step(qed_plan p, hipStream_t st)
     const InstDev<R> *inst = (const InstDev<R> *)p->d_inst;
     if (p->nblk_lep > 0) {
         if (p->tau)
-            QS_LAUNCH(K_PLAN_LEPTON, (k_plan_main<R, 0, true>), dim3(p->nblk_lep), dim3(kBlock), p->lds, st, inst, P,
+            QS_LAUNCH(K_PLAN_LEPTON, (k_plan_main<R, 0, true, true>), dim3(p->nblk_lep), dim3(kBlock), p->lds, st, inst, P,
+                      p->T->dev, 0);
+        else if (p->grid)
+            QS_LAUNCH(K_PLAN_LEPTON, (k_plan_main<R, 0, false, true>), dim3(p->nblk_lep), dim3(kBlock), p->lds, st, inst, P,
                       p->T->dev, 0);
         else
-            QS_LAUNCH(K_PLAN_LEPTON, (k_plan_main<R, 0, false>), dim3(p->nblk_lep), dim3(kBlock), p->lds, st, inst, P,
+            QS_LAUNCH(K_PLAN_LEPTON, (k_plan_main<R, 0, false, false>), dim3(p->nblk_lep), dim3(kBlock), p->lds, st, inst, P,
                       p->T->dev, 0);
     }
-    if (p->nblk > p->nblk_lep)
-        QS_LAUNCH(K_PLAN_PHOTON, (k_plan_main<R, 1, false>), dim3(p->nblk - p->nblk_lep), dim3(kBlock), p->lds, st, inst, P,
-                  p->T->dev, p->nblk_lep);
+    if (p->nblk > p->nblk_lep) {
+        if (p->grid)
+            QS_LAUNCH(K_PLAN_PHOTON, (k_plan_main<R, 1, false, true>), dim3(p->nblk - p->nblk_lep), dim3(kBlock), p->lds, st,
+                      inst, P, p->T->dev, p->nblk_lep);
+        else
+            QS_LAUNCH(K_PLAN_PHOTON, (k_plan_main<R, 1, false, false>), dim3(p->nblk - p->nblk_lep), dim3(kBlock), p->lds, st,
+                      inst, P, p->T->dev, p->nblk_lep);
+    }
     QS_LAUNCH(K_BOOK, k_plan_book<R>, dim3(1 + (int)cdiv(p->nblk, kCtrGroup)), dim3(kBlock), 0, st, inst, P);
     // processing: with a learned inverse CDF, a first pass writes its inputs, the network runs on
     // the dense list of transitions, and a second pass finishes them with its nu
     const bool sl = p->sur[0] != nullptr, sp = p->sur[1] != nullptr;
     const bool has_l = p->nblk_lep > 0, has_g = p->nblk > p->nblk_lep;
-    const int nl = p->nblk_lep, ng = p->nblk - p->nblk_lep;
-    if (has_l)
-        QS_LAUNCH(K_PLAN_PROCESS, (k_plan_process<R, 0>), dim3(nl), dim3(kBlock), p->lds, st, inst, P, p->T->dev, 0,
-                  sl ? 1 : 0);
-    if (has_g)
-        QS_LAUNCH(K_PLAN_PROCESS, (k_plan_process<R, 1>), dim3(ng), dim3(kBlock), p->lds, st, inst, P, p->T->dev, nl,
-                  sp ? 1 : 0);
-    if (has_l && sl) qs_surrogate_eval_ranks(p->sur[0], P.sx, P.gpre, 0, nl, P.snu, st);
-    if (has_g && sp) qs_surrogate_eval_ranks(p->sur[1], P.sx, P.gpre, nl, p->nblk, P.snu, st);
-    if (has_l && sl)
-        QS_LAUNCH(K_PLAN_PROCESS, (k_plan_process<R, 0>), dim3(nl), dim3(kBlock), p->lds, st, inst, P, p->T->dev, 0, 2);
-    if (has_g && sp)
-        QS_LAUNCH(K_PLAN_PROCESS, (k_plan_process<R, 1>), dim3(ng), dim3(kBlock), p->lds, st, inst, P, p->T->dev, nl, 2);
+    // pass 1 over every set; with a learned inverse CDF it writes the inputs, the network runs on
+    // each process's dense rank range, and pass 2 finishes with its nu (blocks of the sets that
+    // use the tables are skipped in it)
+    const int np_all = p->npb, np_l = p->npb_lep;
+    auto proc = p->grid ? k_plan_process<R, true> : k_plan_process<R, false>;
+    const int mode1 = (sl || sp) ? 1 : 0;
+    if (!(sl || sp)) {
+        if (np_all > 0)
+            QS_LAUNCH(K_PLAN_PROCESS, proc, dim3(np_all), dim3(kBlock), p->lds, st, inst, P, p->T->dev, 0, 0);
+    } else {
+        // tables for the process without a network, inputs for the one with it
+        if (np_l > 0)
+            QS_LAUNCH(K_PLAN_PROCESS, proc, dim3(np_l), dim3(kBlock), p->lds, st, inst, P, p->T->dev, 0,
+                      sl ? mode1 : 0);
+        if (np_all > np_l)
+            QS_LAUNCH(K_PLAN_PROCESS, proc, dim3(np_all - np_l), dim3(kBlock), p->lds, st, inst, P, p->T->dev,
+                      np_l, sp ? mode1 : 0);
+        if (has_l && sl) qs_surrogate_eval_ranks(p->sur[0], P.sx, P.gpre, 0, p->nblk_lep, P.snu, st);
+        if (has_g && sp) qs_surrogate_eval_ranks(p->sur[1], P.sx, P.gpre, p->nblk_lep, p->nblk, P.snu, st);
+        if (np_l > 0 && sl)
+            QS_LAUNCH(K_PLAN_PROCESS, proc, dim3(np_l), dim3(kBlock), p->lds, st, inst, P, p->T->dev, 0, 2);
+        if (np_all > np_l && sp)
+            QS_LAUNCH(K_PLAN_PROCESS, proc, dim3(np_all - np_l), dim3(kBlock), p->lds, st, inst, P, p->T->dev,
+                      np_l, 2);
+    }
     return qs_launch_status("qed_plan_step");
 }
 
@@ -505,14 +558,15 @@ extern "C" qed_status qed_plan_create(qed_tables T, int n_instances, const qed_i
         if (!instance_ok(&instances[i])) return QED_ERR_INVALID;
     const int ppb = config && config->particles_per_block > 0 ? config->particles_per_block : kBlock;
     const int maxb = config && config->max_blocks_per_set > 0 ? config->max_blocks_per_set : kMaxGrid;
+    const int group = config && config->process_group > 0 ? config->process_group : 4;
     qed_surrogate sn = config ? config->icdf_nlc : nullptr, sb = config ? config->icdf_nbw : nullptr;
     // the networks are trained for 24-bit uniforms (single precision) on these tables' ranges
     if ((sn || sb) && T->params.precision != QED_F32) return QED_ERR_UNSUPPORTED;
     if (sn && (qs_surrogate_process(sn) != 0 || qs_surrogate_tables(sn) != T)) return QED_ERR_INVALID;
     if (sb && (qs_surrogate_process(sb) != 1 || qs_surrogate_tables(sb) != T)) return QED_ERR_INVALID;
     qs_clear_error();
-    if (T->params.precision == QED_F64) return plan_create<double>(T, n_instances, instances, ppb, maxb, sn, sb, out);
-    return plan_create<float>(T, n_instances, instances, ppb, maxb, sn, sb, out);
+    if (T->params.precision == QED_F64) return plan_create<double>(T, n_instances, instances, ppb, maxb, group, sn, sb, out);
+    return plan_create<float>(T, n_instances, instances, ppb, maxb, group, sn, sb, out);
 }
 
 extern "C" qed_status qed_plan_step(qed_plan plan, qed_stream stream)

@@ -28,7 +28,7 @@ __global__ void __launch_bounds__(kBlock) k_push(LepDev<R> L, FieldDev F, StepDe
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
         V3<R> x = ldx(L.x, i), p = ld3(L.p, i), s = ld3(L.s, i);
         V3<R> E, B;
-        eval_fields<R>(F, (double)x.x, (double)x.y, S.t, E, B);
+        eval_fields<R, true>(F, (double)x.x, (double)x.y, S.t, E, B);
         const V3<R> d = push<R>(q, (R)S.a_e, E, B, (R)S.dt, (S.flags & F_TBMT) != 0, p, s);
         stx(L.x, i, x + d);
         st3(L.p, i, p);
@@ -36,7 +36,7 @@ __global__ void __launch_bounds__(kBlock) k_push(LepDev<R> L, FieldDev F, StepDe
     }
 }
 
-template <class R, bool TAU>
+template <class R, bool TAU, bool GRID>
 __global__ void __launch_bounds__(kBlock) k_lepton_main(LepDev<R> L, FieldDev F, StepDev S0, TablesDev T,
                                                         uint64_t *mask, int64_t nchunks, uint32_t *bctr, uint32_t *bcnt)
 {
@@ -48,7 +48,7 @@ __global__ void __launch_bounds__(kBlock) k_lepton_main(LepDev<R> L, FieldDev F,
     const int64_t B = block_len(n, gridDim.x);
     const int64_t start = (int64_t)blockIdx.x * B, end = start + B < n ? start + B : n;
     LCount c;
-    lepton_range<R, TAU>(L, F, S, T, lds, start, end, mask, nchunks, c);
+    lepton_range<R, TAU, GRID>(L, F, S, T, lds, start, end, mask, nchunks, c);
     unsigned v[kNCtr + 1] = {};
     v[C_PROB] = c.prob; v[C_CHI] = c.chi; v[C_NORM] = c.norm; v[C_LSTEP] = c.step; v[kNCtr] = c.trans;
     __shared__ unsigned tot[kNCtr + 1];
@@ -57,7 +57,7 @@ __global__ void __launch_bounds__(kBlock) k_lepton_main(LepDev<R> L, FieldDev F,
     else if (threadIdx.x == kNCtr) bcnt[blockIdx.x] = tot[kNCtr];
 }
 
-template <class R>
+template <class R, bool GRID>
 __global__ void __launch_bounds__(kBlock) k_emit_process(LepDev<R> L, PhoDev<R> G, FieldDev F, StepDev S0, TablesDev T,
                                                          const uint64_t *mask, int64_t nchunks, const uint32_t *idx,
                                                          const int64_t *book, unsigned long long *ctr)
@@ -71,13 +71,13 @@ __global__ void __launch_bounds__(kBlock) k_emit_process(LepDev<R> L, PhoDev<R> 
     for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < total; j += (int64_t)gridDim.x * blockDim.x) {
         const int64_t i = idx[j];
         const bool up = (mask[nchunks + (i >> 6)] >> (i & 63)) & 1ull;
-        emit_item<R>(L, G, F, S, T, lds, i, up, j < nfit ? gbase + j : -1, c_ret);
+        emit_item<R, GRID>(L, G, F, S, T, lds, i, up, j < nfit ? gbase + j : -1, c_ret);
     }
     wave_add(ctr, C_RETIRED, c_ret);
 }
 
 // ------------------------------------------------------------------ kernels: photons
-template <class R>
+template <class R, bool GRID>
 __global__ void __launch_bounds__(kBlock) k_photon_main(PhoDev<R> G, FieldDev F, StepDev S0, TablesDev T, uint64_t *mask,
                                                         int64_t nchunks, uint32_t *bctr, uint32_t *bcnt)
 {
@@ -91,7 +91,7 @@ __global__ void __launch_bounds__(kBlock) k_photon_main(PhoDev<R> G, FieldDev F,
     const int64_t start = (int64_t)blockIdx.x * B, end = start + B < n ? start + B : n;
     GCount c;
     for (int64_t tile = start; tile < end; tile += kPhoTile)
-        photon_tile<R>(G, F, S, T, lds, Q, tile, tile + kPhoTile < end ? tile + kPhoTile : end, mask, nchunks, c);
+        photon_tile<R, GRID>(G, F, S, T, lds, Q, tile, tile + kPhoTile < end ? tile + kPhoTile : end, mask, nchunks, c);
     unsigned v[kNCtr + 1] = {};
     v[C_PROB] = c.prob; v[C_CHI] = c.chi; v[C_NORM] = c.norm; v[C_RETIRED] = c.ret; v[C_GSTEP] = c.step;
     v[C_GQED] = c.qed; v[kNCtr] = c.trans;
@@ -101,7 +101,7 @@ __global__ void __launch_bounds__(kBlock) k_photon_main(PhoDev<R> G, FieldDev F,
     else if (threadIdx.x == kNCtr) bcnt[blockIdx.x] = tot[kNCtr];
 }
 
-template <class R>
+template <class R, bool GRID>
 __global__ void __launch_bounds__(kBlock) k_pair_process(PhoDev<R> G, LepDev<R> Le, LepDev<R> Lp, FieldDev F, StepDev S0,
                                                          TablesDev T, const uint64_t *mask, int64_t nchunks,
                                                          const uint32_t *idx, const int64_t *book)
@@ -116,7 +116,7 @@ __global__ void __launch_bounds__(kBlock) k_pair_process(PhoDev<R> G, LepDev<R> 
     for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < total; j += (int64_t)gridDim.x * blockDim.x) {
         const int64_t i = idx[j];
         const bool plus = (mask[nchunks + (i >> 6)] >> (i & 63)) & 1ull;
-        pair_item<R>(G, Le, Lp, F, S, T, lds, i, plus, j < nfit ? be + j : -1, bp + j);
+        pair_item<R, GRID>(G, Le, Lp, F, S, T, lds, i, plus, j < nfit ? be + j : -1, bp + j);
     }
 }
 
@@ -299,18 +299,22 @@ qed_status emit_impl(qed_tables T, const qed_leptons *L, const qed_fields *f, co
     unsigned long long *c = (unsigned long long *)ctr;
     const size_t lds_nlc = sizeof(R) * 2 * T->dev.n_chi[0];
     const int g = grid_for(L->capacity);
+    const bool grid = f->kind == QED_FIELD_GRID2D;
     if (p->flags & QED_OPTICAL_DEPTH)
-        QS_LAUNCH(K_LEPTON_MAIN, (k_lepton_main<R, true>), dim3(g), dim3(kBlock), lds_nlc, st, ld, fd, sd, T->dev, w.mask,
-                  nch, w.bctr, w.bcnt);
+        QS_LAUNCH(K_LEPTON_MAIN, (k_lepton_main<R, true, true>), dim3(g), dim3(kBlock), lds_nlc, st, ld, fd, sd, T->dev,
+                  w.mask, nch, w.bctr, w.bcnt);
+    else if (grid)
+        QS_LAUNCH(K_LEPTON_MAIN, (k_lepton_main<R, false, true>), dim3(g), dim3(kBlock), lds_nlc, st, ld, fd, sd, T->dev,
+                  w.mask, nch, w.bctr, w.bcnt);
     else
-        QS_LAUNCH(K_LEPTON_MAIN, (k_lepton_main<R, false>), dim3(g), dim3(kBlock), lds_nlc, st, ld, fd, sd, T->dev, w.mask,
-                  nch, w.bctr, w.bcnt);
+        QS_LAUNCH(K_LEPTON_MAIN, (k_lepton_main<R, false, false>), dim3(g), dim3(kBlock), lds_nlc, st, ld, fd, sd, T->dev,
+                  w.mask, nch, w.bctr, w.bcnt);
     const PhoDev<R> gd = pho_dev<R>((p->flags & QED_EMIT) ? G : nullptr);
     QS_LAUNCH(K_MASK_EXPAND, k_expand, dim3(g), dim3(kBlock), 0, st, (const uint64_t *)w.mask, (const uint32_t *)w.bcnt,
               (const int64_t *)L->d_count, w.book, 0, gd.count, gd.cap, (int64_t *)nullptr, (int64_t)0,
               (int64_t *)nullptr, c, (const uint32_t *)w.bctr, w.idx);
-    QS_LAUNCH(K_EMIT_PROCESS, k_emit_process<R>, dim3(g), dim3(kBlock), lds_nlc, st, ld, gd, fd, sd, T->dev, w.mask, nch, w.idx,
-                       w.book, c);
+    QS_LAUNCH(K_EMIT_PROCESS, (k_emit_process<R, true>), dim3(g), dim3(kBlock), lds_nlc, st, ld, gd, fd, sd, T->dev, w.mask,
+              nch, w.idx, w.book, c);
     return qs_launch_status(__func__);
 }
 
@@ -327,13 +331,17 @@ qed_status pair_impl(qed_tables T, const qed_photons *G, const qed_fields *f, co
     unsigned long long *c = (unsigned long long *)ctr;
     const size_t lds_nbw = sizeof(R) * 2 * T->dev.n_chi[1];
     const int g = grid_for(G->capacity);
-    QS_LAUNCH(K_PHOTON_MAIN, k_photon_main<R>, dim3(g), dim3(kBlock), lds_nbw, st, gd, fd, sd, T->dev, w.mask, nch, w.bctr,
-              w.bcnt);
+    if (f->kind == QED_FIELD_GRID2D)
+        QS_LAUNCH(K_PHOTON_MAIN, (k_photon_main<R, true>), dim3(g), dim3(kBlock), lds_nbw, st, gd, fd, sd, T->dev, w.mask,
+                  nch, w.bctr, w.bcnt);
+    else
+        QS_LAUNCH(K_PHOTON_MAIN, (k_photon_main<R, false>), dim3(g), dim3(kBlock), lds_nbw, st, gd, fd, sd, T->dev, w.mask,
+                  nch, w.bctr, w.bcnt);
     QS_LAUNCH(K_MASK_EXPAND, k_expand, dim3(g), dim3(kBlock), 0, st, (const uint64_t *)w.mask, (const uint32_t *)w.bcnt,
               (const int64_t *)G->d_count_prev, w.book, 1, Le->d_count, Le->capacity, Lp->d_count, Lp->capacity,
               (int64_t *)nullptr, c, (const uint32_t *)w.bctr, w.idx);
-    QS_LAUNCH(K_PAIR_PROCESS, k_pair_process<R>, dim3(g), dim3(kBlock), lds_nbw, st, gd, lep_dev<R>(Le), lep_dev<R>(Lp), fd, sd,
-                       T->dev, w.mask, nch, w.idx, w.book);
+    QS_LAUNCH(K_PAIR_PROCESS, (k_pair_process<R, true>), dim3(g), dim3(kBlock), lds_nbw, st, gd, lep_dev<R>(Le),
+              lep_dev<R>(Lp), fd, sd, T->dev, w.mask, nch, w.idx, w.book);
     return qs_launch_status(__func__);
 }
 
