@@ -286,11 +286,11 @@ struct LCount { unsigned prob = 0, chi = 0, norm = 0, step = 0, trans = 0; };
 // variant without it needs fewer registers).
 template <class R, bool TAU, bool GRID>
 __device__ __forceinline__ void lepton_item(const LepDev<R> &L, const FieldDev &F, const StepDev &S, const TablesDev &T,
-                                            const R *lds, int64_t i, bool &emit, bool &up, LCount &c)
+                                            const R *lds, int64_t i, V3<R> x, V3<R> p, V3<R> s, bool &emit, bool &up,
+                                            LCount &c)
 {
     const int q = L.species == 0 ? -1 : 1;
     ++c.step;
-    V3<R> x = ldx(L.x, i), p = ld3(L.p, i), s = ld3(L.s, i);
     V3<R> E, B;
     if (S.flags & F_PUSH) {
         eval_fields<R, GRID>(F, (double)x.x, (double)x.y, S.t, E, B);
@@ -354,10 +354,19 @@ __device__ __forceinline__ void lepton_range(const LepDev<R> &L, const FieldDev 
                                              LCount &c)
 {
     const int lane = threadIdx.x & 63;
+    // the next particle's x, p, s are loaded before this one is worked on
+    V3<R> xn = {0, 0, 0}, pn = {0, 0, 0}, sn = {0, 0, 0};
+    {
+        const int64_t i = start + (threadIdx.x & ~63) + lane;
+        if (i < end) { xn = ldx(L.x, i); pn = ld3(L.p, i); sn = ld3(L.s, i); }
+    }
     for (int64_t base = start + (threadIdx.x & ~63); base < end; base += blockDim.x) {
         const int64_t i = base + lane;
+        const V3<R> x = xn, p = pn, s = sn;
+        const int64_t inext = i + blockDim.x;
+        if (inext < end) { xn = ldx(L.x, inext); pn = ld3(L.p, inext); sn = ld3(L.s, inext); }
         bool emit = false, up = false;
-        if (i < end) lepton_item<R, TAU, GRID>(L, F, S, T, lds, i, emit, up, c);
+        if (i < end) lepton_item<R, TAU, GRID>(L, F, S, T, lds, i, x, p, s, emit, up, c);
         const uint64_t m = __ballot(emit), mu = __ballot(up);
         if (lane == 0) {
             mask[base >> 6] = m;
@@ -468,32 +477,47 @@ __device__ __forceinline__ void photon_tile(const PhoDev<R> &G, const FieldDev &
     if (threadIdx.x < kPhoTile / 64) { Q.bits[0][threadIdx.x] = 0ull; Q.bits[1][threadIdx.x] = 0ull; }
     if (threadIdx.x == 0) Q.n = 0;
     __syncthreads();
-    for (int64_t base = tile + (threadIdx.x & ~63); base < tend; base += blockDim.x) {
+    // the slots of this thread: all loads first (id, k and x do not wait for each other), then the
+    // work; a dead slot (id 0) loads values it never uses
+    constexpr int kPer = kPhoTile / kBlock;
+    uint64_t idv[kPer];
+    V3<R> kv[kPer], xv[kPer];
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) {
+        const int64_t i = tile + (threadIdx.x & ~63) + (int64_t)u * kBlock + lane;
+        idv[u] = 0;
+        if (i < tend) {
+            idv[u] = G.id[i];
+            kv[u] = ld3(G.k, i);
+            xv[u] = ldx(G.x, i);
+        }
+    }
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) {
+        const int64_t base = tile + (threadIdx.x & ~63) + (int64_t)u * kBlock;
+        if (base >= tend) break;                      // wave-uniform
         const int64_t i = base + lane;
         bool cand = false;
         R xq = (R)0, yq = (R)0;
-        if (i < tend) {
-            const uint64_t id = G.id[i];
-            if (id != 0) {
-                ++c.step;
-                const V3<R> k = ld3(G.k, i);
-                const R k0r = sqrt_r(dot(k, k));
-                V3<R> x = ldx(G.x, i);
-                x = x + ((R)S.dt / k0r) * k;
-                stx(G.x, i, x);
-                // retirement: too soft to ever reach chi_min, or behind the trailing edge of the
-                // plane-wave pulse (the phase t + x of a photon never decreases)
-                const bool behind = F.kind == 1 && F.phase_len > 0.0 && S.t + S.dt + (double)x.x > F.phase_len;
-                if ((double)k0r < S.k_retire || behind) {
-                    G.id[i] = 0;
-                    ++c.ret;
-                } else if (qed) {
-                    V3<R> E, Bf;
-                    eval_fields<R, GRID>(F, (double)x.x, (double)x.y, S.t + S.dt, E, Bf);
-                    cand = photon_candidate<R>(S, k0r, E, Bf);
-                    xq = x.x;
-                    if (GRID) yq = x.y;
-                }
+        if (idv[u] != 0) {
+            ++c.step;
+            const V3<R> k = kv[u];
+            const R k0r = sqrt_r(dot(k, k));
+            V3<R> x = xv[u];
+            x = x + ((R)S.dt / k0r) * k;
+            stx(G.x, i, x);
+            // retirement: too soft to ever reach chi_min, or behind the trailing edge of the
+            // plane-wave pulse (the phase t + x of a photon never decreases)
+            const bool behind = F.kind == 1 && F.phase_len > 0.0 && S.t + S.dt + (double)x.x > F.phase_len;
+            if ((double)k0r < S.k_retire || behind) {
+                G.id[i] = 0;
+                ++c.ret;
+            } else if (qed) {
+                V3<R> E, Bf;
+                eval_fields<R, GRID>(F, (double)x.x, (double)x.y, S.t + S.dt, E, Bf);
+                cand = photon_candidate<R>(S, k0r, E, Bf);
+                xq = x.x;
+                if (GRID) yq = x.y;
             }
         }
         const uint64_t m = __ballot(cand);
