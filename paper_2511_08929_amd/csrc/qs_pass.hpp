@@ -462,7 +462,9 @@ constexpr int kPhoTile = 1024;
 
 template <class R> struct PhoQueue {
     uint32_t idx[kPhoTile];
+    uint64_t id[kPhoTile];
     R x[kPhoTile], y[kPhoTile];
+    R k[3][kPhoTile];              // the candidates' momenta, read once in phase 1
     unsigned long long bits[2][kPhoTile / 64];
     uint32_t n;
 };
@@ -527,8 +529,12 @@ __device__ __forceinline__ void photon_tile(const PhoDev<R> &G, const FieldDev &
         if (cand) {
             const uint32_t r = wbase + (uint32_t)__popcll(m & ((1ull << lane) - 1ull));
             Q.idx[r] = (uint32_t)(i - tile);
+            Q.id[r] = idv[u];
             Q.x[r] = xq;
             if (GRID) Q.y[r] = yq;
+            Q.k[0][r] = kv[u].x;
+            Q.k[1][r] = kv[u].y;
+            Q.k[2][r] = kv[u].z;
         }
     }
     __syncthreads();
@@ -536,12 +542,12 @@ __device__ __forceinline__ void photon_tile(const PhoDev<R> &G, const FieldDev &
     for (uint32_t j = threadIdx.x; j < nq; j += blockDim.x) {
         const uint32_t o = Q.idx[j];
         const int64_t i = tile + o;
-        const uint64_t id = G.id[i];
-        const V3<R> k = ld3(G.k, i);
+        const V3<R> P = ld3(G.P, i);                  // the one global load of phase 2
+        const uint64_t id = Q.id[j];
+        const V3<R> k = {Q.k[0][j], Q.k[1][j], Q.k[2][j]};
         const double k0 = (double)sqrt_r(dot(k, k));
         V3<R> E, Bf;
         eval_fields<R, GRID>(F, (double)Q.x[j], GRID ? (double)Q.y[j] : 0.0, S.t + S.dt, E, Bf);
-        const V3<R> P = ld3(G.P, i);
         const PDecide<R> d = photon_decide<R>(S, T, lds, id, k, k0, P, E, Bf);
         if (!d.active) continue;
         ++c.qed;
