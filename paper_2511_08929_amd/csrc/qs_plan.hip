@@ -63,29 +63,9 @@ struct PlanDev {
     SegBook *sbook;            // [nseg]
     int64_t *clock_used;       // [ninst] step clock of the last main pass
     float *sx, *snu;           // learned inverse CDF: inputs [3] and nu per global transition rank
+    const int *bseg, *binst;   // [nblk] segment and instance of each streaming block
+    const int4 *pbd;           // [npb] processing block: segment, streaming blocks [mb0, mb1), instance
 };
-
-__device__ __forceinline__ int seg_of(const SegDev *seg, int nseg, int b)
-{
-    int lo = 0, hi = nseg - 1;
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (seg[mid].b0 <= b) lo = mid;
-        else hi = mid - 1;
-    }
-    return lo;
-}
-
-__device__ __forceinline__ int seg_of_pb(const SegDev *seg, int nseg, int pb)
-{
-    int lo = 0, hi = nseg - 1;
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (seg[mid].pb0 <= pb) lo = mid;
-        else hi = mid - 1;
-    }
-    return lo;
-}
 
 __device__ __forceinline__ int64_t seg_total(const PlanDev &P, int sj)
 {
@@ -96,116 +76,163 @@ __device__ __forceinline__ int64_t seg_total(const PlanDev &P, int sj)
     return (int64_t)hi - (int64_t)lo;
 }
 
-constexpr int kCtrGroup = 64;   // main blocks whose event counts one bookkeeping block adds up
+constexpr int kCtrGroup = 64;   // main blocks whose event counts one bookkeeping wave adds up
+constexpr int kScanChunk = 8192; // block counts the scan holds in LDS at a time
+constexpr int kSegLds = 1024;    // segments whose boundary prefixes the scan keeps in LDS
+
+// What one instance's bookkeeping reads besides the segment totals.  Loaded before the scan:
+// none of it depends on the scan, and nothing else writes it during the launch.
+struct BookIn {
+    int64_t ne, np, gb, ng, clock;
+};
+
+template <class R> __device__ __forceinline__ BookIn book_load(const InstDev<R> &I)
+{
+    BookIn b;
+    b.ne = *I.E.count;
+    b.np = I.sp >= 0 ? *I.P.count : 0;
+    b.gb = I.G.count != nullptr ? *I.G.count : 0;
+    b.ng = I.sg >= 0 ? *I.G.count_prev : 0;
+    b.clock = I.S.clock ? *I.S.clock : 0;
+    return b;
+}
 
 // Block 0: scan of the transition counts of all main blocks, then per-instance bookkeeping (one
-// thread per instance).  Block 1 + g: event counts of main blocks [64 g, 64 g + 64) added to
-// their instances' counters (one atomic per counter and run of blocks of one instance).
+// thread per instance).  Block 1 + w / 4, wave w % 4: event counts of main blocks
+// [64 w, 64 w + 64) added to their instances' counters, one atomic per counter and run of
+// blocks of one instance.
 template <class R>
 __global__ void __launch_bounds__(kBlock) k_plan_book(const InstDev<R> *inst, PlanDev P)
 {
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     if (blockIdx.x > 0) {
-        __shared__ uint32_t cnt[kCtrGroup][kNCtr];
-        __shared__ int iid[kCtrGroup];
-        const int b0 = (blockIdx.x - 1) * kCtrGroup;
+        const int b0 = ((blockIdx.x - 1) * (kBlock / 64) + wid) * kCtrGroup;
+        if (b0 >= P.nblk) return;                                // wave-uniform
         const int gsz = P.nblk - b0 < kCtrGroup ? P.nblk - b0 : kCtrGroup;
-        if ((int)threadIdx.x < gsz) {
-            const int b = b0 + threadIdx.x;
-            iid[threadIdx.x] = P.seg[seg_of(P.seg, P.nseg, b)].inst;
-            for (int c = 0; c < kNCtr; ++c) cnt[threadIdx.x][c] = P.bctr[(int64_t)b * kNCtr + c];
-        }
-        __syncthreads();
-        if (threadIdx.x < kNCtr) {
-            const int c = threadIdx.x;
-            unsigned long long acc = 0;
-            int cur = iid[0];
-            for (int t = 0; t < gsz; ++t) {
-                if (iid[t] != cur) {
-                    if (acc) atomicAdd(inst[cur].ctr + c, acc);
-                    cur = iid[t];
-                    acc = 0;
-                }
-                acc += cnt[t][c];
+        const bool on = lane < gsz;
+        const int b = b0 + lane;
+        const int me = on ? P.binst[b] : -1;
+        uint32_t v[kNCtr];
+#pragma unroll
+        for (int c = 0; c < kNCtr; ++c) v[c] = on ? P.bctr[(int64_t)b * kNCtr + c] : 0u;
+        // runs of lanes of one instance (a segment's blocks are contiguous): a segmented sum
+        // within each run, added by the run's last lane
+        const int prev = __shfl_up(me, 1);
+        const uint64_t heads = __ballot(on && (lane == 0 || prev != me));
+        const int rs = 63 - __clzll((long long)(heads & ((2ull << lane) - 1ull)));   // first lane of my run
+        const bool last = on && (lane == gsz - 1 || (lane < 63 && ((heads >> (lane + 1)) & 1ull)));
+#pragma unroll
+        for (int c = 0; c < kNCtr; ++c) {
+            unsigned long long acc = v[c];
+            for (int o = 1; o < 64; o <<= 1) {
+                const unsigned long long y = __shfl_up(acc, o);
+                if (lane - o >= rs) acc += y;
             }
-            if (acc) atomicAdd(inst[cur].ctr + c, acc);
+            if (last && acc) atomicAdd(inst[me].ctr + c, acc);
         }
         return;
     }
-    // thread t owns the contiguous run [t m, t m + m) of block counts: all loads in flight at once,
-    // a serial sum, one block-wide scan of the 256 run totals, then the run's prefixes
+    __shared__ uint32_t sc[kScanChunk];
     __shared__ uint32_t wsum[kBlock / 64];
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    const int m = (int)cdiv(P.nblk, kBlock);
-    const int lo = threadIdx.x * m, hi = lo + m < P.nblk ? lo + m : P.nblk;
-    uint32_t run = 0;
-    int b = lo;
-    for (; b + 8 <= hi; b += 8) {              // eight independent loads in flight
-        uint32_t v[8];
-#pragma unroll
-        for (int j = 0; j < 8; ++j) v[j] = P.bcnt[b + j];
-#pragma unroll
-        for (int j = 0; j < 8; ++j) run += v[j];
+    __shared__ uint32_t sbeg[kSegLds], send[kSegLds];
+    __shared__ int sb0[kSegLds], sb1[kSegLds];
+    const bool seg_lds = P.nseg <= kSegLds;
+    if (seg_lds)
+        for (int sj = threadIdx.x; sj < P.nseg; sj += kBlock) {
+            sb0[sj] = P.seg[sj].b0;
+            sb1[sj] = P.seg[sj].b0 + P.seg[sj].nb;
+        }
+    // the first instance of this thread: its inputs load while the scan runs
+    BookIn in0 = {0, 0, 0, 0, 0};
+    if ((int)threadIdx.x < P.ninst) in0 = book_load<R>(inst[threadIdx.x]);
+    // the block counts pass through LDS in chunks: coalesced loads, all in flight at once; thread t
+    // then sums the contiguous run [t m, t m + m) of the chunk, one block-wide scan of the 256 run
+    // totals gives the run's offset, the run's prefixes overwrite the counts in LDS, segment
+    // boundaries inside the chunk copy theirs, and coalesced stores write them out
+    uint32_t carry = 0;                        // prefix before the chunk
+    for (int c0 = 0; c0 < P.nblk; c0 += kScanChunk) {
+        const int n = P.nblk - c0 < kScanChunk ? P.nblk - c0 : kScanChunk;
+#pragma unroll 8
+        for (int j = threadIdx.x; j < n; j += kBlock) sc[j] = P.bcnt[c0 + j];
+        __syncthreads();
+        const int m = (int)cdiv(n, kBlock);
+        const int lo = (int)threadIdx.x * m < n ? (int)threadIdx.x * m : n, hi = lo + m < n ? lo + m : n;
+        uint32_t run = 0;
+        for (int b = lo; b < hi; ++b) run += sc[b];
+        uint32_t incl = run;
+        for (int o = 1; o < 64; o <<= 1) {
+            const uint32_t y = __shfl_up(incl, o);
+            if (lane >= o) incl += y;
+        }
+        if (lane == 63) wsum[wid] = incl;
+        __syncthreads();
+        uint32_t off = carry + incl - run;
+        for (int w = 0; w < wid; ++w) off += wsum[w];
+        for (int w = 0; w < kBlock / 64; ++w) carry += wsum[w];
+        for (int b = lo; b < hi; ++b) {
+            const uint32_t v = sc[b];
+            sc[b] = off;
+            off += v;
+        }
+        __syncthreads();
+#pragma unroll 8
+        for (int j = threadIdx.x; j < n; j += kBlock) P.gpre[c0 + j] = sc[j];
+        if (seg_lds)
+            for (int sj = threadIdx.x; sj < P.nseg; sj += kBlock) {
+                const int sb = sb0[sj], se = sb1[sj];
+                if (sb >= c0 && sb < c0 + n) sbeg[sj] = sc[sb - c0];
+                if (se >= c0 && se < c0 + n) send[sj] = sc[se - c0];
+            }
+        __syncthreads();                       // sc and wsum are reused by the next chunk
     }
-    for (; b < hi; ++b) run += P.bcnt[b];
-    uint32_t incl = run;
-    for (int o = 1; o < 64; o <<= 1) {
-        const uint32_t y = __shfl_up(incl, o);
-        if (lane >= o) incl += y;
-    }
-    if (lane == 63) wsum[wid] = incl;
+    if (seg_lds)
+        for (int sj = threadIdx.x; sj < P.nseg; sj += kBlock)
+            if (sb1[sj] == P.nblk) send[sj] = carry;
+    if (threadIdx.x == 0) P.gpre[P.nblk] = carry;
     __syncthreads();
-    uint32_t off = incl - run;
-    for (int w = 0; w < wid; ++w) off += wsum[w];
-    for (int bb = lo; bb < hi; ++bb) {
-        const uint32_t v = P.bcnt[bb];
-        P.gpre[bb] = off;
-        off += v;
-    }
-    if (threadIdx.x == kBlock - 1) P.gpre[P.nblk] = off;
-    __syncthreads();
+    auto total = [&](int sj) -> int64_t {
+        if (sj < 0) return 0;
+        if (seg_lds) return (int64_t)send[sj] - (int64_t)sbeg[sj];
+        return seg_total(P, sj);
+    };
     for (int i = threadIdx.x; i < P.ninst; i += blockDim.x) {
-        // every load first (they do not depend on each other), then the arithmetic and the stores
         const InstDev<R> &I = inst[i];
+        const BookIn in = i < kBlock ? in0 : book_load<R>(I);
         unsigned long long *ctr = I.ctr;
         const bool has_g = I.G.count != nullptr, pair = I.sg >= 0;
-        const int64_t te = seg_total(P, I.se), tp = seg_total(P, I.sp), tg = seg_total(P, I.sg);
-        const int64_t ne = *I.E.count;
-        const int64_t np = I.sp >= 0 ? *I.P.count : 0;
-        const int64_t gb = has_g ? *I.G.count : 0;
-        const int64_t ng = pair ? *I.G.count_prev : 0;
+        const int64_t te = total(I.se), tp = total(I.sp), tg = total(I.sg);
         int64_t *clk = const_cast<int64_t *>(I.S.clock);
-        const int64_t clock = clk ? *clk : 0;
         int64_t over = 0;
         // emission: photons of electrons, then of positrons
         if (has_g) {
-            const int64_t room = I.G.cap - gb > 0 ? I.G.cap - gb : 0;
+            const int64_t room = I.G.cap - in.gb > 0 ? I.G.cap - in.gb : 0;
             const int64_t nfe = te < room ? te : room;
             const int64_t nfp = tp < room - nfe ? tp : room - nfe;
-            const int64_t gnew = gb + nfe + nfp;
+            const int64_t gnew = in.gb + nfe + nfp;
             *I.G.count = gnew;
-            P.sbook[I.se] = SegBook{ne, gb, 0, te, nfe};
-            if (I.sp >= 0) P.sbook[I.sp] = SegBook{np, gb + nfe, 0, tp, nfp};
+            P.sbook[I.se] = SegBook{in.ne, in.gb, 0, te, nfe};
+            if (I.sp >= 0) P.sbook[I.sp] = SegBook{in.np, in.gb + nfe, 0, tp, nfp};
             over += (te - nfe) + (tp - nfp);
             if (te + tp) atomicAdd(ctr + C_EMIT, (unsigned long long)(te + tp));
             // photons born in this step wait for the next one
             if (pair) *I.G.count_prev = gnew;
         } else {
-            P.sbook[I.se] = SegBook{ne, 0, 0, te, 0};
+            P.sbook[I.se] = SegBook{in.ne, 0, 0, te, 0};
         }
         // pairs of the photons stepped in this pass, appended after the leptons stepped in it
         if (pair) {
-            int64_t room = I.E.cap - ne < I.P.cap - np ? I.E.cap - ne : I.P.cap - np;
+            int64_t room = I.E.cap - in.ne < I.P.cap - in.np ? I.E.cap - in.ne : I.P.cap - in.np;
             room = room > 0 ? room : 0;
             const int64_t nfg = tg < room ? tg : room;
-            *I.E.count = ne + nfg;
-            *I.P.count = np + nfg;
-            P.sbook[I.sg] = SegBook{ng, ne, np, tg, nfg};
+            *I.E.count = in.ne + nfg;
+            *I.P.count = in.np + nfg;
+            P.sbook[I.sg] = SegBook{in.ng, in.ne, in.np, tg, nfg};
             over += tg - nfg;
             if (tg) atomicAdd(ctr + C_PAIR, (unsigned long long)tg);
         }
         if (over) atomicAdd(ctr + C_OVER, (unsigned long long)over);
-        P.clock_used[i] = clock;
-        if (clk) *clk = clock + 1;
+        P.clock_used[i] = in.clock;
+        if (clk) *clk = in.clock + 1;
     }
 }
 
@@ -219,11 +246,11 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(siz
     __shared__ PhoQueue<R> Q;
     __shared__ unsigned tot[kNCtr + 1];
     const int b = b_first + blockIdx.x;
-    const int sj = seg_of(P.seg, P.nseg, b);
+    const int sj = P.bseg[b];
     const SegDev sg = P.seg[sj];
     // local copies of the instance's views: the particle stores below may not alias them, so
     // they stay in registers instead of being re-read from global memory after every store
-    const InstDev<R> *Ip = inst + sg.inst;
+    const InstDev<R> *Ip = inst + P.binst[b];
     const StepDev S = localize(Ip->S);
     const FieldDev F = Ip->F;
     uint64_t *mask = P.mask + sg.mask_off;
@@ -269,13 +296,11 @@ __global__ void __launch_bounds__(kBlock) k_plan_process(const InstDev<R> *inst,
     __shared__ uint16_t list[kExpandWords * 64];
     __shared__ uint32_t nlist;
     // this block covers the streaming blocks [mb0, mb1) of one segment: a contiguous slot range
-    const int pb = b_first + blockIdx.x;
-    const int sj = seg_of_pb(P.seg, P.nseg, pb);
+    const int4 pd = P.pbd[b_first + blockIdx.x];
+    const int sj = pd.x, mb0 = pd.y, mb1 = pd.z;
     const SegDev sg = P.seg[sj];
-    const int mb0 = sg.b0 + (pb - sg.pb0) * P.group;
-    const int mb1 = mb0 + P.group < sg.b0 + sg.nb ? mb0 + P.group : sg.b0 + sg.nb;
     if (P.gpre[mb1] == P.gpre[mb0]) return;           // no transition in this range
-    const InstDev<R> *Ip = inst + sg.inst;
+    const InstDev<R> *Ip = inst + pd.w;
     StepDev S = Ip->S;
     S.step += P.clock_used[sg.inst];
     S.t += (double)P.clock_used[sg.inst] * S.dt;
@@ -347,6 +372,8 @@ struct qed_plan_s {
     int64_t *d_clock_used;
     uint32_t *d_bctr;
     float *d_sx, *d_snu;
+    int *d_bseg, *d_binst;
+    int4 *d_pbd;
     qed_surrogate sur[2];      // learned inverse CDF per process (NULL: tables)
     bool tau;                  // some instance decides emission by the optical depth
     bool grid;                 // some instance uses the grid field model
@@ -382,6 +409,9 @@ void plan_free(qed_plan p)
     (void)hipFree(p->d_bctr);
     (void)hipFree(p->d_sx);
     (void)hipFree(p->d_snu);
+    (void)hipFree(p->d_bseg);
+    (void)hipFree(p->d_binst);
+    (void)hipFree(p->d_pbd);
     delete p;
 }
 
@@ -456,6 +486,27 @@ qed_status plan_create(qed_tables T, int n, const qed_instance *in, int ppb, int
     }
     if (e == hipSuccess) e = hipMemcpy(p->d_inst, inst.data(), sizeof(InstDev<R>) * n, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(p->d_seg, seg.data(), sizeof(SegDev) * seg.size(), hipMemcpyHostToDevice);
+    // block -> segment (and instance) tables: one load instead of a search over the segments
+    std::vector<int> bseg(nblk), binst(nblk);
+    std::vector<int4> pbd(npb > 0 ? npb : 1);
+    for (int sj = 0; sj < (int)seg.size(); ++sj) {
+        const SegDev &sg = seg[sj];
+        for (int b = sg.b0; b < sg.b0 + sg.nb; ++b) {
+            bseg[b] = sj;
+            binst[b] = sg.inst;
+        }
+        for (int pb = sg.pb0; pb < sg.pb0 + sg.npb; ++pb) {
+            const int mb0 = sg.b0 + (pb - sg.pb0) * group;
+            const int mb1 = mb0 + group < sg.b0 + sg.nb ? mb0 + group : sg.b0 + sg.nb;
+            pbd[pb] = make_int4(sj, mb0, mb1, sg.inst);
+        }
+    }
+    if (e == hipSuccess) e = hipMalloc((void **)&p->d_bseg, sizeof(int) * nblk);
+    if (e == hipSuccess) e = hipMalloc((void **)&p->d_binst, sizeof(int) * nblk);
+    if (e == hipSuccess) e = hipMalloc((void **)&p->d_pbd, sizeof(int4) * pbd.size());
+    if (e == hipSuccess) e = hipMemcpy(p->d_bseg, bseg.data(), sizeof(int) * nblk, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(p->d_binst, binst.data(), sizeof(int) * nblk, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(p->d_pbd, pbd.data(), sizeof(int4) * pbd.size(), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemset(p->d_gpre, 0, sizeof(uint32_t) * (nblk + 1));
     if (e == hipSuccess) e = hipDeviceSynchronize();
     if (e != hipSuccess) {
@@ -482,6 +533,9 @@ template <class R> qed_status plan_step(qed_plan p, hipStream_t st)
     P.bctr = p->d_bctr;
     P.sx = p->d_sx;
     P.snu = p->d_snu;
+    P.bseg = p->d_bseg;
+    P.binst = p->d_binst;
+    P.pbd = p->d_pbd;
     const InstDev<R> *inst = (const InstDev<R> *)p->d_inst;
     if (p->nblk_lep > 0) {
         if (p->tau)
@@ -502,7 +556,8 @@ template <class R> qed_status plan_step(qed_plan p, hipStream_t st)
             QS_LAUNCH(K_PLAN_PHOTON, (k_plan_main<R, 1, false, false>), dim3(p->nblk - p->nblk_lep), dim3(kBlock), p->lds, st,
                       inst, P, p->T->dev, p->nblk_lep);
     }
-    QS_LAUNCH(K_BOOK, k_plan_book<R>, dim3(1 + (int)cdiv(p->nblk, kCtrGroup)), dim3(kBlock), 0, st, inst, P);
+    QS_LAUNCH(K_BOOK, k_plan_book<R>, dim3(1 + (int)cdiv(cdiv(p->nblk, kCtrGroup), kBlock / 64)), dim3(kBlock), 0, st,
+              inst, P);
     // processing: with a learned inverse CDF, a first pass writes its inputs, the network runs on
     // the dense list of transitions, and a second pass finishes them with its nu
     const bool sl = p->sur[0] != nullptr, sp = p->sur[1] != nullptr;

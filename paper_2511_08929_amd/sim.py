@@ -23,7 +23,7 @@ class Simulation:
     def __init__(self, tables: Tables, *, cap_e, cap_p, cap_g, track, fields, dt, eps_r, seed, flags,
                  k_retire=0.0, t0=0.0, a_e=ALPHA / (2 * math.pi), chi_e_min=1e-3, chi_e_max=1e2, chi_g_min=0.05,
                  chi_g_max=1e2, device="cuda", device_clock=False, merged=False, particles_per_block=0,
-                 optical_depth=False, surrogates=(None, None)):
+                 max_blocks_per_set=0, optical_depth=False, surrogates=(None, None)):
         import torch
         self.tables = tables
         self.dtype = torch.float64 if tables.precision == QED_F64 else torch.float32
@@ -42,7 +42,7 @@ class Simulation:
         self._sp = None
         merged = merged or any(x is not None for x in surrogates)     # the learned inverse CDF runs in plans
         self.clock = torch.zeros(1, dtype=torch.int64, device=device) if (device_clock or merged) else None
-        self.merged, self.ppb = merged, particles_per_block
+        self.merged, self.ppb, self.maxb = merged, particles_per_block, max_blocks_per_set
         self.surrogates = surrogates
         self.plan = None
 
@@ -66,7 +66,8 @@ class Simulation:
     def _ensure_plan(self):
         if self.merged and self.plan is None:
             self.plan = Plan(self.tables, [(self.e, self.p, self.g, self.fields, self._params(), self.ctr)],
-                             particles_per_block=self.ppb, surrogates=self.surrogates)
+                             particles_per_block=self.ppb, max_blocks_per_set=self.maxb,
+                             surrogates=self.surrogates)
 
     def _enqueue_step(self, stream=None):
         if self.merged:

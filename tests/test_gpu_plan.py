@@ -31,12 +31,13 @@ def tabs(q):
     return {"fp64": q.Tables(precision=q.QED_F64), "fp32": q.Tables(precision=q.QED_F32)}
 
 
-def _sim(q, tab, w, merged, cap_e, cap_p, cap_g, flags=None, ppb=0, tau=False):
+def _sim(q, tab, w, merged, cap_e, cap_p, cap_g, flags=None, ppb=0, tau=False, maxb=0):
     from paper_2511_08929_amd.sim import Simulation
     f = q.make_fields(w.field_kind, E0=w.E0, B0=w.B0, a0=w.a0, phase_len=w.phase_len)
     sim = Simulation(tab, cap_e=cap_e, cap_p=cap_p, cap_g=cap_g, track=w.track, fields=f, dt=w.dt, eps_r=EPS,
                      seed=w.seed, flags=q.QED_ALL if flags is None else flags, k_retire=w.k_retire,
-                     device_clock=True, merged=merged, particles_per_block=ppb, optical_depth=tau)
+                     device_clock=True, merged=merged, particles_per_block=ppb, optical_depth=tau,
+                     max_blocks_per_set=maxb)
     sim.e.load(w.x, w.p, w.s)
     return sim
 
@@ -155,3 +156,17 @@ def test_plan_batched_instances(q, tabs):
     tot = [q.counters_dict(i["ctr"]) for i in bat.inst]
     print(tot)
     assert sum(t["n_emit"] for t in tot) > 1000
+
+
+def test_plan_equals_per_species_many_blocks(q, tabs):
+    """All 10^6 electrons of the head-on collision in blocks of 64 particles and no cap on the
+    blocks of a set: about 47 000 main blocks, so the bookkeeping scan runs over several LDS
+    chunks of block counts."""
+    w = synth.c2()
+    a = _sim(q, tabs["fp32"], w, False, w.n + 20_000, 20_000, 2_000_000)
+    b = _sim(q, tabs["fp32"], w, True, w.n + 20_000, 20_000, 2_000_000, ppb=64, maxb=1 << 20)
+    for _ in range(40):
+        a.step(); b.step()
+    assert b.plan.blocks > 2 * 8192
+    _assert_same(_state(q, a), _state(q, b), "many blocks")
+    assert q.counters_dict(b.ctr)["n_emit"] > 0
