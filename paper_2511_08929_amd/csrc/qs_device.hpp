@@ -130,13 +130,33 @@ __device__ inline Bessel3 bessel3_scaled(double x, const double *nodes)
     const int off = k == 0 ? 0 : kBn64N0 + (k - 1) * kBn64N, nn = k == 0 ? kBn64N0 : kBn64N;
     const double2 *q = reinterpret_cast<const double2 *>(nodes) + 2 * off;
     double s13 = 0.5, s23 = 0.5, sik = 0.5;     // t = 0 node, half weight
-    for (int j = 1; j < nn; ++j) {
-        const double2 a = q[2 * j], b = q[2 * j + 1];   // (cosh t - 1, cosh t/3), (cosh 2t/3, cosh t/3 / cosh t)
-        const double e = exp(-x * a.x);
-        s13 += e * a.y;
-        s23 += e * b.x;
-        sik += e * b.y;
-        if (x * a.x > 44.0 && x * (1.0 + a.x) > 44.0) break;
+    // nodes in groups of four: the group's loads are issued together, the sums run node by node
+    // in the same order (and stop at the same node) as a plain loop
+    for (int j0 = 1; j0 < nn; j0 += 4) {
+        double2 a[4], b[4];                           // (cosh t - 1, cosh t/3), (cosh 2t/3, cosh t/3 / cosh t)
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int j = j0 + u < nn ? j0 + u : nn - 1;
+            a[u] = q[2 * j];
+            b[u] = q[2 * j + 1];
+        }
+        bool done = false;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            if (j0 + u >= nn) {
+                done = true;
+                break;
+            }
+            const double e = exp(-x * a[u].x);
+            s13 += e * a[u].y;
+            s23 += e * b[u].x;
+            sik += e * b[u].y;
+            if (x * a[u].x > 44.0 && x * (1.0 + a[u].x) > 44.0) {
+                done = true;
+                break;
+            }
+        }
+        if (done) break;
     }
     o.k13 = h * s13;
     o.k23 = h * s23;
@@ -161,13 +181,28 @@ template <> __device__ __forceinline__ void bessel_ratios<float>(double xd, cons
     const int off = k == 0 ? 0 : kBn32N0 + (k - 1) * kBn32N, nn = k == 0 ? kBn32N0 : kBn32N;
     const float4 *q = reinterpret_cast<const float4 *>(nodes) + off;
     float s13 = 0.5f, s23 = 0.5f, sik = 0.5f;
-    for (int j = 1; j < nn; ++j) {
-        const float4 a = q[j];                          // cosh t - 1, cosh t/3, cosh 2t/3, ratio
-        const float e = expf(-x * a.x);
-        s13 += e * a.y;
-        s23 += e * a.z;
-        sik += e * a.w;
-        if (x * a.x > 22.0f && x * (1.0f + a.x) > 22.0f) break;
+    // nodes in groups of four, as in the double precision sum
+    for (int j0 = 1; j0 < nn; j0 += 4) {
+        float4 a[4];                                    // cosh t - 1, cosh t/3, cosh 2t/3, ratio
+#pragma unroll
+        for (int u = 0; u < 4; ++u) a[u] = q[j0 + u < nn ? j0 + u : nn - 1];
+        bool done = false;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            if (j0 + u >= nn) {
+                done = true;
+                break;
+            }
+            const float e = expf(-x * a[u].x);
+            s13 += e * a[u].y;
+            s23 += e * a[u].z;
+            sik += e * a[u].w;
+            if (x * a[u].x > 22.0f && x * (1.0f + a[u].x) > 22.0f) {
+                done = true;
+                break;
+            }
+        }
+        if (done) break;
     }
     K1 = s13 / s23;       // the step h cancels in the ratios
     I = sik / s23;

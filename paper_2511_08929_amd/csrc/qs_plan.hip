@@ -52,6 +52,18 @@ struct SegBook {
     int64_t total, nfit;       // transitions, of which stored
 };
 
+// An instance's counts and step clock at the start of a step (written by the lepton streaming
+// pass, read by the processing pass that does the bookkeeping itself)
+struct Snap {
+    int64_t ne, np, gb, ng, clock;
+};
+
+// Streaming block ranges [b0, b1) of an instance's electron, positron and photon sets (empty
+// ranges for sets that are not stepped)
+struct InstSeg {
+    int e0, e1, p0, p1, g0, g1;
+};
+
 struct PlanDev {
     const SegDev *seg;
     int nseg, nblk, ninst;
@@ -65,6 +77,8 @@ struct PlanDev {
     float *sx, *snu;           // learned inverse CDF: inputs [3] and nu per global transition rank
     const int *bseg, *binst;   // [nblk] segment and instance of each streaming block
     const int4 *pbd;           // [npb] processing block: segment, streaming blocks [mb0, mb1), instance
+    const InstSeg *iseg;       // [ninst]
+    Snap *snap;                // [ninst]
 };
 
 __device__ __forceinline__ int64_t seg_total(const PlanDev &P, int sj)
@@ -257,6 +271,15 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(siz
     unsigned v[kNCtr + 1] = {};
     if (!PHO) {
         const LepDev<R> L = sg.kind == 0 ? Ip->E : Ip->P;
+        if (sg.kind == 0 && b == sg.b0 && threadIdx.x == 0) {
+            Snap sn;
+            sn.ne = *Ip->E.count;
+            sn.np = Ip->sp >= 0 ? *Ip->P.count : 0;
+            sn.gb = Ip->G.count != nullptr ? *Ip->G.count : 0;
+            sn.ng = Ip->sg >= 0 ? *Ip->G.count_prev : 0;
+            sn.clock = Ip->S.clock ? *Ip->S.clock : 0;
+            P.snap[P.binst[b]] = sn;
+        }
         stage_rates<R>(T, 0, lds);
         const int64_t n = *L.count;
         const int64_t B = block_len(n, sg.nb);
@@ -284,10 +307,34 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(siz
 
 constexpr int kExpandWords = 64;   // mask words expanded per round of the process pass (4096 slots)
 
+constexpr int kAggGroups = 16;   // processing blocks per event-count aggregation (fused bookkeeping)
+
+// Sums of a[0..3] over the block (every thread gets them); red: LDS.  Synchronizes.
+__device__ __forceinline__ void block_totals4(unsigned long long (&a)[4], unsigned long long (*red)[kBlock / 64])
+{
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        for (int o = 32; o > 0; o >>= 1) a[k] += __shfl_xor(a[k], o);
+        if ((threadIdx.x & 63) == 0) red[k][threadIdx.x >> 6] = a[k];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        a[k] = 0;
+        for (int w = 0; w < kBlock / 64; ++w) a[k] += red[k][w];
+    }
+}
+
 // One launch over the processing blocks of every set (lepton sets first, then photons); the
 // channel follows the block's set.  mode 0: tables; 1: write the inverse-CDF inputs of every
 // transition (learned inverse CDF); 2: finish the transitions with the learned nu.
-template <class R, bool GRID>
+// FUSED (tables only): no bookkeeping launch before this one.  Each block sums the transition
+// counts it needs (its rank offset inside its set, the totals of its instance's sets) and
+// derives its append base from the counts at the start of the step; the first block of an
+// instance's electron set stores the new counts, the counters and the next clock (no block of
+// this launch reads them), and every kAggGroups-th block of a set adds the event counts of its
+// streaming blocks to the instance's counters.
+template <class R, bool GRID, bool FUSED>
 __global__ void __launch_bounds__(kBlock) k_plan_process(const InstDev<R> *inst, PlanDev P, TablesDev T, int b_first,
                                                          int mode)
 {
@@ -299,13 +346,94 @@ __global__ void __launch_bounds__(kBlock) k_plan_process(const InstDev<R> *inst,
     const int4 pd = P.pbd[b_first + blockIdx.x];
     const int sj = pd.x, mb0 = pd.y, mb1 = pd.z;
     const SegDev sg = P.seg[sj];
-    if (P.gpre[mb1] == P.gpre[mb0]) return;           // no transition in this range
     const InstDev<R> *Ip = inst + pd.w;
+    SegBook bk;
+    int64_t rank0, clock;
+    if (FUSED) {
+        __shared__ unsigned long long red[4][kBlock / 64];
+        // transitions of this block's streaming blocks: one load per lane, a wave sum
+        uint32_t mine = 0;
+        for (int b = mb0 + (int)(threadIdx.x & 63); b < mb1; b += 64) mine += P.bcnt[b];
+        for (int o = 32; o > 0; o >>= 1) mine += __shfl_xor(mine, o);
+        const bool lead = sg.kind == 0 && mb0 == sg.b0;
+        const bool agg = ((mb0 - sg.b0) / P.group) % kAggGroups == 0;
+        if (mine == 0 && !lead && !agg) return;           // block-uniform
+        const InstSeg is = P.iseg[pd.w];
+        const Snap sn = P.snap[pd.w];
+        if (agg && threadIdx.x < 64) {
+            const int lane = threadIdx.x;
+            const int bend = mb0 + kAggGroups * P.group < sg.b0 + sg.nb ? mb0 + kAggGroups * P.group : sg.b0 + sg.nb;
+            unsigned long long v[kNCtr] = {};
+            for (int b = mb0 + lane; b < bend; b += 64)
+#pragma unroll
+                for (int c = 0; c < kNCtr; ++c) v[c] += P.bctr[(int64_t)b * kNCtr + c];
+#pragma unroll
+            for (int c = 0; c < kNCtr; ++c) {
+                unsigned long long t = v[c];
+                for (int o = 32; o > 0; o >>= 1) t += __shfl_xor(t, o);
+                if (lane == 0 && t) atomicAdd(Ip->ctr + c, t);
+            }
+        }
+        // transition counts: rank offset inside the set, totals of the sets this block needs
+        const bool ne_ = sg.kind != 2 || lead, np_ = sg.kind == 1 || lead, ng_ = sg.kind == 2 || lead;
+        // every load first (independent), then the sums
+        unsigned long long a[4] = {0, 0, 0, 0};
+        auto range_sum = [&](int lo, int hi) -> unsigned long long {
+            unsigned long long t = 0;
+#pragma unroll 4
+            for (int b = lo + (int)threadIdx.x; b < hi; b += kBlock) t += P.bcnt[b];
+            return t;
+        };
+        a[0] = range_sum(sg.b0, mb0);
+        if (ne_) a[1] = range_sum(is.e0, is.e1);
+        if (np_) a[2] = range_sum(is.p0, is.p1);
+        if (ng_) a[3] = range_sum(is.g0, is.g1);
+        block_totals4(a, red);
+        rank0 = (int64_t)a[0];
+        const int64_t te = (int64_t)a[1], tp = (int64_t)a[2], tg = (int64_t)a[3];
+        // the bookkeeping of the separate launch, from the counts at the start of the step
+        const bool has_g = Ip->G.count != nullptr, pair = Ip->sg >= 0;
+        const int64_t room_g = has_g && Ip->G.cap - sn.gb > 0 ? Ip->G.cap - sn.gb : 0;
+        const int64_t nfe = te < room_g ? te : room_g;
+        const int64_t nfp = tp < room_g - nfe ? tp : room_g - nfe;
+        int64_t room_p = Ip->E.cap - sn.ne < Ip->P.cap - sn.np ? Ip->E.cap - sn.ne : Ip->P.cap - sn.np;
+        room_p = room_p > 0 ? room_p : 0;
+        const int64_t nfg = tg < room_p ? tg : room_p;
+        if (sg.kind == 0) bk = SegBook{sn.ne, sn.gb, 0, te, nfe};
+        else if (sg.kind == 1) bk = SegBook{sn.np, sn.gb + nfe, 0, tp, nfp};
+        else bk = SegBook{sn.ng, sn.ne, sn.np, tg, nfg};
+        if (lead && threadIdx.x == 0) {
+            unsigned long long *ctr = Ip->ctr;
+            int64_t over = 0;
+            if (has_g) {
+                const int64_t gnew = sn.gb + nfe + nfp;
+                *Ip->G.count = gnew;
+                over += (te - nfe) + (tp - nfp);
+                if (te + tp) atomicAdd(ctr + C_EMIT, (unsigned long long)(te + tp));
+                // photons born in this step wait for the next one
+                if (pair) *Ip->G.count_prev = gnew;
+            }
+            if (pair) {
+                *Ip->E.count = sn.ne + nfg;
+                *Ip->P.count = sn.np + nfg;
+                over += tg - nfg;
+                if (tg) atomicAdd(ctr + C_PAIR, (unsigned long long)tg);
+            }
+            if (over) atomicAdd(ctr + C_OVER, (unsigned long long)over);
+            if (Ip->S.clock) *const_cast<int64_t *>(Ip->S.clock) = sn.clock + 1;
+        }
+        if (mine == 0) return;                             // block-uniform
+        clock = sn.clock;
+    } else {
+        if (P.gpre[mb1] == P.gpre[mb0]) return;           // no transition in this range
+        bk = P.sbook[sj];
+        rank0 = (int64_t)P.gpre[mb0] - (int64_t)P.gpre[sg.b0];
+        clock = P.clock_used[pd.w];
+    }
     StepDev S = Ip->S;
-    S.step += P.clock_used[sg.inst];
-    S.t += (double)P.clock_used[sg.inst] * S.dt;
+    S.step += clock;
+    S.t += (double)clock * S.dt;
     const FieldDev F = Ip->F;
-    const SegBook bk = P.sbook[sj];
     const int PHO = sg.kind == 2;
     stage_rates<R>(T, PHO, lds);
     const uint64_t *mask = P.mask + sg.mask_off;
@@ -313,7 +441,6 @@ __global__ void __launch_bounds__(kBlock) k_plan_process(const InstDev<R> *inst,
     const int64_t B = block_len(n, sg.nb);
     const int64_t start = (int64_t)(mb0 - sg.b0) * B;
     const int64_t end = (int64_t)(mb1 - sg.b0) * B < n ? (int64_t)(mb1 - sg.b0) * B : n;
-    int64_t rank0 = (int64_t)P.gpre[mb0] - (int64_t)P.gpre[sg.b0];
     const int lane = threadIdx.x & 63;
     unsigned c_ret = 0;
     for (int64_t c0 = start >> 6; c0 < cdiv(end, 64); c0 += kExpandWords) {
@@ -342,10 +469,14 @@ __global__ void __launch_bounds__(kBlock) k_plan_process(const InstDev<R> *inst,
         for (uint32_t j = threadIdx.x; j < nl; j += blockDim.x) {
             const int64_t i = c0 * 64 + list[j];
             const int64_t r = rank0 + j;
-            const int64_t gr = (int64_t)P.gpre[sg.b0] + r;            // global transition rank
             const bool br = (mask[sg.nchunks + (i >> 6)] >> (i & 63)) & 1ull;
-            const float *nu_in = mode == 2 ? P.snu + gr : nullptr;
-            float *x_out = mode == 1 ? P.sx + 3 * gr : nullptr;
+            const float *nu_in = nullptr;
+            float *x_out = nullptr;
+            if (!FUSED && mode != 0) {
+                const int64_t gr = (int64_t)P.gpre[sg.b0] + r;        // global transition rank
+                if (mode == 2) nu_in = P.snu + gr;
+                else x_out = P.sx + 3 * gr;
+            }
             if (!PHO)
                 emit_item<R, GRID>(sg.kind == 0 ? Ip->E : Ip->P, Ip->G, F, S, T, lds, i, br, r < bk.nfit ? bk.base + r : -1,
                              c_ret, nu_in, x_out);
@@ -374,6 +505,8 @@ struct qed_plan_s {
     float *d_sx, *d_snu;
     int *d_bseg, *d_binst;
     int4 *d_pbd;
+    InstSeg *d_iseg;
+    Snap *d_snap;
     qed_surrogate sur[2];      // learned inverse CDF per process (NULL: tables)
     bool tau;                  // some instance decides emission by the optical depth
     bool grid;                 // some instance uses the grid field model
@@ -412,6 +545,8 @@ void plan_free(qed_plan p)
     (void)hipFree(p->d_bseg);
     (void)hipFree(p->d_binst);
     (void)hipFree(p->d_pbd);
+    (void)hipFree(p->d_iseg);
+    (void)hipFree(p->d_snap);
     delete p;
 }
 
@@ -507,6 +642,19 @@ qed_status plan_create(qed_tables T, int n, const qed_instance *in, int ppb, int
     if (e == hipSuccess) e = hipMemcpy(p->d_bseg, bseg.data(), sizeof(int) * nblk, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(p->d_binst, binst.data(), sizeof(int) * nblk, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(p->d_pbd, pbd.data(), sizeof(int4) * pbd.size(), hipMemcpyHostToDevice);
+    std::vector<InstSeg> iseg(n);
+    for (int i = 0; i < n; ++i) {
+        auto range = [&](int sj, int &b0, int &b1) {
+            b0 = sj >= 0 ? seg[sj].b0 : 0;
+            b1 = sj >= 0 ? seg[sj].b0 + seg[sj].nb : 0;
+        };
+        range(inst[i].se, iseg[i].e0, iseg[i].e1);
+        range(inst[i].sp, iseg[i].p0, iseg[i].p1);
+        range(inst[i].sg, iseg[i].g0, iseg[i].g1);
+    }
+    if (e == hipSuccess) e = hipMalloc((void **)&p->d_iseg, sizeof(InstSeg) * n);
+    if (e == hipSuccess) e = hipMalloc((void **)&p->d_snap, sizeof(Snap) * n);
+    if (e == hipSuccess) e = hipMemcpy(p->d_iseg, iseg.data(), sizeof(InstSeg) * n, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemset(p->d_gpre, 0, sizeof(uint32_t) * (nblk + 1));
     if (e == hipSuccess) e = hipDeviceSynchronize();
     if (e != hipSuccess) {
@@ -536,6 +684,8 @@ template <class R> qed_status plan_step(qed_plan p, hipStream_t st)
     P.bseg = p->d_bseg;
     P.binst = p->d_binst;
     P.pbd = p->d_pbd;
+    P.iseg = p->d_iseg;
+    P.snap = p->d_snap;
     const InstDev<R> *inst = (const InstDev<R> *)p->d_inst;
     if (p->nblk_lep > 0) {
         if (p->tau)
@@ -556,37 +706,33 @@ template <class R> qed_status plan_step(qed_plan p, hipStream_t st)
             QS_LAUNCH(K_PLAN_PHOTON, (k_plan_main<R, 1, false, false>), dim3(p->nblk - p->nblk_lep), dim3(kBlock), p->lds, st,
                       inst, P, p->T->dev, p->nblk_lep);
     }
+    const bool sl = p->sur[0] != nullptr, sp = p->sur[1] != nullptr;
+    const int np_all = p->npb, np_l = p->npb_lep;
+    if (!(sl || sp)) {
+        // tables: the processing launch does the bookkeeping itself
+        auto proc = p->grid ? k_plan_process<R, true, true> : k_plan_process<R, false, true>;
+        QS_LAUNCH(K_PLAN_PROCESS, proc, dim3(np_all), dim3(kBlock), p->lds, st, inst, P, p->T->dev, 0, 0);
+        return qs_launch_status("qed_plan_step");
+    }
+    // learned inverse CDF: the bookkeeping launch scans the transition counts into global ranks;
+    // a first processing pass writes the network's inputs (tables for a process without a
+    // network), the network runs on each process's dense rank range, and a second pass finishes
+    // the transitions with its nu
     QS_LAUNCH(K_BOOK, k_plan_book<R>, dim3(1 + (int)cdiv(cdiv(p->nblk, kCtrGroup), kBlock / 64)), dim3(kBlock), 0, st,
               inst, P);
-    // processing: with a learned inverse CDF, a first pass writes its inputs, the network runs on
-    // the dense list of transitions, and a second pass finishes them with its nu
-    const bool sl = p->sur[0] != nullptr, sp = p->sur[1] != nullptr;
     const bool has_l = p->nblk_lep > 0, has_g = p->nblk > p->nblk_lep;
-    // pass 1 over every set; with a learned inverse CDF it writes the inputs, the network runs on
-    // each process's dense rank range, and pass 2 finishes with its nu (blocks of the sets that
-    // use the tables are skipped in it)
-    const int np_all = p->npb, np_l = p->npb_lep;
-    auto proc = p->grid ? k_plan_process<R, true> : k_plan_process<R, false>;
-    const int mode1 = (sl || sp) ? 1 : 0;
-    if (!(sl || sp)) {
-        if (np_all > 0)
-            QS_LAUNCH(K_PLAN_PROCESS, proc, dim3(np_all), dim3(kBlock), p->lds, st, inst, P, p->T->dev, 0, 0);
-    } else {
-        // tables for the process without a network, inputs for the one with it
-        if (np_l > 0)
-            QS_LAUNCH(K_PLAN_PROCESS, proc, dim3(np_l), dim3(kBlock), p->lds, st, inst, P, p->T->dev, 0,
-                      sl ? mode1 : 0);
-        if (np_all > np_l)
-            QS_LAUNCH(K_PLAN_PROCESS, proc, dim3(np_all - np_l), dim3(kBlock), p->lds, st, inst, P, p->T->dev,
-                      np_l, sp ? mode1 : 0);
-        if (has_l && sl) qs_surrogate_eval_ranks(p->sur[0], P.sx, P.gpre, 0, p->nblk_lep, P.snu, st);
-        if (has_g && sp) qs_surrogate_eval_ranks(p->sur[1], P.sx, P.gpre, p->nblk_lep, p->nblk, P.snu, st);
-        if (np_l > 0 && sl)
-            QS_LAUNCH(K_PLAN_PROCESS, proc, dim3(np_l), dim3(kBlock), p->lds, st, inst, P, p->T->dev, 0, 2);
-        if (np_all > np_l && sp)
-            QS_LAUNCH(K_PLAN_PROCESS, proc, dim3(np_all - np_l), dim3(kBlock), p->lds, st, inst, P, p->T->dev,
-                      np_l, 2);
-    }
+    auto proc = p->grid ? k_plan_process<R, true, false> : k_plan_process<R, false, false>;
+    if (np_l > 0)
+        QS_LAUNCH(K_PLAN_PROCESS, proc, dim3(np_l), dim3(kBlock), p->lds, st, inst, P, p->T->dev, 0, sl ? 1 : 0);
+    if (np_all > np_l)
+        QS_LAUNCH(K_PLAN_PROCESS, proc, dim3(np_all - np_l), dim3(kBlock), p->lds, st, inst, P, p->T->dev, np_l,
+                  sp ? 1 : 0);
+    if (has_l && sl) qs_surrogate_eval_ranks(p->sur[0], P.sx, P.gpre, 0, p->nblk_lep, P.snu, st);
+    if (has_g && sp) qs_surrogate_eval_ranks(p->sur[1], P.sx, P.gpre, p->nblk_lep, p->nblk, P.snu, st);
+    if (np_l > 0 && sl)
+        QS_LAUNCH(K_PLAN_PROCESS, proc, dim3(np_l), dim3(kBlock), p->lds, st, inst, P, p->T->dev, 0, 2);
+    if (np_all > np_l && sp)
+        QS_LAUNCH(K_PLAN_PROCESS, proc, dim3(np_all - np_l), dim3(kBlock), p->lds, st, inst, P, p->T->dev, np_l, 2);
     return qs_launch_status("qed_plan_step");
 }
 
