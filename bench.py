@@ -321,13 +321,14 @@ def main():
         return
 
     t32, t64 = q.Tables(precision=q.QED_F32), q.Tables(precision=q.QED_F64)
-    # block shape of the plan: particles per block chosen by timing the first 600 steps of each
-    # candidate (graph replays), before the timed region
+    # block shape of the plan: particles per block chosen by timing every step of the workload
+    # for each candidate (graph replays; the photon population grows over the run, so a prefix
+    # of it would favour other shapes), before the timed region
     tune = {}
-    for ppb in (256, 512, 1024, 2048, 4096):
-        tune[ppb] = run_gpu(q, t32, w, 600, 0, args.compact_every, profile=False, graph=True, ppb=ppb)["wall"]
+    for ppb in (256, 512, 1024, 2048):
+        tune[ppb] = run_gpu(q, t32, w, args.steps, 0, args.compact_every, profile=False, graph=True, ppb=ppb)["wall"]
     ppb = min(tune, key=tune.get)
-    log(f"particles per block {ppb} (600-step times {tune})")
+    log(f"particles per block {ppb} ({args.steps}-step times {tune})")
     args.ppb = ppb
     # timed run: graph replays (no per-launch host work); kernel timing in a separate eager run
     r32 = run_gpu(q, t32, w, args.steps, args.warmup, args.compact_every, profile=False, graph=True, ppb=ppb)
@@ -362,7 +363,7 @@ def main():
                       "time_steps": args.steps, "precision": "FP32 bulk + FP64 islands",
                       "channels": "NLC + NBW, spin and polarization resolved"},
            "roofline": roof,
-           "tuning": {"particles_per_block": ppb, "s_per_600_steps": {str(k): round(v, 4) for k, v in tune.items()}},
+           "tuning": {"particles_per_block": ppb, "steps": args.steps, "s_per_run": {str(k): round(v, 4) for k, v in tune.items()}},
            "work": {"lepton_steps": c["n_lepton_steps"], "photon_steps": c["n_photon_steps"],
                     "photons_emitted": c["n_emit"], "pairs": c["n_pair"]}}
 

@@ -233,14 +233,16 @@ qed_status qed_profile_start(void);
 qed_status qed_profile_stop(qed_kernel_time *out, int max_entries, int *n_entries);
 
 /* ---------------------------------------------------------------------------------------
-   Whole steps of one or many independent instances (collisions) in two launches.
+   Whole steps of one or many independent instances (collisions) in three launches.
 
    One step of an instance is the paper's per-step sequence (NLC section flow chart for the
    leptons, NBW section for the photons): qed_emit for the electrons, qed_emit for the
    positrons, qed_pair for the photons stored before the step, then the step clock advances.
-   qed_plan_step produces the same particles, bit for bit, for every instance at once: one
-   streaming launch over all particle sets (each set owns a contiguous range of blocks) and one
-   launch that processes the emitters and the decaying photons.  Appends keep the per-species
+   qed_plan_step produces the same particles, bit for bit, for every instance at once: a lepton
+   and a photon streaming launch over all particle sets (each set owns a contiguous range of
+   blocks), then one launch that does the bookkeeping and processes the emitters and the
+   decaying photons (with a learned inverse CDF: a bookkeeping launch, then two processing
+   passes around the network).  Appends keep the per-species
    order (photons of electrons, then of positrons, in emitter order; pairs in photon order). */
 typedef struct {
     qed_leptons     electrons;   /* species 0 */

@@ -1,5 +1,5 @@
 // qs_plan.hip -- one whole step (NLC for electrons and positrons, NBW for photons) of any number
-// of independent instances in five launches: qed_plan_create / qed_plan_step / qed_plan_destroy.
+// of independent instances in three launches: qed_plan_create / qed_plan_step / qed_plan_destroy.
 //
 // A plan splits every particle set of every instance into a contiguous range of blocks of one
 // block index space ("segments": the electrons and positrons of every instance, then the photons
@@ -7,14 +7,16 @@
 //   main     block b streams its share of its segment (lepton push + decision + no-emission
 //            update, or the two-phase photon pass) and writes its transition count and event
 //            counts (plain stores); leptons and photons are two launches, each with its own
-//            register allocation;
-//   book     block 0 scans the transition counts of all blocks in index order and does each
-//            instance's bookkeeping: append bases, capacity clamp, device counts, the step
-//            clock; the other blocks add the event counts of 64 main blocks each to the
-//            instances' counters;
-//   process  block b expands its own mask words into an ordered list in LDS and processes its
-//            transitions, writing photons (or pairs) at the instance's base + the rank (again
-//            one launch for the lepton blocks and one for the photon blocks).
+//            register allocation; the first lepton block of an instance also stores the
+//            instance's counts and clock at the start of the step;
+//   process  each block covers a group of main blocks of one segment: it sums the transition
+//            counts it needs (its rank offset in its set, the totals of its instance's sets),
+//            derives the append bases from the stored counts, expands its own mask words into
+//            an ordered list in LDS and processes its transitions, writing photons (or pairs)
+//            at the instance's base + the rank; the first block of an instance stores the new
+//            counts and clock, and every 16th block of a set adds event counts to the counters.
+// With a learned inverse CDF a bookkeeping launch (book) scans the transition counts into
+// global ranks first, and the processing runs as two passes around the network.
 // No block waits for another and no fence orders blocks: every hand-over is a launch boundary
 // on the stream.  (On this chip the L2 is per XCD, so a device-scope release or acquire fence
 // inside a kernel writes back or invalidates a whole L2.)
