@@ -77,6 +77,24 @@ def test_plan_equals_per_species_head_on(q, tabs, prec):
     assert int(a.clock.item()) == int(b.clock.item()) == 1000
 
 
+def test_plan_equals_per_species_pair_overflow(q, tabs):
+    """Positron store of four slots: pairs beyond it are counted as overflow and not stored, in
+    the plan as in the per-species calls (the pair append bases and the capacity clamp of the
+    processing launch's own bookkeeping)."""
+    import torch
+    w = synth.subsample(synth.c2(), np.arange(3000))
+    a = _sim(q, tabs["fp32"], w, False, w.n + 4, 4, 200_000)
+    b = _sim(q, tabs["fp32"], w, True, w.n + 4, 4, 200_000)
+    for k in range(1, 1201):
+        a.step(); b.step()
+        if k % 50 == 0:
+            a.compact(); b.compact()
+    torch.cuda.synchronize()
+    _assert_same(_state(q, a), _state(q, b), "pair overflow")
+    c = q.counters_dict(b.ctr)
+    assert b.p.n() == 4 and c["n_pair"] > 4 and c["n_capacity_overflow"] == c["n_pair"] - 4
+
+
 def test_plan_equals_per_species_optical_depth(q, tabs):
     """Optical-depth decision in the merged step: 1500 electrons of the head-on collision, FP32,
     tau and targets compared too."""
