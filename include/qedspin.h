@@ -259,7 +259,9 @@ typedef struct qed_surrogate_s *qed_surrogate;   /* opaque, library-owned; see b
 
 typedef struct {
     int particles_per_block;     /* blocks of a set = ceil(capacity / this), default 256 */
-    int max_blocks_per_set;      /* cap on the blocks of one set, default 2048 */
+    int max_blocks_per_set;      /* cap on the blocks of one set; default: the blocks of the photon
+                                    streaming kernel resident at once on the device (1024 on
+                                    MI355X in single precision) */
     qed_surrogate icdf_nlc;      /* learned inverse CDF for the emission energy (NULL: tables); */
     qed_surrogate icdf_nbw;      /* ... for the pair split.  Only with QED_F32 tables, and built on
                                     the same tables (else QED_ERR_UNSUPPORTED / QED_ERR_INVALID).

@@ -307,7 +307,7 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(siz
     else if (threadIdx.x == kNCtr) P.bcnt[b] = tot[kNCtr];
 }
 
-constexpr int kExpandWords = 64;   // mask words expanded per round of the process pass (4096 slots)
+constexpr int kExpandWords = kBlock; // mask words expanded per round of the process pass, one per thread (16384 slots)
 
 constexpr int kAggGroups = 16;   // processing blocks per event-count aggregation (fused bookkeeping)
 
@@ -343,7 +343,7 @@ __global__ void __launch_bounds__(kBlock) k_plan_process(const InstDev<R> *inst,
     extern __shared__ unsigned char smem_raw[];
     R *lds = reinterpret_cast<R *>(smem_raw);
     __shared__ uint16_t list[kExpandWords * 64];
-    __shared__ uint32_t nlist;
+    __shared__ uint32_t nlist, wtot[kBlock / 64];
     // this block covers the streaming blocks [mb0, mb1) of one segment: a contiguous slot range
     const int4 pd = P.pbd[b_first + blockIdx.x];
     const int sj = pd.x, mb0 = pd.y, mb1 = pd.z;
@@ -447,25 +447,26 @@ __global__ void __launch_bounds__(kBlock) k_plan_process(const InstDev<R> *inst,
     unsigned c_ret = 0;
     for (int64_t c0 = start >> 6; c0 < cdiv(end, 64); c0 += kExpandWords) {
         const int64_t c1 = c0 + kExpandWords < cdiv(end, 64) ? c0 + kExpandWords : cdiv(end, 64);
-        // wave 0: one mask word per lane, positions by an inclusive scan of the popcounts
-        if (threadIdx.x < 64) {
-            const int64_t c = c0 + lane;
-            const uint64_t m = c < c1 ? mask[c] : 0ull;
-            const uint32_t pc = __popcll(m);
-            uint32_t incl = pc;
-            for (int o = 1; o < 64; o <<= 1) {
-                const uint32_t y = __shfl_up(incl, o);
-                if (lane >= o) incl += y;
-            }
-            uint32_t pos = incl - pc;
-            uint64_t bits = m;
-            while (bits) {
-                const int bit = __ffsll((long long)bits) - 1;
-                list[pos++] = (uint16_t)(lane * 64 + bit);
-                bits &= bits - 1;
-            }
-            if (lane == 63) nlist = incl;
+        // one mask word per thread; positions by a block-wide exclusive scan of the popcounts
+        const int64_t c = c0 + threadIdx.x;
+        const uint64_t m = c < c1 ? mask[c] : 0ull;
+        const uint32_t pc = __popcll(m);
+        uint32_t incl = pc;
+        for (int o = 1; o < 64; o <<= 1) {
+            const uint32_t y = __shfl_up(incl, o);
+            if (lane >= o) incl += y;
         }
+        if (lane == 63) wtot[threadIdx.x >> 6] = incl;
+        __syncthreads();
+        uint32_t pos = incl - pc;
+        for (int w = 0; w < (int)(threadIdx.x >> 6); ++w) pos += wtot[w];
+        uint64_t bits = m;
+        while (bits) {
+            const int bit = __ffsll((long long)bits) - 1;
+            list[pos++] = (uint16_t)(threadIdx.x * 64 + bit);
+            bits &= bits - 1;
+        }
+        if (threadIdx.x == kBlock - 1) nlist = pos;
         __syncthreads();
         const uint32_t nl = nlist;
         for (uint32_t j = threadIdx.x; j < nl; j += blockDim.x) {
@@ -552,10 +553,26 @@ void plan_free(qed_plan p)
     delete p;
 }
 
+// Default cap on the blocks of one set: one resident round of the photon streaming kernel on
+// this device (compute units x blocks per compute unit at its register and LDS use), so that a
+// set's blocks all run at once instead of in a ragged second round.
+template <class R> int resident_blocks(size_t lds)
+{
+    int dev = 0, cus = 0, per_cu = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return kMaxGrid;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0) return kMaxGrid;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_plan_main<R, 1, false, false>, kBlock, lds) != hipSuccess ||
+        per_cu <= 0)
+        return kMaxGrid;
+    return cus * per_cu;
+}
+
 template <class R>
 qed_status plan_create(qed_tables T, int n, const qed_instance *in, int ppb, int maxb, int group, qed_surrogate s_nlc,
                        qed_surrogate s_nbw, qed_plan *out)
 {
+    const size_t lds = sizeof(R) * 2 * (T->dev.n_chi[0] > T->dev.n_chi[1] ? T->dev.n_chi[0] : T->dev.n_chi[1]);
+    if (maxb <= 0) maxb = resident_blocks<R>(lds);
     std::vector<InstDev<R>> inst(n);
     std::vector<SegDev> seg;
     int64_t nblk = 0, mask_words = 0;
@@ -597,7 +614,7 @@ qed_status plan_create(qed_tables T, int n, const qed_instance *in, int ppb, int
     p->npb = (int)npb;
     p->npb_lep = (int)npb_lep;
     p->group = group;
-    p->lds = sizeof(R) * 2 * (T->dev.n_chi[0] > T->dev.n_chi[1] ? T->dev.n_chi[0] : T->dev.n_chi[1]);
+    p->lds = lds;
     hipError_t e = hipMalloc(&p->d_inst, sizeof(InstDev<R>) * n);
     if (e == hipSuccess) e = hipMalloc((void **)&p->d_seg, sizeof(SegDev) * seg.size());
     if (e == hipSuccess) e = hipMalloc((void **)&p->d_mask, sizeof(uint64_t) * mask_words);
@@ -760,7 +777,7 @@ extern "C" qed_status qed_plan_create(qed_tables T, int n_instances, const qed_i
     for (int i = 0; i < n_instances; ++i)
         if (!instance_ok(&instances[i])) return QED_ERR_INVALID;
     const int ppb = config && config->particles_per_block > 0 ? config->particles_per_block : kBlock;
-    const int maxb = config && config->max_blocks_per_set > 0 ? config->max_blocks_per_set : kMaxGrid;
+    const int maxb = config && config->max_blocks_per_set > 0 ? config->max_blocks_per_set : 0;   // 0: one resident round
     const int group = config && config->process_group > 0 ? config->process_group : 4;
     qed_surrogate sn = config ? config->icdf_nlc : nullptr, sb = config ? config->icdf_nbw : nullptr;
     // the networks are trained for 24-bit uniforms (single precision) on these tables' ranges
