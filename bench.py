@@ -43,14 +43,15 @@ def bytes_per_unit(es, tracked_x=1):
     return lep, pho
 
 
-def run_gpu(q, tab, w, steps, warmup, compact_every, profile, graph=True, merged=True, surrogates=(None, None), ppb=0):
+def run_gpu(q, tab, w, steps, warmup, compact_every, profile, graph=True, merged=True, surrogates=(None, None), ppb=0,
+            photons_per_electron=30):
     """Time `steps` steps from the initial state.  With graph=True each run of `compact_every`
     steps plus the compaction is one captured HIP graph (recorded before the timed region).
     merged=True runs each step as one qed_plan_step; surrogates: learned inverse CDFs (NLC, NBW)."""
     import torch
     from paper_2511_08929_amd.sim import Simulation
     cap_p = max(1000, w.n // 5)
-    cap_g = max(100_000, 30 * w.n)
+    cap_g = max(100_000, photons_per_electron * w.n)
     fields = q.make_fields(w.field_kind, a0=w.a0, phase_len=w.phase_len)
 
     def fresh():
@@ -168,11 +169,12 @@ def spectrum_error(ref, got, bins_per_decade=8, min_count=10_000):
                 photons_ref=int(ref["k"].size), photons=int(got["k"].size))
 
 
-def run_batched(q, tab, ws, steps, compact_every, ppb, graph=True):
+def run_batched(q, tab, ws, steps, compact_every, ppb, graph=True, photons_per_electron=40):
     """C5-shaped ensembles in one plan; returns wall time and the summed counters"""
     import torch
     from paper_2511_08929_amd.sim import Batch
-    specs = [dict(cap_e=w.n + max(1000, w.n // 5), cap_p=max(1000, w.n // 5), cap_g=max(100_000, 40 * w.n),
+    specs = [dict(cap_e=w.n + max(1000, w.n // 5), cap_p=max(1000, w.n // 5),
+                  cap_g=max(100_000, photons_per_electron * w.n),
                   track=w.track, fields=dict(kind=w.field_kind, a0=w.a0, phase_len=w.phase_len), dt=w.dt,
                   eps_r=synth.EPS_R, seed=w.seed, flags=q.QED_ALL, k_retire=w.k_retire) for w in ws]
     bat = Batch(tab, specs, particles_per_block=ppb)
@@ -286,6 +288,50 @@ def extras(q, args, w, t32, t64, out, v32, v64):
                       "fp64_value": round(vb64, 1), "speedup_vs_fp64": round(vb / vb64, 3)}
 
 
+def full_scale(q, args, t32, t64, out):
+    """Two workloads at their stated sizes (opt-in, several minutes): the learned inverse CDF on
+    10^8 electrons of the head-on collision, with the FP32 and FP64 table paths on the same
+    steps; and the 64 batched ensembles at full particle counts, FP32 and FP64."""
+    import torch
+    res = {}
+    wb = synth.c2(n=args.full_n)
+    log(f"full scale: head-on collision, {wb.n} electrons, {args.steps} steps")
+    sn, sb = q.Surrogate(t32, 0, seed=1), q.Surrogate(t32, 1, seed=2)
+    sn.fit(), sb.fit()
+    for label, tab, sur in (("fp32", t32, (None, None)), ("surrogate", t32, (sn, sb)), ("fp64", t64, (None, None))):
+        r = run_gpu(q, tab, wb, args.steps, 0, args.compact_every, profile=False, graph=True, surrogates=sur,
+                    ppb=args.ppb, photons_per_electron=24)
+        c = r["ctr"]
+        v = (c["n_lepton_steps"] + c["n_photon_steps"]) / r["wall"]
+        res[label] = {"value": round(v, 1), "wall_s": round(r["wall"], 3), "photons_emitted": c["n_emit"],
+                      "pairs": c["n_pair"], "capacity_overflow": c["n_capacity_overflow"]}
+        log(f"full scale {label}: {r['wall']:.2f} s, {v:.4g}/s, counters {c}")
+        torch.cuda.empty_cache()
+    res["surrogate"]["speedup_vs_fp64"] = round(res["surrogate"]["value"] / res["fp64"]["value"], 3)
+    res["fp32"]["speedup_vs_fp64"] = round(res["fp32"]["value"] / res["fp64"]["value"], 3)
+    out["full_scale_head_on"] = dict(electrons=wb.n, steps=args.steps, photon_capacity_per_electron=24, **res)
+    del sn, sb, wb
+    torch.cuda.empty_cache()
+    ws = synth.c5(scale=1.0)
+    steps_b = 2000
+    log(f"full scale: batched, {len(ws)} instances, {sum(x.n for x in ws)} electrons, {steps_b} steps")
+    cand = {}
+    for ppb in (512, 1024, 2048):
+        cand[ppb] = run_batched(q, t32, ws, 300, args.compact_every, ppb, photons_per_electron=24)["wall"]
+    best = min(cand, key=cand.get)
+    rb = {}
+    for label, tab in (("fp32", t32), ("fp64", t64)):
+        r = run_batched(q, tab, ws, steps_b, args.compact_every, best, photons_per_electron=24)
+        c = r["ctr"]
+        rb[label] = {"value": round((c["n_lepton_steps"] + c["n_photon_steps"]) / r["wall"], 1),
+                     "wall_s": round(r["wall"], 3), "capacity_overflow": c["n_capacity_overflow"]}
+        torch.cuda.empty_cache()
+        log(f"full scale batched {label}: {r['wall']:.2f} s, {rb[label]['value']:.4g}/s, counters {c}")
+    out["full_scale_batched"] = dict(instances=len(ws), electrons=int(sum(x.n for x in ws)), steps=steps_b,
+                                     particles_per_block=best, speedup_vs_fp64=round(rb["fp32"]["value"] /
+                                                                                     rb["fp64"]["value"], 3), **rb)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -301,6 +347,10 @@ def main():
     ap.add_argument("--batched-scale", type=float, default=0.05,
                     help="particle counts of the 64 batched ensembles relative to the full recipe")
     ap.add_argument("--ppb", type=int, default=0, help="particles per block of the plan in --probe runs (0: 256)")
+    ap.add_argument("--full-scale", action="store_true",
+                    help="also run the learned inverse CDF on 10^8 electrons and the batched ensembles at full "
+                         "size (several minutes)")
+    ap.add_argument("--full-n", type=int, default=100_000_000, help="electrons of the --full-scale head-on run")
     ap.add_argument("--probe", action="store_true",
                     help="profiler run: copy calibration + the FP32 path, eager, no JSON line")
     args = ap.parse_args()
@@ -377,6 +427,8 @@ def main():
 
     if not args.no_extras:
         extras(q, args, w, t32, t64, out, value, out.get("fp64_value"))
+    if args.full_scale:
+        full_scale(q, args, t32, t64, out)
 
     if not args.no_cpu_baseline:
         nthreads = min(16, os.cpu_count() or 1)

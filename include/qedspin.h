@@ -216,8 +216,9 @@ qed_status qed_pair(qed_tables tables, const qed_photons *photons, const qed_fie
                     size_t workspace_bytes, qed_stream stream);
 
 /* Order-preserving removal of dead photon slots (id == 0); updates *d_count and
-   *d_count_prev.  The workspace must hold qed_workspace_size(capacity) bytes plus one photon
-   record per slot: see qed_compact_workspace_size. */
+   *d_count_prev.  The workspace must hold qed_workspace_size(capacity) bytes plus a staging
+   buffer of min(capacity, 2^26) photon records (the survivors are copied in rounds of that
+   many): see qed_compact_workspace_size. */
 size_t qed_compact_workspace_size(const qed_photons *photons, qed_precision precision);
 qed_status qed_compact(const qed_photons *photons, qed_precision precision, void *workspace,
                        size_t workspace_bytes, qed_stream stream);

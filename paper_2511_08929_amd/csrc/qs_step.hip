@@ -256,34 +256,44 @@ template <class R> struct PhoStage {
     uint64_t *id;
 };
 
+// The survivors are copied in rounds of at most kCompactChunk ranks through a staging buffer of
+// that size: round [r0, r0 + len) gathers the survivors of ranks r0.. (at slots idx[r] >= r) and
+// writes them back to slots r0..  Later rounds read slots idx[r] >= r >= r0 + len only, which
+// this round does not write, so the stream order of the rounds makes the copy exact.
+constexpr int64_t kCompactChunk = int64_t(1) << 26;
+
 template <class R>
-__global__ void __launch_bounds__(kBlock) k_gather(PhoDev<R> G, PhoStage<R> T, const uint32_t *idx, const int64_t *book)
+__global__ void __launch_bounds__(kBlock) k_gather(PhoDev<R> G, PhoStage<R> T, const uint32_t *idx, const int64_t *book,
+                                                   int64_t r0, int64_t len)
 {
-    const int64_t total = book[1];
-    for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < total; j += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t i = idx[j];
-        T.id[j] = G.id[i];
+    const int64_t hi = book[1] < r0 + len ? book[1] : r0 + len;
+    for (int64_t j = r0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < hi; j += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i = idx[j], t = j - r0;
+        T.id[t] = G.id[i];
         for (int c = 0; c < 3; ++c) {
-            if (G.x[c]) T.x[c][j] = G.x[c][i];
-            T.k[c][j] = G.k[c][i];
-            T.P[c][j] = G.P[c][i];
+            if (G.x[c]) T.x[c][t] = G.x[c][i];
+            T.k[c][t] = G.k[c][i];
+            T.P[c][t] = G.P[c][i];
         }
     }
 }
 
 template <class R>
-__global__ void __launch_bounds__(kBlock) k_scatter_back(PhoDev<R> G, PhoStage<R> T, const int64_t *book)
+__global__ void __launch_bounds__(kBlock) k_scatter_back(PhoDev<R> G, PhoStage<R> T, const int64_t *book, int64_t r0,
+                                                         int64_t len)
 {
     const int64_t total = book[1];
-    for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < total; j += (int64_t)gridDim.x * blockDim.x) {
-        G.id[j] = T.id[j];
+    const int64_t hi = total < r0 + len ? total : r0 + len;
+    for (int64_t j = r0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < hi; j += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t t = j - r0;
+        G.id[j] = T.id[t];
         for (int c = 0; c < 3; ++c) {
-            if (G.x[c]) G.x[c][j] = T.x[c][j];
-            G.k[c][j] = T.k[c][j];
-            G.P[c][j] = T.P[c][j];
+            if (G.x[c]) G.x[c][j] = T.x[c][t];
+            G.k[c][j] = T.k[c][t];
+            G.P[c][j] = T.P[c][t];
         }
     }
-    if (blockIdx.x == 0 && threadIdx.x == 0) *G.count = total;
+    if (r0 == 0 && blockIdx.x == 0 && threadIdx.x == 0) *G.count = total;
 }
 
 // ------------------------------------------------------------------ host side
@@ -418,8 +428,8 @@ extern "C" size_t qed_compact_workspace_size(const qed_photons *G, qed_precision
     const size_t es = prec == QED_F64 ? sizeof(double) : sizeof(float);
     int ncomp = 6;
     for (int c = 0; c < 3; ++c) ncomp += G->x[c] != nullptr;
-    return qed_workspace_size(G->capacity) + ncomp * align256(es * (G->capacity > 0 ? G->capacity : 1)) +
-           align256(sizeof(uint64_t) * (G->capacity > 0 ? G->capacity : 1));
+    const int64_t stage = G->capacity < kCompactChunk ? (G->capacity > 0 ? G->capacity : 1) : kCompactChunk;
+    return qed_workspace_size(G->capacity) + ncomp * align256(es * stage) + align256(sizeof(uint64_t) * stage);
 }
 
 template <class R> static qed_status compact_impl(const qed_photons *G, void *ws, hipStream_t st)
@@ -428,13 +438,14 @@ template <class R> static qed_status compact_impl(const qed_photons *G, void *ws
     const WS w = carve(ws, G->capacity, &nch);
     char *b = (char *)ws + qed_workspace_size(G->capacity);
     const int64_t cap = G->capacity > 0 ? G->capacity : 1;
+    const int64_t stage = cap < kCompactChunk ? cap : kCompactChunk;
     PhoStage<R> S;
     for (int c = 0; c < 3; ++c) {
         S.x[c] = nullptr;
-        if (G->x[c]) { S.x[c] = (R *)b; b += align256(sizeof(R) * cap); }
+        if (G->x[c]) { S.x[c] = (R *)b; b += align256(sizeof(R) * stage); }
     }
-    for (int c = 0; c < 3; ++c) { S.k[c] = (R *)b; b += align256(sizeof(R) * cap); }
-    for (int c = 0; c < 3; ++c) { S.P[c] = (R *)b; b += align256(sizeof(R) * cap); }
+    for (int c = 0; c < 3; ++c) { S.k[c] = (R *)b; b += align256(sizeof(R) * stage); }
+    for (int c = 0; c < 3; ++c) { S.P[c] = (R *)b; b += align256(sizeof(R) * stage); }
     S.id = (uint64_t *)b;
     const PhoDev<R> gd = pho_dev<R>(G);
     const int g = grid_for(G->capacity);
@@ -442,8 +453,11 @@ template <class R> static qed_status compact_impl(const qed_photons *G, void *ws
     QS_LAUNCH(K_MASK_EXPAND, k_expand, dim3(g), dim3(kBlock), 0, st, (const uint64_t *)w.mask, (const uint32_t *)w.bcnt,
               (const int64_t *)G->d_count, w.book, 2, (int64_t *)nullptr, (int64_t)0, (int64_t *)nullptr, (int64_t)0,
               G->d_count_prev, (unsigned long long *)nullptr, (const uint32_t *)nullptr, w.idx);
-    QS_LAUNCH(K_GATHER, k_gather<R>, dim3(g), dim3(kBlock), 0, st, gd, S, w.idx, w.book);
-    QS_LAUNCH(K_SCATTER_BACK, k_scatter_back<R>, dim3(g), dim3(kBlock), 0, st, gd, S, w.book);
+    const int gs = grid_for(stage);
+    for (int64_t r0 = 0; r0 < cap; r0 += stage) {
+        QS_LAUNCH(K_GATHER, k_gather<R>, dim3(gs), dim3(kBlock), 0, st, gd, S, w.idx, w.book, r0, stage);
+        QS_LAUNCH(K_SCATTER_BACK, k_scatter_back<R>, dim3(gs), dim3(kBlock), 0, st, gd, S, w.book, r0, stage);
+    }
     return qs_launch_status(__func__);
 }
 

@@ -485,3 +485,31 @@ def test_graph_replay_matches_eager(q, gtab64):
             np.testing.assert_array_equal(x, y)
         assert q.counters_dict(a.ctr) == q.counters_dict(b.ctr), rep
     assert a.n == b.n and q.counters_dict(a.ctr)["n_emit"] > 0
+
+
+def test_compaction_in_rounds(q):
+    """More survivors than one staging round holds (2^26): a store of 80 million FP32 photons with
+    every 7th slot dead, compacted in two copy rounds, against torch's order-preserving boolean
+    selection of the same arrays."""
+    import torch
+    n = 80_000_000
+    g = q.PhotonBuffers(n, torch.float32, track=(True, False, False))
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(5)
+    for a in [g.x[0]] + g.k + g.P:
+        a.uniform_(-1.0, 1.0, generator=gen)
+    ids = torch.arange(1, n + 1, dtype=torch.int64, device="cuda")
+    ids[::7] = 0
+    g.id.copy_(ids)
+    g.count.fill_(n)
+    g.count_prev.fill_(n)
+    live = g.id != 0
+    expect = [a[live] for a in [g.x[0]] + g.k + g.P + [g.id]]
+    m = int(live.sum().item())
+    assert m > 2 ** 26
+    ws = q.new_workspace(q.qed_compact_workspace_size(g, q.QED_F32))
+    q.qed_compact(g, q.QED_F32, ws)
+    torch.cuda.synchronize()
+    assert g.n() == m and int(g.count_prev.item()) == m
+    for a, e in zip([g.x[0]] + g.k + g.P + [g.id], expect):
+        assert torch.equal(a[:m], e)

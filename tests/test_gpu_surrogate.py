@@ -170,3 +170,51 @@ def test_merged_step_with_surrogate(q, t32, trained):
     torch.cuda.synchronize()
     for x, y in zip(c.e.arrays() + c.g.arrays(), d.e.arrays() + d.g.arrays()):
         np.testing.assert_array_equal(x, y)
+
+
+def test_surrogate_step_full_size(q, t32, trained):
+    """The learned-inverse-CDF workload at its stated size: all 10^8 electrons of the head-on
+    collision, FP32, started at the centre of the pulse.  One step from the same state with the
+    tables and with the network: the same emitters (the same photon ids in the same slots), photon
+    energies within the network's stated error, and every electron that did not emit equal bit for
+    bit (its step does not involve the inverse CDF)."""
+    import torch
+    from paper_2511_08929_amd.sim import Simulation
+    w = synth.c2(n=100_000_000)
+    f = q.make_fields(w.field_kind, a0=w.a0, phase_len=w.phase_len)
+    t0 = 0.5 * w.phase_len + math.pi            # electron phases t + x in the middle of the pulse
+    sur = (trained[0][0], trained[1][0])
+
+    def mk(use):
+        sim = Simulation(t32, cap_e=w.n + 1000, cap_p=1000, cap_g=w.n // 4, track=w.track, fields=f, dt=w.dt,
+                         eps_r=EPS, seed=w.seed, flags=q.QED_ALL, k_retire=0.0, t0=t0, device_clock=True,
+                         merged=True, surrogates=sur if use else (None, None))
+        sim.e.load(w.x, w.p, w.s)
+        return sim
+
+    a = mk(False)
+    a.step()
+    torch.cuda.synchronize()
+    ca = q.counters_dict(a.ctr)
+    ng = a.g.n()
+    ida = a.g.id[:ng].cpu().numpy()
+    ka = np.stack([a.g.k[i][:ng].double().cpu().numpy() for i in range(3)])
+    pa = [a.e.p[i][:w.n].cpu().numpy() for i in range(3)]
+    del a
+    torch.cuda.empty_cache()
+    b = mk(True)
+    b.step()
+    torch.cuda.synchronize()
+    cb = q.counters_dict(b.ctr)
+    assert ca["n_capacity_overflow"] == 0 and cb["n_capacity_overflow"] == 0
+    assert ca["n_emit"] == cb["n_emit"] == ng == b.g.n() and ng > 10**6
+    np.testing.assert_array_equal(ida, b.g.id[:ng].cpu().numpy())
+    kb = np.stack([b.g.k[i][:ng].double().cpu().numpy() for i in range(3)])
+    rel = np.linalg.norm(kb - ka, axis=0) / np.linalg.norm(ka, axis=0)
+    print(f"10^8 electrons, one step: {ng} photons, energy rel err median {np.median(rel):.3g} "
+          f"p99 {np.quantile(rel, 0.99):.3g}")
+    assert np.median(rel) < 0.04
+    same = np.ones(w.n, dtype=bool)
+    for i in range(3):
+        same &= pa[i] == b.e.p[i][:w.n].cpu().numpy()
+    assert (~same).sum() <= ng                   # only emitters differ (recoil with the network's lambda)
