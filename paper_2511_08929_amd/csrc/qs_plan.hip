@@ -437,7 +437,16 @@ __global__ void __launch_bounds__(kBlock) k_plan_process(const InstDev<R> *inst,
     S.t += (double)clock * S.dt;
     const FieldDev F = Ip->F;
     const int PHO = sg.kind == 2;
-    stage_rates<R>(T, PHO, lds);
+    // single precision: the Bessel quadrature nodes (6 KB) join the rate rows in LDS, so the
+    // node-by-node sums of the emitters and pairs read LDS instead of L2
+    __shared__ float4 bnodes[sizeof(R) == 4 ? kBn32Nodes : 1];
+    TablesDev Tl = T;
+    if (sizeof(R) == 4) {
+        const float4 *src = reinterpret_cast<const float4 *>(T.bn32);
+        for (int j = threadIdx.x; j < kBn32Nodes; j += kBlock) bnodes[j] = src[j];
+        Tl.bn32 = reinterpret_cast<const float *>(bnodes);
+    }
+    stage_rates<R>(T, PHO, lds);                      // (its barrier also covers the nodes)
     const uint64_t *mask = P.mask + sg.mask_off;
     const int64_t n = bk.n_main;
     const int64_t B = block_len(n, sg.nb);
@@ -481,10 +490,10 @@ __global__ void __launch_bounds__(kBlock) k_plan_process(const InstDev<R> *inst,
                 else x_out = P.sx + 3 * gr;
             }
             if (!PHO)
-                emit_item<R, GRID>(sg.kind == 0 ? Ip->E : Ip->P, Ip->G, F, S, T, lds, i, br, r < bk.nfit ? bk.base + r : -1,
+                emit_item<R, GRID>(sg.kind == 0 ? Ip->E : Ip->P, Ip->G, F, S, Tl, lds, i, br, r < bk.nfit ? bk.base + r : -1,
                              c_ret, nu_in, x_out);
             else
-                pair_item<R, GRID>(Ip->G, Ip->E, Ip->P, F, S, T, lds, i, br, r < bk.nfit ? bk.base + r : -1, bk.base2 + r, nu_in,
+                pair_item<R, GRID>(Ip->G, Ip->E, Ip->P, F, S, Tl, lds, i, br, r < bk.nfit ? bk.base + r : -1, bk.base2 + r, nu_in,
                              x_out);
         }
         rank0 += nl;
