@@ -119,6 +119,22 @@ def load_traffic(kernel):
     return blob.get("traffic_bytes_per_launch")
 
 
+VALU_FILE = os.path.join(ROOT, "profiles", "plan_kernels_head_on_1e6_fp32_valu.md")
+
+
+def load_valu(kernel):
+    """VALU issue fraction of `kernel` (SQ_INSTS_VALU per launch over one 64-lane instruction per CU
+    per cycle at 2.4 GHz for the traced duration) from the committed counter summary, or None if
+    absent or taken on other sources."""
+    try:
+        blob = json.loads(open(VALU_FILE).read().split("```json", 1)[1].split("```", 1)[0])
+    except (OSError, IndexError, ValueError):
+        return None
+    if blob.get("source_sha256") != kernel_source_hash():
+        return None
+    return blob.get("kernels", {}).get(kernel, {}).get("valu_issue_frac")
+
+
 def spectra(q, tab, w, steps, surrogates=(None, None)):
     """Every photon emitted in `steps` steps of workload w (no retirement, no compaction: dead
     slots keep their momentum and P-vector) and the electrons' final spins."""
@@ -399,7 +415,7 @@ def main():
     calls, ms = kt[dom]
     achieved = bytes_of[dom] / (ms * 1e-3) / 1e9
     roof = dict(bound="hbm", kernel=dom, achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
-                frac=round(achieved / HBM_PEAK_GBS, 4), traffic=load_traffic(dom),
+                frac=round(achieved / HBM_PEAK_GBS, 4), traffic=load_traffic(dom), valu_issue_frac=load_valu(dom),
                 avg_launch_us=round(ms * 1e3 / calls, 2), launches=calls,
                 bytes_per_launch=round(bytes_of[dom] / calls),
                 kernel_ms={k: round(v[1], 3) for k, v in rk["ktimes"].items()})
