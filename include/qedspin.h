@@ -242,8 +242,7 @@ qed_status qed_profile_stop(qed_kernel_time *out, int max_entries, int *n_entrie
    qed_plan_step produces the same particles, bit for bit, for every instance at once: a lepton
    and a photon streaming launch over all particle sets (each set owns a contiguous range of
    blocks), then one launch that does the bookkeeping and processes the emitters and the
-   decaying photons (with a learned inverse CDF: a bookkeeping launch, then two processing
-   passes around the network).  Appends keep the per-species
+   decaying photons (with a learned inverse CDF too: the network runs in that launch).  Appends keep the per-species
    order (photons of electrons, then of positrons, in emitter order; pairs in photon order). */
 typedef struct {
     qed_leptons     electrons;   /* species 0 */
@@ -266,7 +265,8 @@ typedef struct {
     qed_surrogate icdf_nlc;      /* learned inverse CDF for the emission energy (NULL: tables); */
     qed_surrogate icdf_nbw;      /* ... for the pair split.  Only with QED_F32 tables, and built on
                                     the same tables (else QED_ERR_UNSUPPORTED / QED_ERR_INVALID).
-                                    The plan keeps a scratch of 16 bytes per particle slot. */
+                                    The network runs inside the processing launch, on the
+                                    matrix cores, for the transitions each block holds. */
     int process_group;           /* streaming blocks whose transitions one block processes, default 4 */
 } qed_plan_config;
 

@@ -43,12 +43,6 @@ __device__ inline void draw_sample(const MlpDev &M, const TablesDev &T, int proc
     yo = (float)(nu / (double)M.out_s);
 }
 
-__device__ inline void normalize(const MlpDev &M, const float *xr, float xo[3])
-{
-    xo[0] = (xr[0] - M.in_m) / M.in_h;
-    xo[1] = xr[1] / M.rho_s;
-    xo[2] = xr[2] > 0.0f ? 1.0f : -1.0f;
-}
 
 // One training step's gradients.  xs/ys given (n samples, raw ln chi, rho, c and target nu):
 // the gradient of sum_i (y_i - nu_i/out_s)^2 over them; otherwise samples drawn from the tables.
@@ -73,7 +67,7 @@ __global__ void __launch_bounds__(kMlpBlock) k_mlp_grad(MlpDev M, TablesDev T, i
             if (xs) {
                 valid = id < n;
                 if (valid) {
-                    normalize(M, xs + 3 * id, xo);
+                    mlp_normalize(M, xs + 3 * id, xo);
                     yo = ys[id] / M.out_s;
                 }
             } else {
@@ -160,35 +154,12 @@ __global__ void __launch_bounds__(kMlpBlock) k_mlp_eval(MlpDev M, const float *x
         const int64_t id = tile * 16 + (l & 15);
         if (l < 16) {
             float xo[3] = {0.0f, 0.0f, 1.0f};
-            if (id < n) normalize(M, xs + 3 * id, xo);
+            if (id < n) mlp_normalize(M, xs + 3 * id, xo);
             W.x[l][0] = xo[0]; W.x[l][1] = xo[1]; W.x[l][2] = xo[2];
         }
         __syncthreads();
         const float y = mlp_forward(M, W);
         if (l < 16 && id < n) nu[id] = M.out_s * y;
-        __syncthreads();
-    }
-}
-
-// nu for the samples with global ranks [gpre[b_lo], gpre[b_hi]) (bounds read on the device)
-__global__ void __launch_bounds__(kMlpBlock) k_mlp_eval_ranks(MlpDev M, const float *xs, const uint32_t *gpre, int b_lo,
-                                                              int b_hi, float *nu)
-{
-    __shared__ MlpWave Wv[kMlpBlock / 64];
-    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
-    MlpWave &W = Wv[w];
-    const int64_t lo = gpre[b_lo], hi = gpre[b_hi];
-    const int64_t ntiles = cdiv(hi - lo, 16);
-    for (int64_t t0 = (int64_t)blockIdx.x * (kMlpBlock / 64); t0 < ntiles; t0 += (int64_t)gridDim.x * (kMlpBlock / 64)) {
-        const int64_t id = lo + (t0 + w) * 16 + (l & 15);
-        if (l < 16) {
-            float xo[3] = {0.0f, 0.0f, 1.0f};
-            if (id < hi) normalize(M, xs + 3 * id, xo);
-            W.x[l][0] = xo[0]; W.x[l][1] = xo[1]; W.x[l][2] = xo[2];
-        }
-        __syncthreads();
-        const float y = mlp_forward(M, W);
-        if (l < 16 && id < hi) nu[id] = M.out_s * y;
         __syncthreads();
     }
 }
@@ -239,11 +210,6 @@ int qs_surrogate_process(const qed_surrogate_s *s) { return s->proc; }
 const qed_tables_s *qs_surrogate_tables(const qed_surrogate_s *s) { return s->T; }
 
 // the learned nu of the transitions with global ranks [gpre[b_lo], gpre[b_hi]) of a plan step
-void qs_surrogate_eval_ranks(const qed_surrogate_s *s, const float *xs, const uint32_t *gpre, int b_lo, int b_hi,
-                             float *nu, hipStream_t st)
-{
-    QS_LAUNCH(K_SURROGATE, k_mlp_eval_ranks, dim3(1024), dim3(kMlpBlock), 0, st, mlp_dev(s), xs, gpre, b_lo, b_hi, nu);
-}
 
 extern "C" int64_t qed_surrogate_n_params(void) { return kNP; }
 

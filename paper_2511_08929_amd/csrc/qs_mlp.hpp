@@ -55,6 +55,25 @@ struct MlpWave {
     float x[16][3];              // normalized inputs u, v, c
 };
 
+// What the forward pass alone needs of a wave's LDS: one pre-activation buffer, reused by every
+// layer (a wave reads a layer's buffer into registers before it writes the next layer's).
+struct MlpFwdWave {
+    float z[1][16][mlp::kH];
+    float x[16][3];
+};
+
+// pre-activations of hidden layer k (0..3)
+__device__ __forceinline__ float (*zbuf(MlpWave &W, int k))[mlp::kH] { return W.z[k]; }
+__device__ __forceinline__ float (*zbuf(MlpFwdWave &W, int))[mlp::kH] { return W.z[0]; }
+
+// network inputs from the raw ones (ln chi, rho, channel sign)
+__device__ __forceinline__ void mlp_normalize(const MlpDev &M, const float *xr, float xo[3])
+{
+    xo[0] = (xr[0] - M.in_m) / M.in_h;
+    xo[1] = xr[1] / M.rho_s;
+    xo[2] = xr[2] > 0.0f ? 1.0f : -1.0f;
+}
+
 __device__ __forceinline__ float silu_f(float z) { return z * rcp_r(1.0f + exp_r(-z)); }
 __device__ __forceinline__ float dsilu_f(float z)
 {
@@ -62,8 +81,9 @@ __device__ __forceinline__ float dsilu_f(float z)
     return s * (1.0f + z * (1.0f - s));
 }
 
-// Forward pass of the 16 rows in W.x; returns y of row l%16 in every lane.  Leaves W.z filled.
-__device__ inline float mlp_forward(const MlpDev &M, MlpWave &W)
+// Forward pass of the 16 rows in W.x; returns y of row l%16 in every lane.  With an MlpWave it
+// leaves the pre-activations of every layer in W.z (for the backward pass).
+template <class WV> __device__ inline float mlp_forward(const MlpDev &M, WV &W)
 {
     using namespace mlp;
     const int l = threadIdx.x & 63, r = l & 15, q = l >> 4;
@@ -77,7 +97,7 @@ __device__ inline float mlp_forward(const MlpDev &M, MlpWave &W)
             const int k = kb * 16 + 4 * q + j;
             const float z = bf2f(wt[kB1 + k]) + bf2f(wt[kW1 + k]) * x0 + bf2f(wt[kW1 + kH + k]) * x1 +
                             bf2f(wt[kW1 + 2 * kH + k]) * x2;
-            W.z[0][r][k] = z;
+            zbuf(W, 0)[r][k] = z;
             a[kb][j] = (short)f2bf(silu_f(z));
         }
     }
@@ -91,19 +111,19 @@ __device__ inline float mlp_forward(const MlpDev &M, MlpWave &W)
                 acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[kb], M.img[(L - 2) * 1024 + (kb * 4 + nb) * 64 + l], acc, 0,
                                                                 0, 0);
 #pragma unroll
-            for (int j = 0; j < 4; ++j) W.z[L - 1][4 * q + j][nb * 16 + r] = acc[j];
+            for (int j = 0; j < 4; ++j) zbuf(W, L - 1)[4 * q + j][nb * 16 + r] = acc[j];
         }
         __syncthreads();
 #pragma unroll
         for (int kb = 0; kb < 4; ++kb)
 #pragma unroll
-            for (int j = 0; j < 4; ++j) a[kb][j] = (short)f2bf(silu_f(W.z[L - 1][r][kb * 16 + 4 * q + j]));
+            for (int j = 0; j < 4; ++j) a[kb][j] = (short)f2bf(silu_f(zbuf(W, L - 1)[r][kb * 16 + 4 * q + j]));
     }
     float s = 0.0f;
 #pragma unroll
     for (int j = 0; j < 16; ++j) {
         const int k = 16 * q + j;
-        s += bf2f(wt[kW5 + k]) * silu_f(W.z[3][r][k]);
+        s += bf2f(wt[kW5 + k]) * silu_f(zbuf(W, 3)[r][k]);
     }
     s += __shfl_xor(s, 16);
     s += __shfl_xor(s, 32);
@@ -216,5 +236,3 @@ __device__ inline void mlp_backward(const MlpDev &M, MlpWave &W, float dy, float
 qs::MlpDev qs_surrogate_view(const qed_surrogate_s *s);
 int qs_surrogate_process(const qed_surrogate_s *s);
 const qed_tables_s *qs_surrogate_tables(const qed_surrogate_s *s);
-void qs_surrogate_eval_ranks(const qed_surrogate_s *s, const float *xs, const uint32_t *gpre, int b_lo, int b_hi,
-                             float *nu, hipStream_t st);

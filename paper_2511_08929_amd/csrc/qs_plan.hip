@@ -15,8 +15,8 @@
 //            an ordered list in LDS and processes its transitions, writing photons (or pairs)
 //            at the instance's base + the rank; the first block of an instance stores the new
 //            counts and clock, and every 16th block of a set adds event counts to the counters.
-// With a learned inverse CDF a bookkeeping launch (book) scans the transition counts into
-// global ranks first, and the processing runs as two passes around the network.
+// With a learned inverse CDF the processing launch also runs the network on the transitions of
+// each block (inputs and outputs stay in LDS).
 // No block waits for another and no fence orders blocks: every hand-over is a launch boundary
 // on the stream.  (On this chip the L2 is per XCD, so a device-scope release or acquire fence
 // inside a kernel writes back or invalidates a whole L2.)
@@ -47,7 +47,7 @@ struct SegDev {
     int64_t mask_off, nchunks; // decision plane at mask + mask_off, branch plane nchunks words later
 };
 
-// written by the bookkeeping block, read by the process pass
+// a processing block's view of its set's bookkeeping
 struct SegBook {
     int64_t n_main;            // particles the main pass covered
     int64_t base, base2;       // append base (photons; pairs: electrons, positrons)
@@ -73,184 +73,13 @@ struct PlanDev {
     uint64_t *mask;
     uint32_t *bcnt;            // [nblk]
     uint32_t *bctr;            // [nblk][kNCtr] event counts of each main block
-    uint32_t *gpre;            // [nblk + 1] exclusive prefix of bcnt in grid order
-    SegBook *sbook;            // [nseg]
-    int64_t *clock_used;       // [ninst] step clock of the last main pass
-    float *sx, *snu;           // learned inverse CDF: inputs [3] and nu per global transition rank
     const int *bseg, *binst;   // [nblk] segment and instance of each streaming block
     const int4 *pbd;           // [npb] processing block: segment, streaming blocks [mb0, mb1), instance
     const InstSeg *iseg;       // [ninst]
     Snap *snap;                // [ninst]
+    MlpDev mlp[2];             // learned inverse CDF of NLC and NBW, used where mlp_on is set
+    int mlp_on[2];
 };
-
-__device__ __forceinline__ int64_t seg_total(const PlanDev &P, int sj)
-{
-    // read back what other threads of this block just stored, past the vector L1
-    if (sj < 0) return 0;
-    const uint32_t hi = __hip_atomic_load(P.gpre + P.seg[sj].b0 + P.seg[sj].nb, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    const uint32_t lo = __hip_atomic_load(P.gpre + P.seg[sj].b0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    return (int64_t)hi - (int64_t)lo;
-}
-
-constexpr int kCtrGroup = 64;   // main blocks whose event counts one bookkeeping wave adds up
-constexpr int kScanChunk = 8192; // block counts the scan holds in LDS at a time
-constexpr int kSegLds = 1024;    // segments whose boundary prefixes the scan keeps in LDS
-
-// What one instance's bookkeeping reads besides the segment totals.  Loaded before the scan:
-// none of it depends on the scan, and nothing else writes it during the launch.
-struct BookIn {
-    int64_t ne, np, gb, ng, clock;
-};
-
-template <class R> __device__ __forceinline__ BookIn book_load(const InstDev<R> &I)
-{
-    BookIn b;
-    b.ne = *I.E.count;
-    b.np = I.sp >= 0 ? *I.P.count : 0;
-    b.gb = I.G.count != nullptr ? *I.G.count : 0;
-    b.ng = I.sg >= 0 ? *I.G.count_prev : 0;
-    b.clock = I.S.clock ? *I.S.clock : 0;
-    return b;
-}
-
-// Block 0: scan of the transition counts of all main blocks, then per-instance bookkeeping (one
-// thread per instance).  Block 1 + w / 4, wave w % 4: event counts of main blocks
-// [64 w, 64 w + 64) added to their instances' counters, one atomic per counter and run of
-// blocks of one instance.
-template <class R>
-__global__ void __launch_bounds__(kBlock) k_plan_book(const InstDev<R> *inst, PlanDev P)
-{
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    if (blockIdx.x > 0) {
-        const int b0 = ((blockIdx.x - 1) * (kBlock / 64) + wid) * kCtrGroup;
-        if (b0 >= P.nblk) return;                                // wave-uniform
-        const int gsz = P.nblk - b0 < kCtrGroup ? P.nblk - b0 : kCtrGroup;
-        const bool on = lane < gsz;
-        const int b = b0 + lane;
-        const int me = on ? P.binst[b] : -1;
-        uint32_t v[kNCtr];
-#pragma unroll
-        for (int c = 0; c < kNCtr; ++c) v[c] = on ? P.bctr[(int64_t)b * kNCtr + c] : 0u;
-        // runs of lanes of one instance (a segment's blocks are contiguous): a segmented sum
-        // within each run, added by the run's last lane
-        const int prev = __shfl_up(me, 1);
-        const uint64_t heads = __ballot(on && (lane == 0 || prev != me));
-        const int rs = 63 - __clzll((long long)(heads & ((2ull << lane) - 1ull)));   // first lane of my run
-        const bool last = on && (lane == gsz - 1 || (lane < 63 && ((heads >> (lane + 1)) & 1ull)));
-#pragma unroll
-        for (int c = 0; c < kNCtr; ++c) {
-            unsigned long long acc = v[c];
-            for (int o = 1; o < 64; o <<= 1) {
-                const unsigned long long y = __shfl_up(acc, o);
-                if (lane - o >= rs) acc += y;
-            }
-            if (last && acc) atomicAdd(inst[me].ctr + c, acc);
-        }
-        return;
-    }
-    __shared__ uint32_t sc[kScanChunk];
-    __shared__ uint32_t wsum[kBlock / 64];
-    __shared__ uint32_t sbeg[kSegLds], send[kSegLds];
-    __shared__ int sb0[kSegLds], sb1[kSegLds];
-    const bool seg_lds = P.nseg <= kSegLds;
-    if (seg_lds)
-        for (int sj = threadIdx.x; sj < P.nseg; sj += kBlock) {
-            sb0[sj] = P.seg[sj].b0;
-            sb1[sj] = P.seg[sj].b0 + P.seg[sj].nb;
-        }
-    // the first instance of this thread: its inputs load while the scan runs
-    BookIn in0 = {0, 0, 0, 0, 0};
-    if ((int)threadIdx.x < P.ninst) in0 = book_load<R>(inst[threadIdx.x]);
-    // the block counts pass through LDS in chunks: coalesced loads, all in flight at once; thread t
-    // then sums the contiguous run [t m, t m + m) of the chunk, one block-wide scan of the 256 run
-    // totals gives the run's offset, the run's prefixes overwrite the counts in LDS, segment
-    // boundaries inside the chunk copy theirs, and coalesced stores write them out
-    uint32_t carry = 0;                        // prefix before the chunk
-    for (int c0 = 0; c0 < P.nblk; c0 += kScanChunk) {
-        const int n = P.nblk - c0 < kScanChunk ? P.nblk - c0 : kScanChunk;
-#pragma unroll 8
-        for (int j = threadIdx.x; j < n; j += kBlock) sc[j] = P.bcnt[c0 + j];
-        __syncthreads();
-        const int m = (int)cdiv(n, kBlock);
-        const int lo = (int)threadIdx.x * m < n ? (int)threadIdx.x * m : n, hi = lo + m < n ? lo + m : n;
-        uint32_t run = 0;
-        for (int b = lo; b < hi; ++b) run += sc[b];
-        uint32_t incl = run;
-        for (int o = 1; o < 64; o <<= 1) {
-            const uint32_t y = __shfl_up(incl, o);
-            if (lane >= o) incl += y;
-        }
-        if (lane == 63) wsum[wid] = incl;
-        __syncthreads();
-        uint32_t off = carry + incl - run;
-        for (int w = 0; w < wid; ++w) off += wsum[w];
-        for (int w = 0; w < kBlock / 64; ++w) carry += wsum[w];
-        for (int b = lo; b < hi; ++b) {
-            const uint32_t v = sc[b];
-            sc[b] = off;
-            off += v;
-        }
-        __syncthreads();
-#pragma unroll 8
-        for (int j = threadIdx.x; j < n; j += kBlock) P.gpre[c0 + j] = sc[j];
-        if (seg_lds)
-            for (int sj = threadIdx.x; sj < P.nseg; sj += kBlock) {
-                const int sb = sb0[sj], se = sb1[sj];
-                if (sb >= c0 && sb < c0 + n) sbeg[sj] = sc[sb - c0];
-                if (se >= c0 && se < c0 + n) send[sj] = sc[se - c0];
-            }
-        __syncthreads();                       // sc and wsum are reused by the next chunk
-    }
-    if (seg_lds)
-        for (int sj = threadIdx.x; sj < P.nseg; sj += kBlock)
-            if (sb1[sj] == P.nblk) send[sj] = carry;
-    if (threadIdx.x == 0) P.gpre[P.nblk] = carry;
-    __syncthreads();
-    auto total = [&](int sj) -> int64_t {
-        if (sj < 0) return 0;
-        if (seg_lds) return (int64_t)send[sj] - (int64_t)sbeg[sj];
-        return seg_total(P, sj);
-    };
-    for (int i = threadIdx.x; i < P.ninst; i += blockDim.x) {
-        const InstDev<R> &I = inst[i];
-        const BookIn in = i < kBlock ? in0 : book_load<R>(I);
-        unsigned long long *ctr = I.ctr;
-        const bool has_g = I.G.count != nullptr, pair = I.sg >= 0;
-        const int64_t te = total(I.se), tp = total(I.sp), tg = total(I.sg);
-        int64_t *clk = const_cast<int64_t *>(I.S.clock);
-        int64_t over = 0;
-        // emission: photons of electrons, then of positrons
-        if (has_g) {
-            const int64_t room = I.G.cap - in.gb > 0 ? I.G.cap - in.gb : 0;
-            const int64_t nfe = te < room ? te : room;
-            const int64_t nfp = tp < room - nfe ? tp : room - nfe;
-            const int64_t gnew = in.gb + nfe + nfp;
-            *I.G.count = gnew;
-            P.sbook[I.se] = SegBook{in.ne, in.gb, 0, te, nfe};
-            if (I.sp >= 0) P.sbook[I.sp] = SegBook{in.np, in.gb + nfe, 0, tp, nfp};
-            over += (te - nfe) + (tp - nfp);
-            if (te + tp) atomicAdd(ctr + C_EMIT, (unsigned long long)(te + tp));
-            // photons born in this step wait for the next one
-            if (pair) *I.G.count_prev = gnew;
-        } else {
-            P.sbook[I.se] = SegBook{in.ne, 0, 0, te, 0};
-        }
-        // pairs of the photons stepped in this pass, appended after the leptons stepped in it
-        if (pair) {
-            int64_t room = I.E.cap - in.ne < I.P.cap - in.np ? I.E.cap - in.ne : I.P.cap - in.np;
-            room = room > 0 ? room : 0;
-            const int64_t nfg = tg < room ? tg : room;
-            *I.E.count = in.ne + nfg;
-            *I.P.count = in.np + nfg;
-            P.sbook[I.sg] = SegBook{in.ng, in.ne, in.np, tg, nfg};
-            over += tg - nfg;
-            if (tg) atomicAdd(ctr + C_PAIR, (unsigned long long)tg);
-        }
-        if (over) atomicAdd(ctr + C_OVER, (unsigned long long)over);
-        P.clock_used[i] = in.clock;
-        if (clk) *clk = in.clock + 1;
-    }
-}
 
 // The streaming pass runs as two launches with their own register allocation: PHO = 0 over the
 // lepton segments (blocks [0, nblk_lep)), PHO = 1 over the photon segments (the rest).
@@ -327,114 +156,118 @@ __device__ __forceinline__ void block_totals4(unsigned long long (&a)[4], unsign
     }
 }
 
+// LDS of the learned inverse CDF in the processing pass: per wave the forward pass's rows, per
+// thread one transition's raw inputs and nu
+template <bool SUR> struct SurLds {
+    MlpFwdWave wv[kBlock / 64];
+    float xin[kBlock][3];
+    float nu[kBlock];
+};
+template <> struct SurLds<false> {
+    int unused;
+};
+
 // One launch over the processing blocks of every set (lepton sets first, then photons); the
-// channel follows the block's set.  mode 0: tables; 1: write the inverse-CDF inputs of every
-// transition (learned inverse CDF); 2: finish the transitions with the learned nu.
-// FUSED (tables only): no bookkeeping launch before this one.  Each block sums the transition
-// counts it needs (its rank offset inside its set, the totals of its instance's sets) and
-// derives its append base from the counts at the start of the step; the first block of an
-// instance's electron set stores the new counts, the counters and the next clock (no block of
-// this launch reads them), and every kAggGroups-th block of a set adds the event counts of its
+// channel follows the block's set.  No bookkeeping launch precedes it: each block sums the
+// transition counts it needs (its rank offset inside its set, the totals of its instance's
+// sets) and derives its append base from the counts at the start of the step; the first block
+// of an instance's electron set stores the new counts, the counters and the next clock (no block
+// of this launch reads them), and every kAggGroups-th block of a set adds the event counts of its
 // streaming blocks to the instance's counters.
-template <class R, bool GRID, bool FUSED>
-__global__ void __launch_bounds__(kBlock) k_plan_process(const InstDev<R> *inst, PlanDev P, TablesDev T, int b_first,
-                                                         int mode)
+// SUR: a process with a learned inverse CDF (P.mlp_on) handles its transitions in rounds of one
+// per thread: each thread writes its transition's network inputs to LDS, the waves run the
+// network on the round's rows (16 per forward pass), and each thread finishes its transition
+// with its nu.
+template <class R, bool GRID, bool SUR>
+__global__ void __launch_bounds__(kBlock) k_plan_process(const InstDev<R> *inst, PlanDev P, TablesDev T, int b_first)
 {
     extern __shared__ unsigned char smem_raw[];
     R *lds = reinterpret_cast<R *>(smem_raw);
     __shared__ uint16_t list[kExpandWords * 64];
     __shared__ uint32_t nlist, wtot[kBlock / 64];
+    __shared__ unsigned long long red[4][kBlock / 64];
+    __shared__ SurLds<SUR> sl;
     // this block covers the streaming blocks [mb0, mb1) of one segment: a contiguous slot range
     const int4 pd = P.pbd[b_first + blockIdx.x];
     const int sj = pd.x, mb0 = pd.y, mb1 = pd.z;
     const SegDev sg = P.seg[sj];
     const InstDev<R> *Ip = inst + pd.w;
-    SegBook bk;
-    int64_t rank0, clock;
-    if (FUSED) {
-        __shared__ unsigned long long red[4][kBlock / 64];
-        // transitions of this block's streaming blocks: one load per lane, a wave sum
-        uint32_t mine = 0;
-        for (int b = mb0 + (int)(threadIdx.x & 63); b < mb1; b += 64) mine += P.bcnt[b];
-        for (int o = 32; o > 0; o >>= 1) mine += __shfl_xor(mine, o);
-        const bool lead = sg.kind == 0 && mb0 == sg.b0;
-        const bool agg = ((mb0 - sg.b0) / P.group) % kAggGroups == 0;
-        if (mine == 0 && !lead && !agg) return;           // block-uniform
-        const InstSeg is = P.iseg[pd.w];
-        const Snap sn = P.snap[pd.w];
-        if (agg && threadIdx.x < 64) {
-            const int lane = threadIdx.x;
-            const int bend = mb0 + kAggGroups * P.group < sg.b0 + sg.nb ? mb0 + kAggGroups * P.group : sg.b0 + sg.nb;
-            unsigned long long v[kNCtr] = {};
-            for (int b = mb0 + lane; b < bend; b += 64)
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    // transitions of this block's streaming blocks: one load per lane, a wave sum
+    uint32_t mine = 0;
+    for (int b = mb0 + lane; b < mb1; b += 64) mine += P.bcnt[b];
+    for (int o = 32; o > 0; o >>= 1) mine += __shfl_xor(mine, o);
+    const bool lead = sg.kind == 0 && mb0 == sg.b0;
+    const bool agg = ((mb0 - sg.b0) / P.group) % kAggGroups == 0;
+    if (mine == 0 && !lead && !agg) return;           // block-uniform
+    const InstSeg is = P.iseg[pd.w];
+    const Snap sn = P.snap[pd.w];
+    if (agg && threadIdx.x < 64) {
+        const int bend = mb0 + kAggGroups * P.group < sg.b0 + sg.nb ? mb0 + kAggGroups * P.group : sg.b0 + sg.nb;
+        unsigned long long v[kNCtr] = {};
+        for (int b = mb0 + lane; b < bend; b += 64)
 #pragma unroll
-                for (int c = 0; c < kNCtr; ++c) v[c] += P.bctr[(int64_t)b * kNCtr + c];
+            for (int c = 0; c < kNCtr; ++c) v[c] += P.bctr[(int64_t)b * kNCtr + c];
 #pragma unroll
-            for (int c = 0; c < kNCtr; ++c) {
-                unsigned long long t = v[c];
-                for (int o = 32; o > 0; o >>= 1) t += __shfl_xor(t, o);
-                if (lane == 0 && t) atomicAdd(Ip->ctr + c, t);
-            }
+        for (int c = 0; c < kNCtr; ++c) {
+            unsigned long long t = v[c];
+            for (int o = 32; o > 0; o >>= 1) t += __shfl_xor(t, o);
+            if (lane == 0 && t) atomicAdd(Ip->ctr + c, t);
         }
-        // transition counts: rank offset inside the set, totals of the sets this block needs
-        const bool ne_ = sg.kind != 2 || lead, np_ = sg.kind == 1 || lead, ng_ = sg.kind == 2 || lead;
-        // every load first (independent), then the sums
-        unsigned long long a[4] = {0, 0, 0, 0};
-        auto range_sum = [&](int lo, int hi) -> unsigned long long {
-            unsigned long long t = 0;
-#pragma unroll 4
-            for (int b = lo + (int)threadIdx.x; b < hi; b += kBlock) t += P.bcnt[b];
-            return t;
-        };
-        a[0] = range_sum(sg.b0, mb0);
-        if (ne_) a[1] = range_sum(is.e0, is.e1);
-        if (np_) a[2] = range_sum(is.p0, is.p1);
-        if (ng_) a[3] = range_sum(is.g0, is.g1);
-        block_totals4(a, red);
-        rank0 = (int64_t)a[0];
-        const int64_t te = (int64_t)a[1], tp = (int64_t)a[2], tg = (int64_t)a[3];
-        // the bookkeeping of the separate launch, from the counts at the start of the step
-        const bool has_g = Ip->G.count != nullptr, pair = Ip->sg >= 0;
-        const int64_t room_g = has_g && Ip->G.cap - sn.gb > 0 ? Ip->G.cap - sn.gb : 0;
-        const int64_t nfe = te < room_g ? te : room_g;
-        const int64_t nfp = tp < room_g - nfe ? tp : room_g - nfe;
-        int64_t room_p = Ip->E.cap - sn.ne < Ip->P.cap - sn.np ? Ip->E.cap - sn.ne : Ip->P.cap - sn.np;
-        room_p = room_p > 0 ? room_p : 0;
-        const int64_t nfg = tg < room_p ? tg : room_p;
-        if (sg.kind == 0) bk = SegBook{sn.ne, sn.gb, 0, te, nfe};
-        else if (sg.kind == 1) bk = SegBook{sn.np, sn.gb + nfe, 0, tp, nfp};
-        else bk = SegBook{sn.ng, sn.ne, sn.np, tg, nfg};
-        if (lead && threadIdx.x == 0) {
-            unsigned long long *ctr = Ip->ctr;
-            int64_t over = 0;
-            if (has_g) {
-                const int64_t gnew = sn.gb + nfe + nfp;
-                *Ip->G.count = gnew;
-                over += (te - nfe) + (tp - nfp);
-                if (te + tp) atomicAdd(ctr + C_EMIT, (unsigned long long)(te + tp));
-                // photons born in this step wait for the next one
-                if (pair) *Ip->G.count_prev = gnew;
-            }
-            if (pair) {
-                *Ip->E.count = sn.ne + nfg;
-                *Ip->P.count = sn.np + nfg;
-                over += tg - nfg;
-                if (tg) atomicAdd(ctr + C_PAIR, (unsigned long long)tg);
-            }
-            if (over) atomicAdd(ctr + C_OVER, (unsigned long long)over);
-            if (Ip->S.clock) *const_cast<int64_t *>(Ip->S.clock) = sn.clock + 1;
-        }
-        if (mine == 0) return;                             // block-uniform
-        clock = sn.clock;
-    } else {
-        if (P.gpre[mb1] == P.gpre[mb0]) return;           // no transition in this range
-        bk = P.sbook[sj];
-        rank0 = (int64_t)P.gpre[mb0] - (int64_t)P.gpre[sg.b0];
-        clock = P.clock_used[pd.w];
     }
+    // transition counts: rank offset inside the set, totals of the sets this block needs;
+    // every load first (independent), then the sums
+    const bool ne_ = sg.kind != 2 || lead, np_ = sg.kind == 1 || lead, ng_ = sg.kind == 2 || lead;
+    unsigned long long a[4] = {0, 0, 0, 0};
+    auto range_sum = [&](int lo, int hi) -> unsigned long long {
+        unsigned long long t = 0;
+#pragma unroll 4
+        for (int b = lo + (int)threadIdx.x; b < hi; b += kBlock) t += P.bcnt[b];
+        return t;
+    };
+    a[0] = range_sum(sg.b0, mb0);
+    if (ne_) a[1] = range_sum(is.e0, is.e1);
+    if (np_) a[2] = range_sum(is.p0, is.p1);
+    if (ng_) a[3] = range_sum(is.g0, is.g1);
+    block_totals4(a, red);
+    int64_t rank0 = (int64_t)a[0];
+    const int64_t te = (int64_t)a[1], tp = (int64_t)a[2], tg = (int64_t)a[3];
+    // append bases and capacity clamps from the counts at the start of the step
+    const bool has_g = Ip->G.count != nullptr, pair = Ip->sg >= 0;
+    const int64_t room_g = has_g && Ip->G.cap - sn.gb > 0 ? Ip->G.cap - sn.gb : 0;
+    const int64_t nfe = te < room_g ? te : room_g;
+    const int64_t nfp = tp < room_g - nfe ? tp : room_g - nfe;
+    int64_t room_p = Ip->E.cap - sn.ne < Ip->P.cap - sn.np ? Ip->E.cap - sn.ne : Ip->P.cap - sn.np;
+    room_p = room_p > 0 ? room_p : 0;
+    const int64_t nfg = tg < room_p ? tg : room_p;
+    SegBook bk;
+    if (sg.kind == 0) bk = SegBook{sn.ne, sn.gb, 0, te, nfe};
+    else if (sg.kind == 1) bk = SegBook{sn.np, sn.gb + nfe, 0, tp, nfp};
+    else bk = SegBook{sn.ng, sn.ne, sn.np, tg, nfg};
+    if (lead && threadIdx.x == 0) {
+        unsigned long long *ctr = Ip->ctr;
+        int64_t over = 0;
+        if (has_g) {
+            const int64_t gnew = sn.gb + nfe + nfp;
+            *Ip->G.count = gnew;
+            over += (te - nfe) + (tp - nfp);
+            if (te + tp) atomicAdd(ctr + C_EMIT, (unsigned long long)(te + tp));
+            // photons born in this step wait for the next one
+            if (pair) *Ip->G.count_prev = gnew;
+        }
+        if (pair) {
+            *Ip->E.count = sn.ne + nfg;
+            *Ip->P.count = sn.np + nfg;
+            over += tg - nfg;
+            if (tg) atomicAdd(ctr + C_PAIR, (unsigned long long)tg);
+        }
+        if (over) atomicAdd(ctr + C_OVER, (unsigned long long)over);
+        if (Ip->S.clock) *const_cast<int64_t *>(Ip->S.clock) = sn.clock + 1;
+    }
+    if (mine == 0) return;                             // block-uniform
     StepDev S = Ip->S;
-    S.step += clock;
-    S.t += (double)clock * S.dt;
+    S.step += sn.clock;
+    S.t += (double)sn.clock * S.dt;
     const FieldDev F = Ip->F;
     const int PHO = sg.kind == 2;
     // single precision: the Bessel quadrature nodes (6 KB) join the rate rows in LDS, so the
@@ -452,7 +285,7 @@ __global__ void __launch_bounds__(kBlock) k_plan_process(const InstDev<R> *inst,
     const int64_t B = block_len(n, sg.nb);
     const int64_t start = (int64_t)(mb0 - sg.b0) * B;
     const int64_t end = (int64_t)(mb1 - sg.b0) * B < n ? (int64_t)(mb1 - sg.b0) * B : n;
-    const int lane = threadIdx.x & 63;
+    const bool net = SUR && P.mlp_on[PHO];
     unsigned c_ret = 0;
     for (int64_t c0 = start >> 6; c0 < cdiv(end, 64); c0 += kExpandWords) {
         const int64_t c1 = c0 + kExpandWords < cdiv(end, 64) ? c0 + kExpandWords : cdiv(end, 64);
@@ -465,10 +298,10 @@ __global__ void __launch_bounds__(kBlock) k_plan_process(const InstDev<R> *inst,
             const uint32_t y = __shfl_up(incl, o);
             if (lane >= o) incl += y;
         }
-        if (lane == 63) wtot[threadIdx.x >> 6] = incl;
+        if (lane == 63) wtot[wid] = incl;
         __syncthreads();
         uint32_t pos = incl - pc;
-        for (int w = 0; w < (int)(threadIdx.x >> 6); ++w) pos += wtot[w];
+        for (int w = 0; w < wid; ++w) pos += wtot[w];
         uint64_t bits = m;
         while (bits) {
             const int bit = __ffsll((long long)bits) - 1;
@@ -478,23 +311,47 @@ __global__ void __launch_bounds__(kBlock) k_plan_process(const InstDev<R> *inst,
         if (threadIdx.x == kBlock - 1) nlist = pos;
         __syncthreads();
         const uint32_t nl = nlist;
-        for (uint32_t j = threadIdx.x; j < nl; j += blockDim.x) {
+        // transition j of this round: emitter (photon into slot base + rank) or decaying photon
+        auto item = [&](uint32_t j, const float *nu_in, float *x_out) {
             const int64_t i = c0 * 64 + list[j];
             const int64_t r = rank0 + j;
             const bool br = (mask[sg.nchunks + (i >> 6)] >> (i & 63)) & 1ull;
-            const float *nu_in = nullptr;
-            float *x_out = nullptr;
-            if (!FUSED && mode != 0) {
-                const int64_t gr = (int64_t)P.gpre[sg.b0] + r;        // global transition rank
-                if (mode == 2) nu_in = P.snu + gr;
-                else x_out = P.sx + 3 * gr;
-            }
             if (!PHO)
                 emit_item<R, GRID>(sg.kind == 0 ? Ip->E : Ip->P, Ip->G, F, S, Tl, lds, i, br, r < bk.nfit ? bk.base + r : -1,
-                             c_ret, nu_in, x_out);
+                                   c_ret, nu_in, x_out);
             else
-                pair_item<R, GRID>(Ip->G, Ip->E, Ip->P, F, S, Tl, lds, i, br, r < bk.nfit ? bk.base + r : -1, bk.base2 + r, nu_in,
-                             x_out);
+                pair_item<R, GRID>(Ip->G, Ip->E, Ip->P, F, S, Tl, lds, i, br, r < bk.nfit ? bk.base + r : -1, bk.base2 + r,
+                                   nu_in, x_out);
+        };
+        if (net) {
+            if constexpr (SUR) {
+                const MlpDev &M = P.mlp[PHO];
+                for (uint32_t j0 = 0; j0 < nl; j0 += kBlock) {
+                    const uint32_t j = j0 + threadIdx.x;
+                    const int rows = nl - j0 < (uint32_t)kBlock ? (int)(nl - j0) : kBlock;
+                    if (j < nl) item(j, nullptr, sl.xin[threadIdx.x]);
+                    __syncthreads();
+                    // every wave runs the same number of forward passes (they synchronize the block)
+                    const int calls = (int)cdiv(cdiv(rows, 16), kBlock / 64);
+                    MlpFwdWave &W = sl.wv[wid];
+                    for (int k = 0; k < calls; ++k) {
+                        const int row = (k * (kBlock / 64) + wid) * 16 + (lane & 15);
+                        if (lane < 16) {
+                            float xo[3] = {0.0f, 0.0f, 1.0f};
+                            if (row < rows) mlp_normalize(M, sl.xin[row], xo);
+                            W.x[lane][0] = xo[0]; W.x[lane][1] = xo[1]; W.x[lane][2] = xo[2];
+                        }
+                        __syncthreads();
+                        const float y = mlp_forward(M, W);
+                        if (lane < 16 && row < rows) sl.nu[row] = M.out_s * y;
+                        __syncthreads();
+                    }
+                    if (j < nl) item(j, &sl.nu[threadIdx.x], nullptr);
+                    __syncthreads();
+                }
+            }
+        } else {
+            for (uint32_t j = threadIdx.x; j < nl; j += blockDim.x) item(j, nullptr, nullptr);
         }
         rank0 += nl;
         __syncthreads();
@@ -510,11 +367,8 @@ struct qed_plan_s {
     void *d_inst;
     SegDev *d_seg;
     uint64_t *d_mask;
-    uint32_t *d_bcnt, *d_gpre;
-    SegBook *d_sbook;
-    int64_t *d_clock_used;
+    uint32_t *d_bcnt;
     uint32_t *d_bctr;
-    float *d_sx, *d_snu;
     int *d_bseg, *d_binst;
     int4 *d_pbd;
     InstSeg *d_iseg;
@@ -548,12 +402,7 @@ void plan_free(qed_plan p)
     (void)hipFree(p->d_seg);
     (void)hipFree(p->d_mask);
     (void)hipFree(p->d_bcnt);
-    (void)hipFree(p->d_gpre);
-    (void)hipFree(p->d_sbook);
-    (void)hipFree(p->d_clock_used);
     (void)hipFree(p->d_bctr);
-    (void)hipFree(p->d_sx);
-    (void)hipFree(p->d_snu);
     (void)hipFree(p->d_bseg);
     (void)hipFree(p->d_binst);
     (void)hipFree(p->d_pbd);
@@ -628,9 +477,6 @@ qed_status plan_create(qed_tables T, int n, const qed_instance *in, int ppb, int
     if (e == hipSuccess) e = hipMalloc((void **)&p->d_seg, sizeof(SegDev) * seg.size());
     if (e == hipSuccess) e = hipMalloc((void **)&p->d_mask, sizeof(uint64_t) * mask_words);
     if (e == hipSuccess) e = hipMalloc((void **)&p->d_bcnt, sizeof(uint32_t) * nblk);
-    if (e == hipSuccess) e = hipMalloc((void **)&p->d_gpre, sizeof(uint32_t) * (nblk + 1));
-    if (e == hipSuccess) e = hipMalloc((void **)&p->d_sbook, sizeof(SegBook) * seg.size());
-    if (e == hipSuccess) e = hipMalloc((void **)&p->d_clock_used, sizeof(int64_t) * n);
     if (e == hipSuccess) e = hipMalloc((void **)&p->d_bctr, sizeof(uint32_t) * kNCtr * nblk);
     p->sur[0] = s_nlc;
     p->sur[1] = s_nbw;
@@ -639,13 +485,6 @@ qed_status plan_create(qed_tables T, int n, const qed_instance *in, int ppb, int
     for (int i = 0; i < n; ++i) {
         p->tau = p->tau || (in[i].params.flags & QED_OPTICAL_DEPTH);
         p->grid = p->grid || in[i].fields.kind == QED_FIELD_GRID2D;
-    }
-    if (s_nlc || s_nbw) {
-        // one record per possible transition: every slot of every set
-        int64_t slots = 0;
-        for (const SegDev &sg : seg) slots += sg.nchunks * 64;
-        if (e == hipSuccess) e = hipMalloc((void **)&p->d_sx, sizeof(float) * 3 * slots);
-        if (e == hipSuccess) e = hipMalloc((void **)&p->d_snu, sizeof(float) * slots);
     }
     if (e == hipSuccess) e = hipMemcpy(p->d_inst, inst.data(), sizeof(InstDev<R>) * n, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(p->d_seg, seg.data(), sizeof(SegDev) * seg.size(), hipMemcpyHostToDevice);
@@ -683,7 +522,6 @@ qed_status plan_create(qed_tables T, int n, const qed_instance *in, int ppb, int
     if (e == hipSuccess) e = hipMalloc((void **)&p->d_iseg, sizeof(InstSeg) * n);
     if (e == hipSuccess) e = hipMalloc((void **)&p->d_snap, sizeof(Snap) * n);
     if (e == hipSuccess) e = hipMemcpy(p->d_iseg, iseg.data(), sizeof(InstSeg) * n, hipMemcpyHostToDevice);
-    if (e == hipSuccess) e = hipMemset(p->d_gpre, 0, sizeof(uint32_t) * (nblk + 1));
     if (e == hipSuccess) e = hipDeviceSynchronize();
     if (e != hipSuccess) {
         plan_free(p);
@@ -703,17 +541,14 @@ template <class R> qed_status plan_step(qed_plan p, hipStream_t st)
     P.ninst = p->ninst;
     P.mask = p->d_mask;
     P.bcnt = p->d_bcnt;
-    P.gpre = p->d_gpre;
-    P.sbook = p->d_sbook;
-    P.clock_used = p->d_clock_used;
     P.bctr = p->d_bctr;
-    P.sx = p->d_sx;
-    P.snu = p->d_snu;
     P.bseg = p->d_bseg;
     P.binst = p->d_binst;
     P.pbd = p->d_pbd;
     P.iseg = p->d_iseg;
     P.snap = p->d_snap;
+    memset(P.mlp, 0, sizeof(P.mlp));
+    P.mlp_on[0] = P.mlp_on[1] = 0;
     const InstDev<R> *inst = (const InstDev<R> *)p->d_inst;
     if (p->nblk_lep > 0) {
         if (p->tau)
@@ -734,33 +569,24 @@ template <class R> qed_status plan_step(qed_plan p, hipStream_t st)
             QS_LAUNCH(K_PLAN_PHOTON, (k_plan_main<R, 1, false, false>), dim3(p->nblk - p->nblk_lep), dim3(kBlock), p->lds, st,
                       inst, P, p->T->dev, p->nblk_lep);
     }
-    const bool sl = p->sur[0] != nullptr, sp = p->sur[1] != nullptr;
-    const int np_all = p->npb, np_l = p->npb_lep;
-    if (!(sl || sp)) {
-        // tables: the processing launch does the bookkeeping itself
-        auto proc = p->grid ? k_plan_process<R, true, true> : k_plan_process<R, false, true>;
-        QS_LAUNCH(K_PLAN_PROCESS, proc, dim3(np_all), dim3(kBlock), p->lds, st, inst, P, p->T->dev, 0, 0);
-        return qs_launch_status("qed_plan_step");
+    // processing, with the bookkeeping; a process with a learned inverse CDF evaluates it in the
+    // same launch (single precision only)
+    const bool sl = p->sur[0] != nullptr, sb = p->sur[1] != nullptr;
+    if (p->npb > 0) {
+        if constexpr (sizeof(R) == 4) {
+            if (sl || sb) {
+                if (sl) P.mlp[0] = qs_surrogate_view(p->sur[0]);
+                if (sb) P.mlp[1] = qs_surrogate_view(p->sur[1]);
+                P.mlp_on[0] = sl;
+                P.mlp_on[1] = sb;
+                auto proc = p->grid ? k_plan_process<R, true, true> : k_plan_process<R, false, true>;
+                QS_LAUNCH(K_PLAN_PROCESS, proc, dim3(p->npb), dim3(kBlock), p->lds, st, inst, P, p->T->dev, 0);
+                return qs_launch_status("qed_plan_step");
+            }
+        }
+        auto proc = p->grid ? k_plan_process<R, true, false> : k_plan_process<R, false, false>;
+        QS_LAUNCH(K_PLAN_PROCESS, proc, dim3(p->npb), dim3(kBlock), p->lds, st, inst, P, p->T->dev, 0);
     }
-    // learned inverse CDF: the bookkeeping launch scans the transition counts into global ranks;
-    // a first processing pass writes the network's inputs (tables for a process without a
-    // network), the network runs on each process's dense rank range, and a second pass finishes
-    // the transitions with its nu
-    QS_LAUNCH(K_BOOK, k_plan_book<R>, dim3(1 + (int)cdiv(cdiv(p->nblk, kCtrGroup), kBlock / 64)), dim3(kBlock), 0, st,
-              inst, P);
-    const bool has_l = p->nblk_lep > 0, has_g = p->nblk > p->nblk_lep;
-    auto proc = p->grid ? k_plan_process<R, true, false> : k_plan_process<R, false, false>;
-    if (np_l > 0)
-        QS_LAUNCH(K_PLAN_PROCESS, proc, dim3(np_l), dim3(kBlock), p->lds, st, inst, P, p->T->dev, 0, sl ? 1 : 0);
-    if (np_all > np_l)
-        QS_LAUNCH(K_PLAN_PROCESS, proc, dim3(np_all - np_l), dim3(kBlock), p->lds, st, inst, P, p->T->dev, np_l,
-                  sp ? 1 : 0);
-    if (has_l && sl) qs_surrogate_eval_ranks(p->sur[0], P.sx, P.gpre, 0, p->nblk_lep, P.snu, st);
-    if (has_g && sp) qs_surrogate_eval_ranks(p->sur[1], P.sx, P.gpre, p->nblk_lep, p->nblk, P.snu, st);
-    if (np_l > 0 && sl)
-        QS_LAUNCH(K_PLAN_PROCESS, proc, dim3(np_l), dim3(kBlock), p->lds, st, inst, P, p->T->dev, 0, 2);
-    if (np_all > np_l && sp)
-        QS_LAUNCH(K_PLAN_PROCESS, proc, dim3(np_all - np_l), dim3(kBlock), p->lds, st, inst, P, p->T->dev, np_l, 2);
     return qs_launch_status("qed_plan_step");
 }
 
