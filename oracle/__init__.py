@@ -37,7 +37,7 @@ F_TAU = 1 << 11
 F_ALL = (F_PUSH | F_TBMT | F_EMIT | F_RECOIL | F_SPIN | F_NOEMIT | F_PHOTON_POL
          | F_PAIR | F_NOPAIR | F_PAIR_SPIN)
 
-FIELD_UNIFORM, FIELD_PLANE_LP, FIELD_GRID2D = 0, 1, 2
+FIELD_UNIFORM, FIELD_PLANE_LP, FIELD_GRID2D, FIELD_ROTATING_E = 0, 1, 2, 3
 
 
 def build(force: bool = False) -> Path:

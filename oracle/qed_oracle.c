@@ -679,6 +679,11 @@ void orc_fields_eval(const orc_fields *f, const double x[3], double t, double E[
         double ey = f->a0 * g * cos(phi);
         E[1] += ey;
         B[2] += -ey;
+    } else if (f->kind == ORC_FIELD_ROTATING_E) {
+        /* uniform electric field of magnitude a0 rotating in the (x, y) plane at the laser
+           frequency (polarized-cascade section: the 0-D rotating-field setup) */
+        E[0] += f->a0 * cos(t);
+        E[1] += f->a0 * sin(t);
     } else if (f->kind == ORC_FIELD_GRID2D) {
         /* bilinear interpolation between the four nodes around (x, y), periodic grid */
         double u = (x[0] - f->x0) / f->dx, v = (x[1] - f->y0) / f->dy;

@@ -69,7 +69,7 @@ double orc_table_lnrate(const orc_tables *T, int channel, double lnchi);
 double orc_table_nu(const orc_tables *T, int channel, double lnchi, double rho);
 
 /* ---------------- fields ---------------- */
-enum { ORC_FIELD_UNIFORM = 0, ORC_FIELD_PLANE_LP = 1, ORC_FIELD_GRID2D = 2 };
+enum { ORC_FIELD_UNIFORM = 0, ORC_FIELD_PLANE_LP = 1, ORC_FIELD_GRID2D = 2, ORC_FIELD_ROTATING_E = 3 };
 typedef struct {
     int    kind;
     double E0[3], B0[3];    /* uniform */

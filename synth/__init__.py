@@ -23,7 +23,7 @@ LAMBDA_UM = 0.8
 EPS_R = HC_EV_NM / (LAMBDA_UM * 1000.0) / MEC2_EV      # hbar omega_r / (m c^2)
 OMEGA_R = 2.0 * math.pi * C_LIGHT / (LAMBDA_UM * 1e-6)  # rad/s
 
-FIELD_UNIFORM, FIELD_PLANE_LP, FIELD_GRID2D = 0, 1, 2
+FIELD_UNIFORM, FIELD_PLANE_LP, FIELD_GRID2D, FIELD_ROTATING_E = 0, 1, 2, 3
 
 
 @dataclass
@@ -155,6 +155,21 @@ def c5(n_instances: int = 64, seed: int = 5, steps: int = 2000, n_min: float = 1
         w.extra = dict(a0=a0, gamma0=g0, pol_degree=d, pol_axis=axis)
         out.append(w)
     return out
+
+
+def c6(n: int = 64, seed: int = 6, steps: int = 2000, a0: float = 1000.0, dt: float = 0.005) -> Workload:
+    """Seeded pair cascade in a rotating electric field (polarized-cascade section): a uniform field
+    of magnitude a0 = 1000 rotating in the (x, y) plane at the laser frequency (lambda = 0.8 um),
+    n seed electrons at rest with isotropic unit spins (an unpolarized seed), both channels.
+    dt = 0.005 / omega: electrons reach gamma ~ a0 and chi ~ 3, where W dt stays near 0.03.
+    Photons are retired below k = chi_g_min / (a0 eps_r), under which chi_gamma cannot reach
+    chi_g_min in a field of magnitude a0.  No position is tracked (0-D)."""
+    rng = np.random.default_rng(seed)
+    x = np.zeros((3, n))
+    p = np.zeros((3, n))
+    s = random_unit_vectors(rng, n)
+    return Workload("c6_cascade_rotating_e_a0_1000", n, steps, dt, seed, FIELD_ROTATING_E, a0=a0,
+                    track=(False, False, False), pair=True, k_retire=0.05 / (a0 * EPS_R), x=x, p=p, s=s)
 
 
 def subsample(w: Workload, idx) -> Workload:

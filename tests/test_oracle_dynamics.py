@@ -386,3 +386,32 @@ def test_grid_fields_bilinear_and_periodic():
     E1, B1 = oracle.fields_eval(F, [x, y, 0], 0)
     E2, B2 = oracle.fields_eval(F, [x + 3 * nx * dx, y - 2 * ny * dy, 0], 0)
     np.testing.assert_allclose(np.concatenate([E1, B1]), np.concatenate([E2, B2]), atol=1e-12)
+
+
+def test_rotating_field_classical_orbit(otables):
+    """The rotating-field model of the cascade setup (polarized-cascade section): without QED an
+    electron (q = -1) released at rest at t = 0 in E = a0 (cos t, sin t, 0) has
+    p(t) = q a0 (sin t, 1 - cos t, 0), so |p| = 2 a0 |sin(t/2)| (the classical advection the
+    section's phase-space figure draws).  Pushed step by step over one period with the fields at
+    the start of each step, the oracle's error is first order in dt: it halves with dt."""
+    a0, T = 1000.0, 2 * math.pi
+    F = oracle.make_fields(oracle.FIELD_ROTATING_E, a0=a0)
+    errs = []
+    for dt in (2e-2, 1e-2):
+        L = oracle.LeptonSet(0, 1, track=(False, False, False))
+        L.set(np.zeros((3, 1)), np.zeros((3, 1)), np.array([[0.0], [0.0], [1.0]]))
+        G = oracle.PhotonSet(1, track=(False, False, False))
+        n = int(round(T / dt))
+        worst = 0.0
+        for k in range(n):
+            prm = oracle.make_params(dt, EPS, step=k, t=k * dt, seed=1, flags=oracle.F_PUSH)
+            oracle.lepton_step(otables, prm, F, L, G, oracle.Counters())
+            t = (k + 1) * dt
+            exact = -a0 * np.array([math.sin(t), 1 - math.cos(t), 0.0])
+            got = np.array([L.p[c][0] for c in range(3)])
+            worst = max(worst, float(np.abs(got - exact).max()))
+            if k + 1 == n // 2:                        # t = pi: the left-point error of p_x is q a0 dt
+                assert abs((got[0] - exact[0]) / (-a0 * dt) - 1) < 0.1
+        errs.append(worst)
+        assert worst < 1.05 * a0 * dt                  # left-point rule: a0 dt (1 + O(dt)) at cos t = -1
+    assert 1.8 < errs[0] / errs[1] < 2.2
