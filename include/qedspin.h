@@ -83,10 +83,14 @@ enum {
     QED_FIELD_PLANE_LP = 1,    /* E0, B0 plus a linearly polarized wave along -x:
                                   E_y = a0 g(phi) cos(phi), B_z = -E_y, phi = t + x,
                                   g = sin^2(pi phi / phase_len) on [0, phase_len] (1 if phase_len = 0) */
-    QED_FIELD_GRID2D = 2       /* E0, B0 plus a static field on a periodic 2-D grid in (x, y): six FP32
+    QED_FIELD_GRID2D = 2,      /* E0, B0 plus a static field on a periodic 2-D grid in (x, y): six FP32
                                   device arrays Ex, Ey, Ez, Bx, By, Bz of nx * ny nodes, node (i, j) at
                                   (x0 + i dx, y0 + j dy), index j * nx + i; bilinear interpolation
                                   (particles need x[0] and x[1]) */
+    QED_FIELD_ROTATING_E = 3   /* E0, B0 plus a uniform electric field of magnitude a0 rotating in the
+                                  (x, y) plane at the reference frequency: E_x = a0 cos t,
+                                  E_y = a0 sin t (the 0-D cascade setup of the polarized-cascade
+                                  section); no position needed */
 };
 
 /* Rate / inverse-CDF table grid: nodes uniform in ln chi and in rho = ln(r/(1-r)).

@@ -29,7 +29,7 @@ QED_PAIR, QED_NOPAIR, QED_PAIR_SPIN = 1 << 8, 1 << 9, 1 << 10
 QED_OPTICAL_DEPTH = 1 << 11
 QED_ALL = (QED_PUSH | QED_TBMT | QED_EMIT | QED_RECOIL | QED_SPIN | QED_NOEMIT | QED_PHOTON_POL
            | QED_PAIR | QED_NOPAIR | QED_PAIR_SPIN)
-QED_FIELD_UNIFORM, QED_FIELD_PLANE_LP, QED_FIELD_GRID2D = 0, 1, 2
+QED_FIELD_UNIFORM, QED_FIELD_PLANE_LP, QED_FIELD_GRID2D, QED_FIELD_ROTATING_E = 0, 1, 2, 3
 
 ABI_SYMBOLS = ("qed_init_tables", "qed_last_error", "qed_free_tables", "qed_tables_download", "qed_workspace_size",
                "qed_push_spin", "qed_emit", "qed_pair", "qed_compact_workspace_size", "qed_compact",

@@ -264,6 +264,9 @@ static __device__ __forceinline__ void eval(const FieldDev &f, double x0, double
         const double ey = f.a0 * g * cos(phi);
         E.y += ey;
         B.z -= ey;
+    } else if (f.kind == 3) {
+        E.x += f.a0 * cos(t);
+        E.y += f.a0 * sin(t);
     } else if (GRID && f.kind == 2) {
         add_grid<double>(f, x0, y0, E, B);
     }
@@ -292,6 +295,11 @@ static __device__ __forceinline__ void eval(const FieldDev &f, double x0, double
         const float ey = (float)f.a0 * g * __builtin_amdgcn_cosf(red);
         E.y += ey;
         B.z -= ey;
+    } else if (f.kind == 3) {
+        const double rev = t * (0.5 / kPi);
+        const float red = (float)(rev - rint(rev));
+        E.x += (float)f.a0 * __builtin_amdgcn_cosf(red);
+        E.y += (float)f.a0 * __builtin_amdgcn_sinf(red);
     } else if (GRID && f.kind == 2) {
         add_grid<float>(f, x0, y0, E, B);
     }

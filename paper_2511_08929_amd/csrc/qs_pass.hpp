@@ -764,6 +764,7 @@ inline bool fields_ok(const qed_fields *f)
 {
     if (!f) return false;
     if (f->kind == QED_FIELD_UNIFORM || f->kind == QED_FIELD_PLANE_LP) return true;
+    if (f->kind == QED_FIELD_ROTATING_E) return f->a0 == f->a0;
     if (f->kind != QED_FIELD_GRID2D) return false;
     for (int c = 0; c < 6; ++c)
         if (!f->grid[c]) return false;

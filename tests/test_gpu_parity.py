@@ -513,3 +513,77 @@ def test_compaction_in_rounds(q):
     assert g.n() == m and int(g.count_prev.item()) == m
     for a, e in zip([g.x[0]] + g.k + g.P + [g.id], expect):
         assert torch.equal(a[:m], e)
+
+
+def test_cascade_small_run_fp64(q, gtab64, otables):
+    """Seeded pair cascade in the rotating field (a0 = 1000), 64 electrons from rest for 800 steps
+    (omega t = 4, first pairs and their emission), both channels, compaction every 50 steps: every
+    lepton, pair-born lepton and photon compared with the oracle."""
+    w = synth.c6(n=64)
+    steps, cap_l, cap_g = 800, 2_000, 20_000
+    sim = _sim(q, gtab64, w, cap_l, cap_l, cap_g, q.QED_ALL)
+    sim.e.load(w.x, w.p, w.s)
+    for k in range(steps):
+        sim.step()
+        if k % 50 == 49:
+            sim.compact()
+    ref = oracle_run(otables, w, steps, q.QED_ALL, cap_e=cap_l, cap_p=cap_l, cap_g=cap_g)
+    c = q.counters_dict(sim.ctr)
+    print("cascade gpu", c, "oracle", ref["ctr"])
+    assert ref["near_e"].sum() == 0 and ref["near_g"].sum() == 0
+    assert c["n_emit"] == ref["ctr"]["n_emit"] > 500 and c["n_pair"] == ref["ctr"]["n_pair"] > 10
+    tol = tol_k(steps)
+    compare_leptons(sim.e.arrays(), ref["E"].arrays(), np.zeros(ref["E"].n, bool), tol, tol, rtol_x=tol,
+                    what="cascade electrons", events=c["n_emit"])
+    compare_leptons(sim.p.arrays(), ref["P"].arrays(), np.zeros(ref["P"].n, bool), tol, tol, rtol_x=tol,
+                    what="cascade positrons")
+    compare_photons(sim.g.arrays(), ref["G"].arrays(), set(), tol, tol, what="cascade photons")
+
+
+def test_cascade_polarization(q, gtab32):
+    """The seeded cascade (64 electrons, FP32, merged step) to omega t = 16, in its exponential
+    phase: the photons emitted in the rotation plane's polarization outnumber those polarized
+    along the rotation axis about 4 to 1, the ratio the polarized-cascade section prints (loose
+    pin: 3 to 5); the electrons and the positrons carry the same spin polarization along the
+    basis vector beta (within 0.05 of each other), with a clear majority."""
+    import torch
+    from paper_2511_08929_amd.sim import Simulation
+    w = synth.c6(n=64)
+    f = q.make_fields(w.field_kind, a0=w.a0)
+    sim = Simulation(gtab32, cap_e=400_000, cap_p=400_000, cap_g=6_000_000, track=w.track, fields=f, dt=w.dt,
+                     eps_r=EPS, seed=w.seed, flags=q.QED_ALL, k_retire=w.k_retire, device_clock=True, merged=True)
+    sim.e.load(w.x, w.p, w.s)
+    nsteps = int(round(16.0 / w.dt))
+    for k in range(1, nsteps + 1):
+        sim.step()
+        if k % 50 == 0:
+            sim.compact()
+    torch.cuda.synchronize()
+    c = q.counters_dict(sim.ctr)
+    assert c["n_capacity_overflow"] == 0 and sim.e.n() > 20 * w.n and sim.p.n() > 19 * w.n
+    t = nsteps * w.dt
+    E = w.a0 * np.array([math.cos(t), math.sin(t), 0.0])[:, None]
+    sb_mean = []
+    for L, qq in ((sim.e, -1.0), (sim.p, 1.0)):
+        n = L.n()
+        sv = np.stack([a[:n].double().cpu().numpy() for a in L.s])
+        pv = np.stack([a[:n].double().cpu().numpy() for a in L.p])
+        kh = pv / np.linalg.norm(pv, axis=0)
+        eps = -qq * (E - kh * np.sum(E * kh, axis=0))
+        eps /= np.linalg.norm(eps, axis=0)
+        beta = np.cross(kh.T, eps.T).T
+        sb_mean.append(float(np.sum(sv * beta, axis=0).mean()))
+    ng = sim.g.n()
+    kv = np.stack([a[:ng].double().cpu().numpy() for a in sim.g.k])
+    P = np.stack([a[:ng].double().cpu().numpy() for a in sim.g.P])
+    kh = kv / np.linalg.norm(kv, axis=0)
+    ez = np.array([0.0, 0.0, 1.0])[:, None] - kh * kh[2]
+    ez /= np.linalg.norm(ez, axis=0)
+    ein = np.cross(kh.T, ez.T).T                          # in the rotation plane, normal to k
+    lin = np.sum(P * ein, axis=0) ** 2 - np.sum(P * ez, axis=0) ** 2
+    ratio_g = np.sum(lin > 0) / np.sum(lin < 0)
+    ratio_l = [(1 + m) / (1 - m) for m in sb_mean]
+    print(f"cascade at omega t = {t}: {sim.e.n()} e-, {sim.p.n()} e+, {ng} photons; photons in-plane : axis "
+          f"= {ratio_g:.2f}; lepton spin along beta majority : minority = {ratio_l[0]:.2f} (e-), {ratio_l[1]:.2f} (e+)")
+    assert 3.0 < ratio_g < 5.0
+    assert abs(sb_mean[0] - sb_mean[1]) < 0.05 and min(ratio_l) > 1.5
