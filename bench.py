@@ -44,7 +44,7 @@ def bytes_per_unit(es, tracked_x=1):
 
 
 def run_gpu(q, tab, w, steps, warmup, compact_every, profile, graph=True, merged=True, surrogates=(None, None), ppb=0,
-            photons_per_electron=30):
+            photons_per_electron=30, caps=None):
     """Time `steps` steps from the initial state.  With graph=True each run of `compact_every`
     steps plus the compaction is one captured HIP graph (recorded before the timed region).
     merged=True runs each step as one qed_plan_step; surrogates: learned inverse CDFs (NLC, NBW)."""
@@ -52,10 +52,13 @@ def run_gpu(q, tab, w, steps, warmup, compact_every, profile, graph=True, merged
     from paper_2511_08929_amd.sim import Simulation
     cap_p = max(1000, w.n // 5)
     cap_g = max(100_000, photons_per_electron * w.n)
+    cap_e = w.n + cap_p
+    if caps is not None:
+        cap_e, cap_p, cap_g = caps
     fields = q.make_fields(w.field_kind, a0=w.a0, phase_len=w.phase_len)
 
     def fresh():
-        sim = Simulation(tab, cap_e=w.n + cap_p, cap_p=cap_p, cap_g=cap_g, track=w.track, fields=fields, dt=w.dt,
+        sim = Simulation(tab, cap_e=cap_e, cap_p=cap_p, cap_g=cap_g, track=w.track, fields=fields, dt=w.dt,
                          eps_r=synth.EPS_R, seed=w.seed, flags=q.QED_ALL, k_retire=w.k_retire, device_clock=graph,
                          merged=merged, surrogates=surrogates, particles_per_block=ppb)
         sim.e.load(w.x, w.p, w.s)
@@ -302,6 +305,21 @@ def extras(q, args, w, t32, t64, out, v32, v64):
                                 "a0 ~ U[20, 200], gamma0 ~ U[500, 1e4], spin degree ~ U[0, 1]",
                       "particles_per_block": best, "tuning_s_per_300_steps": {str(k): round(v, 4) for k, v in cand.items()},
                       "fp64_value": round(vb64, 1), "speedup_vs_fp64": round(vb / vb64, 3)}
+    # seeded pair cascade in the rotating field (a0 = 1000): 20000 seed electrons to omega t = 16
+    wc = synth.c6(n=20_000, steps=3200)
+    caps = (2_000_000, 2_000_000, 30_000_000)
+    rc = {}
+    for label, tab in (("fp32", t32), ("fp64", t64)):
+        r = run_gpu(q, tab, wc, wc.steps, 0, args.compact_every, profile=False, graph=True, ppb=args.ppb, caps=caps)
+        c = r["ctr"]
+        rc[label] = dict(value=round((c["n_lepton_steps"] + c["n_photon_steps"]) / r["wall"], 1),
+                         wall_s=round(r["wall"], 4), electrons=r["n_e"], positrons=r["n_p"], photons=r["n_photons"],
+                         capacity_overflow=c["n_capacity_overflow"])
+        log(f"cascade {label}: {r['wall']:.3f} s, {rc[label]['value']:.4g}/s, final e- {r['n_e']} e+ {r['n_p']} "
+            f"photons {r['n_photons']}")
+    out["cascade"] = dict(workload="seeded pair cascade, rotating E field a0 = 1000, 20000 electrons from rest, "
+                                   "omega t = 16 (3200 steps of 0.005)", unit="particle-QED-steps/s",
+                          speedup_fp32_vs_fp64=round(rc["fp32"]["value"] / rc["fp64"]["value"], 3), **rc)
 
 
 def full_scale(q, args, t32, t64, out):
@@ -346,6 +364,25 @@ def full_scale(q, args, t32, t64, out):
     out["full_scale_batched"] = dict(instances=len(ws), electrons=int(sum(x.n for x in ws)), steps=steps_b,
                                      particles_per_block=best, speedup_vs_fp64=round(rb["fp32"]["value"] /
                                                                                      rb["fp64"]["value"], 3), **rb)
+
+
+def copy_gbs(reps=10):
+    """Achievable HBM bandwidth on this device: a plain device-to-device copy of 1 GiB (read 1 GiB,
+    write 1 GiB), timed with HIP events, best of `reps`."""
+    import torch
+    a = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    best = float("inf")
+    for _ in range(reps + 1):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        b.copy_(a)
+        e1.record()
+        e1.synchronize()
+        best = min(best, e0.elapsed_time(e1))
+    del a, b
+    torch.cuda.empty_cache()
+    return 2 * (1 << 30) / (best * 1e-3) / 1e9
 
 
 def main():
@@ -414,10 +451,13 @@ def main():
     dom = max(kt, key=lambda k: kt[k][1])
     calls, ms = kt[dom]
     achieved = bytes_of[dom] / (ms * 1e-3) / 1e9
+    cgbs = copy_gbs()
+    log(f"device copy: {cgbs:.1f} GB/s")
     roof = dict(bound="hbm", kernel=dom, achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
                 frac=round(achieved / HBM_PEAK_GBS, 4), traffic=load_traffic(dom), valu_issue_frac=load_valu(dom),
                 avg_launch_us=round(ms * 1e3 / calls, 2), launches=calls,
                 bytes_per_launch=round(bytes_of[dom] / calls),
+                copy_achieved=round(cgbs, 1), frac_of_copy=round(achieved / cgbs, 4),
                 kernel_ms={k: round(v[1], 3) for k, v in rk["ktimes"].items()})
 
     out = {"metric": METRIC, "value": round(value, 1), "unit": "particle-QED-steps/s", "n_gpus": 1,
