@@ -587,3 +587,41 @@ def test_cascade_polarization(q, gtab32):
           f"= {ratio_g:.2f}; lepton spin along beta majority : minority = {ratio_l[0]:.2f} (e-), {ratio_l[1]:.2f} (e+)")
     assert 3.0 < ratio_g < 5.0
     assert abs(sb_mean[0] - sb_mean[1]) < 0.05 and min(ratio_l) > 1.5
+
+
+def test_cascade_photon_seed_polarization(q, gtab32):
+    """Photon-seeded cascade start (polarized-cascade section): 10^5 photons of k = 2000 m c
+    moving along +x in the rotating field from t = pi/2 (E = a0 y, chi_gamma ~ 6), linearly
+    polarized along the rotation axis (perpendicular) or in the rotation plane (parallel).  Over
+    the first 20 steps (omega t = 0.1, little depletion) the perpendicular seed makes about twice
+    the pairs (the section prints almost two times; the rates' ratio J(-1)/J(+1) is 1.7 to 1.9
+    there), loose pin 1.4 to 2.3."""
+    import torch
+    from paper_2511_08929_amd.sim import Simulation
+    n, k0, steps = 100_000, 2000.0, 20
+    w = synth.c6(n=1)
+    f = q.make_fields(w.field_kind, a0=w.a0)
+    kvec = np.array([k0, 0.0, 0.0])
+    _, e, b, kh = oracle.basis(0, EPS, np.array([0.0, w.a0, 0.0]), np.zeros(3), kvec)
+    pairs = {}
+    for name, xi3 in (("perp", -1.0), ("par", 1.0)):
+        Pv = oracle.stokes_to_P(np.array([0.0, 0.0, xi3]), e, b, kh)
+        sim = Simulation(gtab32, cap_e=200_000, cap_p=200_000, cap_g=n + 400_000, track=w.track, fields=f,
+                         dt=w.dt, eps_r=EPS, seed=17, flags=q.QED_ALL, k_retire=w.k_retire, t0=0.5 * math.pi,
+                         device_clock=True, merged=True)
+        g = sim.g
+        for c in range(3):
+            g.k[c][:n].fill_(float(kvec[c]))
+            g.P[c][:n].fill_(float(Pv[c]))
+        g.id[:n].copy_(torch.arange(1, n + 1, dtype=torch.int64, device="cuda") | (1 << 62))
+        g.count.fill_(n)
+        g.count_prev.fill_(n)
+        for _ in range(steps):
+            sim.step()
+        torch.cuda.synchronize()
+        c = q.counters_dict(sim.ctr)
+        assert c["n_capacity_overflow"] == 0
+        pairs[name] = c["n_pair"]
+    ratio = pairs["perp"] / pairs["par"]
+    print(f"photon seeds: pairs {pairs}, perpendicular / parallel = {ratio:.2f}")
+    assert pairs["par"] > 1000 and 1.4 < ratio < 2.3
