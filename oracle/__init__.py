@@ -34,6 +34,7 @@ F_PUSH, F_TBMT, F_EMIT, F_RECOIL = 1 << 0, 1 << 1, 1 << 2, 1 << 3
 F_SPIN, F_NOEMIT, F_PHOTON_POL, F_MEAN = 1 << 4, 1 << 5, 1 << 6, 1 << 7
 F_PAIR, F_NOPAIR, F_PAIR_SPIN = 1 << 8, 1 << 9, 1 << 10
 F_TAU = 1 << 11
+F_REJECT = 1 << 12
 F_ALL = (F_PUSH | F_TBMT | F_EMIT | F_RECOIL | F_SPIN | F_NOEMIT | F_PHOTON_POL
          | F_PAIR | F_NOPAIR | F_PAIR_SPIN)
 

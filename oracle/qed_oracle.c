@@ -866,6 +866,26 @@ int orc_lepton_qed_one(const orc_tables *T, const orc_params *prm, int species, 
     uniforms2(prm, id, 0, &r1, &r2);
     double Wbar = 0.5 * (Wup + Wdn), dW = 0.5 * (Wup - Wdn);
     double thr;
+    double lam, oml;
+    if (fl & ORC_F_REJECT) {
+        /* rejection sampling (spectrum-sampling section): the candidate lambda = r1^3 is accepted
+           with probability 3 r1^2 dW/dlambda dt, dW/dlambda = Ce w(lambda, s_beta) the spectrum of
+           the initial spin state summed over the final states; integrated over r1 this is W_s dt */
+        lam = r1 * r1 * r1;
+        oml = (1.0 - r1) * (1.0 + r1 + r1 * r1);
+        spec_pt q0 = nlc_point(chi, lam, oml);
+        double A = 3.0 * r1 * r1 * Ce * nlc_w_pt(&q0, sb) * dt;
+        if (A > 1.0) ctr->n_prob_clamped++;
+        if (near_tie(r2, A, prm->near_tol)) near = 1;
+        if (!(r2 < A)) {
+            if (fl & ORC_F_NOEMIT) {
+                if (P < 1.0) no_emission_update(s, bh, Wbar, dW, dt, P, ctr);
+                else ctr->n_prob_clamped++;
+            }
+            return near << 1;
+        }
+        goto emission;
+    }
     if ((fl & ORC_F_TAU) && tau2) {
         /* optical depth (R10) */
         uint32_t w4[4];
@@ -901,8 +921,8 @@ int orc_lepton_qed_one(const orc_tables *T, const orc_params *prm, int species, 
     int up = !(r1 < thr);
     double rho = log(r2) - log1p(-r2);
     double nu = orc_table_nu(T, up ? 1 : 0, lnchi, rho);
-    double lam, oml;
     lam_from_nu(nu, &lam, &oml);
+emission:
     for (int i = 0; i < 3; ++i) k_out[i] = lam * p[i];
     double r3, r4;
     uniforms2(prm, id, 1, &r3, &r4);

@@ -88,7 +88,10 @@ enum {
     ORC_F_PUSH = 1u << 0, ORC_F_TBMT = 1u << 1, ORC_F_EMIT = 1u << 2, ORC_F_RECOIL = 1u << 3,
     ORC_F_SPIN = 1u << 4, ORC_F_NOEMIT = 1u << 5, ORC_F_PHOTON_POL = 1u << 6, ORC_F_MEAN = 1u << 7,
     ORC_F_PAIR = 1u << 8, ORC_F_NOPAIR = 1u << 9, ORC_F_PAIR_SPIN = 1u << 10,
-    ORC_F_TAU = 1u << 11     /* emission decided by the optical depth instead of the per-step draw */
+    ORC_F_TAU = 1u << 11,    /* emission decided by the optical depth instead of the per-step draw */
+    ORC_F_REJECT = 1u << 12  /* emission decided and lambda sampled together by rejection from the
+                                spin-resolved spectrum with candidates lambda = r1^3 (spectrum-sampling
+                                section), instead of the draw against W dt and the inverse CDF */
 };
 
 typedef struct {
