@@ -72,9 +72,14 @@ enum {
     QED_PAIR = 1u << 8,        /* nonlinear Breit-Wheeler pair creation */
     QED_NOPAIR = 1u << 9,      /* no-transition polarization update of surviving photons */
     QED_PAIR_SPIN = 1u << 10,  /* correlated pair spins (else unpolarized pairs) */
-    QED_OPTICAL_DEPTH = 1u << 11 /* emission decided by the optical depth (decision-making overview):
+    QED_OPTICAL_DEPTH = 1u << 11, /* emission decided by the optical depth (decision-making overview):
                                   tau += W dt in FP64, emission when tau >= tau* = -ln(1 - u), u from
                                   Philox channel 4; the leptons' tau / tau_target arrays are required */
+    QED_REJECTION = 1u << 12   /* emission decided and lambda sampled together by rejection
+                                  (spectrum-sampling section): the candidate lambda = r1^3 is accepted
+                                  when r2 < 3 r1^2 dW/dlambda dt, dW/dlambda the spectrum of the
+                                  lepton's spin state; no inverse-CDF table is read for the emission.
+                                  Not with QED_OPTICAL_DEPTH (QED_ERR_INVALID) */
 };
 
 /* Field models evaluated at each particle. */

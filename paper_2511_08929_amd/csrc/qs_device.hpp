@@ -17,7 +17,7 @@ constexpr double kPi = 3.14159265358979323846;
 enum : uint32_t {
     F_PUSH = 1u << 0, F_TBMT = 1u << 1, F_EMIT = 1u << 2, F_RECOIL = 1u << 3, F_SPIN = 1u << 4,
     F_NOEMIT = 1u << 5, F_PHOTON_POL = 1u << 6, F_MEAN = 1u << 7, F_PAIR = 1u << 8,
-    F_NOPAIR = 1u << 9, F_PAIR_SPIN = 1u << 10, F_TAU = 1u << 11
+    F_NOPAIR = 1u << 9, F_PAIR_SPIN = 1u << 10, F_TAU = 1u << 11, F_REJECT = 1u << 12
 };
 
 // ------------------------------------------------------------------ small vectors
@@ -118,6 +118,7 @@ constexpr int kBn64Levels = 5, kBn64N0 = 1024, kBn64N = 64;
 constexpr int kBn32Levels = 3, kBn32N0 = 256, kBn32N = 64;
 constexpr int kBn64Nodes = kBn64N0 + (kBn64Levels - 1) * kBn64N;
 constexpr int kBn32Nodes = kBn32N0 + (kBn32Levels - 1) * kBn32N;
+constexpr double kBn32H[kBn32Levels] = {0.4, 0.1, 0.025};
 
 struct Bessel3 { double k13, k23, ik; };
 
@@ -174,13 +175,15 @@ template <> __device__ __forceinline__ void bessel_ratios<double>(double x, cons
     I = b.ik / b.k23;
 }
 
-template <> __device__ __forceinline__ void bessel_ratios<float>(double xd, const void *nodes, float &K1, float &I)
+// FP32 trapezoid sums of e^{x} K_1/3, e^{x} K_2/3 and e^{x} IntK_1/3 without the step h of
+// their level (lvl)
+__device__ __forceinline__ void bessel_sums32(float x, const void *nodes, float &s13, float &s23, float &sik, int &lvl)
 {
-    const float x = fmaxf((float)xd, 1e-30f);
     const int k = x <= 6.25f ? 0 : (x <= 100.0f ? 1 : 2);
     const int off = k == 0 ? 0 : kBn32N0 + (k - 1) * kBn32N, nn = k == 0 ? kBn32N0 : kBn32N;
     const float4 *q = reinterpret_cast<const float4 *>(nodes) + off;
-    float s13 = 0.5f, s23 = 0.5f, sik = 0.5f;
+    s13 = 0.5f; s23 = 0.5f; sik = 0.5f;
+    lvl = k;
     // nodes in groups of four, as in the double precision sum
     for (int j0 = 1; j0 < nn; j0 += 4) {
         float4 a[4];                                    // cosh t - 1, cosh t/3, cosh 2t/3, ratio
@@ -204,8 +207,42 @@ template <> __device__ __forceinline__ void bessel_ratios<float>(double xd, cons
         }
         if (done) break;
     }
+}
+
+template <> __device__ __forceinline__ void bessel_ratios<float>(double xd, const void *nodes, float &K1, float &I)
+{
+    float s13, s23, sik;
+    int lvl;
+    bessel_sums32(fmaxf((float)xd, 1e-30f), nodes, s13, s23, sik, lvl);
     K1 = s13 / s23;       // the step h cancels in the ratios
     I = sik / s23;
+}
+
+// K_1/3, K_2/3 and IntK_1/3 at x themselves (the rejection step needs the spectrum's size)
+template <class R> __device__ __forceinline__ void bessel_abs(double x, const void *nodes, R &K13, R &K23, R &IK);
+
+template <> __device__ __forceinline__ void bessel_abs<double>(double x, const void *nodes, double &K13, double &K23,
+                                                               double &IK)
+{
+    const Bessel3 b = bessel3_scaled(x, (const double *)nodes);
+    const double e = x < 700.0 ? exp(-x) : 0.0;
+    K13 = b.k13 * e;
+    K23 = b.k23 * e;
+    IK = b.ik * e;
+}
+
+template <> __device__ __forceinline__ void bessel_abs<float>(double xd, const void *nodes, float &K13, float &K23,
+                                                              float &IK)
+{
+    const float x = fmaxf((float)xd, 1e-30f);
+    float s13, s23, sik;
+    int lvl;
+    bessel_sums32(x, nodes, s13, s23, sik, lvl);
+    const float h = (float)(lvl == 0 ? kBn32H[0] : (lvl == 1 ? kBn32H[1] : kBn32H[2]));
+    const float f = h * expf(-x);
+    K13 = s13 * f;
+    K23 = s23 * f;
+    IK = sik * f;
 }
 
 // ------------------------------------------------------------------ fields

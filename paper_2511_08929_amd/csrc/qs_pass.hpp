@@ -187,7 +187,7 @@ template <class R> __device__ __forceinline__ bool zero_field(V3<R> E, V3<R> B)
 template <class R> struct LDecide {
     double chi;        // clamped for lookups
     Basis<R> bs;
-    R Wdn, Wup, a, P, r1, r2;
+    R Ce, Wdn, Wup, a, P, r1, r2;
     bool active;       // chi >= chi_min
     bool clamped_chi;
 };
@@ -214,6 +214,7 @@ __device__ __forceinline__ LDecide<R> lepton_decide(const StepDev &S, const Tabl
     const R lnchi = log_r((R)d.chi);
     const R x0 = (R)T.lnchi0[0], h = (R)T.dlnchi[0];
     const R Ce = ratio_r<R>(S.Kc, gam);
+    d.Ce = Ce;
     d.Wdn = Ce * exp_r(rate_lookup(lds, lnchi, x0, h, n));
     d.Wup = Ce * exp_r(rate_lookup(lds + n, lnchi, x0, h, n));
     const R sb = dot(s, d.bs.b);
@@ -320,6 +321,24 @@ __device__ __forceinline__ void lepton_item(const LepDev<R> &L, const FieldDev &
                     if (d.P < (R)1) noemit_update = true;
                     else if (S.flags & F_NOEMIT) ++c.prob;
                 }
+            } else if (S.flags & F_REJECT) {
+                // rejection (spectrum-sampling section): candidate lambda = r1^3, accepted when
+                // r2 < 3 r1^2 dW/dlambda dt with the spectrum of the lepton's spin state
+                const double r1 = (double)d.r1;
+                const double lam = r1 * r1 * r1, oml = (1.0 - r1) * (1.0 + r1 + r1 * r1);
+                R K13, K23, IK;
+                bessel_abs<R>(2.0 * (lam / oml) / (3.0 * d.chi), bn_of<R>(T), K13, K23, IK);
+                const R kappa = (R)(1.0 / oml + oml);
+                const R w = -IK + kappa * K23 + (R)lam * dot(s, d.bs.b) * K13;
+                const R A = (R)(3.0 * r1 * r1) * d.Ce * w * (R)S.dt;
+                c.prob += A > (R)1;
+                if (d.r2 < A) {
+                    emit = true;
+                } else if (d.P < (R)1) {
+                    noemit_update = true;
+                } else if (S.flags & F_NOEMIT) {
+                    ++c.prob;
+                }
             } else if (d.P <= (R)1 && !(d.r1 < d.P)) {
                 noemit_update = true;
             } else {
@@ -398,8 +417,16 @@ __device__ __forceinline__ void emit_item(const LepDev<R> &L, const PhoDev<R> &G
         x_out[2] = up ? 1.0f : -1.0f;
         return;
     }
-    const double nu = nu_in ? (double)*nu_in : icdf_nu(T, up ? 1 : 0, log(d.chi), rho);
-    const double lam_d = 1.0 / (1.0 + exp(-nu)), oml_d = 1.0 / (1.0 + exp(nu));
+    double lam_d, oml_d;
+    if (S.flags & F_REJECT) {                     // the candidate the streaming pass accepted
+        const double r1 = (double)d.r1;
+        lam_d = r1 * r1 * r1;
+        oml_d = (1.0 - r1) * (1.0 + r1 + r1 * r1);
+    } else {
+        const double nu = nu_in ? (double)*nu_in : icdf_nu(T, up ? 1 : 0, log(d.chi), rho);
+        lam_d = 1.0 / (1.0 + exp(-nu));
+        oml_d = 1.0 / (1.0 + exp(nu));
+    }
     const double u_d = lam_d / oml_d;
     const V3<R> k = (R)lam_d * p;
     R r3, r4;

@@ -388,6 +388,7 @@ extern "C" qed_status qed_emit(qed_tables T, const qed_leptons *L, const qed_fie
     if (!T || !leptons_ok(L) || !p || !fields_ok(f) || !ctr || !ws) return QED_ERR_INVALID;
     if ((p->flags & QED_EMIT) && !photons_ok(G)) return QED_ERR_INVALID;
     if (!tau_ok(L, p->flags)) return QED_ERR_INVALID;
+    if ((p->flags & QED_REJECTION) && (p->flags & QED_OPTICAL_DEPTH)) return QED_ERR_INVALID;
     if (!(p->dt > 0.0) || !(p->eps_r > 0.0)) return QED_ERR_INVALID;
     if (ws_bytes < qed_workspace_size(L->capacity)) return QED_ERR_CAPACITY;
     hipStream_t st = (hipStream_t)stream;

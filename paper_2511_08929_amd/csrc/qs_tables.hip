@@ -92,7 +92,7 @@ void fill_nodes(std::vector<double> &n64, std::vector<float> &n32)
         }
     }
     n32.assign(4 * qs::kBn32Nodes, 0.0f);
-    const double h32[qs::kBn32Levels] = {0.4, 0.1, 0.025};
+    const double *h32 = qs::kBn32H;
     for (int k = 0; k < qs::kBn32Levels; ++k) {
         const int off = k == 0 ? 0 : qs::kBn32N0 + (k - 1) * qs::kBn32N, nn = k == 0 ? qs::kBn32N0 : qs::kBn32N;
         for (int j = 0; j < nn; ++j) {

@@ -625,3 +625,72 @@ def test_cascade_photon_seed_polarization(q, gtab32):
     ratio = pairs["perp"] / pairs["par"]
     print(f"photon seeds: pairs {pairs}, perpendicular / parallel = {ratio:.2f}")
     assert pairs["par"] > 1000 and 1.4 < ratio < 2.3
+
+
+# ------------------------------------------------------------------ rejection sampling
+def test_rejection_c1_run_fp64(q, gtab64, otables):
+    """Rejection sampling of the emission (QED_REJECTION): the test-particle workload at dt / 10
+    (the acceptance stays below 1), 512 electrons for 300 steps, every particle and photon
+    compared with the oracle."""
+    w = synth.c1(n=512)
+    w.dt /= 10
+    steps = 300
+    flags = (q.QED_ALL & ~q.QED_PAIR) | q.QED_REJECTION
+    cap_g = w.n * steps
+    sim = _sim(q, gtab64, w, w.n, 1, cap_g, flags)
+    sim.e.load(w.x, w.p, w.s)
+    for _ in range(steps):
+        sim.step()
+    ref = oracle_run(otables, w, steps, flags, cap_g=cap_g)
+    ex = ref["near_e"]
+    c = q.counters_dict(sim.ctr)
+    print("rejection c1: near", int(ex.sum()), "gpu", c, "oracle", ref["ctr"])
+    assert ex.sum() == 0 and c["n_emit"] == ref["ctr"]["n_emit"] > 5_000 and c["n_prob_clamped"] == 0
+    compare_leptons(sim.e.arrays(), ref["E"].arrays(), ex, tol_k(steps), tol_k(steps), what="rejection c1 leptons",
+                    events=c["n_emit"])
+    compare_photons(sim.g.arrays(), ref["G"].arrays(), set(), tol_k(steps), tol_k(steps), what="rejection c1 photons")
+
+
+def test_rejection_head_on_fp64(q, gtab64, otables):
+    """Rejection sampling in the head-on collision: 400 electrons through the whole pulse (1700
+    steps), both channels (pairs keep their inverse-CDF sampling), compaction every 200 steps."""
+    w = synth.subsample(synth.c2(), np.arange(400))
+    steps = 1700
+    flags = q.QED_ALL | q.QED_REJECTION
+    cap_g, cap_p = 60_000, 2_000
+    sim = _sim(q, gtab64, w, w.n + cap_p, cap_p, cap_g, flags)
+    sim.e.load(w.x, w.p, w.s)
+    for k in range(steps):
+        sim.step()
+        if k % 200 == 199:
+            sim.compact()
+    ref = oracle_run(otables, w, steps, flags, cap_e=w.n + cap_p, cap_p=cap_p, cap_g=cap_g)
+    c = q.counters_dict(sim.ctr)
+    print("rejection head-on gpu", c, "oracle", ref["ctr"])
+    assert ref["near_e"].sum() == 0 and ref["near_g"].sum() == 0
+    assert c["n_emit"] == ref["ctr"]["n_emit"] > 10_000 and c["n_pair"] == ref["ctr"]["n_pair"]
+    t = tol_k(steps)
+    compare_leptons(sim.e.arrays(), ref["E"].arrays(), np.zeros(ref["E"].n, bool), t, t, rtol_x=t,
+                    what="rejection electrons", events=c["n_emit"])
+    compare_leptons(sim.p.arrays(), ref["P"].arrays(), np.zeros(ref["P"].n, bool), t, t, rtol_x=t,
+                    what="rejection positrons")
+    compare_photons(sim.g.arrays(), ref["G"].arrays(), set(), t, t, what="rejection photons")
+
+
+def test_rejection_step_fp32(q, gtab32, otables):
+    """Rejection sampling in single precision, one step of 4000 electrons in a uniform field
+    (FP32 inputs, 24-bit uniforms): decisions equal except near ties, particles within 1e-5."""
+    n = 4000
+    w = _workload_uniform(n, dt=0.05)
+    w.x, w.p, w.s = (a.astype(np.float32).astype(np.float64) for a in (w.x, w.p, w.s))
+    flags = (q.QED_ALL & ~q.QED_PAIR) | q.QED_REJECTION
+    sim = _sim(q, gtab32, w, n, 1, 2 * n, flags, k_retire=0.0)
+    sim.e.load(w.x, w.p, w.s)
+    sim.step()
+    ref = oracle_run(otables, w, 1, flags, cap_g=2 * n, k_retire=0.0, u24=True, near_tol=1e-5)
+    ex = ref["near_e"]
+    print("rejection fp32: near-tie fraction", ex.mean(), "emitted", ref["ctr"]["n_emit"])
+    assert ex.mean() < 0.01 and ref["ctr"]["n_emit"] > 100
+    compare_leptons(sim.e.arrays(), ref["E"].arrays(), ex, 1e-5, 1e-5, what="rejection fp32 leptons")
+    compare_photons(sim.g.arrays(), ref["G"].arrays(), {(0, int(i)) for i in np.nonzero(ex)[0]}, 1e-5, 1e-5,
+                    what="rejection fp32 photons")

@@ -95,6 +95,23 @@ def test_plan_equals_per_species_pair_overflow(q, tabs):
     assert b.p.n() == 4 and c["n_pair"] > 4 and c["n_capacity_overflow"] == c["n_pair"] - 4
 
 
+def test_plan_equals_per_species_rejection(q, tabs):
+    """Rejection sampling of the emission in the merged step: 2000 electrons of the head-on
+    collision, FP32, 800 steps, against the per-species calls bit for bit."""
+    import torch
+    w = synth.subsample(synth.c2(), np.arange(2000))
+    flags = q.QED_ALL | q.QED_REJECTION
+    a = _sim(q, tabs["fp32"], w, False, w.n + 3000, 3000, 150_000, flags)
+    b = _sim(q, tabs["fp32"], w, True, w.n + 3000, 3000, 150_000, flags)
+    for k in range(1, 801):
+        a.step(); b.step()
+        if k % 50 == 0:
+            a.compact(); b.compact()
+    torch.cuda.synchronize()
+    _assert_same(_state(q, a), _state(q, b), "rejection")
+    assert q.counters_dict(b.ctr)["n_emit"] > 10_000
+
+
 def test_plan_equals_per_species_optical_depth(q, tabs):
     """Optical-depth decision in the merged step: 1500 electrons of the head-on collision, FP32,
     tau and targets compared too."""
