@@ -44,7 +44,7 @@ def bytes_per_unit(es, tracked_x=1):
 
 
 def run_gpu(q, tab, w, steps, warmup, compact_every, profile, graph=True, merged=True, surrogates=(None, None), ppb=0,
-            photons_per_electron=30, caps=None):
+            photons_per_electron=30, caps=None, flags=None):
     """Time `steps` steps from the initial state.  With graph=True each run of `compact_every`
     steps plus the compaction is one captured HIP graph (recorded before the timed region).
     merged=True runs each step as one qed_plan_step; surrogates: learned inverse CDFs (NLC, NBW)."""
@@ -59,7 +59,8 @@ def run_gpu(q, tab, w, steps, warmup, compact_every, profile, graph=True, merged
 
     def fresh():
         sim = Simulation(tab, cap_e=cap_e, cap_p=cap_p, cap_g=cap_g, track=w.track, fields=fields, dt=w.dt,
-                         eps_r=synth.EPS_R, seed=w.seed, flags=q.QED_ALL, k_retire=w.k_retire, device_clock=graph,
+                         eps_r=synth.EPS_R, seed=w.seed, flags=q.QED_ALL if flags is None else flags,
+                         k_retire=w.k_retire, device_clock=graph,
                          merged=merged, surrogates=surrogates, particles_per_block=ppb)
         sim.e.load(w.x, w.p, w.s)
         return sim
@@ -138,14 +139,15 @@ def load_valu(kernel):
     return blob.get("kernels", {}).get(kernel, {}).get("valu_issue_frac")
 
 
-def spectra(q, tab, w, steps, surrogates=(None, None)):
+def spectra(q, tab, w, steps, surrogates=(None, None), flags=None):
     """Every photon emitted in `steps` steps of workload w (no retirement, no compaction: dead
     slots keep their momentum and P-vector) and the electrons' final spins."""
     import torch
     from paper_2511_08929_amd.sim import Simulation
     fields = q.make_fields(w.field_kind, a0=w.a0, phase_len=w.phase_len)
     sim = Simulation(tab, cap_e=w.n * 2 + 1000, cap_p=w.n + 1000, cap_g=120 * w.n, track=w.track, fields=fields,
-                     dt=w.dt, eps_r=synth.EPS_R, seed=w.seed, flags=q.QED_ALL, k_retire=0.0, device_clock=True,
+                     dt=w.dt, eps_r=synth.EPS_R, seed=w.seed, flags=q.QED_ALL if flags is None else flags, k_retire=0.0,
+                     device_clock=True,
                      merged=True, surrogates=surrogates)
     sim.e.load(w.x, w.p, w.s)
     for _ in range(steps):
@@ -278,6 +280,19 @@ def extras(q, args, w, t32, t64, out, v32, v64):
     esu = spectrum_error(ref, spectra(q, t32, wsub, steps_e, surrogates=(sn, sb)))
     log(f"error vs fp64: fp32 {e32}; learned inverse CDF {esu}")
     sur["error_vs_fp64"] = esu
+    # rejection sampling of the emission (no inverse-CDF table for it): throughput and the same
+    # stated error against the FP64 inverse-CDF path
+    rflags = q.QED_ALL | q.QED_REJECTION
+    rr = run_gpu(q, t32, w, args.steps, args.warmup, args.compact_every, profile=False, graph=True, ppb=args.ppb,
+                 flags=rflags)
+    cr = rr["ctr"]
+    vr = (cr["n_lepton_steps"] + cr["n_photon_steps"]) / rr["wall"]
+    er = spectrum_error(ref, spectra(q, t32, wsub, steps_e, flags=rflags))
+    log(f"fp32 rejection sampling (graph): {rr['wall']:.3f} s, {vr:.4g}/s; error vs fp64 {er}")
+    out["rejection"] = {"value": round(vr, 1), "unit": "particle-QED-steps/s", "flags": "QED_ALL | QED_REJECTION",
+                        "photons_emitted": cr["n_emit"], "error_vs_fp64": er}
+    if v64:
+        out["rejection"]["speedup_vs_fp64"] = round(vr / v64, 3)
     out["fp32_error_vs_fp64"] = e32
     out["error_workload"] = f"first {wsub.n} electrons of the same collision, {steps_e} steps, every photon kept"
     out["surrogate"] = sur

@@ -301,7 +301,7 @@ static __device__ __forceinline__ void eval(const FieldDev &f, double x0, double
         const double ey = f.a0 * g * cos(phi);
         E.y += ey;
         B.z -= ey;
-    } else if (f.kind == 3) {
+    } else if (GRID && f.kind == 3) {
         E.x += f.a0 * cos(t);
         E.y += f.a0 * sin(t);
     } else if (GRID && f.kind == 2) {
@@ -332,7 +332,7 @@ static __device__ __forceinline__ void eval(const FieldDev &f, double x0, double
         const float ey = (float)f.a0 * g * __builtin_amdgcn_cosf(red);
         E.y += ey;
         B.z -= ey;
-    } else if (f.kind == 3) {
+    } else if (GRID && f.kind == 3) {
         const double rev = t * (0.5 / kPi);
         const float red = (float)(rev - rint(rev));
         E.x += (float)f.a0 * __builtin_amdgcn_cosf(red);
@@ -343,6 +343,8 @@ static __device__ __forceinline__ void eval(const FieldDev &f, double x0, double
 }
 };
 
+// GRID: the general variant, with the grid and the rotating field (the plane-wave and uniform
+// models need fewer registers without them)
 template <class R, bool GRID = true>
 __device__ __forceinline__ void eval_fields(const FieldDev &f, double x0, double y0, double t, V3<R> &E, V3<R> &B)
 {

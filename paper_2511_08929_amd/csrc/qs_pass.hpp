@@ -283,9 +283,10 @@ struct LCount { unsigned prob = 0, chi = 0, norm = 0, step = 0, trans = 0; };
 
 // Main pass, one lepton: Boris push and T-BMT rotation with the fields at t, the fields at
 // t + dt, chi and the decision (NLC section); a non-emitter gets the no-transition spin update
-// (non-transition section).  Stores x, p, s.  TAU: compiled with the optical-depth decision (the
-// variant without it needs fewer registers).
-template <class R, bool TAU, bool GRID>
+// (non-transition section).  Stores x, p, s.  DEC: decision variants compiled in (bit 0: the
+// optical-depth decision, bit 1: rejection sampling; the variant with neither needs the fewest
+// registers); the step's flags choose among the compiled ones.
+template <class R, int DEC, bool GRID>
 __device__ __forceinline__ void lepton_item(const LepDev<R> &L, const FieldDev &F, const StepDev &S, const TablesDev &T,
                                             const R *lds, int64_t i, V3<R> x, V3<R> p, V3<R> s, bool &emit, bool &up,
                                             LCount &c)
@@ -303,7 +304,7 @@ __device__ __forceinline__ void lepton_item(const LepDev<R> &L, const FieldDev &
         if (d.active) {
             c.chi += d.clamped_chi;
             bool noemit_update = false;
-            if (TAU && (S.flags & F_TAU) && L.tau) {
+            if ((DEC & 1) && (S.flags & F_TAU) && L.tau) {
                 // optical depth in FP64: tau += W dt; emission at tau >= tau*, tau* = -ln(1 - u)
                 // from channel 4 (words 0,1 if no target is set yet, words 2,3 after an emission)
                 const uint4 w4 = philox_block(S.seed, lepton_id(L.species, i), S.step, 4u);
@@ -321,7 +322,7 @@ __device__ __forceinline__ void lepton_item(const LepDev<R> &L, const FieldDev &
                     if (d.P < (R)1) noemit_update = true;
                     else if (S.flags & F_NOEMIT) ++c.prob;
                 }
-            } else if (S.flags & F_REJECT) {
+            } else if ((DEC & 2) && (S.flags & F_REJECT)) {
                 // rejection (spectrum-sampling section): candidate lambda = r1^3, accepted when
                 // r2 < 3 r1^2 dW/dlambda dt with the spectrum of the lepton's spin state
                 const double r1 = (double)d.r1;
@@ -367,7 +368,7 @@ __device__ __forceinline__ void lepton_item(const LepDev<R> &L, const FieldDev &
 
 // Main pass over the lepton range [start, end) (start a multiple of 64): the wave's decisions
 // and branch choices go to mask[w] and mask[nchunks + w] of its 64-particle word w.
-template <class R, bool TAU, bool GRID>
+template <class R, int DEC, bool GRID>
 __device__ __forceinline__ void lepton_range(const LepDev<R> &L, const FieldDev &F, const StepDev &S, const TablesDev &T,
                                              const R *lds, int64_t start, int64_t end, uint64_t *mask, int64_t nchunks,
                                              LCount &c)
@@ -385,7 +386,7 @@ __device__ __forceinline__ void lepton_range(const LepDev<R> &L, const FieldDev 
         const int64_t inext = i + blockDim.x;
         if (inext < end) { xn = ldx(L.x, inext); pn = ld3(L.p, inext); sn = ld3(L.s, inext); }
         bool emit = false, up = false;
-        if (i < end) lepton_item<R, TAU, GRID>(L, F, S, T, lds, i, x, p, s, emit, up, c);
+        if (i < end) lepton_item<R, DEC, GRID>(L, F, S, T, lds, i, x, p, s, emit, up, c);
         const uint64_t m = __ballot(emit), mu = __ballot(up);
         if (lane == 0) {
             mask[base >> 6] = m;
@@ -785,6 +786,12 @@ inline bool photons_ok(const qed_photons *G)
     for (int c = 0; c < 3; ++c)
         if (!G->k[c] || !G->P[c]) return false;
     return true;
+}
+
+// field models compiled only into the general (GRID) variants: the grid and the rotating field
+inline bool general_fields(const qed_fields *f)
+{
+    return f->kind == QED_FIELD_GRID2D || f->kind == QED_FIELD_ROTATING_E;
 }
 
 inline bool fields_ok(const qed_fields *f)

@@ -83,7 +83,7 @@ struct PlanDev {
 
 // The streaming pass runs as two launches with their own register allocation: PHO = 0 over the
 // lepton segments (blocks [0, nblk_lep)), PHO = 1 over the photon segments (the rest).
-template <class R, int PHO, bool TAU, bool GRID>
+template <class R, int PHO, int DEC, bool GRID>
 __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 ? 4 : 1))) k_plan_main(const InstDev<R> *inst, PlanDev P, TablesDev T, int b_first)
 {
     extern __shared__ unsigned char smem_raw[];
@@ -116,7 +116,7 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(siz
         const int64_t B = block_len(n, sg.nb);
         const int64_t start = (int64_t)(b - sg.b0) * B, end = start + B < n ? start + B : n;
         LCount c;
-        lepton_range<R, TAU, GRID>(L, F, S, T, lds, start, end, mask, sg.nchunks, c);
+        lepton_range<R, DEC, GRID>(L, F, S, T, lds, start, end, mask, sg.nchunks, c);
         v[C_PROB] = c.prob; v[C_CHI] = c.chi; v[C_NORM] = c.norm; v[C_LSTEP] = c.step; v[kNCtr] = c.trans;
     } else {
         const PhoDev<R> G = Ip->G;
@@ -374,8 +374,8 @@ struct qed_plan_s {
     InstSeg *d_iseg;
     Snap *d_snap;
     qed_surrogate sur[2];      // learned inverse CDF per process (NULL: tables)
-    bool tau;                  // some instance decides emission by the optical depth
-    bool grid;                 // some instance uses the grid field model
+    int dec;                   // decision variants needed (bit 0: optical depth, bit 1: rejection)
+    bool grid;                 // some instance uses a field model beyond the uniform and plane-wave ones
     size_t lds;
 };
 
@@ -480,11 +480,12 @@ qed_status plan_create(qed_tables T, int n, const qed_instance *in, int ppb, int
     if (e == hipSuccess) e = hipMalloc((void **)&p->d_bctr, sizeof(uint32_t) * kNCtr * nblk);
     p->sur[0] = s_nlc;
     p->sur[1] = s_nbw;
-    p->tau = false;
+    p->dec = 0;
     p->grid = false;
     for (int i = 0; i < n; ++i) {
-        p->tau = p->tau || (in[i].params.flags & QED_OPTICAL_DEPTH);
-        p->grid = p->grid || in[i].fields.kind == QED_FIELD_GRID2D;
+        if (in[i].params.flags & QED_OPTICAL_DEPTH) p->dec |= 1;
+        if (in[i].params.flags & QED_REJECTION) p->dec |= 2;
+        p->grid = p->grid || general_fields(&in[i].fields);
     }
     if (e == hipSuccess) e = hipMemcpy(p->d_inst, inst.data(), sizeof(InstDev<R>) * n, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(p->d_seg, seg.data(), sizeof(SegDev) * seg.size(), hipMemcpyHostToDevice);
@@ -551,22 +552,28 @@ template <class R> qed_status plan_step(qed_plan p, hipStream_t st)
     P.mlp_on[0] = P.mlp_on[1] = 0;
     const InstDev<R> *inst = (const InstDev<R> *)p->d_inst;
     if (p->nblk_lep > 0) {
-        if (p->tau)
-            QS_LAUNCH(K_PLAN_LEPTON, (k_plan_main<R, 0, true, true>), dim3(p->nblk_lep), dim3(kBlock), p->lds, st, inst, P,
+        if (p->dec == 3)
+            QS_LAUNCH(K_PLAN_LEPTON, (k_plan_main<R, 0, 3, true>), dim3(p->nblk_lep), dim3(kBlock), p->lds, st, inst, P,
+                      p->T->dev, 0);
+        else if (p->dec == 2)
+            QS_LAUNCH(K_PLAN_LEPTON, (k_plan_main<R, 0, 2, true>), dim3(p->nblk_lep), dim3(kBlock), p->lds, st, inst, P,
+                      p->T->dev, 0);
+        else if (p->dec == 1)
+            QS_LAUNCH(K_PLAN_LEPTON, (k_plan_main<R, 0, 1, true>), dim3(p->nblk_lep), dim3(kBlock), p->lds, st, inst, P,
                       p->T->dev, 0);
         else if (p->grid)
-            QS_LAUNCH(K_PLAN_LEPTON, (k_plan_main<R, 0, false, true>), dim3(p->nblk_lep), dim3(kBlock), p->lds, st, inst, P,
+            QS_LAUNCH(K_PLAN_LEPTON, (k_plan_main<R, 0, 0, true>), dim3(p->nblk_lep), dim3(kBlock), p->lds, st, inst, P,
                       p->T->dev, 0);
         else
-            QS_LAUNCH(K_PLAN_LEPTON, (k_plan_main<R, 0, false, false>), dim3(p->nblk_lep), dim3(kBlock), p->lds, st, inst, P,
+            QS_LAUNCH(K_PLAN_LEPTON, (k_plan_main<R, 0, 0, false>), dim3(p->nblk_lep), dim3(kBlock), p->lds, st, inst, P,
                       p->T->dev, 0);
     }
     if (p->nblk > p->nblk_lep) {
         if (p->grid)
-            QS_LAUNCH(K_PLAN_PHOTON, (k_plan_main<R, 1, false, true>), dim3(p->nblk - p->nblk_lep), dim3(kBlock), p->lds, st,
+            QS_LAUNCH(K_PLAN_PHOTON, (k_plan_main<R, 1, 0, true>), dim3(p->nblk - p->nblk_lep), dim3(kBlock), p->lds, st,
                       inst, P, p->T->dev, p->nblk_lep);
         else
-            QS_LAUNCH(K_PLAN_PHOTON, (k_plan_main<R, 1, false, false>), dim3(p->nblk - p->nblk_lep), dim3(kBlock), p->lds, st,
+            QS_LAUNCH(K_PLAN_PHOTON, (k_plan_main<R, 1, 0, false>), dim3(p->nblk - p->nblk_lep), dim3(kBlock), p->lds, st,
                       inst, P, p->T->dev, p->nblk_lep);
     }
     // processing, with the bookkeeping; a process with a learned inverse CDF evaluates it in the

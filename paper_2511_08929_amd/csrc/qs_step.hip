@@ -36,7 +36,7 @@ __global__ void __launch_bounds__(kBlock) k_push(LepDev<R> L, FieldDev F, StepDe
     }
 }
 
-template <class R, bool TAU, bool GRID>
+template <class R, int DEC, bool GRID>
 __global__ void __launch_bounds__(kBlock) k_lepton_main(LepDev<R> L, FieldDev F, StepDev S0, TablesDev T,
                                                         uint64_t *mask, int64_t nchunks, uint32_t *bctr, uint32_t *bcnt)
 {
@@ -48,7 +48,7 @@ __global__ void __launch_bounds__(kBlock) k_lepton_main(LepDev<R> L, FieldDev F,
     const int64_t B = block_len(n, gridDim.x);
     const int64_t start = (int64_t)blockIdx.x * B, end = start + B < n ? start + B : n;
     LCount c;
-    lepton_range<R, TAU, GRID>(L, F, S, T, lds, start, end, mask, nchunks, c);
+    lepton_range<R, DEC, GRID>(L, F, S, T, lds, start, end, mask, nchunks, c);
     unsigned v[kNCtr + 1] = {};
     v[C_PROB] = c.prob; v[C_CHI] = c.chi; v[C_NORM] = c.norm; v[C_LSTEP] = c.step; v[kNCtr] = c.trans;
     __shared__ unsigned tot[kNCtr + 1];
@@ -309,15 +309,18 @@ qed_status emit_impl(qed_tables T, const qed_leptons *L, const qed_fields *f, co
     unsigned long long *c = (unsigned long long *)ctr;
     const size_t lds_nlc = sizeof(R) * 2 * T->dev.n_chi[0];
     const int g = grid_for(L->capacity);
-    const bool grid = f->kind == QED_FIELD_GRID2D;
+    const bool grid = general_fields(f);
     if (p->flags & QED_OPTICAL_DEPTH)
-        QS_LAUNCH(K_LEPTON_MAIN, (k_lepton_main<R, true, true>), dim3(g), dim3(kBlock), lds_nlc, st, ld, fd, sd, T->dev,
+        QS_LAUNCH(K_LEPTON_MAIN, (k_lepton_main<R, 1, true>), dim3(g), dim3(kBlock), lds_nlc, st, ld, fd, sd, T->dev,
+                  w.mask, nch, w.bctr, w.bcnt);
+    else if (p->flags & QED_REJECTION)
+        QS_LAUNCH(K_LEPTON_MAIN, (k_lepton_main<R, 2, true>), dim3(g), dim3(kBlock), lds_nlc, st, ld, fd, sd, T->dev,
                   w.mask, nch, w.bctr, w.bcnt);
     else if (grid)
-        QS_LAUNCH(K_LEPTON_MAIN, (k_lepton_main<R, false, true>), dim3(g), dim3(kBlock), lds_nlc, st, ld, fd, sd, T->dev,
+        QS_LAUNCH(K_LEPTON_MAIN, (k_lepton_main<R, 0, true>), dim3(g), dim3(kBlock), lds_nlc, st, ld, fd, sd, T->dev,
                   w.mask, nch, w.bctr, w.bcnt);
     else
-        QS_LAUNCH(K_LEPTON_MAIN, (k_lepton_main<R, false, false>), dim3(g), dim3(kBlock), lds_nlc, st, ld, fd, sd, T->dev,
+        QS_LAUNCH(K_LEPTON_MAIN, (k_lepton_main<R, 0, false>), dim3(g), dim3(kBlock), lds_nlc, st, ld, fd, sd, T->dev,
                   w.mask, nch, w.bctr, w.bcnt);
     const PhoDev<R> gd = pho_dev<R>((p->flags & QED_EMIT) ? G : nullptr);
     QS_LAUNCH(K_MASK_EXPAND, k_expand, dim3(g), dim3(kBlock), 0, st, (const uint64_t *)w.mask, (const uint32_t *)w.bcnt,
@@ -341,7 +344,7 @@ qed_status pair_impl(qed_tables T, const qed_photons *G, const qed_fields *f, co
     unsigned long long *c = (unsigned long long *)ctr;
     const size_t lds_nbw = sizeof(R) * 2 * T->dev.n_chi[1];
     const int g = grid_for(G->capacity);
-    if (f->kind == QED_FIELD_GRID2D)
+    if (general_fields(f))
         QS_LAUNCH(K_PHOTON_MAIN, (k_photon_main<R, true>), dim3(g), dim3(kBlock), lds_nbw, st, gd, fd, sd, T->dev, w.mask,
                   nch, w.bctr, w.bcnt);
     else
