@@ -209,8 +209,6 @@ MlpDev qs_surrogate_view(const qed_surrogate_s *s) { return mlp_dev(s); }
 int qs_surrogate_process(const qed_surrogate_s *s) { return s->proc; }
 const qed_tables_s *qs_surrogate_tables(const qed_surrogate_s *s) { return s->T; }
 
-// the learned nu of the transitions with global ranks [gpre[b_lo], gpre[b_hi]) of a plan step
-
 extern "C" int64_t qed_surrogate_n_params(void) { return kNP; }
 
 extern "C" qed_status qed_surrogate_create(qed_tables T, int process, uint64_t seed, qed_surrogate *out)

@@ -17,9 +17,9 @@ std::vector<Rec> g_recs;
 std::vector<hipEvent_t> g_pool;
 hipEvent_t g_open = nullptr;
 
-const char *const kNames[K_NKERNELS] = {"table_build", "push", "lepton_main", "emit_process", "photon_main",
-                                        "pair_process", "mask_reduce", "book", "expand", "clock",
-                                        "alive_mask", "gather", "scatter_back", "plan_lepton", "plan_photon", "plan_process", "surrogate"};
+const char *const kNames[K_NKERNELS] = {"table_build", "push",       "lepton_main", "emit_process", "photon_main",
+                                        "pair_process", "expand",    "clock",       "alive_mask",   "gather",
+                                        "scatter_back", "plan_lepton", "plan_photon", "plan_process"};
 
 hipEvent_t take()
 {
