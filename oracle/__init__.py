@@ -35,6 +35,8 @@ F_SPIN, F_NOEMIT, F_PHOTON_POL, F_MEAN = 1 << 4, 1 << 5, 1 << 6, 1 << 7
 F_PAIR, F_NOPAIR, F_PAIR_SPIN = 1 << 8, 1 << 9, 1 << 10
 F_TAU = 1 << 11
 F_REJECT = 1 << 12
+F_GCHI = 1 << 13
+GF_N, GF_LNCHI0, GF_DLNCHI = 705, -16.11809565095832, 0.03597789207803197
 F_ALL = (F_PUSH | F_TBMT | F_EMIT | F_RECOIL | F_SPIN | F_NOEMIT | F_PHOTON_POL
          | F_PAIR | F_NOPAIR | F_PAIR_SPIN)
 
@@ -63,7 +65,7 @@ class TableSpec(C.Structure):
 
 class Tables(C.Structure):
     _fields_ = [("spec", TableSpec), ("lnrate", C.POINTER(C.c_double)), ("nu", C.POINTER(C.c_double)),
-                ("off_rate", C.c_int64 * 4), ("off_nu", C.c_int64 * 4)]
+                ("off_rate", C.c_int64 * 4), ("off_nu", C.c_int64 * 4), ("lngfac", C.POINTER(C.c_double))]
 
 
 class Fields(C.Structure):
@@ -125,12 +127,15 @@ def lib():
         L.orc_ccdf.argtypes = [i, d, d]; L.orc_ccdf.restype = d
         L.orc_icdf_nu.argtypes = [i, d, d]; L.orc_icdf_nu.restype = d
         L.orc_tables_build.argtypes = [C.POINTER(Tables), C.POINTER(TableSpec), i]
-        L.orc_tables_load.argtypes = [C.POINTER(Tables), C.POINTER(TableSpec), DP, DP]
+        L.orc_tables_load.argtypes = [C.POINTER(Tables), C.POINTER(TableSpec), DP, DP, DP]
         L.orc_tables_free.argtypes = [C.POINTER(Tables)]
         L.orc_table_lnrate.argtypes = [C.POINTER(Tables), i, d]; L.orc_table_lnrate.restype = d
         L.orc_table_nu.argtypes = [C.POINTER(Tables), i, d, d]; L.orc_table_nu.restype = d
         L.orc_fields_eval.argtypes = [C.POINTER(Fields), DP, d, DP, DP]
-        L.orc_push_one.argtypes = [i, d, DP, DP, d, u32, DP, DP, DP]
+        L.orc_push_one.argtypes = [i, d, DP, DP, d, u32, C.POINTER(Tables), d, DP, DP, DP]
+        L.orc_scorer_gi.argtypes = [d]; L.orc_scorer_gi.restype = d
+        L.orc_gfactor_ratio.argtypes = [d]; L.orc_gfactor_ratio.restype = d
+        L.orc_table_gfac.argtypes = [C.POINTER(Tables), d]; L.orc_table_gfac.restype = d
         L.orc_lepton_step.argtypes = [C.POINTER(Tables), C.POINTER(Params), C.POINTER(Fields),
                                       C.POINTER(Leptons), C.POINTER(Photons), C.POINTER(Counters), i]
         L.orc_photon_step.argtypes = [C.POINTER(Tables), C.POINTER(Params), C.POINTER(Fields),
@@ -256,12 +261,27 @@ def P_to_stokes(P, e, b, k):
     return xi
 
 
-def push_one(charge, a_e, E, B, dt, flags, p, s, x):
+def push_one(charge, a_e, E, B, dt, flags, p, s, x, tables=None, eps_r=0.0):
+    """One push; with F_GCHI the anomalous moment a_e a(chi)/a(0) comes from `tables`
+    (an OracleTables) at the mid-step chi (eps_r needed)."""
     E, pE = _v(E); B, pB = _v(B)
     p = np.array(p, dtype=np.float64); s = np.array(s, dtype=np.float64); x = np.array(x, dtype=np.float64)
-    lib().orc_push_one(charge, a_e, pE, pB, dt, flags, p.ctypes.data_as(DP), s.ctypes.data_as(DP),
+    if (flags & F_GCHI) and tables is None:
+        raise ValueError("F_GCHI needs the oracle tables")
+    T = C.byref(tables.struct) if tables is not None else None
+    lib().orc_push_one(charge, a_e, pE, pB, dt, flags, T, eps_r, p.ctypes.data_as(DP), s.ctypes.data_as(DP),
                        x.ctypes.data_as(DP))
     return p, s, x
+
+
+def scorer_gi(z):
+    """Scorer function Gi(z), z >= 0 (loop appendix)."""
+    return lib().orc_scorer_gi(z)
+
+
+def gfactor_ratio(chi):
+    """a(chi)/a(0) of the field-dependent anomalous moment, by direct quadrature."""
+    return lib().orc_gfactor_ratio(chi)
 
 
 # ---------------------------------------------------------------- tables
@@ -296,19 +316,20 @@ class OracleTables:
         ss = _spec_struct(self.spec)
         if cache and path.exists():
             z = np.load(path)
-            self._lnrate, self._nu = z["lnrate"], z["nu"]
+            self._lnrate, self._nu, self._lngfac = z["lnrate"], z["nu"], z["lngfac"]
             lib().orc_tables_load(C.byref(self.struct), C.byref(ss), self._lnrate.ctypes.data_as(DP),
-                                  self._nu.ctypes.data_as(DP))
+                                  self._nu.ctypes.data_as(DP), self._lngfac.ctypes.data_as(DP))
         else:
             lib().orc_tables_build(C.byref(self.struct), C.byref(ss), nthreads)
             nr = sum(self.n_chi(c) for c in range(4))
             nv = nr * self.spec["n_rho"]
             self._lnrate = np.ctypeslib.as_array(self.struct.lnrate, shape=(nr,)).copy()
             self._nu = np.ctypeslib.as_array(self.struct.nu, shape=(nv,)).copy()
+            self._lngfac = np.ctypeslib.as_array(self.struct.lngfac, shape=(GF_N,)).copy()
             if cache:
                 CACHE.mkdir(parents=True, exist_ok=True)
                 tmp = path.with_suffix(".tmp.npz")
-                np.savez(tmp, lnrate=self._lnrate, nu=self._nu)
+                np.savez(tmp, lnrate=self._lnrate, nu=self._nu, lngfac=self._lngfac)
                 os.replace(tmp, path)
 
     def n_chi(self, ch):
@@ -327,6 +348,14 @@ class OracleTables:
 
     def nu(self, ch, lnchi, rho):
         return lib().orc_table_nu(C.byref(self.struct), ch, lnchi, rho)
+
+    def lngfac_nodes(self):
+        """ln(a(chi)/a(0)) at ln chi = GF_LNCHI0 + i GF_DLNCHI, i < GF_N."""
+        return self._lngfac
+
+    def gfac(self, chi):
+        """a(chi)/a(0) interpolated from the table."""
+        return lib().orc_table_gfac(C.byref(self.struct), chi)
 
     def __del__(self):
         try:

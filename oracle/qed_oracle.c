@@ -35,6 +35,13 @@
  *      words 2,3 after an emission, when tau restarts at 0).  The up/down branch is then
  *      r1 < a/P with the step's r1; without emission the no-transition update is the same as
  *      with the per-step draw, applied only while W dt < 1 (otherwise skipped and counted).
+ *  R11 Field-dependent g (loop appendix): the Scorer-function term of the one-loop
+ *      self-energy is taken as the anomalous moment a(chi) of the T-BMT equation, with
+ *      a(chi)/a(0) = 2 pi int_0^inf du/(1+u)^3 z Gi(z), z = (u/chi)^(2/3) (the standard one-loop
+ *      form; the appendix's own prefactors are garbled).  chi is taken at the Boris mid step
+ *      (momentum (u- + u+)/2, energy gamma-), and the ratio is tabulated like the rates: ln of it
+ *      at 64 nodes per decade of chi from 1e-7 to 1e4, 4-point Lagrange in ln chi; 1 below,
+ *      the chi^(-2/3) law above.
  */
 #include "qed_oracle.h"
 
@@ -580,6 +587,16 @@ static void alloc_tables(orc_tables *T, const orc_table_spec *spec)
     }
     T->lnrate = (double *)calloc(r, sizeof(double));
     T->nu = (double *)calloc(v, sizeof(double));
+    T->lngfac = (double *)calloc(ORC_GF_N, sizeof(double));
+}
+
+static void gfac_build(orc_tables *T, int nthreads)
+{
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#pragma omp parallel for schedule(dynamic, 8)
+#endif
+    for (int i = 0; i < ORC_GF_N; ++i) T->lngfac[i] = log(orc_gfactor_ratio(exp(ORC_GF_LNCHI0 + i * ORC_GF_DLNCHI)));
 }
 
 int orc_tables_build(orc_tables *T, const orc_table_spec *spec, int nthreads)
@@ -604,23 +621,27 @@ int orc_tables_build(orc_tables *T, const orc_table_spec *spec, int nthreads)
         for (int j = 0; j < spec->n_rho; ++j) row[j] = icdf_ctx(&C, spec->rho0 + j * spec->drho);
         cdf_free(&C);
     }
+    gfac_build(T, nthreads);
     return 0;
 }
 
-int orc_tables_load(orc_tables *T, const orc_table_spec *spec, const double *lnrate, const double *nu)
+int orc_tables_load(orc_tables *T, const orc_table_spec *spec, const double *lnrate, const double *nu,
+                    const double *lngfac)
 {
     alloc_tables(T, spec);
     int64_t nr = T->off_rate[3] + nchi_of(spec, 3);
     int64_t nv = T->off_nu[3] + (int64_t)nchi_of(spec, 3) * spec->n_rho;
     memcpy(T->lnrate, lnrate, sizeof(double) * nr);
     memcpy(T->nu, nu, sizeof(double) * nv);
+    if (lngfac) memcpy(T->lngfac, lngfac, sizeof(double) * ORC_GF_N);
+    else gfac_build(T, 0);
     return 0;
 }
 
 void orc_tables_free(orc_tables *T)
 {
-    free(T->lnrate); free(T->nu);
-    T->lnrate = T->nu = NULL;
+    free(T->lnrate); free(T->nu); free(T->lngfac);
+    T->lnrate = T->nu = T->lngfac = NULL;
 }
 
 /* 4-point Lagrange weights on nodes v0 + i h (i = 0..n-1), one-sided at the ends */
@@ -661,6 +682,87 @@ double orc_table_nu(const orc_tables *T, int ch, double lnchi, double rho)
         acc += Lc[a] * (Lr[0] * row[0] + Lr[1] * row[1] + Lr[2] * row[2] + Lr[3] * row[3]);
     }
     return acc;
+}
+
+/* ====================================================================== */
+/* Field-dependent anomalous magnetic moment (loop appendix).  The Scorer-  */
+/* function term of the one-loop self-energy rotates the spin like an      */
+/* anomalous moment a(chi) that falls from Schwinger's alpha/(2 pi) at     */
+/* chi -> 0; written through the Airy-Scorer integral of the appendix,     */
+/*   a(chi) = alpha int_0^inf du/(1+u)^3 z Gi(z),  z = (u/chi)^(2/3),     */
+/* i.e. a(chi)/a(0) = 2 pi int_0^inf du/(1+u)^3 z Gi(z).                   */
+/* ====================================================================== */
+/* Gi(z) for z >= 0.  From Ai + i Gi = (1/pi) int_0^inf exp(i(z t + t^3/3)) dt, turned onto the ray
+   t = exp(i pi/6) s (the arc at infinity vanishes in that sector):
+     Gi(z) = (1/pi) int_0^inf exp(-s^3/3 - z s/2) sin((sqrt3/2) z s + pi/6) ds,
+   by 20-point Gauss-Legendre panels of width at most 1/(1+z) up to where the exponent reaches -45.
+   For z > 20 the large-argument expansion Gi = (1/(pi z)) sum_k (3k)!/(k! (3 z^3)^k), ten terms
+   (remainder below 1e-18 relative there). */
+double orc_scorer_gi(double z)
+{
+    if (z > 20.0) {
+        double x = 1.0 / (3.0 * z * z * z), term = 1.0, sum = 1.0;
+        for (int k = 1; k <= 10; ++k) {
+            term *= (3.0 * k) * (3.0 * k - 1.0) * (3.0 * k - 2.0) / k * x;   /* (3k)!/k! x^k */
+            sum += term;
+        }
+        return sum / (ORC_PI * z);
+    }
+    double send = 0.0;                      /* root of s^3/3 + z s/2 = 45 by bisection */
+    {
+        double lo = 0.0, hi = 10.0;
+        for (int it = 0; it < 200; ++it) {
+            double mid = 0.5 * (lo + hi);
+            if (mid * mid * mid / 3.0 + 0.5 * z * mid < 45.0) lo = mid; else hi = mid;
+        }
+        send = hi;
+    }
+    double wmax = 1.0 / (1.0 + z);
+    int np = (int)ceil(send / wmax);
+    double w = send / np, acc = 0.0;
+    for (int k = 0; k < np; ++k) {
+        double mid = (k + 0.5) * w, half = 0.5 * w, ps = 0.0;
+        for (int i = 0; i < NGL; ++i) {
+            double s = mid + half * gl_x[i];
+            ps += gl_w[i] * exp(-s * s * s / 3.0 - 0.5 * z * s) * sin(0.5 * sqrt(3.0) * z * s + ORC_PI / 6.0);
+        }
+        acc += half * ps;
+    }
+    return acc / ORC_PI;
+}
+
+/* a(chi)/a(0) = 2 pi int dv e^v/(1+e^v)^3 z Gi(z), u = e^v, z = exp(2 (v - ln chi)/3), by the
+   trapezoidal rule in v with step 0.2 on [min(ln chi, 0) - 40, 25].  The integrand is analytic in
+   |Im v| < pi/2 and decays exponentially at both ends (as e^(5v/3) and e^(-2v)), so the rule's
+   error is of order exp(-pi^2/0.2), far below rounding. */
+double orc_gfactor_ratio(double chi)
+{
+    if (!(chi > 0.0)) return 1.0;
+    double lc = log(chi), vlo = (lc < 0.0 ? lc : 0.0) - 40.0, vhi = 25.0, h = 0.2, acc = 0.0;
+    int n = (int)ceil((vhi - vlo) / h);
+    for (int k = 0; k <= n; ++k) {
+        double v = vlo + k * h, u = exp(v), z = exp(2.0 * (v - lc) / 3.0);
+        double f = u / ((1.0 + u) * (1.0 + u) * (1.0 + u)) * z * orc_scorer_gi(z);
+        acc += (k == 0 || k == n) ? 0.5 * f : f;
+    }
+    return 2.0 * ORC_PI * h * acc;
+}
+
+/* Table: 4-point Lagrange in ln chi of ln(a/a(0)) on the nodes ORC_GF_LNCHI0 + i ORC_GF_DLNCHI.
+   Below the first node (chi < 1e-7, where 1 - a/a(0) < 2e-12) the ratio is 1; beyond the last
+   (chi > 1e4) it follows the large-chi law a ~ chi^(-2/3) from the last node. */
+double orc_table_gfac(const orc_tables *T, double chi)
+{
+    if (!(chi > 0.0)) return 1.0;
+    double lc = log(chi);
+    if (lc < ORC_GF_LNCHI0) return 1.0;
+    double lnlast = ORC_GF_LNCHI0 + (ORC_GF_N - 1) * ORC_GF_DLNCHI;
+    if (lc > lnlast) return exp(T->lngfac[ORC_GF_N - 1] - (2.0 / 3.0) * (lc - lnlast));
+    int i0;
+    double L[4];
+    lagrange4(lc, ORC_GF_LNCHI0, ORC_GF_DLNCHI, ORC_GF_N, &i0, L);
+    const double *g = T->lngfac + i0;
+    return exp(L[0] * g[0] + L[1] * g[1] + L[2] * g[2] + L[3] * g[3]);
 }
 
 /* ====================================================================== */
@@ -779,7 +881,7 @@ static void cayley(double v[3], const double t[3])
 }
 
 void orc_push_one(int q, double a_e, const double E[3], const double B[3], double dt,
-                  uint32_t flags, double p[3], double s[3], double x[3])
+                  uint32_t flags, const orc_tables *T, double eps_r, double p[3], double s[3], double x[3])
 {
     double um[3], up[3], t[3];
     for (int i = 0; i < 3; ++i) um[i] = p[i] + 0.5 * q * dt * E[i];
@@ -792,6 +894,15 @@ void orc_push_one(int q, double a_e, const double E[3], const double B[3], doubl
         for (int i = 0; i < 3; ++i) be[i] = 0.5 * (um[i] + up[i]) / gm;
         cross3(be, E, bxE);
         double bB = dot3(be, B);
+        if (flags & ORC_F_GCHI) {
+            /* chi at the mid step: momentum u = (u- + u+)/2, energy gamma- */
+            double u[3], uxB[3], F[3];
+            for (int i = 0; i < 3; ++i) u[i] = 0.5 * (um[i] + up[i]);
+            cross3(u, B, uxB);
+            for (int i = 0; i < 3; ++i) F[i] = gm * E[i] + uxB[i];
+            double uE = dot3(u, E), rad = dot3(F, F) - uE * uE;
+            a_e *= orc_table_gfac(T, eps_r * sqrt(rad > 0.0 ? rad : 0.0));
+        }
         for (int i = 0; i < 3; ++i)
             Om[i] = -q * ((a_e + 1.0 / gm) * B[i] - (a_e * gm / (gm + 1.0)) * bB * be[i]
                           - (a_e + 1.0 / (gm + 1.0)) * bxE[i]);
@@ -1106,7 +1217,7 @@ int orc_lepton_step(const orc_tables *T, const orc_params *prm, const orc_fields
             double E[3], B[3];
             if (prm->flags & ORC_F_PUSH) {
                 orc_fields_eval(f, x, prm->t, E, B);
-                orc_push_one(q, prm->a_e, E, B, prm->dt, prm->flags, p, s, x);
+                orc_push_one(q, prm->a_e, E, B, prm->dt, prm->flags, T, prm->eps_r, p, s, x);
             }
             orc_fields_eval(f, x, prm->t + prm->dt, E, B);
             int64_t idx = L->index ? L->index[j] : j;

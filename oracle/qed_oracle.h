@@ -60,11 +60,14 @@ typedef struct {
     double *lnrate;         /* [4][n_chi(channel)] : ln int spectrum */
     double *nu;             /* [4][n_chi(channel)][n_rho] */
     int64_t off_rate[4], off_nu[4];
+    double *lngfac;         /* [ORC_GF_N]: ln(a(chi)/a(0)) at ln chi = ORC_GF_LNCHI0 + i ORC_GF_DLNCHI */
 } orc_tables;
 
 int    orc_tables_build(orc_tables *T, const orc_table_spec *spec, int nthreads);
 void   orc_tables_free(orc_tables *T);
-int    orc_tables_load(orc_tables *T, const orc_table_spec *spec, const double *lnrate, const double *nu);
+/* lngfac may be NULL: the g-factor table is then built here */
+int    orc_tables_load(orc_tables *T, const orc_table_spec *spec, const double *lnrate, const double *nu,
+                       const double *lngfac);
 double orc_table_lnrate(const orc_tables *T, int channel, double lnchi);
 double orc_table_nu(const orc_tables *T, int channel, double lnchi, double rho);
 
@@ -89,9 +92,11 @@ enum {
     ORC_F_SPIN = 1u << 4, ORC_F_NOEMIT = 1u << 5, ORC_F_PHOTON_POL = 1u << 6, ORC_F_MEAN = 1u << 7,
     ORC_F_PAIR = 1u << 8, ORC_F_NOPAIR = 1u << 9, ORC_F_PAIR_SPIN = 1u << 10,
     ORC_F_TAU = 1u << 11,    /* emission decided by the optical depth instead of the per-step draw */
-    ORC_F_REJECT = 1u << 12  /* emission decided and lambda sampled together by rejection from the
+    ORC_F_REJECT = 1u << 12, /* emission decided and lambda sampled together by rejection from the
                                 spin-resolved spectrum with candidates lambda = r1^3 (spectrum-sampling
                                 section), instead of the draw against W dt and the inverse CDF */
+    ORC_F_GCHI = 1u << 13    /* T-BMT with the field-dependent anomalous moment a_e a(chi)/a(0)
+                                (loop appendix) instead of the constant a_e */
 };
 
 typedef struct {
@@ -126,9 +131,19 @@ typedef struct {
             n_capacity_overflow, n_retired, n_near_threshold, n_lepton_steps, n_photon_steps;
 } orc_counters;
 
-/* Lorentz (Boris) push + T-BMT rotation + position advance for one lepton. */
+/* Lorentz (Boris) push + T-BMT rotation + position advance for one lepton.  With ORC_F_GCHI the
+   anomalous moment is a_e times the tabulated a(chi)/a(0) at the mid-step chi (T and eps_r
+   needed then; otherwise T may be NULL). */
 void orc_push_one(int charge, double a_e, const double E[3], const double B[3], double dt,
-                  uint32_t flags, double p[3], double s[3], double x[3]);
+                  uint32_t flags, const orc_tables *T, double eps_r, double p[3], double s[3], double x[3]);
+
+/* Field-dependent anomalous moment (loop appendix). */
+double orc_scorer_gi(double z);              /* Scorer function Gi(z), z >= 0 */
+double orc_gfactor_ratio(double chi);        /* a(chi)/a(0) by direct quadrature */
+double orc_table_gfac(const orc_tables *T, double chi);   /* the same from the table */
+#define ORC_GF_N 705                         /* chi from 1e-7 to 1e4, 64 nodes per decade */
+#define ORC_GF_LNCHI0 (-16.11809565095832)   /* ln 1e-7 */
+#define ORC_GF_DLNCHI (0.03597789207803197)  /* ln 10 / 64 */
 
 /* One whole lepton step (push with fields at t, QED with fields at t+dt) over L. */
 int orc_lepton_step(const orc_tables *T, const orc_params *prm, const orc_fields *f,
