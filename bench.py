@@ -276,7 +276,8 @@ def extras(q, args, w, t32, t64, out, v32, v64):
     wsub = synth.subsample(w, np.arange(min(w.n, 100_000)))
     steps_e = min(args.steps, 2000)
     ref = spectra(q, t64, wsub, steps_e)
-    e32 = spectrum_error(ref, spectra(q, t32, wsub, steps_e))
+    sp32 = spectra(q, t32, wsub, steps_e)
+    e32 = spectrum_error(ref, sp32)
     esu = spectrum_error(ref, spectra(q, t32, wsub, steps_e, surrogates=(sn, sb)))
     log(f"error vs fp64: fp32 {e32}; learned inverse CDF {esu}")
     sur["error_vs_fp64"] = esu
@@ -293,6 +294,21 @@ def extras(q, args, w, t32, t64, out, v32, v64):
                         "photons_emitted": cr["n_emit"], "error_vs_fp64": er}
     if v64:
         out["rejection"]["speedup_vs_fp64"] = round(vr / v64, 3)
+    # field-dependent anomalous moment in the T-BMT push: throughput, and the shift of the
+    # electrons' mean spin against the constant moment on the same draws
+    gflags = q.QED_ALL | q.QED_G_CHI
+    rg = run_gpu(q, t32, w, args.steps, args.warmup, args.compact_every, profile=False, graph=True, ppb=args.ppb,
+                 flags=gflags)
+    cg = rg["ctr"]
+    vg = (cg["n_lepton_steps"] + cg["n_photon_steps"]) / rg["wall"]
+    sg = spectra(q, t32, wsub, steps_e, flags=gflags)
+    shift = [round(float(v), 6) for v in sg["s_mean"] - sp32["s_mean"]]
+    log(f"fp32 field-dependent g (graph): {rg['wall']:.3f} s, {vg:.4g}/s; mean-spin shift {shift}")
+    out["g_chi"] = {"value": round(vg, 1), "unit": "particle-QED-steps/s", "flags": "QED_ALL | QED_G_CHI",
+                    "mean_spin": [round(float(v), 6) for v in sg["s_mean"]],
+                    "mean_spin_shift_vs_constant_moment": shift}
+    if v64:
+        out["g_chi"]["speedup_vs_fp64"] = round(vg / v64, 3)
     out["fp32_error_vs_fp64"] = e32
     out["error_workload"] = f"first {wsub.n} electrons of the same collision, {steps_e} steps, every photon kept"
     out["surrogate"] = sur

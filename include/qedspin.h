@@ -75,11 +75,19 @@ enum {
     QED_OPTICAL_DEPTH = 1u << 11, /* emission decided by the optical depth (decision-making overview):
                                   tau += W dt in FP64, emission when tau >= tau* = -ln(1 - u), u from
                                   Philox channel 4; the leptons' tau / tau_target arrays are required */
-    QED_REJECTION = 1u << 12   /* emission decided and lambda sampled together by rejection
+    QED_REJECTION = 1u << 12,  /* emission decided and lambda sampled together by rejection
                                   (spectrum-sampling section): the candidate lambda = r1^3 is accepted
                                   when r2 < 3 r1^2 dW/dlambda dt, dW/dlambda the spectrum of the
                                   lepton's spin state; no inverse-CDF table is read for the emission.
                                   Not with QED_OPTICAL_DEPTH (QED_ERR_INVALID) */
+    QED_G_CHI = 1u << 13       /* T-BMT with the field-dependent anomalous moment (loop appendix: the
+                                  Scorer-function term of the one-loop self-energy): a_e is scaled by
+                                  a(chi)/a(0) = 2 pi int_0^inf du/(1+u)^3 z Gi(z), z = (u/chi)^(2/3),
+                                  at the Boris mid-step chi (momentum (u- + u+)/2, energy gamma-),
+                                  from a table built by qed_init_tables: ln a(chi)/a(0) at 64 nodes per
+                                  decade of chi from 1e-7 to 1e4, 4-point Lagrange in ln chi; 1 below
+                                  chi = 1e-7, the chi^(-2/3) law above 1e4.  a_e = alpha/(2 pi) gives
+                                  the one-loop moment, a_e = 0 keeps g = 2 */
 };
 
 /* Field models evaluated at each particle. */
@@ -189,6 +197,11 @@ qed_status qed_init_tables(const qed_table_params *params, qed_stream stream, qe
 /* Text of the HIP error behind the most recent QED_ERR_HIP returned on this thread
    ("" if none).  The string is owned by the library. */
 const char *qed_last_error(void);
+
+/* Copy the g-factor table of QED_G_CHI to host memory: ln(a(chi)/a(0)) at ln chi = ln 1e-7 +
+   i ln(10)/64, i < *n (705).  Either pointer may be NULL (then that part is skipped); host
+   pointers, synchronous. */
+qed_status qed_tables_download_gfac(qed_tables tables, double *lngfac, int64_t *n);
 
 /* Release the tables (device memory).  Safe on NULL. */
 qed_status qed_free_tables(qed_tables tables);

@@ -28,11 +28,13 @@ QED_SPIN, QED_NOEMIT, QED_PHOTON_POL, QED_MEAN = 1 << 4, 1 << 5, 1 << 6, 1 << 7
 QED_PAIR, QED_NOPAIR, QED_PAIR_SPIN = 1 << 8, 1 << 9, 1 << 10
 QED_OPTICAL_DEPTH = 1 << 11
 QED_REJECTION = 1 << 12
+QED_G_CHI = 1 << 13
 QED_ALL = (QED_PUSH | QED_TBMT | QED_EMIT | QED_RECOIL | QED_SPIN | QED_NOEMIT | QED_PHOTON_POL
            | QED_PAIR | QED_NOPAIR | QED_PAIR_SPIN)
 QED_FIELD_UNIFORM, QED_FIELD_PLANE_LP, QED_FIELD_GRID2D, QED_FIELD_ROTATING_E = 0, 1, 2, 3
 
-ABI_SYMBOLS = ("qed_init_tables", "qed_last_error", "qed_free_tables", "qed_tables_download", "qed_workspace_size",
+ABI_SYMBOLS = ("qed_init_tables", "qed_last_error", "qed_free_tables", "qed_tables_download",
+               "qed_tables_download_gfac", "qed_workspace_size",
                "qed_push_spin", "qed_emit", "qed_pair", "qed_compact_workspace_size", "qed_compact",
                "qed_profile_start", "qed_profile_stop", "qed_clock_advance", "qed_plan_create", "qed_plan_step",
                "qed_plan_blocks", "qed_plan_destroy", "qed_surrogate_n_params", "qed_surrogate_create",
@@ -115,6 +117,7 @@ def lib():
         L.qed_last_error.argtypes = []
         L.qed_last_error.restype = C.c_char_p
         L.qed_tables_download.argtypes = [vp, vp, P(i64), vp, P(i64)]
+        L.qed_tables_download_gfac.argtypes = [vp, vp, P(i64)]
         L.qed_workspace_size.argtypes = [i64]; L.qed_workspace_size.restype = sz
         L.qed_push_spin.argtypes = [P(Leptons), P(Fields), P(StepParams), vp, vp]
         L.qed_emit.argtypes = [vp, P(Leptons), P(Fields), P(StepParams), P(Photons), vp, vp, sz, vp]
@@ -198,6 +201,15 @@ class Tables:
         _check(lib().qed_tables_download(self.handle, lnrate.ctypes.data, None, nu.ctypes.data, None),
                "qed_tables_download")
         return lnrate, nu
+
+    def download_gfac(self):
+        """ln(a(chi)/a(0)) nodes of the field-dependent anomalous moment (QED_G_CHI)."""
+        import numpy as np
+        n = C.c_int64()
+        _check(lib().qed_tables_download_gfac(self.handle, None, C.byref(n)), "qed_tables_download_gfac")
+        out = np.zeros(n.value)
+        _check(lib().qed_tables_download_gfac(self.handle, out.ctypes.data, None), "qed_tables_download_gfac")
+        return out
 
     def close(self):
         if getattr(self, "handle", None):

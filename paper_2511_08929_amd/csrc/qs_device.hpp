@@ -17,8 +17,14 @@ constexpr double kPi = 3.14159265358979323846;
 enum : uint32_t {
     F_PUSH = 1u << 0, F_TBMT = 1u << 1, F_EMIT = 1u << 2, F_RECOIL = 1u << 3, F_SPIN = 1u << 4,
     F_NOEMIT = 1u << 5, F_PHOTON_POL = 1u << 6, F_MEAN = 1u << 7, F_PAIR = 1u << 8,
-    F_NOPAIR = 1u << 9, F_PAIR_SPIN = 1u << 10, F_TAU = 1u << 11, F_REJECT = 1u << 12
+    F_NOPAIR = 1u << 9, F_PAIR_SPIN = 1u << 10, F_TAU = 1u << 11, F_REJECT = 1u << 12, F_GCHI = 1u << 13
 };
+
+// Field-dependent anomalous moment (loop appendix): table of ln(a(chi)/a(0)) at 64 nodes per
+// decade of chi from 1e-7 to 1e4 (node i at ln chi = kGfLnChi0 + i kGfDlnChi).
+constexpr int kGfN = 705;
+constexpr double kGfLnChi0 = -16.11809565095832;   // ln 1e-7
+constexpr double kGfDlnChi = 0.03597789207803197;  // ln 10 / 64
 
 // ------------------------------------------------------------------ small vectors
 // A renormalization of |s| or |xi| is counted when the excess over 1 of the squared norm is
@@ -360,11 +366,45 @@ template <class R> __device__ __forceinline__ V3<R> cayley(V3<R> v, V3<R> t)
     return v + cross(vp, f * t);
 }
 
+// ------------------------------------------------------------------ table interpolation
+// 4-point Lagrange weights on nodes v0 + i h, i = 0..n-1 (one-sided at the ends).
+template <class R> __device__ __forceinline__ int lagrange4(R v, R v0, R h, int n, R L[4])
+{
+    R s = (v - v0) / h;
+    s = s < (R)0 ? (R)0 : s;
+    s = s > (R)(n - 1) ? (R)(n - 1) : s;
+    int i = (int)floor(s) - 1;
+    i = i < 0 ? 0 : (i > n - 4 ? n - 4 : i);
+    const R t = s - (R)i;
+    const R a = t - (R)1, b = t - (R)2, c = t - (R)3;
+    L[0] = -(a * b * c) / (R)6;
+    L[1] = (t * b * c) / (R)2;
+    L[2] = -(t * a * c) / (R)2;
+    L[3] = (t * a * b) / (R)6;
+    return i;
+}
+
+// a(chi)/a(0) from the table: 4-point Lagrange in ln chi of its logarithm; 1 below the first
+// node (chi < 1e-7), the chi^(-2/3) law from the last node above chi = 1e4.
+template <class R> __device__ __forceinline__ R gfac_ratio(const R *lng, R chi)
+{
+    if (!(chi > (R)0)) return (R)1;
+    const R lc = log_r(chi);
+    if (lc < (R)kGfLnChi0) return (R)1;
+    const R lnlast = (R)(kGfLnChi0 + (kGfN - 1) * kGfDlnChi);
+    if (lc > lnlast) return exp_r(lng[kGfN - 1] - (R)(2.0 / 3.0) * (lc - lnlast));
+    R L[4];
+    const int i = lagrange4(lc, (R)kGfLnChi0, (R)kGfDlnChi, kGfN, L);
+    return exp_r(L[0] * lng[i] + L[1] * lng[i + 1] + L[2] * lng[i + 2] + L[3] * lng[i + 3]);
+}
+
 // Boris momentum update with fields at the old position; T-BMT with the standard E-term
 // coefficient a + 1/(gamma+1), the Boris mid-step gamma and beta = (u- + u+)/(2 gamma);
-// returns the displacement p/gamma dt with the new momentum.
+// returns the displacement p/gamma dt with the new momentum.  With a g-factor table `lng` the
+// anomalous moment is a_e a(chi)/a(0), chi at the mid step (momentum (u- + u+)/2, energy gamma-).
 template <class R>
-__device__ __forceinline__ V3<R> push(int q, R a_e, V3<R> E, V3<R> B, R dt, bool tbmt, V3<R> &p, V3<R> &s)
+__device__ __forceinline__ V3<R> push(int q, R a_e, V3<R> E, V3<R> B, R dt, bool tbmt, V3<R> &p, V3<R> &s,
+                                      const R *lng = nullptr, R eps_r = (R)0)
 {
     const R hq = (R)0.5 * (R)q * dt;
     const V3<R> um = p + hq * E;
@@ -374,6 +414,12 @@ __device__ __forceinline__ V3<R> push(int q, R a_e, V3<R> E, V3<R> B, R dt, bool
         const V3<R> be = ((R)0.5 / gm) * (um + up);
         const V3<R> bxE = cross(be, E);
         const R bB = dot(be, B);
+        if (lng) {
+            const V3<R> u = (R)0.5 * (um + up);
+            const V3<R> F = gm * E + cross(u, B);
+            const R uE = dot(u, E), rad = dot(F, F) - uE * uE;
+            a_e *= gfac_ratio<R>(lng, eps_r * sqrt_r(rad > (R)0 ? rad : (R)0));
+        }
         const V3<R> Om = (R)(-q) * ((a_e + (R)1 / gm) * B - (a_e * gm / (gm + (R)1) * bB) * be -
                                     (a_e + (R)1 / (gm + (R)1)) * bxE);
         s = cayley(s, ((R)(-0.5) * dt) * Om);
@@ -412,24 +458,6 @@ __device__ __forceinline__ double basis_chi(int charge, double eps_r, V3<R> p, d
     out.e = (sgn * rsqrt_r((R)ft2)) * cvt<R>(Ft);
     out.b = cross(out.k, out.e);
     return eps_r * (double)sqrt_r((R)(rad > 0.0 ? rad : 0.0));
-}
-
-// ------------------------------------------------------------------ table interpolation
-// 4-point Lagrange weights on nodes v0 + i h, i = 0..n-1 (one-sided at the ends).
-template <class R> __device__ __forceinline__ int lagrange4(R v, R v0, R h, int n, R L[4])
-{
-    R s = (v - v0) / h;
-    s = s < (R)0 ? (R)0 : s;
-    s = s > (R)(n - 1) ? (R)(n - 1) : s;
-    int i = (int)floor(s) - 1;
-    i = i < 0 ? 0 : (i > n - 4 ? n - 4 : i);
-    const R t = s - (R)i;
-    const R a = t - (R)1, b = t - (R)2, c = t - (R)3;
-    L[0] = -(a * b * c) / (R)6;
-    L[1] = (t * b * c) / (R)2;
-    L[2] = -(t * a * c) / (R)2;
-    L[3] = (t * a * b) / (R)6;
-    return i;
 }
 
 // ------------------------------------------------------------------ P-vector <-> Stokes

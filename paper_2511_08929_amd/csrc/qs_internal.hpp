@@ -18,6 +18,8 @@ struct TablesDev {
     const double *nu;         // [sum n_chi(channel) * n_rho]
     const double *bn64;       // trapezoid nodes of the Bessel functions, FP64 levels
     const float *bn32;        // FP32 levels
+    const double *lng;        // [kGfN] ln(a(chi)/a(0)) of the field-dependent anomalous moment
+    const float *lng32;
     int off_rate[4];
     int64_t off_nu[4];
 };
@@ -30,6 +32,8 @@ struct qed_tables_s {
     double *d_nu;
     double *d_bn64;
     float *d_bn32;
+    double *d_lng;
+    float *d_lng32;
     int64_t n_rate, n_nu;
 };
 

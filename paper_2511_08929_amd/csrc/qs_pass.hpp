@@ -80,6 +80,15 @@ template <class R> __device__ __forceinline__ const R *rate_src(const TablesDev 
 template <> __device__ __forceinline__ const double *rate_src<double>(const TablesDev &T) { return T.lnrate; }
 template <> __device__ __forceinline__ const float *rate_src<float>(const TablesDev &T) { return T.lnrate32; }
 
+// the g-factor table of the push when the step asks for the field-dependent anomalous moment
+// (compiled into the general variants only), else NULL
+template <class R, bool GRID> __device__ __forceinline__ const R *gfac_src(const TablesDev &T, uint32_t flags)
+{
+    if (!GRID || !(flags & F_GCHI)) return nullptr;
+    if constexpr (sizeof(R) == 8) return (const R *)T.lng;
+    else return (const R *)T.lng32;
+}
+
 template <class R> __device__ __forceinline__ const void *bn_of(const TablesDev &T)
 {
     return sizeof(R) == 8 ? (const void *)T.bn64 : (const void *)T.bn32;
@@ -296,7 +305,8 @@ __device__ __forceinline__ void lepton_item(const LepDev<R> &L, const FieldDev &
     V3<R> E, B;
     if (S.flags & F_PUSH) {
         eval_fields<R, GRID>(F, (double)x.x, (double)x.y, S.t, E, B);
-        x = x + push<R>(q, (R)S.a_e, E, B, (R)S.dt, (S.flags & F_TBMT) != 0, p, s);
+        x = x + push<R>(q, (R)S.a_e, E, B, (R)S.dt, (S.flags & F_TBMT) != 0, p, s, gfac_src<R, GRID>(T, S.flags),
+                        (R)S.eps_r);
     }
     if (S.flags & F_EMIT) {
         eval_fields<R, GRID>(F, (double)x.x, (double)x.y, S.t + S.dt, E, B);
@@ -793,6 +803,9 @@ inline bool general_fields(const qed_fields *f)
 {
     return f->kind == QED_FIELD_GRID2D || f->kind == QED_FIELD_ROTATING_E;
 }
+
+// lepton passes that need the general variant: its field models or the field-dependent g
+inline bool general_leptons(const qed_fields *f, uint32_t flags) { return general_fields(f) || (flags & QED_G_CHI); }
 
 inline bool fields_ok(const qed_fields *f)
 {

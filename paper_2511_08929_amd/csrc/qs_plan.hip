@@ -376,6 +376,7 @@ struct qed_plan_s {
     qed_surrogate sur[2];      // learned inverse CDF per process (NULL: tables)
     int dec;                   // decision variants needed (bit 0: optical depth, bit 1: rejection)
     bool grid;                 // some instance uses a field model beyond the uniform and plane-wave ones
+    bool glep;                 // the lepton pass needs the general variant (grid, or the field-dependent g)
     size_t lds;
 };
 
@@ -482,10 +483,12 @@ qed_status plan_create(qed_tables T, int n, const qed_instance *in, int ppb, int
     p->sur[1] = s_nbw;
     p->dec = 0;
     p->grid = false;
+    p->glep = false;
     for (int i = 0; i < n; ++i) {
         if (in[i].params.flags & QED_OPTICAL_DEPTH) p->dec |= 1;
         if (in[i].params.flags & QED_REJECTION) p->dec |= 2;
         p->grid = p->grid || general_fields(&in[i].fields);
+        p->glep = p->glep || general_leptons(&in[i].fields, in[i].params.flags);
     }
     if (e == hipSuccess) e = hipMemcpy(p->d_inst, inst.data(), sizeof(InstDev<R>) * n, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(p->d_seg, seg.data(), sizeof(SegDev) * seg.size(), hipMemcpyHostToDevice);
@@ -561,7 +564,7 @@ template <class R> qed_status plan_step(qed_plan p, hipStream_t st)
         else if (p->dec == 1)
             QS_LAUNCH(K_PLAN_LEPTON, (k_plan_main<R, 0, 1, true>), dim3(p->nblk_lep), dim3(kBlock), p->lds, st, inst, P,
                       p->T->dev, 0);
-        else if (p->grid)
+        else if (p->glep)
             QS_LAUNCH(K_PLAN_LEPTON, (k_plan_main<R, 0, 0, true>), dim3(p->nblk_lep), dim3(kBlock), p->lds, st, inst, P,
                       p->T->dev, 0);
         else

@@ -20,7 +20,7 @@ using namespace qs;
 
 // ------------------------------------------------------------------ kernels: leptons
 template <class R>
-__global__ void __launch_bounds__(kBlock) k_push(LepDev<R> L, FieldDev F, StepDev S0)
+__global__ void __launch_bounds__(kBlock) k_push(LepDev<R> L, FieldDev F, StepDev S0, TablesDev T)
 {
     const StepDev S = localize(S0);
     const int64_t n = *L.count;
@@ -29,7 +29,8 @@ __global__ void __launch_bounds__(kBlock) k_push(LepDev<R> L, FieldDev F, StepDe
         V3<R> x = ldx(L.x, i), p = ld3(L.p, i), s = ld3(L.s, i);
         V3<R> E, B;
         eval_fields<R, true>(F, (double)x.x, (double)x.y, S.t, E, B);
-        const V3<R> d = push<R>(q, (R)S.a_e, E, B, (R)S.dt, (S.flags & F_TBMT) != 0, p, s);
+        const V3<R> d = push<R>(q, (R)S.a_e, E, B, (R)S.dt, (S.flags & F_TBMT) != 0, p, s,
+                                gfac_src<R, true>(T, S.flags), (R)S.eps_r);
         stx(L.x, i, x + d);
         st3(L.p, i, p);
         st3(L.s, i, s);
@@ -309,7 +310,7 @@ qed_status emit_impl(qed_tables T, const qed_leptons *L, const qed_fields *f, co
     unsigned long long *c = (unsigned long long *)ctr;
     const size_t lds_nlc = sizeof(R) * 2 * T->dev.n_chi[0];
     const int g = grid_for(L->capacity);
-    const bool grid = general_fields(f);
+    const bool grid = general_leptons(f, p->flags);
     if (p->flags & QED_OPTICAL_DEPTH)
         QS_LAUNCH(K_LEPTON_MAIN, (k_lepton_main<R, 1, true>), dim3(g), dim3(kBlock), lds_nlc, st, ld, fd, sd, T->dev,
                   w.mask, nch, w.bctr, w.bcnt);
@@ -379,9 +380,9 @@ extern "C" qed_status qed_push_spin(const qed_leptons *L, const qed_fields *f, c
     const StepDev sd = step_dev(p);
     const int g = grid_for(L->capacity);
     if (T->params.precision == QED_F64)
-        QS_LAUNCH(K_PUSH, k_push<double>, dim3(g), dim3(kBlock), 0, st, lep_dev<double>(L), fd, sd);
+        QS_LAUNCH(K_PUSH, k_push<double>, dim3(g), dim3(kBlock), 0, st, lep_dev<double>(L), fd, sd, T->dev);
     else
-        QS_LAUNCH(K_PUSH, k_push<float>, dim3(g), dim3(kBlock), 0, st, lep_dev<float>(L), fd, sd);
+        QS_LAUNCH(K_PUSH, k_push<float>, dim3(g), dim3(kBlock), 0, st, lep_dev<float>(L), fd, sd, T->dev);
     return qs_launch_status(__func__);
 }
 

@@ -256,6 +256,65 @@ __global__ void __launch_bounds__(256) k_build_tables(BuildArgs A, GL12 g, doubl
     }
 }
 
+// ---------------------------------------------------------------- field-dependent g (loop appendix)
+// Scorer function Gi(z), z >= 0.  For z <= 16 the ray form of Ai + i Gi = (1/pi) int_0^inf
+// exp(i(z t + t^3/3)) dt at t = exp(i pi/6) s,
+//   Gi(z) = (1/pi) int_0^inf exp(-s^3/3 - z s/2) sin((sqrt3/2) z s + pi/6) ds,
+// by the trapezoidal rule in w = ln s with step 1/20 (the integrand is analytic for |Im w| < pi/6,
+// so the rule's error is of order exp(-pi^2/(3 h)) = e^-66), from w = -45 until the exponent
+// passes -50.  For z > 16 the large-argument series (1/(pi z)) sum_k (3k)!/(k! (3 z^3)^k), summed
+// until a term falls below 1e-18 of the sum (its smallest term there is far below that).
+__device__ double scorer_gi(double z)
+{
+    if (z > 16.0) {
+        const double x = 1.0 / (3.0 * z * z * z);
+        double term = 1.0, sum = 1.0;
+        for (int k = 1; k < 40; ++k) {
+            term *= (3.0 * k) * (3.0 * k - 1.0) * (3.0 * k - 2.0) / k * x;
+            sum += term;
+            if (term < 1e-18 * sum) break;
+        }
+        return sum / (qs::kPi * z);
+    }
+    const double h = 0.05, c = 0.5 * sqrt(3.0) * z;
+    double acc = 0.0;
+    for (int k = 0; k < 1000; ++k) {
+        const double s = exp(-45.0 + k * h), ex = s * s * s / 3.0 + 0.5 * z * s;
+        if (ex > 50.0) break;
+        acc += s * exp(-ex) * sin(c * s + qs::kPi / 6.0);
+    }
+    return acc * h / qs::kPi;
+}
+
+// One block per node: a(chi)/a(0) = 2 pi int_0^1 (1 - lam) z Gi(z) dlam, z = (lam/((1-lam) chi))^(2/3),
+// in nu = ln(lam/(1-lam)) (dlam = lam (1-lam) dnu), by 12-point Gauss-Legendre panels at most 1/2
+// wide on [min(ln chi, 0) - 40, 25] (the integrand falls as e^(5 nu/3) and e^(-2 nu) at the ends
+// and is analytic within pi/2 of the real axis).  Threads take the points in a fixed order and
+// the block sums them by a fixed tree, so the table is the same on every build.
+__global__ void __launch_bounds__(256) k_build_gfac(GL12 g, double *lng)
+{
+    __shared__ double part[256];
+    const int node = blockIdx.x;
+    const double lc = qs::kGfLnChi0 + node * qs::kGfDlnChi;
+    const double a = (lc < 0.0 ? lc : 0.0) - 40.0, b = 25.0;
+    const int np = (int)ceil((b - a) / 0.5);
+    const double w = (b - a) / np;
+    double acc = 0.0;
+    for (int k = threadIdx.x; k < np * kNQ; k += blockDim.x) {
+        const int pnl = k / kNQ, q = k % kNQ;
+        const double nu = a + (pnl + 0.5) * w + 0.5 * w * g.x[q];
+        const double u = exp(nu), z = exp(2.0 * (nu - lc) / 3.0);
+        acc += g.w[q] * u / ((1.0 + u) * (1.0 + u) * (1.0 + u)) * z * scorer_gi(z);
+    }
+    part[threadIdx.x] = acc;
+    __syncthreads();
+    for (int st = blockDim.x / 2; st > 0; st >>= 1) {
+        if ((int)threadIdx.x < st) part[threadIdx.x] += part[threadIdx.x + st];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) lng[node] = log(2.0 * qs::kPi * 0.5 * w * part[0]);
+}
+
 __global__ void k_to_float(const double *src, float *dst, int n)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -317,6 +376,8 @@ extern "C" qed_status qed_init_tables(const qed_table_params *params, qed_stream
     if (e == hipSuccess) e = hipMalloc(&T->d_nu, sizeof(double) * v);
     if (e == hipSuccess) e = hipMalloc(&T->d_bn64, sizeof(double) * n64.size());
     if (e == hipSuccess) e = hipMalloc(&T->d_bn32, sizeof(float) * n32.size());
+    if (e == hipSuccess) e = hipMalloc(&T->d_lng, sizeof(double) * qs::kGfN);
+    if (e == hipSuccess) e = hipMalloc(&T->d_lng32, sizeof(float) * qs::kGfN);
     if (e == hipSuccess) e = hipMemcpyAsync(T->d_bn64, n64.data(), sizeof(double) * n64.size(), hipMemcpyHostToDevice, st);
     if (e == hipSuccess) e = hipMemcpyAsync(T->d_bn32, n32.data(), sizeof(float) * n32.size(), hipMemcpyHostToDevice, st);
     if (e != hipSuccess) {
@@ -328,6 +389,9 @@ extern "C" qed_status qed_init_tables(const qed_table_params *params, qed_stream
     QS_LAUNCH(K_TABLES, k_build_tables, dim3(ntask), dim3(256), 0, st, A, g, T->d_lnrate, T->d_nu,
               (const double *)T->d_bn64);
     QS_LAUNCH(K_TABLES, k_to_float, dim3((r + 255) / 256), dim3(256), 0, st, T->d_lnrate, T->d_lnrate32, r);
+    QS_LAUNCH(K_TABLES, k_build_gfac, dim3(qs::kGfN), dim3(256), 0, st, g, T->d_lng);
+    QS_LAUNCH(K_TABLES, k_to_float, dim3((qs::kGfN + 255) / 256), dim3(256), 0, st, (const double *)T->d_lng,
+              T->d_lng32, qs::kGfN);
     e = hipGetLastError();
     if (e == hipSuccess) e = hipStreamSynchronize(st);
     if (e != hipSuccess) {
@@ -348,6 +412,8 @@ extern "C" qed_status qed_init_tables(const qed_table_params *params, qed_stream
     D.nu = T->d_nu;
     D.bn64 = T->d_bn64;
     D.bn32 = T->d_bn32;
+    D.lng = T->d_lng;
+    D.lng32 = T->d_lng32;
     *out = T;
     return QED_OK;
 }
@@ -360,6 +426,8 @@ extern "C" qed_status qed_free_tables(qed_tables T)
     if (T->d_nu) (void)hipFree(T->d_nu);
     if (T->d_bn64) (void)hipFree(T->d_bn64);
     if (T->d_bn32) (void)hipFree(T->d_bn32);
+    if (T->d_lng) (void)hipFree(T->d_lng);
+    if (T->d_lng32) (void)hipFree(T->d_lng32);
     free(T);
     return QED_OK;
 }
@@ -371,5 +439,13 @@ extern "C" qed_status qed_tables_download(qed_tables T, double *lnrate, int64_t 
     if (n_nu) *n_nu = T->n_nu;
     if (lnrate) QS_CHECK(hipMemcpy(lnrate, T->d_lnrate, sizeof(double) * T->n_rate, hipMemcpyDeviceToHost));
     if (nu) QS_CHECK(hipMemcpy(nu, T->d_nu, sizeof(double) * T->n_nu, hipMemcpyDeviceToHost));
+    return QED_OK;
+}
+
+extern "C" qed_status qed_tables_download_gfac(qed_tables T, double *lngfac, int64_t *n)
+{
+    if (!T) return QED_ERR_INVALID;
+    if (n) *n = qs::kGfN;
+    if (lngfac) QS_CHECK(hipMemcpy(lngfac, T->d_lng, sizeof(double) * qs::kGfN, hipMemcpyDeviceToHost));
     return QED_OK;
 }

@@ -1,0 +1,165 @@
+"""GPU parity of the field-dependent anomalous moment (QED_G_CHI, loop appendix): the g-factor
+table built on the GPU against the oracle's, the push of qed_push_spin particle by particle, one
+whole lepton step in FP64 and FP32 (per-species calls), and the head-on collision through the
+merged plan step in FP64, all against the oracle on the same inputs and Philox counters."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from parity import compare_leptons, compare_photons, oracle_run
+
+pytestmark = pytest.mark.gpu
+EPS = synth.EPS_R
+A_E = oracle.ALPHA / (2 * math.pi)
+
+
+def tol_k(steps):
+    return 1e-12 * max(1.0, steps / 250.0)
+
+
+@pytest.fixture(scope="module")
+def q():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("GPU test run without a GPU")
+    import paper_2511_08929_amd as q
+    q.lib()
+    return q
+
+
+@pytest.fixture(scope="module")
+def gtab64(q):
+    return q.Tables(precision=q.QED_F64)
+
+
+@pytest.fixture(scope="module")
+def gtab32(q):
+    return q.Tables(precision=q.QED_F32)
+
+
+def _sim(q, tab, w, cap_e, cap_p, cap_g, flags, merged=False, k_retire=None):
+    from paper_2511_08929_amd.sim import Simulation
+    f = q.make_fields(w.field_kind, E0=w.E0, B0=w.B0, a0=w.a0, phase_len=w.phase_len)
+    return Simulation(tab, cap_e=cap_e, cap_p=cap_p, cap_g=cap_g, track=w.track, fields=f, dt=w.dt, eps_r=EPS,
+                      seed=w.seed, flags=flags, k_retire=w.k_retire if k_retire is None else k_retire,
+                      merged=merged)
+
+
+def _workload(n, dt, seed=33, B0=(0.0, 0.0, 160.0), E0=(0.0, 40.0, 0.0)):
+    """Random leptons (gamma log-uniform in [30, 2e4], isotropic, partly polarized) in a strong
+    uniform field: chi from about 0.01 to 10."""
+    rng = np.random.default_rng(seed)
+    d = synth.random_unit_vectors(rng, n)
+    g = np.exp(rng.uniform(math.log(30.0), math.log(2e4), n))
+    p = d * np.sqrt(g * g - 1)
+    s = synth.random_unit_vectors(rng, n) * np.where(rng.random(n) < 0.2, rng.uniform(0, 1, n), 1.0)
+    x = np.stack([rng.uniform(0, 200, n), rng.uniform(-5, 5, n), rng.uniform(-5, 5, n)])
+    w = synth.Workload("random_leptons_uniform_field", n, 1, dt, seed, synth.FIELD_UNIFORM, E0=E0, B0=B0,
+                       track=(True, True, True))
+    w.x, w.p, w.s = x, p, s
+    return w
+
+
+def test_gfac_table_matches_oracle(gtab64, otables):
+    g = gtab64.download_gfac()
+    ref = otables.lngfac_nodes()
+    assert g.shape == ref.shape == (oracle.GF_N,)
+    d = np.abs(g - ref).max()
+    print(f"g-factor table parity: max |d ln(a/a0)| = {d:.2e}")
+    assert d < 1e-14
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_gchi_push_spin(q, gtab64, gtab32, otables, prec):
+    """qed_push_spin with T-BMT and the field-dependent moment, 1000 leptons (ragged), against the
+    oracle's push particle by particle; the same push with a constant moment differs visibly."""
+    n = 1000
+    w = _workload(n, dt=0.2)
+    if prec == "fp32":
+        w.x, w.p, w.s = (a.astype(np.float32).astype(np.float64) for a in (w.x, w.p, w.s))
+    tab = gtab64 if prec == "fp64" else gtab32
+    flags = q.QED_PUSH | q.QED_TBMT | q.QED_G_CHI
+    sim = _sim(q, tab, w, n, 1, 1, flags)
+    sim.e.load(w.x, w.p, w.s)
+    q.qed_push_spin(sim.e, sim.fields, sim.step_params(0), tab)
+    gx, gp, gs = sim.e.arrays()
+    E = np.array(w.E0, float); B = np.array(w.B0, float)
+    ref_p, ref_s, ref_x, const_s = (np.zeros((3, n)) for _ in range(4))
+    for i in range(n):
+        ref_p[:, i], ref_s[:, i], ref_x[:, i] = oracle.push_one(-1, A_E, E, B, w.dt, flags, w.p[:, i], w.s[:, i],
+                                                                w.x[:, i], tables=otables, eps_r=EPS)
+        const_s[:, i] = oracle.push_one(-1, A_E, E, B, w.dt, flags & ~q.QED_G_CHI, w.p[:, i], w.s[:, i],
+                                        w.x[:, i])[1]
+    tol = 1e-12 if prec == "fp64" else 1e-5
+    dp = (np.linalg.norm(gp - ref_p, axis=0) / np.linalg.norm(ref_p, axis=0)).max()
+    ds = np.abs(gs - ref_s).max()
+    dx = (np.abs(gx - ref_x) / np.maximum(1.0, np.abs(ref_x))).max()
+    effect = np.abs(const_s - ref_s).max()
+    print(f"g(chi) push {prec}: max rel dp {dp:.2e}, max |ds| {ds:.2e}, max rel dx {dx:.2e}, "
+          f"constant-moment difference {effect:.2e}")
+    assert dp < tol and ds < tol and dx < tol
+    assert effect > 1e-3
+
+
+def test_gchi_lepton_step_fp64(q, gtab64, otables):
+    """One whole NLC step (push with a(chi), emission, no-emission update) of 1000 leptons through
+    the per-species calls, against the oracle."""
+    n = 1000
+    w = _workload(n, dt=0.5)
+    flags = (q.QED_ALL & ~q.QED_PAIR) | q.QED_G_CHI
+    sim = _sim(q, gtab64, w, n, 1, 2 * n, flags, k_retire=0.0)
+    sim.e.load(w.x, w.p, w.s)
+    sim.step()
+    ref = oracle_run(otables, w, 1, flags, cap_g=2 * n, k_retire=0.0)
+    ex = ref["near_e"]
+    assert ex.sum() <= 2 and ref["ctr"]["n_emit"] > 100
+    compare_leptons(sim.e.arrays(), ref["E"].arrays(), ex, 1e-12, 1e-12, rtol_x=1e-12, what="g(chi) leptons")
+    compare_photons(sim.g.arrays(), ref["G"].arrays(), {(0, int(i)) for i in np.nonzero(ex)[0]}, 1e-12, 1e-12,
+                    what="g(chi) photons")
+    assert q.counters_dict(sim.ctr)["n_emit"] == ref["ctr"]["n_emit"]
+
+
+def test_gchi_lepton_step_fp32(q, gtab32, otables):
+    n = 4000
+    w = _workload(n, dt=0.05)
+    w.x, w.p, w.s = (a.astype(np.float32).astype(np.float64) for a in (w.x, w.p, w.s))
+    flags = (q.QED_ALL & ~q.QED_PAIR) | q.QED_G_CHI
+    sim = _sim(q, gtab32, w, n, 1, 2 * n, flags, k_retire=0.0)
+    sim.e.load(w.x, w.p, w.s)
+    sim.step()
+    ref = oracle_run(otables, w, 1, flags, cap_g=2 * n, k_retire=0.0, u24=True, near_tol=1e-5)
+    ex = ref["near_e"]
+    print("g(chi) fp32: near-tie fraction", ex.mean(), "emitted", ref["ctr"]["n_emit"])
+    assert ex.mean() < 0.01 and ref["ctr"]["n_emit"] > 100
+    compare_leptons(sim.e.arrays(), ref["E"].arrays(), ex, 1e-5, 1e-5, what="g(chi) fp32 leptons")
+    compare_photons(sim.g.arrays(), ref["G"].arrays(), {(0, int(i)) for i in np.nonzero(ex)[0]}, 1e-5, 1e-5,
+                    what="g(chi) fp32 photons")
+
+
+def test_gchi_head_on_merged_fp64(q, gtab64, otables):
+    """The head-on collision with the field-dependent moment through the merged plan step: 300
+    electrons through the whole pulse (1700 steps), both channels, compaction every 200 steps."""
+    w = synth.subsample(synth.c2(), np.arange(300))
+    steps = 1700
+    flags = q.QED_ALL | q.QED_G_CHI
+    cap_g, cap_p = 50_000, 2_000
+    sim = _sim(q, gtab64, w, w.n + cap_p, cap_p, cap_g, flags, merged=True)
+    sim.e.load(w.x, w.p, w.s)
+    for k in range(steps):
+        sim.step()
+        if k % 200 == 199:
+            sim.compact()
+    ref = oracle_run(otables, w, steps, flags, cap_e=w.n + cap_p, cap_p=cap_p, cap_g=cap_g)
+    c = q.counters_dict(sim.ctr)
+    print("g(chi) head-on gpu", c, "oracle", ref["ctr"])
+    assert ref["near_e"].sum() == 0 and ref["near_g"].sum() == 0
+    assert c["n_emit"] == ref["ctr"]["n_emit"] > 5_000 and c["n_pair"] == ref["ctr"]["n_pair"]
+    t = tol_k(steps)
+    compare_leptons(sim.e.arrays(), ref["E"].arrays(), np.zeros(ref["E"].n, bool), t, t, rtol_x=t,
+                    what="g(chi) electrons", events=c["n_emit"])
+    compare_leptons(sim.p.arrays(), ref["P"].arrays(), np.zeros(ref["P"].n, bool), t, t, rtol_x=t,
+                    what="g(chi) positrons")
+    compare_photons(sim.g.arrays(), ref["G"].arrays(), set(), t, t, what="g(chi) photons")
