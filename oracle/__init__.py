@@ -36,6 +36,8 @@ F_PAIR, F_NOPAIR, F_PAIR_SPIN = 1 << 8, 1 << 9, 1 << 10
 F_TAU = 1 << 11
 F_REJECT = 1 << 12
 F_GCHI = 1 << 13
+F_SUB = 1 << 14
+SUB_ROUNDS, SUB_WDT = 16, 0.1
 GF_N, GF_LNCHI0, GF_DLNCHI = 705, -16.11809565095832, 0.03597789207803197
 F_ALL = (F_PUSH | F_TBMT | F_EMIT | F_RECOIL | F_SPIN | F_NOEMIT | F_PHOTON_POL
          | F_PAIR | F_NOPAIR | F_PAIR_SPIN)
@@ -79,7 +81,8 @@ class Params(C.Structure):
     _fields_ = [("t", C.c_double), ("dt", C.c_double), ("a_e", C.c_double), ("eps_r", C.c_double),
                 ("chi_e_min", C.c_double), ("chi_e_max", C.c_double), ("chi_g_min", C.c_double),
                 ("chi_g_max", C.c_double), ("k_retire", C.c_double), ("near_tol", C.c_double),
-                ("step", C.c_int64), ("seed", C.c_uint64), ("flags", C.c_uint32), ("u24", C.c_int)]
+                ("step", C.c_int64), ("seed", C.c_uint64), ("flags", C.c_uint32), ("u24", C.c_int),
+                ("sub_round", C.c_int)]
 
 
 DP = C.POINTER(C.c_double)

@@ -42,6 +42,12 @@
  *      (momentum (u- + u+)/2, energy gamma-), and the ratio is tabulated like the rates: ln of it
  *      at 64 nodes per decade of chi from 1e-7 to 1e4, 4-point Lagrange in ln chi; 1 below,
  *      the chi^(-2/3) law above.
+ *  R12 Sub-cycling (the decision-making section requires W dt << 1 and flags the accuracy of
+ *      the per-step draw as the weak point): after the push a lepton takes m sub-steps of the
+ *      whole QED part, m the smallest power of two with W_s dt / m <= 0.1 (at most 16), W_s dt
+ *      at the state after the push; the sub-steps run in 16 rounds over the set (a lepton takes
+ *      one in every 16/m-th round), with the Philox channels of round r offset by 16 r and r in
+ *      the photon id, each round's photons appended after the previous round's.
  */
 #include "qed_oracle.h"
 
@@ -101,7 +107,7 @@ static void philox_block(uint64_t seed, uint64_t id, int64_t step, uint32_t chan
 static void uniforms2(const orc_params *prm, uint64_t id, uint32_t channel, double *ra, double *rb)
 {
     uint32_t w[4];
-    philox_block(prm->seed, id, prm->step, channel, w);
+    philox_block(prm->seed, id, prm->step, channel + 16u * (uint32_t)prm->sub_round, w);
     if (prm->u24) { *ra = orc_u01_24(w[0]); *rb = orc_u01_24(w[2]); }
     else          { *ra = orc_u01_53(w[0], w[1]); *rb = orc_u01_53(w[2], w[3]); }
 }
@@ -925,10 +931,11 @@ static int near_tie(double r, double thr, double tol)
 
 static uint64_t lepton_id(int species, int64_t index) { return ((uint64_t)species << 62) | (uint64_t)index; }
 
-static uint64_t photon_id(int species, int64_t index, int64_t step)
+/* 2^63 | species << 61 | (sub-cycling round << 33 | parent index mod 2^33) << 24 | step mod 2^24 */
+static uint64_t photon_id(int species, int64_t index, int64_t step, int round)
 {
-    return (1ull << 63) | ((uint64_t)species << 61) | (((uint64_t)index & ((1ull << 37) - 1)) << 24)
-           | ((uint64_t)step & 0xFFFFFFull);
+    return (1ull << 63) | ((uint64_t)species << 61) | ((uint64_t)(round & 15) << 57)
+           | (((uint64_t)index & ((1ull << 33) - 1)) << 24) | ((uint64_t)step & 0xFFFFFFull);
 }
 
 /* no-transition spin update (non-transition section), renormalised if it leaves |s| > 1 (R6) */
@@ -1078,7 +1085,7 @@ emission:
     orc_stokes_to_P(xi, eh, bh, kh, P_out);
     if (fl & ORC_F_RECOIL) for (int i = 0; i < 3; ++i) p[i] *= oml;
     if (fl & ORC_F_SPIN) for (int i = 0; i < 3; ++i) s[i] = sf[0] * eh[i] + sf[1] * bh[i] + sf[2] * kh[i];
-    *id_out = photon_id(species, index, prm->step);
+    *id_out = photon_id(species, index, prm->step, prm->sub_round);
     ctr->n_emit++;
     return 1 | (near << 1);
 }
@@ -1193,9 +1200,154 @@ static void add_counters(orc_counters *d, const orc_counters *s)
     d->n_lepton_steps += s->n_lepton_steps; d->n_photon_steps += s->n_photon_steps;
 }
 
+/* append the photons of one pass over the leptons in lepton index order */
+static void append_photons(const orc_params *prm, const orc_leptons *L, orc_photons *G, int64_t n,
+                           const char *emitted, const double *kb, const uint64_t *ib, orc_counters *tot)
+{
+    for (int64_t j = 0; j < n; ++j) {
+        if (!emitted[j]) continue;
+        if (G->n >= G->cap) { tot->n_capacity_overflow++; continue; }
+        int64_t m = G->n++;
+        const double *kk = kb + 6 * j, *PP = kb + 6 * j + 3;
+        double k0 = sqrt(kk[0] * kk[0] + kk[1] * kk[1] + kk[2] * kk[2]);
+        if (k0 < prm->k_retire) {
+            G->id[m] = 0;
+            for (int i = 0; i < 3; ++i) { if (G->x[i]) G->x[i][m] = 0.0; G->k[i][m] = 0.0; G->P[i][m] = 0.0; }
+            tot->n_retired++;
+            continue;
+        }
+        G->id[m] = ib[j];
+        for (int i = 0; i < 3; ++i) {
+            if (G->x[i]) G->x[i][m] = getx(L->x, i, j);
+            G->k[i][m] = kk[i];
+            G->P[i][m] = PP[i];
+        }
+        if (G->near) G->near[m] = 0;
+    }
+}
+
+/* The spin-weighted emission probability W_s dt of the decision (NLC section) at the lepton's
+   current state, 0 where the step does no QED; sets *near when it lies within near_tol of a
+   sub-cycling boundary ORC_SUB_WDT 2^k. */
+static double lepton_wdt(const orc_tables *T, const orc_params *prm, int species, const double E[3],
+                         const double B[3], const double p[3], const double s[3], int *near)
+{
+    double eh[3], bh[3], kh[3];
+    double chi = orc_basis(species == 0 ? -1 : 1, prm->eps_r, E, B, p, eh, bh, kh);
+    if (!(chi >= prm->chi_e_min)) return 0.0;
+    if (chi > prm->chi_e_max) chi = prm->chi_e_max;
+    double gamma = sqrt(1.0 + dot3(p, p));
+    double Ce = ORC_ALPHA / (sqrt(3.0) * ORC_PI * prm->eps_r * gamma);
+    double lnchi = log(chi);
+    double sb = dot3(s, bh);
+    double a = Ce * exp(orc_table_lnrate(T, 0, lnchi)) * 0.5 * (1.0 - sb) * prm->dt;
+    double b = Ce * exp(orc_table_lnrate(T, 1, lnchi)) * 0.5 * (1.0 + sb) * prm->dt;
+    double P = a + b;
+    for (int m = 1; m < ORC_SUB_ROUNDS; m *= 2)
+        if (near_tie(P, ORC_SUB_WDT * m, prm->near_tol)) *near = 1;
+    return P;
+}
+
+/* Per-particle sub-cycling of the lepton step where the per-step draw would need W dt << 1
+   (decision-making section).  After the push, each lepton takes m sub-steps of dt/m, m the
+   smallest power of two with W_s dt / m <= ORC_SUB_WDT, at most ORC_SUB_ROUNDS, W_s dt taken at
+   the state after the push.  The sub-steps run in ORC_SUB_ROUNDS rounds over the whole set: in
+   round r a lepton with m sub-steps takes one (the whole QED part with the fields at t + dt:
+   decision with its current chi and spin, emission with recoil and collapses, or the
+   no-transition update over dt/m) when r is a multiple of ORC_SUB_ROUNDS/m.  Each round's
+   photons are appended in lepton index order after the previous round's. */
+static int lepton_step_subcycled(const orc_tables *T, const orc_params *prm, const orc_fields *f,
+                                 orc_leptons *L, orc_photons *G, orc_counters *ctr, int nthreads)
+{
+    int64_t n = L->n;
+    int q = L->species == 0 ? -1 : 1;
+    int *msub = (int *)malloc(sizeof(int) * (n > 0 ? n : 1));
+    char *near = (char *)calloc(n > 0 ? n : 1, 1);
+    char *emitted = (char *)calloc(n > 0 ? n : 1, 1);
+    double *kb = (double *)malloc(sizeof(double) * 6 * (n > 0 ? n : 1));
+    uint64_t *ib = (uint64_t *)malloc(sizeof(uint64_t) * (n > 0 ? n : 1));
+    orc_counters tot = {0};
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#endif
+    /* the push, and the number of sub-steps */
+#pragma omp parallel
+    {
+        orc_counters loc = {0};
+#pragma omp for schedule(static)
+        for (int64_t j = 0; j < n; ++j) {
+            loc.n_lepton_steps++;
+            double x[3] = {getx(L->x, 0, j), getx(L->x, 1, j), getx(L->x, 2, j)};
+            double p[3] = {L->p[0][j], L->p[1][j], L->p[2][j]};
+            double s[3] = {L->s[0][j], L->s[1][j], L->s[2][j]};
+            double E[3], B[3];
+            if (prm->flags & ORC_F_PUSH) {
+                orc_fields_eval(f, x, prm->t, E, B);
+                orc_push_one(q, prm->a_e, E, B, prm->dt, prm->flags, T, prm->eps_r, p, s, x);
+            }
+            int m = 1;
+            if (prm->flags & ORC_F_EMIT) {
+                orc_fields_eval(f, x, prm->t + prm->dt, E, B);
+                int nr = 0;
+                double P = lepton_wdt(T, prm, L->species, E, B, p, s, &nr);
+                while (m < ORC_SUB_ROUNDS && P > ORC_SUB_WDT * m) m *= 2;
+                near[j] = (char)nr;
+            }
+            msub[j] = m;
+            for (int i = 0; i < 3; ++i) {
+                if (L->x[i]) L->x[i][j] = x[i];
+                L->p[i][j] = p[i];
+                L->s[i][j] = s[i];
+            }
+        }
+#pragma omp critical
+        add_counters(&tot, &loc);
+    }
+    /* the rounds */
+    for (int r = 0; r < ORC_SUB_ROUNDS && (prm->flags & ORC_F_EMIT); ++r) {
+#pragma omp parallel
+        {
+            orc_counters loc = {0};
+#pragma omp for schedule(static)
+            for (int64_t j = 0; j < n; ++j) {
+                emitted[j] = 0;
+                if (r % (ORC_SUB_ROUNDS / msub[j]) != 0) continue;
+                orc_params sub = *prm;
+                sub.dt = prm->dt / msub[j];
+                sub.sub_round = r;
+                double x[3] = {getx(L->x, 0, j), getx(L->x, 1, j), getx(L->x, 2, j)};
+                double p[3] = {L->p[0][j], L->p[1][j], L->p[2][j]};
+                double s[3] = {L->s[0][j], L->s[1][j], L->s[2][j]};
+                double E[3], B[3];
+                orc_fields_eval(f, x, prm->t + prm->dt, E, B);
+                int64_t idx = L->index ? L->index[j] : j;
+                int res = orc_lepton_qed_one(T, &sub, L->species, idx, E, B, x, p, s, kb + 6 * j, kb + 6 * j + 3,
+                                             ib + j, NULL, &loc);
+                emitted[j] = (char)(res & 1);
+                if (res & 2) near[j] = 1;
+                for (int i = 0; i < 3; ++i) {
+                    L->p[i][j] = p[i];
+                    L->s[i][j] = s[i];
+                }
+            }
+#pragma omp critical
+            add_counters(&tot, &loc);
+        }
+        append_photons(prm, L, G, n, emitted, kb, ib, &tot);
+    }
+    for (int64_t j = 0; j < n; ++j) {
+        if (near[j]) tot.n_near_threshold++;
+        if (L->near) L->near[j] = (uint8_t)near[j];
+    }
+    add_counters(ctr, &tot);
+    free(msub); free(near); free(emitted); free(kb); free(ib);
+    return 0;
+}
+
 int orc_lepton_step(const orc_tables *T, const orc_params *prm, const orc_fields *f,
                     orc_leptons *L, orc_photons *G, orc_counters *ctr, int nthreads)
 {
+    if (prm->flags & ORC_F_SUB) return lepton_step_subcycled(T, prm, f, L, G, ctr, nthreads);
     int64_t n = L->n;
     int q = L->species == 0 ? -1 : 1;
     char *emitted = (char *)calloc(n > 0 ? n : 1, 1);
@@ -1238,27 +1390,7 @@ int orc_lepton_step(const orc_tables *T, const orc_params *prm, const orc_fields
 #pragma omp critical
         add_counters(&tot, &loc);
     }
-    /* append photons in lepton index order */
-    for (int64_t j = 0; j < n; ++j) {
-        if (!emitted[j]) continue;
-        if (G->n >= G->cap) { tot.n_capacity_overflow++; continue; }
-        int64_t m = G->n++;
-        const double *kk = kb + 6 * j, *PP = kb + 6 * j + 3;
-        double k0 = sqrt(kk[0] * kk[0] + kk[1] * kk[1] + kk[2] * kk[2]);
-        if (k0 < prm->k_retire) {
-            G->id[m] = 0;
-            for (int i = 0; i < 3; ++i) { if (G->x[i]) G->x[i][m] = 0.0; G->k[i][m] = 0.0; G->P[i][m] = 0.0; }
-            tot.n_retired++;
-            continue;
-        }
-        G->id[m] = ib[j];
-        for (int i = 0; i < 3; ++i) {
-            if (G->x[i]) G->x[i][m] = getx(L->x, i, j);
-            G->k[i][m] = kk[i];
-            G->P[i][m] = PP[i];
-        }
-        if (G->near) G->near[m] = 0;
-    }
+    append_photons(prm, L, G, n, emitted, kb, ib, &tot);
     add_counters(ctr, &tot);
     free(emitted); free(kb); free(ib);
     return 0;

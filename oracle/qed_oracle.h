@@ -95,9 +95,14 @@ enum {
     ORC_F_REJECT = 1u << 12, /* emission decided and lambda sampled together by rejection from the
                                 spin-resolved spectrum with candidates lambda = r1^3 (spectrum-sampling
                                 section), instead of the draw against W dt and the inverse CDF */
-    ORC_F_GCHI = 1u << 13    /* T-BMT with the field-dependent anomalous moment a_e a(chi)/a(0)
+    ORC_F_GCHI = 1u << 13,   /* T-BMT with the field-dependent anomalous moment a_e a(chi)/a(0)
                                 (loop appendix) instead of the constant a_e */
+    ORC_F_SUB = 1u << 14     /* per-particle sub-cycling of the lepton QED part where W dt is large:
+                                m = the smallest power of two with W_s dt / m <= ORC_SUB_WDT (at most
+                                ORC_SUB_ROUNDS) sub-steps of dt/m, taken in ORC_SUB_ROUNDS rounds */
 };
+#define ORC_SUB_ROUNDS 16
+#define ORC_SUB_WDT 0.1
 
 typedef struct {
     double   t, dt, a_e, eps_r;
@@ -108,6 +113,8 @@ typedef struct {
     uint64_t seed;
     uint32_t flags;
     int      u24;           /* 1: uniforms from the 24-bit map (single-precision path) */
+    int      sub_round;     /* sub-cycling round of this call (0 otherwise): Philox channels of the
+                               lepton step are offset by 16 sub_round, and the photon id carries it */
 } orc_params;
 
 typedef struct {
