@@ -35,7 +35,8 @@
  *    increasing photon index, so results are bitwise reproducible run to run.
  *  - Random numbers: Philox4x32-10 keyed by the 64-bit seed, counter
  *    (id low, id high, step, channel).  Lepton id = (species << 62) | index; photon id =
- *    2^63 | (parent species << 61) | ((parent index mod 2^37) << 24) | (step mod 2^24).
+ *    2^63 | (parent species << 61) | (round << 57) | ((parent index mod 2^33) << 24) |
+ *    (step mod 2^24), round = the sub-cycling round (QED_SUBCYCLE; 0 otherwise).
  */
 #ifndef QEDSPIN_H
 #define QEDSPIN_H
@@ -80,7 +81,7 @@ enum {
                                   when r2 < 3 r1^2 dW/dlambda dt, dW/dlambda the spectrum of the
                                   lepton's spin state; no inverse-CDF table is read for the emission.
                                   Not with QED_OPTICAL_DEPTH (QED_ERR_INVALID) */
-    QED_G_CHI = 1u << 13       /* T-BMT with the field-dependent anomalous moment (loop appendix: the
+    QED_G_CHI = 1u << 13,      /* T-BMT with the field-dependent anomalous moment (loop appendix: the
                                   Scorer-function term of the one-loop self-energy): a_e is scaled by
                                   a(chi)/a(0) = 2 pi int_0^inf du/(1+u)^3 z Gi(z), z = (u/chi)^(2/3),
                                   at the Boris mid-step chi (momentum (u- + u+)/2, energy gamma-),
@@ -88,6 +89,17 @@ enum {
                                   decade of chi from 1e-7 to 1e4, 4-point Lagrange in ln chi; 1 below
                                   chi = 1e-7, the chi^(-2/3) law above 1e4.  a_e = alpha/(2 pi) gives
                                   the one-loop moment, a_e = 0 keeps g = 2 */
+    QED_SUBCYCLE = 1u << 14    /* per-particle sub-cycling of the lepton QED part where the per-step
+                                  draw needs W dt << 1 (decision-making section): after the push a
+                                  lepton takes m sub-steps of dt/m, m the smallest power of two with
+                                  W_s dt / m <= 0.1 (at most 16), W_s dt at the state after the push;
+                                  the sub-steps run in 16 rounds (a lepton takes one in every
+                                  16/m-th), each the whole QED part at its current chi and spin, with
+                                  Philox channels offset by 16 x round and the round in the photon id;
+                                  a round's photons follow the previous round's.  qed_emit only (not
+                                  in plans: QED_ERR_INVALID there), not with QED_OPTICAL_DEPTH or
+                                  QED_REJECTION (QED_ERR_INVALID).  Leptons below W dt = 0.1 step
+                                  exactly as without it */
 };
 
 /* Field models evaluated at each particle. */

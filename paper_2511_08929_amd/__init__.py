@@ -29,6 +29,7 @@ QED_PAIR, QED_NOPAIR, QED_PAIR_SPIN = 1 << 8, 1 << 9, 1 << 10
 QED_OPTICAL_DEPTH = 1 << 11
 QED_REJECTION = 1 << 12
 QED_G_CHI = 1 << 13
+QED_SUBCYCLE = 1 << 14
 QED_ALL = (QED_PUSH | QED_TBMT | QED_EMIT | QED_RECOIL | QED_SPIN | QED_NOEMIT | QED_PHOTON_POL
            | QED_PAIR | QED_NOPAIR | QED_PAIR_SPIN)
 QED_FIELD_UNIFORM, QED_FIELD_PLANE_LP, QED_FIELD_GRID2D, QED_FIELD_ROTATING_E = 0, 1, 2, 3

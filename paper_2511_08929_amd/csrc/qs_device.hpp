@@ -17,8 +17,15 @@ constexpr double kPi = 3.14159265358979323846;
 enum : uint32_t {
     F_PUSH = 1u << 0, F_TBMT = 1u << 1, F_EMIT = 1u << 2, F_RECOIL = 1u << 3, F_SPIN = 1u << 4,
     F_NOEMIT = 1u << 5, F_PHOTON_POL = 1u << 6, F_MEAN = 1u << 7, F_PAIR = 1u << 8,
-    F_NOPAIR = 1u << 9, F_PAIR_SPIN = 1u << 10, F_TAU = 1u << 11, F_REJECT = 1u << 12, F_GCHI = 1u << 13
+    F_NOPAIR = 1u << 9, F_PAIR_SPIN = 1u << 10, F_TAU = 1u << 11, F_REJECT = 1u << 12, F_GCHI = 1u << 13,
+    F_SUB = 1u << 14
 };
+
+// Sub-cycling of the lepton step: a lepton takes 2^k <= kSubRounds sub-steps, the smallest with
+// W_s dt / 2^k <= kSubWdt, one in every kSubRounds / 2^k-th of kSubRounds rounds.
+constexpr int kSubRounds = 16;
+constexpr int kSubLog2Max = 4;
+constexpr double kSubWdt = 0.1;
 
 // Field-dependent anomalous moment (loop appendix): table of ln(a(chi)/a(0)) at 64 nodes per
 // decade of chi from 1e-7 to 1e4 (node i at ln chi = kGfLnChi0 + i kGfDlnChi).
@@ -103,10 +110,11 @@ template <> struct Unif<float> {
 };
 
 __device__ __forceinline__ uint64_t lepton_id(int species, int64_t index) { return ((uint64_t)species << 62) | (uint64_t)index; }
-__device__ __forceinline__ uint64_t photon_id(int species, int64_t index, int64_t step)
+// 2^63 | species << 61 | (sub-cycling round << 33 | parent index mod 2^33) << 24 | step mod 2^24
+__device__ __forceinline__ uint64_t photon_id(int species, int64_t index, int64_t step, int round)
 {
-    return (1ull << 63) | ((uint64_t)species << 61) | (((uint64_t)index & ((1ull << 37) - 1)) << 24) |
-           ((uint64_t)step & 0xFFFFFFull);
+    return (1ull << 63) | ((uint64_t)species << 61) | ((uint64_t)(round & 15) << 57) |
+           (((uint64_t)index & ((1ull << 33) - 1)) << 24) | ((uint64_t)step & 0xFFFFFFull);
 }
 
 // ------------------------------------------------------------------ Bessel functions

@@ -19,6 +19,7 @@ template <class R> struct LepDev {
     int species;
     R *x[3], *p[3], *s[3];
     double *tau, *tau_t;       // optical depth and its target (FP64 in both precisions), or NULL
+    uint8_t *msub;             // log2 of the sub-steps of this time step (sub-cycling only)
 };
 
 template <class R> struct PhoDev {
@@ -34,6 +35,7 @@ struct StepDev {
     int64_t step;
     uint64_t seed;
     uint32_t flags;
+    int sub_round;             // sub-cycling round (Philox channels + 16 sub_round; photon ids)
     const int64_t *clock;      // optional device step offset (replayable launches)
 };
 
@@ -56,6 +58,7 @@ struct WS {
     int64_t *book;       // [8]: base0, total, base1, n_fit, n processed, block range
     uint32_t *bctr;      // [kMaxGrid][kNCtr]: per-block counts of the streaming pass
     uint32_t *idx;       // [max particles]
+    uint8_t *msub;       // [max particles]: log2 of each lepton's sub-steps (sub-cycling)
 };
 
 __host__ __device__ inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
@@ -70,7 +73,8 @@ inline WS carve(void *ws, int64_t cap, int64_t *nchunks_out)
     w.bcnt = (uint32_t *)b; b += align256(sizeof(uint32_t) * kMaxGrid);
     w.book = (int64_t *)b;  b += align256(sizeof(int64_t) * 8);
     w.bctr = (uint32_t *)b; b += align256(sizeof(uint32_t) * kMaxGrid * kNCtr);
-    w.idx = (uint32_t *)b;
+    w.idx = (uint32_t *)b; b += align256(sizeof(uint32_t) * (cap > 0 ? cap : 1));
+    w.msub = (uint8_t *)b;
     *nchunks_out = nch;
     return w;
 }
@@ -231,7 +235,7 @@ __device__ __forceinline__ LDecide<R> lepton_decide(const StepDev &S, const Tabl
     d.a = d.Wdn * (R)0.5 * ((R)1 - sb) * dt;
     const R b = d.Wup * (R)0.5 * ((R)1 + sb) * dt;
     d.P = d.a + b;
-    const uint4 w = philox_block(S.seed, lepton_id(species, index), S.step, 0u);
+    const uint4 w = philox_block(S.seed, lepton_id(species, index), S.step, 16u * (uint32_t)S.sub_round);
     Unif<R>::two(w, d.r1, d.r2);
     return d;
 }
@@ -293,15 +297,29 @@ struct LCount { unsigned prob = 0, chi = 0, norm = 0, step = 0, trans = 0; };
 // Main pass, one lepton: Boris push and T-BMT rotation with the fields at t, the fields at
 // t + dt, chi and the decision (NLC section); a non-emitter gets the no-transition spin update
 // (non-transition section).  Stores x, p, s.  DEC: decision variants compiled in (bit 0: the
-// optical-depth decision, bit 1: rejection sampling; the variant with neither needs the fewest
-// registers); the step's flags choose among the compiled ones.
+// optical-depth decision, bit 1: rejection sampling, bit 2: sub-cycling; the variant with none
+// needs the fewest registers); the step's flags choose among the compiled ones.
+// Sub-cycling (bit 2) runs the QED part in kSubRounds launches (S.sub_round): round 0 pushes and
+// sets the lepton's sub-steps 2^k from W_s dt; a lepton takes its sub-steps of dt/2^k in the
+// rounds that are multiples of kSubRounds/2^k and leaves its state alone in the others.
 template <class R, int DEC, bool GRID>
 __device__ __forceinline__ void lepton_item(const LepDev<R> &L, const FieldDev &F, const StepDev &S, const TablesDev &T,
                                             const R *lds, int64_t i, V3<R> x, V3<R> p, V3<R> s, bool &emit, bool &up,
                                             LCount &c)
 {
     const int q = L.species == 0 ? -1 : 1;
-    ++c.step;
+    int msh = 0;                                  // log2 of the sub-steps (sub-cycling)
+    if constexpr ((DEC & 4) != 0) {
+        if (S.sub_round > 0) {
+            msh = L.msub[i];
+            if ((S.sub_round & ((kSubRounds >> msh) - 1)) != 0) return;     // not this lepton's round
+        } else {
+            ++c.step;
+            L.msub[i] = 0;
+        }
+    } else {
+        ++c.step;
+    }
     V3<R> E, B;
     if (S.flags & F_PUSH) {
         eval_fields<R, GRID>(F, (double)x.x, (double)x.y, S.t, E, B);
@@ -310,7 +328,17 @@ __device__ __forceinline__ void lepton_item(const LepDev<R> &L, const FieldDev &
     }
     if (S.flags & F_EMIT) {
         eval_fields<R, GRID>(F, (double)x.x, (double)x.y, S.t + S.dt, E, B);
-        const LDecide<R> d = lepton_decide<R>(S, T, lds, L.species, i, p, s, E, B);
+        LDecide<R> d = lepton_decide<R>(S, T, lds, L.species, i, p, s, E, B);
+        if constexpr ((DEC & 4) != 0) {
+            if (d.active) {
+                if (S.sub_round == 0) {
+                    while (msh < kSubLog2Max && d.P > (R)kSubWdt * (R)(1 << msh)) ++msh;
+                    L.msub[i] = (uint8_t)msh;
+                }
+                d.a = ldexp(d.a, -msh);               // W dt / 2^k, exact
+                d.P = ldexp(d.P, -msh);
+            }
+        }
         if (d.active) {
             c.chi += d.clamped_chi;
             bool noemit_update = false;
@@ -359,7 +387,7 @@ __device__ __forceinline__ void lepton_item(const LepDev<R> &L, const FieldDev &
                 up = !(d.r1 < thr);
             }
             if (noemit_update && (S.flags & F_NOEMIT)) {
-                const R dt = (R)S.dt;
+                const R dt = ldexp((R)S.dt, -msh);
                 const R Wbar = (R)0.5 * (d.Wup + d.Wdn), dW = (R)0.5 * (d.Wup - d.Wdn);
                 const R inv = (R)1 / ((R)1 - d.P);
                 s = inv * (((R)1 - Wbar * dt) * s - (dW * dt) * d.bs.b);
@@ -441,7 +469,7 @@ __device__ __forceinline__ void emit_item(const LepDev<R> &L, const PhoDev<R> &G
     const double u_d = lam_d / oml_d;
     const V3<R> k = (R)lam_d * p;
     R r3, r4;
-    Unif<R>::two(philox_block(S.seed, lepton_id(L.species, i), S.step, 1u), r3, r4);
+    Unif<R>::two(philox_block(S.seed, lepton_id(L.species, i), S.step, 1u + 16u * (uint32_t)S.sub_round), r3, r4);
     SpecPt<R> qp;
     qp.lam = (R)lam_d; qp.oml = (R)oml_d; qp.u = (R)u_d;
     bessel_ratios<R>(2.0 * u_d / (3.0 * d.chi), bn_of<R>(T), qp.K1, qp.I);
@@ -481,7 +509,7 @@ __device__ __forceinline__ void emit_item(const LepDev<R> &L, const PhoDev<R> &G
             G.id[slot] = 0;
             ++c_ret;
         } else {
-            G.id[slot] = photon_id(L.species, i, S.step);
+            G.id[slot] = photon_id(L.species, i, S.step, S.sub_round);
             stx(G.x, slot, x);
             st3(G.k, slot, k);
             st3(G.P, slot, Pv);
@@ -712,6 +740,7 @@ template <class R> LepDev<R> lep_dev(const qed_leptons *L)
     }
     d.tau = L->tau;
     d.tau_t = L->tau_target;
+    d.msub = nullptr;
     return d;
 }
 
@@ -764,6 +793,7 @@ inline StepDev step_dev(const qed_step_params *p)
     s.k_retire = p->k_retire;
     s.Kc = kAlpha / (sqrt(3.0) * kPi * p->eps_r);
     s.step = p->step; s.seed = p->seed; s.flags = p->flags;
+    s.sub_round = 0;
     s.clock = p->d_clock;
     return s;
 }

@@ -605,6 +605,7 @@ bool instance_ok(const qed_instance *in)
     const uint32_t fl = in->params.flags;
     if (!leptons_ok(&in->electrons) || in->electrons.species != 0 || !tau_ok(&in->electrons, fl)) return false;
     if ((fl & QED_REJECTION) && (fl & QED_OPTICAL_DEPTH)) return false;
+    if (fl & QED_SUBCYCLE) return false;          // sub-cycling runs in the per-species calls only
     if (!fields_ok(&in->fields) || !in->d_counters || !in->params.d_clock) return false;
     if (!(in->params.dt > 0.0) || !(in->params.eps_r > 0.0)) return false;
     if ((fl & (QED_EMIT | QED_PAIR)) && !photons_ok(&in->photons)) return false;

@@ -311,6 +311,26 @@ qed_status emit_impl(qed_tables T, const qed_leptons *L, const qed_fields *f, co
     const size_t lds_nlc = sizeof(R) * 2 * T->dev.n_chi[0];
     const int g = grid_for(L->capacity);
     const bool grid = general_leptons(f, p->flags);
+    if (p->flags & QED_SUBCYCLE) {
+        // the QED part in kSubRounds rounds of streaming pass, expansion and processing; the push
+        // only in round 0; each round appends its photons after the previous round's
+        LepDev<R> ls = ld;
+        ls.msub = w.msub;
+        const PhoDev<R> gs = pho_dev<R>((p->flags & QED_EMIT) ? G : nullptr);
+        for (int r = 0; r < kSubRounds; ++r) {
+            StepDev sr = sd;
+            sr.sub_round = r;
+            if (r > 0) sr.flags &= ~(uint32_t)QED_PUSH;
+            QS_LAUNCH(K_LEPTON_MAIN, (k_lepton_main<R, 4, true>), dim3(g), dim3(kBlock), lds_nlc, st, ls, fd, sr, T->dev,
+                      w.mask, nch, w.bctr, w.bcnt);
+            QS_LAUNCH(K_MASK_EXPAND, k_expand, dim3(g), dim3(kBlock), 0, st, (const uint64_t *)w.mask,
+                      (const uint32_t *)w.bcnt, (const int64_t *)L->d_count, w.book, 0, gs.count, gs.cap,
+                      (int64_t *)nullptr, (int64_t)0, (int64_t *)nullptr, c, (const uint32_t *)w.bctr, w.idx);
+            QS_LAUNCH(K_EMIT_PROCESS, (k_emit_process<R, true>), dim3(g), dim3(kBlock), lds_nlc, st, ls, gs, fd, sr,
+                      T->dev, w.mask, nch, w.idx, w.book, c);
+        }
+        return qs_launch_status(__func__);
+    }
     if (p->flags & QED_OPTICAL_DEPTH)
         QS_LAUNCH(K_LEPTON_MAIN, (k_lepton_main<R, 1, true>), dim3(g), dim3(kBlock), lds_nlc, st, ld, fd, sd, T->dev,
                   w.mask, nch, w.bctr, w.bcnt);
@@ -367,7 +387,8 @@ extern "C" size_t qed_workspace_size(int64_t max_particles)
     const int64_t cap = max_particles > 0 ? max_particles : 1;
     const int64_t nch = cdiv(cap, 64);
     return align256(sizeof(uint64_t) * 2 * nch) + align256(sizeof(uint32_t) * kMaxGrid) +
-           align256(sizeof(int64_t) * 8) + align256(sizeof(uint32_t) * kMaxGrid * kNCtr) + align256(sizeof(uint32_t) * cap);
+           align256(sizeof(int64_t) * 8) + align256(sizeof(uint32_t) * kMaxGrid * kNCtr) + align256(sizeof(uint32_t) * cap) +
+           align256(sizeof(uint8_t) * cap);
 }
 
 extern "C" qed_status qed_push_spin(const qed_leptons *L, const qed_fields *f, const qed_step_params *p, qed_tables T,
@@ -393,6 +414,7 @@ extern "C" qed_status qed_emit(qed_tables T, const qed_leptons *L, const qed_fie
     if ((p->flags & QED_EMIT) && !photons_ok(G)) return QED_ERR_INVALID;
     if (!tau_ok(L, p->flags)) return QED_ERR_INVALID;
     if ((p->flags & QED_REJECTION) && (p->flags & QED_OPTICAL_DEPTH)) return QED_ERR_INVALID;
+    if ((p->flags & QED_SUBCYCLE) && (p->flags & (QED_REJECTION | QED_OPTICAL_DEPTH))) return QED_ERR_INVALID;
     if (!(p->dt > 0.0) || !(p->eps_r > 0.0)) return QED_ERR_INVALID;
     if (ws_bytes < qed_workspace_size(L->capacity)) return QED_ERR_CAPACITY;
     hipStream_t st = (hipStream_t)stream;

@@ -1,0 +1,158 @@
+"""GPU parity of the per-particle sub-cycling of the lepton step (QED_SUBCYCLE; decision-making
+section): the test-particle workload (W dt ~ 0.95, 16 sub-steps) over 100 steps and a mixed
+population in one step (1 to 16 sub-steps) in FP64, one step in FP32, and bit equality with the
+plain step where every lepton is below W dt = 0.1, all against the oracle on the same inputs."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from parity import compare_leptons, compare_photons, oracle_run
+
+pytestmark = pytest.mark.gpu
+EPS = synth.EPS_R
+
+
+def tol_k(steps):
+    return 1e-12 * max(1.0, steps / 250.0)
+
+
+@pytest.fixture(scope="module")
+def q():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("GPU test run without a GPU")
+    import paper_2511_08929_amd as q
+    q.lib()
+    return q
+
+
+@pytest.fixture(scope="module")
+def gtab64(q):
+    return q.Tables(precision=q.QED_F64)
+
+
+@pytest.fixture(scope="module")
+def gtab32(q):
+    return q.Tables(precision=q.QED_F32)
+
+
+def _sim(q, tab, w, cap_e, cap_p, cap_g, flags, merged=False, k_retire=None):
+    from paper_2511_08929_amd.sim import Simulation
+    f = q.make_fields(w.field_kind, E0=w.E0, B0=w.B0, a0=w.a0, phase_len=w.phase_len)
+    return Simulation(tab, cap_e=cap_e, cap_p=cap_p, cap_g=cap_g, track=w.track, fields=f, dt=w.dt, eps_r=EPS,
+                      seed=w.seed, flags=flags, k_retire=w.k_retire if k_retire is None else k_retire,
+                      merged=merged)
+
+
+def _workload(n, dt, seed=41, B0=(0.0, 0.0, 160.0), E0=(0.0, 40.0, 0.0)):
+    """Random leptons (gamma log-uniform in [30, 2e4], isotropic, partly polarized) in a strong
+    uniform field."""
+    rng = np.random.default_rng(seed)
+    d = synth.random_unit_vectors(rng, n)
+    g = np.exp(rng.uniform(math.log(30.0), math.log(2e4), n))
+    p = d * np.sqrt(g * g - 1)
+    s = synth.random_unit_vectors(rng, n) * np.where(rng.random(n) < 0.2, rng.uniform(0, 1, n), 1.0)
+    x = np.stack([rng.uniform(0, 200, n), rng.uniform(-5, 5, n), rng.uniform(-5, 5, n)])
+    w = synth.Workload("random_leptons_uniform_field", n, 1, dt, seed, synth.FIELD_UNIFORM, E0=E0, B0=B0,
+                       track=(True, True, True))
+    w.x, w.p, w.s = x, p, s
+    return w
+
+
+def _rounds(ids):
+    ids = ids.astype(np.uint64)
+    return ((ids >> np.uint64(57)) & np.uint64(15)).astype(np.int64)
+
+
+def test_subcycle_c1_run_fp64(q, gtab64, otables):
+    """512 electrons of the test-particle workload for 100 steps, every particle and photon."""
+    w = synth.c1(n=512)
+    steps = 100
+    flags = (q.QED_ALL & ~q.QED_PAIR) | q.QED_SUBCYCLE
+    cap_g = w.n * steps * 3
+    sim = _sim(q, gtab64, w, w.n, 1, cap_g, flags)
+    sim.e.load(w.x, w.p, w.s)
+    for _ in range(steps):
+        sim.step()
+    ref = oracle_run(otables, w, steps, flags, cap_g=cap_g)
+    ex = ref["near_e"]
+    c = q.counters_dict(sim.ctr)
+    print("sub-cycled c1: near", int(ex.sum()), "gpu", c, "oracle", ref["ctr"])
+    assert ex.sum() == 0 and c["n_emit"] == ref["ctr"]["n_emit"] > 30_000 and c["n_prob_clamped"] == 0
+    assert c["n_lepton_steps"] == w.n * steps
+    rounds = _rounds(sim.g.arrays()[3])
+    assert len(np.unique(rounds)) == 16          # every lepton takes 16 sub-steps here
+    compare_leptons(sim.e.arrays(), ref["E"].arrays(), ex, tol_k(steps), tol_k(steps), what="sub-cycled c1 leptons",
+                    events=c["n_emit"])
+    compare_photons(sim.g.arrays(), ref["G"].arrays(), set(), tol_k(steps), tol_k(steps),
+                    what="sub-cycled c1 photons")
+
+
+def test_subcycle_mixed_step_fp64(q, gtab64, otables):
+    """One step of 1000 leptons (ragged) with W dt from below 0.1 to 1: 1 to 16 sub-steps."""
+    n = 1000
+    w = _workload(n, dt=0.5)
+    flags = (q.QED_ALL & ~q.QED_PAIR) | q.QED_SUBCYCLE
+    sim = _sim(q, gtab64, w, n, 1, 20 * n, flags, k_retire=0.0)
+    sim.e.load(w.x, w.p, w.s)
+    sim.step()
+    ref = oracle_run(otables, w, 1, flags, cap_g=20 * n, k_retire=0.0)
+    ex = ref["near_e"]
+    c = q.counters_dict(sim.ctr)
+    print("sub-cycled mixed: near", int(ex.sum()), "gpu", c, "oracle", ref["ctr"])
+    assert ex.sum() <= 2 and ref["ctr"]["n_emit"] > 300
+    gids = sim.g.arrays()[3]
+    assert len(np.unique(_rounds(gids))) == 16 and np.bincount(_rounds(gids))[0] < len(gids)
+    compare_leptons(sim.e.arrays(), ref["E"].arrays(), ex, 1e-12, 1e-12, rtol_x=1e-12, what="sub-cycled leptons")
+    compare_photons(sim.g.arrays(), ref["G"].arrays(), {(0, int(i)) for i in np.nonzero(ex)[0]}, 1e-12, 1e-12,
+                    what="sub-cycled photons")
+    assert c["n_emit"] == ref["ctr"]["n_emit"] or ex.sum() > 0
+
+
+def test_subcycle_step_fp32(q, gtab32, otables):
+    n = 4000
+    w = _workload(n, dt=0.5)
+    w.x, w.p, w.s = (a.astype(np.float32).astype(np.float64) for a in (w.x, w.p, w.s))
+    flags = (q.QED_ALL & ~q.QED_PAIR) | q.QED_SUBCYCLE
+    sim = _sim(q, gtab32, w, n, 1, 20 * n, flags, k_retire=0.0)
+    sim.e.load(w.x, w.p, w.s)
+    sim.step()
+    ref = oracle_run(otables, w, 1, flags, cap_g=20 * n, k_retire=0.0, u24=True, near_tol=1e-5)
+    ex = ref["near_e"]
+    print("sub-cycled fp32: near-tie fraction", ex.mean(), "emitted", ref["ctr"]["n_emit"])
+    assert ex.mean() < 0.01 and ref["ctr"]["n_emit"] > 500
+    compare_leptons(sim.e.arrays(), ref["E"].arrays(), ex, 1e-5, 1e-5, what="sub-cycled fp32 leptons")
+    compare_photons(sim.g.arrays(), ref["G"].arrays(), {(0, int(i)) for i in np.nonzero(ex)[0]}, 1e-5, 1e-5,
+                    what="sub-cycled fp32 photons")
+
+
+def test_subcycle_below_threshold_is_plain_step(q, gtab64):
+    """Where every lepton has W dt <= 0.1 the sub-cycled step equals the plain one bit for bit."""
+    n = 2000
+    w = _workload(n, dt=0.03)                   # largest W dt about 0.06
+    base = (q.QED_ALL & ~q.QED_PAIR)
+    out = []
+    for flags in (base, base | q.QED_SUBCYCLE):
+        sim = _sim(q, gtab64, w, n, 1, 2 * n, flags, k_retire=0.0)
+        sim.e.load(w.x, w.p, w.s)
+        for _ in range(3):
+            sim.step()
+        out.append((sim.e.arrays(), sim.g.arrays(), q.counters_dict(sim.ctr)))
+    assert out[0][2]["n_emit"] > 20 and out[0][2] == out[1][2]
+    for u, v in zip(out[0][0] + out[0][1], out[1][0] + out[1][1]):
+        np.testing.assert_array_equal(u, v)
+
+
+def test_subcycle_rejected_in_plans_and_with_other_decisions(q, gtab64):
+    w = _workload(64, dt=0.1)
+    with pytest.raises(Exception):
+        sim = _sim(q, gtab64, w, 64, 1, 128, q.QED_ALL | q.QED_SUBCYCLE, merged=True)
+        sim.e.load(w.x, w.p, w.s)
+        sim.step()
+    with pytest.raises(Exception):
+        sim = _sim(q, gtab64, w, 64, 1, 128, (q.QED_ALL & ~q.QED_PAIR) | q.QED_SUBCYCLE | q.QED_REJECTION)
+        sim.e.load(w.x, w.p, w.s)
+        sim.step()
