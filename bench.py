@@ -351,6 +351,53 @@ def extras(q, args, w, t32, t64, out, v32, v64):
     out["cascade"] = dict(workload="seeded pair cascade, rotating E field a0 = 1000, 20000 electrons from rest, "
                                    "omega t = 16 (3200 steps of 0.005)", unit="particle-QED-steps/s",
                           speedup_fp32_vs_fp64=round(rc["fp32"]["value"] / rc["fp64"]["value"], 3), **rc)
+    out["subcycle"] = subcycle_study(q, t64)
+
+
+def subcycle_study(q, tab, n=100_000, steps=200):
+    """Per-particle sub-cycling in the test-particle workload (W dt ~ 0.95 at the start): the
+    electrons' mean energy loss and mean s.beta after `steps` steps with the plain step and with
+    sub-cycling, against the plain step at dt/16 (16 x the steps), and the throughput of both (eager
+    per-species calls, FP64, lepton-steps per second)"""
+    import torch
+    from paper_2511_08929_amd.sim import Simulation
+    w = synth.c1(n=n)
+    base = q.QED_ALL & ~q.QED_PAIR
+    g0 = w.extra["gamma0"]
+
+    def run(dt, nsteps, flags, every):
+        sim = Simulation(tab, cap_e=n, cap_p=1, cap_g=24 * n, track=w.track, fields=q.make_fields(w.field_kind, B0=w.B0),
+                         dt=dt, eps_r=synth.EPS_R, seed=w.seed, flags=flags, k_retire=1e30)
+        sim.e.load(w.x, w.p, w.s)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for k in range(nsteps):
+            sim.step()
+            if k % every == every - 1:
+                sim.compact()
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        _, p, s = sim.e.arrays()
+        gam = np.sqrt(1 + np.sum(p * p, axis=0))
+        c = q.counters_dict(sim.ctr)
+        assert c["n_capacity_overflow"] == 0, c
+        return dict(loss=float(g0 - gam.mean()), s_beta=float(-s[2].mean()), wall=wall, emitted=c["n_emit"],
+                    rate=n * nsteps / wall)
+
+    ref = run(w.dt / 16, 16 * steps, base, 160)
+    plain = run(w.dt, steps, base, 10)
+    sub = run(w.dt, steps, base | q.QED_SUBCYCLE, 10)
+    res = {"workload": f"test particle in a uniform B (chi = 1, gamma0 = 2000), {n} electrons, {steps} steps of "
+                       "1/100 gyro period (W dt ~ 0.95), FP64",
+           "unit": "lepton-steps/s", "value": round(sub["rate"], 1), "plain_value": round(plain["rate"], 1)}
+    for key, r in (("reference_dt_over_16", ref), ("plain", plain), ("subcycled", sub)):
+        res[key] = {"mean_energy_loss": round(r["loss"], 3), "mean_s_beta": round(r["s_beta"], 5),
+                    "photons": r["emitted"]}
+    for key, r in (("plain", plain), ("subcycled", sub)):
+        res[key]["energy_loss_rel_error"] = round(abs(r["loss"] / ref["loss"] - 1), 5)
+        res[key]["s_beta_abs_error"] = round(abs(r["s_beta"] - ref["s_beta"]), 5)
+    log(f"sub-cycling: {res}")
+    return res
 
 
 def full_scale(q, args, t32, t64, out):
