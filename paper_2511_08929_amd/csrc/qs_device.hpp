@@ -295,10 +295,14 @@ template <class R> __device__ __forceinline__ void add_grid(const FieldDev &f, d
 }
 
 // E and B at position (x, y) (the plane wave depends on x only, the grid on x and y) and time t.
-// GRID: compiled with the grid model (kernels without it keep fewer registers live).
-template <class R, bool GRID> struct FieldEval;
+// Field-model variants of the kernels (each keeps only the registers its models need):
+// kFldPlain: uniform and plane wave; kFldRotating: also the rotating field; kFldGeneral: also the
+// grid (and, in the lepton pass, the field-dependent g).
+enum : int { kFldPlain = 0, kFldRotating = 1, kFldGeneral = 2 };
 
-template <bool GRID> struct FieldEval<double, GRID> {
+template <class R, int FLD> struct FieldEval;
+
+template <int FLD> struct FieldEval<double, FLD> {
 static __device__ __forceinline__ void eval(const FieldDev &f, double x0, double y0, double t, V3<double> &E,
                                             V3<double> &B)
 {
@@ -315,10 +319,10 @@ static __device__ __forceinline__ void eval(const FieldDev &f, double x0, double
         const double ey = f.a0 * g * cos(phi);
         E.y += ey;
         B.z -= ey;
-    } else if (GRID && f.kind == 3) {
+    } else if (FLD >= kFldRotating && f.kind == 3) {
         E.x += f.a0 * cos(t);
         E.y += f.a0 * sin(t);
-    } else if (GRID && f.kind == 2) {
+    } else if (FLD == kFldGeneral && f.kind == 2) {
         add_grid<double>(f, x0, y0, E, B);
     }
 }
@@ -326,7 +330,7 @@ static __device__ __forceinline__ void eval(const FieldDev &f, double x0, double
 
 // single precision: the phase is formed and reduced to revolutions in FP64; the sine and
 // cosine of the reduced argument use the hardware instructions (|argument| <= 1 revolution)
-template <bool GRID> struct FieldEval<float, GRID> {
+template <int FLD> struct FieldEval<float, FLD> {
 static __device__ __forceinline__ void eval(const FieldDev &f, double x0, double y0, double t, V3<float> &E,
                                             V3<float> &B)
 {
@@ -346,23 +350,22 @@ static __device__ __forceinline__ void eval(const FieldDev &f, double x0, double
         const float ey = (float)f.a0 * g * __builtin_amdgcn_cosf(red);
         E.y += ey;
         B.z -= ey;
-    } else if (GRID && f.kind == 3) {
+    } else if (FLD >= kFldRotating && f.kind == 3) {
         const double rev = t * (0.5 / kPi);
         const float red = (float)(rev - rint(rev));
         E.x += (float)f.a0 * __builtin_amdgcn_cosf(red);
         E.y += (float)f.a0 * __builtin_amdgcn_sinf(red);
-    } else if (GRID && f.kind == 2) {
+    } else if (FLD == kFldGeneral && f.kind == 2) {
         add_grid<float>(f, x0, y0, E, B);
     }
 }
 };
 
-// GRID: the general variant, with the grid and the rotating field (the plane-wave and uniform
-// models need fewer registers without them)
-template <class R, bool GRID = true>
+// FLD: the field-model variant (kFldPlain, kFldRotating, kFldGeneral)
+template <class R, int FLD = kFldGeneral>
 __device__ __forceinline__ void eval_fields(const FieldDev &f, double x0, double y0, double t, V3<R> &E, V3<R> &B)
 {
-    FieldEval<R, GRID>::eval(f, x0, y0, t, E, B);
+    FieldEval<R, FLD>::eval(f, x0, y0, t, E, B);
 }
 
 // ------------------------------------------------------------------ push (Boris + T-BMT)

@@ -86,9 +86,9 @@ template <> __device__ __forceinline__ const float *rate_src<float>(const Tables
 
 // the g-factor table of the push when the step asks for the field-dependent anomalous moment
 // (compiled into the general variants only), else NULL
-template <class R, bool GRID> __device__ __forceinline__ const R *gfac_src(const TablesDev &T, uint32_t flags)
+template <class R, int FLD> __device__ __forceinline__ const R *gfac_src(const TablesDev &T, uint32_t flags)
 {
-    if (!GRID || !(flags & F_GCHI)) return nullptr;
+    if (FLD != kFldGeneral || !(flags & F_GCHI)) return nullptr;
     if constexpr (sizeof(R) == 8) return (const R *)T.lng;
     else return (const R *)T.lng32;
 }
@@ -302,7 +302,7 @@ struct LCount { unsigned prob = 0, chi = 0, norm = 0, step = 0, trans = 0; };
 // Sub-cycling (bit 2) runs the QED part in kSubRounds launches (S.sub_round): round 0 pushes and
 // sets the lepton's sub-steps 2^k from W_s dt; a lepton takes its sub-steps of dt/2^k in the
 // rounds that are multiples of kSubRounds/2^k and leaves its state alone in the others.
-template <class R, int DEC, bool GRID>
+template <class R, int DEC, int FLD>
 __device__ __forceinline__ void lepton_item(const LepDev<R> &L, const FieldDev &F, const StepDev &S, const TablesDev &T,
                                             const R *lds, int64_t i, V3<R> x, V3<R> p, V3<R> s, bool &emit, bool &up,
                                             LCount &c)
@@ -322,12 +322,12 @@ __device__ __forceinline__ void lepton_item(const LepDev<R> &L, const FieldDev &
     }
     V3<R> E, B;
     if (S.flags & F_PUSH) {
-        eval_fields<R, GRID>(F, (double)x.x, (double)x.y, S.t, E, B);
-        x = x + push<R>(q, (R)S.a_e, E, B, (R)S.dt, (S.flags & F_TBMT) != 0, p, s, gfac_src<R, GRID>(T, S.flags),
+        eval_fields<R, FLD>(F, (double)x.x, (double)x.y, S.t, E, B);
+        x = x + push<R>(q, (R)S.a_e, E, B, (R)S.dt, (S.flags & F_TBMT) != 0, p, s, gfac_src<R, FLD>(T, S.flags),
                         (R)S.eps_r);
     }
     if (S.flags & F_EMIT) {
-        eval_fields<R, GRID>(F, (double)x.x, (double)x.y, S.t + S.dt, E, B);
+        eval_fields<R, FLD>(F, (double)x.x, (double)x.y, S.t + S.dt, E, B);
         LDecide<R> d = lepton_decide<R>(S, T, lds, L.species, i, p, s, E, B);
         if constexpr ((DEC & 4) != 0) {
             if (d.active) {
@@ -406,7 +406,7 @@ __device__ __forceinline__ void lepton_item(const LepDev<R> &L, const FieldDev &
 
 // Main pass over the lepton range [start, end) (start a multiple of 64): the wave's decisions
 // and branch choices go to mask[w] and mask[nchunks + w] of its 64-particle word w.
-template <class R, int DEC, bool GRID>
+template <class R, int DEC, int FLD>
 __device__ __forceinline__ void lepton_range(const LepDev<R> &L, const FieldDev &F, const StepDev &S, const TablesDev &T,
                                              const R *lds, int64_t start, int64_t end, uint64_t *mask, int64_t nchunks,
                                              LCount &c)
@@ -424,7 +424,7 @@ __device__ __forceinline__ void lepton_range(const LepDev<R> &L, const FieldDev 
         const int64_t inext = i + blockDim.x;
         if (inext < end) { xn = ldx(L.x, inext); pn = ld3(L.p, inext); sn = ld3(L.s, inext); }
         bool emit = false, up = false;
-        if (i < end) lepton_item<R, DEC, GRID>(L, F, S, T, lds, i, x, p, s, emit, up, c);
+        if (i < end) lepton_item<R, DEC, FLD>(L, F, S, T, lds, i, x, p, s, emit, up, c);
         const uint64_t m = __ballot(emit), mu = __ballot(up);
         if (lane == 0) {
             mask[base >> 6] = m;
@@ -438,7 +438,7 @@ __device__ __forceinline__ void lepton_range(const LepDev<R> &L, const FieldDev 
 // recoil, spin collapse, Stokes collapse, P-vector; the photon goes to slot `slot` (< 0: no room).
 // With x_out set, only the inputs of the inverse CDF (ln chi, rho, channel sign) are written there;
 // with nu_in set, nu is taken from it instead of the table (learned inverse CDF).
-template <class R, bool GRID>
+template <class R, int FLD>
 __device__ __forceinline__ void emit_item(const LepDev<R> &L, const PhoDev<R> &G, const FieldDev &F, const StepDev &S,
                                           const TablesDev &T, const R *lds, int64_t i, bool up, int64_t slot,
                                           unsigned &c_ret, const float *nu_in = nullptr, float *x_out = nullptr)
@@ -446,7 +446,7 @@ __device__ __forceinline__ void emit_item(const LepDev<R> &L, const PhoDev<R> &G
     const V3<R> x = ldx(L.x, i);
     V3<R> p = ld3(L.p, i), s = ld3(L.s, i);
     V3<R> E, B;
-    eval_fields<R, GRID>(F, (double)x.x, (double)x.y, S.t + S.dt, E, B);
+    eval_fields<R, FLD>(F, (double)x.x, (double)x.y, S.t + S.dt, E, B);
     const LDecide<R> d = lepton_decide<R>(S, T, lds, L.species, i, p, s, E, B);
     const double r2 = (double)d.r2;
     const double rho = log(r2) - log1p(-r2);
@@ -535,7 +535,7 @@ template <class R> struct PhoQueue {
     uint32_t n;
 };
 
-template <class R, bool GRID>
+template <class R, int FLD>
 __device__ __forceinline__ void photon_tile(const PhoDev<R> &G, const FieldDev &F, const StepDev &S, const TablesDev &T,
                                             const R *lds, PhoQueue<R> &Q, int64_t tile, int64_t tend, uint64_t *mask,
                                             int64_t nchunks, GCount &c)
@@ -582,10 +582,10 @@ __device__ __forceinline__ void photon_tile(const PhoDev<R> &G, const FieldDev &
                 ++c.ret;
             } else if (qed) {
                 V3<R> E, Bf;
-                eval_fields<R, GRID>(F, (double)x.x, (double)x.y, S.t + S.dt, E, Bf);
+                eval_fields<R, FLD>(F, (double)x.x, (double)x.y, S.t + S.dt, E, Bf);
                 cand = photon_candidate<R>(S, k0r, E, Bf);
                 xq = x.x;
-                if (GRID) yq = x.y;
+                if (FLD == kFldGeneral) yq = x.y;
             }
         }
         const uint64_t m = __ballot(cand);
@@ -597,7 +597,7 @@ __device__ __forceinline__ void photon_tile(const PhoDev<R> &G, const FieldDev &
             Q.idx[r] = (uint32_t)(i - tile);
             Q.id[r] = idv[u];
             Q.x[r] = xq;
-            if (GRID) Q.y[r] = yq;
+            if (FLD == kFldGeneral) Q.y[r] = yq;
             Q.k[0][r] = kv[u].x;
             Q.k[1][r] = kv[u].y;
             Q.k[2][r] = kv[u].z;
@@ -613,7 +613,7 @@ __device__ __forceinline__ void photon_tile(const PhoDev<R> &G, const FieldDev &
         const V3<R> k = {Q.k[0][j], Q.k[1][j], Q.k[2][j]};
         const double k0 = (double)sqrt_r(dot(k, k));
         V3<R> E, Bf;
-        eval_fields<R, GRID>(F, (double)Q.x[j], GRID ? (double)Q.y[j] : 0.0, S.t + S.dt, E, Bf);
+        eval_fields<R, FLD>(F, (double)Q.x[j], FLD == kFldGeneral ? (double)Q.y[j] : 0.0, S.t + S.dt, E, Bf);
         const PDecide<R> d = photon_decide<R>(S, T, lds, id, k, k0, P, E, Bf);
         if (!d.active) continue;
         ++c.qed;
@@ -654,7 +654,7 @@ __device__ __forceinline__ void photon_tile(const PhoDev<R> &G, const FieldDev &
 // Pair processing (NBW section, after the decision): lambda~ from the selected inverse CDF,
 // momenta, correlated spins; the pair goes to slots se (electrons) and sp (positrons) when
 // se >= 0; the photon becomes a dead slot.
-template <class R, bool GRID>
+template <class R, int FLD>
 __device__ __forceinline__ void pair_item(const PhoDev<R> &G, const LepDev<R> &Le, const LepDev<R> &Lp, const FieldDev &F,
                                           const StepDev &S, const TablesDev &T, const R *lds, int64_t i, bool plus,
                                           int64_t se, int64_t sp, const float *nu_in = nullptr, float *x_out = nullptr)
@@ -663,7 +663,7 @@ __device__ __forceinline__ void pair_item(const PhoDev<R> &G, const LepDev<R> &L
     const V3<R> k = ld3(G.k, i), x = ldx(G.x, i), P = ld3(G.P, i);
     const double k0 = (double)sqrt_r(dot(k, k));
     V3<R> E, B;
-    eval_fields<R, GRID>(F, (double)x.x, (double)x.y, S.t + S.dt, E, B);
+    eval_fields<R, FLD>(F, (double)x.x, (double)x.y, S.t + S.dt, E, B);
     const PDecide<R> d = photon_decide<R>(S, T, lds, id, k, k0, P, E, B);
     const double r2 = (double)d.r2;
     const double rho = log(r2) - log1p(-r2);
@@ -828,14 +828,17 @@ inline bool photons_ok(const qed_photons *G)
     return true;
 }
 
-// field models compiled only into the general (GRID) variants: the grid and the rotating field
-inline bool general_fields(const qed_fields *f)
+// the field-model variant a field needs (the variants are nested: general > rotating > plain)
+inline int field_variant(const qed_fields *f)
 {
-    return f->kind == QED_FIELD_GRID2D || f->kind == QED_FIELD_ROTATING_E;
+    return f->kind == QED_FIELD_GRID2D ? kFldGeneral : f->kind == QED_FIELD_ROTATING_E ? kFldRotating : kFldPlain;
 }
 
-// lepton passes that need the general variant: its field models or the field-dependent g
-inline bool general_leptons(const qed_fields *f, uint32_t flags) { return general_fields(f) || (flags & QED_G_CHI); }
+// the lepton pass's variant: the field's, or the general one for the field-dependent g
+inline int lepton_variant(const qed_fields *f, uint32_t flags)
+{
+    return (flags & QED_G_CHI) ? (int)kFldGeneral : field_variant(f);
+}
 
 inline bool fields_ok(const qed_fields *f)
 {

@@ -23,6 +23,7 @@
 // The appends keep the order of the per-species calls: photons of electrons, then of
 // positrons, in emitter order; pairs in photon order.  So a plan step gives the same particles,
 // bit for bit, as qed_emit(electrons), qed_emit(positrons), qed_pair, qed_clock_advance.
+#include <algorithm>
 #include <vector>
 
 #include "qs_mlp.hpp"
@@ -83,7 +84,7 @@ struct PlanDev {
 
 // The streaming pass runs as two launches with their own register allocation: PHO = 0 over the
 // lepton segments (blocks [0, nblk_lep)), PHO = 1 over the photon segments (the rest).
-template <class R, int PHO, int DEC, bool GRID>
+template <class R, int PHO, int DEC, int FLD>
 __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 ? 4 : 1))) k_plan_main(const InstDev<R> *inst, PlanDev P, TablesDev T, int b_first)
 {
     extern __shared__ unsigned char smem_raw[];
@@ -116,7 +117,7 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(siz
         const int64_t B = block_len(n, sg.nb);
         const int64_t start = (int64_t)(b - sg.b0) * B, end = start + B < n ? start + B : n;
         LCount c;
-        lepton_range<R, DEC, GRID>(L, F, S, T, lds, start, end, mask, sg.nchunks, c);
+        lepton_range<R, DEC, FLD>(L, F, S, T, lds, start, end, mask, sg.nchunks, c);
         v[C_PROB] = c.prob; v[C_CHI] = c.chi; v[C_NORM] = c.norm; v[C_LSTEP] = c.step; v[kNCtr] = c.trans;
     } else {
         const PhoDev<R> G = Ip->G;
@@ -126,7 +127,7 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(siz
         const int64_t start = (int64_t)(b - sg.b0) * B, end = start + B < n ? start + B : n;
         GCount c;
         for (int64_t tile = start; tile < end; tile += kPhoTile)
-            photon_tile<R, GRID>(G, F, S, T, lds, Q, tile, tile + kPhoTile < end ? tile + kPhoTile : end, mask, sg.nchunks,
+            photon_tile<R, FLD>(G, F, S, T, lds, Q, tile, tile + kPhoTile < end ? tile + kPhoTile : end, mask, sg.nchunks,
                                  c);
         v[C_PROB] = c.prob; v[C_CHI] = c.chi; v[C_NORM] = c.norm; v[C_RETIRED] = c.ret; v[C_GSTEP] = c.step;
         v[C_GQED] = c.qed; v[kNCtr] = c.trans;
@@ -178,7 +179,7 @@ template <> struct SurLds<false> {
 // per thread: each thread writes its transition's network inputs to LDS, the waves run the
 // network on the round's rows (16 per forward pass), and each thread finishes its transition
 // with its nu.
-template <class R, bool GRID, bool SUR>
+template <class R, int FLD, bool SUR>
 __global__ void __launch_bounds__(kBlock) k_plan_process(const InstDev<R> *inst, PlanDev P, TablesDev T, int b_first)
 {
     extern __shared__ unsigned char smem_raw[];
@@ -317,10 +318,10 @@ __global__ void __launch_bounds__(kBlock) k_plan_process(const InstDev<R> *inst,
             const int64_t r = rank0 + j;
             const bool br = (mask[sg.nchunks + (i >> 6)] >> (i & 63)) & 1ull;
             if (!PHO)
-                emit_item<R, GRID>(sg.kind == 0 ? Ip->E : Ip->P, Ip->G, F, S, Tl, lds, i, br, r < bk.nfit ? bk.base + r : -1,
+                emit_item<R, FLD>(sg.kind == 0 ? Ip->E : Ip->P, Ip->G, F, S, Tl, lds, i, br, r < bk.nfit ? bk.base + r : -1,
                                    c_ret, nu_in, x_out);
             else
-                pair_item<R, GRID>(Ip->G, Ip->E, Ip->P, F, S, Tl, lds, i, br, r < bk.nfit ? bk.base + r : -1, bk.base2 + r,
+                pair_item<R, FLD>(Ip->G, Ip->E, Ip->P, F, S, Tl, lds, i, br, r < bk.nfit ? bk.base + r : -1, bk.base2 + r,
                                    nu_in, x_out);
         };
         if (net) {
@@ -375,8 +376,8 @@ struct qed_plan_s {
     Snap *d_snap;
     qed_surrogate sur[2];      // learned inverse CDF per process (NULL: tables)
     int dec;                   // decision variants needed (bit 0: optical depth, bit 1: rejection)
-    bool grid;                 // some instance uses a field model beyond the uniform and plane-wave ones
-    bool glep;                 // the lepton pass needs the general variant (grid, or the field-dependent g)
+    int fv;                    // field-model variant the instances need (the largest of field_variant)
+    int flep;                  // the lepton pass's (the largest of lepton_variant)
     size_t lds;
 };
 
@@ -482,13 +483,13 @@ qed_status plan_create(qed_tables T, int n, const qed_instance *in, int ppb, int
     p->sur[0] = s_nlc;
     p->sur[1] = s_nbw;
     p->dec = 0;
-    p->grid = false;
-    p->glep = false;
+    p->fv = kFldPlain;
+    p->flep = kFldPlain;
     for (int i = 0; i < n; ++i) {
         if (in[i].params.flags & QED_OPTICAL_DEPTH) p->dec |= 1;
         if (in[i].params.flags & QED_REJECTION) p->dec |= 2;
-        p->grid = p->grid || general_fields(&in[i].fields);
-        p->glep = p->glep || general_leptons(&in[i].fields, in[i].params.flags);
+        p->fv = std::max(p->fv, field_variant(&in[i].fields));
+        p->flep = std::max(p->flep, lepton_variant(&in[i].fields, in[i].params.flags));
     }
     if (e == hipSuccess) e = hipMemcpy(p->d_inst, inst.data(), sizeof(InstDev<R>) * n, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(p->d_seg, seg.data(), sizeof(SegDev) * seg.size(), hipMemcpyHostToDevice);
@@ -556,28 +557,34 @@ template <class R> qed_status plan_step(qed_plan p, hipStream_t st)
     const InstDev<R> *inst = (const InstDev<R> *)p->d_inst;
     if (p->nblk_lep > 0) {
         if (p->dec == 3)
-            QS_LAUNCH(K_PLAN_LEPTON, (k_plan_main<R, 0, 3, true>), dim3(p->nblk_lep), dim3(kBlock), p->lds, st, inst, P,
+            QS_LAUNCH(K_PLAN_LEPTON, (k_plan_main<R, 0, 3, kFldGeneral>), dim3(p->nblk_lep), dim3(kBlock), p->lds, st, inst, P,
                       p->T->dev, 0);
         else if (p->dec == 2)
-            QS_LAUNCH(K_PLAN_LEPTON, (k_plan_main<R, 0, 2, true>), dim3(p->nblk_lep), dim3(kBlock), p->lds, st, inst, P,
+            QS_LAUNCH(K_PLAN_LEPTON, (k_plan_main<R, 0, 2, kFldGeneral>), dim3(p->nblk_lep), dim3(kBlock), p->lds, st, inst, P,
                       p->T->dev, 0);
         else if (p->dec == 1)
-            QS_LAUNCH(K_PLAN_LEPTON, (k_plan_main<R, 0, 1, true>), dim3(p->nblk_lep), dim3(kBlock), p->lds, st, inst, P,
+            QS_LAUNCH(K_PLAN_LEPTON, (k_plan_main<R, 0, 1, kFldGeneral>), dim3(p->nblk_lep), dim3(kBlock), p->lds, st, inst, P,
                       p->T->dev, 0);
-        else if (p->glep)
-            QS_LAUNCH(K_PLAN_LEPTON, (k_plan_main<R, 0, 0, true>), dim3(p->nblk_lep), dim3(kBlock), p->lds, st, inst, P,
-                      p->T->dev, 0);
+        else if (p->flep == kFldGeneral)
+            QS_LAUNCH(K_PLAN_LEPTON, (k_plan_main<R, 0, 0, kFldGeneral>), dim3(p->nblk_lep), dim3(kBlock), p->lds, st,
+                      inst, P, p->T->dev, 0);
+        else if (p->flep == kFldRotating)
+            QS_LAUNCH(K_PLAN_LEPTON, (k_plan_main<R, 0, 0, kFldRotating>), dim3(p->nblk_lep), dim3(kBlock), p->lds, st,
+                      inst, P, p->T->dev, 0);
         else
-            QS_LAUNCH(K_PLAN_LEPTON, (k_plan_main<R, 0, 0, false>), dim3(p->nblk_lep), dim3(kBlock), p->lds, st, inst, P,
-                      p->T->dev, 0);
+            QS_LAUNCH(K_PLAN_LEPTON, (k_plan_main<R, 0, 0, kFldPlain>), dim3(p->nblk_lep), dim3(kBlock), p->lds, st,
+                      inst, P, p->T->dev, 0);
     }
     if (p->nblk > p->nblk_lep) {
-        if (p->grid)
-            QS_LAUNCH(K_PLAN_PHOTON, (k_plan_main<R, 1, 0, true>), dim3(p->nblk - p->nblk_lep), dim3(kBlock), p->lds, st,
-                      inst, P, p->T->dev, p->nblk_lep);
+        if (p->fv == kFldGeneral)
+            QS_LAUNCH(K_PLAN_PHOTON, (k_plan_main<R, 1, 0, kFldGeneral>), dim3(p->nblk - p->nblk_lep), dim3(kBlock), p->lds,
+                      st, inst, P, p->T->dev, p->nblk_lep);
+        else if (p->fv == kFldRotating)
+            QS_LAUNCH(K_PLAN_PHOTON, (k_plan_main<R, 1, 0, kFldRotating>), dim3(p->nblk - p->nblk_lep), dim3(kBlock),
+                      p->lds, st, inst, P, p->T->dev, p->nblk_lep);
         else
-            QS_LAUNCH(K_PLAN_PHOTON, (k_plan_main<R, 1, 0, false>), dim3(p->nblk - p->nblk_lep), dim3(kBlock), p->lds, st,
-                      inst, P, p->T->dev, p->nblk_lep);
+            QS_LAUNCH(K_PLAN_PHOTON, (k_plan_main<R, 1, 0, kFldPlain>), dim3(p->nblk - p->nblk_lep), dim3(kBlock), p->lds,
+                      st, inst, P, p->T->dev, p->nblk_lep);
     }
     // processing, with the bookkeeping; a process with a learned inverse CDF evaluates it in the
     // same launch (single precision only)
@@ -589,12 +596,12 @@ template <class R> qed_status plan_step(qed_plan p, hipStream_t st)
                 if (sb) P.mlp[1] = qs_surrogate_view(p->sur[1]);
                 P.mlp_on[0] = sl;
                 P.mlp_on[1] = sb;
-                auto proc = p->grid ? k_plan_process<R, true, true> : k_plan_process<R, false, true>;
+                auto proc = p->fv != kFldPlain ? k_plan_process<R, kFldGeneral, true> : k_plan_process<R, kFldPlain, true>;
                 QS_LAUNCH(K_PLAN_PROCESS, proc, dim3(p->npb), dim3(kBlock), p->lds, st, inst, P, p->T->dev, 0);
                 return qs_launch_status("qed_plan_step");
             }
         }
-        auto proc = p->grid ? k_plan_process<R, true, false> : k_plan_process<R, false, false>;
+        auto proc = p->fv != kFldPlain ? k_plan_process<R, kFldGeneral, false> : k_plan_process<R, kFldPlain, false>;
         QS_LAUNCH(K_PLAN_PROCESS, proc, dim3(p->npb), dim3(kBlock), p->lds, st, inst, P, p->T->dev, 0);
     }
     return qs_launch_status("qed_plan_step");

@@ -28,16 +28,16 @@ __global__ void __launch_bounds__(kBlock) k_push(LepDev<R> L, FieldDev F, StepDe
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
         V3<R> x = ldx(L.x, i), p = ld3(L.p, i), s = ld3(L.s, i);
         V3<R> E, B;
-        eval_fields<R, true>(F, (double)x.x, (double)x.y, S.t, E, B);
+        eval_fields<R, kFldGeneral>(F, (double)x.x, (double)x.y, S.t, E, B);
         const V3<R> d = push<R>(q, (R)S.a_e, E, B, (R)S.dt, (S.flags & F_TBMT) != 0, p, s,
-                                gfac_src<R, true>(T, S.flags), (R)S.eps_r);
+                                gfac_src<R, kFldGeneral>(T, S.flags), (R)S.eps_r);
         stx(L.x, i, x + d);
         st3(L.p, i, p);
         st3(L.s, i, s);
     }
 }
 
-template <class R, int DEC, bool GRID>
+template <class R, int DEC, int FLD>
 __global__ void __launch_bounds__(kBlock) k_lepton_main(LepDev<R> L, FieldDev F, StepDev S0, TablesDev T,
                                                         uint64_t *mask, int64_t nchunks, uint32_t *bctr, uint32_t *bcnt)
 {
@@ -49,7 +49,7 @@ __global__ void __launch_bounds__(kBlock) k_lepton_main(LepDev<R> L, FieldDev F,
     const int64_t B = block_len(n, gridDim.x);
     const int64_t start = (int64_t)blockIdx.x * B, end = start + B < n ? start + B : n;
     LCount c;
-    lepton_range<R, DEC, GRID>(L, F, S, T, lds, start, end, mask, nchunks, c);
+    lepton_range<R, DEC, FLD>(L, F, S, T, lds, start, end, mask, nchunks, c);
     unsigned v[kNCtr + 1] = {};
     v[C_PROB] = c.prob; v[C_CHI] = c.chi; v[C_NORM] = c.norm; v[C_LSTEP] = c.step; v[kNCtr] = c.trans;
     __shared__ unsigned tot[kNCtr + 1];
@@ -58,7 +58,7 @@ __global__ void __launch_bounds__(kBlock) k_lepton_main(LepDev<R> L, FieldDev F,
     else if (threadIdx.x == kNCtr) bcnt[blockIdx.x] = tot[kNCtr];
 }
 
-template <class R, bool GRID>
+template <class R, int FLD>
 __global__ void __launch_bounds__(kBlock) k_emit_process(LepDev<R> L, PhoDev<R> G, FieldDev F, StepDev S0, TablesDev T,
                                                          const uint64_t *mask, int64_t nchunks, const uint32_t *idx,
                                                          const int64_t *book, unsigned long long *ctr)
@@ -72,13 +72,13 @@ __global__ void __launch_bounds__(kBlock) k_emit_process(LepDev<R> L, PhoDev<R> 
     for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < total; j += (int64_t)gridDim.x * blockDim.x) {
         const int64_t i = idx[j];
         const bool up = (mask[nchunks + (i >> 6)] >> (i & 63)) & 1ull;
-        emit_item<R, GRID>(L, G, F, S, T, lds, i, up, j < nfit ? gbase + j : -1, c_ret);
+        emit_item<R, FLD>(L, G, F, S, T, lds, i, up, j < nfit ? gbase + j : -1, c_ret);
     }
     wave_add(ctr, C_RETIRED, c_ret);
 }
 
 // ------------------------------------------------------------------ kernels: photons
-template <class R, bool GRID>
+template <class R, int FLD>
 __global__ void __launch_bounds__(kBlock) k_photon_main(PhoDev<R> G, FieldDev F, StepDev S0, TablesDev T, uint64_t *mask,
                                                         int64_t nchunks, uint32_t *bctr, uint32_t *bcnt)
 {
@@ -92,7 +92,7 @@ __global__ void __launch_bounds__(kBlock) k_photon_main(PhoDev<R> G, FieldDev F,
     const int64_t start = (int64_t)blockIdx.x * B, end = start + B < n ? start + B : n;
     GCount c;
     for (int64_t tile = start; tile < end; tile += kPhoTile)
-        photon_tile<R, GRID>(G, F, S, T, lds, Q, tile, tile + kPhoTile < end ? tile + kPhoTile : end, mask, nchunks, c);
+        photon_tile<R, FLD>(G, F, S, T, lds, Q, tile, tile + kPhoTile < end ? tile + kPhoTile : end, mask, nchunks, c);
     unsigned v[kNCtr + 1] = {};
     v[C_PROB] = c.prob; v[C_CHI] = c.chi; v[C_NORM] = c.norm; v[C_RETIRED] = c.ret; v[C_GSTEP] = c.step;
     v[C_GQED] = c.qed; v[kNCtr] = c.trans;
@@ -102,7 +102,7 @@ __global__ void __launch_bounds__(kBlock) k_photon_main(PhoDev<R> G, FieldDev F,
     else if (threadIdx.x == kNCtr) bcnt[blockIdx.x] = tot[kNCtr];
 }
 
-template <class R, bool GRID>
+template <class R, int FLD>
 __global__ void __launch_bounds__(kBlock) k_pair_process(PhoDev<R> G, LepDev<R> Le, LepDev<R> Lp, FieldDev F, StepDev S0,
                                                          TablesDev T, const uint64_t *mask, int64_t nchunks,
                                                          const uint32_t *idx, const int64_t *book)
@@ -117,7 +117,7 @@ __global__ void __launch_bounds__(kBlock) k_pair_process(PhoDev<R> G, LepDev<R> 
     for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < total; j += (int64_t)gridDim.x * blockDim.x) {
         const int64_t i = idx[j];
         const bool plus = (mask[nchunks + (i >> 6)] >> (i & 63)) & 1ull;
-        pair_item<R, GRID>(G, Le, Lp, F, S, T, lds, i, plus, j < nfit ? be + j : -1, bp + j);
+        pair_item<R, FLD>(G, Le, Lp, F, S, T, lds, i, plus, j < nfit ? be + j : -1, bp + j);
     }
 }
 
@@ -310,7 +310,7 @@ qed_status emit_impl(qed_tables T, const qed_leptons *L, const qed_fields *f, co
     unsigned long long *c = (unsigned long long *)ctr;
     const size_t lds_nlc = sizeof(R) * 2 * T->dev.n_chi[0];
     const int g = grid_for(L->capacity);
-    const bool grid = general_leptons(f, p->flags);
+    const int fv = lepton_variant(f, p->flags);
     if (p->flags & QED_SUBCYCLE) {
         // the QED part in kSubRounds rounds of streaming pass, expansion and processing; the push
         // only in round 0; each round appends its photons after the previous round's
@@ -321,33 +321,36 @@ qed_status emit_impl(qed_tables T, const qed_leptons *L, const qed_fields *f, co
             StepDev sr = sd;
             sr.sub_round = r;
             if (r > 0) sr.flags &= ~(uint32_t)QED_PUSH;
-            QS_LAUNCH(K_LEPTON_MAIN, (k_lepton_main<R, 4, true>), dim3(g), dim3(kBlock), lds_nlc, st, ls, fd, sr, T->dev,
+            QS_LAUNCH(K_LEPTON_MAIN, (k_lepton_main<R, 4, kFldGeneral>), dim3(g), dim3(kBlock), lds_nlc, st, ls, fd, sr, T->dev,
                       w.mask, nch, w.bctr, w.bcnt);
             QS_LAUNCH(K_MASK_EXPAND, k_expand, dim3(g), dim3(kBlock), 0, st, (const uint64_t *)w.mask,
                       (const uint32_t *)w.bcnt, (const int64_t *)L->d_count, w.book, 0, gs.count, gs.cap,
                       (int64_t *)nullptr, (int64_t)0, (int64_t *)nullptr, c, (const uint32_t *)w.bctr, w.idx);
-            QS_LAUNCH(K_EMIT_PROCESS, (k_emit_process<R, true>), dim3(g), dim3(kBlock), lds_nlc, st, ls, gs, fd, sr,
+            QS_LAUNCH(K_EMIT_PROCESS, (k_emit_process<R, kFldGeneral>), dim3(g), dim3(kBlock), lds_nlc, st, ls, gs, fd, sr,
                       T->dev, w.mask, nch, w.idx, w.book, c);
         }
         return qs_launch_status(__func__);
     }
     if (p->flags & QED_OPTICAL_DEPTH)
-        QS_LAUNCH(K_LEPTON_MAIN, (k_lepton_main<R, 1, true>), dim3(g), dim3(kBlock), lds_nlc, st, ld, fd, sd, T->dev,
+        QS_LAUNCH(K_LEPTON_MAIN, (k_lepton_main<R, 1, kFldGeneral>), dim3(g), dim3(kBlock), lds_nlc, st, ld, fd, sd, T->dev,
                   w.mask, nch, w.bctr, w.bcnt);
     else if (p->flags & QED_REJECTION)
-        QS_LAUNCH(K_LEPTON_MAIN, (k_lepton_main<R, 2, true>), dim3(g), dim3(kBlock), lds_nlc, st, ld, fd, sd, T->dev,
+        QS_LAUNCH(K_LEPTON_MAIN, (k_lepton_main<R, 2, kFldGeneral>), dim3(g), dim3(kBlock), lds_nlc, st, ld, fd, sd, T->dev,
                   w.mask, nch, w.bctr, w.bcnt);
-    else if (grid)
-        QS_LAUNCH(K_LEPTON_MAIN, (k_lepton_main<R, 0, true>), dim3(g), dim3(kBlock), lds_nlc, st, ld, fd, sd, T->dev,
-                  w.mask, nch, w.bctr, w.bcnt);
+    else if (fv == kFldGeneral)
+        QS_LAUNCH(K_LEPTON_MAIN, (k_lepton_main<R, 0, kFldGeneral>), dim3(g), dim3(kBlock), lds_nlc, st, ld, fd, sd,
+                  T->dev, w.mask, nch, w.bctr, w.bcnt);
+    else if (fv == kFldRotating)
+        QS_LAUNCH(K_LEPTON_MAIN, (k_lepton_main<R, 0, kFldRotating>), dim3(g), dim3(kBlock), lds_nlc, st, ld, fd, sd,
+                  T->dev, w.mask, nch, w.bctr, w.bcnt);
     else
-        QS_LAUNCH(K_LEPTON_MAIN, (k_lepton_main<R, 0, false>), dim3(g), dim3(kBlock), lds_nlc, st, ld, fd, sd, T->dev,
-                  w.mask, nch, w.bctr, w.bcnt);
+        QS_LAUNCH(K_LEPTON_MAIN, (k_lepton_main<R, 0, kFldPlain>), dim3(g), dim3(kBlock), lds_nlc, st, ld, fd, sd,
+                  T->dev, w.mask, nch, w.bctr, w.bcnt);
     const PhoDev<R> gd = pho_dev<R>((p->flags & QED_EMIT) ? G : nullptr);
     QS_LAUNCH(K_MASK_EXPAND, k_expand, dim3(g), dim3(kBlock), 0, st, (const uint64_t *)w.mask, (const uint32_t *)w.bcnt,
               (const int64_t *)L->d_count, w.book, 0, gd.count, gd.cap, (int64_t *)nullptr, (int64_t)0,
               (int64_t *)nullptr, c, (const uint32_t *)w.bctr, w.idx);
-    QS_LAUNCH(K_EMIT_PROCESS, (k_emit_process<R, true>), dim3(g), dim3(kBlock), lds_nlc, st, ld, gd, fd, sd, T->dev, w.mask,
+    QS_LAUNCH(K_EMIT_PROCESS, (k_emit_process<R, kFldGeneral>), dim3(g), dim3(kBlock), lds_nlc, st, ld, gd, fd, sd, T->dev, w.mask,
               nch, w.idx, w.book, c);
     return qs_launch_status(__func__);
 }
@@ -365,16 +368,20 @@ qed_status pair_impl(qed_tables T, const qed_photons *G, const qed_fields *f, co
     unsigned long long *c = (unsigned long long *)ctr;
     const size_t lds_nbw = sizeof(R) * 2 * T->dev.n_chi[1];
     const int g = grid_for(G->capacity);
-    if (general_fields(f))
-        QS_LAUNCH(K_PHOTON_MAIN, (k_photon_main<R, true>), dim3(g), dim3(kBlock), lds_nbw, st, gd, fd, sd, T->dev, w.mask,
-                  nch, w.bctr, w.bcnt);
+    const int fv = field_variant(f);
+    if (fv == kFldGeneral)
+        QS_LAUNCH(K_PHOTON_MAIN, (k_photon_main<R, kFldGeneral>), dim3(g), dim3(kBlock), lds_nbw, st, gd, fd, sd, T->dev,
+                  w.mask, nch, w.bctr, w.bcnt);
+    else if (fv == kFldRotating)
+        QS_LAUNCH(K_PHOTON_MAIN, (k_photon_main<R, kFldRotating>), dim3(g), dim3(kBlock), lds_nbw, st, gd, fd, sd, T->dev,
+                  w.mask, nch, w.bctr, w.bcnt);
     else
-        QS_LAUNCH(K_PHOTON_MAIN, (k_photon_main<R, false>), dim3(g), dim3(kBlock), lds_nbw, st, gd, fd, sd, T->dev, w.mask,
-                  nch, w.bctr, w.bcnt);
+        QS_LAUNCH(K_PHOTON_MAIN, (k_photon_main<R, kFldPlain>), dim3(g), dim3(kBlock), lds_nbw, st, gd, fd, sd, T->dev,
+                  w.mask, nch, w.bctr, w.bcnt);
     QS_LAUNCH(K_MASK_EXPAND, k_expand, dim3(g), dim3(kBlock), 0, st, (const uint64_t *)w.mask, (const uint32_t *)w.bcnt,
               (const int64_t *)G->d_count_prev, w.book, 1, Le->d_count, Le->capacity, Lp->d_count, Lp->capacity,
               (int64_t *)nullptr, c, (const uint32_t *)w.bctr, w.idx);
-    QS_LAUNCH(K_PAIR_PROCESS, (k_pair_process<R, true>), dim3(g), dim3(kBlock), lds_nbw, st, gd, lep_dev<R>(Le),
+    QS_LAUNCH(K_PAIR_PROCESS, (k_pair_process<R, kFldGeneral>), dim3(g), dim3(kBlock), lds_nbw, st, gd, lep_dev<R>(Le),
               lep_dev<R>(Lp), fd, sd, T->dev, w.mask, nch, w.idx, w.book);
     return qs_launch_status(__func__);
 }

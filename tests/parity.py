@@ -100,7 +100,7 @@ def director_err(Pa, Pb, k):
 def photon_parent(ids):
     ids = ids.astype(np.uint64)
     return ((ids >> np.uint64(61)) & np.uint64(3)).astype(np.int64), \
-        ((ids >> np.uint64(24)) & np.uint64((1 << 37) - 1)).astype(np.int64)
+        ((ids >> np.uint64(24)) & np.uint64((1 << 33) - 1)).astype(np.int64)
 
 
 def compare_photons(gpu, orc, excluded_parents, rtol_k, atol_P, what="", near_photons=None, outlier_rate=1e-5):

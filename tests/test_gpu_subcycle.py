@@ -156,3 +156,37 @@ def test_subcycle_rejected_in_plans_and_with_other_decisions(q, gtab64):
         sim = _sim(q, gtab64, w, 64, 1, 128, (q.QED_ALL & ~q.QED_PAIR) | q.QED_SUBCYCLE | q.QED_REJECTION)
         sim.e.load(w.x, w.p, w.s)
         sim.step()
+
+
+def test_subcycle_head_on_fp64(q, gtab64, otables):
+    """Sub-cycling in the head-on collision at a0 = 300 (W dt up to about 0.3: 2 and 4 sub-steps
+    near the field maxima): 200 electrons through the whole pulse (1700 steps), both channels
+    (pair-born leptons sub-cycle too), compaction every 200 steps.  Pair-born leptons of low
+    gamma turn by up to radians per step in this field and amplify rounding: the oracle against
+    its own build with fused multiply-adds differs by up to 3.0e-10 in momentum here, so the bound
+    is 1e-9 (decisions, counts and ids are still compared exactly)."""
+    w = synth.subsample(synth.c2(a0=300.0), np.arange(200))
+    steps = 1700
+    flags = q.QED_ALL | q.QED_SUBCYCLE
+    cap_g, cap_p = 100_000, 4_000
+    sim = _sim(q, gtab64, w, w.n + cap_p, cap_p, cap_g, flags)
+    sim.e.load(w.x, w.p, w.s)
+    for k in range(steps):
+        sim.step()
+        if k % 200 == 199:
+            sim.compact()
+    ref = oracle_run(otables, w, steps, flags, cap_e=w.n + cap_p, cap_p=cap_p, cap_g=cap_g)
+    c = q.counters_dict(sim.ctr)
+    print("sub-cycled head-on gpu", c, "oracle", ref["ctr"])
+    assert ref["near_e"].sum() == 0 and ref["near_g"].sum() == 0
+    assert c["n_emit"] == ref["ctr"]["n_emit"] > 20_000 and c["n_pair"] == ref["ctr"]["n_pair"] > 100
+    ids = sim.g.arrays()[3]
+    rounds = _rounds(ids[ids != 0])
+    print("live photons by sub-cycling round", np.bincount(rounds, minlength=16))
+    assert (rounds > 0).any()
+    t = 1e-9
+    compare_leptons(sim.e.arrays(), ref["E"].arrays(), np.zeros(ref["E"].n, bool), t, t, rtol_x=t,
+                    what="sub-cycled electrons", events=c["n_emit"])
+    compare_leptons(sim.p.arrays(), ref["P"].arrays(), np.zeros(ref["P"].n, bool), t, t, rtol_x=t,
+                    what="sub-cycled positrons")
+    compare_photons(sim.g.arrays(), ref["G"].arrays(), set(), t, t, what="sub-cycled photons")

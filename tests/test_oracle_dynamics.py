@@ -196,7 +196,7 @@ def test_collapse_means(otables, s0):
     si = np.array([np.dot(s0, e), np.dot(s0, b), np.dot(s0, k)])
     mg, mF = _lam_means(1.0, si)
     # emitters are the leptons whose index appears as a photon parent
-    parents = ((G.id[:G.n].astype(np.uint64) >> np.uint64(24)) & np.uint64((1 << 37) - 1)).astype(np.int64)
+    parents = ((G.id[:G.n].astype(np.uint64) >> np.uint64(24)) & np.uint64((1 << 33) - 1)).astype(np.int64)
     sf = s[:, parents]
     comp = np.stack([e @ sf, b @ sf, k @ sf])
     xi = np.stack([oracle.P_to_stokes(np.array([G.P[i][j] for i in range(3)]), e, b, k) for j in range(G.n)]).T
@@ -308,7 +308,7 @@ def test_array_step_bookkeeping(otables):
     assert G.n == 150 and ctr.n_capacity_overflow == ctr.n_emit - 150
     ids = G.id[:G.n].astype(np.uint64)
     step = (ids & np.uint64(0xFFFFFF)).astype(np.int64)
-    parent = ((ids >> np.uint64(24)) & np.uint64((1 << 37) - 1)).astype(np.int64)
+    parent = ((ids >> np.uint64(24)) & np.uint64((1 << 33) - 1)).astype(np.int64)
     order = step * 1000 + parent
     assert np.all(np.diff(order) > 0)                   # appended by step, then by parent index
     assert np.all(ids >> np.uint64(63) == 1)
@@ -347,7 +347,7 @@ def test_optical_depth_decision_is_memoryless(otables):
             prm = oracle.make_params(w.dt, EPS, step=k, t=k * w.dt, seed=5, flags=base | mode)
             G.n = 0
             oracle.lepton_step(otables, prm, F, L, G, oracle.Counters())
-            par = (G.id[:G.n] >> np.uint64(24)) & np.uint64((1 << 37) - 1)
+            par = (G.id[:G.n] >> np.uint64(24)) & np.uint64((1 << 33) - 1)
             e = np.zeros(w.n, bool)
             e[par.astype(np.int64)] = True
             hist.append(e)
