@@ -596,12 +596,16 @@ template <class R> qed_status plan_step(qed_plan p, hipStream_t st)
                 if (sb) P.mlp[1] = qs_surrogate_view(p->sur[1]);
                 P.mlp_on[0] = sl;
                 P.mlp_on[1] = sb;
-                auto proc = p->fv != kFldPlain ? k_plan_process<R, kFldGeneral, true> : k_plan_process<R, kFldPlain, true>;
+                auto proc = p->fv == kFldGeneral    ? k_plan_process<R, kFldGeneral, true>
+                            : p->fv == kFldRotating ? k_plan_process<R, kFldRotating, true>
+                                                    : k_plan_process<R, kFldPlain, true>;
                 QS_LAUNCH(K_PLAN_PROCESS, proc, dim3(p->npb), dim3(kBlock), p->lds, st, inst, P, p->T->dev, 0);
                 return qs_launch_status("qed_plan_step");
             }
         }
-        auto proc = p->fv != kFldPlain ? k_plan_process<R, kFldGeneral, false> : k_plan_process<R, kFldPlain, false>;
+        auto proc = p->fv == kFldGeneral    ? k_plan_process<R, kFldGeneral, false>
+                    : p->fv == kFldRotating ? k_plan_process<R, kFldRotating, false>
+                                            : k_plan_process<R, kFldPlain, false>;
         QS_LAUNCH(K_PLAN_PROCESS, proc, dim3(p->npb), dim3(kBlock), p->lds, st, inst, P, p->T->dev, 0);
     }
     return qs_launch_status("qed_plan_step");
