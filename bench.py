@@ -44,7 +44,7 @@ def bytes_per_unit(es, tracked_x=1):
 
 
 def run_gpu(q, tab, w, steps, warmup, compact_every, profile, graph=True, merged=True, surrogates=(None, None), ppb=0,
-            photons_per_electron=30, caps=None, flags=None):
+            photons_per_electron=30, caps=None, flags=None, fields=None):
     """Time `steps` steps from the initial state.  With graph=True each run of `compact_every`
     steps plus the compaction is one captured HIP graph (recorded before the timed region).
     merged=True runs each step as one qed_plan_step; surrogates: learned inverse CDFs (NLC, NBW)."""
@@ -55,7 +55,8 @@ def run_gpu(q, tab, w, steps, warmup, compact_every, profile, graph=True, merged
     cap_e = w.n + cap_p
     if caps is not None:
         cap_e, cap_p, cap_g = caps
-    fields = q.make_fields(w.field_kind, a0=w.a0, phase_len=w.phase_len)
+    if fields is None:
+        fields = q.make_fields(w.field_kind, a0=w.a0, phase_len=w.phase_len)
 
     def fresh():
         sim = Simulation(tab, cap_e=cap_e, cap_p=cap_p, cap_g=cap_g, track=w.track, fields=fields, dt=w.dt,
@@ -352,6 +353,26 @@ def extras(q, args, w, t32, t64, out, v32, v64):
                                    "omega t = 16 (3200 steps of 0.005)", unit="particle-QED-steps/s",
                           speedup_fp32_vs_fp64=round(rc["fp32"]["value"] / rc["fp64"]["value"], 3), **rc)
     out["subcycle"] = subcycle_study(q, t64)
+    out["grid"] = grid_run(q, t32, args)
+
+
+def grid_run(q, tab, args, n=1 << 24, steps=200):
+    """The grid workload (fields bilinearly interpolated from a 4096 x 1024 FP32 snapshot of two
+    counter-propagating circularly polarized waves of a0 = 200 with 1 % noise) at a quarter of its
+    electrons, FP32, graph-captured merged steps"""
+    import torch
+    wg = synth.c3(n=n, steps=steps)
+    fg = q.make_fields(q.QED_FIELD_GRID2D, grid=torch.as_tensor(wg.extra["grid"], device="cuda"), dx=wg.extra["dx"],
+                       dy=wg.extra["dy"])
+    r = run_gpu(q, tab, wg, steps, 0, args.compact_every, profile=False, graph=True, ppb=args.ppb, fields=fg,
+                photons_per_electron=16)
+    c = r["ctr"]
+    v = (c["n_lepton_steps"] + c["n_photon_steps"]) / r["wall"]
+    log(f"grid workload: {n} electrons, {steps} steps in {r['wall']:.3f} s, {v:.4g}/s, counters {c}")
+    return {"workload": f"grid-interpolated fields (4096 x 1024 cells, a0 = 200 standing CP waves, 1 % noise), {n} "
+                        f"electrons (16 per cell at 2^26), gamma ~ LogUniform(10, 1e4), {steps} steps, FP32",
+            "value": round(v, 1), "unit": "particle-QED-steps/s", "wall_s": round(r["wall"], 4),
+            "photons_emitted": c["n_emit"], "pairs": c["n_pair"], "capacity_overflow": c["n_capacity_overflow"]}
 
 
 def subcycle_study(q, tab, n=100_000, steps=200):

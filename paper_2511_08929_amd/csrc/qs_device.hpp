@@ -266,6 +266,8 @@ struct FieldDev {
     double a0, phase_len;
     double inv_phase_len;      // 1 / phase_len (0 without envelope)
     const float *g[6];         // grid: Ex, Ey, Ez, Bx, By, Bz node arrays [ny][nx]
+    const float4 *gn;          // or NULL: the same nodes interleaved, two float4 per node
+                               // (Ex, Ey, Ez, Bx), (By, Bz, 0, 0), so a corner is one 32-byte read
     int nx, ny;
     double gx0, gy0, inv_dx, inv_dy, inv_nx, inv_ny;
 };
@@ -285,10 +287,24 @@ template <class R> __device__ __forceinline__ void add_grid(const FieldDev &f, d
     const int64_t a = (int64_t)j0 * f.nx, b = (int64_t)j1 * f.nx;
     const R w00 = ((R)1 - ax) * ((R)1 - ay), w10 = ax * ((R)1 - ay), w01 = ((R)1 - ax) * ay, w11 = ax * ay;
     R val[6];
+    if (f.gn) {
+        // the same sums over the interleaved copy (same values, same order: equal bit for bit)
+        const float4 *q = f.gn;
+        const float4 c00 = q[2 * (a + i0)], c10 = q[2 * (a + i1)], c01 = q[2 * (b + i0)], c11 = q[2 * (b + i1)];
+        const float4 d00 = q[2 * (a + i0) + 1], d10 = q[2 * (a + i1) + 1], d01 = q[2 * (b + i0) + 1],
+                     d11 = q[2 * (b + i1) + 1];
+        val[0] = w00 * (R)c00.x + w10 * (R)c10.x + w01 * (R)c01.x + w11 * (R)c11.x;
+        val[1] = w00 * (R)c00.y + w10 * (R)c10.y + w01 * (R)c01.y + w11 * (R)c11.y;
+        val[2] = w00 * (R)c00.z + w10 * (R)c10.z + w01 * (R)c01.z + w11 * (R)c11.z;
+        val[3] = w00 * (R)c00.w + w10 * (R)c10.w + w01 * (R)c01.w + w11 * (R)c11.w;
+        val[4] = w00 * (R)d00.x + w10 * (R)d10.x + w01 * (R)d01.x + w11 * (R)d11.x;
+        val[5] = w00 * (R)d00.y + w10 * (R)d10.y + w01 * (R)d01.y + w11 * (R)d11.y;
+    } else {
 #pragma unroll
-    for (int c = 0; c < 6; ++c) {
-        const float *g = f.g[c];
-        val[c] = w00 * (R)g[a + i0] + w10 * (R)g[a + i1] + w01 * (R)g[b + i0] + w11 * (R)g[b + i1];
+        for (int c = 0; c < 6; ++c) {
+            const float *g = f.g[c];
+            val[c] = w00 * (R)g[a + i0] + w10 * (R)g[a + i1] + w01 * (R)g[b + i0] + w11 * (R)g[b + i1];
+        }
     }
     E.x += val[0]; E.y += val[1]; E.z += val[2];
     B.x += val[3]; B.y += val[4]; B.z += val[5];

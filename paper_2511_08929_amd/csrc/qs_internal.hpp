@@ -59,7 +59,7 @@ inline qed_status qs_launch_status(const char *where)
 // the launch stream; qed_profile_stop synchronizes and reports per-kernel calls and time.
 enum QsKernel {
     K_TABLES = 0, K_PUSH, K_LEPTON_MAIN, K_EMIT_PROCESS, K_PHOTON_MAIN, K_PAIR_PROCESS, K_MASK_EXPAND, K_SET_PREV,
-    K_ALIVE_MASK, K_GATHER, K_SCATTER_BACK, K_PLAN_LEPTON, K_PLAN_PHOTON, K_PLAN_PROCESS, K_NKERNELS
+    K_ALIVE_MASK, K_GATHER, K_SCATTER_BACK, K_PLAN_LEPTON, K_PLAN_PHOTON, K_PLAN_PROCESS, K_GRID_PACK, K_NKERNELS
 };
 extern bool g_qs_profiling;
 void qs_prof_begin(int kid, hipStream_t st);

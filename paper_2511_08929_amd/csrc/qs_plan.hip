@@ -375,6 +375,8 @@ struct qed_plan_s {
     InstSeg *d_iseg;
     Snap *d_snap;
     qed_surrogate sur[2];      // learned inverse CDF per process (NULL: tables)
+    FieldDev *h_grid;          // [ninst] host copy of each instance's fields (grid instances only)
+    float4 **h_gn;             // [ninst] the plan's interleaved copy of that grid, or NULL
     int dec;                   // decision variants needed (bit 0: optical depth, bit 1: rejection)
     int fv;                    // field-model variant the instances need (the largest of field_variant)
     int flep;                  // the lepton pass's (the largest of lepton_variant)
@@ -410,7 +412,22 @@ void plan_free(qed_plan p)
     (void)hipFree(p->d_pbd);
     (void)hipFree(p->d_iseg);
     (void)hipFree(p->d_snap);
+    if (p->h_gn)
+        for (int i = 0; i < p->ninst; ++i)
+            if (p->h_gn[i]) (void)hipFree(p->h_gn[i]);
+    free(p->h_gn);
+    free(p->h_grid);
     delete p;
+}
+
+// the caller's six grid arrays, interleaved two float4 per node (the plan's copy of the step)
+__global__ void __launch_bounds__(kBlock) k_pack_grid(FieldDev f, float4 *gn)
+{
+    const int64_t n = (int64_t)f.nx * f.ny;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        gn[2 * i] = make_float4(f.g[0][i], f.g[1][i], f.g[2][i], f.g[3][i]);
+        gn[2 * i + 1] = make_float4(f.g[4][i], f.g[5][i], 0.0f, 0.0f);
+    }
 }
 
 // Default cap on the blocks of one set: one resident round of the photon streaming kernel on
@@ -421,7 +438,7 @@ template <class R> int resident_blocks(size_t lds)
     int dev = 0, cus = 0, per_cu = 0;
     if (hipGetDevice(&dev) != hipSuccess) return kMaxGrid;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0) return kMaxGrid;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_plan_main<R, 1, false, false>, kBlock, lds) != hipSuccess ||
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_plan_main<R, 1, 0, kFldPlain>, kBlock, lds) != hipSuccess ||
         per_cu <= 0)
         return kMaxGrid;
     return cus * per_cu;
@@ -491,6 +508,17 @@ qed_status plan_create(qed_tables T, int n, const qed_instance *in, int ppb, int
         p->fv = std::max(p->fv, field_variant(&in[i].fields));
         p->flep = std::max(p->flep, lepton_variant(&in[i].fields, in[i].params.flags));
     }
+    // grid fields: the plan keeps a node-interleaved copy, refreshed from the caller's arrays at
+    // the start of every step, so an interpolation reads four 32-byte corners instead of 24 scalars
+    p->h_grid = (FieldDev *)calloc(n, sizeof(FieldDev));
+    p->h_gn = (float4 **)calloc(n, sizeof(float4 *));
+    if (!p->h_grid || !p->h_gn) e = hipErrorOutOfMemory;
+    for (int i = 0; i < n && e == hipSuccess; ++i) {
+        if (in[i].fields.kind != QED_FIELD_GRID2D) continue;
+        p->h_grid[i] = inst[i].F;
+        e = hipMalloc((void **)&p->h_gn[i], sizeof(float4) * 2 * (size_t)in[i].fields.nx * (size_t)in[i].fields.ny);
+        inst[i].F.gn = p->h_gn[i];
+    }
     if (e == hipSuccess) e = hipMemcpy(p->d_inst, inst.data(), sizeof(InstDev<R>) * n, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(p->d_seg, seg.data(), sizeof(SegDev) * seg.size(), hipMemcpyHostToDevice);
     // block -> segment (and instance) tables: one load instead of a search over the segments
@@ -555,6 +583,12 @@ template <class R> qed_status plan_step(qed_plan p, hipStream_t st)
     memset(P.mlp, 0, sizeof(P.mlp));
     P.mlp_on[0] = P.mlp_on[1] = 0;
     const InstDev<R> *inst = (const InstDev<R> *)p->d_inst;
+    for (int i = 0; i < p->ninst; ++i)
+        if (p->h_gn[i]) {
+            const int64_t nn = (int64_t)p->h_grid[i].nx * p->h_grid[i].ny;
+            const int gb = (int)std::min<int64_t>(cdiv(nn, kBlock), 4096);
+            QS_LAUNCH(K_GRID_PACK, k_pack_grid, dim3(gb), dim3(kBlock), 0, st, p->h_grid[i], p->h_gn[i]);
+        }
     if (p->nblk_lep > 0) {
         if (p->dec == 3)
             QS_LAUNCH(K_PLAN_LEPTON, (k_plan_main<R, 0, 3, kFldGeneral>), dim3(p->nblk_lep), dim3(kBlock), p->lds, st, inst, P,

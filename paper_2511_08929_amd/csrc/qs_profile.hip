@@ -19,7 +19,8 @@ hipEvent_t g_open = nullptr;
 
 const char *const kNames[K_NKERNELS] = {"table_build", "push",       "lepton_main", "emit_process", "photon_main",
                                         "pair_process", "expand",    "clock",       "alive_mask",   "gather",
-                                        "scatter_back", "plan_lepton", "plan_photon", "plan_process"};
+                                        "scatter_back", "plan_lepton", "plan_photon", "plan_process",
+                                        "grid_pack"};
 
 hipEvent_t take()
 {

@@ -31,9 +31,9 @@ def tabs(q):
     return {"fp64": q.Tables(precision=q.QED_F64), "fp32": q.Tables(precision=q.QED_F32)}
 
 
-def _sim(q, tab, w, merged, cap_e, cap_p, cap_g, flags=None, ppb=0, tau=False, maxb=0):
+def _sim(q, tab, w, merged, cap_e, cap_p, cap_g, flags=None, ppb=0, tau=False, maxb=0, fields=None):
     from paper_2511_08929_amd.sim import Simulation
-    f = q.make_fields(w.field_kind, E0=w.E0, B0=w.B0, a0=w.a0, phase_len=w.phase_len)
+    f = fields or q.make_fields(w.field_kind, E0=w.E0, B0=w.B0, a0=w.a0, phase_len=w.phase_len)
     sim = Simulation(tab, cap_e=cap_e, cap_p=cap_p, cap_g=cap_g, track=w.track, fields=f, dt=w.dt, eps_r=EPS,
                      seed=w.seed, flags=q.QED_ALL if flags is None else flags, k_retire=w.k_retire,
                      device_clock=True, merged=merged, particles_per_block=ppb, optical_depth=tau,
@@ -205,3 +205,28 @@ def test_plan_equals_per_species_many_blocks(q, tabs):
     assert b.plan.blocks > 2 * 8192
     _assert_same(_state(q, a), _state(q, b), "many blocks")
     assert q.counters_dict(b.ctr)["n_emit"] > 0
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_plan_equals_per_species_grid(q, tabs, prec):
+    """Grid fields in the merged step, which interpolates from its own node-interleaved copy of the
+    grid (refreshed every step), against the per-species calls, which read the caller's six
+    arrays: 20000 electrons of the grid workload over 60 steps with pairs, bit for bit; the
+    grid is then changed between steps and both must follow it."""
+    import torch
+    w = synth.c3(n=20_000, steps=60)
+    grid = torch.as_tensor(w.extra["grid"], device="cuda")
+    f = q.make_fields(q.QED_FIELD_GRID2D, grid=grid, dx=w.extra["dx"], dy=w.extra["dy"])
+    a = _sim(q, tabs[prec], w, False, 4 * w.n, 2 * w.n, 40 * w.n, fields=f)
+    b = _sim(q, tabs[prec], w, True, 4 * w.n, 2 * w.n, 40 * w.n, fields=f)
+    for k in range(1, 61):
+        if k == 31:
+            grid.mul_(1.25)                  # the field changes between steps
+            torch.cuda.synchronize()
+        a.step(); b.step()
+        if k % 20 == 0:
+            a.compact(); b.compact()
+    torch.cuda.synchronize()
+    _assert_same(_state(q, a), _state(q, b), f"grid {prec}")
+    c = q.counters_dict(b.ctr)
+    assert c["n_emit"] > 10_000 and c["n_pair"] > 0, c
