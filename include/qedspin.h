@@ -111,7 +111,9 @@ enum {
     QED_FIELD_GRID2D = 2,      /* E0, B0 plus a static field on a periodic 2-D grid in (x, y): six FP32
                                   device arrays Ex, Ey, Ez, Bx, By, Bz of nx * ny nodes, node (i, j) at
                                   (x0 + i dx, y0 + j dy), index j * nx + i; bilinear interpolation
-                                  (particles need x[0] and x[1]) */
+                                  (particles need x[0] and x[1]).  The arrays are read at every step;
+                                  a plan copies them into its own node-interleaved layout at the
+                                  start of each of its steps (the plan allocates 32 bytes per node) */
     QED_FIELD_ROTATING_E = 3   /* E0, B0 plus a uniform electric field of magnitude a0 rotating in the
                                   (x, y) plane at the reference frequency: E_x = a0 cos t,
                                   E_y = a0 sin t (the 0-D cascade setup of the polarized-cascade
