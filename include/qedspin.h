@@ -229,8 +229,9 @@ qed_status qed_tables_download(qed_tables tables, double *lnrate, int64_t *n_lnr
    max_particles elements (leptons or photons, whichever is larger). */
 size_t qed_workspace_size(int64_t max_particles);
 
-/* Lorentz (Boris) push with fields at (x, t), T-BMT rotation (if QED_TBMT), then
-   x += v dt, for leptons [0, *d_count).  In place. */
+/* Lorentz (Boris) push with fields at (x, t), T-BMT rotation (if QED_TBMT; with QED_G_CHI the
+   anomalous moment from the tables' g-factor table), then x += v dt, for leptons [0, *d_count).
+   In place. */
 qed_status qed_push_spin(const qed_leptons *leptons, const qed_fields *fields,
                          const qed_step_params *params, qed_tables tables, qed_stream stream);
 
@@ -278,8 +279,10 @@ qed_status qed_profile_stop(qed_kernel_time *out, int max_entries, int *n_entrie
    qed_plan_step produces the same particles, bit for bit, for every instance at once: a lepton
    and a photon streaming launch over all particle sets (each set owns a contiguous range of
    blocks), then one launch that does the bookkeeping and processes the emitters and the
-   decaying photons (with a learned inverse CDF too: the network runs in that launch).  Appends keep the per-species
-   order (photons of electrons, then of positrons, in emitter order; pairs in photon order). */
+   decaying photons (with a learned inverse CDF too: the network runs in that launch); an
+   instance with grid fields adds one launch that refreshes the plan's interleaved copy of its
+   grid.  Appends keep the per-species order (photons of electrons, then of positrons, in
+   emitter order; pairs in photon order). */
 typedef struct {
     qed_leptons     electrons;   /* species 0 */
     qed_leptons     positrons;   /* species 1; stepped (and filled by pairs) only with QED_PAIR */
@@ -309,11 +312,12 @@ typedef struct {
 typedef struct qed_plan_s *qed_plan;   /* opaque, library-owned */
 
 /* Copy the instance descriptions (pointers, capacities, fields, parameters) to the device and
-   allocate the plan's scratch: two mask planes of one bit per particle slot, per-block counts
-   and per-set bookkeeping.  Allocates device memory and synchronizes the device; afterwards the
-   arrays and counters named here must stay allocated and keep their addresses.  config may be
-   NULL.  QED_ERR_INVALID for a NULL pointer, an inconsistent set (species, missing arrays,
-   dt or eps_r <= 0, no d_clock or d_counters) or more than 2^24 blocks. */
+   allocate the plan's scratch: two mask planes of one bit per particle slot, per-block counts,
+   per-set bookkeeping and, per instance with grid fields, 32 bytes per grid node.  Allocates
+   device memory and synchronizes the device; afterwards the arrays and counters named here must
+   stay allocated and keep their addresses.  config may be NULL.  QED_ERR_INVALID for a NULL
+   pointer, an inconsistent set (species, missing arrays, dt or eps_r <= 0, no d_clock or
+   d_counters), QED_SUBCYCLE, QED_REJECTION with QED_OPTICAL_DEPTH, or more than 2^24 blocks. */
 qed_status qed_plan_create(qed_tables tables, int n_instances, const qed_instance *instances,
                            const qed_plan_config *config, qed_plan *out);
 
