@@ -493,7 +493,7 @@ def main():
     ap.add_argument("--compact-every", type=int, default=50)
     ap.add_argument("--no-fp64", action="store_true", help="skip timing the FP64 path")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample", type=int, default=3000)
+    ap.add_argument("--cpu-sample", type=int, default=30000)
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the learned-inverse-CDF, batched and spectral-error measurements")
     ap.add_argument("--batched-scale", type=float, default=0.05,
