@@ -210,7 +210,7 @@ __device__ __forceinline__ void bessel_sums32(float x, const void *nodes, float 
                 done = true;
                 break;
             }
-            const float e = expf(-x * a[u].x);
+            const float e = exp_r(-x * a[u].x);
             s13 += e * a[u].y;
             s23 += e * a[u].z;
             sik += e * a[u].w;
@@ -253,7 +253,7 @@ template <> __device__ __forceinline__ void bessel_abs<float>(double xd, const v
     int lvl;
     bessel_sums32(x, nodes, s13, s23, sik, lvl);
     const float h = (float)(lvl == 0 ? kBn32H[0] : (lvl == 1 ? kBn32H[1] : kBn32H[2]));
-    const float f = h * expf(-x);
+    const float f = h * exp_r(-x);
     K13 = s13 * f;
     K23 = s23 * f;
     IK = sik * f;
