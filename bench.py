@@ -507,7 +507,7 @@ def main():
                     help="profiler run: copy calibration + the FP32 path, eager, no JSON line")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py: this build measures one GPU; multi-GPU runs are out of scope (the path shards by "
+        print("bench.py measures one GPU; multi-GPU runs are out of scope (the path shards by "
               "particle index with no per-step exchange).", file=sys.stderr)
         sys.exit(2)
 

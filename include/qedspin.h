@@ -342,7 +342,7 @@ qed_status qed_plan_destroy(qed_plan plan);
    64 SiLU units; output nu = 20 y.  12801 parameters in the flat order W1 (3x64, row = input),
    b1, W2 (64x64, row = input unit), b2, W3, b3, W4, b4, W5 (64), b5.  Evaluation runs the 64x64
    layers on the matrix cores in BF16 with FP32 accumulation (BF16 weights); the tables remain
-   the fallback and the judge of its error. */
+   the alternative and the reference its error is measured against. */
 int64_t qed_surrogate_n_params(void);
 
 /* Allocate a surrogate for process 0 (NLC) or 1 (NBW) of these tables, parameters initialized

@@ -3,8 +3,8 @@
 // Training data come from the library's own inverse-CDF tables (FP64 interpolation, the same
 // lookup the table path uses): every step draws fresh samples (ln chi, rho, c) from Philox
 // channel 6 (ln chi uniform; rho half uniform, half distributed as in the sampling) and fits
-// y = nu/out_s by mean squared error with Adam.  The tables stay the fallback
-// and the judge of the network's error.
+// y = nu/out_s by mean squared error with Adam.  The tables stay the alternative
+// and the reference the network's error is measured against.
 //   k_mlp_grad   forward + backward of 16-row tiles per wave on the matrix cores; parameter
 //                gradients summed per block in LDS, written per block
 //   k_mlp_adam   sums the block gradients, Adam update of the FP32 master, BF16 copy
