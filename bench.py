@@ -378,8 +378,8 @@ def grid_run(q, tab, args, n=1 << 24, steps=200):
 def subcycle_study(q, tab, n=100_000, steps=200):
     """Per-particle sub-cycling in the test-particle workload (W dt ~ 0.95 at the start): the
     electrons' mean energy loss and mean s.beta after `steps` steps with the plain step and with
-    sub-cycling, against the plain step at dt/16 (16 x the steps), and the throughput of both (eager
-    per-species calls, FP64, lepton-steps per second)"""
+    sub-cycling, against the plain step at dt/16 (16 x the steps), and the throughput of both
+    (per-species calls replayed from HIP graphs, FP64, lepton-steps per second)"""
     import torch
     from paper_2511_08929_amd.sim import Simulation
     w = synth.c1(n=n)
@@ -388,14 +388,13 @@ def subcycle_study(q, tab, n=100_000, steps=200):
 
     def run(dt, nsteps, flags, every):
         sim = Simulation(tab, cap_e=n, cap_p=1, cap_g=24 * n, track=w.track, fields=q.make_fields(w.field_kind, B0=w.B0),
-                         dt=dt, eps_r=synth.EPS_R, seed=w.seed, flags=flags, k_retire=1e30)
+                         dt=dt, eps_r=synth.EPS_R, seed=w.seed, flags=flags, k_retire=1e30, device_clock=True)
         sim.e.load(w.x, w.p, w.s)
+        g = sim.capture(every)                    # `every` steps and a compaction
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        for k in range(nsteps):
-            sim.step()
-            if k % every == every - 1:
-                sim.compact()
+        for _ in range(nsteps // every):
+            sim.replay(g)
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
         _, p, s = sim.e.arrays()
