@@ -416,6 +416,30 @@ def subcycle_study(q, tab, n=100_000, steps=200):
     for key, r in (("plain", plain), ("subcycled", sub)):
         res[key]["energy_loss_rel_error"] = round(abs(r["loss"] / ref["loss"] - 1), 5)
         res[key]["s_beta_abs_error"] = round(abs(r["s_beta"] - ref["s_beta"]), 5)
+    # a mixed population: the head-on collision at a0 = 300, where only leptons near the field
+    # maxima need more than one sub-step (same per-species calls and graph replays)
+    wh = synth.subsample(synth.c2(a0=300.0), np.arange(100_000))
+    mixed = {}
+    for key, fl in (("plain", q.QED_ALL), ("subcycled", q.QED_ALL | q.QED_SUBCYCLE)):
+        sim = Simulation(tab, cap_e=4 * wh.n, cap_p=3 * wh.n, cap_g=40 * wh.n, track=wh.track,
+                         fields=q.make_fields(wh.field_kind, a0=wh.a0, phase_len=wh.phase_len), dt=wh.dt,
+                         eps_r=synth.EPS_R, seed=wh.seed, flags=fl, k_retire=wh.k_retire, device_clock=True)
+        sim.e.load(wh.x, wh.p, wh.s)
+        g = sim.capture(50)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(1700 // 50):
+            sim.replay(g)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        c = q.counters_dict(sim.ctr)
+        mixed[key] = {"value": round((c["n_lepton_steps"] + c["n_photon_steps"]) / wall, 1), "wall_s": round(wall, 4),
+                      "photons_emitted": c["n_emit"], "pairs": c["n_pair"]}
+        del sim, g
+        torch.cuda.empty_cache()
+    res["head_on_a0_300"] = {"workload": "head-on collision at a0 = 300, 10^5 electrons, 1700 steps, FP64, "
+                                         "per-species calls replayed from graphs", "unit": "particle-QED-steps/s",
+                             **mixed}
     log(f"sub-cycling: {res}")
     return res
 

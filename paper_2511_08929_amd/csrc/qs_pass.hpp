@@ -412,6 +412,24 @@ __device__ __forceinline__ void lepton_range(const LepDev<R> &L, const FieldDev 
                                              LCount &c)
 {
     const int lane = threadIdx.x & 63;
+    if constexpr ((DEC & 4) != 0) {
+        if (S.sub_round > 0) {
+            // a later sub-cycling round: only the leptons with a sub-step in it load their state
+            for (int64_t base = start + (threadIdx.x & ~63); base < end; base += blockDim.x) {
+                const int64_t i = base + lane;
+                bool emit = false, up = false;
+                if (i < end && (S.sub_round & ((kSubRounds >> L.msub[i]) - 1)) == 0)
+                    lepton_item<R, DEC, FLD>(L, F, S, T, lds, i, ldx(L.x, i), ld3(L.p, i), ld3(L.s, i), emit, up, c);
+                const uint64_t m = __ballot(emit), mu = __ballot(up);
+                if (lane == 0) {
+                    mask[base >> 6] = m;
+                    mask[nchunks + (base >> 6)] = mu;
+                    c.trans += __popcll(m);
+                }
+            }
+            return;
+        }
+    }
     // the next particle's x, p, s are loaded before this one is worked on
     V3<R> xn = {0, 0, 0}, pn = {0, 0, 0}, sn = {0, 0, 0};
     {
