@@ -564,7 +564,10 @@ __device__ __forceinline__ void photon_tile(const PhoDev<R> &G, const FieldDev &
     if (threadIdx.x == 0) Q.n = 0;
     __syncthreads();
     // the slots of this thread: all loads first (id, k and x do not wait for each other), then the
-    // work; a dead slot (id 0) loads values it never uses
+    // work; a dead slot (id 0) loads values it never uses.  The pass streams through the photon
+    // store once per step, so these reads and the position write are non-temporal: they do not
+    // push the lepton arrays and tables out of the caches (the sparse P-vector accesses of phase
+    // 2 stay ordinary: non-temporal partial writes cost more there)
     constexpr int kPer = kPhoTile / kBlock;
     uint64_t idv[kPer];
     V3<R> kv[kPer], xv[kPer];
@@ -573,9 +576,12 @@ __device__ __forceinline__ void photon_tile(const PhoDev<R> &G, const FieldDev &
         const int64_t i = tile + (threadIdx.x & ~63) + (int64_t)u * kBlock + lane;
         idv[u] = 0;
         if (i < tend) {
-            idv[u] = G.id[i];
-            kv[u] = ld3(G.k, i);
-            xv[u] = ldx(G.x, i);
+            idv[u] = __builtin_nontemporal_load(&G.id[i]);
+            kv[u] = {__builtin_nontemporal_load(&G.k[0][i]), __builtin_nontemporal_load(&G.k[1][i]),
+                     __builtin_nontemporal_load(&G.k[2][i])};
+            xv[u] = {G.x[0] ? __builtin_nontemporal_load(&G.x[0][i]) : (R)0,
+                     G.x[1] ? __builtin_nontemporal_load(&G.x[1][i]) : (R)0,
+                     G.x[2] ? __builtin_nontemporal_load(&G.x[2][i]) : (R)0};
         }
     }
 #pragma unroll
@@ -591,7 +597,9 @@ __device__ __forceinline__ void photon_tile(const PhoDev<R> &G, const FieldDev &
             const R k0r = sqrt_r(dot(k, k));
             V3<R> x = xv[u];
             x = x + ((R)S.dt / k0r) * k;
-            stx(G.x, i, x);
+            if (G.x[0]) __builtin_nontemporal_store(x.x, &G.x[0][i]);
+            if (G.x[1]) __builtin_nontemporal_store(x.y, &G.x[1][i]);
+            if (G.x[2]) __builtin_nontemporal_store(x.z, &G.x[2][i]);
             // retirement: too soft to ever reach chi_min, or behind the trailing edge of the
             // plane-wave pulse (the phase t + x of a photon never decreases)
             const bool behind = F.kind == 1 && F.phase_len > 0.0 && S.t + S.dt + (double)x.x > F.phase_len;
