@@ -223,11 +223,51 @@ __device__ __forceinline__ void bessel_sums32(float x, const void *nodes, float 
     }
 }
 
+// Small x (below 1/2) in FP32: the ascending series K_nu = (pi / (2 sin nu pi)) (I_-nu - I_nu) with
+// I_mu = sum_k (x/2)^(2k+mu) / (k! Gamma(k+mu+1)) (sin(pi/3) = sin(2 pi/3), so one factor pi/sqrt3
+// for both orders), and IntK_1/3(x) = pi/sqrt3 - int_0^x K_1/3 from the term-wise integrals
+// 2 (x/2)^(2k+mu+1) / ((2k+mu+1) k! Gamma(k+mu+1)); the common factor pi/sqrt3 cancels in the
+// ratios.  Seven terms: the eighth is below 1e-9 of the first at x = 1/2.
+template <int M3> struct SmallSeries {                 // mu = M3 / 3
+    static __device__ __forceinline__ void sum(float h, float lh, float rg, float &s, float &j)
+    {
+        constexpr float mu = (float)M3 / 3.0f;
+        const float h2 = h * h;
+        float t = rg * exp_r(mu * lh);                  // (x/2)^mu / Gamma(mu + 1)
+        s = t;
+        j = t * h * (2.0f / (mu + 1.0f));
+#pragma unroll
+        for (int k = 1; k < 7; ++k) {
+            t *= h2 * (1.0f / ((float)k * ((float)k + mu)));
+            s += t;
+            j += t * h * (2.0f / (2.0f * (float)k + mu + 1.0f));
+        }
+    }
+};
+
+__device__ __forceinline__ void bessel_ratios_small32(float x, float &K1, float &I)
+{
+    const float h = 0.5f * x, lh = log_r(h);
+    float sm2, jm2, sm1, jm1, sp1, jp1, sp2, jp2;
+    SmallSeries<-2>::sum(h, lh, 1.0f / 2.678938534707747f, sm2, jm2);      // 1 / Gamma(1/3)
+    SmallSeries<-1>::sum(h, lh, 1.0f / 1.3541179394264005f, sm1, jm1);     // 1 / Gamma(2/3)
+    SmallSeries<1>::sum(h, lh, 1.0f / 0.8929795115692492f, sp1, jp1);      // 1 / Gamma(4/3)
+    SmallSeries<2>::sum(h, lh, 1.0f / 0.9027452929509336f, sp2, jp2);      // 1 / Gamma(5/3)
+    const float k23 = sm2 - sp2;
+    K1 = (sm1 - sp1) / k23;
+    I = (1.0f - (jm1 - jp1)) / k23;
+}
+
 template <> __device__ __forceinline__ void bessel_ratios<float>(double xd, const void *nodes, float &K1, float &I)
 {
+    const float x = fmaxf((float)xd, 1e-30f);
+    if (x < 0.5f) {
+        bessel_ratios_small32(x, K1, I);
+        return;
+    }
     float s13, s23, sik;
     int lvl;
-    bessel_sums32(fmaxf((float)xd, 1e-30f), nodes, s13, s23, sik, lvl);
+    bessel_sums32(x, nodes, s13, s23, sik, lvl);
     K1 = s13 / s23;       // the step h cancels in the ratios
     I = sik / s23;
 }
