@@ -245,7 +245,8 @@ template <int M3> struct SmallSeries {                 // mu = M3 / 3
     }
 };
 
-__device__ __forceinline__ void bessel_ratios_small32(float x, float &K1, float &I)
+// K_1/3, K_2/3 and IntK_1/3 at x < 1/2, each divided by pi/sqrt3
+__device__ __forceinline__ void bessel_small32(float x, float &k13, float &k23, float &ik)
 {
     const float h = 0.5f * x, lh = log_r(h);
     float sm2, jm2, sm1, jm1, sp1, jp1, sp2, jp2;
@@ -253,9 +254,17 @@ __device__ __forceinline__ void bessel_ratios_small32(float x, float &K1, float 
     SmallSeries<-1>::sum(h, lh, 1.0f / 1.3541179394264005f, sm1, jm1);     // 1 / Gamma(2/3)
     SmallSeries<1>::sum(h, lh, 1.0f / 0.8929795115692492f, sp1, jp1);      // 1 / Gamma(4/3)
     SmallSeries<2>::sum(h, lh, 1.0f / 0.9027452929509336f, sp2, jp2);      // 1 / Gamma(5/3)
-    const float k23 = sm2 - sp2;
-    K1 = (sm1 - sp1) / k23;
-    I = (1.0f - (jm1 - jp1)) / k23;
+    k13 = sm1 - sp1;
+    k23 = sm2 - sp2;
+    ik = 1.0f - (jm1 - jp1);
+}
+
+__device__ __forceinline__ void bessel_ratios_small32(float x, float &K1, float &I)
+{
+    float k13, k23, ik;
+    bessel_small32(x, k13, k23, ik);
+    K1 = k13 / k23;
+    I = ik / k23;
 }
 
 template <> __device__ __forceinline__ void bessel_ratios<float>(double xd, const void *nodes, float &K1, float &I)
@@ -289,6 +298,14 @@ template <> __device__ __forceinline__ void bessel_abs<float>(double xd, const v
                                                               float &IK)
 {
     const float x = fmaxf((float)xd, 1e-30f);
+    if (x < 0.5f) {
+        constexpr float c = 1.8137993642342178f;    // pi / sqrt3
+        bessel_small32(x, K13, K23, IK);
+        K13 *= c;
+        K23 *= c;
+        IK *= c;
+        return;
+    }
     float s13, s23, sik;
     int lvl;
     bessel_sums32(x, nodes, s13, s23, sik, lvl);
