@@ -37,3 +37,31 @@ def test_binding_has_no_cpu_fallback(tmp_path, monkeypatch):
     monkeypatch.setattr(q, "_lib", None)
     with pytest.raises(q.QedError):
         q.lib()
+
+
+def _header_enum_values():
+    text = HEADER.read_text()
+    vals = {m.group(1): 1 << int(m.group(2)) for m in re.finditer(r"\b(QED_[A-Z0-9_]+)\s*=\s*1u\s*<<\s*(\d+)", text)}
+    for m in re.finditer(r"\b(QED_FIELD_[A-Z0-9_]+)\s*=\s*(\d+)", text):
+        vals[m.group(1)] = int(m.group(2))
+    return vals
+
+
+def test_flag_values_agree_across_header_binding_and_oracle():
+    """The physics switches and field models have one meaning everywhere: the header's values,
+    the binding's constants and the oracle's (whose flag words the tests pass straight through)."""
+    import oracle
+    import paper_2511_08929_amd as q
+    hv = _header_enum_values()
+    assert len(hv) >= 19
+    for name, v in hv.items():
+        assert getattr(q, name) == v, name
+    pairs = {"QED_PUSH": "F_PUSH", "QED_TBMT": "F_TBMT", "QED_EMIT": "F_EMIT", "QED_RECOIL": "F_RECOIL",
+             "QED_SPIN": "F_SPIN", "QED_NOEMIT": "F_NOEMIT", "QED_PHOTON_POL": "F_PHOTON_POL", "QED_MEAN": "F_MEAN",
+             "QED_PAIR": "F_PAIR", "QED_NOPAIR": "F_NOPAIR", "QED_PAIR_SPIN": "F_PAIR_SPIN",
+             "QED_OPTICAL_DEPTH": "F_TAU", "QED_REJECTION": "F_REJECT", "QED_G_CHI": "F_GCHI",
+             "QED_SUBCYCLE": "F_SUB", "QED_FIELD_UNIFORM": "FIELD_UNIFORM", "QED_FIELD_PLANE_LP": "FIELD_PLANE_LP",
+             "QED_FIELD_GRID2D": "FIELD_GRID2D", "QED_FIELD_ROTATING_E": "FIELD_ROTATING_E"}
+    for h, o in pairs.items():
+        assert hv[h] == getattr(oracle, o), (h, o)
+    assert q.QED_ALL == oracle.F_ALL
