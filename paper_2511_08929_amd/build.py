@@ -16,6 +16,10 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC", "-shared",
          # FP32 division and square root by the hardware approximations (FP64 is unaffected)
          "-fno-hip-fp32-correctly-rounded-divide-sqrt",
+         # FP32 denormals flushed to zero (FP64 keeps them): the single-precision values of the
+         # step are far from 1e-38, and reciprocals, square roots and exponentials then need no
+         # rescaling around the hardware instructions
+         "-fgpu-flush-denormals-to-zero",
          # fused multiply-add only where one source expression has the form a*b+c: the same
          # function inlined into different kernels then rounds the same way, so the per-species
          # calls and the merged step agree bit for bit
