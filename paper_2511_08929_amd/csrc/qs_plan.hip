@@ -83,9 +83,12 @@ struct PlanDev {
 };
 
 // The streaming pass runs as two launches with their own register allocation: PHO = 0 over the
-// lepton segments (blocks [0, nblk_lep)), PHO = 1 over the photon segments (the rest).
+// lepton segments (blocks [0, nblk_lep)), PHO = 1 over the photon segments (the rest).  The plain
+// FP32 lepton pass runs five waves per SIMD; its other variants and the photon pass four.
 template <class R, int PHO, int DEC, int FLD>
-__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 ? 4 : 1))) k_plan_main(const InstDev<R> *inst, PlanDev P, TablesDev T, int b_first)
+__global__ void __launch_bounds__(kBlock)
+__attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 ? ((PHO == 0 && DEC == 0 && FLD == kFldPlain) ? 5 : 4) : 1)))
+k_plan_main(const InstDev<R> *inst, PlanDev P, TablesDev T, int b_first)
 {
     extern __shared__ unsigned char smem_raw[];
     R *lds = reinterpret_cast<R *>(smem_raw);
