@@ -84,14 +84,11 @@ struct PlanDev {
 
 // The streaming pass runs as two launches with their own register allocation: PHO = 0 over the
 // lepton segments (blocks [0, nblk_lep)), PHO = 1 over the photon segments (the rest).  Waves per
-// SIMD in FP32: five for the plain lepton pass, three for the photon pass of the general field
-// variant (which spills at four), four otherwise.
+// SIMD in FP32: three for the photon pass of the general field variant (which spills at four),
+// four otherwise.
 template <class R, int PHO, int DEC, int FLD>
 __global__ void __launch_bounds__(kBlock)
-__attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 ? ((PHO == 0 && DEC == 0 && FLD == kFldPlain) ? 5
-                                                     : (PHO == 1 && FLD == kFldGeneral)             ? 3
-                                                                                                   : 4)
-                                                  : 1)))
+__attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 ? ((PHO == 1 && FLD == kFldGeneral) ? 3 : 4) : 1)))
 k_plan_main(const InstDev<R> *inst, PlanDev P, TablesDev T, int b_first)
 {
     extern __shared__ unsigned char smem_raw[];
