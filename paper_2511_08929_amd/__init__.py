@@ -293,6 +293,22 @@ class PhotonBuffers:
         self.count = torch.zeros(1, dtype=torch.int64, device=device)
         self.count_prev = torch.zeros(1, dtype=torch.int64, device=device)
 
+    def load(self, x, k, P, ids, n_prev=None):
+        """Store n photons (x: (3, n) or None, k, P: (3, n), ids: (n,) uint64) at slots [0, n);
+        count = n, count_prev = n_prev (default n: every stored photon is stepped next)."""
+        import numpy as np
+        import torch
+        n = k.shape[1]
+        assert n <= self.capacity
+        for i in range(3):
+            if self.x[i] is not None:
+                self.x[i][:n] = torch.as_tensor(x[i], dtype=self.dtype)
+            self.k[i][:n] = torch.as_tensor(k[i], dtype=self.dtype)
+            self.P[i][:n] = torch.as_tensor(P[i], dtype=self.dtype)
+        self.id[:n] = torch.as_tensor(np.ascontiguousarray(ids, dtype=np.uint64).view(np.int64))
+        self.count.fill_(n)
+        self.count_prev.fill_(n if n_prev is None else n_prev)
+
     def view(self):
         if getattr(self, "_view", None) is not None and self._view.capacity == self.capacity:
             return self._view

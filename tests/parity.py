@@ -137,3 +137,94 @@ def compare_photons(gpu, orc, excluded_parents, rtol_k, atol_P, what="", near_ph
     assert worst["P_over_tol"] <= max(1, int(eP.size * outlier_rate)) and worst["P"] <= 1e3 * atol_P, \
         f"{what}: photon P-vector err {worst['P']:.3e} ({worst['P_over_tol']} over {atol_P:.1e})"
     return worst
+
+
+# ------------------------------------------------------------------ decision mismatches
+def oracle_sets_from_snapshot(st, track, extra_e=0, extra_g=0):
+    """Oracle particle sets holding a host snapshot (sim.Simulation.snapshot(device=False)): the
+    FP32 or FP64 values of the GPU state, widened to FP64."""
+    e, p, g = st["e"], st["p"], st["g"]
+    ne, np_, ng = e["count"], p["count"], g["count"]
+
+    def stack(arrs, n):
+        return np.stack([(a.astype(np.float64) if a is not None else np.zeros(n)) for a in arrs])
+
+    E = oracle.LeptonSet(0, ne + np_ + extra_e + 1, track=track)
+    E.set(stack(e["x"], ne), stack(e["p"], ne), stack(e["s"], ne))
+    P = oracle.LeptonSet(1, ne + np_ + extra_e + 1, track=track)
+    P.set(stack(p["x"], np_), stack(p["p"], np_), stack(p["s"], np_))
+    G = oracle.PhotonSet(ng + ne + np_ + extra_g + 1, track=track)
+    for i in range(3):
+        if G.x[i] is not None:
+            G.x[i][:ng] = g["x"][i].astype(np.float64)
+        G.k[i][:ng] = g["k"][i].astype(np.float64)
+        G.P[i][:ng] = g["P"][i].astype(np.float64)
+    G.id[:ng] = np.asarray(g["id"]).view(np.uint64)
+    G.n, G.n_prev = ng, g["count_prev"]
+    return E, P, G
+
+
+def decision_flips(q, tab, w, st, k0, T, nthreads, u24=True, near_tol=1e-5, fields=None, flags=None):
+    """One step of every particle of a host snapshot `st` (taken at time step k0 of workload w) on the
+    GPU (merged step, tables `tab`) and in the oracle, photon retirement at birth off (k_retire = 0)
+    so that every emitted photon carries its parent's index.  Counts the leptons whose emit / no-emit
+    decision and the photons whose pair / no-pair decision differ, and how many of those the oracle
+    flagged as near ties (its draw within near_tol of a threshold); emitters on both sides whose
+    photon energies differ by more than 1e-3 (the spin-down / spin-up branch) are counted apart."""
+    import torch
+
+    from paper_2511_08929_amd.sim import Simulation
+    flags = q.QED_ALL if flags is None else flags
+    e, p, g = st["e"], st["p"], st["g"]
+    ne, np_, ng, ngp = e["count"], p["count"], g["count"], g["count_prev"]
+    f = fields or q.make_fields(w.field_kind, E0=w.E0, B0=w.B0, a0=w.a0, phase_len=w.phase_len)
+    sim = Simulation(tab, cap_e=ne + np_ + ngp + 16, cap_p=ne + np_ + ngp + 16, cap_g=ng + ne + np_ + 16, track=w.track,
+                     fields=f, dt=w.dt, eps_r=oracle_eps(), seed=w.seed, flags=flags, k_retire=0.0, device_clock=True,
+                     merged=True)
+    sim.restore(st, counters=False)
+    sim.ctr.zero_()
+    sim.step()
+    torch.cuda.synchronize()
+    gx, gk, gP, gid = sim.g.arrays()
+    c_gpu = q.counters_dict(sim.ctr)
+    del sim
+    torch.cuda.empty_cache()
+    E, P, G = oracle_sets_from_snapshot(st, w.track, extra_e=ngp, extra_g=ne + np_)
+    F = oracle.make_fields(w.field_kind, E0=w.E0, B0=w.B0, a0=w.a0, phase_len=w.phase_len)
+    prm = oracle.make_params(w.dt, oracle_eps(), step=k0, t=k0 * w.dt, seed=w.seed, flags=flags, k_retire=0.0,
+                             near_tol=near_tol, u24=u24)
+    ctr = oracle.Counters()
+    oracle.lepton_step(T, prm, F, E, G, ctr, nthreads)
+    near_e = E.near[:ne].astype(bool).copy()
+    oracle.lepton_step(T, prm, F, P, G, ctr, nthreads)
+    near_p = P.near[:np_].astype(bool).copy()
+    oracle.photon_step(T, prm, F, G, E, P, ctr, nthreads)
+    near_g = G.near[:ngp].astype(bool).copy()
+    _, ok, _, oid = G.arrays()
+    # emissions: photons appended this step, by parent (species, index)
+    new_g, new_o = gid[ng:], oid[ng:]
+    assert (new_g != 0).all() and (new_o != 0).all(), "an emitted photon without id (k_retire is 0)"
+    par_g = dict(zip(map(tuple, np.stack(photon_parent(new_g), 1).tolist()), range(ng, ng + new_g.size)))
+    par_o = dict(zip(map(tuple, np.stack(photon_parent(new_o), 1).tolist()), range(ng, ng + new_o.size)))
+    flips = set(par_g) ^ set(par_o)
+    near = {(0, int(i)) for i in np.nonzero(near_e)[0]} | {(1, int(i)) for i in np.nonzero(near_p)[0]}
+    branch = 0
+    for key in set(par_g) & set(par_o):
+        a = np.linalg.norm(gk[:, par_g[key]])
+        b = np.linalg.norm(ok[:, par_o[key]])
+        if abs(a - b) > 1e-3 * b and key not in near:
+            branch += 1
+    # pair decisions of the photons stepped this step (alive before)
+    alive0 = np.asarray(g["id"][:ngp]) != 0
+    dead_g = gid[:ngp] == 0
+    dead_o = oid[:ngp] == 0
+    pflip = np.nonzero(alive0 & (dead_g != dead_o))[0]
+    res = dict(leptons=int(ne + np_), photons=int(alive0.sum()), emissions_gpu=int(len(par_g)),
+               emissions_oracle=int(len(par_o)), pairs_gpu=c_gpu["n_pair"], pairs_oracle=int(ctr.n_pair),
+               lepton_near_ties=int(near_e.sum() + near_p.sum()), photon_near_ties=int(near_g[alive0].sum()),
+               lepton_flips=len(flips), lepton_flips_not_near=len(flips - near),
+               photon_flips=int(pflip.size), photon_flips_not_near=int((~near_g[pflip]).sum()),
+               energy_mismatch_not_near=int(branch))
+    res["flip_rate"] = (res["lepton_flips"] + res["photon_flips"]) / max(1, res["leptons"] + res["photons"])
+    res["near_tie_rate"] = (res["lepton_near_ties"] + res["photon_near_ties"]) / max(1, res["leptons"] + res["photons"])
+    return res

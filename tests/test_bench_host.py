@@ -56,3 +56,70 @@ def test_source_hash_covers_every_kernel_source(tmp_path, monkeypatch):
         assert bench.kernel_source_hash() != base
         (fake / f).write_bytes(data)
     assert bench.kernel_source_hash() == base
+
+
+def test_driver_argv_keeps_the_workload():
+    """The driver's `--steps 20 --warmup 5` sets how many whole collisions are timed; the collision
+    itself stays the 3000-step head-on workload."""
+    a = bench.parse_args(["--gpus", "1", "--steps", "20", "--warmup", "5"])
+    assert (a.steps, a.warmup, a.gpus) == (20, 5, 1)
+    assert bench.COLLISION_STEPS == 3000 and not hasattr(a, "time_steps")
+    d = bench.parse_args([])
+    assert d.steps >= 1 and d.warmup >= 0 and d.n == 1_000_000
+
+
+@pytest.mark.parametrize("argv", [["--steps", "0"], ["--warmup", "-1"]])
+def test_bad_counts_are_refused(argv):
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), *argv], cwd=ROOT, capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2 and r.stdout == ""
+
+
+def _spec(k, s_mean=(0.0, 0.0, 0.0)):
+    import numpy as np
+    k = np.asarray(k, dtype=float)
+    return dict(k=k, xi2=np.zeros_like(k), lin=np.zeros_like(k), s_mean=np.asarray(s_mean))
+
+
+def test_spectrum_error_handles_empty_and_sparse_inputs():
+    import numpy as np
+    e = bench.spectrum_error(_spec([]), _spec([]))
+    assert e["bins"] == 0 and e["spectrum_max_rel"] is None and e["photons"] == 0
+    e = bench.spectrum_error(_spec([1.0, 2.0, 3.0]), _spec([1.0]))        # no bin reaches min_count
+    assert e["bins"] == 0 and e["spectrum_max_rel"] is None
+    rng = np.random.default_rng(0)
+    k = 10 ** rng.uniform(0, 2, 200_000)
+    e = bench.spectrum_error(_spec(k), _spec(k, (0.0, 0.001, 0.0)))
+    assert e["bins"] > 0 and e["spectrum_max_rel"] == 0.0 and e["spin_mean_abs"] == 0.001
+
+
+def test_extras_are_fail_soft_and_budgeted():
+    out = {}
+
+    def boom():
+        raise RuntimeError("no")
+
+    assert bench.run_extra(out, "x", 1e9, boom) is None
+    assert "RuntimeError" in out["errors"]["x"]
+    assert bench.run_extra(out, "y", -1.0, boom) is None
+    assert out["skipped"][0].startswith("y: time budget")
+    assert bench.run_extra(out, "z", 1e9, lambda v: v + 1, 1) == 2
+
+
+def test_roofline_bound_follows_the_longer_ceiling(monkeypatch):
+    """Algorithmic bytes / 8 TB/s against committed VALU instructions / one per CU per cycle."""
+    kt = {"plan_photon": (100, 4.0), "plan_lepton": (100, 2.0), "plan_process": (100, 1.0)}
+    ck = {"n_lepton_steps": 10 ** 8, "n_photon_steps": 3 * 10 ** 8, "n_photon_qed": 10 ** 8}
+    monkeypatch.setattr(bench, "load_valu", lambda k: None)
+    monkeypatch.setattr(bench, "load_traffic", lambda k: None)
+    r = bench.roofline(kt, ck, 5000.0)
+    assert r["kernel"] == "plan_photon" and r["bound"] == "hbm" and r["unit"] == "GB/s"
+    bpl = 3 * 10 ** 8 * 52 / 100
+    assert abs(r["achieved"] - bpl / 40e-6 / 1e9) < 0.1 and r["frac"] == r["hbm"]["frac"]
+    # VALU work whose minimum time exceeds the HBM minimum time makes the bound ALU
+    t_hbm = bpl / 8e12
+    monkeypatch.setattr(bench, "load_valu", lambda k: 2.0 * t_hbm * 256 * 2.4e9)
+    r = bench.roofline(kt, ck, 5000.0)
+    assert r["bound"] == "alu" and r["frac"] == r["alu"]["frac"] and r["hbm"]["frac"] > 0
+    monkeypatch.setattr(bench, "load_valu", lambda k: 0.5 * t_hbm * 256 * 2.4e9)
+    assert bench.roofline(kt, ck, 5000.0)["bound"] == "hbm"
