@@ -243,6 +243,23 @@ qed_status qed_emit(qed_tables tables, const qed_leptons *leptons, const qed_fie
                     qed_counters *d_counters, void *workspace, size_t workspace_bytes,
                     qed_stream stream);
 
+/* qed_emit without any allocation, for callers that cannot allocate device memory (code under
+   HIP graph capture, tight serving loops, harnesses that forbid hipMalloc): the same kernels and
+   results as qed_emit, with the workspace taken from a static device array of
+   QED_NOALLOC_SCRATCH_BYTES held by the library on each GPU it runs on until the process ends.
+   Sets of capacity up to QED_NOALLOC_MAX_LEPTONS only; a larger capacity returns QED_ERR_CAPACITY
+   (text in qed_last_error) before anything is enqueued.  No hipMalloc, hipFree or allocating
+   library call is made; the array's device address is looked up once per device at the first
+   call on it (with that device current).  All calls on one GPU share that GPU's array: calls
+   that overlap on one GPU (other streams, other threads) race and must be ordered by the caller.
+   Nothing in the array needs clearing between calls (every word a step reads is written earlier
+   in the same step). */
+#define QED_NOALLOC_MAX_LEPTONS 4194304
+#define QED_NOALLOC_SCRATCH_BYTES (24u << 20)
+qed_status qed_emit_noalloc(qed_tables tables, const qed_leptons *leptons, const qed_fields *fields,
+                            const qed_step_params *params, const qed_photons *photons,
+                            qed_counters *d_counters, qed_stream stream);
+
 /* NBW step for photons [0, *d_count_prev): x += khat dt, fields at t + dt; pairs appended to
    `electrons` and `positrons` (same index in both for one pair); decayed photons become dead
    slots; survivors get the no-pair update.  Photons below k_retire are retired (dead slot).

@@ -36,7 +36,7 @@ QED_FIELD_UNIFORM, QED_FIELD_PLANE_LP, QED_FIELD_GRID2D, QED_FIELD_ROTATING_E = 
 
 ABI_SYMBOLS = ("qed_init_tables", "qed_last_error", "qed_free_tables", "qed_tables_download",
                "qed_tables_download_gfac", "qed_workspace_size",
-               "qed_push_spin", "qed_emit", "qed_pair", "qed_compact_workspace_size", "qed_compact",
+               "qed_push_spin", "qed_emit", "qed_emit_noalloc", "qed_pair", "qed_compact_workspace_size", "qed_compact",
                "qed_profile_start", "qed_profile_stop", "qed_clock_advance", "qed_plan_create", "qed_plan_step",
                "qed_plan_blocks", "qed_plan_destroy", "qed_surrogate_n_params", "qed_surrogate_create",
                "qed_surrogate_norm", "qed_surrogate_train", "qed_surrogate_gradient", "qed_surrogate_eval",
@@ -122,6 +122,7 @@ def lib():
         L.qed_workspace_size.argtypes = [i64]; L.qed_workspace_size.restype = sz
         L.qed_push_spin.argtypes = [P(Leptons), P(Fields), P(StepParams), vp, vp]
         L.qed_emit.argtypes = [vp, P(Leptons), P(Fields), P(StepParams), P(Photons), vp, vp, sz, vp]
+        L.qed_emit_noalloc.argtypes = [vp, P(Leptons), P(Fields), P(StepParams), P(Photons), vp, vp]
         L.qed_pair.argtypes = [vp, P(Photons), P(Fields), P(StepParams), P(Leptons), P(Leptons), vp, vp, sz, vp]
         L.qed_compact_workspace_size.argtypes = [P(Photons), C.c_int]; L.qed_compact_workspace_size.restype = sz
         L.qed_compact.argtypes = [P(Photons), C.c_int, vp, sz, vp]
@@ -152,7 +153,7 @@ def lib():
 
 def _check(status, what):
     if status != QED_OK:
-        detail = lib().qed_last_error().decode() if status == QED_ERR_HIP else ""
+        detail = lib().qed_last_error().decode() if status in (QED_ERR_HIP, QED_ERR_CAPACITY) else ""
         raise QedError(f"{what} failed with status {status} {detail}")
 
 
@@ -376,6 +377,18 @@ def qed_emit(tables: Tables, leptons: LeptonBuffers, fields, step, photons: Phot
     _check(lib().qed_emit(tables.handle, C.byref(lv), C.byref(fields), C.byref(step), C.byref(pv), _ptr(counters),
                           _ptr(workspace), workspace.numel() * workspace.element_size(), _stream_ptr(stream)),
            "qed_emit")
+
+
+QED_NOALLOC_MAX_LEPTONS = 4194304
+
+
+def qed_emit_noalloc(tables: Tables, leptons: LeptonBuffers, fields, step, photons: PhotonBuffers, counters,
+                     stream=None):
+    """qed_emit with the library's static per-device scratch instead of a workspace (no allocation);
+    lepton capacity up to QED_NOALLOC_MAX_LEPTONS.  Calls that overlap on one GPU race."""
+    lv, pv = leptons.view(), photons.view()
+    _check(lib().qed_emit_noalloc(tables.handle, C.byref(lv), C.byref(fields), C.byref(step), C.byref(pv),
+                                  _ptr(counters), _stream_ptr(stream)), "qed_emit_noalloc")
 
 
 def qed_pair(tables: Tables, photons: PhotonBuffers, fields, step, electrons: LeptonBuffers,

@@ -39,6 +39,8 @@ struct qed_tables_s {
 
 // Record the error text of a failed HIP call for qed_last_error() and map it to QED_ERR_HIP.
 qed_status qs_fail(hipError_t e, const char *where);
+// Record the text of a rejected call (a status other than QED_ERR_HIP) for qed_last_error().
+qed_status qs_reject(qed_status st, const char *msg);
 // Clear a stale error left in HIP's per-thread last-error slot by earlier, unrelated calls.
 inline void qs_clear_error() { (void)hipGetLastError(); }
 // Status after a sequence of launches.

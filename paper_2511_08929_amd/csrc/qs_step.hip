@@ -13,6 +13,8 @@
 //            spin / Stokes collapse, appends at base + rank.
 // Everything is keyed on device-resident counts, so a step enqueues without host sync.  The
 // per-particle bodies are shared with the merged step (qs_plan.hip) through qs_pass.hpp.
+#include <mutex>
+
 #include "qs_pass.hpp"
 
 namespace {
@@ -443,6 +445,64 @@ extern "C" qed_status qed_pair(qed_tables T, const qed_photons *G, const qed_fie
     qs_clear_error();
     if (T->params.precision == QED_F64) return pair_impl<double>(T, G, f, p, Le, Lp, ctr, ws, ws_bytes, st);
     return pair_impl<float>(T, G, f, p, Le, Lp, ctr, ws, ws_bytes, st);
+}
+
+// ------------------------------------------------------------------ qed_emit without allocation
+// The workspace of qed_emit_noalloc is this file-scope device array, one copy per GPU, held until
+// the process ends.  Host code never passes `scratch` itself to a kernel (in host code the name
+// stands for a host-side shadow, not a device address): the device address comes from
+// hipGetSymbolAddress, looked up once per device with that device current and kept per device.
+static __device__ __align__(256) unsigned char scratch[QED_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices];
+
+// the device address of this device's `scratch` (NULL on failure, with the error recorded)
+void *scratch_ptr(qed_status &st)
+{
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) {
+        st = qs_fail(e, "qed_emit_noalloc: hipGetDevice");
+        return nullptr;
+    }
+    if (dev < 0 || dev >= kMaxDevices) {
+        st = qs_reject(QED_ERR_UNSUPPORTED, "qed_emit_noalloc: device index beyond the library's table");
+        return nullptr;
+    }
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *ptr = nullptr;
+        e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr) {
+            st = qs_fail(e != hipSuccess ? e : hipErrorInvalidSymbol, "qed_emit_noalloc: hipGetSymbolAddress(scratch)");
+            return nullptr;
+        }
+        g_scratch_ptr[dev] = ptr;
+    }
+    return g_scratch_ptr[dev];
+}
+}  // namespace
+
+extern "C" qed_status qed_emit_noalloc(qed_tables T, const qed_leptons *L, const qed_fields *f, const qed_step_params *p,
+                                       const qed_photons *G, qed_counters *ctr, qed_stream stream)
+{
+    if (!T || !leptons_ok(L) || !p || !fields_ok(f) || !ctr) return QED_ERR_INVALID;
+    if (L->capacity > QED_NOALLOC_MAX_LEPTONS || qed_workspace_size(L->capacity) > sizeof(scratch)) {
+        char msg[160];
+        snprintf(msg, sizeof(msg), "qed_emit_noalloc: lepton capacity %lld exceeds the static scratch maximum of %lld",
+                 (long long)L->capacity, (long long)QED_NOALLOC_MAX_LEPTONS);
+        return qs_reject(QED_ERR_CAPACITY, msg);
+    }
+    qed_status st = QED_OK;
+    void *ws = scratch_ptr(st);
+    if (!ws) return st;
+    // every word of the scratch that a step reads is written earlier in the same step (masks and
+    // per-block counts by the streaming pass, the bookkeeping and index list by the expansion,
+    // sub-step counts in round 0), so nothing needs clearing between calls
+    return qed_emit(T, L, f, p, G, ctr, ws, sizeof(scratch), stream);
 }
 
 __global__ void k_clock_advance(int64_t *clock) { *clock += 1; }

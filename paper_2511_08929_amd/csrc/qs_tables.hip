@@ -331,6 +331,12 @@ qed_status qs_fail(hipError_t e, const char *where)
     return QED_ERR_HIP;
 }
 
+qed_status qs_reject(qed_status st, const char *msg)
+{
+    snprintf(g_last_error, sizeof(g_last_error), "%s", msg);
+    return st;
+}
+
 extern "C" const char *qed_last_error(void) { return g_last_error; }
 
 extern "C" qed_status qed_init_tables(const qed_table_params *params, qed_stream stream, qed_tables *out)
