@@ -45,19 +45,52 @@ F_ALL = (F_PUSH | F_TBMT | F_EMIT | F_RECOIL | F_SPIN | F_NOEMIT | F_PHOTON_POL
 FIELD_UNIFORM, FIELD_PLANE_LP, FIELD_GRID2D, FIELD_ROTATING_E = 0, 1, 2, 3
 
 
-def build(force: bool = False) -> Path:
-    """Compile the oracle with gcc (portable -O2, OpenMP, no fast-math)."""
-    if LIB.exists() and not force and LIB.stat().st_mtime > max(SRC.stat().st_mtime, HDR.stat().st_mtime):
-        return LIB
-    tmp = LIB.with_suffix(".so.tmp")
-    cmd = ["gcc", "-O2", "-std=c11", "-D_GNU_SOURCE", "-fopenmp", "-fPIC", "-shared",
+# A second build of the same source with fused multiply-adds wherever an expression allows
+# (-mfma -ffp-contract=fast).  It is the same algorithm rounded differently: where the two builds
+# disagree on a particle, rounding alone moves that particle's trajectory that far, which the
+# parity tests use as the particle's sensitivity to rounding.
+LIB_FMA = HERE / "liborc_fma.so"
+_VARIANT_FLAGS = {"": [], "fma": ["-mfma", "-ffp-contract=fast"]}
+
+
+def build(force: bool = False, variant: str = "") -> Path:
+    """Compile the oracle with gcc (portable -O2, OpenMP, no fast-math); variant "fma": the build
+    with contracted multiply-adds."""
+    out = LIB if not variant else LIB_FMA
+    if out.exists() and not force and out.stat().st_mtime > max(SRC.stat().st_mtime, HDR.stat().st_mtime):
+        return out
+    tmp = out.with_suffix(".so.tmp")
+    cmd = ["gcc", "-O2", "-std=c11", "-D_GNU_SOURCE", "-fopenmp", "-fPIC", "-shared", *_VARIANT_FLAGS[variant],
            "-Wall", "-Wno-unknown-pragmas", "-o", str(tmp), str(SRC), "-lm"]
     subprocess.run(cmd, check=True)
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, out)
+    return out
 
 
 _lib = None
+_libs = {}
+_active = ""
+
+
+class use_variant:
+    """Context manager: the oracle calls inside it run on the given build ("" or "fma").  Tables
+    built or loaded by either build serve both (plain C structs and arrays)."""
+
+    def __init__(self, variant):
+        self.variant = variant
+
+    def __enter__(self):
+        global _active, _lib
+        self.prev = _active
+        _active = self.variant
+        _lib = None
+        return self
+
+    def __exit__(self, *exc):
+        global _active, _lib
+        _active = self.prev
+        _lib = None
+        return False
 
 
 class TableSpec(C.Structure):
@@ -91,13 +124,13 @@ DP = C.POINTER(C.c_double)
 class Leptons(C.Structure):
     _fields_ = [("n", C.c_int64), ("cap", C.c_int64), ("species", C.c_int),
                 ("x", DP * 3), ("p", DP * 3), ("s", DP * 3), ("near", C.POINTER(C.c_uint8)),
-                ("index", C.POINTER(C.c_int64)), ("tau", DP), ("tau_target", DP)]
+                ("index", C.POINTER(C.c_int64)), ("tau", DP), ("tau_target", DP), ("cond", DP)]
 
 
 class Photons(C.Structure):
     _fields_ = [("n", C.c_int64), ("cap", C.c_int64), ("n_prev", C.c_int64),
                 ("x", DP * 3), ("k", DP * 3), ("P", DP * 3), ("id", C.POINTER(C.c_uint64)),
-                ("near", C.POINTER(C.c_uint8))]
+                ("near", C.POINTER(C.c_uint8)), ("cond", DP)]
 
 
 class Counters(C.Structure):
@@ -111,9 +144,10 @@ class Counters(C.Structure):
 
 def lib():
     global _lib
+    if _lib is None and _active in _libs:
+        _lib = _libs[_active]
     if _lib is None:
-        build()
-        L = C.CDLL(str(LIB))
+        L = C.CDLL(str(build(variant=_active)))
         d, i, u32, u64 = C.c_double, C.c_int, C.c_uint32, C.c_uint64
         L.orc_philox4x32_10.argtypes = [C.POINTER(u32), C.POINTER(u32), C.POINTER(u32)]
         L.orc_u01_53.argtypes = [u32, u32]; L.orc_u01_53.restype = d
@@ -154,6 +188,7 @@ def lib():
         L.orc_stokes_to_P.argtypes = [DP, DP, DP, DP, DP]
         L.orc_P_to_stokes.argtypes = [DP, DP, DP, DP, DP]
         L.orc_basis.argtypes = [i, d, DP, DP, DP, DP, DP, DP]; L.orc_basis.restype = d
+        _libs[_active] = L
         _lib = L
     return _lib
 
@@ -368,6 +403,19 @@ class OracleTables:
 
 
 # ---------------------------------------------------------------- particle sets
+class SetArrays(tuple):
+    """The arrays of a particle set; ``cond`` holds, per particle, the conditioning of the collapse
+    axes behind its spin (leptons) or polarization (photons): how many times the rounding of the
+    spectrum's terms the direction can be off (0 or 1 where no collapse was made)."""
+    cond = None
+
+
+def _set_arrays(vals, cond):
+    t = SetArrays(vals)
+    t.cond = cond
+    return t
+
+
 class LeptonSet:
     """SoA lepton storage (float64) with a capacity; x components may be absent."""
 
@@ -380,6 +428,7 @@ class LeptonSet:
         self.index = None
         self.tau = np.zeros(cap) if tau else None           # optical depth and its target
         self.tau_target = np.zeros(cap) if tau else None
+        self.cond = np.zeros(cap)
 
     def set(self, x, p, s, index=None):
         n = p.shape[1]
@@ -406,12 +455,14 @@ class LeptonSet:
                    else C.POINTER(C.c_int64)())
         L.tau = self.tau.ctypes.data_as(DP) if self.tau is not None else DP()
         L.tau_target = self.tau_target.ctypes.data_as(DP) if self.tau_target is not None else DP()
+        L.cond = self.cond.ctypes.data_as(DP)
         return L
 
     def arrays(self):
         n = self.n
         x = np.stack([(a[:n] if a is not None else np.zeros(n)) for a in self.x])
-        return x, np.stack([a[:n] for a in self.p]), np.stack([a[:n] for a in self.s])
+        return _set_arrays((x, np.stack([a[:n] for a in self.p]), np.stack([a[:n] for a in self.s])),
+                           self.cond[:n].copy())
 
 
 class PhotonSet:
@@ -422,6 +473,7 @@ class PhotonSet:
         self.P = [np.zeros(cap) for _ in range(3)]
         self.id = np.zeros(cap, dtype=np.uint64)
         self.near = np.zeros(cap, dtype=np.uint8)
+        self.cond = np.zeros(cap)
 
     def struct(self):
         G = Photons()
@@ -432,6 +484,7 @@ class PhotonSet:
             G.P[i] = self.P[i].ctypes.data_as(DP)
         G.id = self.id.ctypes.data_as(C.POINTER(C.c_uint64))
         G.near = self.near.ctypes.data_as(C.POINTER(C.c_uint8))
+        G.cond = self.cond.ctypes.data_as(DP)
         return G
 
     def pull(self, G):
@@ -440,8 +493,8 @@ class PhotonSet:
     def arrays(self):
         n = self.n
         x = np.stack([(a[:n] if a is not None else np.zeros(n)) for a in self.x])
-        return (x, np.stack([a[:n] for a in self.k]), np.stack([a[:n] for a in self.P]),
-                self.id[:n].copy())
+        return _set_arrays((x, np.stack([a[:n] for a in self.k]), np.stack([a[:n] for a in self.P]),
+                            self.id[:n].copy()), self.cond[:n].copy())
 
 
 def make_params(dt, eps_r, step=0, t=0.0, seed=1, flags=F_ALL, a_e=ALPHA / (2 * np.pi),

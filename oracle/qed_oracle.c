@@ -952,6 +952,48 @@ static void no_emission_update(double s[3], const double bh[3], double Wbar, dou
     }
 }
 
+/* Conditioning of the collapse axes of the last orc_lepton_qed_one / orc_photon_qed_one call on
+   this thread (diagnostics for the comparisons; the step never reads them): the norm of the vector
+   of each component's sum of absolute terms -- the scale that rounding the terms works on -- over
+   the norm of the vector the axis is taken from. */
+static _Thread_local double g_cond_spin, g_cond_pol, g_cond_pe, g_cond_pp;
+
+static double norm3(double x, double y, double z) { return sqrt(x * x + y * y + z * z); }
+
+/* rounding scale of g (terms of nlc_g_pt in absolute value) */
+static double nlc_g_scale(const spec_pt *q, const double si[3])
+{
+    double u = q->lam / q->oml, c = q->IK + 2.0 * q->K23;
+    return norm3(c * fabs(si[0]), u * q->K13 + c * fabs(si[1]),
+                 c * fabs(si[2]) + q->lam * u * (q->IK + q->K23) * fabs(si[2]));
+}
+
+/* rounding scale of F = (F1, F2, F3) (terms of nlc_F_pt in absolute value) */
+static double nlc_F_scale(const spec_pt *q, const double a[3], const double b[3])
+{
+    double lam = q->lam, oml = q->oml, u = lam / oml;
+    double kap = 1.0 / oml + oml, kapt = fabs(1.0 / oml - oml);
+    double I = q->IK, K1 = q->K13, K2 = q->K23;
+    double A[3] = {fabs(a[0]), fabs(a[1]), fabs(a[2])}, B[3] = {fabs(b[0]), fabs(b[1]), fabs(b[2])};
+    double f1 = K1 * (u * A[0] + lam * B[0]) + 0.5 * lam * u * I * (B[0] * A[1] + B[1] * A[0])
+                + 0.5 * kapt * K2 * (B[0] * A[1] + B[1] * A[0]);
+    double f2 = 0.5 * kapt * K1 * (B[1] * A[2] + B[2] * A[1]) + (lam * I + kapt * K2) * A[2]
+                + (u * I + kapt * K2) * B[2] + 0.5 * lam * u * K1 * (B[2] * A[1] + B[1] * A[2]);
+    double f3 = K2 + (u * A[1] + lam * B[1]) * K1 + 0.5 * lam * u * I * (B[0] * A[0] + B[1] * A[1])
+                + 0.5 * kap * K2 * (B[0] * A[0] + B[1] * A[1] + B[2] * A[2]) + 0.5 * lam * u * K2 * B[2] * A[2];
+    return norm3(f1, f2, f3);
+}
+
+/* rounding scales of j_e and j_p (terms of nbw_j_pt in absolute value) */
+static void nbw_j_scale(const spec_pt *q, const double xi[3], double *se, double *sp)
+{
+    double lam = q->lam, oml = q->oml;
+    double rhot = fabs(oml / lam - lam / oml);
+    double I = q->IK, K1 = q->K13, K2 = q->K23;
+    *se = norm3(fabs(xi[0]) * K1 / lam, (1.0 / oml + fabs(xi[2]) / lam) * K1, fabs(xi[1]) * (I / oml + rhot * K2));
+    *sp = norm3(fabs(xi[0]) * K1 / oml, (1.0 / lam + fabs(xi[2]) / oml) * K1, fabs(xi[1]) * (I / lam + rhot * K2));
+}
+
 /* returns 1 if a photon was emitted (k_out, P_out, id_out valid), 0 otherwise;
    bit 1 of the return value flags a near tie of one of the decisions.  tau2 = {tau, tau*}
    of the lepton, updated in place, with ORC_F_TAU (may be NULL otherwise). */
@@ -1051,10 +1093,13 @@ emission:
     double g[3];
     nlc_g_pt(&qp, si, g);
     double sf[3] = {si[0], si[1], si[2]};
+    g_cond_spin = 1.0;
+    g_cond_pol = 1.0;
     if (fl & ORC_F_SPIN) {
         if (fl & ORC_F_MEAN) { for (int i = 0; i < 3; ++i) sf[i] = g[i] / w; }
         else {
             double gn = sqrt(dot3(g, g));
+            g_cond_spin = gn > 0.0 ? nlc_g_scale(&qp, si) / gn : HUGE_VAL;
             double S[3];
             if (gn > 0.0) for (int i = 0; i < 3; ++i) S[i] = g[i] / gn;
             else { S[0] = 0.0; S[1] = 1.0; S[2] = 0.0; }
@@ -1075,6 +1120,7 @@ emission:
             nlc_F_pt(&qp, si, sf, F);
             double Fn = sqrt(F[1] * F[1] + F[2] * F[2] + F[3] * F[3]);
             if (Fn > 0.0) {
+                g_cond_pol = nlc_F_scale(&qp, si, sf) * (1.0 + g_cond_spin) / Fn;
                 double thr4 = (F[0] - Fn) / (2.0 * F[0]);
                 if (near_tie(r4, thr4, prm->near_tol)) near = 1;
                 double sg = (r4 < thr4) ? -1.0 : 1.0;
@@ -1146,6 +1192,8 @@ int orc_photon_qed_one(const orc_tables *T, const orc_params *prm, uint64_t id,
     lam_from_nu(nu, &lam, &oml);
     for (int i = 0; i < 3; ++i) { pp[i] = lam * k[i]; pe[i] = oml * k[i]; }
     double e_c[3] = {0.0, 0.0, 0.0}, p_c[3] = {0.0, 0.0, 0.0};
+    g_cond_pe = 1.0;
+    g_cond_pp = 1.0;
     if (fl & ORC_F_PAIR_SPIN) {
         spec_pt qp = nbw_point(chi, lam, oml);
         double w0, je[3], jp[3];
@@ -1157,6 +1205,10 @@ int orc_photon_qed_one(const orc_tables *T, const orc_params *prm, uint64_t id,
             uniforms2(prm, id, 3, &r3, &r3b);
             double Se[3], Sp[3];
             double jen = sqrt(dot3(je, je)), jpn = sqrt(dot3(jp, jp));
+            double sce, scp;
+            nbw_j_scale(&qp, xi, &sce, &scp);
+            g_cond_pe = jen > 0.0 ? sce / jen : HUGE_VAL;
+            g_cond_pp = jpn > 0.0 ? scp / jpn : HUGE_VAL;
             for (int i = 0; i < 3; ++i) {
                 Se[i] = jen > 0.0 ? je[i] / jen : (i == 1 ? 1.0 : 0.0);
                 Sp[i] = jpn > 0.0 ? jp[i] / jpn : (i == 1 ? 1.0 : 0.0);
@@ -1202,7 +1254,8 @@ static void add_counters(orc_counters *d, const orc_counters *s)
 
 /* append the photons of one pass over the leptons in lepton index order */
 static void append_photons(const orc_params *prm, const orc_leptons *L, orc_photons *G, int64_t n,
-                           const char *emitted, const double *kb, const uint64_t *ib, orc_counters *tot)
+                           const char *emitted, const double *kb, const uint64_t *ib, const double *cb,
+                           orc_counters *tot)
 {
     for (int64_t j = 0; j < n; ++j) {
         if (!emitted[j]) continue;
@@ -1213,10 +1266,12 @@ static void append_photons(const orc_params *prm, const orc_leptons *L, orc_phot
         if (k0 < prm->k_retire) {
             G->id[m] = 0;
             for (int i = 0; i < 3; ++i) { if (G->x[i]) G->x[i][m] = 0.0; G->k[i][m] = 0.0; G->P[i][m] = 0.0; }
+            if (G->cond) G->cond[m] = 0.0;
             tot->n_retired++;
             continue;
         }
         G->id[m] = ib[j];
+        if (G->cond) G->cond[m] = cb[j];
         for (int i = 0; i < 3; ++i) {
             if (G->x[i]) G->x[i][m] = getx(L->x, i, j);
             G->k[i][m] = kk[i];
@@ -1266,6 +1321,7 @@ static int lepton_step_subcycled(const orc_tables *T, const orc_params *prm, con
     char *emitted = (char *)calloc(n > 0 ? n : 1, 1);
     double *kb = (double *)malloc(sizeof(double) * 6 * (n > 0 ? n : 1));
     uint64_t *ib = (uint64_t *)malloc(sizeof(uint64_t) * (n > 0 ? n : 1));
+    double *cb = (double *)malloc(sizeof(double) * (n > 0 ? n : 1));
     orc_counters tot = {0};
 #ifdef _OPENMP
     if (nthreads > 0) omp_set_num_threads(nthreads);
@@ -1324,6 +1380,10 @@ static int lepton_step_subcycled(const orc_tables *T, const orc_params *prm, con
                 int res = orc_lepton_qed_one(T, &sub, L->species, idx, E, B, x, p, s, kb + 6 * j, kb + 6 * j + 3,
                                              ib + j, NULL, &loc);
                 emitted[j] = (char)(res & 1);
+                if (res & 1) {
+                    cb[j] = g_cond_pol;
+                    if (L->cond && g_cond_spin > L->cond[j]) L->cond[j] = g_cond_spin;
+                }
                 if (res & 2) near[j] = 1;
                 for (int i = 0; i < 3; ++i) {
                     L->p[i][j] = p[i];
@@ -1333,14 +1393,14 @@ static int lepton_step_subcycled(const orc_tables *T, const orc_params *prm, con
 #pragma omp critical
             add_counters(&tot, &loc);
         }
-        append_photons(prm, L, G, n, emitted, kb, ib, &tot);
+        append_photons(prm, L, G, n, emitted, kb, ib, cb, &tot);
     }
     for (int64_t j = 0; j < n; ++j) {
         if (near[j]) tot.n_near_threshold++;
         if (L->near) L->near[j] = (uint8_t)near[j];
     }
     add_counters(ctr, &tot);
-    free(msub); free(near); free(emitted); free(kb); free(ib);
+    free(msub); free(near); free(emitted); free(kb); free(ib); free(cb);
     return 0;
 }
 
@@ -1353,6 +1413,7 @@ int orc_lepton_step(const orc_tables *T, const orc_params *prm, const orc_fields
     char *emitted = (char *)calloc(n > 0 ? n : 1, 1);
     double *kb = (double *)malloc(sizeof(double) * 6 * (n > 0 ? n : 1));
     uint64_t *ib = (uint64_t *)malloc(sizeof(uint64_t) * (n > 0 ? n : 1));
+    double *cb = (double *)malloc(sizeof(double) * (n > 0 ? n : 1));
     orc_counters tot = {0};
 #ifdef _OPENMP
     if (nthreads > 0) omp_set_num_threads(nthreads);
@@ -1379,6 +1440,10 @@ int orc_lepton_step(const orc_tables *T, const orc_params *prm, const orc_fields
                                        ib + j, mode_b ? tau2 : NULL, &loc);
             if (mode_b) { L->tau[j] = tau2[0]; L->tau_target[j] = tau2[1]; }
             emitted[j] = (char)(r & 1);
+            if (r & 1) {
+                cb[j] = g_cond_pol;
+                if (L->cond && g_cond_spin > L->cond[j]) L->cond[j] = g_cond_spin;
+            }
             if (r & 2) loc.n_near_threshold++;
             if (L->near) L->near[j] = (uint8_t)((r >> 1) & 1);
             for (int i = 0; i < 3; ++i) {
@@ -1390,9 +1455,9 @@ int orc_lepton_step(const orc_tables *T, const orc_params *prm, const orc_fields
 #pragma omp critical
         add_counters(&tot, &loc);
     }
-    append_photons(prm, L, G, n, emitted, kb, ib, &tot);
+    append_photons(prm, L, G, n, emitted, kb, ib, cb, &tot);
     add_counters(ctr, &tot);
-    free(emitted); free(kb); free(ib);
+    free(emitted); free(kb); free(ib); free(cb);
     return 0;
 }
 
@@ -1401,7 +1466,7 @@ int orc_photon_step(const orc_tables *T, const orc_params *prm, const orc_fields
 {
     int64_t n = G->n_prev;
     char *pair = (char *)calloc(n > 0 ? n : 1, 1);
-    double *ob = (double *)malloc(sizeof(double) * 12 * (n > 0 ? n : 1));
+    double *ob = (double *)malloc(sizeof(double) * 14 * (n > 0 ? n : 1));
     orc_counters tot = {0};
 #ifdef _OPENMP
     if (nthreads > 0) omp_set_num_threads(nthreads);
@@ -1426,8 +1491,9 @@ int orc_photon_step(const orc_tables *T, const orc_params *prm, const orc_fields
             double E[3], B[3];
             orc_fields_eval(f, x, prm->t + prm->dt, E, B);
             double P[3] = {G->P[0][j], G->P[1][j], G->P[2][j]};
-            double *o = ob + 12 * j;
+            double *o = ob + 14 * j;
             int r = orc_photon_qed_one(T, prm, G->id[j], E, B, k, P, o, o + 3, o + 6, o + 9, &loc);
+            if (r & 1) { o[12] = g_cond_pe; o[13] = g_cond_pp; }
             if (r & 2) loc.n_near_threshold++;
             if (G->near) G->near[j] = (uint8_t)((r >> 1) & 1);
             if (r & 1) { pair[j] = 1; G->id[j] = 0; }
@@ -1438,9 +1504,11 @@ int orc_photon_step(const orc_tables *T, const orc_params *prm, const orc_fields
     }
     for (int64_t j = 0; j < n; ++j) {
         if (!pair[j]) continue;
-        const double *o = ob + 12 * j;
+        const double *o = ob + 14 * j;
         if (Le->n >= Le->cap || Lp->n >= Lp->cap) { tot.n_capacity_overflow++; continue; }
         int64_t me = Le->n++, mp = Lp->n++;
+        if (Le->cond) Le->cond[me] = o[12];
+        if (Lp->cond) Lp->cond[mp] = o[13];
         if (Le->index) Le->index[me] = me;
         if (Lp->index) Lp->index[mp] = mp;
         /* new leptons start with no optical depth and no target (drawn at their first step) */
@@ -1469,6 +1537,7 @@ void orc_compact(orc_photons *G)
         if (G->id[j] == 0) continue;
         if (m != j) {
             G->id[m] = G->id[j];
+            if (G->cond) G->cond[m] = G->cond[j];
             for (int i = 0; i < 3; ++i) {
                 if (G->x[i]) G->x[i][m] = G->x[i][j];
                 G->k[i][m] = G->k[i][j];

@@ -124,6 +124,12 @@ typedef struct {
     uint8_t *near;          /* optional: set to 1 when a decision of this particle was a near tie */
     int64_t *index;         /* optional: index that names particle j in its full set (default j) */
     double  *tau, *tau_target;  /* optical depth and its target (ORC_F_TAU only); target 0 = not drawn */
+    double  *cond;          /* optional diagnostic, no effect on the step: the conditioning of the
+                               collapse axes behind the particle's spin, i.e. how many times the
+                               unit roundoff the axis direction can be off: the norm of the sums of
+                               the absolute terms of g over |g| (NLC appendix: s_f = +-g/|g|), the
+                               largest over its emissions so far; the same of j over |j| for a
+                               lepton made by a pair (NBW appendix); 0 with no collapse */
 } orc_leptons;
 
 typedef struct {
@@ -131,6 +137,10 @@ typedef struct {
     double   *x[3], *k[3], *P[3];
     uint64_t *id;           /* 0 = dead slot */
     uint8_t  *near;         /* optional, as for leptons */
+    double   *cond;         /* optional diagnostic, as for leptons: of the Stokes collapse
+                               xi = +-F/|F| at the photon's birth, the norm of the sums of the
+                               absolute terms of F over |F|, times 1 + the parent's spin-axis
+                               conditioning (F is taken at the collapsed s_f); 1 without it */
 } orc_photons;
 
 typedef struct {

@@ -39,10 +39,13 @@ def _sample(n):
 
 
 def _own_photons(arrays, idx):
+    """the live photons of the sampled electrons (with the oracle's conditioning when present)"""
     x, k, P, ids = arrays
     sp, par = photon_parent(ids)
     mine = (ids != 0) & (sp == 0) & np.isin(par, idx)
-    return x[:, mine], k[:, mine], P[:, mine], ids[mine]
+    out = oracle.SetArrays((x[:, mine], k[:, mine], P[:, mine], ids[mine]))
+    out.cond = arrays.cond[mine] if getattr(arrays, "cond", None) is not None else None
+    return out
 
 
 def test_head_on_full_size_graph_fp64(q, otables):
@@ -65,7 +68,7 @@ def test_head_on_full_size_graph_fp64(q, otables):
     x, p, s = sim.e.arrays()
     t = 1e-12 * steps / 250
     compare_leptons((x[:, idx], p[:, idx], s[:, idx]), tuple(a[:, :256] for a in ref["E"].arrays()), ex, t, t,
-                    rtol_x=t, what="sampled electrons", events=ref["ctr"]["n_emit"])
+                    rtol_x=t, what="sampled electrons", cond=ref["E"].cond[:256])
     compare_photons(_own_photons(sim.g.arrays(), idx), _own_photons(ref["G"].arrays(), idx),
                     {(0, int(i)) for i in idx[ex]}, t, t, what="their photons")
 
@@ -103,6 +106,6 @@ def test_head_on_full_size_peak_fp32(q, otables):
     ex = ref["near_e"][:256]
     xg, pg, sg = sim.e.arrays()
     compare_leptons((xg[:, idx], pg[:, idx], sg[:, idx]), tuple(a[:, :256] for a in ref["E"].arrays()), ex, 1e-5, 1e-5,
-                    what="sampled electrons fp32", outlier_rate=1e-2)
+                    what="sampled electrons fp32", cond=ref["E"].cond[:256])
     compare_photons(_own_photons(sim.g.arrays(), idx), _own_photons(ref["G"].arrays(), idx),
-                    {(0, int(i)) for i in idx[ex]}, 1e-5, 5e-5, what="their photons fp32", outlier_rate=1e-2)
+                    {(0, int(i)) for i in idx[ex]}, 1e-5, 1e-5, what="their photons fp32")

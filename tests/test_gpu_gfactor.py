@@ -159,7 +159,7 @@ def test_gchi_head_on_merged_fp64(q, gtab64, otables):
     assert c["n_emit"] == ref["ctr"]["n_emit"] > 5_000 and c["n_pair"] == ref["ctr"]["n_pair"]
     t = tol_k(steps)
     compare_leptons(sim.e.arrays(), ref["E"].arrays(), np.zeros(ref["E"].n, bool), t, t, rtol_x=t,
-                    what="g(chi) electrons", events=c["n_emit"])
+                    what="g(chi) electrons")
     compare_leptons(sim.p.arrays(), ref["P"].arrays(), np.zeros(ref["P"].n, bool), t, t, rtol_x=t,
                     what="g(chi) positrons")
     compare_photons(sim.g.arrays(), ref["G"].arrays(), set(), t, t, what="g(chi) photons")

@@ -85,8 +85,7 @@ def test_subcycle_c1_run_fp64(q, gtab64, otables):
     assert c["n_lepton_steps"] == w.n * steps
     rounds = _rounds(sim.g.arrays()[3])
     assert len(np.unique(rounds)) == 16          # every lepton takes 16 sub-steps here
-    compare_leptons(sim.e.arrays(), ref["E"].arrays(), ex, tol_k(steps), tol_k(steps), what="sub-cycled c1 leptons",
-                    events=c["n_emit"])
+    compare_leptons(sim.e.arrays(), ref["E"].arrays(), ex, tol_k(steps), tol_k(steps), what="sub-cycled c1 leptons")
     compare_photons(sim.g.arrays(), ref["G"].arrays(), set(), tol_k(steps), tol_k(steps),
                     what="sub-cycled c1 photons")
 
@@ -186,7 +185,7 @@ def test_subcycle_head_on_fp64(q, gtab64, otables):
     assert (rounds > 0).any()
     t = 1e-9
     compare_leptons(sim.e.arrays(), ref["E"].arrays(), np.zeros(ref["E"].n, bool), t, t, rtol_x=t,
-                    what="sub-cycled electrons", events=c["n_emit"])
+                    what="sub-cycled electrons")
     compare_leptons(sim.p.arrays(), ref["P"].arrays(), np.zeros(ref["P"].n, bool), t, t, rtol_x=t,
                     what="sub-cycled positrons")
     compare_photons(sim.g.arrays(), ref["G"].arrays(), set(), t, t, what="sub-cycled photons")

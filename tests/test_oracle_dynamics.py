@@ -415,3 +415,21 @@ def test_rotating_field_classical_orbit(otables):
         errs.append(worst)
         assert worst < 1.05 * a0 * dt                  # left-point rule: a0 dt (1 + O(dt)) at cos t = -1
     assert 1.8 < errs[0] / errs[1] < 2.2
+
+
+def test_multiply_add_build_is_the_same_algorithm(otables):
+    """The oracle's second build (contracted multiply-adds) makes the same decisions as the plain
+    build and differs from it only at the rounding level on a short run; the conditioning it
+    records for collapses is at least 1 (a sum of absolute terms is never below the norm)."""
+    import synth
+    from parity import oracle_run, sensitivity_run
+    w = synth.subsample(synth.c1(n=64), np.arange(64))
+    ref = oracle_run(otables, w, 20, oracle.F_ALL & ~oracle.F_PAIR, cap_g=64 * 20, k_retire=0.0)
+    alt = sensitivity_run(otables, w, 20, oracle.F_ALL & ~oracle.F_PAIR, ref, cap_g=64 * 20, k_retire=0.0)
+    _, p0, s0 = ref["E"].arrays()
+    _, p1, s1 = alt["E"].arrays()
+    d = np.linalg.norm(p0 - p1, axis=0) / np.linalg.norm(p0, axis=0)
+    assert 0 < d.max() < 1e-12 and np.abs(s0 - s1).max() < 1e-12
+    c = ref["E"].cond[:64]
+    assert (c >= 1.0).all() and ref["ctr"]["n_emit"] > 500
+    assert (ref["G"].cond[:ref["G"].n] >= 1.0).all()
