@@ -192,7 +192,15 @@ typedef struct {                /* device-resident, accumulated */
                        n_capacity_overflow, n_retired,
                        n_lepton_steps,   /* leptons stepped by qed_emit */
                        n_photon_steps,   /* live photons stepped by qed_pair */
-                       n_photon_qed;     /* of those, photons with chi_gamma >= chi_g_min (full NBW step) */
+                       n_photon_qed,     /* of those, photons with chi_gamma >= chi_g_min (full NBW step) */
+                       n_nonfinite;      /* particle-steps skipped for a NaN or infinity: a lepton whose
+                                            x, p or s is not finite keeps its stored state (no push, no
+                                            QED); one whose fields at t are not finite is not pushed;
+                                            one whose fields at t + dt are not finite is pushed but gets
+                                            no QED part; a photon whose k or x is not finite, or whose P
+                                            is not finite when its chi_gamma >= chi_g_min, becomes a dead
+                                            slot (so does one with k = 0); one whose fields are not finite gets no QED part.  The
+                                            step writes no NaN or infinity of its own */
 } qed_counters;
 
 typedef struct {
@@ -231,7 +239,8 @@ size_t qed_workspace_size(int64_t max_particles);
 
 /* Lorentz (Boris) push with fields at (x, t), T-BMT rotation (if QED_TBMT; with QED_G_CHI the
    anomalous moment from the tables' g-factor table), then x += v dt, for leptons [0, *d_count).
-   In place. */
+   In place.  A lepton whose state or fields are not finite is left as stored (not counted: this
+   call takes no counters). */
 qed_status qed_push_spin(const qed_leptons *leptons, const qed_fields *fields,
                          const qed_step_params *params, qed_tables tables, qed_stream stream);
 

@@ -136,7 +136,8 @@ class Photons(C.Structure):
 class Counters(C.Structure):
     _fields_ = [(n, C.c_int64) for n in ("n_emit", "n_pair", "n_prob_clamped", "n_chi_clamped",
                                          "n_norm_clamped", "n_capacity_overflow", "n_retired",
-                                         "n_near_threshold", "n_lepton_steps", "n_photon_steps")]
+                                         "n_near_threshold", "n_lepton_steps", "n_photon_steps",
+                                         "n_nonfinite")]
 
     def as_dict(self):
         return {n: int(getattr(self, n)) for n, _ in self._fields_}

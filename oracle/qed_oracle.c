@@ -813,6 +813,10 @@ void orc_fields_eval(const orc_fields *f, const double x[3], double t, double E[
 /* Vector helpers                                                          */
 /* ====================================================================== */
 static double dot3(const double a[3], const double b[3]) { return a[0] * b[0] + a[1] * b[1] + a[2] * b[2]; }
+
+/* Inputs that are not finite (NaN or infinity) are not stepped: a lepton keeps its state, a
+   photon is removed, and each is counted; a step in a non-finite field is cut short. */
+static int finite3(const double v[3]) { return isfinite(v[0]) && isfinite(v[1]) && isfinite(v[2]); }
 static void cross3(const double a[3], const double b[3], double c[3])
 {
     c[0] = a[1] * b[2] - a[2] * b[1];
@@ -1152,6 +1156,7 @@ int orc_photon_qed_one(const orc_tables *T, const orc_params *prm, uint64_t id,
     double chi = orc_basis(0, prm->eps_r, E, B, k, eh, bh, kh);
     if (!(chi >= prm->chi_g_min)) return 0;
     if (chi > prm->chi_g_max) { chi = prm->chi_g_max; ctr->n_chi_clamped++; }
+    if (!finite3(P)) return 4;                 /* a photon whose polarization is not finite is removed */
     double k0 = sqrt(dot3(k, k));
     double Cg = ORC_ALPHA / (sqrt(3.0) * ORC_PI * prm->eps_r * k0);
     double lnchi = log(chi);
@@ -1250,6 +1255,7 @@ static void add_counters(orc_counters *d, const orc_counters *s)
     d->n_capacity_overflow += s->n_capacity_overflow; d->n_retired += s->n_retired;
     d->n_near_threshold += s->n_near_threshold;
     d->n_lepton_steps += s->n_lepton_steps; d->n_photon_steps += s->n_photon_steps;
+    d->n_nonfinite += s->n_nonfinite;
 }
 
 /* append the photons of one pass over the leptons in lepton index order */
@@ -1337,18 +1343,27 @@ static int lepton_step_subcycled(const orc_tables *T, const orc_params *prm, con
             double p[3] = {L->p[0][j], L->p[1][j], L->p[2][j]};
             double s[3] = {L->s[0][j], L->s[1][j], L->s[2][j]};
             double E[3], B[3];
+            msub[j] = 0;                                  /* 0: no sub-step in any round */
+            if (!(finite3(x) && finite3(p) && finite3(s))) { loc.n_nonfinite++; continue; }
             if (prm->flags & ORC_F_PUSH) {
                 orc_fields_eval(f, x, prm->t, E, B);
+                if (!(finite3(E) && finite3(B))) { loc.n_nonfinite++; continue; }
                 orc_push_one(q, prm->a_e, E, B, prm->dt, prm->flags, T, prm->eps_r, p, s, x);
             }
             int m = 1;
             if (prm->flags & ORC_F_EMIT) {
                 orc_fields_eval(f, x, prm->t + prm->dt, E, B);
+                if (!(finite3(E) && finite3(B))) {
+                    loc.n_nonfinite++;
+                    m = 0;
+                    goto store;
+                }
                 int nr = 0;
                 double P = lepton_wdt(T, prm, L->species, E, B, p, s, &nr);
                 while (m < ORC_SUB_ROUNDS && P > ORC_SUB_WDT * m) m *= 2;
                 near[j] = (char)nr;
             }
+        store:
             msub[j] = m;
             for (int i = 0; i < 3; ++i) {
                 if (L->x[i]) L->x[i][j] = x[i];
@@ -1367,7 +1382,7 @@ static int lepton_step_subcycled(const orc_tables *T, const orc_params *prm, con
 #pragma omp for schedule(static)
             for (int64_t j = 0; j < n; ++j) {
                 emitted[j] = 0;
-                if (r % (ORC_SUB_ROUNDS / msub[j]) != 0) continue;
+                if (msub[j] == 0 || r % (ORC_SUB_ROUNDS / msub[j]) != 0) continue;
                 orc_params sub = *prm;
                 sub.dt = prm->dt / msub[j];
                 sub.sub_round = r;
@@ -1428,11 +1443,27 @@ int orc_lepton_step(const orc_tables *T, const orc_params *prm, const orc_fields
             double p[3] = {L->p[0][j], L->p[1][j], L->p[2][j]};
             double s[3] = {L->s[0][j], L->s[1][j], L->s[2][j]};
             double E[3], B[3];
+            if (L->near) L->near[j] = 0;
+            if (!(finite3(x) && finite3(p) && finite3(s))) { loc.n_nonfinite++; continue; }
             if (prm->flags & ORC_F_PUSH) {
                 orc_fields_eval(f, x, prm->t, E, B);
+                if (!(finite3(E) && finite3(B))) { loc.n_nonfinite++; continue; }
                 orc_push_one(q, prm->a_e, E, B, prm->dt, prm->flags, T, prm->eps_r, p, s, x);
             }
-            orc_fields_eval(f, x, prm->t + prm->dt, E, B);
+            if (prm->flags & ORC_F_EMIT) {
+                orc_fields_eval(f, x, prm->t + prm->dt, E, B);
+                if (!(finite3(E) && finite3(B))) {
+                    loc.n_nonfinite++;
+                    for (int i = 0; i < 3; ++i) {
+                        if (L->x[i]) L->x[i][j] = x[i];
+                        L->p[i][j] = p[i];
+                        L->s[i][j] = s[i];
+                    }
+                    continue;
+                }
+            } else {
+                orc_fields_eval(f, x, prm->t + prm->dt, E, B);
+            }
             int64_t idx = L->index ? L->index[j] : j;
             double tau2[2] = {L->tau ? L->tau[j] : 0.0, L->tau_target ? L->tau_target[j] : 0.0};
             int mode_b = (prm->flags & ORC_F_TAU) && L->tau && L->tau_target;
@@ -1479,6 +1510,12 @@ int orc_photon_step(const orc_tables *T, const orc_params *prm, const orc_fields
             if (G->id[j] == 0) continue;
             double k[3] = {G->k[0][j], G->k[1][j], G->k[2][j]};
             double k0 = sqrt(dot3(k, k));
+            double x0[3] = {getx(G->x, 0, j), getx(G->x, 1, j), getx(G->x, 2, j)};
+            if (!(finite3(k) && finite3(x0) && (k[0] != 0.0 || k[1] != 0.0 || k[2] != 0.0))) {
+                G->id[j] = 0;
+                loc.n_nonfinite++;
+                continue;
+            }
             double x[3];
             for (int i = 0; i < 3; ++i) {
                 x[i] = getx(G->x, i, j) + k[i] / k0 * prm->dt;
@@ -1490,9 +1527,11 @@ int orc_photon_step(const orc_tables *T, const orc_params *prm, const orc_fields
             if (k0 < prm->k_retire || behind) { G->id[j] = 0; loc.n_retired++; continue; }
             double E[3], B[3];
             orc_fields_eval(f, x, prm->t + prm->dt, E, B);
+            if ((prm->flags & ORC_F_PAIR) && !(finite3(E) && finite3(B))) { loc.n_nonfinite++; continue; }
             double P[3] = {G->P[0][j], G->P[1][j], G->P[2][j]};
             double *o = ob + 14 * j;
             int r = orc_photon_qed_one(T, prm, G->id[j], E, B, k, P, o, o + 3, o + 6, o + 9, &loc);
+            if (r & 4) { G->id[j] = 0; loc.n_nonfinite++; continue; }
             if (r & 1) { o[12] = g_cond_pe; o[13] = g_cond_pp; }
             if (r & 2) loc.n_near_threshold++;
             if (G->near) G->near[j] = (uint8_t)((r >> 1) & 1);

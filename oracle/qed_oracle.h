@@ -145,7 +145,8 @@ typedef struct {
 
 typedef struct {
     int64_t n_emit, n_pair, n_prob_clamped, n_chi_clamped, n_norm_clamped,
-            n_capacity_overflow, n_retired, n_near_threshold, n_lepton_steps, n_photon_steps;
+            n_capacity_overflow, n_retired, n_near_threshold, n_lepton_steps, n_photon_steps,
+            n_nonfinite;    /* particle-steps not taken for a NaN or infinity in the inputs (see the steps) */
 } orc_counters;
 
 /* Lorentz (Boris) push + T-BMT rotation + position advance for one lepton.  With ORC_F_GCHI the

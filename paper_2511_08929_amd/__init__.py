@@ -82,7 +82,8 @@ class StepParams(C.Structure):
 
 
 COUNTER_NAMES = ("n_emit", "n_pair", "n_prob_clamped", "n_chi_clamped", "n_norm_clamped",
-                 "n_capacity_overflow", "n_retired", "n_lepton_steps", "n_photon_steps", "n_photon_qed")
+                 "n_capacity_overflow", "n_retired", "n_lepton_steps", "n_photon_steps", "n_photon_qed",
+                 "n_nonfinite")
 
 
 class Instance(C.Structure):

@@ -50,7 +50,7 @@ __device__ __forceinline__ StepDev localize(StepDev S)
     return S;
 }
 
-enum { C_EMIT = 0, C_PAIR, C_PROB, C_CHI, C_NORM, C_OVER, C_RETIRED, C_LSTEP, C_GSTEP, C_GQED, kNCtr };
+enum { C_EMIT = 0, C_PAIR, C_PROB, C_CHI, C_NORM, C_OVER, C_RETIRED, C_LSTEP, C_GSTEP, C_GQED, C_NONFIN, kNCtr };
 
 struct WS {
     uint64_t *mask;      // [2][nchunks]: transition, branch (up / plus)
@@ -189,6 +189,14 @@ __device__ __forceinline__ void wave_add(unsigned long long *ctr, int slot, unsi
     if ((threadIdx.x & 63) == 0 && v) atomicAdd(ctr + slot, (unsigned long long)v);
 }
 
+// Non-finite inputs (NaN or infinity in a particle's state or in the fields it sees) are not
+// stepped: such a lepton keeps its stored state, such a photon becomes a dead slot, and each is
+// counted in n_nonfinite; the step writes no NaN of its own.
+template <class R> __device__ __forceinline__ bool finite3(V3<R> v)
+{
+    return __builtin_isfinite(v.x) && __builtin_isfinite(v.y) && __builtin_isfinite(v.z);
+}
+
 template <class R> __device__ __forceinline__ bool zero_field(V3<R> E, V3<R> B)
 {
     return E.x == (R)0 && E.y == (R)0 && E.z == (R)0 && B.x == (R)0 && B.y == (R)0 && B.z == (R)0;
@@ -279,6 +287,15 @@ __device__ __forceinline__ PDecide<R> photon_decide(const StepDev &S, const Tabl
     return d;
 }
 
+// chi_gamma >= chi_min (the test photon_decide makes first), for a photon whose polarization is
+// not used because it is not finite
+template <class R> __device__ __forceinline__ bool photon_active(const StepDev &S, V3<R> k, double k0, V3<R> E, V3<R> B)
+{
+    if (zero_field(E, B)) return false;
+    Basis<R> bs;
+    return basis_chi(0, S.eps_r, k, k0, E, B, bs) >= S.chi_g_min;
+}
+
 // Photons whose FP32 bound eps_r k0 (|E| + |B|) >= |F_perp| eps_r = chi cannot reach chi_min skip
 // the QED part.  The bound carries a relative margin far above FP32 rounding, so every photon
 // with chi >= chi_min (FP64) is a candidate.
@@ -292,7 +309,7 @@ template <class R> __device__ __forceinline__ bool photon_candidate(const StepDe
 // ------------------------------------------------------------------ per-particle work
 // The bodies below are shared by the per-species entry points and the merged step.
 
-struct LCount { unsigned prob = 0, chi = 0, norm = 0, step = 0, trans = 0; };
+struct LCount { unsigned prob = 0, chi = 0, norm = 0, step = 0, trans = 0, nonfin = 0; };
 
 // Main pass, one lepton: Boris push and T-BMT rotation with the fields at t, the fields at
 // t + dt, chi and the decision (NLC section); a non-emitter gets the no-transition spin update
@@ -320,14 +337,29 @@ __device__ __forceinline__ void lepton_item(const LepDev<R> &L, const FieldDev &
     } else {
         ++c.step;
     }
+    if (!(finite3(x) && finite3(p) && finite3(s))) {      // left as stored
+        ++c.nonfin;
+        return;
+    }
     V3<R> E, B;
     if (S.flags & F_PUSH) {
         eval_fields<R, FLD>(F, (double)x.x, (double)x.y, S.t, E, B);
+        if (!(finite3(E) && finite3(B))) {                // no push, no QED
+            ++c.nonfin;
+            return;
+        }
         x = x + push<R>(q, (R)S.a_e, E, B, (R)S.dt, (S.flags & F_TBMT) != 0, p, s, gfac_src<R, FLD>(T, S.flags),
                         (R)S.eps_r);
     }
     if (S.flags & F_EMIT) {
         eval_fields<R, FLD>(F, (double)x.x, (double)x.y, S.t + S.dt, E, B);
+        if (!(finite3(E) && finite3(B))) {                // the push stands, no QED
+            ++c.nonfin;
+            stx(L.x, i, x);
+            st3(L.p, i, p);
+            st3(L.s, i, s);
+            return;
+        }
         LDecide<R> d = lepton_decide<R>(S, T, lds, L.species, i, p, s, E, B);
         if constexpr ((DEC & 4) != 0) {
             if (d.active) {
@@ -535,7 +567,7 @@ __device__ __forceinline__ void emit_item(const LepDev<R> &L, const PhoDev<R> &G
     }
 }
 
-struct GCount { unsigned chi = 0, norm = 0, ret = 0, prob = 0, step = 0, qed = 0, trans = 0; };
+struct GCount { unsigned chi = 0, norm = 0, ret = 0, prob = 0, step = 0, qed = 0, trans = 0, nonfin = 0; };
 
 // Photon streaming pass, one tile of at most kPhoTile slots starting at `tile` (a multiple of 64).
 // Phase 1 (every slot): advance x, retire, evaluate the fields, queue the chi candidates in LDS.
@@ -591,7 +623,11 @@ __device__ __forceinline__ void photon_tile(const PhoDev<R> &G, const FieldDev &
         const int64_t i = base + lane;
         bool cand = false;
         R xq = (R)0, yq = (R)0;
-        if (idv[u] != 0) {
+        if (idv[u] != 0 && !(finite3(kv[u]) && finite3(xv[u]) &&
+                             (kv[u].x != (R)0 || kv[u].y != (R)0 || kv[u].z != (R)0))) {
+            G.id[i] = 0;                                  // a non-finite (or k = 0) photon is removed
+            ++c.nonfin;
+        } else if (idv[u] != 0) {
             ++c.step;
             const V3<R> k = kv[u];
             const R k0r = sqrt_r(dot(k, k));
@@ -609,7 +645,8 @@ __device__ __forceinline__ void photon_tile(const PhoDev<R> &G, const FieldDev &
             } else if (qed) {
                 V3<R> E, Bf;
                 eval_fields<R, FLD>(F, (double)x.x, (double)x.y, S.t + S.dt, E, Bf);
-                cand = photon_candidate<R>(S, k0r, E, Bf);
+                if (finite3(E) && finite3(Bf)) cand = photon_candidate<R>(S, k0r, E, Bf);
+                else ++c.nonfin;                          // no QED in a non-finite field
                 xq = x.x;
                 if (FLD == kFldGeneral) yq = x.y;
             }
@@ -640,6 +677,13 @@ __device__ __forceinline__ void photon_tile(const PhoDev<R> &G, const FieldDev &
         const double k0 = (double)sqrt_r(dot(k, k));
         V3<R> E, Bf;
         eval_fields<R, FLD>(F, (double)Q.x[j], FLD == kFldGeneral ? (double)Q.y[j] : 0.0, S.t + S.dt, E, Bf);
+        if (!finite3(P)) {                                // a non-finite polarization: removed
+            if (photon_active<R>(S, k, k0, E, Bf)) {
+                G.id[i] = 0;
+                ++c.nonfin;
+            }
+            continue;
+        }
         const PDecide<R> d = photon_decide<R>(S, T, lds, id, k, k0, P, E, Bf);
         if (!d.active) continue;
         ++c.qed;

@@ -122,7 +122,8 @@ k_plan_main(const InstDev<R> *inst, PlanDev P, TablesDev T, int b_first)
         const int64_t start = (int64_t)(b - sg.b0) * B, end = start + B < n ? start + B : n;
         LCount c;
         lepton_range<R, DEC, FLD>(L, F, S, T, lds, start, end, mask, sg.nchunks, c);
-        v[C_PROB] = c.prob; v[C_CHI] = c.chi; v[C_NORM] = c.norm; v[C_LSTEP] = c.step; v[kNCtr] = c.trans;
+        v[C_PROB] = c.prob; v[C_CHI] = c.chi; v[C_NORM] = c.norm; v[C_LSTEP] = c.step; v[C_NONFIN] = c.nonfin;
+        v[kNCtr] = c.trans;
     } else {
         const PhoDev<R> G = Ip->G;
         stage_rates<R>(T, 1, lds);
@@ -134,7 +135,7 @@ k_plan_main(const InstDev<R> *inst, PlanDev P, TablesDev T, int b_first)
             photon_tile<R, FLD>(G, F, S, T, lds, Q, tile, tile + kPhoTile < end ? tile + kPhoTile : end, mask, sg.nchunks,
                                  c);
         v[C_PROB] = c.prob; v[C_CHI] = c.chi; v[C_NORM] = c.norm; v[C_RETIRED] = c.ret; v[C_GSTEP] = c.step;
-        v[C_GQED] = c.qed; v[kNCtr] = c.trans;
+        v[C_GQED] = c.qed; v[C_NONFIN] = c.nonfin; v[kNCtr] = c.trans;
     }
     block_sum(v, tot);
     if (threadIdx.x < kNCtr) P.bctr[(int64_t)b * kNCtr + threadIdx.x] = tot[threadIdx.x];

@@ -30,7 +30,9 @@ __global__ void __launch_bounds__(kBlock) k_push(LepDev<R> L, FieldDev F, StepDe
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
         V3<R> x = ldx(L.x, i), p = ld3(L.p, i), s = ld3(L.s, i);
         V3<R> E, B;
+        if (!(finite3(x) && finite3(p) && finite3(s))) continue;      // non-finite: left as stored
         eval_fields<R, kFldGeneral>(F, (double)x.x, (double)x.y, S.t, E, B);
+        if (!(finite3(E) && finite3(B))) continue;
         const V3<R> d = push<R>(q, (R)S.a_e, E, B, (R)S.dt, (S.flags & F_TBMT) != 0, p, s,
                                 gfac_src<R, kFldGeneral>(T, S.flags), (R)S.eps_r);
         stx(L.x, i, x + d);
@@ -53,7 +55,8 @@ __global__ void __launch_bounds__(kBlock) k_lepton_main(LepDev<R> L, FieldDev F,
     LCount c;
     lepton_range<R, DEC, FLD>(L, F, S, T, lds, start, end, mask, nchunks, c);
     unsigned v[kNCtr + 1] = {};
-    v[C_PROB] = c.prob; v[C_CHI] = c.chi; v[C_NORM] = c.norm; v[C_LSTEP] = c.step; v[kNCtr] = c.trans;
+    v[C_PROB] = c.prob; v[C_CHI] = c.chi; v[C_NORM] = c.norm; v[C_LSTEP] = c.step; v[C_NONFIN] = c.nonfin;
+        v[kNCtr] = c.trans;
     __shared__ unsigned tot[kNCtr + 1];
     block_sum(v, tot);
     if (threadIdx.x < kNCtr) bctr[blockIdx.x * kNCtr + threadIdx.x] = tot[threadIdx.x];
@@ -97,7 +100,7 @@ __global__ void __launch_bounds__(kBlock) k_photon_main(PhoDev<R> G, FieldDev F,
         photon_tile<R, FLD>(G, F, S, T, lds, Q, tile, tile + kPhoTile < end ? tile + kPhoTile : end, mask, nchunks, c);
     unsigned v[kNCtr + 1] = {};
     v[C_PROB] = c.prob; v[C_CHI] = c.chi; v[C_NORM] = c.norm; v[C_RETIRED] = c.ret; v[C_GSTEP] = c.step;
-    v[C_GQED] = c.qed; v[kNCtr] = c.trans;
+    v[C_GQED] = c.qed; v[C_NONFIN] = c.nonfin; v[kNCtr] = c.trans;
     __shared__ unsigned tot[kNCtr + 1];
     block_sum(v, tot);
     if (threadIdx.x < kNCtr) bctr[blockIdx.x * kNCtr + threadIdx.x] = tot[threadIdx.x];

@@ -151,3 +151,85 @@ def test_photons_along_B_and_unpolarized(q, tabs, prec):
     assert ctr.n_pair == q.counters_dict(sim.ctr)["n_pair"] > 0
     tol = 1e-5 if fp32 else 1e-12
     compare_photons(sim.g.arrays(), G.arrays(), set(), tol, tol, what="photons along and across B")
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("merged", [False, True])
+def test_nonfinite_inputs(q, tabs, prec, merged):
+    """NaN and infinity in lepton and photon states (and k = 0) in one step with both channels:
+    the leptons keep their stored values bit for bit, the photons become dead slots, every one
+    is counted in n_nonfinite as by the oracle, nothing else becomes non-finite, and every other
+    particle equals the oracle's."""
+    import math
+
+    import torch
+    rng = np.random.default_rng(12)
+    n, m = 400, 300
+    d = synth.random_unit_vectors(rng, n)
+    g = np.exp(rng.uniform(math.log(500.0), math.log(5000.0), n))
+    p = d * np.sqrt(g * g - 1)
+    s = synth.random_unit_vectors(rng, n)
+    x = np.stack([rng.uniform(0, 50, n), rng.uniform(-5, 5, n), rng.uniform(-5, 5, n)])
+    for j, (arr, c, v) in {3: (p, 0, np.nan), 17: (s, 2, np.inf), 55: (x, 0, -np.inf), 300: (p, 1, -np.inf)}.items():
+        arr[c, j] = v
+    kd = synth.random_unit_vectors(rng, m) * np.exp(rng.uniform(math.log(2e3), math.log(2e4), m))
+    P = synth.random_unit_vectors(rng, m) * 0.8
+    xg = rng.uniform(0, 10, (3, m))
+    ids = (np.uint64(1) << np.uint64(63)) | (np.arange(m, dtype=np.uint64) << np.uint64(24)) | np.uint64(3)
+    kd[0, 4] = np.nan
+    xg[1, 9] = np.inf
+    P[2, 20] = np.nan
+    kd[:, 30] = 0.0
+    if prec == "fp32":
+        p, s, x, kd, P, xg = (a.astype(np.float32).astype(np.float64) for a in (p, s, x, kd, P, xg))
+    E0, B0 = (0.0, 30.0, 0.0), (0.0, 0.0, 120.0)
+    w = _workload(E0, B0, p, s)
+    w.x, w.dt = x, 0.5
+    from paper_2511_08929_amd.sim import Simulation
+    f = q.make_fields(w.field_kind, E0=E0, B0=B0)
+    sim = Simulation(tabs[prec], cap_e=3 * n, cap_p=2 * n, cap_g=m + 2 * n, track=w.track, fields=f, dt=w.dt,
+                     eps_r=EPS, seed=w.seed, flags=q.QED_ALL, k_retire=0.0, device_clock=merged, merged=merged)
+    sim.e.load(x, p, s)
+    sim.g.load(xg, kd, P, ids)
+    sim.step()
+    torch.cuda.synchronize()
+    c = q.counters_dict(sim.ctr)
+    # the oracle on the same inputs, in the same order
+    T = oracle_tables()
+    E = oracle.LeptonSet(0, 3 * n, track=w.track)
+    E.set(x, p, s)
+    Pp = oracle.LeptonSet(1, 2 * n, track=w.track)
+    G = oracle.PhotonSet(m + 2 * n, track=w.track)
+    for i in range(3):
+        G.x[i][:m], G.k[i][:m], G.P[i][:m] = xg[i], kd[i], P[i]
+    G.id[:m] = ids
+    G.n = G.n_prev = m
+    fo = oracle.make_fields(oracle.FIELD_UNIFORM, E0=E0, B0=B0)
+    prm = oracle.make_params(w.dt, EPS, step=0, seed=w.seed, flags=q.QED_ALL, k_retire=0.0,
+                             near_tol=1e-10 if prec == "fp64" else 1e-5, u24=prec == "fp32")
+    ctr = oracle.Counters()
+    oracle.lepton_step(T, prm, fo, E, G, ctr, 8)
+    near = E.near[:n].astype(bool).copy()
+    oracle.lepton_step(T, prm, fo, Pp, G, ctr, 8)
+    oracle.photon_step(T, prm, fo, G, E, Pp, ctr, 8)
+    oc = ctr.as_dict()
+    print(prec, merged, c, oc)
+    assert c["n_nonfinite"] == oc["n_nonfinite"] == 4 + 4
+    assert c["n_emit"] == oc["n_emit"] > 50 and c["n_pair"] == oc["n_pair"] > 0
+    xo_, po_, so_ = sim.e.arrays()
+    bj = np.array([3, 17, 55, 300])
+    for a, b in ((xo_, x), (po_, p), (so_, s)):
+        np.testing.assert_array_equal(a[:, bj], b[:, bj])
+    good = np.setdiff1d(np.arange(sim.e.n()), bj)
+    assert all(np.isfinite(a[:, good]).all() for a in (xo_, po_, so_))
+    tol = 1e-12 if prec == "fp64" else 1e-5
+    oa = E.arrays()
+    ex = np.zeros(sim.e.n(), bool)
+    ex[:n] = near
+    ex[bj] = True
+    compare_leptons((xo_, po_, so_), oa, ex, tol, tol, rtol_x=tol, what="leptons beside non-finite ones")
+    ga = sim.g.arrays()
+    assert (ga[3][[4, 9, 20, 30]] == 0).all()
+    live = ga[3] != 0
+    assert np.isfinite(ga[1][:, live]).all() and np.isfinite(ga[2][:, live]).all()
+    compare_photons(ga, G.arrays(), {(0, int(i)) for i in np.nonzero(near)[0]}, tol, tol, what="photons")
