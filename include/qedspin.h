@@ -193,14 +193,19 @@ typedef struct {                /* device-resident, accumulated */
                        n_lepton_steps,   /* leptons stepped by qed_emit */
                        n_photon_steps,   /* live photons stepped by qed_pair */
                        n_photon_qed,     /* of those, photons with chi_gamma >= chi_g_min (full NBW step) */
-                       n_nonfinite;      /* particle-steps skipped for a NaN or infinity: a lepton whose
-                                            x, p or s is not finite keeps its stored state (no push, no
-                                            QED); one whose fields at t are not finite is not pushed;
-                                            one whose fields at t + dt are not finite is pushed but gets
-                                            no QED part; a photon whose k or x is not finite, or whose P
-                                            is not finite when its chi_gamma >= chi_g_min, becomes a dead
-                                            slot (so does one with k = 0); one whose fields are not finite gets no QED part.  The
-                                            step writes no NaN or infinity of its own */
+                       n_nonfinite;      /* particle-steps with a NaN or infinity in their inputs: a
+                                            lepton whose x, p or s is not finite keeps its stored state
+                                            (no push, no QED); one whose grid field at t is not finite is
+                                            not pushed, one whose grid field at t + dt is not finite is
+                                            pushed without the QED part; a photon whose k or x is not
+                                            finite (or whose k is 0) becomes a dead slot; one whose P
+                                            is not finite takes its QED part as unpolarized (P = 0); one
+                                            in a non-finite grid field gets no QED part.  The step
+                                            writes no NaN or infinity of its own.  Analytic field models
+                                            take finite parameters of magnitude below 1e30 only
+                                            (QED_ERR_INVALID otherwise).  A state is tested through the
+                                            sum of its components, so magnitudes beyond a ninth of the
+                                            element type's range also count as non-finite */
 } qed_counters;
 
 typedef struct {

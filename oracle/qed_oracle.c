@@ -1156,14 +1156,14 @@ int orc_photon_qed_one(const orc_tables *T, const orc_params *prm, uint64_t id,
     double chi = orc_basis(0, prm->eps_r, E, B, k, eh, bh, kh);
     if (!(chi >= prm->chi_g_min)) return 0;
     if (chi > prm->chi_g_max) { chi = prm->chi_g_max; ctr->n_chi_clamped++; }
-    if (!finite3(P)) return 4;                 /* a photon whose polarization is not finite is removed */
     double k0 = sqrt(dot3(k, k));
     double Cg = ORC_ALPHA / (sqrt(3.0) * ORC_PI * prm->eps_r * k0);
     double lnchi = log(chi);
     double Wm = Cg * exp(orc_table_lnrate(T, 2, lnchi));
     double Wp = Cg * exp(orc_table_lnrate(T, 3, lnchi));
-    double xi[3];
-    orc_P_to_stokes(P, eh, bh, kh, xi);
+    double xi[3] = {0.0, 0.0, 0.0};
+    if (finite3(P)) orc_P_to_stokes(P, eh, bh, kh, xi);
+    else ctr->n_nonfinite++;                   /* a non-finite P-vector is stepped as unpolarized */
     double dt = prm->dt;
     double a = Wm * 0.5 * (1.0 - xi[2]) * dt;
     double b = Wp * 0.5 * (1.0 + xi[2]) * dt;
@@ -1531,7 +1531,6 @@ int orc_photon_step(const orc_tables *T, const orc_params *prm, const orc_fields
             double P[3] = {G->P[0][j], G->P[1][j], G->P[2][j]};
             double *o = ob + 14 * j;
             int r = orc_photon_qed_one(T, prm, G->id[j], E, B, k, P, o, o + 3, o + 6, o + 9, &loc);
-            if (r & 4) { G->id[j] = 0; loc.n_nonfinite++; continue; }
             if (r & 1) { o[12] = g_cond_pe; o[13] = g_cond_pp; }
             if (r & 2) loc.n_near_threshold++;
             if (G->near) G->near[j] = (uint8_t)((r >> 1) & 1);

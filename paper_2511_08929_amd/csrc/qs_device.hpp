@@ -570,10 +570,13 @@ template <class R> __device__ __forceinline__ V3<R> stokes_to_P(R x1, R x2, R x3
     return (tr * c) * bs.e + (tr * sn) * bs.b + x2 * bs.k;
 }
 
-template <class R> __device__ __forceinline__ void P_to_stokes(V3<R> P, const Basis<R> &bs, R &x1, R &x2, R &x3)
+// A P-vector with a NaN or infinity decodes as unpolarized (all Stokes parameters 0); the
+// return value is false then.
+template <class R> __device__ __forceinline__ bool P_to_stokes(V3<R> P, const Basis<R> &bs, R &x1, R &x2, R &x3)
 {
     const R d2 = dot(P, P);
-    if (!(d2 > (R)0)) { x1 = x2 = x3 = 0; return; }
+    const bool fin = __builtin_isfinite(d2);
+    if (!(d2 > (R)0) || !fin) { x1 = x2 = x3 = 0; return fin; }
     const R d = sqrt_r(d2), id = (R)1 / d;
     const R p1 = dot(P, bs.e) * id, p2 = dot(P, bs.b) * id, pk = dot(P, bs.k) * id;
     const R rr = p1 * p1 + p2 * p2;
@@ -585,6 +588,7 @@ template <class R> __device__ __forceinline__ void P_to_stokes(V3<R> P, const Ba
         x1 = x3 = 0;
     }
     x2 = d * pk;
+    return true;
 }
 
 // ------------------------------------------------------------------ spectra

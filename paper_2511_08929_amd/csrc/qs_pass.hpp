@@ -191,11 +191,14 @@ __device__ __forceinline__ void wave_add(unsigned long long *ctr, int slot, unsi
 
 // Non-finite inputs (NaN or infinity in a particle's state or in the fields it sees) are not
 // stepped: such a lepton keeps its stored state, such a photon becomes a dead slot, and each is
-// counted in n_nonfinite; the step writes no NaN of its own.
-template <class R> __device__ __forceinline__ bool finite3(V3<R> v)
-{
-    return __builtin_isfinite(v.x) && __builtin_isfinite(v.y) && __builtin_isfinite(v.z);
-}
+// counted in n_nonfinite; the step writes no NaN of its own.  Analytic field models with finite
+// parameters (checked on the host) give finite fields, so only interpolated grid values are
+// checked per particle (the general field variant).
+// One test on a sum: an infinite or NaN component makes the sum non-finite, and a finite sum of
+// finite components needs magnitudes beyond a ninth of the type's range to overflow (which then
+// counts as non-finite too).
+template <class R> __device__ __forceinline__ bool finite_sum(R a) { return __builtin_isfinite(a); }
+template <class R> __device__ __forceinline__ bool finite3(V3<R> v) { return finite_sum(v.x + v.y + v.z); }
 
 template <class R> __device__ __forceinline__ bool zero_field(V3<R> E, V3<R> B)
 {
@@ -254,6 +257,7 @@ template <class R> struct PDecide {
     Basis<R> bs;
     R Wm, Wp, a, P, r1, r2, x1, x2, x3;
     bool active, clamped_chi;
+    bool nonfinite;    // the P-vector is not finite: the photon is stepped as unpolarized
 };
 
 template <class R>
@@ -262,6 +266,7 @@ __device__ __forceinline__ PDecide<R> photon_decide(const StepDev &S, const Tabl
 {
     PDecide<R> d;
     d.clamped_chi = false;
+    d.nonfinite = false;
     if (zero_field(E, B)) {
         d.active = false;
         d.chi = 0.0;
@@ -278,22 +283,13 @@ __device__ __forceinline__ PDecide<R> photon_decide(const StepDev &S, const Tabl
     const R Cg = ratio_r<R>(S.Kc, k0);
     d.Wm = Cg * exp_r(rate_lookup(lds, lnchi, x0, h, n));
     d.Wp = Cg * exp_r(rate_lookup(lds + n, lnchi, x0, h, n));
-    P_to_stokes(P, d.bs, d.x1, d.x2, d.x3);
+    d.nonfinite = !P_to_stokes(P, d.bs, d.x1, d.x2, d.x3);
     const R dt = (R)S.dt;
     d.a = d.Wm * (R)0.5 * ((R)1 - d.x3) * dt;
     const R b = d.Wp * (R)0.5 * ((R)1 + d.x3) * dt;
     d.P = d.a + b;
     Unif<R>::two(philox_block(S.seed, id, S.step, 2u), d.r1, d.r2);
     return d;
-}
-
-// chi_gamma >= chi_min (the test photon_decide makes first), for a photon whose polarization is
-// not used because it is not finite
-template <class R> __device__ __forceinline__ bool photon_active(const StepDev &S, V3<R> k, double k0, V3<R> E, V3<R> B)
-{
-    if (zero_field(E, B)) return false;
-    Basis<R> bs;
-    return basis_chi(0, S.eps_r, k, k0, E, B, bs) >= S.chi_g_min;
 }
 
 // Photons whose FP32 bound eps_r k0 (|E| + |B|) >= |F_perp| eps_r = chi cannot reach chi_min skip
@@ -337,29 +333,29 @@ __device__ __forceinline__ void lepton_item(const LepDev<R> &L, const FieldDev &
     } else {
         ++c.step;
     }
-    if (!(finite3(x) && finite3(p) && finite3(s))) {      // left as stored
-        ++c.nonfin;
-        return;
-    }
+    // a non-finite lepton is neither pushed nor stepped (stored back as it is); a non-finite grid
+    // field at t stops the step there, one at t + dt leaves the push without the QED part
+    bool go = finite_sum(x.x + x.y + x.z + p.x + p.y + p.z + s.x + s.y + s.z);
+    c.nonfin += !go;
     V3<R> E, B;
-    if (S.flags & F_PUSH) {
+    if (go && (S.flags & F_PUSH)) {
         eval_fields<R, FLD>(F, (double)x.x, (double)x.y, S.t, E, B);
-        if (!(finite3(E) && finite3(B))) {                // no push, no QED
+        if (FLD == kFldGeneral && !finite_sum(E.x + E.y + E.z + B.x + B.y + B.z)) {
             ++c.nonfin;
-            return;
+            go = false;
+        } else {
+            x = x + push<R>(q, (R)S.a_e, E, B, (R)S.dt, (S.flags & F_TBMT) != 0, p, s, gfac_src<R, FLD>(T, S.flags),
+                            (R)S.eps_r);
         }
-        x = x + push<R>(q, (R)S.a_e, E, B, (R)S.dt, (S.flags & F_TBMT) != 0, p, s, gfac_src<R, FLD>(T, S.flags),
-                        (R)S.eps_r);
     }
-    if (S.flags & F_EMIT) {
+    if (go && (S.flags & F_EMIT)) {
         eval_fields<R, FLD>(F, (double)x.x, (double)x.y, S.t + S.dt, E, B);
-        if (!(finite3(E) && finite3(B))) {                // the push stands, no QED
+        if (FLD == kFldGeneral && !finite_sum(E.x + E.y + E.z + B.x + B.y + B.z)) {
             ++c.nonfin;
-            stx(L.x, i, x);
-            st3(L.p, i, p);
-            st3(L.s, i, s);
-            return;
+            go = false;
         }
+    }
+    if (go && (S.flags & F_EMIT)) {
         LDecide<R> d = lepton_decide<R>(S, T, lds, L.species, i, p, s, E, B);
         if constexpr ((DEC & 4) != 0) {
             if (d.active) {
@@ -623,30 +619,34 @@ __device__ __forceinline__ void photon_tile(const PhoDev<R> &G, const FieldDev &
         const int64_t i = base + lane;
         bool cand = false;
         R xq = (R)0, yq = (R)0;
-        if (idv[u] != 0 && !(finite3(kv[u]) && finite3(xv[u]) &&
-                             (kv[u].x != (R)0 || kv[u].y != (R)0 || kv[u].z != (R)0))) {
-            G.id[i] = 0;                                  // a non-finite (or k = 0) photon is removed
-            ++c.nonfin;
-        } else if (idv[u] != 0) {
-            ++c.step;
+        if (idv[u] != 0) {
             const V3<R> k = kv[u];
             const R k0r = sqrt_r(dot(k, k));
             V3<R> x = xv[u];
             x = x + ((R)S.dt / k0r) * k;
-            if (G.x[0]) __builtin_nontemporal_store(x.x, &G.x[0][i]);
-            if (G.x[1]) __builtin_nontemporal_store(x.y, &G.x[1][i]);
-            if (G.x[2]) __builtin_nontemporal_store(x.z, &G.x[2][i]);
+            // removed: k = 0 or a NaN or infinity in k or x (then the moved x is not finite), or
+            // |k| beyond the type's range
+            const bool fin = finite_sum(x.x + x.y + x.z) && finite_sum(k0r);
+            if (fin) {
+                ++c.step;
+                if (G.x[0]) __builtin_nontemporal_store(x.x, &G.x[0][i]);
+                if (G.x[1]) __builtin_nontemporal_store(x.y, &G.x[1][i]);
+                if (G.x[2]) __builtin_nontemporal_store(x.z, &G.x[2][i]);
+            }
             // retirement: too soft to ever reach chi_min, or behind the trailing edge of the
             // plane-wave pulse (the phase t + x of a photon never decreases)
             const bool behind = F.kind == 1 && F.phase_len > 0.0 && S.t + S.dt + (double)x.x > F.phase_len;
-            if ((double)k0r < S.k_retire || behind) {
+            if (!fin) {
+                G.id[i] = 0;
+                ++c.nonfin;
+            } else if ((double)k0r < S.k_retire || behind) {
                 G.id[i] = 0;
                 ++c.ret;
             } else if (qed) {
                 V3<R> E, Bf;
                 eval_fields<R, FLD>(F, (double)x.x, (double)x.y, S.t + S.dt, E, Bf);
-                if (finite3(E) && finite3(Bf)) cand = photon_candidate<R>(S, k0r, E, Bf);
-                else ++c.nonfin;                          // no QED in a non-finite field
+                if (FLD != kFldGeneral || (finite3(E) && finite3(Bf))) cand = photon_candidate<R>(S, k0r, E, Bf);
+                else ++c.nonfin;                          // no QED in a non-finite grid field
                 xq = x.x;
                 if (FLD == kFldGeneral) yq = x.y;
             }
@@ -677,15 +677,9 @@ __device__ __forceinline__ void photon_tile(const PhoDev<R> &G, const FieldDev &
         const double k0 = (double)sqrt_r(dot(k, k));
         V3<R> E, Bf;
         eval_fields<R, FLD>(F, (double)Q.x[j], FLD == kFldGeneral ? (double)Q.y[j] : 0.0, S.t + S.dt, E, Bf);
-        if (!finite3(P)) {                                // a non-finite polarization: removed
-            if (photon_active<R>(S, k, k0, E, Bf)) {
-                G.id[i] = 0;
-                ++c.nonfin;
-            }
-            continue;
-        }
         const PDecide<R> d = photon_decide<R>(S, T, lds, id, k, k0, P, E, Bf);
         if (!d.active) continue;
+        c.nonfin += d.nonfinite;
         ++c.qed;
         c.chi += d.clamped_chi;
         if (d.P <= (R)1 && !(d.r1 < d.P)) {
@@ -910,15 +904,23 @@ inline int lepton_variant(const qed_fields *f, uint32_t flags)
     return (flags & QED_G_CHI) ? (int)kFldGeneral : field_variant(f);
 }
 
+// field parameters must be finite and far below the FP32 range (so every analytic field value is
+// finite in both precisions)
+inline bool field_param_ok(double v) { return v == v && v < 1e30 && v > -1e30; }
+
 inline bool fields_ok(const qed_fields *f)
 {
     if (!f) return false;
+    for (int c = 0; c < 3; ++c)
+        if (!field_param_ok(f->E0[c]) || !field_param_ok(f->B0[c])) return false;
+    if (!field_param_ok(f->a0) || !field_param_ok(f->phase_len)) return false;
     if (f->kind == QED_FIELD_UNIFORM || f->kind == QED_FIELD_PLANE_LP) return true;
     if (f->kind == QED_FIELD_ROTATING_E) return f->a0 == f->a0;
     if (f->kind != QED_FIELD_GRID2D) return false;
     for (int c = 0; c < 6; ++c)
         if (!f->grid[c]) return false;
-    return f->nx >= 2 && f->ny >= 2 && f->dx > 0.0 && f->dy > 0.0;
+    return f->nx >= 2 && f->ny >= 2 && f->dx > 0.0 && f->dy > 0.0 && field_param_ok(f->dx) && field_param_ok(f->dy) &&
+           field_param_ok(f->x0) && field_param_ok(f->y0);
 }
 
 }  // namespace qs

@@ -32,7 +32,7 @@ __global__ void __launch_bounds__(kBlock) k_push(LepDev<R> L, FieldDev F, StepDe
         V3<R> E, B;
         if (!(finite3(x) && finite3(p) && finite3(s))) continue;      // non-finite: left as stored
         eval_fields<R, kFldGeneral>(F, (double)x.x, (double)x.y, S.t, E, B);
-        if (!(finite3(E) && finite3(B))) continue;
+        if (!(finite3(E) && finite3(B))) continue;                      // (grid values)
         const V3<R> d = push<R>(q, (R)S.a_e, E, B, (R)S.dt, (S.flags & F_TBMT) != 0, p, s,
                                 gfac_src<R, kFldGeneral>(T, S.flags), (R)S.eps_r);
         stx(L.x, i, x + d);

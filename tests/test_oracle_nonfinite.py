@@ -1,7 +1,7 @@
 """The non-finite input rule of the step, pinned in the oracle by independence: a lepton whose
 state or fields hold a NaN or an infinity keeps its stored state (or only its push) and is
-counted; a photon whose k, x or (with chi_gamma >= chi_min) P is not finite is removed and
-counted; every other particle steps exactly as it does in a run without the bad ones, since
+counted; a photon whose k or x is not finite is removed, one whose P is not finite is stepped
+as unpolarized, each counted; every other particle steps exactly as it does in a run without the bad ones, since
 particles do not interact within a step and keep their Philox ids."""
 import math
 
@@ -82,7 +82,7 @@ def test_nonfinite_photons_are_removed(otables):
     ids = (np.uint64(1) << np.uint64(63)) | (np.arange(n, dtype=np.uint64) << np.uint64(24)) | np.uint64(3)
     k[0, 4] = NAN
     x[1, 9] = INF
-    P[2, 20] = NAN                     # chi_gamma >= chi_min here: removed
+    P[2, 20] = NAN                     # chi_gamma >= chi_min here: stepped as unpolarized
     k[:, 30] = 0.0                     # no direction: removed
     f = oracle.make_fields(oracle.FIELD_UNIFORM, E0=(0.0, 0.0, 0.0), B0=(0.0, 0.0, 150.0))
 
@@ -103,9 +103,12 @@ def test_nonfinite_photons_are_removed(otables):
     allm = np.ones(n, bool)
     G, c = run(allm)
     assert c["n_nonfinite"] == 4
-    assert (G.id[[4, 9, 20, 30]] == 0).all()
+    assert (G.id[[4, 9, 30]] == 0).all()
+    if G.id[20] != 0:                                    # survived: stepped as unpolarized, finite now
+        assert np.isfinite([G.P[i][20] for i in range(3)]).all()
     good = allm.copy()
-    good[[4, 9, 20, 30]] = False
+    good[[4, 9, 30]] = False
+    P[:, 20] = 0.0                                       # the same photon given as unpolarized
     G2, c2 = run(good)
     assert c2["n_nonfinite"] == 0 and c2["n_pair"] == c["n_pair"]
     live = G.id[:n] != 0
