@@ -214,7 +214,9 @@ typedef struct {
     double      total_ms;       /* sum of launch durations measured with HIP events on the launch stream */
 } qed_kernel_time;
 
-/* Build the rate tables ln int_0^1 w dlam (spin-down, spin-up; xi3 = -1, +1) and inverse-CDF
+/* Build the rate tables ln int_0^1 w dlam (spin-down, spin-up; xi3 = -1, +1; the pair rows hold
+   ln int w dlam + 8/(3 chi_gamma), which takes out the exponential fall of the pair rate at small
+   chi_gamma and leaves a row that 4-point interpolation follows to 1e-8) and inverse-CDF
    tables nu = ln(lam/(1-lam)) at rho = ln(r/(1-r)) on the given grid, by quadrature on the GPU
    (NLC section: rate and ICDF tabulated only for s_beta = -1, +1; NBW section: only for
    xi3 = -1, +1).  Allocates device memory; synchronizes the stream.  Returns QED_ERR_INVALID
@@ -234,7 +236,7 @@ qed_status qed_tables_download_gfac(qed_tables tables, double *lngfac, int64_t *
 qed_status qed_free_tables(qed_tables tables);
 
 /* Copy the FP64 tables to host memory (layout [4 channels][n_chi][...], channels NLC-down,
-   NLC-up, NBW-minus, NBW-plus).  Sizes in elements are returned when the pointers are NULL. */
+   NLC-up, NBW-minus, NBW-plus; the pair rate rows with their + 8/(3 chi) as stored).  Sizes in elements are returned when the pointers are NULL. */
 qed_status qed_tables_download(qed_tables tables, double *lnrate, int64_t *n_lnrate,
                                double *nu, int64_t *n_nu);
 

@@ -324,7 +324,7 @@ def gfactor_ratio(chi):
 
 
 # ---------------------------------------------------------------- tables
-def default_spec(n_chi_per_decade=32, n_rho=256, rho_max=37.5,
+def default_spec(n_chi_per_decade=32, n_rho=1024, rho_max=37.5,
                  nlc_range=(1e-3, 1e2), nbw_chi_min=0.05, nbw_decades=3.3125):
     """The table grid of the method contract: nodes uniform in ln chi and in rho = logit r."""
     h = np.log(10.0) / n_chi_per_decade
@@ -375,6 +375,7 @@ class OracleTables:
         return self.spec["n_chi"][0 if ch < 2 else 1]
 
     def lnrate_nodes(self, ch):
+        """the stored rate row: ln int w dlam at the nodes, + 8/(3 chi) in the pair rows (2, 3)"""
         o = self.struct.off_rate[ch]
         return self._lnrate[o:o + self.n_chi(ch)]
 

@@ -57,7 +57,7 @@ typedef struct {
 
 typedef struct {
     orc_table_spec spec;
-    double *lnrate;         /* [4][n_chi(channel)] : ln int spectrum */
+    double *lnrate;         /* [4][n_chi(channel)] : ln int spectrum, + 8/(3 chi) in the pair rows */
     double *nu;             /* [4][n_chi(channel)][n_rho] */
     int64_t off_rate[4], off_nu[4];
     double *lngfac;         /* [ORC_GF_N]: ln(a(chi)/a(0)) at ln chi = ORC_GF_LNCHI0 + i ORC_GF_DLNCHI */

@@ -169,7 +169,7 @@ def _ptr(t):
 
 
 # ------------------------------------------------------------------ table grid
-def contract_grid(n_chi_per_decade=32, n_rho=256, rho_max=37.5, nlc_range=(1e-3, 1e2),
+def contract_grid(n_chi_per_decade=32, n_rho=1024, rho_max=37.5, nlc_range=(1e-3, 1e2),
                   nbw_chi_min=0.05, nbw_decades=3.3125):
     """The table grid of the method contract: nodes uniform in ln chi and in rho = logit r."""
     h = math.log(10.0) / n_chi_per_decade

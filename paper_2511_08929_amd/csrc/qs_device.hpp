@@ -12,6 +12,9 @@ namespace qs {
 
 constexpr double kAlpha = 7.2973525693e-3;
 constexpr double kPi = 3.14159265358979323846;
+// exponent of the low-chi pair rate, W ~ exp(-kErber / chi_gamma): the pair rows of the rate table
+// hold ln W + kErber / chi
+constexpr double kErber = 8.0 / 3.0;
 
 // physics switches (values of the C ABI enum)
 enum : uint32_t {

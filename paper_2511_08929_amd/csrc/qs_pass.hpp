@@ -281,8 +281,9 @@ __device__ __forceinline__ PDecide<R> photon_decide(const StepDev &S, const Tabl
     const R lnchi = log_r((R)d.chi);
     const R x0 = (R)T.lnchi0[1], h = (R)T.dlnchi[1];
     const R Cg = ratio_r<R>(S.Kc, k0);
-    d.Wm = Cg * exp_r(rate_lookup(lds, lnchi, x0, h, n));
-    d.Wp = Cg * exp_r(rate_lookup(lds + n, lnchi, x0, h, n));
+    const R erb = (R)kErber / (R)d.chi;                  // the rows hold ln W + 8/(3 chi)
+    d.Wm = Cg * exp_r(rate_lookup(lds, lnchi, x0, h, n) - erb);
+    d.Wp = Cg * exp_r(rate_lookup(lds + n, lnchi, x0, h, n) - erb);
     d.nonfinite = !P_to_stokes(P, d.bs, d.x1, d.x2, d.x3);
     const R dt = (R)S.dt;
     d.a = d.Wm * (R)0.5 * ((R)1 - d.x3) * dt;

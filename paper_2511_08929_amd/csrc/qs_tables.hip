@@ -225,7 +225,8 @@ __global__ void __launch_bounds__(256) k_build_tables(BuildArgs A, GL12 g, doubl
         s_total = tail + right[0];
         s_tail = tail;
         s_np = np;
-        lnrate[A.off_rate[ch] + i] = log(s_total);
+        // pair rows: ln W + 8/(3 chi), the Erber exponent taken out so the rows are smooth in ln chi
+        lnrate[A.off_rate[ch] + i] = log(s_total) + (ch >= 2 ? qs::kErber / chi : 0.0);
     }
     __syncthreads();
     const double total = s_total, tail = s_tail;
