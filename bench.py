@@ -14,7 +14,7 @@ region.  The number of time steps per collision is fixed: it is part of the work
 
 value = (lepton steps + live photon steps) counted on the device over the K collisions / wall
 time.  Prints one JSON line.  Besides the headline it reports the FP64 path on the same
-collision, the dominant kernel's achieved HBM bandwidth (HIP events on its launch stream) next
+collision, the dominant kernel's achieved HBM bandwidth (HIP events that its dispatches stamp) next
 to its VALU issue and counted traffic, the whole-step bandwidth, the oracle's throughput on the
 host cores (`cpu_baseline`) with the decision mismatch rate of the single-precision path and the
 table method error, and extras (learned inverse CDF, batched ensembles, rejection sampling,
@@ -137,7 +137,8 @@ class Collision:
 
 
 def profiled_collision(q, tab, w, cfg):
-    """One eager collision with every launch bracketed by HIP events on its stream; per-kernel
+    """One eager collision with every launch timed by a start and a stop event that its dispatch
+    stamps (the kernel's own begin and end); per-kernel
     (calls, total ms), the counters of that collision and its wall time."""
     import torch
     from paper_2511_08929_amd.sim import Simulation

@@ -211,7 +211,7 @@ typedef struct {                /* device-resident, accumulated */
 typedef struct {
     const char *name;           /* kernel name (library-owned string) */
     long long   calls;
-    double      total_ms;       /* sum of launch durations measured with HIP events on the launch stream */
+    double      total_ms;       /* sum of kernel durations: start and stop events stamped by each dispatch */
 } qed_kernel_time;
 
 /* Build the rate tables ln int_0^1 w dlam (spin-down, spin-up; xi3 = -1, +1; the pair rows hold
@@ -296,8 +296,9 @@ qed_status qed_compact(const qed_photons *photons, qed_precision precision, void
 /* *d_clock += 1 on the stream (one-thread kernel), for replayed step sequences. */
 qed_status qed_clock_advance(int64_t *d_clock, qed_stream stream);
 
-/* Kernel timing for measurement tools: qed_profile_start clears the record and brackets every
-   subsequent launch with HIP events on its stream; qed_profile_stop synchronizes on them, writes
+/* Kernel timing for measurement tools: qed_profile_start clears the record and gives every
+   subsequent launch a start and a stop event that the dispatch itself stamps (the kernel's begin
+   and end, as a kernel trace reports them); qed_profile_stop synchronizes on them, writes
    up to max_entries per-kernel totals and the number of kernels seen, and stops recording.
    Process-wide and not thread-safe. */
 qed_status qed_profile_start(void);

@@ -5,7 +5,9 @@ streaming block, streaming blocks per processing block, and the cap on the block
 Which values are fastest depends on the workload (set sizes, the share of transitions, how
 the photon population grows over a run) and on the device, so they are chosen by timing the
 caller's own workload.  A search is coordinate-wise: each parameter in turn is swept with the
-others held at the best values so far.  Results are cached per (workload key, device name,
+others held at the best values so far, and a value replaces the one held only when it is
+faster by more than a margin (1%: closer timings are within the run-to-run noise, and a
+search that followed them would pick a different shape on each run).  Results are cached per (workload key, device name,
 library build) in memory and, when a path is given, in a JSON file, so a second tuning of the
 same workload on the same device and build costs nothing.
 
@@ -52,11 +54,12 @@ def _read(path):
         return {}
 
 
-def tune(workload_key: str, run, space=None, start=None, cache_path=None, order=None, log=None):
+def tune(workload_key: str, run, space=None, start=None, cache_path=None, order=None, log=None, margin=0.01):
     """Coordinate search over ``space`` (dict name -> candidate values).  ``run(cfg)`` executes the
     workload with launch configuration ``cfg`` (a dict with every name of the space) and returns
-    its wall time in seconds.  Returns (best cfg, {"cfg as text": seconds} of every timing made,
-    cached flag)."""
+    its wall time in seconds; a value replaces the one held when its time is below
+    (1 - ``margin``) times the held one's.  Returns (best cfg, {"cfg as text": seconds} of every
+    timing made, cached flag)."""
     space = dict(SPACE if space is None else space)
     key = cache_key(workload_key)
     if key in _memory:
@@ -80,12 +83,15 @@ def tune(workload_key: str, run, space=None, start=None, cache_path=None, order=
         return timings[label]
 
     for name in (order or list(space)):
+        held = measure(best)
         vals = {}
         for v in space[name]:
             cfg = dict(best)
             cfg[name] = v
             vals[v] = measure(cfg)
-        best[name] = min(vals, key=vals.get)
+        cand = min(vals, key=vals.get)
+        if vals[cand] < (1.0 - margin) * held:
+            best[name] = cand
     entry = {"workload": workload_key, "best": best, "timings": timings}
     _memory[key] = entry
     if cache_path:

@@ -1,5 +1,6 @@
 // qs_internal.hpp -- host-side internals shared by the table builder and the step kernels.
 #pragma once
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include "../../include/qedspin.h"
@@ -57,19 +58,26 @@ inline qed_status qs_launch_status(const char *where)
     } while (0)
 
 // ---------------------------------------------------------------- kernel timing
-// With profiling on (qed_profile_start), every launch is bracketed by two HIP events recorded on
-// the launch stream; qed_profile_stop synchronizes and reports per-kernel calls and time.
+// With profiling on (qed_profile_start), every launch goes through hipExtLaunchKernelGGL with a
+// start and a stop event, which the runtime stamps with the begin and end of the kernel's own
+// dispatch (the interval a kernel trace reports; events recorded around the launch would also
+// take in the dispatch latency, ~2 us); qed_profile_stop synchronizes and reports per-kernel
+// calls and time.
 enum QsKernel {
     K_TABLES = 0, K_PUSH, K_LEPTON_MAIN, K_EMIT_PROCESS, K_PHOTON_MAIN, K_PAIR_PROCESS, K_MASK_EXPAND, K_SET_PREV,
     K_ALIVE_MASK, K_GATHER, K_SCATTER_BACK, K_PLAN_LEPTON, K_PLAN_PHOTON, K_PLAN_PROCESS, K_GRID_PACK, K_NKERNELS
 };
 extern bool g_qs_profiling;
-void qs_prof_begin(int kid, hipStream_t st);
-void qs_prof_end(int kid, hipStream_t st);
+// a start and a stop event for one launch of kernel kid (both null if none could be made)
+void qs_prof_events(int kid, hipEvent_t *start, hipEvent_t *stop);
 
-#define QS_LAUNCH(kid, kernel, grid, block, lds, stream, ...)                        \
-    do {                                                                            \
-        if (g_qs_profiling) qs_prof_begin(kid, stream);                             \
-        hipLaunchKernelGGL(kernel, grid, block, lds, stream, __VA_ARGS__);          \
-        if (g_qs_profiling) qs_prof_end(kid, stream);                               \
+#define QS_LAUNCH(kid, kernel, grid, block, lds, stream, ...)                                     \
+    do {                                                                                         \
+        if (g_qs_profiling) {                                                                    \
+            hipEvent_t a_, b_;                                                                   \
+            qs_prof_events(kid, &a_, &b_);                                                       \
+            hipExtLaunchKernelGGL(kernel, grid, block, lds, stream, a_, b_, 0, __VA_ARGS__);     \
+        } else {                                                                                 \
+            hipLaunchKernelGGL(kernel, grid, block, lds, stream, __VA_ARGS__);                   \
+        }                                                                                        \
     } while (0)

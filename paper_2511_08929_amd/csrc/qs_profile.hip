@@ -1,4 +1,5 @@
-// qs_profile.hip -- per-kernel timing with HIP events (qed_profile_start / qed_profile_stop).
+// qs_profile.hip -- per-kernel timing with HIP events stamped by the kernel dispatch itself
+// (qed_profile_start / qed_profile_stop).
 // Single-threaded host use: the event records live in one process-wide list.
 #include <string.h>
 
@@ -15,7 +16,6 @@ struct Rec {
 };
 std::vector<Rec> g_recs;
 std::vector<hipEvent_t> g_pool;
-hipEvent_t g_open = nullptr;
 
 const char *const kNames[K_NKERNELS] = {"table_build", "push",       "lepton_main", "emit_process", "photon_main",
                                         "pair_process", "expand",    "clock",       "alive_mask",   "gather",
@@ -35,19 +35,17 @@ hipEvent_t take()
 }
 }  // namespace
 
-void qs_prof_begin(int, hipStream_t st)
+void qs_prof_events(int kid, hipEvent_t *start, hipEvent_t *stop)
 {
-    g_open = take();
-    if (g_open) (void)hipEventRecord(g_open, st);
-}
-
-void qs_prof_end(int kid, hipStream_t st)
-{
-    hipEvent_t b = take();
-    if (!g_open || !b) return;
-    (void)hipEventRecord(b, st);
-    g_recs.push_back({kid, g_open, b});
-    g_open = nullptr;
+    hipEvent_t a = take(), b = a ? take() : nullptr;
+    if (!b) {
+        if (a) g_pool.push_back(a);
+        *start = *stop = nullptr;                // launched untimed
+        return;
+    }
+    g_recs.push_back({kid, a, b});
+    *start = a;
+    *stop = b;
 }
 
 extern "C" qed_status qed_profile_start(void)
