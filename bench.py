@@ -434,11 +434,15 @@ def table_method_error():
 
 
 # ----------------------------------------------------------------------------- extras
+SURROGATE_JUDGE_BOUND = 0.01      # |dnu| above which a coarse cell falls back to the table inverse CDF
+
+
 def extra_surrogate(q, args, w, t32, t64, cfg, out, v64):
     import torch
     t0 = time.perf_counter()
     sn, sb = q.Surrogate(t32, 0, seed=1), q.Surrogate(t32, 1, seed=2)
     ln, lb = sn.fit(), sb.fit()
+    judged = [s.judge(SURROGATE_JUDGE_BOUND)[1] for s in (sn, sb)]
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t0
     col = Collision(q, t32, w, cfg, surrogates=(sn, sb))
@@ -446,8 +450,16 @@ def extra_surrogate(q, args, w, t32, t64, cfg, out, v64):
     col.close()
     vs = work_of(c) / wall
     log(f"fp32 + learned inverse CDF: {vs:.4g}/s (training {t_train:.2f} s)")
+    info = [s.info() for s in (sn, sb)]
+    sp = t32.grid
+    fine = [2 * sp["n_chi"][g] * sp["n_rho"] * 8 for g in (0, 1)]
     sur = {"value": round(vs, 1), "unit": "particle-QED-steps/s", "train_s": round(t_train, 3),
-           "final_mse": [round(float(ln[-1]), 8), round(float(lb[-1]), 8)], "network_bytes_bf16": sn.n_params * 2}
+           "final_mse_y": [round(float(ln[-1]), 8), round(float(lb[-1]), 8)],
+           "residual_scale": [round(i.out_s, 6) for i in info],
+           "judge": {"bound_dnu": SURROGATE_JUDGE_BOUND, "points_per_cell": 64, "cells": [i.n_cells for i in info],
+                     "marked": judged},
+           "bytes": {"network_bf16": [i.bytes_network for i in info], "coarse_table_fp32": [i.bytes_base for i in info],
+                     "mask": [i.bytes_mask for i in info], "fine_tables_fp64": fine}}
     if v64:
         sur["speedup_vs_fp64"] = round(vs / v64, 3)
     wsub = synth.subsample(w, np.arange(min(w.n, 100_000)))

@@ -339,7 +339,9 @@ typedef struct {
     qed_surrogate icdf_nbw;      /* ... for the pair split.  Only with QED_F32 tables, and built on
                                     the same tables (else QED_ERR_UNSUPPORTED / QED_ERR_INVALID).
                                     The network runs inside the processing launch, on the
-                                    matrix cores, for the transitions each block holds. */
+                                    matrix cores, for the transitions each block holds; in the
+                                    cells its last qed_surrogate_judge marked, the table inverse
+                                    CDF is used. */
     int process_group;           /* streaming blocks whose transitions one block processes, default 4 */
 } qed_plan_config;
 
@@ -369,39 +371,76 @@ qed_status qed_plan_destroy(qed_plan plan);
 /* ---------------------------------------------------------------------------------------
    Learned inverse CDF.  The NLCS and NBW implementation sections tabulate the inverse CDF of
    the photon (pair) energy only for the two spin (xi3) channels, because the full dependence
-   is too large to tabulate.  A surrogate is a small network nu(ln chi, rho, c), c = -1 / +1
-   (NLC: spin down / up; NBW: xi3 = -1 / +1), that stands in for the two tables of one process:
-   inputs u = (ln chi - m)/h (m, h: centre and half-width of the table's ln chi range),
-   v = rho/17 (rho = ln(r/(1-r)) of a 24-bit uniform, |rho| <= 16.64), c; four hidden layers of
-   64 SiLU units; output nu = 20 y.  12801 parameters in the flat order W1 (3x64, row = input),
-   b1, W2 (64x64, row = input unit), b2, W3, b3, W4, b4, W5 (64), b5.  Evaluation runs the 64x64
-   layers on the matrix cores in BF16 with FP32 accumulation (BF16 weights); the tables remain
-   the alternative and the reference its error is measured against. */
+   is too large to tabulate.  A surrogate stands in for the two fine tables of one process with
+   nu(ln chi, rho, c) = base(ln chi, rho, c) + s y(u, v, c), c = -1 / +1 (NLC: spin down / up;
+   NBW: xi3 = -1 / +1), s = 1.25 times the coarse table's largest error over 8 x 8 points per
+   coarse cell (so that y spans about [-1, 1]; qed_surrogate_norm):
+   - base: a coarse FP32 table of nu (the fine tables' values at its nodes; at least 4 ln chi
+     nodes per decade over the fine table's range, rho nodes every 1 on [-20, 20]; 4-point
+     Lagrange in each axis);
+   - y: a network with inputs u = (ln chi - m)/h (m, h: centre and half-width of the table's
+     ln chi range), v = rho/17 (rho = ln(r/(1-r)) of a 24-bit uniform, |rho| <= 16.64) and c;
+     four hidden layers of 64 SiLU units and one linear output.  12801 parameters in the flat
+     order W1 (3x64, row = input), b1, W2 (64x64, row = input unit), b2, W3, b3, W4, b4, W5 (64),
+     b5.  The 64x64 layers run on the matrix cores in BF16 with FP32 accumulation (BF16 weights).
+   The fine tables are the judge and the fallback: qed_surrogate_judge marks the coarse cells
+   where the surrogate's error exceeds a bound, and there the table inverse CDF is used. */
 int64_t qed_surrogate_n_params(void);
 
 /* Allocate a surrogate for process 0 (NLC) or 1 (NBW) of these tables, parameters initialized
    from Philox channel 7 with `seed` (uniform, variance 2 / fan-in).  Synchronizes the device. */
 qed_status qed_surrogate_create(qed_tables tables, int process, uint64_t seed, qed_surrogate *out);
 
-/* Normalization constants {m, h, rho scale, nu scale} (host array of 4). */
+/* Normalization constants {m, h, rho scale, residual scale} (host array of 4). */
 qed_status qed_surrogate_norm(qed_surrogate s, float *out4);
 
-/* `steps` Adam steps (lr; betas 0.9, 0.999) on the mean squared error of y against nu/20, each
-   on 4 x 256 x tiles_per_wave x 16 fresh samples drawn from Philox channel 6: ln chi uniform over
-   the table range, rho half the time uniform over [-17, 17] and half the time logit(r) of a
-   uniform r (as in the sampling), c = +-1; targets nu from the tables.  d_loss (device,
-   `steps` floats, may be NULL) receives each step's mean squared error. */
+/* Shape, judgement and size of a surrogate. */
+typedef struct {
+    int     process;
+    int     n_params;
+    float   in_m, in_h, rho_s, out_s;          /* as qed_surrogate_norm */
+    float   base_lnchi0, base_dlnchi;          /* coarse ln chi nodes: base_lnchi0 + i base_dlnchi */
+    int     base_n_chi;
+    float   base_rho0, base_drho;              /* coarse rho nodes */
+    int     base_n_rho;
+    int64_t n_cells;                           /* 2 (base_n_chi - 1)(base_n_rho - 1): cell (c i j) */
+    int64_t n_masked;                          /* cells marked by the last judgement */
+    float   bound;                             /* its bound (0 before the first) */
+    int64_t bytes_network, bytes_base, bytes_mask;  /* BF16 parameters, FP32 coarse table, mask */
+} qed_surrogate_info;
+qed_status qed_surrogate_get_info(qed_surrogate s, qed_surrogate_info *out);
+
+/* `steps` Adam steps (lr; betas 0.9, 0.999) on the mean squared error of y against the residual
+   (nu - base)/s, each on 4 x 256 x tiles_per_wave x 16 fresh samples drawn from Philox
+   channel 6: ln chi uniform over the table range, rho half the time uniform over [-17, 17] and
+   half the time logit(r) of a uniform r (as in the sampling), c = +-1; targets nu from the fine
+   tables.  d_loss (device, `steps` floats, may be NULL) receives each step's mean squared
+   error. */
 qed_status qed_surrogate_train(qed_surrogate s, int steps, int tiles_per_wave, float lr, float *d_loss,
                                qed_stream stream);
 
-/* Gradient of sum_i (y_i - nu_i/20)^2 over n given samples (device: d_x[n][3] = ln chi, rho, c;
-   d_nu[n]) with respect to the parameters: d_grad[12801], then the sum of squares in
-   d_grad[12801].  n <= 16384.  For checks of the training kernels. */
-qed_status qed_surrogate_gradient(qed_surrogate s, const float *d_x, const float *d_nu, int64_t n,
+/* Gradient of sum_i (y(x_i) - y_i)^2 over n given samples (device: d_x[n][3] = ln chi, rho, c;
+   d_y[n]: targets of the network output) with respect to the parameters: d_grad[12801], then the
+   sum of squares in d_grad[12801].  n <= 16384.  For checks of the training kernels. */
+qed_status qed_surrogate_gradient(qed_surrogate s, const float *d_x, const float *d_y, int64_t n,
                                   float *d_grad, qed_stream stream);
 
-/* nu for n samples d_x[n][3] = (ln chi, rho, c) (device) into d_nu[n]. */
-qed_status qed_surrogate_eval(qed_surrogate s, const float *d_x, int64_t n, float *d_nu, qed_stream stream);
+/* nu for n samples d_x[n][3] = (ln chi, rho, c) (device) into d_nu[n]:
+   QED_SURROGATE_AS_USED as the step uses it (the fine table in marked cells, else base + net),
+   QED_SURROGATE_NETWORK base + net everywhere, QED_SURROGATE_BASE the coarse table alone. */
+enum { QED_SURROGATE_AS_USED = 0, QED_SURROGATE_NETWORK = 1, QED_SURROGATE_BASE = 2 };
+qed_status qed_surrogate_eval(qed_surrogate s, const float *d_x, int64_t n, int mode, float *d_nu,
+                              qed_stream stream);
+
+/* Judge the surrogate by the fine tables: for every coarse cell, the largest |base + net - table|
+   over the centres of a points_per_axis^2 subdivision with |rho| <= 16.64 (cells beyond that
+   rho are never reached by 24-bit uniforms and report 0), into cell_err (host, n_cells floats,
+   may be NULL); cells above `bound` are marked, and the step and QED_SURROGATE_AS_USED use the
+   table inverse CDF there.  *n_masked (may be NULL) receives their number.  Synchronizes the
+   stream.  qed_surrogate_train and qed_surrogate_set_params clear the marks (a judgement holds
+   for the parameters it saw): judge again after them. */
+qed_status qed_surrogate_judge(qed_surrogate s, float bound, int points_per_axis, float *cell_err,
+                               int64_t *n_masked, qed_stream stream);
 
 /* Copy the FP32 parameters out of / into the surrogate (device arrays of 12801 floats). */
 qed_status qed_surrogate_get_params(qed_surrogate s, float *d_params, qed_stream stream);

@@ -40,7 +40,8 @@ ABI_SYMBOLS = ("qed_init_tables", "qed_last_error", "qed_free_tables", "qed_tabl
                "qed_profile_start", "qed_profile_stop", "qed_clock_advance", "qed_plan_create", "qed_plan_step",
                "qed_plan_blocks", "qed_plan_destroy", "qed_surrogate_n_params", "qed_surrogate_create",
                "qed_surrogate_norm", "qed_surrogate_train", "qed_surrogate_gradient", "qed_surrogate_eval",
-               "qed_surrogate_get_params", "qed_surrogate_set_params", "qed_surrogate_destroy")
+               "qed_surrogate_get_params", "qed_surrogate_set_params", "qed_surrogate_destroy",
+               "qed_surrogate_judge", "qed_surrogate_get_info")
 
 
 class QedError(RuntimeError):
@@ -138,7 +139,9 @@ def lib():
         L.qed_surrogate_norm.argtypes = [vp, P(f)]
         L.qed_surrogate_train.argtypes = [vp, C.c_int, C.c_int, f, vp, vp]
         L.qed_surrogate_gradient.argtypes = [vp, vp, vp, i64, vp, vp]
-        L.qed_surrogate_eval.argtypes = [vp, vp, i64, vp, vp]
+        L.qed_surrogate_eval.argtypes = [vp, vp, i64, C.c_int, vp, vp]
+        L.qed_surrogate_judge.argtypes = [vp, f, C.c_int, vp, P(i64), vp]
+        L.qed_surrogate_get_info.argtypes = [vp, P(SurrogateInfo)]
         L.qed_surrogate_get_params.argtypes = [vp, vp, vp]
         L.qed_surrogate_set_params.argtypes = [vp, vp, vp]
         L.qed_surrogate_destroy.argtypes = [vp]
@@ -484,8 +487,21 @@ class Plan:
             pass
 
 
+SURROGATE_AS_USED, SURROGATE_NETWORK, SURROGATE_BASE = 0, 1, 2
+
+
+class SurrogateInfo(C.Structure):
+    _fields_ = [("process", C.c_int), ("n_params", C.c_int), ("in_m", C.c_float), ("in_h", C.c_float),
+                ("rho_s", C.c_float), ("out_s", C.c_float), ("base_lnchi0", C.c_float), ("base_dlnchi", C.c_float),
+                ("base_n_chi", C.c_int), ("base_rho0", C.c_float), ("base_drho", C.c_float), ("base_n_rho", C.c_int),
+                ("n_cells", C.c_int64), ("n_masked", C.c_int64), ("bound", C.c_float),
+                ("bytes_network", C.c_int64), ("bytes_base", C.c_int64), ("bytes_mask", C.c_int64)]
+
+
 class Surrogate:
-    """qed_surrogate: the learned inverse CDF of one process (0 = NLC, 1 = NBW)."""
+    """qed_surrogate: the learned inverse CDF of one process (0 = NLC, 1 = NBW): a coarse table
+    plus a network for its residual, judged by the fine tables (table inverse CDF in the cells
+    the judgement marks)."""
 
     def __init__(self, tables: Tables, process, seed=1):
         h = C.c_void_p()
@@ -511,21 +527,40 @@ class Surrogate:
         import torch
         return torch.cat([self.train(n, tiles_per_wave, lr, stream) for lr, n in schedule])
 
-    def gradient(self, x, nu, stream=None):
-        """gradient of sum (y - nu/20)^2 over the samples (x: (n, 3) float32 device, nu: (n,)); the
-        returned tensor has n_params + 1 entries, the last one the sum of squares"""
+    def gradient(self, x, y, stream=None):
+        """gradient of sum (y(x) - y)^2 over the samples (x: (n, 3) float32 device, y: (n,) targets
+        of the network output); the returned tensor has n_params + 1 entries, the last one the sum
+        of squares"""
         import torch
         g = torch.zeros(self.n_params + 1, dtype=torch.float32, device="cuda")
-        _check(lib().qed_surrogate_gradient(self.handle, _ptr(x), _ptr(nu), x.shape[0], _ptr(g), _stream_ptr(stream)),
+        _check(lib().qed_surrogate_gradient(self.handle, _ptr(x), _ptr(y), x.shape[0], _ptr(g), _stream_ptr(stream)),
                "qed_surrogate_gradient")
         return g
 
-    def eval(self, x, stream=None):
+    def eval(self, x, mode=SURROGATE_AS_USED, stream=None):
+        """nu at raw inputs x (n, 3) = (ln chi, rho, c): as the step uses it, the network without
+        the fallback (SURROGATE_NETWORK) or the coarse table alone (SURROGATE_BASE)"""
         import torch
         nu = torch.empty(x.shape[0], dtype=torch.float32, device="cuda")
-        _check(lib().qed_surrogate_eval(self.handle, _ptr(x), x.shape[0], _ptr(nu), _stream_ptr(stream)),
+        _check(lib().qed_surrogate_eval(self.handle, _ptr(x), x.shape[0], mode, _ptr(nu), _stream_ptr(stream)),
                "qed_surrogate_eval")
         return nu
+
+    def judge(self, bound, points_per_axis=8, stream=None):
+        """mark the coarse cells whose largest sampled error against the fine tables exceeds
+        `bound`; returns (per-cell largest error as a numpy array, number marked)"""
+        import numpy as np
+        info = self.info()
+        err = np.zeros(info.n_cells, dtype=np.float32)
+        nm = C.c_int64(0)
+        _check(lib().qed_surrogate_judge(self.handle, bound, points_per_axis, err.ctypes.data_as(C.c_void_p),
+                                         C.byref(nm), _stream_ptr(stream)), "qed_surrogate_judge")
+        return err, int(nm.value)
+
+    def info(self):
+        out = SurrogateInfo()
+        _check(lib().qed_surrogate_get_info(self.handle, C.byref(out)), "qed_surrogate_get_info")
+        return out
 
     def get_params(self, stream=None):
         import torch

@@ -1,8 +1,11 @@
-// qs_mlp.hpp -- the learned inverse CDF: a multilayer perceptron nu(ln chi, rho, c) with inputs
-// u = (ln chi - m)/h, v = rho/rho_s and the channel c = -1 / +1 (spin down / up for NLC,
-// xi3 = -1 / +1 for NBW), four hidden layers of 64 SiLU units, one linear output y = nu/out_s.
-// It stands in for the two inverse-CDF tables of one process (NLCS and NBW implementation
-// sections tabulate only these two channels).
+// qs_mlp.hpp -- the learned inverse CDF: nu(ln chi, rho, c) = base(ln chi, rho, c) + out_s y, with
+// base a coarse FP32 table of nu (4-point Lagrange in ln chi and rho, a few nodes per decade and
+// per unit of rho) and y a multilayer perceptron with inputs u = (ln chi - m)/h, v = rho/rho_s and
+// the channel c = -1 / +1 (spin down / up for NLC, xi3 = -1 / +1 for NBW), four hidden layers of
+// 64 SiLU units and one linear output.  It stands in for the two fine inverse-CDF tables of one
+// process (NLCS and NBW implementation sections tabulate only these two channels).  The fine
+// tables judge it: every cell of the coarse grid whose largest sampled error exceeds a stated
+// bound is marked, and in a marked cell the table inverse CDF is used instead.
 //
 // Precision: weights and activations enter the three 64x64 layers as BF16 on the matrix cores
 // (v_mfma_f32_16x16x16bf16_1k), accumulation and everything else in FP32.
@@ -46,8 +49,45 @@ struct MlpDev {
     const float *p;              // FP32 master parameters [kNP] (training only)
     const unsigned short *wt;    // BF16 copy of every parameter [kNP] (layouts as in p)
     const bf16x4 *img;           // W2..W4 as B operands: img[(l-2)*1024 + (kb*4 + nb)*64 + lane]
+    const float *base;           // coarse nu nodes [2 channels][bnx][bny]
+    const uint32_t *mask;        // judged cells, bit (c (bnx-1) + i) (bny-1) + j: table inverse CDF
+                                 // there (NULL: no cell marked)
     float in_m, in_h, rho_s, out_s;
+    float bx0, bhx, by0, bhy;    // coarse grid: ln chi = bx0 + i bhx, rho = by0 + j bhy
+    int bnx, bny;
 };
+
+// coarse cell of raw inputs (ln chi, rho, c): the node interval of each axis, clamped to the grid
+__device__ __forceinline__ int mlp_cell(const MlpDev &M, const float *xr)
+{
+    int i = (int)floorf((xr[0] - M.bx0) / M.bhx), j = (int)floorf((xr[1] - M.by0) / M.bhy);
+    i = i < 0 ? 0 : (i > M.bnx - 2 ? M.bnx - 2 : i);
+    j = j < 0 ? 0 : (j > M.bny - 2 ? M.bny - 2 : j);
+    return ((xr[2] > 0.0f ? 1 : 0) * (M.bnx - 1) + i) * (M.bny - 1) + j;
+}
+
+__device__ __forceinline__ bool mlp_masked(const MlpDev &M, const float *xr)
+{
+    if (!M.mask) return false;
+    const int b = mlp_cell(M, xr);
+    return (M.mask[b >> 5] >> (b & 31)) & 1u;
+}
+
+// coarse-table nu at raw inputs (the lookup of the fine tables, in FP32 on the coarse nodes)
+__device__ __forceinline__ float mlp_base(const MlpDev &M, const float *xr)
+{
+    float Lx[4], Ly[4];
+    const int i0 = lagrange4(xr[0], M.bx0, M.bhx, M.bnx, Lx);
+    const int j0 = lagrange4(xr[1], M.by0, M.bhy, M.bny, Ly);
+    const float *b = M.base + ((int64_t)(xr[2] > 0.0f ? 1 : 0) * M.bnx + i0) * M.bny + j0;
+    float acc = 0.0f;
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+        const float *r = b + a * M.bny;
+        acc += Lx[a] * (Ly[0] * r[0] + Ly[1] * r[1] + Ly[2] * r[2] + Ly[3] * r[3]);
+    }
+    return acc;
+}
 
 struct MlpWave {
     float z[4][16][mlp::kH];     // pre-activations of the hidden layers

@@ -183,7 +183,8 @@ template <> struct SurLds<false> {
 // SUR: a process with a learned inverse CDF (P.mlp_on) handles its transitions in rounds of one
 // per thread: each thread writes its transition's network inputs to LDS, the waves run the
 // network on the round's rows (16 per forward pass), and each thread finishes its transition
-// with its nu.
+// with its nu (coarse table + network), or with the table inverse CDF where the tables judged
+// the network out of bound.
 template <class R, int FLD, bool SUR>
 __global__ void __launch_bounds__(kBlock) k_plan_process(const InstDev<R> *inst, PlanDev P, TablesDev T, int b_first)
 {
@@ -349,10 +350,11 @@ __global__ void __launch_bounds__(kBlock) k_plan_process(const InstDev<R> *inst,
                         }
                         __syncthreads();
                         const float y = mlp_forward(M, W);
-                        if (lane < 16 && row < rows) sl.nu[row] = M.out_s * y;
+                        if (lane < 16 && row < rows) sl.nu[row] = mlp_base(M, sl.xin[row]) + M.out_s * y;
                         __syncthreads();
                     }
-                    if (j < nl) item(j, &sl.nu[threadIdx.x], nullptr);
+                    // in a cell the tables judged the network out of bound, the table inverse CDF
+                    if (j < nl) item(j, mlp_masked(M, sl.xin[threadIdx.x]) ? nullptr : &sl.nu[threadIdx.x], nullptr);
                     __syncthreads();
                 }
             }
