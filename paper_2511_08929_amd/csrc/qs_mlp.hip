@@ -151,16 +151,16 @@ __global__ void k_mlp_to_bf16(const float *p, unsigned short *wt)
     if (i < kNP) wt[i] = f2bf(p[i]);
 }
 
-// img[(L-2)*1024 + (kb*4 + nb)*64 + lane][j] = W_L[k = kb*16 + 4(lane/16) + j][n = nb*16 + lane%16]
-__global__ void k_mlp_image(const unsigned short *wt, bf16x4 *img)
+// img[(L-2)*512 + (kc*4 + nb)*64 + lane][j] = W_L[k = kc*32 + 8(lane/16) + j][n = nb*16 + lane%16]
+__global__ void k_mlp_image(const unsigned short *wt, s16x8 *img)
 {
     const int e = blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= kImg) return;
-    const int L = 2 + e / 1024, kbnb = (e % 1024) / 64, lane = e % 64;
-    const int kb = kbnb / 4, nb = kbnb % 4;
-    bf16x4 v;
-    for (int j = 0; j < 4; ++j)
-        v[j] = (short)wt[kW(L) + (kb * 16 + 4 * (lane / 16) + j) * kH + nb * 16 + (lane % 16)];
+    const int L = 2 + e / 512, kcnb = (e % 512) / 64, lane = e % 64;
+    const int kc = kcnb / 4, nb = kcnb % 4;
+    s16x8 v;
+    for (int j = 0; j < 8; ++j)
+        v[j] = (short)wt[kW(L) + (kc * 32 + 8 * (lane / 16) + j) * kH + nb * 16 + (lane % 16)];
     img[e] = v;
 }
 
@@ -244,7 +244,7 @@ struct qed_surrogate_s {
     int64_t steps_done;
     float *p, *m1, *m2, *acc, *loss_tmp;
     unsigned short *wt;
-    bf16x4 *img;
+    s16x8 *img;
     float *base;                 // coarse table [2][bnx][bny]
     uint32_t *mask;              // judged cells (bit per cell)
     unsigned *cell_err;          // largest sampled error per cell of the last judgement (float bits)
@@ -356,7 +356,7 @@ extern "C" qed_status qed_surrogate_create(qed_tables T, int process, uint64_t s
     if (e == hipSuccess) e = hipMalloc((void **)&s->acc, sizeof(float) * kAcc * kGradGrid);
     if (e == hipSuccess) e = hipMalloc((void **)&s->loss_tmp, sizeof(float) * kAcc);
     if (e == hipSuccess) e = hipMalloc((void **)&s->wt, sizeof(unsigned short) * kNP);
-    if (e == hipSuccess) e = hipMalloc((void **)&s->img, sizeof(bf16x4) * kImg);
+    if (e == hipSuccess) e = hipMalloc((void **)&s->img, sizeof(s16x8) * kImg);
     if (e == hipSuccess) e = hipMalloc((void **)&s->base, sizeof(float) * 2 * s->bnx * s->bny);
     if (e == hipSuccess) e = hipMalloc((void **)&s->mask, sizeof(uint32_t) * ((n_cells(s) + 31) / 32));
     if (e == hipSuccess) e = hipMalloc((void **)&s->cell_err, sizeof(unsigned) * n_cells(s));

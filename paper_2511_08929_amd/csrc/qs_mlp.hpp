@@ -8,10 +8,14 @@
 // bound is marked, and in a marked cell the table inverse CDF is used instead.
 //
 // Precision: weights and activations enter the three 64x64 layers as BF16 on the matrix cores
-// (v_mfma_f32_16x16x16bf16_1k), accumulation and everything else in FP32.
+// (v_mfma_f32_16x16x32_bf16, two per 16 x 16 output block), accumulation and everything else in
+// FP32.
 //
-// A wave evaluates 16 samples (rows) at a time.  MFMA operand layouts (16x16x16): lane l holds
-//   A[m = l%16][k = 4(l/16) + j],  B[k = 4(l/16) + j][n = l%16],  D[m = 4(l/16) + j][n = l%16].
+// A wave evaluates 16 samples (rows) at a time.  MFMA operand layouts (16x16x32): lane l holds
+//   A[m = l%16][k = 8(l/16) + j],  B[k = 8(l/16) + j][n = l%16]  (j < 8),
+//   D[m = 4(l/16) + j][n = l%16]  (j < 4);
+// the weight-gradient products (K = the 16 rows of a tile) use the 16x16x16 form, whose lane l
+// holds A[m = l%16][k = 4(l/16) + j] and B[k = 4(l/16) + j][n = l%16] (j < 4), D as above.
 // Activations pass between layers through LDS (the D layout of one layer is transposed with
 // respect to the A layout of the next).  All waves of a block call these functions the same
 // number of times: they synchronize the block.
@@ -30,11 +34,20 @@ __host__ __device__ constexpr int kB(int l) { return kW(l) + kH * kH; }
 constexpr int kW5 = kL2 + 3 * kLayer;
 constexpr int kB5 = kW5 + kH;
 constexpr int kNP = kB5 + 1;                 // 12801 parameters
-constexpr int kImg = 3 * 16 * 64;            // bf16x4 entries of the B-operand image of W2..W4
+constexpr int kImg = 3 * 8 * 64;             // bf16x8 entries of the B-operand image of W2..W4
 }  // namespace mlp
 
 typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef short s16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+// D += A B over K = 32 (16 x 16 output), operands as BF16 bit patterns
+__device__ __forceinline__ f32x4 mfma32(s16x8 a, s16x8 b, f32x4 d)
+{
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a), __builtin_bit_cast(bf16x8, b), d, 0, 0,
+                                                   0);
+}
 
 __host__ __device__ inline unsigned short f2bf(float f)    // round to nearest even (finite f)
 {
@@ -48,7 +61,7 @@ __device__ __forceinline__ float bf2f(unsigned short h) { return __uint_as_float
 struct MlpDev {
     const float *p;              // FP32 master parameters [kNP] (training only)
     const unsigned short *wt;    // BF16 copy of every parameter [kNP] (layouts as in p)
-    const bf16x4 *img;           // W2..W4 as B operands: img[(l-2)*1024 + (kb*4 + nb)*64 + lane]
+    const s16x8 *img;            // W2..W4 as B operands: img[(l-2)*512 + (kc*4 + nb)*64 + lane]
     const float *base;           // coarse nu nodes [2 channels][bnx][bny]
     const uint32_t *mask;        // judged cells, bit (c (bnx-1) + i) (bny-1) + j: table inverse CDF
                                  // there (NULL: no cell marked)
@@ -128,17 +141,17 @@ template <class WV> __device__ inline float mlp_forward(const MlpDev &M, WV &W)
     using namespace mlp;
     const int l = threadIdx.x & 63, r = l & 15, q = l >> 4;
     const unsigned short *wt = M.wt;
-    bf16x4 a[4];
+    s16x8 a[2];                      // A operand: activations of row r, units kc*32 + 8q + j
     const float x0 = W.x[r][0], x1 = W.x[r][1], x2 = W.x[r][2];
 #pragma unroll
-    for (int kb = 0; kb < 4; ++kb) {
+    for (int kc = 0; kc < 2; ++kc) {
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const int k = kb * 16 + 4 * q + j;
+        for (int j = 0; j < 8; ++j) {
+            const int k = kc * 32 + 8 * q + j;
             const float z = bf2f(wt[kB1 + k]) + bf2f(wt[kW1 + k]) * x0 + bf2f(wt[kW1 + kH + k]) * x1 +
                             bf2f(wt[kW1 + 2 * kH + k]) * x2;
             zbuf(W, 0)[r][k] = z;
-            a[kb][j] = (short)f2bf(silu_f(z));
+            a[kc][j] = (short)f2bf(silu_f(z));
         }
     }
     for (int L = 2; L <= 4; ++L) {
@@ -147,17 +160,15 @@ template <class WV> __device__ inline float mlp_forward(const MlpDev &M, WV &W)
             const float bias = bf2f(wt[kB(L) + nb * 16 + r]);
             f32x4 acc = {bias, bias, bias, bias};
 #pragma unroll
-            for (int kb = 0; kb < 4; ++kb)
-                acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[kb], M.img[(L - 2) * 1024 + (kb * 4 + nb) * 64 + l], acc, 0,
-                                                                0, 0);
+            for (int kc = 0; kc < 2; ++kc) acc = mfma32(a[kc], M.img[(L - 2) * 512 + (kc * 4 + nb) * 64 + l], acc);
 #pragma unroll
             for (int j = 0; j < 4; ++j) zbuf(W, L - 1)[4 * q + j][nb * 16 + r] = acc[j];
         }
         __syncthreads();
 #pragma unroll
-        for (int kb = 0; kb < 4; ++kb)
+        for (int kc = 0; kc < 2; ++kc)
 #pragma unroll
-            for (int j = 0; j < 4; ++j) a[kb][j] = (short)f2bf(silu_f(zbuf(W, L - 1)[r][kb * 16 + 4 * q + j]));
+            for (int j = 0; j < 8; ++j) a[kc][j] = (short)f2bf(silu_f(zbuf(W, L - 1)[r][kc * 32 + 8 * q + j]));
     }
     float s = 0.0f;
 #pragma unroll
@@ -230,17 +241,17 @@ __device__ inline void mlp_backward(const MlpDev &M, MlpWave &W, float dy, float
 #pragma unroll
         for (int nb = 0; nb < 4; ++nb) dh[nb] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
-        for (int kb = 0; kb < 4; ++kb) {
-            bf16x4 da;
+        for (int kc = 0; kc < 2; ++kc) {
+            s16x8 da;
 #pragma unroll
-            for (int j = 0; j < 4; ++j) da[j] = (short)f2bf(W.dz[r][kb * 16 + 4 * q + j]);
+            for (int j = 0; j < 8; ++j) da[j] = (short)f2bf(W.dz[r][kc * 32 + 8 * q + j]);
 #pragma unroll
             for (int nb = 0; nb < 4; ++nb) {
-                bf16x4 wb;
-                const unsigned short *row = wt + kW(L) + (nb * 16 + r) * kH + kb * 16 + 4 * q;
+                s16x8 wb;
+                const unsigned short *row = wt + kW(L) + (nb * 16 + r) * kH + kc * 32 + 8 * q;
 #pragma unroll
-                for (int j = 0; j < 4; ++j) wb[j] = (short)row[j];
-                dh[nb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(da, wb, dh[nb], 0, 0, 0);
+                for (int j = 0; j < 8; ++j) wb[j] = (short)row[j];
+                dh[nb] = mfma32(da, wb, dh[nb]);
             }
         }
         __syncthreads();
