@@ -182,11 +182,21 @@ __device__ __forceinline__ void block_sum(unsigned (&v)[kNCtr + 1], unsigned (&t
     __syncthreads();
 }
 
-__device__ __forceinline__ void wave_add(unsigned long long *ctr, int slot, unsigned v)
+// Reduce over the block (of kBlock threads, every one of which calls this), one atomic per
+// block.  Atomics on one address are performed one after the other: with one per wave, the
+// hundreds of waves of a processing launch spent several microseconds queued on the counter.
+__device__ __forceinline__ void block_add(unsigned long long *ctr, int slot, unsigned v)
 {
-    // reduce over the wave, one atomic per wave
+    __shared__ unsigned part[kBlock / 64];
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
-    if ((threadIdx.x & 63) == 0 && v) atomicAdd(ctr + slot, (unsigned long long)v);
+    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned t = 0;
+#pragma unroll
+        for (int w = 0; w < kBlock / 64; ++w) t += part[w];
+        if (t) atomicAdd(ctr + slot, (unsigned long long)t);
+    }
 }
 
 // Non-finite inputs (NaN or infinity in a particle's state or in the fields it sees) are not

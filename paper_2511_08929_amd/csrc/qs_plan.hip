@@ -364,7 +364,7 @@ __global__ void __launch_bounds__(kBlock) k_plan_process(const InstDev<R> *inst,
         rank0 += nl;
         __syncthreads();
     }
-    wave_add(Ip->ctr, C_RETIRED, c_ret);
+    block_add(Ip->ctr, C_RETIRED, c_ret);
 }
 
 }  // namespace

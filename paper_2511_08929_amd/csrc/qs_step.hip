@@ -79,7 +79,7 @@ __global__ void __launch_bounds__(kBlock) k_emit_process(LepDev<R> L, PhoDev<R> 
         const bool up = (mask[nchunks + (i >> 6)] >> (i & 63)) & 1ull;
         emit_item<R, FLD>(L, G, F, S, T, lds, i, up, j < nfit ? gbase + j : -1, c_ret);
     }
-    wave_add(ctr, C_RETIRED, c_ret);
+    block_add(ctr, C_RETIRED, c_ret);
 }
 
 // ------------------------------------------------------------------ kernels: photons
