@@ -571,19 +571,21 @@ def extra_grid(q, args, t32, cfg, out, n=1 << 24, steps=200):
                    "photons_emitted": c["n_emit"], "pairs": c["n_pair"], "capacity_overflow": c["n_capacity_overflow"]}
 
 
-def extra_subcycle(q, args, t64, out, n=100_000, steps=200):
+def extra_subcycle(q, args, t64, out, n=100_000, steps=200, n_mixed=100_000):
     """Per-particle sub-cycling in the test-particle workload (W dt ~ 0.95 at the start) against the
-    plain step at dt/16, and the throughput of both (per-species calls replayed from HIP graphs)"""
+    plain step at dt/16, and the throughput of both, per-species calls and merged step replayed
+    from HIP graphs; then a mixed population (the head-on collision at a0 = 300, where few leptons
+    need sub-steps), merged step with and without sub-cycling"""
     import torch
     from paper_2511_08929_amd.sim import Simulation
     w = synth.c1(n=n)
     base = q.QED_ALL & ~q.QED_PAIR
     g0 = w.extra["gamma0"]
 
-    def run(dt, nsteps, flags, every):
+    def run(dt, nsteps, flags, every, merged=False):
         sim = Simulation(t64, cap_e=n, cap_p=1, cap_g=24 * n, track=w.track,
                          fields=q.make_fields(w.field_kind, B0=w.B0), dt=dt, eps_r=synth.EPS_R, seed=w.seed,
-                         flags=flags, k_retire=1e30, device_clock=True)
+                         flags=flags, k_retire=1e30, device_clock=True, merged=merged)
         sim.e.load(w.x, w.p, w.s)
         g = sim.capture(every)
         torch.cuda.synchronize()
@@ -600,18 +602,32 @@ def extra_subcycle(q, args, t64, out, n=100_000, steps=200):
         return dict(loss=float(g0 - gam.mean()), s_beta=float(-s[2].mean()), wall=wall, emitted=c["n_emit"],
                     rate=n * nsteps / wall)
 
-    ref = run(w.dt / 16, 16 * steps, base, 160)
-    plain = run(w.dt, steps, base, 10)
-    sub = run(w.dt, steps, base | q.QED_SUBCYCLE, 10)
+    ref = run(w.dt / 16, 16 * steps, base, 160, merged=True)
+    plain = run(w.dt, steps, base, 10, merged=True)
+    sub_ps = run(w.dt, steps, base | q.QED_SUBCYCLE, 10)
+    sub = run(w.dt, steps, base | q.QED_SUBCYCLE, 10, merged=True)
     res = {"workload": f"test particle in a uniform B (chi = 1, gamma0 = 2000), {n} electrons, {steps} steps of "
                        "1/100 gyro period (W dt ~ 0.95), FP64",
-           "unit": "lepton-steps/s", "value": round(sub["rate"], 1), "plain_value": round(plain["rate"], 1)}
+           "unit": "lepton-steps/s", "value": round(sub["rate"], 1), "per_species_value": round(sub_ps["rate"], 1),
+           "plain_value": round(plain["rate"], 1),
+           "merged_equals_per_species": sub["loss"] == sub_ps["loss"] and sub["s_beta"] == sub_ps["s_beta"]}
     for key, r in (("reference_dt_over_16", ref), ("plain", plain), ("subcycled", sub)):
         res[key] = {"mean_energy_loss": round(r["loss"], 3), "mean_s_beta": round(r["s_beta"], 5),
                     "photons": r["emitted"]}
     for key, r in (("plain", plain), ("subcycled", sub)):
         res[key]["energy_loss_rel_error"] = round(abs(r["loss"] / ref["loss"] - 1), 5)
         res[key]["s_beta_abs_error"] = round(abs(r["s_beta"] - ref["s_beta"]), 5)
+    # mixed population: merged step, sub-cycled against plain, whole collisions from HIP graphs
+    wm = synth.subsample(synth.c2(a0=300.0), np.arange(n_mixed))
+    mixed = {}
+    for key, flags in (("plain", q.QED_ALL), ("subcycled", q.QED_ALL | q.QED_SUBCYCLE)):
+        col = Collision(q, t64, wm, {}, flags=flags)
+        wall, c = col.timed(1, 0)
+        col.close()
+        mixed[key] = {"value": round(work_of(c) / wall, 1), "emitted": c["n_emit"], "pairs": c["n_pair"]}
+    mixed["slowdown"] = round(mixed["plain"]["value"] / mixed["subcycled"]["value"], 3)
+    res["mixed"] = {"workload": f"head-on collision at a0 = 300, {n_mixed} electrons, {COLLISION_STEPS} steps, FP64, "
+                                "merged step", "unit": "particle-QED-steps/s", **mixed}
     out["subcycle"] = res
     log(f"sub-cycling: {res}")
 

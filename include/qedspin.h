@@ -96,10 +96,15 @@ enum {
                                   the sub-steps run in 16 rounds (a lepton takes one in every
                                   16/m-th), each the whole QED part at its current chi and spin, with
                                   Philox channels offset by 16 x round and the round in the photon id;
-                                  a round's photons follow the previous round's.  qed_emit only (not
-                                  in plans: QED_ERR_INVALID there), not with QED_OPTICAL_DEPTH or
-                                  QED_REJECTION (QED_ERR_INVALID).  Leptons below W dt = 0.1 step
-                                  exactly as without it */
+                                  a round's photons follow the previous round's.  qed_emit runs the
+                                  rounds as 16 launches of its three kernels; a plan runs them in its
+                                  own launches (each lepton takes all its sub-steps in the streaming
+                                  pass to count its block's photons per round, and again in the
+                                  processing pass to store them in that order), with the same
+                                  results bit for bit.  Not with QED_OPTICAL_DEPTH or QED_REJECTION
+                                  (QED_ERR_INVALID), nor in a plan with a learned inverse CDF
+                                  (QED_ERR_UNSUPPORTED).  Leptons below W dt = 0.1 step exactly as
+                                  without it */
 };
 
 /* Field models evaluated at each particle. */
@@ -349,11 +354,13 @@ typedef struct qed_plan_s *qed_plan;   /* opaque, library-owned */
 
 /* Copy the instance descriptions (pointers, capacities, fields, parameters) to the device and
    allocate the plan's scratch: two mask planes of one bit per particle slot, per-block counts,
-   per-set bookkeeping and, per instance with grid fields, 32 bytes per grid node.  Allocates
-   device memory and synchronizes the device; afterwards the arrays and counters named here must
-   stay allocated and keep their addresses.  config may be NULL.  QED_ERR_INVALID for a NULL
-   pointer, an inconsistent set (species, missing arrays, dt or eps_r <= 0, no d_clock or
-   d_counters), QED_SUBCYCLE, QED_REJECTION with QED_OPTICAL_DEPTH, or more than 2^24 blocks. */
+   per-set bookkeeping, per instance with grid fields 32 bytes per grid node and, per lepton set
+   with QED_SUBCYCLE, 4 bytes per slot and 64 bytes per streaming block.  Allocates device memory
+   and synchronizes the device; afterwards the arrays and counters named here must stay
+   allocated and keep their addresses.  config may be NULL.  QED_ERR_INVALID for a NULL pointer,
+   an inconsistent set (species, missing arrays, dt or eps_r <= 0, no d_clock or d_counters),
+   QED_SUBCYCLE with QED_REJECTION or QED_OPTICAL_DEPTH, QED_REJECTION with QED_OPTICAL_DEPTH, or
+   more than 2^24 blocks. */
 qed_status qed_plan_create(qed_tables tables, int n_instances, const qed_instance *instances,
                            const qed_plan_config *config, qed_plan *out);
 

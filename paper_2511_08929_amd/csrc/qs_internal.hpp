@@ -65,7 +65,7 @@ inline qed_status qs_launch_status(const char *where)
 // calls and time.
 enum QsKernel {
     K_TABLES = 0, K_PUSH, K_LEPTON_MAIN, K_EMIT_PROCESS, K_PHOTON_MAIN, K_PAIR_PROCESS, K_MASK_EXPAND, K_SET_PREV,
-    K_ALIVE_MASK, K_GATHER, K_SCATTER_BACK, K_PLAN_LEPTON, K_PLAN_PHOTON, K_PLAN_PROCESS, K_GRID_PACK, K_NKERNELS
+    K_ALIVE_MASK, K_GATHER, K_SCATTER_BACK, K_PLAN_LEPTON, K_PLAN_PHOTON, K_PLAN_PROCESS, K_GRID_PACK, K_PLAN_SUB, K_NKERNELS
 };
 extern bool g_qs_profiling;
 // a start and a stop event for one launch of kernel kid (both null if none could be made)

@@ -20,6 +20,9 @@ template <class R> struct LepDev {
     R *x[3], *p[3], *s[3];
     double *tau, *tau_t;       // optical depth and its target (FP64 in both precisions), or NULL
     uint8_t *msub;             // log2 of the sub-steps of this time step (sub-cycling only)
+    uint32_t *sub;             // merged step with sub-cycling: per slot of a lepton with a photon this
+                               // step, (log2 of its sub-steps << 16) | (bit r: a photon in round r);
+                               // NULL: no sub-cycling
 };
 
 template <class R> struct PhoDev {
@@ -316,7 +319,127 @@ template <class R> __device__ __forceinline__ bool photon_candidate(const StepDe
 // ------------------------------------------------------------------ per-particle work
 // The bodies below are shared by the per-species entry points and the merged step.
 
-struct LCount { unsigned prob = 0, chi = 0, norm = 0, step = 0, trans = 0, nonfin = 0; };
+// The emission of a lepton whose decision d (taken at its state p, s) chose the spin branch `up`
+// (NLC section): lambda from the selected inverse CDF (or the accepted rejection candidate), the
+// photon's momentum k and P-vector from the Stokes collapse, and the lepton's recoil and spin
+// collapse, in p and s.  nu_in: nu from the learned inverse CDF instead of the table.  PHOTON =
+// false leaves out the photon's Stokes collapse and P-vector (k and Pv unset), which the lepton's
+// own state does not depend on.
+template <class R, bool PHOTON = true>
+__device__ __forceinline__ void emit_core(const StepDev &S, const TablesDev &T, const LDecide<R> &d, int species,
+                                          int64_t i, bool up, V3<R> &p, V3<R> &s, V3<R> &k, V3<R> &Pv,
+                                          const float *nu_in = nullptr)
+{
+    const double r2 = (double)d.r2;
+    const double rho = log(r2) - log1p(-r2);
+    double lam_d, oml_d;
+    if (S.flags & F_REJECT) {                     // the candidate the streaming pass accepted
+        const double r1 = (double)d.r1;
+        lam_d = r1 * r1 * r1;
+        oml_d = (1.0 - r1) * (1.0 + r1 + r1 * r1);
+    } else {
+        const double nu = nu_in ? (double)*nu_in : icdf_nu(T, up ? 1 : 0, log(d.chi), rho);
+        lam_d = 1.0 / (1.0 + exp(-nu));
+        oml_d = 1.0 / (1.0 + exp(nu));
+    }
+    const double u_d = lam_d / oml_d;
+    k = (R)lam_d * p;
+    R r3, r4;
+    Unif<R>::two(philox_block(S.seed, lepton_id(species, i), S.step, 1u + 16u * (uint32_t)S.sub_round), r3, r4);
+    SpecPt<R> qp;
+    qp.lam = (R)lam_d; qp.oml = (R)oml_d; qp.u = (R)u_d;
+    bessel_ratios<R>(2.0 * u_d / (3.0 * d.chi), bn_of<R>(T), qp.K1, qp.I);
+    const V3<R> si = {dot(s, d.bs.e), dot(s, d.bs.b), dot(s, d.bs.k)};
+    const R w = nlc_w(qp, si.y);
+    const V3<R> g = nlc_g(qp, si);
+    V3<R> sf = si;
+    if (S.flags & F_SPIN) {
+        if (S.flags & F_MEAN) sf = ((R)1 / w) * g;
+        else {
+            const R gn = sqrt_r(dot(g, g));
+            const V3<R> Sq = gn > (R)0 ? ((R)1 / gn) * g : v3<R>(0, 1, 0);
+            const R thr3 = (w - gn) / ((R)2 * w);
+            sf = (r3 < thr3 ? (R)-1 : (R)1) * Sq;
+        }
+    }
+    V3<R> xi = {0, 0, 0};
+    if (PHOTON && (S.flags & F_PHOTON_POL)) {
+        if (S.flags & F_MEAN) xi = ((R)1 / w) * nlc_F(qp, si, v3<R>(0, 0, 0));
+        else {
+            const V3<R> Fv = nlc_F(qp, si, sf);
+            const R F0 = w + dot(sf, g);
+            const R Fn = sqrt_r(dot(Fv, Fv));
+            if (Fn > (R)0) {
+                const R thr4 = (F0 - Fn) / ((R)2 * F0);
+                xi = ((r4 < thr4 ? (R)-1 : (R)1) / Fn) * Fv;
+            }
+        }
+    }
+    if (PHOTON) Pv = stokes_to_P(xi.x, xi.y, xi.z, d.bs);
+    if (S.flags & F_RECOIL) p = (R)oml_d * p;
+    if (S.flags & F_SPIN) s = sf.x * d.bs.e + sf.y * d.bs.b + sf.z * d.bs.k;
+}
+
+// The emitted photon into slot `slot`: a dead slot (id 0) below the retirement energy, counted
+template <class R>
+__device__ __forceinline__ void store_photon(const PhoDev<R> &G, const StepDev &S, int species, int64_t i, int64_t slot,
+                                             V3<R> x, V3<R> k, V3<R> Pv, unsigned &c_ret)
+{
+    if (sqrt(dot(cvt<double>(k), cvt<double>(k))) < S.k_retire) {
+        G.id[slot] = 0;
+        ++c_ret;
+    } else {
+        G.id[slot] = photon_id(species, i, S.step, S.sub_round);
+        stx(G.x, slot, x);
+        st3(G.k, slot, k);
+        st3(G.P, slot, Pv);
+    }
+}
+
+struct LCount {
+    unsigned prob = 0, chi = 0, norm = 0, step = 0, trans = 0, nonfin = 0;
+    unsigned rnd[kSubRounds] = {};          // merged step with sub-cycling: photons per round
+};
+
+// No-transition spin update over dt 2^-msh (non-transition section), renormalized where rounding
+// pushed |s| past 1
+template <class R>
+__device__ __forceinline__ void noemit_spin(const StepDev &S, const LDecide<R> &d, int msh, V3<R> &s, unsigned &norm)
+{
+    const R dt = ldexp((R)S.dt, -msh);
+    const R Wbar = (R)0.5 * (d.Wup + d.Wdn), dW = (R)0.5 * (d.Wup - d.Wdn);
+    const R inv = (R)1 / ((R)1 - d.P);
+    s = inv * (((R)1 - Wbar * dt) * s - (dW * dt) * d.bs.b);
+    const R n2 = dot(s, s);
+    if (n2 > (R)1) {
+        s = rsqrt_r(n2) * s;
+        norm += n2 > (R)1 + norm_count_tol<R>();
+    }
+}
+
+// One sub-step of a sub-cycled lepton in the merged step (decision-making section): the decision
+// d of round S.sub_round (taken at the current p, s) with W dt scaled by 2^-msh (exact), then the
+// emission (true; photon in k, Pv; p, s recoiled and collapsed) or the no-transition update over
+// dt 2^-msh.  With c, the counts lepton_item keeps (chi clamps, P > 1, renormalizations).
+template <class R, bool PHOTON = true>
+__device__ __forceinline__ bool lepton_substep(const StepDev &S, const TablesDev &T, int species, int64_t i, int msh,
+                                               LDecide<R> d, V3<R> &p, V3<R> &s, V3<R> &k, V3<R> &Pv, LCount *c)
+{
+    if (!d.active) return false;
+    d.a = ldexp(d.a, -msh);
+    d.P = ldexp(d.P, -msh);
+    if (c) c->chi += d.clamped_chi;
+    if (d.P <= (R)1 && !(d.r1 < d.P)) {
+        unsigned nrm = 0;
+        if (S.flags & F_NOEMIT) noemit_spin<R>(S, d, msh, s, nrm);
+        if (c) c->norm += nrm;
+        return false;
+    }
+    if (c) c->prob += d.P > (R)1;
+    const R thr = d.P <= (R)1 ? d.a : d.a / d.P;
+    emit_core<R, PHOTON>(S, T, d, species, i, !(d.r1 < thr), p, s, k, Pv);
+    return true;
+}
 
 // Main pass, one lepton: Boris push and T-BMT rotation with the fields at t, the fields at
 // t + dt, chi and the decision (NLC section); a non-emitter gets the no-transition spin update
@@ -368,6 +491,21 @@ __device__ __forceinline__ void lepton_item(const LepDev<R> &L, const FieldDev &
     }
     if (go && (S.flags & F_EMIT)) {
         LDecide<R> d = lepton_decide<R>(S, T, lds, L.species, i, p, s, E, B);
+        if constexpr ((DEC & 8) != 0) {
+            // merged step with sub-cycling: a lepton with more than one sub-step is only flagged
+            // here (no transition, branch bit set: a combination no decision produces) with its
+            // sub-step count; its state after the push is stored below, and the plan's sub-step
+            // launch runs its sub-steps
+            if (L.sub && d.active) {
+                int m = 0;
+                while (m < kSubLog2Max && d.P > (R)kSubWdt * (R)(1 << m)) ++m;
+                if (m > 0) {
+                    L.sub[i] = (unsigned)m << 16;
+                    up = true;
+                    d.active = false;                 // the plain path below is skipped
+                }
+            }
+        }
         if constexpr ((DEC & 4) != 0) {
             if (d.active) {
                 if (S.sub_round == 0) {
@@ -424,18 +562,14 @@ __device__ __forceinline__ void lepton_item(const LepDev<R> &L, const FieldDev &
                 c.prob += d.P > (R)1;
                 const R thr = d.P <= (R)1 ? d.a : d.a / d.P;
                 up = !(d.r1 < thr);
-            }
-            if (noemit_update && (S.flags & F_NOEMIT)) {
-                const R dt = ldexp((R)S.dt, -msh);
-                const R Wbar = (R)0.5 * (d.Wup + d.Wdn), dW = (R)0.5 * (d.Wup - d.Wdn);
-                const R inv = (R)1 / ((R)1 - d.P);
-                s = inv * (((R)1 - Wbar * dt) * s - (dW * dt) * d.bs.b);
-                const R n2 = dot(s, s);
-                if (n2 > (R)1) {
-                    s = rsqrt_r(n2) * s;
-                    c.norm += n2 > (R)1 + norm_count_tol<R>();
+                if constexpr ((DEC & 8) != 0) {
+                    if (L.sub) {                      // one sub-step: its photon is in round 0
+                        L.sub[i] = 1u;
+                        ++c.rnd[0];
+                    }
                 }
             }
+            if (noemit_update && (S.flags & F_NOEMIT)) noemit_spin<R>(S, d, msh, s, c.norm);
         }
     }
     stx(L.x, i, x);
@@ -505,73 +639,18 @@ __device__ __forceinline__ void emit_item(const LepDev<R> &L, const PhoDev<R> &G
     V3<R> E, B;
     eval_fields<R, FLD>(F, (double)x.x, (double)x.y, S.t + S.dt, E, B);
     const LDecide<R> d = lepton_decide<R>(S, T, lds, L.species, i, p, s, E, B);
-    const double r2 = (double)d.r2;
-    const double rho = log(r2) - log1p(-r2);
     if (x_out) {
+        const double r2 = (double)d.r2;
         x_out[0] = (float)log(d.chi);
-        x_out[1] = (float)rho;
+        x_out[1] = (float)(log(r2) - log1p(-r2));
         x_out[2] = up ? 1.0f : -1.0f;
         return;
     }
-    double lam_d, oml_d;
-    if (S.flags & F_REJECT) {                     // the candidate the streaming pass accepted
-        const double r1 = (double)d.r1;
-        lam_d = r1 * r1 * r1;
-        oml_d = (1.0 - r1) * (1.0 + r1 + r1 * r1);
-    } else {
-        const double nu = nu_in ? (double)*nu_in : icdf_nu(T, up ? 1 : 0, log(d.chi), rho);
-        lam_d = 1.0 / (1.0 + exp(-nu));
-        oml_d = 1.0 / (1.0 + exp(nu));
-    }
-    const double u_d = lam_d / oml_d;
-    const V3<R> k = (R)lam_d * p;
-    R r3, r4;
-    Unif<R>::two(philox_block(S.seed, lepton_id(L.species, i), S.step, 1u + 16u * (uint32_t)S.sub_round), r3, r4);
-    SpecPt<R> qp;
-    qp.lam = (R)lam_d; qp.oml = (R)oml_d; qp.u = (R)u_d;
-    bessel_ratios<R>(2.0 * u_d / (3.0 * d.chi), bn_of<R>(T), qp.K1, qp.I);
-    const V3<R> si = {dot(s, d.bs.e), dot(s, d.bs.b), dot(s, d.bs.k)};
-    const R w = nlc_w(qp, si.y);
-    const V3<R> g = nlc_g(qp, si);
-    V3<R> sf = si;
-    if (S.flags & F_SPIN) {
-        if (S.flags & F_MEAN) sf = ((R)1 / w) * g;
-        else {
-            const R gn = sqrt_r(dot(g, g));
-            const V3<R> Sq = gn > (R)0 ? ((R)1 / gn) * g : v3<R>(0, 1, 0);
-            const R thr3 = (w - gn) / ((R)2 * w);
-            sf = (r3 < thr3 ? (R)-1 : (R)1) * Sq;
-        }
-    }
-    V3<R> xi = {0, 0, 0};
-    if (S.flags & F_PHOTON_POL) {
-        if (S.flags & F_MEAN) xi = ((R)1 / w) * nlc_F(qp, si, v3<R>(0, 0, 0));
-        else {
-            const V3<R> Fv = nlc_F(qp, si, sf);
-            const R F0 = w + dot(sf, g);
-            const R Fn = sqrt_r(dot(Fv, Fv));
-            if (Fn > (R)0) {
-                const R thr4 = (F0 - Fn) / ((R)2 * F0);
-                xi = ((r4 < thr4 ? (R)-1 : (R)1) / Fn) * Fv;
-            }
-        }
-    }
-    const V3<R> Pv = stokes_to_P(xi.x, xi.y, xi.z, d.bs);
-    if (S.flags & F_RECOIL) p = (R)oml_d * p;
-    if (S.flags & F_SPIN) s = sf.x * d.bs.e + sf.y * d.bs.b + sf.z * d.bs.k;
+    V3<R> k, Pv;
+    emit_core<R>(S, T, d, L.species, i, up, p, s, k, Pv, nu_in);
     st3(L.p, i, p);
     st3(L.s, i, s);
-    if (slot >= 0) {
-        if (sqrt(dot(cvt<double>(k), cvt<double>(k))) < S.k_retire) {
-            G.id[slot] = 0;
-            ++c_ret;
-        } else {
-            G.id[slot] = photon_id(L.species, i, S.step, S.sub_round);
-            stx(G.x, slot, x);
-            st3(G.k, slot, k);
-            st3(G.P, slot, Pv);
-        }
-    }
+    if (slot >= 0) store_photon<R>(G, S, L.species, i, slot, x, k, Pv, c_ret);
 }
 
 struct GCount { unsigned chi = 0, norm = 0, ret = 0, prob = 0, step = 0, qed = 0, trans = 0, nonfin = 0; };
@@ -816,6 +895,7 @@ template <class R> LepDev<R> lep_dev(const qed_leptons *L)
     d.tau = L->tau;
     d.tau_t = L->tau_target;
     d.msub = nullptr;
+    d.sub = nullptr;
     return d;
 }
 

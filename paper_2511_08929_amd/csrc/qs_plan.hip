@@ -80,6 +80,7 @@ struct PlanDev {
     Snap *snap;                // [ninst]
     MlpDev mlp[2];             // learned inverse CDF of NLC and NBW, used where mlp_on is set
     int mlp_on[2];
+    uint32_t *bsub;            // [lepton streaming blocks][kSubRounds] photons per sub-cycling round
 };
 
 // The streaming pass runs as two launches with their own register allocation: PHO = 0 over the
@@ -124,6 +125,29 @@ k_plan_main(const InstDev<R> *inst, PlanDev P, TablesDev T, int b_first)
         lepton_range<R, DEC, FLD>(L, F, S, T, lds, start, end, mask, sg.nchunks, c);
         v[C_PROB] = c.prob; v[C_CHI] = c.chi; v[C_NORM] = c.norm; v[C_LSTEP] = c.step; v[C_NONFIN] = c.nonfin;
         v[kNCtr] = c.trans;
+        if constexpr ((DEC & 8) != 0) {
+            if (L.sub) {
+                // sub-cycling: the block's photons per round, and its photons in all (not its
+                // transitions) as the count the processing pass ranks and books
+                __shared__ unsigned rsum[kSubRounds][kBlock / 64];
+                unsigned ph = 0;
+#pragma unroll
+                for (int r = 0; r < kSubRounds; ++r) {
+                    unsigned t = c.rnd[r];
+                    ph += t;
+                    for (int o = 32; o > 0; o >>= 1) t += __shfl_xor(t, o);
+                    if ((threadIdx.x & 63) == 0) rsum[r][threadIdx.x >> 6] = t;
+                }
+                v[kNCtr] = ph;
+                __syncthreads();
+                if (threadIdx.x < kSubRounds) {
+                    unsigned t = 0;
+#pragma unroll
+                    for (int w = 0; w < kBlock / 64; ++w) t += rsum[threadIdx.x][w];
+                    P.bsub[(int64_t)b * kSubRounds + threadIdx.x] = t;
+                }
+            }
+        }
     } else {
         const PhoDev<R> G = Ip->G;
         stage_rates<R>(T, 1, lds);
@@ -143,6 +167,123 @@ k_plan_main(const InstDev<R> *inst, PlanDev P, TablesDev T, int b_first)
 }
 
 constexpr int kExpandWords = kBlock; // mask words expanded per round of the process pass, one per thread (16384 slots)
+
+// The set bits of the mask words [c0, c1) (word c0 + t given as m by thread t, 0 past c1) as
+// positions 64 (word - c0) + bit in slot order, into list; returns their number.  Block-wide.
+__device__ __forceinline__ uint32_t mask_list(uint64_t m, uint16_t *list, uint32_t *wtot, uint32_t *nlist)
+{
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    const uint32_t pc = __popcll(m);
+    uint32_t incl = pc;
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t y = __shfl_up(incl, o);
+        if (lane >= o) incl += y;
+    }
+    if (lane == 63) wtot[wid] = incl;
+    __syncthreads();
+    uint32_t pos = incl - pc;
+    for (int w = 0; w < wid; ++w) pos += wtot[w];
+    uint64_t bits = m;
+    while (bits) {
+        const int bit = __ffsll((long long)bits) - 1;
+        list[pos++] = (uint16_t)(threadIdx.x * 64 + bit);
+        bits &= bits - 1;
+    }
+    if (threadIdx.x == kBlock - 1) *nlist = pos;
+    __syncthreads();
+    return *nlist;
+}
+
+// Sub-cycled leptons of the merged step (QED_SUBCYCLE), one block per lepton streaming block,
+// between the streaming and the processing launches.  The block gathers the leptons its
+// streaming block flagged (branch bit without a transition), runs all sub-steps of each on full
+// waves, and books their photons per round: the rounds with a photon in the lepton's sub-step
+// word, its transition bit if it has one, and the block's photon counts per round and in all and
+// its event counts added to the streaming pass's.  A lepton without a photon is finished here
+// (its state after the sub-steps stored); the processing pass runs the others again from their
+// state after the push to place their photons.
+// Its waves hold long dependent chains (the sub-steps of one lepton run one after the other), so it
+// is held to two waves per SIMD in FP64 (258 registers otherwise: one) and three in FP32.
+template <class R>
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 ? 3 : 2)))
+k_plan_sub(const InstDev<R> *inst, PlanDev P, TablesDev T)
+{
+    extern __shared__ unsigned char smem_raw[];
+    R *lds = reinterpret_cast<R *>(smem_raw);
+    __shared__ uint16_t list[kExpandWords * 64];
+    __shared__ uint32_t nlist, wtot[kBlock / 64];
+    __shared__ unsigned red[kSubRounds + 3][kBlock / 64];
+    const int b = blockIdx.x;
+    const SegDev sg = P.seg[P.bseg[b]];
+    const InstDev<R> *Ip = inst + P.binst[b];
+    const LepDev<R> L = sg.kind == 0 ? Ip->E : Ip->P;
+    if (!L.sub) return;                                // block-uniform: this set does not sub-cycle
+    const StepDev S = localize(Ip->S);
+    const FieldDev F = Ip->F;
+    uint64_t *mask = P.mask + sg.mask_off;
+    stage_rates<R>(T, 0, lds);
+    const int64_t n = *L.count;
+    const int64_t B = block_len(n, sg.nb);
+    const int64_t start = (int64_t)(b - sg.b0) * B, end = start + B < n ? start + B : n;
+    LCount c;
+    for (int64_t c0 = start >> 6; c0 < cdiv(end, 64); c0 += kExpandWords) {
+        const int64_t c1 = c0 + kExpandWords < cdiv(end, 64) ? c0 + kExpandWords : cdiv(end, 64);
+        const int64_t cw = c0 + threadIdx.x;
+        const uint32_t nl = mask_list(cw < c1 ? mask[sg.nchunks + cw] & ~mask[cw] : 0ull, list, wtot, &nlist);
+        for (uint32_t j = threadIdx.x; j < nl; j += kBlock) {
+            const int64_t i = c0 * 64 + list[j];
+            const V3<R> x = ldx(L.x, i);
+            V3<R> p = ld3(L.p, i), s = ld3(L.s, i);
+            V3<R> E, Bf;
+            eval_fields<R, kFldGeneral>(F, (double)x.x, (double)x.y, S.t + S.dt, E, Bf);
+            const int m = min((int)(L.sub[i] >> 16), kSubLog2Max);    // the loop's stride stays >= 1
+            unsigned em = 0;
+            for (int r = 0; r < kSubRounds; r += kSubRounds >> m) {
+                StepDev Sr = S;
+                Sr.sub_round = r;
+                const LDecide<R> d = lepton_decide<R>(Sr, T, lds, L.species, i, p, s, E, Bf);
+                V3<R> k, Pv;
+                if (lepton_substep<R, false>(Sr, T, L.species, i, m, d, p, s, k, Pv, &c)) em |= 1u << r;
+            }
+#pragma unroll
+            for (int r = 0; r < kSubRounds; ++r) c.rnd[r] += (em >> r) & 1u;
+            if (em) {
+                L.sub[i] = ((unsigned)m << 16) | em;
+                atomicOr(reinterpret_cast<unsigned long long *>(mask + (i >> 6)), 1ull << (i & 63));
+            } else {
+                st3(L.p, i, p);
+                st3(L.s, i, s);
+            }
+        }
+        __syncthreads();
+    }
+    // the block's bookkeeping (this block alone writes these entries of its streaming block)
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+    for (int k2 = 0; k2 < kSubRounds + 3; ++k2) {
+        unsigned t = k2 < kSubRounds ? c.rnd[k2] : (k2 == kSubRounds ? c.chi : (k2 == kSubRounds + 1 ? c.prob : c.norm));
+        for (int o = 32; o > 0; o >>= 1) t += __shfl_xor(t, o);
+        if (lane == 0) red[k2][wid] = t;
+    }
+    __syncthreads();
+    __shared__ unsigned tot[kSubRounds + 3];
+    if (threadIdx.x < kSubRounds + 3) {
+        unsigned t = 0;
+#pragma unroll
+        for (int w = 0; w < kBlock / 64; ++w) t += red[threadIdx.x][w];
+        tot[threadIdx.x] = t;
+        if (threadIdx.x < kSubRounds) P.bsub[(int64_t)b * kSubRounds + threadIdx.x] += t;
+        else if (threadIdx.x == kSubRounds) P.bctr[(int64_t)b * kNCtr + C_CHI] += t;
+        else if (threadIdx.x == kSubRounds + 1) P.bctr[(int64_t)b * kNCtr + C_PROB] += t;
+        else P.bctr[(int64_t)b * kNCtr + C_NORM] += t;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned ph = 0;
+        for (int r = 0; r < kSubRounds; ++r) ph += tot[r];
+        P.bcnt[b] += ph;
+    }
+}
 
 constexpr int kAggGroups = 16;   // processing blocks per event-count aggregation (fused bookkeeping)
 
@@ -185,7 +326,12 @@ template <> struct SurLds<false> {
 // network on the round's rows (16 per forward pass), and each thread finishes its transition
 // with its nu (coarse table + network), or with the table inverse CDF where the tables judged
 // the network out of bound.
-template <class R, int FLD, bool SUR>
+// SUB: lepton sets with sub-cycling (their LepDev::sub set) place each lepton's photons round by
+// round: all of a set's round-r photons, in lepton order, before its round-r+1 photons, as the
+// per-species calls do.  The streaming pass ran the sub-steps to count each block's photons per
+// round; here every lepton with a photon runs them again from its state after the push (the same
+// draws give the same sub-steps) and stores each photon at its round's offset plus its rank.
+template <class R, int FLD, bool SUR, bool SUB = false>
 __global__ void __launch_bounds__(kBlock) k_plan_process(const InstDev<R> *inst, PlanDev P, TablesDev T, int b_first)
 {
     extern __shared__ unsigned char smem_raw[];
@@ -294,6 +440,52 @@ __global__ void __launch_bounds__(kBlock) k_plan_process(const InstDev<R> *inst,
     const int64_t end = (int64_t)(mb1 - sg.b0) * B < n ? (int64_t)(mb1 - sg.b0) * B : n;
     const bool net = SUR && P.mlp_on[PHO];
     unsigned c_ret = 0;
+    // sub-cycling: this block's first photon of each round, and per entry of a round of the list
+    // its rank among the round's photons of that round of entries
+    __shared__ unsigned long long sub_off[SUB ? kSubRounds : 1];
+    __shared__ unsigned sub_wt[SUB ? kSubRounds : 1][kBlock / 64];
+    __shared__ unsigned sub_pos[SUB ? kSubRounds : 1][SUB ? kBlock : 1];
+    bool subm = false;
+    if constexpr (SUB) {
+        subm = !PHO && (sg.kind == 0 ? Ip->E.sub : Ip->P.sub) != nullptr;        // block-uniform
+        if (subm) {
+            // per round: the set's photons (all its streaming blocks) and those of the blocks before
+            // this one, summed block-wide
+            __shared__ unsigned red32[2 * kSubRounds][kBlock / 64];
+            unsigned tot[kSubRounds] = {}, pre[kSubRounds] = {};
+            for (int bb = sg.b0 + (int)threadIdx.x; bb < sg.b0 + sg.nb; bb += kBlock) {
+                const uint4 *q = reinterpret_cast<const uint4 *>(P.bsub + (int64_t)bb * kSubRounds);
+#pragma unroll
+                for (int u = 0; u < kSubRounds / 4; ++u) {
+                    const uint4 vv = q[u];
+                    tot[4 * u] += vv.x; tot[4 * u + 1] += vv.y; tot[4 * u + 2] += vv.z; tot[4 * u + 3] += vv.w;
+                    if (bb < mb0) {
+                        pre[4 * u] += vv.x; pre[4 * u + 1] += vv.y; pre[4 * u + 2] += vv.z; pre[4 * u + 3] += vv.w;
+                    }
+                }
+            }
+#pragma unroll
+            for (int k2 = 0; k2 < 2 * kSubRounds; ++k2) {
+                unsigned t = k2 < kSubRounds ? tot[k2] : pre[k2 - kSubRounds];
+                for (int o = 32; o > 0; o >>= 1) t += __shfl_xor(t, o);
+                if (lane == 0) red32[k2][wid] = t;
+            }
+            __syncthreads();
+            if (threadIdx.x == 0) {
+                unsigned long long run = 0;
+                for (int r = 0; r < kSubRounds; ++r) {
+                    unsigned long long tr = 0, pr = 0;
+                    for (int w = 0; w < kBlock / 64; ++w) {
+                        tr += red32[r][w];
+                        pr += red32[kSubRounds + r][w];
+                    }
+                    sub_off[r] = run + pr;
+                    run += tr;
+                }
+            }
+            __syncthreads();
+        }
+    }
     for (int64_t c0 = start >> 6; c0 < cdiv(end, 64); c0 += kExpandWords) {
         const int64_t c1 = c0 + kExpandWords < cdiv(end, 64) ? c0 + kExpandWords : cdiv(end, 64);
         // one mask word per thread; positions by a block-wide exclusive scan of the popcounts
@@ -358,6 +550,52 @@ __global__ void __launch_bounds__(kBlock) k_plan_process(const InstDev<R> *inst,
                     __syncthreads();
                 }
             }
+        } else if (SUB && subm) {
+            if constexpr (SUB) {
+                const LepDev<R> &Ls = sg.kind == 0 ? Ip->E : Ip->P;
+                const uint64_t below = (1ull << lane) - 1ull;
+                for (uint32_t j0 = 0; j0 < nl; j0 += kBlock) {
+                    const uint32_t j = j0 + threadIdx.x;
+                    const int64_t i = c0 * 64 + (j < nl ? list[j] : 0);
+                    const uint32_t wsub = j < nl ? Ls.sub[i] : 0u;
+#pragma unroll
+                    for (int r = 0; r < kSubRounds; ++r) {
+                        const uint64_t bm = __ballot((wsub >> r) & 1u);
+                        if (lane == 0) sub_wt[r][wid] = (unsigned)__popcll(bm);
+                        sub_pos[r][threadIdx.x] = (unsigned)__popcll(bm & below);
+                    }
+                    __syncthreads();
+                    if (j < nl) {
+#pragma unroll
+                        for (int r = 0; r < kSubRounds; ++r)
+                            for (int w = 0; w < wid; ++w) sub_pos[r][threadIdx.x] += sub_wt[r][w];
+                        const V3<R> x = ldx(Ls.x, i);
+                        V3<R> p = ld3(Ls.p, i), s = ld3(Ls.s, i);
+                        V3<R> E, B;
+                        eval_fields<R, FLD>(F, (double)x.x, (double)x.y, S.t + S.dt, E, B);
+                        const int m = min((int)(wsub >> 16), kSubLog2Max);      // the loop's stride stays >= 1
+                        for (int r = 0; r < kSubRounds; r += kSubRounds >> m) {
+                            StepDev Sr = S;
+                            Sr.sub_round = r;
+                            const LDecide<R> d = lepton_decide<R>(Sr, Tl, lds, Ls.species, i, p, s, E, B);
+                            V3<R> k, Pv;
+                            if (lepton_substep<R>(Sr, Tl, Ls.species, i, m, d, p, s, k, Pv, nullptr) && ((wsub >> r) & 1u)) {
+                                const int64_t q = (int64_t)(sub_off[r] + sub_pos[r][threadIdx.x]);
+                                if (q < bk.nfit) store_photon<R>(Ip->G, Sr, Ls.species, i, bk.base + q, x, k, Pv, c_ret);
+                            }
+                        }
+                        st3(Ls.p, i, p);
+                        st3(Ls.s, i, s);
+                    }
+                    __syncthreads();
+                    if (threadIdx.x < kSubRounds) {
+                        unsigned t = 0;
+                        for (int w = 0; w < kBlock / 64; ++w) t += sub_wt[threadIdx.x][w];
+                        sub_off[threadIdx.x] += t;
+                    }
+                    __syncthreads();
+                }
+            }
         } else {
             for (uint32_t j = threadIdx.x; j < nl; j += blockDim.x) item(j, nullptr, nullptr);
         }
@@ -376,6 +614,11 @@ struct qed_plan_s {
     SegDev *d_seg;
     uint64_t *d_mask;
     uint32_t *d_bcnt;
+    uint32_t *d_bsub;          // sub-cycling: photons per round of each lepton streaming block
+    uint32_t *d_sub;           // sub-cycling: the sub-step word of every slot of those lepton sets
+    int sub;                   // some instance sub-cycles
+    hipStream_t side;          // sub-cycling: the sub-step launch runs here, beside the photon pass
+    hipEvent_t fork, join;
     uint32_t *d_bctr;
     int *d_bseg, *d_binst;
     int4 *d_pbd;
@@ -413,6 +656,11 @@ void plan_free(qed_plan p)
     (void)hipFree(p->d_seg);
     (void)hipFree(p->d_mask);
     (void)hipFree(p->d_bcnt);
+    (void)hipFree(p->d_bsub);
+    (void)hipFree(p->d_sub);
+    if (p->fork) (void)hipEventDestroy(p->fork);
+    if (p->join) (void)hipEventDestroy(p->join);
+    if (p->side) (void)hipStreamDestroy(p->side);
     (void)hipFree(p->d_bctr);
     (void)hipFree(p->d_bseg);
     (void)hipFree(p->d_binst);
@@ -512,8 +760,32 @@ qed_status plan_create(qed_tables T, int n, const qed_instance *in, int ppb, int
     for (int i = 0; i < n; ++i) {
         if (in[i].params.flags & QED_OPTICAL_DEPTH) p->dec |= 1;
         if (in[i].params.flags & QED_REJECTION) p->dec |= 2;
+        if (in[i].params.flags & QED_SUBCYCLE) p->sub = 1;
         p->fv = std::max(p->fv, field_variant(&in[i].fields));
         p->flep = std::max(p->flep, lepton_variant(&in[i].fields, in[i].params.flags));
+    }
+    // sub-cycling: a word per slot of each sub-cycled lepton set, and per-round block counts
+    if (p->sub && e == hipSuccess) {
+        int64_t words = 0;
+        for (int i = 0; i < n; ++i)
+            if (in[i].params.flags & QED_SUBCYCLE)
+                words += in[i].electrons.capacity + ((in[i].params.flags & QED_PAIR) ? in[i].positrons.capacity : 0);
+        e = hipMalloc((void **)&p->d_sub, sizeof(uint32_t) * (words > 0 ? words : 1));
+        if (e == hipSuccess) e = hipMalloc((void **)&p->d_bsub, sizeof(uint32_t) * kSubRounds * (nblk_lep > 0 ? nblk_lep : 1));
+        // default priority, like every stream of the library
+        if (e == hipSuccess) e = hipStreamCreateWithFlags(&p->side, hipStreamNonBlocking);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&p->fork, hipEventDisableTiming);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&p->join, hipEventDisableTiming);
+        uint32_t *at = p->d_sub;
+        for (int i = 0; i < n && e == hipSuccess; ++i)
+            if (in[i].params.flags & QED_SUBCYCLE) {
+                inst[i].E.sub = at;
+                at += in[i].electrons.capacity;
+                if (in[i].params.flags & QED_PAIR) {
+                    inst[i].P.sub = at;
+                    at += in[i].positrons.capacity;
+                }
+            }
     }
     // grid fields: the plan keeps a node-interleaved copy, refreshed from the caller's arrays at
     // the start of every step, so an interpolation reads four 32-byte corners instead of 24 scalars
@@ -587,6 +859,7 @@ template <class R> qed_status plan_step(qed_plan p, hipStream_t st)
     P.pbd = p->d_pbd;
     P.iseg = p->d_iseg;
     P.snap = p->d_snap;
+    P.bsub = p->d_bsub;
     memset(P.mlp, 0, sizeof(P.mlp));
     P.mlp_on[0] = P.mlp_on[1] = 0;
     const InstDev<R> *inst = (const InstDev<R> *)p->d_inst;
@@ -597,7 +870,10 @@ template <class R> qed_status plan_step(qed_plan p, hipStream_t st)
             QS_LAUNCH(K_GRID_PACK, k_pack_grid, dim3(gb), dim3(kBlock), 0, st, p->h_grid[i], p->h_gn[i]);
         }
     if (p->nblk_lep > 0) {
-        if (p->dec == 3)
+        if (p->sub)
+            QS_LAUNCH(K_PLAN_LEPTON, (k_plan_main<R, 0, 8, kFldGeneral>), dim3(p->nblk_lep), dim3(kBlock), p->lds, st, inst, P,
+                      p->T->dev, 0);
+        else if (p->dec == 3)
             QS_LAUNCH(K_PLAN_LEPTON, (k_plan_main<R, 0, 3, kFldGeneral>), dim3(p->nblk_lep), dim3(kBlock), p->lds, st, inst, P,
                       p->T->dev, 0);
         else if (p->dec == 2)
@@ -616,6 +892,15 @@ template <class R> qed_status plan_step(qed_plan p, hipStream_t st)
             QS_LAUNCH(K_PLAN_LEPTON, (k_plan_main<R, 0, 0, kFldPlain>), dim3(p->nblk_lep), dim3(kBlock), p->lds, st,
                       inst, P, p->T->dev, 0);
     }
+    // sub-cycling: the sub-step launch (latency-bound: long chains on few waves) on the side stream,
+    // beside the photon pass, which does not touch the leptons; joined before the processing
+    const bool fork = p->sub && p->nblk_lep > 0;
+    if (fork) {
+        QS_CHECK(hipEventRecord(p->fork, st));
+        QS_CHECK(hipStreamWaitEvent(p->side, p->fork, 0));
+        QS_LAUNCH(K_PLAN_SUB, k_plan_sub<R>, dim3(p->nblk_lep), dim3(kBlock), p->lds, p->side, inst, P, p->T->dev);
+        QS_CHECK(hipEventRecord(p->join, p->side));
+    }
     if (p->nblk > p->nblk_lep) {
         if (p->fv == kFldGeneral)
             QS_LAUNCH(K_PLAN_PHOTON, (k_plan_main<R, 1, 0, kFldGeneral>), dim3(p->nblk - p->nblk_lep), dim3(kBlock), p->lds,
@@ -627,6 +912,7 @@ template <class R> qed_status plan_step(qed_plan p, hipStream_t st)
             QS_LAUNCH(K_PLAN_PHOTON, (k_plan_main<R, 1, 0, kFldPlain>), dim3(p->nblk - p->nblk_lep), dim3(kBlock), p->lds,
                       st, inst, P, p->T->dev, p->nblk_lep);
     }
+    if (fork) QS_CHECK(hipStreamWaitEvent(st, p->join, 0));
     // processing, with the bookkeeping; a process with a learned inverse CDF evaluates it in the
     // same launch (single precision only)
     const bool sl = p->sur[0] != nullptr, sb = p->sur[1] != nullptr;
@@ -644,6 +930,11 @@ template <class R> qed_status plan_step(qed_plan p, hipStream_t st)
                 return qs_launch_status("qed_plan_step");
             }
         }
+        if (p->sub) {
+            QS_LAUNCH(K_PLAN_PROCESS, (k_plan_process<R, kFldGeneral, false, true>), dim3(p->npb), dim3(kBlock), p->lds, st,
+                      inst, P, p->T->dev, 0);
+            return qs_launch_status("qed_plan_step");
+        }
         auto proc = p->fv == kFldGeneral    ? k_plan_process<R, kFldGeneral, false>
                     : p->fv == kFldRotating ? k_plan_process<R, kFldRotating, false>
                                             : k_plan_process<R, kFldPlain, false>;
@@ -657,7 +948,7 @@ bool instance_ok(const qed_instance *in)
     const uint32_t fl = in->params.flags;
     if (!leptons_ok(&in->electrons) || in->electrons.species != 0 || !tau_ok(&in->electrons, fl)) return false;
     if ((fl & QED_REJECTION) && (fl & QED_OPTICAL_DEPTH)) return false;
-    if (fl & QED_SUBCYCLE) return false;          // sub-cycling runs in the per-species calls only
+    if ((fl & QED_SUBCYCLE) && (fl & (QED_REJECTION | QED_OPTICAL_DEPTH))) return false;
     if (!fields_ok(&in->fields) || !in->d_counters || !in->params.d_clock) return false;
     if (!(in->params.dt > 0.0) || !(in->params.eps_r > 0.0)) return false;
     if ((fl & (QED_EMIT | QED_PAIR)) && !photons_ok(&in->photons)) return false;
@@ -683,6 +974,9 @@ extern "C" qed_status qed_plan_create(qed_tables T, int n_instances, const qed_i
     if ((sn || sb) && T->params.precision != QED_F32) return QED_ERR_UNSUPPORTED;
     if (sn && (qs_surrogate_process(sn) != 0 || qs_surrogate_tables(sn) != T)) return QED_ERR_INVALID;
     if (sb && (qs_surrogate_process(sb) != 1 || qs_surrogate_tables(sb) != T)) return QED_ERR_INVALID;
+    if (sn || sb)
+        for (int i = 0; i < n_instances; ++i)
+            if (instances[i].params.flags & QED_SUBCYCLE) return QED_ERR_UNSUPPORTED;   // tables only
     qs_clear_error();
     if (T->params.precision == QED_F64) return plan_create<double>(T, n_instances, instances, ppb, maxb, group, sn, sb, out);
     return plan_create<float>(T, n_instances, instances, ppb, maxb, group, sn, sb, out);

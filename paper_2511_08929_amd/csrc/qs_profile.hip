@@ -20,7 +20,7 @@ std::vector<hipEvent_t> g_pool;
 const char *const kNames[K_NKERNELS] = {"table_build", "push",       "lepton_main", "emit_process", "photon_main",
                                         "pair_process", "expand",    "clock",       "alive_mask",   "gather",
                                         "scatter_back", "plan_lepton", "plan_photon", "plan_process",
-                                        "grid_pack"};
+                                        "grid_pack", "plan_sub"};
 
 hipEvent_t take()
 {

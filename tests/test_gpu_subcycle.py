@@ -1,7 +1,9 @@
 """GPU parity of the per-particle sub-cycling of the lepton step (QED_SUBCYCLE; decision-making
 section): the test-particle workload (W dt ~ 0.95, 16 sub-steps) over 100 steps and a mixed
 population in one step (1 to 16 sub-steps) in FP64, one step in FP32, and bit equality with the
-plain step where every lepton is below W dt = 0.1, all against the oracle on the same inputs."""
+plain step where every lepton is below W dt = 0.1, all against the oracle on the same inputs; and
+the merged step's single-pass sub-cycling equal to the per-species calls (16 rounds) bit for bit,
+in both precisions, with pair production through the whole head-on pulse, and in graph replay."""
 import math
 
 import numpy as np
@@ -145,16 +147,65 @@ def test_subcycle_below_threshold_is_plain_step(q, gtab64):
         np.testing.assert_array_equal(u, v)
 
 
-def test_subcycle_rejected_in_plans_and_with_other_decisions(q, gtab64):
+def test_subcycle_rejected_with_other_decisions(q, gtab64):
     w = _workload(64, dt=0.1)
-    with pytest.raises(Exception):
-        sim = _sim(q, gtab64, w, 64, 1, 128, q.QED_ALL | q.QED_SUBCYCLE, merged=True)
+    for merged in (False, True):
+        for other in (q.QED_REJECTION, q.QED_OPTICAL_DEPTH):
+            with pytest.raises(Exception):
+                sim = _sim(q, gtab64, w, 64, 1, 128, (q.QED_ALL & ~q.QED_PAIR) | q.QED_SUBCYCLE | other, merged=merged)
+                sim.e.load(w.x, w.p, w.s)
+                sim.step()
+
+
+def _run_both(q, tab, w, cap_e, cap_p, cap_g, flags, steps, every=0, k_retire=None):
+    """the same run through the per-species calls and through the merged step"""
+    import torch
+    out = []
+    for merged in (False, True):
+        sim = _sim(q, tab, w, cap_e, cap_p, cap_g, flags, merged=merged, k_retire=k_retire)
         sim.e.load(w.x, w.p, w.s)
-        sim.step()
-    with pytest.raises(Exception):
-        sim = _sim(q, gtab64, w, 64, 1, 128, (q.QED_ALL & ~q.QED_PAIR) | q.QED_SUBCYCLE | q.QED_REJECTION)
-        sim.e.load(w.x, w.p, w.s)
-        sim.step()
+        for k in range(steps):
+            sim.step()
+            if every and k % every == every - 1:
+                sim.compact()
+        torch.cuda.synchronize()
+        out.append((sim.e.arrays() + sim.p.arrays() + sim.g.arrays(), q.counters_dict(sim.ctr)))
+        del sim
+    return out
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_plan_subcycle_equals_per_species(q, gtab64, gtab32, prec):
+    """The merged step's sub-cycling (the streaming pass runs each lepton's sub-steps to count its
+    block's photons per round, the processing pass runs them again to place the photons) equals
+    the per-species calls (16 rounds of three launches) bit for bit: 1000 leptons with 1 to 16
+    sub-steps, 4 steps, every photon kept."""
+    tab = gtab64 if prec == "fp64" else gtab32
+    n = 1000
+    w = _workload(n, dt=0.5)
+    if prec == "fp32":
+        w.x, w.p, w.s = (a.astype(np.float32).astype(np.float64) for a in (w.x, w.p, w.s))
+    flags = (q.QED_ALL & ~q.QED_PAIR) | q.QED_SUBCYCLE
+    (a, ca), (b, cb) = _run_both(q, tab, w, n, 1, 80 * n, flags, 4, k_retire=0.0)
+    print(prec, "per-species", ca, "merged", cb)
+    assert ca == cb and ca["n_emit"] > 2000
+    ids = a[-1]
+    assert len(np.unique(_rounds(ids[ids != 0]))) == 16
+    for u, v in zip(a, b):
+        np.testing.assert_array_equal(u, v)
+
+
+def test_plan_subcycle_head_on_equals_per_species(q, gtab64):
+    """Sub-cycling with pair production through the whole head-on pulse at a0 = 300 (200
+    electrons, 1700 steps, compaction every 200): the merged step equals the per-species calls bit
+    for bit (the per-species run is compared with the oracle in test_subcycle_head_on_fp64)."""
+    w = synth.subsample(synth.c2(a0=300.0), np.arange(200))
+    cap_g, cap_p = 100_000, 4_000
+    (a, ca), (b, cb) = _run_both(q, gtab64, w, w.n + cap_p, cap_p, cap_g, q.QED_ALL | q.QED_SUBCYCLE, 1700, every=200)
+    print("head-on per-species", ca, "merged", cb)
+    assert ca == cb and ca["n_emit"] > 20_000 and ca["n_pair"] > 100
+    for u, v in zip(a, b):
+        np.testing.assert_array_equal(u, v)
 
 
 def test_subcycle_head_on_fp64(q, gtab64, otables):
@@ -191,16 +242,18 @@ def test_subcycle_head_on_fp64(q, gtab64, otables):
     compare_photons(sim.g.arrays(), ref["G"].arrays(), set(), t, t, what="sub-cycled photons")
 
 
-def test_subcycle_graph_replay_matches_eager(q, gtab64):
-    """The sub-cycled per-species step (16 rounds of three launches per species) captured with a
-    compaction into a HIP graph and replayed several times, with eager work and synchronizations
-    between the replays, equals the eager run bit for bit after every replay."""
+@pytest.mark.parametrize("merged", [False, True], ids=["per_species", "merged"])
+def test_subcycle_graph_replay_matches_eager(q, gtab64, merged):
+    """The sub-cycled step (per-species: 16 rounds of three launches per species; merged: the
+    plan's three launches) captured with a compaction into a HIP graph and replayed several times,
+    with eager work and synchronizations between the replays, equals the eager run bit for bit
+    after every replay."""
     import torch
     w = synth.subsample(synth.c2(a0=300.0), np.arange(1000))
     period = 20
     flags = q.QED_ALL | q.QED_SUBCYCLE
-    a = _sim(q, gtab64, w, w.n + 4000, 4000, 200_000, flags)
-    b = _sim(q, gtab64, w, w.n + 4000, 4000, 200_000, flags)
+    a = _sim(q, gtab64, w, w.n + 4000, 4000, 200_000, flags, merged=merged)
+    b = _sim(q, gtab64, w, w.n + 4000, 4000, 200_000, flags, merged=merged)
     b.clock = torch.zeros(1, dtype=torch.int64, device="cuda")   # b reads step and time from the device
     a.e.load(w.x, w.p, w.s)
     b.e.load(w.x, w.p, w.s)
