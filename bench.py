@@ -84,7 +84,8 @@ class Collision:
                               k_retire=w.k_retire, device_clock=True, merged=True, surrogates=surrogates,
                               particles_per_block=cfg.get("particles_per_block", 0),
                               process_group=cfg.get("process_group", 0),
-                              max_blocks_per_set=cfg.get("max_blocks_per_set", 0))
+                              max_blocks_per_set=cfg.get("max_blocks_per_set", 0),
+                              photon_variant=cfg.get("photon_variant", 0))
         self.sim.e.load(w.x, w.p, w.s)
         self.init = self.sim.snapshot()
         self.graph = None
@@ -147,7 +148,7 @@ def profiled_collision(q, tab, w, cfg):
                      fields=q.make_fields(w.field_kind, a0=w.a0, phase_len=w.phase_len), dt=w.dt, eps_r=synth.EPS_R,
                      seed=w.seed, flags=q.QED_ALL, k_retire=w.k_retire, device_clock=True, merged=True,
                      particles_per_block=cfg.get("particles_per_block", 0), process_group=cfg.get("process_group", 0),
-                     max_blocks_per_set=cfg.get("max_blocks_per_set", 0))
+                     max_blocks_per_set=cfg.get("max_blocks_per_set", 0), photon_variant=cfg.get("photon_variant", 0))
     sim.e.load(w.x, w.p, w.s)
     init = sim.snapshot()
     sim.step()                                   # the plan is built outside the profiled region
@@ -693,7 +694,7 @@ def probe(q, w, cfg, steps):
                      fields=q.make_fields(w.field_kind, a0=w.a0, phase_len=w.phase_len), dt=w.dt, eps_r=synth.EPS_R,
                      seed=w.seed, flags=q.QED_ALL, k_retire=w.k_retire, device_clock=True, merged=True,
                      particles_per_block=cfg["particles_per_block"], process_group=cfg["process_group"],
-                     max_blocks_per_set=cfg["max_blocks_per_set"])
+                     max_blocks_per_set=cfg["max_blocks_per_set"], photon_variant=cfg.get("photon_variant", 0))
     sim.e.load(w.x, w.p, w.s)
     t0 = time.perf_counter()
     for k in range(steps):

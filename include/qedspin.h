@@ -348,6 +348,11 @@ typedef struct {
                                     cells its last qed_surrogate_judge marked, the table inverse
                                     CDF is used. */
     int process_group;           /* streaming blocks whose transitions one block processes, default 4 */
+    int photon_variant;          /* launch variant of the photon streaming pass (single precision, plain
+                                    and plane-wave fields; ignored otherwise): 0 (default) tiles of
+                                    1024 slots at four waves per SIMD, 1 tiles of 512 slots, 2 tiles of
+                                    1024 at three waves per SIMD; QED_ERR_INVALID outside 0..2.  The
+                                    results do not depend on it. */
 } qed_plan_config;
 
 typedef struct qed_plan_s *qed_plan;   /* opaque, library-owned */

@@ -94,7 +94,7 @@ class Instance(C.Structure):
 
 class PlanConfig(C.Structure):
     _fields_ = [("particles_per_block", C.c_int), ("max_blocks_per_set", C.c_int), ("icdf_nlc", C.c_void_p),
-                ("icdf_nbw", C.c_void_p), ("process_group", C.c_int)]
+                ("icdf_nbw", C.c_void_p), ("process_group", C.c_int), ("photon_variant", C.c_int)]
 
 
 class KernelTime(C.Structure):
@@ -449,7 +449,7 @@ class Plan:
     The buffers must stay alive (and unmoved) for the plan's lifetime; step params need d_clock."""
 
     def __init__(self, tables: Tables, instances, particles_per_block=0, max_blocks_per_set=0, surrogates=(None, None),
-                 process_group=0):
+                 process_group=0, photon_variant=0):
         n = len(instances)
         arr = (Instance * n)()
         self._keep = []
@@ -465,7 +465,7 @@ class Plan:
             self._keep.append((e, p, g, ctr))
         cfg = PlanConfig(particles_per_block, max_blocks_per_set,
                          surrogates[0].handle if surrogates[0] is not None else None,
-                         surrogates[1].handle if surrogates[1] is not None else None, process_group)
+                         surrogates[1].handle if surrogates[1] is not None else None, process_group, photon_variant)
         self._keep.append(surrogates)
         h = C.c_void_p()
         _check(lib().qed_plan_create(tables.handle, n, arr, C.byref(cfg), C.byref(h)), "qed_plan_create")

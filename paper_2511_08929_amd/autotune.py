@@ -1,7 +1,8 @@
 """Launch-shape tuner of the merged step (qed_plan_*).
 
-The merged step has three runtime launch parameters (``qed_plan_config``): particles per
-streaming block, streaming blocks per processing block, and the cap on the blocks of one set.
+The merged step has four runtime launch parameters (``qed_plan_config``): particles per
+streaming block, streaming blocks per processing block, the cap on the blocks of one set, and
+the photon pass's compiled variant (tile size and waves per SIMD; single precision).
 Which values are fastest depends on the workload (set sizes, the share of transitions, how
 the photon population grows over a run) and on the device, so they are chosen by timing the
 caller's own workload.  A search is coordinate-wise: each parameter in turn is swept with the
@@ -26,8 +27,9 @@ SPACE = {
     "particles_per_block": (256, 512, 1024, 2048),
     "process_group": (2, 4, 8),
     "max_blocks_per_set": (0, 2048),
+    "photon_variant": (0, 1, 2),   # photon pass: 1024-slot tiles, 512-slot tiles, 1024 at 3 waves/SIMD
 }
-DEFAULT = {"particles_per_block": 1024, "process_group": 4, "max_blocks_per_set": 0}
+DEFAULT = {"particles_per_block": 1024, "process_group": 4, "max_blocks_per_set": 0, "photon_variant": 0}
 
 _memory: dict = {}
 

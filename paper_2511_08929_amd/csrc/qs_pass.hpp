@@ -662,23 +662,23 @@ struct GCount { unsigned chi = 0, norm = 0, ret = 0, prob = 0, step = 0, qed = 0
 // once: decisions at mask[w], branch (plus) at mask[nchunks + w].
 constexpr int kPhoTile = 1024;
 
-template <class R> struct PhoQueue {
-    uint32_t idx[kPhoTile];
-    uint64_t id[kPhoTile];
-    R x[kPhoTile], y[kPhoTile];
-    R k[3][kPhoTile];              // the candidates' momenta, read once in phase 1
-    unsigned long long bits[2][kPhoTile / 64];
+template <class R, int TILE = kPhoTile> struct PhoQueue {
+    uint32_t idx[TILE];
+    uint64_t id[TILE];
+    R x[TILE], y[TILE];
+    R k[3][TILE];                  // the candidates' momenta, read once in phase 1
+    unsigned long long bits[2][TILE / 64];
     uint32_t n;
 };
 
-template <class R, int FLD>
+template <class R, int FLD, int TILE = kPhoTile>
 __device__ __forceinline__ void photon_tile(const PhoDev<R> &G, const FieldDev &F, const StepDev &S, const TablesDev &T,
-                                            const R *lds, PhoQueue<R> &Q, int64_t tile, int64_t tend, uint64_t *mask,
-                                            int64_t nchunks, GCount &c)
+                                            const R *lds, PhoQueue<R, TILE> &Q, int64_t tile, int64_t tend,
+                                            uint64_t *mask, int64_t nchunks, GCount &c)
 {
     const int lane = threadIdx.x & 63;
     const bool qed = (S.flags & F_PAIR) != 0;
-    if (threadIdx.x < kPhoTile / 64) { Q.bits[0][threadIdx.x] = 0ull; Q.bits[1][threadIdx.x] = 0ull; }
+    if (threadIdx.x < TILE / 64) { Q.bits[0][threadIdx.x] = 0ull; Q.bits[1][threadIdx.x] = 0ull; }
     if (threadIdx.x == 0) Q.n = 0;
     __syncthreads();
     // the slots of this thread: all loads first (id, k and x do not wait for each other), then the
@@ -686,7 +686,7 @@ __device__ __forceinline__ void photon_tile(const PhoDev<R> &G, const FieldDev &
     // store once per step, so these reads and the position write are non-temporal: they do not
     // push the lepton arrays and tables out of the caches (the sparse P-vector accesses of phase
     // 2 stay ordinary: non-temporal partial writes cost more there)
-    constexpr int kPer = kPhoTile / kBlock;
+    constexpr int kPer = TILE / kBlock;
     uint64_t idv[kPer];
     V3<R> kv[kPer], xv[kPer];
 #pragma unroll

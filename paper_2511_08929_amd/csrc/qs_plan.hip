@@ -86,15 +86,20 @@ struct PlanDev {
 // The streaming pass runs as two launches with their own register allocation: PHO = 0 over the
 // lepton segments (blocks [0, nblk_lep)), PHO = 1 over the photon segments (the rest).  Waves per
 // SIMD in FP32: three for the photon pass of the general field variant (which spills at four),
-// four otherwise.
-template <class R, int PHO, int DEC, int FLD>
+// four otherwise.  PV, the photon pass's launch variant (a tuning dimension of the plan): 0 tiles
+// of 1024 slots, 1 tiles of 512 (half the LDS queue), 2 tiles of 1024 at three waves per SIMD
+// (room for 168 registers instead of 128).
+template <int PV> constexpr int pho_tile() { return PV == 1 ? 512 : kPhoTile; }
+
+template <class R, int PHO, int DEC, int FLD, int PV = 0>
 __global__ void __launch_bounds__(kBlock)
-__attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 ? ((PHO == 1 && FLD == kFldGeneral) ? 3 : 4) : 1)))
+__attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 ? ((PHO == 1 && (FLD == kFldGeneral || PV == 2)) ? 3 : 4) : 1)))
 k_plan_main(const InstDev<R> *inst, PlanDev P, TablesDev T, int b_first)
 {
     extern __shared__ unsigned char smem_raw[];
     R *lds = reinterpret_cast<R *>(smem_raw);
-    __shared__ PhoQueue<R> Q;
+    constexpr int TILE = pho_tile<PV>();
+    __shared__ PhoQueue<R, TILE> Q;
     __shared__ unsigned tot[kNCtr + 1];
     const int b = b_first + blockIdx.x;
     const int sj = P.bseg[b];
@@ -155,9 +160,9 @@ k_plan_main(const InstDev<R> *inst, PlanDev P, TablesDev T, int b_first)
         const int64_t B = block_len(n, sg.nb);
         const int64_t start = (int64_t)(b - sg.b0) * B, end = start + B < n ? start + B : n;
         GCount c;
-        for (int64_t tile = start; tile < end; tile += kPhoTile)
-            photon_tile<R, FLD>(G, F, S, T, lds, Q, tile, tile + kPhoTile < end ? tile + kPhoTile : end, mask, sg.nchunks,
-                                 c);
+        for (int64_t tile = start; tile < end; tile += TILE)
+            photon_tile<R, FLD, TILE>(G, F, S, T, lds, Q, tile, tile + TILE < end ? tile + TILE : end, mask, sg.nchunks,
+                                       c);
         v[C_PROB] = c.prob; v[C_CHI] = c.chi; v[C_NORM] = c.norm; v[C_RETIRED] = c.ret; v[C_GSTEP] = c.step;
         v[C_GQED] = c.qed; v[C_NONFIN] = c.nonfin; v[kNCtr] = c.trans;
     }
@@ -629,6 +634,7 @@ struct qed_plan_s {
     float4 **h_gn;             // [ninst] the plan's interleaved copy of that grid, or NULL
     int dec;                   // decision variants needed (bit 0: optical depth, bit 1: rejection)
     int fv;                    // field-model variant the instances need (the largest of field_variant)
+    int pv;                    // photon pass launch variant (single precision, plain fields)
     int flep;                  // the lepton pass's (the largest of lepton_variant)
     size_t lds;
 };
@@ -688,23 +694,26 @@ __global__ void __launch_bounds__(kBlock) k_pack_grid(FieldDev f, float4 *gn)
 // Default cap on the blocks of one set: one resident round of the photon streaming kernel on
 // this device (compute units x blocks per compute unit at its register and LDS use), so that a
 // set's blocks all run at once instead of in a ragged second round.
-template <class R> int resident_blocks(size_t lds)
+template <class R> int resident_blocks(size_t lds, int pv)
 {
     int dev = 0, cus = 0, per_cu = 0;
     if (hipGetDevice(&dev) != hipSuccess) return kMaxGrid;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0) return kMaxGrid;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_plan_main<R, 1, 0, kFldPlain>, kBlock, lds) != hipSuccess ||
-        per_cu <= 0)
-        return kMaxGrid;
+    hipError_t e;
+    if (pv == 1) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_plan_main<R, 1, 0, kFldPlain, 1>, kBlock, lds);
+    else if (pv == 2) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_plan_main<R, 1, 0, kFldPlain, 2>, kBlock, lds);
+    else e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_plan_main<R, 1, 0, kFldPlain>, kBlock, lds);
+    if (e != hipSuccess || per_cu <= 0) return kMaxGrid;
     return cus * per_cu;
 }
 
 template <class R>
-qed_status plan_create(qed_tables T, int n, const qed_instance *in, int ppb, int maxb, int group, qed_surrogate s_nlc,
-                       qed_surrogate s_nbw, qed_plan *out)
+qed_status plan_create(qed_tables T, int n, const qed_instance *in, int ppb, int maxb, int group, int pv,
+                       qed_surrogate s_nlc, qed_surrogate s_nbw, qed_plan *out)
 {
     const size_t lds = sizeof(R) * 2 * (T->dev.n_chi[0] > T->dev.n_chi[1] ? T->dev.n_chi[0] : T->dev.n_chi[1]);
-    if (maxb <= 0) maxb = resident_blocks<R>(lds);
+    if (sizeof(R) != 4) pv = 0;                        // the variants are compiled in single precision
+    if (maxb <= 0) maxb = resident_blocks<R>(lds, pv);
     std::vector<InstDev<R>> inst(n);
     std::vector<SegDev> seg;
     int64_t nblk = 0, mask_words = 0;
@@ -747,6 +756,7 @@ qed_status plan_create(qed_tables T, int n, const qed_instance *in, int ppb, int
     p->npb_lep = (int)npb_lep;
     p->group = group;
     p->lds = lds;
+    p->pv = pv;
     hipError_t e = hipMalloc(&p->d_inst, sizeof(InstDev<R>) * n);
     if (e == hipSuccess) e = hipMalloc((void **)&p->d_seg, sizeof(SegDev) * seg.size());
     if (e == hipSuccess) e = hipMalloc((void **)&p->d_mask, sizeof(uint64_t) * mask_words);
@@ -908,6 +918,12 @@ template <class R> qed_status plan_step(qed_plan p, hipStream_t st)
         else if (p->fv == kFldRotating)
             QS_LAUNCH(K_PLAN_PHOTON, (k_plan_main<R, 1, 0, kFldRotating>), dim3(p->nblk - p->nblk_lep), dim3(kBlock),
                       p->lds, st, inst, P, p->T->dev, p->nblk_lep);
+        else if (p->pv == 1)
+            QS_LAUNCH(K_PLAN_PHOTON, (k_plan_main<R, 1, 0, kFldPlain, 1>), dim3(p->nblk - p->nblk_lep), dim3(kBlock),
+                      p->lds, st, inst, P, p->T->dev, p->nblk_lep);
+        else if (p->pv == 2)
+            QS_LAUNCH(K_PLAN_PHOTON, (k_plan_main<R, 1, 0, kFldPlain, 2>), dim3(p->nblk - p->nblk_lep), dim3(kBlock),
+                      p->lds, st, inst, P, p->T->dev, p->nblk_lep);
         else
             QS_LAUNCH(K_PLAN_PHOTON, (k_plan_main<R, 1, 0, kFldPlain>), dim3(p->nblk - p->nblk_lep), dim3(kBlock), p->lds,
                       st, inst, P, p->T->dev, p->nblk_lep);
@@ -969,6 +985,8 @@ extern "C" qed_status qed_plan_create(qed_tables T, int n_instances, const qed_i
     const int ppb = config && config->particles_per_block > 0 ? config->particles_per_block : kBlock;
     const int maxb = config && config->max_blocks_per_set > 0 ? config->max_blocks_per_set : 0;   // 0: one resident round
     const int group = config && config->process_group > 0 ? config->process_group : 4;
+    const int pv = config ? config->photon_variant : 0;
+    if (pv < 0 || pv > 2) return QED_ERR_INVALID;
     qed_surrogate sn = config ? config->icdf_nlc : nullptr, sb = config ? config->icdf_nbw : nullptr;
     // the networks are trained for 24-bit uniforms (single precision) on these tables' ranges
     if ((sn || sb) && T->params.precision != QED_F32) return QED_ERR_UNSUPPORTED;
@@ -978,8 +996,9 @@ extern "C" qed_status qed_plan_create(qed_tables T, int n_instances, const qed_i
         for (int i = 0; i < n_instances; ++i)
             if (instances[i].params.flags & QED_SUBCYCLE) return QED_ERR_UNSUPPORTED;   // tables only
     qs_clear_error();
-    if (T->params.precision == QED_F64) return plan_create<double>(T, n_instances, instances, ppb, maxb, group, sn, sb, out);
-    return plan_create<float>(T, n_instances, instances, ppb, maxb, group, sn, sb, out);
+    if (T->params.precision == QED_F64)
+        return plan_create<double>(T, n_instances, instances, ppb, maxb, group, pv, sn, sb, out);
+    return plan_create<float>(T, n_instances, instances, ppb, maxb, group, pv, sn, sb, out);
 }
 
 extern "C" qed_status qed_plan_step(qed_plan plan, qed_stream stream)

@@ -14,7 +14,7 @@ from __future__ import annotations
 
 import math
 
-from . import (ALPHA, QED_F64, QED_PAIR, LeptonBuffers, PhotonBuffers, Plan, Tables, make_fields, make_step,
+from . import (ALPHA, QED_F32, QED_F64, QED_PAIR, LeptonBuffers, PhotonBuffers, Plan, Tables, make_fields, make_step,
                new_counters, new_workspace, qed_clock_advance, qed_compact, qed_compact_workspace_size, qed_emit,
                qed_pair, qed_workspace_size)
 
@@ -23,7 +23,8 @@ class Simulation:
     def __init__(self, tables: Tables, *, cap_e, cap_p, cap_g, track, fields, dt, eps_r, seed, flags,
                  k_retire=0.0, t0=0.0, a_e=ALPHA / (2 * math.pi), chi_e_min=1e-3, chi_e_max=1e2, chi_g_min=0.05,
                  chi_g_max=1e2, device="cuda", device_clock=False, merged=False, particles_per_block=0,
-                 max_blocks_per_set=0, process_group=0, optical_depth=False, surrogates=(None, None)):
+                 max_blocks_per_set=0, process_group=0, optical_depth=False, surrogates=(None, None),
+                 photon_variant=0):
         import torch
         self.tables = tables
         self.dtype = torch.float64 if tables.precision == QED_F64 else torch.float32
@@ -43,6 +44,7 @@ class Simulation:
         merged = merged or any(x is not None for x in surrogates)     # the learned inverse CDF runs in plans
         self.clock = torch.zeros(1, dtype=torch.int64, device=device) if (device_clock or merged) else None
         self.merged, self.ppb, self.maxb, self.group = merged, particles_per_block, max_blocks_per_set, process_group
+        self.pvar = photon_variant
         self.surrogates = surrogates
         self.plan = None
 
@@ -67,9 +69,9 @@ class Simulation:
         if self.merged and self.plan is None:
             self.plan = Plan(self.tables, [(self.e, self.p, self.g, self.fields, self._params(), self.ctr)],
                              particles_per_block=self.ppb, max_blocks_per_set=self.maxb,
-                             surrogates=self.surrogates, process_group=self.group)
+                             surrogates=self.surrogates, process_group=self.group, photon_variant=self.pvar)
 
-    def set_launch_config(self, particles_per_block=0, process_group=0, max_blocks_per_set=0):
+    def set_launch_config(self, particles_per_block=0, process_group=0, max_blocks_per_set=0, photon_variant=0):
         """Launch shape of the merged step (0: the library's default).  The plan is rebuilt at the
         next step, so graphs captured before this call must not be replayed after it."""
         import torch
@@ -78,6 +80,7 @@ class Simulation:
             self.plan.close()
             self.plan = None
         self.ppb, self.group, self.maxb = particles_per_block, process_group, max_blocks_per_set
+        self.pvar = photon_variant
 
     def _enqueue_step(self, stream=None):
         if self.merged:
@@ -162,6 +165,9 @@ class Simulation:
         assert self.merged and steps % every == 0
         snap = self.snapshot()
         key = workload_key or self.workload_key(steps)
+        space = dict(autotune.SPACE if space is None else space)
+        if self.tables.precision != QED_F32:
+            space.pop("photon_variant", None)      # the photon pass variants exist in single precision only
 
         def run(cfg):
             import time
@@ -190,7 +196,7 @@ class Batch:
     cap_e, cap_p, cap_g, track, fields, dt, eps_r, seed, flags and optionally k_retire, t0, a_e."""
 
     def __init__(self, tables: Tables, specs, device="cuda", particles_per_block=0, max_blocks_per_set=0,
-                 process_group=0):
+                 process_group=0, photon_variant=0):
         import torch
         self.tables = tables
         self.dtype = torch.float64 if tables.precision == QED_F64 else torch.float32
@@ -208,15 +214,17 @@ class Batch:
             self.inst.append(dict(e=e, p=p, g=g, clock=clock, ctr=ctr, fields=f, step=step))
         self.ws = new_workspace(max(qed_compact_workspace_size(i["g"], tables.precision) for i in self.inst), device)
         self.ppb, self.maxb, self.group = particles_per_block, max_blocks_per_set, process_group
+        self.pvar = photon_variant
         self.plan = None
         self.n = 0
 
     def _ensure_plan(self):
         if self.plan is None:
             self.plan = Plan(self.tables, [(i["e"], i["p"], i["g"], i["fields"], i["step"], i["ctr"]) for i in self.inst],
-                             particles_per_block=self.ppb, max_blocks_per_set=self.maxb, process_group=self.group)
+                             particles_per_block=self.ppb, max_blocks_per_set=self.maxb, process_group=self.group,
+                             photon_variant=self.pvar)
 
-    def set_launch_config(self, particles_per_block=0, process_group=0, max_blocks_per_set=0):
+    def set_launch_config(self, particles_per_block=0, process_group=0, max_blocks_per_set=0, photon_variant=0):
         """As Simulation.set_launch_config: the plan is rebuilt at the next step."""
         import torch
         if self.plan is not None:
@@ -224,6 +232,7 @@ class Batch:
             self.plan.close()
             self.plan = None
         self.ppb, self.group, self.maxb = particles_per_block, process_group, max_blocks_per_set
+        self.pvar = photon_variant
 
     def snapshot(self, device=True):
         return [_snapshot(i["e"], i["p"], i["g"], i["ctr"], self.n, device) for i in self.inst]
@@ -245,6 +254,9 @@ class Batch:
         assert steps % every == 0
         snap = self.snapshot()
         key = workload_key or self.workload_key(steps)
+        space = dict(autotune.SPACE if space is None else space)
+        if self.tables.precision != QED_F32:
+            space.pop("photon_variant", None)      # the photon pass variants exist in single precision only
 
         def run(cfg):
             import time

@@ -31,13 +31,13 @@ def tabs(q):
     return {"fp64": q.Tables(precision=q.QED_F64), "fp32": q.Tables(precision=q.QED_F32)}
 
 
-def _sim(q, tab, w, merged, cap_e, cap_p, cap_g, flags=None, ppb=0, tau=False, maxb=0, fields=None):
+def _sim(q, tab, w, merged, cap_e, cap_p, cap_g, flags=None, ppb=0, tau=False, maxb=0, fields=None, pvar=0):
     from paper_2511_08929_amd.sim import Simulation
     f = fields or q.make_fields(w.field_kind, E0=w.E0, B0=w.B0, a0=w.a0, phase_len=w.phase_len)
     sim = Simulation(tab, cap_e=cap_e, cap_p=cap_p, cap_g=cap_g, track=w.track, fields=f, dt=w.dt, eps_r=EPS,
                      seed=w.seed, flags=q.QED_ALL if flags is None else flags, k_retire=w.k_retire,
                      device_clock=True, merged=merged, particles_per_block=ppb, optical_depth=tau,
-                     max_blocks_per_set=maxb)
+                     max_blocks_per_set=maxb, photon_variant=pvar)
     sim.e.load(w.x, w.p, w.s)
     return sim
 
@@ -75,6 +75,32 @@ def test_plan_equals_per_species_head_on(q, tabs, prec):
     print(prec, c)
     assert c["n_emit"] > 10_000 and c["n_pair"] > 0 and c["n_retired"] > 0
     assert int(a.clock.item()) == int(b.clock.item()) == 1000
+
+
+@pytest.mark.parametrize("pvar", [1, 2])
+def test_plan_photon_variants_equal_per_species(q, tabs, pvar):
+    """The photon pass's launch variants (512-slot tiles; 1024-slot tiles at three waves per SIMD)
+    give the per-species results bit for bit: 2000 electrons of the head-on collision in FP32
+    through the pulse, compaction every 25 steps, with many photon tiles per block (particles per
+    block 4096)."""
+    import torch
+    w = synth.subsample(synth.c2(), np.arange(2000))
+    a = _sim(q, tabs["fp32"], w, False, w.n + 3000, 3000, 150_000)
+    b = _sim(q, tabs["fp32"], w, True, w.n + 3000, 3000, 150_000, ppb=4096, pvar=pvar)
+    for k in range(1, 1001):
+        a.step(); b.step()
+        if k % 25 == 0:
+            a.compact(); b.compact()
+        if k % 250 == 0:
+            torch.cuda.synchronize()
+            _assert_same(_state(q, a), _state(q, b), f"variant {pvar} step {k}")
+    assert q.counters_dict(b.ctr)["n_photon_steps"] > 1_000_000
+
+
+def test_plan_rejects_unknown_photon_variant(q, tabs):
+    w = synth.subsample(synth.c2(), np.arange(64))
+    with pytest.raises(Exception):
+        _sim(q, tabs["fp32"], w, True, 1000, 1000, 1000, pvar=3).step()
 
 
 def test_plan_equals_per_species_pair_overflow(q, tabs):
