@@ -351,8 +351,9 @@ typedef struct {
     int photon_variant;          /* launch variant of the photon streaming pass (single precision, plain
                                     and plane-wave fields; ignored otherwise): 0 (default) tiles of
                                     1024 slots at four waves per SIMD, 1 tiles of 512 slots, 2 tiles of
-                                    1024 at three waves per SIMD; QED_ERR_INVALID outside 0..2.  The
-                                    results do not depend on it. */
+                                    1024 at three waves per SIMD with the next tile's reads issued
+                                    during the current tile's QED part; QED_ERR_INVALID outside 0..2.
+                                    The results do not depend on it. */
 } qed_plan_config;
 
 typedef struct qed_plan_s *qed_plan;   /* opaque, library-owned */

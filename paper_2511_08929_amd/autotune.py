@@ -27,7 +27,7 @@ SPACE = {
     "particles_per_block": (256, 512, 1024, 2048),
     "process_group": (2, 4, 8),
     "max_blocks_per_set": (0, 2048),
-    "photon_variant": (0, 1, 2),   # photon pass: 1024-slot tiles, 512-slot tiles, 1024 at 3 waves/SIMD
+    "photon_variant": (0, 1, 2),   # photon pass: 1024-slot tiles, 512-slot tiles, 1024 prefetching at 3 waves/SIMD
 }
 DEFAULT = {"particles_per_block": 1024, "process_group": 4, "max_blocks_per_set": 0, "photon_variant": 0}
 

@@ -671,10 +671,40 @@ template <class R, int TILE = kPhoTile> struct PhoQueue {
     uint32_t n;
 };
 
-template <class R, int FLD, int TILE = kPhoTile>
+// A tile's phase-1 inputs per thread (slots tile + 64-slot group of its wave + u kBlock + lane)
+template <class R, int TILE> struct TileIn {
+    uint64_t id[TILE / kBlock];
+    V3<R> k[TILE / kBlock], x[TILE / kBlock];
+};
+
+// The reads of id, k and x of the tile [tile, tend) (non-temporal: the pass streams the store once)
+template <class R, int TILE>
+__device__ __forceinline__ void photon_tile_load(const PhoDev<R> &G, int64_t tile, int64_t tend, TileIn<R, TILE> &in)
+{
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int u = 0; u < TILE / kBlock; ++u) {
+        const int64_t i = tile + (threadIdx.x & ~63) + (int64_t)u * kBlock + lane;
+        in.id[u] = 0;
+        if (i < tend) {
+            in.id[u] = __builtin_nontemporal_load(&G.id[i]);
+            in.k[u] = {__builtin_nontemporal_load(&G.k[0][i]), __builtin_nontemporal_load(&G.k[1][i]),
+                       __builtin_nontemporal_load(&G.k[2][i])};
+            in.x[u] = {G.x[0] ? __builtin_nontemporal_load(&G.x[0][i]) : (R)0,
+                       G.x[1] ? __builtin_nontemporal_load(&G.x[1][i]) : (R)0,
+                       G.x[2] ? __builtin_nontemporal_load(&G.x[2][i]) : (R)0};
+        }
+    }
+}
+
+// PREF: the tile's inputs are in *pre already (photon_tile_load), and once phase 1 has used them
+// the next tile's [next, next_end) (next >= 0) are loaded into it, so that their reads are in
+// flight during phase 2; otherwise the tile loads its own.
+template <class R, int FLD, int TILE = kPhoTile, bool PREF = false>
 __device__ __forceinline__ void photon_tile(const PhoDev<R> &G, const FieldDev &F, const StepDev &S, const TablesDev &T,
                                             const R *lds, PhoQueue<R, TILE> &Q, int64_t tile, int64_t tend,
-                                            uint64_t *mask, int64_t nchunks, GCount &c)
+                                            uint64_t *mask, int64_t nchunks, GCount &c, TileIn<R, TILE> *pre = nullptr,
+                                            int64_t next = -1, int64_t next_end = -1)
 {
     const int lane = threadIdx.x & 63;
     const bool qed = (S.flags & F_PAIR) != 0;
@@ -687,21 +717,11 @@ __device__ __forceinline__ void photon_tile(const PhoDev<R> &G, const FieldDev &
     // push the lepton arrays and tables out of the caches (the sparse P-vector accesses of phase
     // 2 stay ordinary: non-temporal partial writes cost more there)
     constexpr int kPer = TILE / kBlock;
-    uint64_t idv[kPer];
-    V3<R> kv[kPer], xv[kPer];
-#pragma unroll
-    for (int u = 0; u < kPer; ++u) {
-        const int64_t i = tile + (threadIdx.x & ~63) + (int64_t)u * kBlock + lane;
-        idv[u] = 0;
-        if (i < tend) {
-            idv[u] = __builtin_nontemporal_load(&G.id[i]);
-            kv[u] = {__builtin_nontemporal_load(&G.k[0][i]), __builtin_nontemporal_load(&G.k[1][i]),
-                     __builtin_nontemporal_load(&G.k[2][i])};
-            xv[u] = {G.x[0] ? __builtin_nontemporal_load(&G.x[0][i]) : (R)0,
-                     G.x[1] ? __builtin_nontemporal_load(&G.x[1][i]) : (R)0,
-                     G.x[2] ? __builtin_nontemporal_load(&G.x[2][i]) : (R)0};
-        }
-    }
+    TileIn<R, TILE> own;
+    if constexpr (!PREF) photon_tile_load<R, TILE>(G, tile, tend, own);
+    TileIn<R, TILE> &in = PREF ? *pre : own;
+    const uint64_t *idv = in.id;
+    const V3<R> *kv = in.k, *xv = in.x;
 #pragma unroll
     for (int u = 0; u < kPer; ++u) {
         const int64_t base = tile + (threadIdx.x & ~63) + (int64_t)u * kBlock;
@@ -757,6 +777,9 @@ __device__ __forceinline__ void photon_tile(const PhoDev<R> &G, const FieldDev &
         }
     }
     __syncthreads();
+    if constexpr (PREF) {
+        if (next >= 0) photon_tile_load<R, TILE>(G, next, next_end, in);   // phase 1 is done with it
+    }
     const uint32_t nq = Q.n;
     for (uint32_t j = threadIdx.x; j < nq; j += blockDim.x) {
         const uint32_t o = Q.idx[j];

@@ -87,13 +87,15 @@ struct PlanDev {
 // lepton segments (blocks [0, nblk_lep)), PHO = 1 over the photon segments (the rest).  Waves per
 // SIMD in FP32: three for the photon pass of the general field variant (which spills at four),
 // four otherwise.  PV, the photon pass's launch variant (a tuning dimension of the plan): 0 tiles
-// of 1024 slots, 1 tiles of 512 (half the LDS queue), 2 tiles of 1024 at three waves per SIMD
-// (room for 168 registers instead of 128).
+// of 1024 slots; 1 tiles of 512 (half the LDS queue); 2 tiles of 1024 at three waves per SIMD
+// (up to 168 registers) with the next tile's reads issued before the current tile's phase 2,
+// which needs the room (at four waves the reads held through phase 2 spill).
 template <int PV> constexpr int pho_tile() { return PV == 1 ? 512 : kPhoTile; }
 
 template <class R, int PHO, int DEC, int FLD, int PV = 0>
 __global__ void __launch_bounds__(kBlock)
-__attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 ? ((PHO == 1 && (FLD == kFldGeneral || PV == 2)) ? 3 : 4) : 1)))
+__attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 ? ((PHO == 1 && (FLD == kFldGeneral || PV == 2)) ? 3 : 4) : 1,
+                                   PV == 2 ? 3 : 8)))
 k_plan_main(const InstDev<R> *inst, PlanDev P, TablesDev T, int b_first)
 {
     extern __shared__ unsigned char smem_raw[];
@@ -160,9 +162,19 @@ k_plan_main(const InstDev<R> *inst, PlanDev P, TablesDev T, int b_first)
         const int64_t B = block_len(n, sg.nb);
         const int64_t start = (int64_t)(b - sg.b0) * B, end = start + B < n ? start + B : n;
         GCount c;
-        for (int64_t tile = start; tile < end; tile += TILE)
-            photon_tile<R, FLD, TILE>(G, F, S, T, lds, Q, tile, tile + TILE < end ? tile + TILE : end, mask, sg.nchunks,
-                                       c);
+        if constexpr (PV == 2) {                      // the next tile's reads issued early
+            TileIn<R, TILE> in;
+            if (start < end) photon_tile_load<R, TILE>(G, start, start + TILE < end ? start + TILE : end, in);
+            for (int64_t tile = start; tile < end; tile += TILE) {
+                const int64_t nt = tile + TILE;
+                photon_tile<R, FLD, TILE, true>(G, F, S, T, lds, Q, tile, nt < end ? nt : end, mask, sg.nchunks, c, &in,
+                                                nt < end ? nt : -1, nt + TILE < end ? nt + TILE : end);
+            }
+        } else {
+            for (int64_t tile = start; tile < end; tile += TILE)
+                photon_tile<R, FLD, TILE>(G, F, S, T, lds, Q, tile, tile + TILE < end ? tile + TILE : end, mask,
+                                          sg.nchunks, c);
+        }
         v[C_PROB] = c.prob; v[C_CHI] = c.chi; v[C_NORM] = c.norm; v[C_RETIRED] = c.ret; v[C_GSTEP] = c.step;
         v[C_GQED] = c.qed; v[C_NONFIN] = c.nonfin; v[kNCtr] = c.trans;
     }
@@ -702,6 +714,7 @@ template <class R> int resident_blocks(size_t lds, int pv)
     hipError_t e;
     if (pv == 1) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_plan_main<R, 1, 0, kFldPlain, 1>, kBlock, lds);
     else if (pv == 2) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_plan_main<R, 1, 0, kFldPlain, 2>, kBlock, lds);
+
     else e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_plan_main<R, 1, 0, kFldPlain>, kBlock, lds);
     if (e != hipSuccess || per_cu <= 0) return kMaxGrid;
     return cus * per_cu;
@@ -924,6 +937,7 @@ template <class R> qed_status plan_step(qed_plan p, hipStream_t st)
         else if (p->pv == 2)
             QS_LAUNCH(K_PLAN_PHOTON, (k_plan_main<R, 1, 0, kFldPlain, 2>), dim3(p->nblk - p->nblk_lep), dim3(kBlock),
                       p->lds, st, inst, P, p->T->dev, p->nblk_lep);
+
         else
             QS_LAUNCH(K_PLAN_PHOTON, (k_plan_main<R, 1, 0, kFldPlain>), dim3(p->nblk - p->nblk_lep), dim3(kBlock), p->lds,
                       st, inst, P, p->T->dev, p->nblk_lep);
