@@ -361,7 +361,9 @@ typedef struct qed_plan_s *qed_plan;   /* opaque, library-owned */
 /* Copy the instance descriptions (pointers, capacities, fields, parameters) to the device and
    allocate the plan's scratch: two mask planes of one bit per particle slot, per-block counts,
    per-set bookkeeping, per instance with grid fields 32 bytes per grid node and, per lepton set
-   with QED_SUBCYCLE, 4 bytes per slot and 64 bytes per streaming block.  Allocates device memory
+   with QED_SUBCYCLE, 4 bytes per slot, 16 x 6 values of the tables' precision per slot (the
+   momenta and P-vectors of the photons of a slot's sub-steps: 384 bytes in single, 768 in double
+   precision) and 64 bytes per streaming block.  Allocates device memory
    and synchronizes the device; afterwards the arrays and counters named here must stay
    allocated and keep their addresses.  config may be NULL.  QED_ERR_INVALID for a NULL pointer,
    an inconsistent set (species, missing arrays, dt or eps_r <= 0, no d_clock or d_counters),

@@ -23,6 +23,8 @@ template <class R> struct LepDev {
     uint32_t *sub;             // merged step with sub-cycling: per slot of a lepton with a photon this
                                // step, (log2 of its sub-steps << 16) | (bit r: a photon in round r);
                                // NULL: no sub-cycling
+    R *stage;                  // ... and per slot kSubRounds x (k, P-vector) of the photons its
+                               // sub-steps made, for the processing pass to place
 };
 
 template <class R> struct PhoDev {
@@ -229,16 +231,18 @@ template <class R> struct LDecide {
     bool clamped_chi;
 };
 
+// The part that depends on the momentum and the fields only: chi_e, the emission basis and the
+// two rates (d.active false outside the pulse or below chi_min).  A sub-cycled lepton keeps it
+// through its sub-steps until an emission changes its momentum.
 template <class R>
-__device__ __forceinline__ LDecide<R> lepton_decide(const StepDev &S, const TablesDev &T, const R *lds, int species,
-                                                    int64_t index, V3<R> p, V3<R> s, V3<R> E, V3<R> B)
+__device__ __forceinline__ void lepton_geom(const StepDev &S, const TablesDev &T, const R *lds, int species, V3<R> p,
+                                            V3<R> E, V3<R> B, LDecide<R> &d)
 {
-    LDecide<R> d;
     d.clamped_chi = false;
     if (zero_field(E, B)) {           // outside the pulse: no QED, skip the FP64 island
         d.active = false;
         d.chi = 0.0;
-        return d;
+        return;
     }
     const int q = species == 0 ? -1 : 1;
     const double gam = sqrt(1.0 + dot(cvt<double>(p), cvt<double>(p)));
@@ -246,7 +250,7 @@ __device__ __forceinline__ LDecide<R> lepton_decide(const StepDev &S, const Tabl
     d.active = d.chi >= S.chi_e_min;
     d.clamped_chi = d.chi > S.chi_e_max;
     if (d.clamped_chi) d.chi = S.chi_e_max;
-    if (!d.active) return d;
+    if (!d.active) return;
     const int n = T.n_chi[0];
     const R lnchi = log_r((R)d.chi);
     const R x0 = (R)T.lnchi0[0], h = (R)T.dlnchi[0];
@@ -254,6 +258,14 @@ __device__ __forceinline__ LDecide<R> lepton_decide(const StepDev &S, const Tabl
     d.Ce = Ce;
     d.Wdn = Ce * exp_r(rate_lookup(lds, lnchi, x0, h, n));
     d.Wup = Ce * exp_r(rate_lookup(lds + n, lnchi, x0, h, n));
+}
+
+// The part that depends on the spin and the draw of this step (and sub-cycling round): the
+// branch weights a = W_down (1 - s.beta)/2 dt, P = a + W_up (1 + s.beta)/2 dt and r1, r2.
+template <class R>
+__device__ __forceinline__ void lepton_draw(const StepDev &S, int species, int64_t index, V3<R> s, LDecide<R> &d)
+{
+    if (!d.active) return;
     const R sb = dot(s, d.bs.b);
     const R dt = (R)S.dt;
     d.a = d.Wdn * (R)0.5 * ((R)1 - sb) * dt;
@@ -261,6 +273,15 @@ __device__ __forceinline__ LDecide<R> lepton_decide(const StepDev &S, const Tabl
     d.P = d.a + b;
     const uint4 w = philox_block(S.seed, lepton_id(species, index), S.step, 16u * (uint32_t)S.sub_round);
     Unif<R>::two(w, d.r1, d.r2);
+}
+
+template <class R>
+__device__ __forceinline__ LDecide<R> lepton_decide(const StepDev &S, const TablesDev &T, const R *lds, int species,
+                                                    int64_t index, V3<R> p, V3<R> s, V3<R> E, V3<R> B)
+{
+    LDecide<R> d;
+    lepton_geom<R>(S, T, lds, species, p, E, B, d);
+    lepton_draw<R>(S, species, index, s, d);
     return d;
 }
 
@@ -421,9 +442,10 @@ __device__ __forceinline__ void noemit_spin(const StepDev &S, const LDecide<R> &
 // d of round S.sub_round (taken at the current p, s) with W dt scaled by 2^-msh (exact), then the
 // emission (true; photon in k, Pv; p, s recoiled and collapsed) or the no-transition update over
 // dt 2^-msh.  With c, the counts lepton_item keeps (chi clamps, P > 1, renormalizations).
-template <class R, bool PHOTON = true>
-__device__ __forceinline__ bool lepton_substep(const StepDev &S, const TablesDev &T, int species, int64_t i, int msh,
-                                               LDecide<R> d, V3<R> &p, V3<R> &s, V3<R> &k, V3<R> &Pv, LCount *c)
+// substep_decide is the part up to the choice (the no-transition update included; true: an
+// emission follows), substep_emit the emission with the d it left.
+template <class R>
+__device__ __forceinline__ bool substep_decide(const StepDev &S, int msh, LDecide<R> &d, V3<R> &s, LCount *c)
 {
     if (!d.active) return false;
     d.a = ldexp(d.a, -msh);
@@ -435,9 +457,24 @@ __device__ __forceinline__ bool lepton_substep(const StepDev &S, const TablesDev
         if (c) c->norm += nrm;
         return false;
     }
+    return true;
+}
+
+template <class R, bool PHOTON = true>
+__device__ __forceinline__ void substep_emit(const StepDev &S, const TablesDev &T, const LDecide<R> &d, int species,
+                                             int64_t i, V3<R> &p, V3<R> &s, V3<R> &k, V3<R> &Pv, LCount *c)
+{
     if (c) c->prob += d.P > (R)1;
     const R thr = d.P <= (R)1 ? d.a : d.a / d.P;
     emit_core<R, PHOTON>(S, T, d, species, i, !(d.r1 < thr), p, s, k, Pv);
+}
+
+template <class R, bool PHOTON = true>
+__device__ __forceinline__ bool lepton_substep(const StepDev &S, const TablesDev &T, int species, int64_t i, int msh,
+                                               LDecide<R> d, V3<R> &p, V3<R> &s, V3<R> &k, V3<R> &Pv, LCount *c)
+{
+    if (!substep_decide<R>(S, msh, d, s, c)) return false;
+    substep_emit<R, PHOTON>(S, T, d, species, i, p, s, k, Pv, c);
     return true;
 }
 
@@ -919,6 +956,7 @@ template <class R> LepDev<R> lep_dev(const qed_leptons *L)
     d.tau_t = L->tau_target;
     d.msub = nullptr;
     d.sub = nullptr;
+    d.stage = nullptr;
     return d;
 }
 

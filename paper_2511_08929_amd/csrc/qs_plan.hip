@@ -184,6 +184,7 @@ k_plan_main(const InstDev<R> *inst, PlanDev P, TablesDev T, int b_first)
 }
 
 constexpr int kExpandWords = kBlock; // mask words expanded per round of the process pass, one per thread (16384 slots)
+constexpr int kStage = kSubRounds * 6;  // per lepton slot with sub-cycling: k and P-vector of each round's photon
 
 // The set bits of the mask words [c0, c1) (word c0 + t given as m by thread t, 0 past c1) as
 // positions 64 (word - c0) + bit in slot order, into list; returns their number.  Block-wide.
@@ -255,22 +256,47 @@ k_plan_sub(const InstDev<R> *inst, PlanDev P, TablesDev T)
             eval_fields<R, kFldGeneral>(F, (double)x.x, (double)x.y, S.t + S.dt, E, Bf);
             const int m = min((int)(L.sub[i] >> 16), kSubLog2Max);    // the loop's stride stays >= 1
             unsigned em = 0;
-            for (int r = 0; r < kSubRounds; r += kSubRounds >> m) {
+            // chi, the basis and the rates hold until an emission changes the momentum.  Each lane
+            // runs its no-emission sub-steps up to its next emission, then the lanes that reached
+            // one emit together: a wave runs the emission code once per emission of its busiest
+            // lepton, not once per sub-step in which some lepton emits.
+            LDecide<R> g;
+            lepton_geom<R>(S, T, lds, L.species, p, E, Bf, g);
+            const int stride = kSubRounds >> m;
+            int r = 0;
+            while (r < kSubRounds) {
+                LDecide<R> d;
+                bool emit = false;
+                for (; r < kSubRounds; r += stride) {
+                    StepDev Sr = S;
+                    Sr.sub_round = r;
+                    d = g;
+                    lepton_draw<R>(Sr, L.species, i, s, d);
+                    if (substep_decide<R>(Sr, m, d, s, &c)) {
+                        emit = true;
+                        break;
+                    }
+                }
+                if (!emit) break;
                 StepDev Sr = S;
                 Sr.sub_round = r;
-                const LDecide<R> d = lepton_decide<R>(Sr, T, lds, L.species, i, p, s, E, Bf);
                 V3<R> k, Pv;
-                if (lepton_substep<R, false>(Sr, T, L.species, i, m, d, p, s, k, Pv, &c)) em |= 1u << r;
+                substep_emit<R>(Sr, T, d, L.species, i, p, s, k, Pv, &c);
+                em |= 1u << r;
+                R *st = L.stage + ((int64_t)i * kSubRounds + r) * 6;
+                st[0] = k.x; st[1] = k.y; st[2] = k.z;
+                st[3] = Pv.x; st[4] = Pv.y; st[5] = Pv.z;
+                lepton_geom<R>(S, T, lds, L.species, p, E, Bf, g);
+                r += stride;
             }
 #pragma unroll
             for (int r = 0; r < kSubRounds; ++r) c.rnd[r] += (em >> r) & 1u;
             if (em) {
                 L.sub[i] = ((unsigned)m << 16) | em;
                 atomicOr(reinterpret_cast<unsigned long long *>(mask + (i >> 6)), 1ull << (i & 63));
-            } else {
-                st3(L.p, i, p);
-                st3(L.s, i, s);
             }
+            st3(L.p, i, p);
+            st3(L.s, i, s);
         }
         __syncthreads();
     }
@@ -345,9 +371,9 @@ template <> struct SurLds<false> {
 // the network out of bound.
 // SUB: lepton sets with sub-cycling (their LepDev::sub set) place each lepton's photons round by
 // round: all of a set's round-r photons, in lepton order, before its round-r+1 photons, as the
-// per-species calls do.  The streaming pass ran the sub-steps to count each block's photons per
-// round; here every lepton with a photon runs them again from its state after the push (the same
-// draws give the same sub-steps) and stores each photon at its round's offset plus its rank.
+// per-species calls do.  The sub-step launch ran the sub-steps, counted each block's photons per
+// round and kept them; here each photon is copied to its round's offset plus its rank, and a
+// lepton the streaming pass chose to emit in its one step (round 0) is processed as usual.
 template <class R, int FLD, bool SUR, bool SUB = false>
 __global__ void __launch_bounds__(kBlock) k_plan_process(const InstDev<R> *inst, PlanDev P, TablesDev T, int b_first)
 {
@@ -587,22 +613,36 @@ __global__ void __launch_bounds__(kBlock) k_plan_process(const InstDev<R> *inst,
                         for (int r = 0; r < kSubRounds; ++r)
                             for (int w = 0; w < wid; ++w) sub_pos[r][threadIdx.x] += sub_wt[r][w];
                         const V3<R> x = ldx(Ls.x, i);
-                        V3<R> p = ld3(Ls.p, i), s = ld3(Ls.s, i);
-                        V3<R> E, B;
-                        eval_fields<R, FLD>(F, (double)x.x, (double)x.y, S.t + S.dt, E, B);
-                        const int m = min((int)(wsub >> 16), kSubLog2Max);      // the loop's stride stays >= 1
-                        for (int r = 0; r < kSubRounds; r += kSubRounds >> m) {
-                            StepDev Sr = S;
-                            Sr.sub_round = r;
-                            const LDecide<R> d = lepton_decide<R>(Sr, Tl, lds, Ls.species, i, p, s, E, B);
+                        if ((wsub >> 16) != 0) {
+                            // sub-cycled: the sub-step launch finished the lepton and kept the
+                            // momentum and P-vector of each of its photons
+                            for (int r = 0; r < kSubRounds; ++r)
+                                if ((wsub >> r) & 1u) {
+                                    const int64_t q = (int64_t)(sub_off[r] + sub_pos[r][threadIdx.x]);
+                                    if (q < bk.nfit) {
+                                        const R *st = Ls.stage + ((int64_t)i * kSubRounds + r) * 6;
+                                        StepDev Sr = S;
+                                        Sr.sub_round = r;
+                                        store_photon<R>(Ip->G, Sr, Ls.species, i, bk.base + q, x, v3<R>(st[0], st[1], st[2]),
+                                                        v3<R>(st[3], st[4], st[5]), c_ret);
+                                    }
+                                }
+                        } else {
+                            // one step (the emission the streaming pass decided): its photon is in round 0
+                            StepDev S0 = S;
+                            S0.sub_round = 0;
+                            V3<R> p = ld3(Ls.p, i), s = ld3(Ls.s, i);
+                            V3<R> E, B;
+                            eval_fields<R, FLD>(F, (double)x.x, (double)x.y, S0.t + S0.dt, E, B);
+                            const LDecide<R> d = lepton_decide<R>(S0, Tl, lds, Ls.species, i, p, s, E, B);
                             V3<R> k, Pv;
-                            if (lepton_substep<R>(Sr, Tl, Ls.species, i, m, d, p, s, k, Pv, nullptr) && ((wsub >> r) & 1u)) {
-                                const int64_t q = (int64_t)(sub_off[r] + sub_pos[r][threadIdx.x]);
-                                if (q < bk.nfit) store_photon<R>(Ip->G, Sr, Ls.species, i, bk.base + q, x, k, Pv, c_ret);
+                            if (lepton_substep<R>(S0, Tl, Ls.species, i, 0, d, p, s, k, Pv, nullptr)) {
+                                const int64_t q = (int64_t)(sub_off[0] + sub_pos[0][threadIdx.x]);
+                                if (q < bk.nfit) store_photon<R>(Ip->G, S0, Ls.species, i, bk.base + q, x, k, Pv, c_ret);
                             }
+                            st3(Ls.p, i, p);
+                            st3(Ls.s, i, s);
                         }
-                        st3(Ls.p, i, p);
-                        st3(Ls.s, i, s);
                     }
                     __syncthreads();
                     if (threadIdx.x < kSubRounds) {
@@ -633,6 +673,7 @@ struct qed_plan_s {
     uint32_t *d_bcnt;
     uint32_t *d_bsub;          // sub-cycling: photons per round of each lepton streaming block
     uint32_t *d_sub;           // sub-cycling: the sub-step word of every slot of those lepton sets
+    void *d_stage;             // ... and the photons of each slot's sub-steps (kStage values of R)
     int sub;                   // some instance sub-cycles
     hipStream_t side;          // sub-cycling: the sub-step launch runs here, beside the photon pass
     hipEvent_t fork, join;
@@ -676,6 +717,7 @@ void plan_free(qed_plan p)
     (void)hipFree(p->d_bcnt);
     (void)hipFree(p->d_bsub);
     (void)hipFree(p->d_sub);
+    (void)hipFree(p->d_stage);
     if (p->fork) (void)hipEventDestroy(p->fork);
     if (p->join) (void)hipEventDestroy(p->join);
     if (p->side) (void)hipStreamDestroy(p->side);
@@ -794,19 +836,25 @@ qed_status plan_create(qed_tables T, int n, const qed_instance *in, int ppb, int
             if (in[i].params.flags & QED_SUBCYCLE)
                 words += in[i].electrons.capacity + ((in[i].params.flags & QED_PAIR) ? in[i].positrons.capacity : 0);
         e = hipMalloc((void **)&p->d_sub, sizeof(uint32_t) * (words > 0 ? words : 1));
+        if (e == hipSuccess) e = hipMalloc(&p->d_stage, sizeof(R) * kStage * (words > 0 ? words : 1));
         if (e == hipSuccess) e = hipMalloc((void **)&p->d_bsub, sizeof(uint32_t) * kSubRounds * (nblk_lep > 0 ? nblk_lep : 1));
         // default priority, like every stream of the library
         if (e == hipSuccess) e = hipStreamCreateWithFlags(&p->side, hipStreamNonBlocking);
         if (e == hipSuccess) e = hipEventCreateWithFlags(&p->fork, hipEventDisableTiming);
         if (e == hipSuccess) e = hipEventCreateWithFlags(&p->join, hipEventDisableTiming);
         uint32_t *at = p->d_sub;
+        R *st = (R *)p->d_stage;
         for (int i = 0; i < n && e == hipSuccess; ++i)
             if (in[i].params.flags & QED_SUBCYCLE) {
                 inst[i].E.sub = at;
+                inst[i].E.stage = st;
                 at += in[i].electrons.capacity;
+                st += kStage * in[i].electrons.capacity;
                 if (in[i].params.flags & QED_PAIR) {
                     inst[i].P.sub = at;
+                    inst[i].P.stage = st;
                     at += in[i].positrons.capacity;
+                    st += kStage * in[i].positrons.capacity;
                 }
             }
     }
