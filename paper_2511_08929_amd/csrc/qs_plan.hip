@@ -222,7 +222,7 @@ __device__ __forceinline__ uint32_t mask_list(uint64_t m, uint16_t *list, uint32
 // state after the push to place their photons.
 // Its waves hold long dependent chains (the sub-steps of one lepton run one after the other), so it
 // is held to two waves per SIMD in FP64 (258 registers otherwise: one) and three in FP32.
-template <class R>
+template <class R, int FLD>
 __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 ? 3 : 2)))
 k_plan_sub(const InstDev<R> *inst, PlanDev P, TablesDev T)
 {
@@ -253,7 +253,7 @@ k_plan_sub(const InstDev<R> *inst, PlanDev P, TablesDev T)
             const V3<R> x = ldx(L.x, i);
             V3<R> p = ld3(L.p, i), s = ld3(L.s, i);
             V3<R> E, Bf;
-            eval_fields<R, kFldGeneral>(F, (double)x.x, (double)x.y, S.t + S.dt, E, Bf);
+            eval_fields<R, FLD>(F, (double)x.x, (double)x.y, S.t + S.dt, E, Bf);
             const int m = min((int)(L.sub[i] >> 16), kSubLog2Max);    // the loop's stride stays >= 1
             unsigned em = 0;
             // chi, the basis and the rates hold until an emission changes the momentum.  Each lane
@@ -941,8 +941,14 @@ template <class R> qed_status plan_step(qed_plan p, hipStream_t st)
             QS_LAUNCH(K_GRID_PACK, k_pack_grid, dim3(gb), dim3(kBlock), 0, st, p->h_grid[i], p->h_gn[i]);
         }
     if (p->nblk_lep > 0) {
-        if (p->sub)
+        if (p->sub && p->flep == kFldGeneral)
             QS_LAUNCH(K_PLAN_LEPTON, (k_plan_main<R, 0, 8, kFldGeneral>), dim3(p->nblk_lep), dim3(kBlock), p->lds, st, inst, P,
+                      p->T->dev, 0);
+        else if (p->sub && p->flep == kFldRotating)
+            QS_LAUNCH(K_PLAN_LEPTON, (k_plan_main<R, 0, 8, kFldRotating>), dim3(p->nblk_lep), dim3(kBlock), p->lds, st, inst,
+                      P, p->T->dev, 0);
+        else if (p->sub)
+            QS_LAUNCH(K_PLAN_LEPTON, (k_plan_main<R, 0, 8, kFldPlain>), dim3(p->nblk_lep), dim3(kBlock), p->lds, st, inst, P,
                       p->T->dev, 0);
         else if (p->dec == 3)
             QS_LAUNCH(K_PLAN_LEPTON, (k_plan_main<R, 0, 3, kFldGeneral>), dim3(p->nblk_lep), dim3(kBlock), p->lds, st, inst, P,
@@ -969,7 +975,9 @@ template <class R> qed_status plan_step(qed_plan p, hipStream_t st)
     if (fork) {
         QS_CHECK(hipEventRecord(p->fork, st));
         QS_CHECK(hipStreamWaitEvent(p->side, p->fork, 0));
-        QS_LAUNCH(K_PLAN_SUB, k_plan_sub<R>, dim3(p->nblk_lep), dim3(kBlock), p->lds, p->side, inst, P, p->T->dev);
+        auto sk = p->fv == kFldGeneral ? k_plan_sub<R, kFldGeneral> : p->fv == kFldRotating ? k_plan_sub<R, kFldRotating>
+                                                                                            : k_plan_sub<R, kFldPlain>;
+        QS_LAUNCH(K_PLAN_SUB, sk, dim3(p->nblk_lep), dim3(kBlock), p->lds, p->side, inst, P, p->T->dev);
         QS_CHECK(hipEventRecord(p->join, p->side));
     }
     if (p->nblk > p->nblk_lep) {
@@ -1009,8 +1017,10 @@ template <class R> qed_status plan_step(qed_plan p, hipStream_t st)
             }
         }
         if (p->sub) {
-            QS_LAUNCH(K_PLAN_PROCESS, (k_plan_process<R, kFldGeneral, false, true>), dim3(p->npb), dim3(kBlock), p->lds, st,
-                      inst, P, p->T->dev, 0);
+            auto proc = p->fv == kFldGeneral    ? k_plan_process<R, kFldGeneral, false, true>
+                        : p->fv == kFldRotating ? k_plan_process<R, kFldRotating, false, true>
+                                                : k_plan_process<R, kFldPlain, false, true>;
+            QS_LAUNCH(K_PLAN_PROCESS, proc, dim3(p->npb), dim3(kBlock), p->lds, st, inst, P, p->T->dev, 0);
             return qs_launch_status("qed_plan_step");
         }
         auto proc = p->fv == kFldGeneral    ? k_plan_process<R, kFldGeneral, false>
