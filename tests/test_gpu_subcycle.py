@@ -174,23 +174,29 @@ def _run_both(q, tab, w, cap_e, cap_p, cap_g, flags, steps, every=0, k_retire=No
     return out
 
 
-@pytest.mark.parametrize("prec", ["fp64", "fp32"])
-def test_plan_subcycle_equals_per_species(q, gtab64, gtab32, prec):
-    """The merged step's sub-cycling (the streaming pass runs each lepton's sub-steps to count its
-    block's photons per round, the processing pass runs them again to place the photons) equals
-    the per-species calls (16 rounds of three launches) bit for bit: 1000 leptons with 1 to 16
-    sub-steps, 4 steps, every photon kept."""
+@pytest.mark.parametrize("prec,cap_per_lepton", [("fp64", 80), ("fp32", 80), ("fp64", 1)])
+def test_plan_subcycle_equals_per_species(q, gtab64, gtab32, prec, cap_per_lepton):
+    """The merged step's sub-cycling (the streaming pass flags the leptons with several sub-steps,
+    the sub-step launch runs them, keeps their photons and counts them per round, the processing
+    pass copies the photons to their places) equals the per-species calls (16 rounds of three
+    launches) bit for bit: 1000 leptons with 1 to 16 sub-steps, 4 steps, every photon kept; and
+    with a photon store of one slot per lepton, which overflows, so both drop
+    the same photons (the latest rounds' first)."""
     tab = gtab64 if prec == "fp64" else gtab32
     n = 1000
     w = _workload(n, dt=0.5)
     if prec == "fp32":
         w.x, w.p, w.s = (a.astype(np.float32).astype(np.float64) for a in (w.x, w.p, w.s))
     flags = (q.QED_ALL & ~q.QED_PAIR) | q.QED_SUBCYCLE
-    (a, ca), (b, cb) = _run_both(q, tab, w, n, 1, 80 * n, flags, 4, k_retire=0.0)
-    print(prec, "per-species", ca, "merged", cb)
+    (a, ca), (b, cb) = _run_both(q, tab, w, n, 1, cap_per_lepton * n, flags, 4, k_retire=0.0)
+    print(prec, cap_per_lepton, "per-species", ca, "merged", cb)
     assert ca == cb and ca["n_emit"] > 2000
-    ids = a[-1]
-    assert len(np.unique(_rounds(ids[ids != 0]))) == 16
+    if cap_per_lepton == 1:
+        assert ca["n_capacity_overflow"] > 0
+    else:
+        assert ca["n_capacity_overflow"] == 0
+        ids = a[-1]
+        assert len(np.unique(_rounds(ids[ids != 0]))) == 16
     for u, v in zip(a, b):
         np.testing.assert_array_equal(u, v)
 
