@@ -493,16 +493,38 @@ def extra_flag_variant(q, args, w, t32, cfg, out, v64, key, flags, ref):
     log(f"{key}: {v:.4g}/s")
 
 
-def extra_batched(q, args, t32, t64, out):
+# Store sizes of an ensemble member, in slots per electron, from its initial chi0 = 2 gamma0 a0
+# eps_r.  Members past chi0 ~ 6.5 cascade (pairs emit and make pairs) and emit some hundreds of
+# photons per electron over the run; members with a0 near 200 need about 16 photon slots per
+# electron between compactions even without.  Measured on the recipe at 5 % of its counts: no
+# member overflows with these.  "compact50" is for compaction every 50 steps; "compact10" needs
+# less room (fewer dead slots wait for the compaction), so the ensembles at full counts fit in
+# FP64 (about 200 GB).
+ENSEMBLE_SLOTS = {"compact50": ((6.5, 200, 4.0), (5.0, 60, 4.0), (0.0, 30, 1.5)),
+                  "compact10": ((6.5, 100, 4.0), (5.0, 30, 4.0), (0.0, 20, 1.5))}
+
+
+def ensemble_caps(x, rule):
+    g0 = float(np.mean(np.sqrt(1.0 + (x.p ** 2).sum(0))))
+    chi0 = 2.0 * g0 * x.a0 * synth.EPS_R
+    pg, pp = next((g, p) for c, g, p in ENSEMBLE_SLOTS[rule] if chi0 >= c)
+    return dict(cap_e=x.n + max(1000, int(pp * x.n)), cap_p=max(1000, int(pp * x.n)), cap_g=max(100_000, pg * x.n))
+
+
+def extra_batched(q, args, t32, t64, out, scale=None, key="batched", every=COMPACT_EVERY):
+    """The 64 batched ensembles (at `scale` of the recipe's particle counts) through one plan, FP32
+    and FP64, each with its tuned launch shape; stores sized by ensemble_caps."""
     import torch
     from paper_2511_08929_amd import autotune
     from paper_2511_08929_amd.sim import Batch
-    ws = synth.c5(scale=args.batched_scale)
+    scale = args.batched_scale if scale is None else scale
+    ws = synth.c5(scale=scale)
     steps_b = 2000
 
     def make(tab):
-        specs = [dict(cap_e=x.n + max(1000, x.n // 5), cap_p=max(1000, x.n // 5), cap_g=max(100_000, 40 * x.n),
-                      track=x.track, fields=dict(kind=x.field_kind, a0=x.a0, phase_len=x.phase_len), dt=x.dt,
+        rule = "compact10" if every <= 10 else "compact50"
+        specs = [dict(**ensemble_caps(x, rule), track=x.track,
+                      fields=dict(kind=x.field_kind, a0=x.a0, phase_len=x.phase_len), dt=x.dt,
                       eps_r=synth.EPS_R, seed=x.seed, flags=q.QED_ALL, k_retire=x.k_retire) for x in ws]
         b = Batch(tab, specs)
         for x, inst in zip(ws, b.inst):
@@ -512,12 +534,12 @@ def extra_batched(q, args, t32, t64, out):
     res = {}
     for label, tab in (("fp32", t32), ("fp64", t64)):
         b = make(tab)
-        best, timings, cached = b.tune(300, every=COMPACT_EVERY, log=log,
+        best, timings, cached = b.tune(300, every=every, log=log,
                                        space={k: v for k, v in autotune.SPACE.items() if k != "max_blocks_per_set"})
-        g = b.capture(COMPACT_EVERY)
+        g = b.capture(every)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        for _ in range(steps_b // COMPACT_EVERY):
+        for _ in range(steps_b // every):
             b.replay(g)
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
@@ -530,9 +552,12 @@ def extra_batched(q, args, t32, t64, out):
         del g, b
         torch.cuda.empty_cache()
         log(f"batched {label}: {res[label]['value']:.4g}/s config {best}")
-    out["batched"] = {"instances": len(ws), "electrons": int(sum(x.n for x in ws)), "steps": steps_b,
+    out[key] = {"instances": len(ws), "electrons": int(sum(x.n for x in ws)), "steps": steps_b,
                       "unit": "particle-QED-steps/s",
-                      "recipe": f"64 head-on collisions, N ~ LogUniform[1e4, 1e7] x {args.batched_scale}, "
+                      "slots_per_electron": {"rule": "compact10" if every <= 10 else "compact50",
+                                             "by_chi0": ENSEMBLE_SLOTS["compact10" if every <= 10 else "compact50"]},
+                      "compact_every": every,
+                      "recipe": f"64 head-on collisions, N ~ LogUniform[1e4, 1e7] x {scale}, "
                                 "a0 ~ U[20, 200], gamma0 ~ U[500, 1e4], spin degree ~ U[0, 1]",
                       "value": res["fp32"]["value"], "fp64_value": res["fp64"]["value"],
                       "speedup_vs_fp64": round(res["fp32"]["value"] / res["fp64"]["value"], 3), **res}
@@ -633,6 +658,36 @@ def extra_subcycle(q, args, t64, out, n=100_000, steps=200, n_mixed=100_000):
     log(f"sub-cycling: {res}")
 
 
+def extra_full_scale(q, args, t32, t64, cfg, out):
+    """The two workloads at their stated sizes (opt-in, several minutes): the head-on collision at
+    10^8 electrons (24 photon slots per electron, every photon kept) through the FP32 tables, the
+    learned inverse CDF and the FP64 tables, in the launch shape tuned on 10^6 electrons; and the 64
+    batched ensembles at full particle counts, FP32 and FP64."""
+    import torch
+    wb = synth.c2(n=args.full_n)
+    log(f"full scale: head-on collision, {wb.n} electrons, {COLLISION_STEPS} steps")
+    sn, sb = q.Surrogate(t32, 0, seed=1), q.Surrogate(t32, 1, seed=2)
+    sn.fit(), sb.fit()
+    for s_ in (sn, sb):
+        s_.judge(SURROGATE_JUDGE_BOUND)
+    res = {}
+    for label, tab, sur in (("fp32", t32, (None, None)), ("surrogate", t32, (sn, sb)), ("fp64", t64, (None, None))):
+        col = Collision(q, tab, wb, cfg, surrogates=sur, photons_per_electron=24)
+        wall, c = col.timed(1, 0)
+        col.close()
+        res[label] = {"value": round(work_of(c) / wall, 1), "wall_s": round(wall, 3), "photons_emitted": c["n_emit"],
+                      "pairs": c["n_pair"], "capacity_overflow": c["n_capacity_overflow"]}
+        log(f"full scale {label}: {wall:.2f} s, {res[label]['value']:.4g}/s, counters {c}")
+        torch.cuda.empty_cache()
+    for label in ("fp32", "surrogate"):
+        res[label]["speedup_vs_fp64"] = round(res[label]["value"] / res["fp64"]["value"], 3)
+    out["full_scale_head_on"] = dict(electrons=wb.n, steps=COLLISION_STEPS, photon_slots_per_electron=24,
+                                     config=cfg, **res)
+    del sn, sb, wb
+    torch.cuda.empty_cache()
+    extra_batched(q, args, t32, t64, out, scale=1.0, key="full_scale_batched", every=args.full_compact_every)
+
+
 def run_extra(out, name, budget_s, fn, *a):
     """run one extra unless the time budget is spent; a failure is recorded, never fatal"""
     el = time.perf_counter() - T_START
@@ -672,6 +727,12 @@ def parse_args(argv=None):
     ap.add_argument("--batched-scale", type=float, default=0.05,
                     help="particle counts of the 64 batched ensembles relative to the full recipe")
     ap.add_argument("--ppb", type=int, default=0, help="fixed particles per block (0: autotuned)")
+    ap.add_argument("--full-scale", action="store_true",
+                    help="also run the head-on collision at 10^8 electrons (FP32 tables, learned inverse CDF, FP64) "
+                         "and the 64 batched ensembles at full particle counts (several minutes)")
+    ap.add_argument("--full-n", type=int, default=100_000_000, help="electrons of the --full-scale head-on run")
+    ap.add_argument("--full-compact-every", type=int, default=10,
+                    help="compaction interval of the --full-scale batched run (its stores are bounded by FP64 memory)")
     ap.add_argument("--probe", action="store_true",
                     help="profiler run: copy calibration + one eager FP32 collision, no JSON line")
     ap.add_argument("--probe-steps", type=int, default=COLLISION_STEPS)
@@ -800,6 +861,8 @@ def main(argv=None):
         run_extra(out, "cascade", args.budget_s, extra_cascade, q, args, t32, t64, cfg, out)
         run_extra(out, "grid", args.budget_s, extra_grid, q, args, t32, cfg, out)
         run_extra(out, "subcycle", args.budget_s, extra_subcycle, q, args, t64, out)
+    if args.full_scale:
+        run_extra(out, "full_scale", float("inf"), extra_full_scale, q, args, t32, t64, cfg, out)
     out["bench_wall_s"] = round(time.perf_counter() - T_START, 1)
     print(json.dumps(out), flush=True)
 

@@ -123,3 +123,28 @@ def test_roofline_bound_follows_the_longer_ceiling(monkeypatch):
     assert r["bound"] == "alu" and r["frac"] == r["alu"]["frac"] and r["hbm"]["frac"] > 0
     monkeypatch.setattr(bench, "load_valu", lambda k: 0.5 * t_hbm * 256 * 2.4e9)
     assert bench.roofline(kt, ck, 5000.0)["bound"] == "hbm"
+
+
+def test_ensemble_stores_follow_initial_chi():
+    """The ensemble members' stores grow with their initial chi (the cascading members get the
+    most room), never below the floors, and the full-count rule needs less room per electron."""
+    import numpy as np
+    from types import SimpleNamespace
+
+    def member(n, gamma0, a0):
+        p = np.zeros((3, n)); p[0] = np.sqrt(gamma0 ** 2 - 1.0)
+        return SimpleNamespace(n=n, p=p, a0=a0)
+
+    eps = bench.synth.EPS_R
+    hot = member(10_000, 9000.0, 200.0)          # chi0 = 2 gamma0 a0 eps_r ~ 10.9
+    warm = member(10_000, 9000.0, 100.0)         # ~ 5.5
+    cold = member(10_000, 1000.0, 50.0)          # ~ 0.3
+    assert 2 * 9000.0 * 200.0 * eps > 6.5 and 5 < 2 * 9000.0 * 100.0 * eps < 6.5
+    for rule in ("compact50", "compact10"):
+        c_hot, c_warm, c_cold = (bench.ensemble_caps(m, rule) for m in (hot, warm, cold))
+        assert c_hot["cap_g"] > c_warm["cap_g"] > c_cold["cap_g"] >= 100_000
+        assert c_hot["cap_p"] >= 4 * hot.n and c_cold["cap_p"] >= 1000
+        assert c_hot["cap_e"] == hot.n + c_hot["cap_p"]
+    assert bench.ensemble_caps(hot, "compact10")["cap_g"] < bench.ensemble_caps(hot, "compact50")["cap_g"]
+    tiny = member(10, 9000.0, 200.0)
+    assert bench.ensemble_caps(tiny, "compact50") == dict(cap_e=1010, cap_p=1000, cap_g=100_000)
