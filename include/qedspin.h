@@ -97,10 +97,10 @@ enum {
                                   16/m-th), each the whole QED part at its current chi and spin, with
                                   Philox channels offset by 16 x round and the round in the photon id;
                                   a round's photons follow the previous round's.  qed_emit runs the
-                                  rounds as 16 launches of its three kernels; a plan runs them in its
-                                  own launches (each lepton takes all its sub-steps in the streaming
-                                  pass to count its block's photons per round, and again in the
-                                  processing pass to store them in that order), with the same
+                                  rounds as 16 launches of its three kernels; a plan runs them in one
+                                  launch of its own (each sub-cycled lepton takes all its sub-steps
+                                  there, and its photons, kept per slot and counted per round, are
+                                  stored in that order by the processing pass), with the same
                                   results bit for bit.  Not with QED_OPTICAL_DEPTH or QED_REJECTION
                                   (QED_ERR_INVALID), nor in a plan with a learned inverse CDF
                                   (QED_ERR_UNSUPPORTED).  Leptons below W dt = 0.1 step exactly as

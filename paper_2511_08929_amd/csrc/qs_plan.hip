@@ -217,11 +217,11 @@ __device__ __forceinline__ uint32_t mask_list(uint64_t m, uint16_t *list, uint32
 // streaming block flagged (branch bit without a transition), runs all sub-steps of each on full
 // waves, and books their photons per round: the rounds with a photon in the lepton's sub-step
 // word, its transition bit if it has one, and the block's photon counts per round and in all and
-// its event counts added to the streaming pass's.  A lepton without a photon is finished here
-// (its state after the sub-steps stored); the processing pass runs the others again from their
-// state after the push to place their photons.
+// its event counts added to the streaming pass's.  Every lepton is finished here (its state after
+// the sub-steps stored), and the momentum and P-vector of each photon its sub-steps make are kept
+// in its slot's staging entries, which the processing pass copies to the photons' places.
 // Its waves hold long dependent chains (the sub-steps of one lepton run one after the other), so it
-// is held to two waves per SIMD in FP64 (258 registers otherwise: one) and three in FP32.
+// is held to two waves per SIMD in FP64 (one otherwise) and three in FP32.
 template <class R, int FLD>
 __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 ? 3 : 2)))
 k_plan_sub(const InstDev<R> *inst, PlanDev P, TablesDev T)
