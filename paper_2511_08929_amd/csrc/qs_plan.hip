@@ -404,11 +404,16 @@ __global__ void __launch_bounds__(kBlock) k_plan_process(const InstDev<R> *inst,
         for (int b = mb0 + lane; b < bend; b += 64)
 #pragma unroll
             for (int c = 0; c < kNCtr; ++c) v[c] += P.bctr[(int64_t)b * kNCtr + c];
+        // every sum first (independent shuffle chains), then the atomics through one pointer read
 #pragma unroll
-        for (int c = 0; c < kNCtr; ++c) {
-            unsigned long long t = v[c];
-            for (int o = 32; o > 0; o >>= 1) t += __shfl_xor(t, o);
-            if (lane == 0 && t) atomicAdd(Ip->ctr + c, t);
+        for (int o = 32; o > 0; o >>= 1)
+#pragma unroll
+            for (int c = 0; c < kNCtr; ++c) v[c] += __shfl_xor(v[c], o);
+        if (lane == 0) {
+            unsigned long long *ctr = Ip->ctr;
+#pragma unroll
+            for (int c = 0; c < kNCtr; ++c)
+                if (v[c]) atomicAdd(ctr + c, v[c]);
         }
     }
     // transition counts: rank offset inside the set, totals of the sets this block needs;
