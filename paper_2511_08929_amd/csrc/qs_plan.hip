@@ -212,26 +212,28 @@ __device__ __forceinline__ uint32_t mask_list(uint64_t m, uint16_t *list, uint32
     return *nlist;
 }
 
-// Sub-cycled leptons of the merged step (QED_SUBCYCLE), one block per lepton streaming block,
-// between the streaming and the processing launches.  The block gathers the leptons its
-// streaming block flagged (branch bit without a transition), runs all sub-steps of each on full
-// waves, and books their photons per round: the rounds with a photon in the lepton's sub-step
-// word, its transition bit if it has one, and the block's photon counts per round and in all and
-// its event counts added to the streaming pass's.  Every lepton is finished here (its state after
+// Sub-cycled leptons of the merged step (QED_SUBCYCLE), `split` blocks per lepton streaming block
+// (each over an equal share of its mask words, at most kBlock slots), between the streaming and
+// the processing launches.  A block gathers the leptons of its share that the streaming pass
+// flagged (branch bit without a transition), runs all sub-steps of each on full waves, and books
+// their photons per round: the rounds with a photon in the lepton's sub-step word, its transition
+// bit if it has one, and its photon counts per round and in all and its event counts added
+// atomically to the streaming block's (the order of the photons comes from the processing pass's
+// ranks, not from these sums).  Every lepton is finished here (its state after
 // the sub-steps stored), and the momentum and P-vector of each photon its sub-steps make are kept
 // in its slot's staging entries, which the processing pass copies to the photons' places.
 // Its waves hold long dependent chains (the sub-steps of one lepton run one after the other), so it
 // is held to two waves per SIMD in FP64 (one otherwise) and three in FP32.
 template <class R, int FLD>
 __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 ? 3 : 2)))
-k_plan_sub(const InstDev<R> *inst, PlanDev P, TablesDev T)
+k_plan_sub(const InstDev<R> *inst, PlanDev P, TablesDev T, int split)
 {
     extern __shared__ unsigned char smem_raw[];
     R *lds = reinterpret_cast<R *>(smem_raw);
     __shared__ uint16_t list[kExpandWords * 64];
     __shared__ uint32_t nlist, wtot[kBlock / 64];
     __shared__ unsigned red[kSubRounds + 3][kBlock / 64];
-    const int b = blockIdx.x;
+    const int b = blockIdx.x / split, q = blockIdx.x - b * split;
     const SegDev sg = P.seg[P.bseg[b]];
     const InstDev<R> *Ip = inst + P.binst[b];
     const LepDev<R> L = sg.kind == 0 ? Ip->E : Ip->P;
@@ -239,15 +241,23 @@ k_plan_sub(const InstDev<R> *inst, PlanDev P, TablesDev T)
     const StepDev S = localize(Ip->S);
     const FieldDev F = Ip->F;
     uint64_t *mask = P.mask + sg.mask_off;
-    stage_rates<R>(T, 0, lds);
     const int64_t n = *L.count;
     const int64_t B = block_len(n, sg.nb);
     const int64_t start = (int64_t)(b - sg.b0) * B, end = start + B < n ? start + B : n;
+    // this block's share of the streaming block's mask words: [w0, w1)
+    const int64_t wl = cdiv(end, 64), wq = cdiv(B >> 6, split);
+    const int64_t w0 = (start >> 6) + q * wq < wl ? (start >> 6) + q * wq : wl;
+    const int64_t w1 = w0 + wq < wl ? w0 + wq : wl;
     LCount c;
-    for (int64_t c0 = start >> 6; c0 < cdiv(end, 64); c0 += kExpandWords) {
-        const int64_t c1 = c0 + kExpandWords < cdiv(end, 64) ? c0 + kExpandWords : cdiv(end, 64);
+    bool staged = false;                               // block-uniform: the rate rows are in LDS
+    for (int64_t c0 = w0; c0 < w1; c0 += kExpandWords) {
+        const int64_t c1 = c0 + kExpandWords < w1 ? c0 + kExpandWords : w1;
         const int64_t cw = c0 + threadIdx.x;
         const uint32_t nl = mask_list(cw < c1 ? mask[sg.nchunks + cw] & ~mask[cw] : 0ull, list, wtot, &nlist);
+        if (nl && !staged) {
+            stage_rates<R>(T, 0, lds);
+            staged = true;
+        }
         for (uint32_t j = threadIdx.x; j < nl; j += kBlock) {
             const int64_t i = c0 * 64 + list[j];
             const V3<R> x = ldx(L.x, i);
@@ -300,7 +310,9 @@ k_plan_sub(const InstDev<R> *inst, PlanDev P, TablesDev T)
         }
         __syncthreads();
     }
-    // the block's bookkeeping (this block alone writes these entries of its streaming block)
+    if (!staged) return;                               // no flagged lepton in this share: nothing to add
+    // the block's bookkeeping, added to its streaming block's entries (the other blocks of the
+    // streaming block add theirs)
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
 #pragma unroll
     for (int k2 = 0; k2 < kSubRounds + 3; ++k2) {
@@ -315,16 +327,15 @@ k_plan_sub(const InstDev<R> *inst, PlanDev P, TablesDev T)
 #pragma unroll
         for (int w = 0; w < kBlock / 64; ++w) t += red[threadIdx.x][w];
         tot[threadIdx.x] = t;
-        if (threadIdx.x < kSubRounds) P.bsub[(int64_t)b * kSubRounds + threadIdx.x] += t;
-        else if (threadIdx.x == kSubRounds) P.bctr[(int64_t)b * kNCtr + C_CHI] += t;
-        else if (threadIdx.x == kSubRounds + 1) P.bctr[(int64_t)b * kNCtr + C_PROB] += t;
-        else P.bctr[(int64_t)b * kNCtr + C_NORM] += t;
+        uint32_t *dst = threadIdx.x < kSubRounds ? P.bsub + (int64_t)b * kSubRounds + threadIdx.x
+                        : P.bctr + (int64_t)b * kNCtr + (threadIdx.x == kSubRounds ? C_CHI : threadIdx.x == kSubRounds + 1 ? C_PROB : C_NORM);
+        if (t) atomicAdd(dst, t);
     }
     __syncthreads();
     if (threadIdx.x == 0) {
         unsigned ph = 0;
         for (int r = 0; r < kSubRounds; ++r) ph += tot[r];
-        P.bcnt[b] += ph;
+        if (ph) atomicAdd(P.bcnt + b, ph);
     }
 }
 
@@ -617,10 +628,10 @@ __global__ void __launch_bounds__(kBlock) k_plan_process(const InstDev<R> *inst,
 #pragma unroll
                         for (int r = 0; r < kSubRounds; ++r)
                             for (int w = 0; w < wid; ++w) sub_pos[r][threadIdx.x] += sub_wt[r][w];
-                        const V3<R> x = ldx(Ls.x, i);
                         if ((wsub >> 16) != 0) {
                             // sub-cycled: the sub-step launch finished the lepton and kept the
                             // momentum and P-vector of each of its photons
+                            const V3<R> x = ldx(Ls.x, i);
                             for (int r = 0; r < kSubRounds; ++r)
                                 if ((wsub >> r) & 1u) {
                                     const int64_t q = (int64_t)(sub_off[r] + sub_pos[r][threadIdx.x]);
@@ -633,20 +644,11 @@ __global__ void __launch_bounds__(kBlock) k_plan_process(const InstDev<R> *inst,
                                     }
                                 }
                         } else {
-                            // one step (the emission the streaming pass decided): its photon is in round 0
-                            StepDev S0 = S;
-                            S0.sub_round = 0;
-                            V3<R> p = ld3(Ls.p, i), s = ld3(Ls.s, i);
-                            V3<R> E, B;
-                            eval_fields<R, FLD>(F, (double)x.x, (double)x.y, S0.t + S0.dt, E, B);
-                            const LDecide<R> d = lepton_decide<R>(S0, Tl, lds, Ls.species, i, p, s, E, B);
-                            V3<R> k, Pv;
-                            if (lepton_substep<R>(S0, Tl, Ls.species, i, 0, d, p, s, k, Pv, nullptr)) {
-                                const int64_t q = (int64_t)(sub_off[0] + sub_pos[0][threadIdx.x]);
-                                if (q < bk.nfit) store_photon<R>(Ip->G, S0, Ls.species, i, bk.base + q, x, k, Pv, c_ret);
-                            }
-                            st3(Ls.p, i, p);
-                            st3(Ls.s, i, s);
+                            // one step (the emission the streaming pass decided, its branch in the
+                            // mask as in the plain path): its photon is in round 0
+                            const int64_t q = (int64_t)(sub_off[0] + sub_pos[0][threadIdx.x]);
+                            const bool br = (mask[sg.nchunks + (i >> 6)] >> (i & 63)) & 1ull;
+                            emit_item<R, FLD>(Ls, Ip->G, F, S, Tl, lds, i, br, q < bk.nfit ? bk.base + q : -1, c_ret);
                         }
                     }
                     __syncthreads();
@@ -680,6 +682,7 @@ struct qed_plan_s {
     uint32_t *d_sub;           // sub-cycling: the sub-step word of every slot of those lepton sets
     void *d_stage;             // ... and the photons of each slot's sub-steps (kStage values of R)
     int sub;                   // some instance sub-cycles
+    int sub_split;             // sub-step blocks per lepton streaming block (kBlock slots or fewer each)
     hipStream_t side;          // sub-cycling: the sub-step launch runs here, beside the photon pass
     hipEvent_t fork, join;
     uint32_t *d_bctr;
@@ -843,6 +846,12 @@ qed_status plan_create(qed_tables T, int n, const qed_instance *in, int ppb, int
         e = hipMalloc((void **)&p->d_sub, sizeof(uint32_t) * (words > 0 ? words : 1));
         if (e == hipSuccess) e = hipMalloc(&p->d_stage, sizeof(R) * kStage * (words > 0 ? words : 1));
         if (e == hipSuccess) e = hipMalloc((void **)&p->d_bsub, sizeof(uint32_t) * kSubRounds * (nblk_lep > 0 ? nblk_lep : 1));
+        // a streaming block's slots are split over sub-step blocks of kBlock slots at most, so each
+        // thread takes the sub-steps of one flagged lepton and small sets still spread over the chip
+        int64_t bmax = 64;
+        for (const SegDev &sgm : seg)
+            if (sgm.kind != 2) bmax = std::max<int64_t>(bmax, block_len(sgm.nchunks * 64, sgm.nb));
+        p->sub_split = (int)cdiv(bmax, kBlock);
         // default priority, like every stream of the library
         if (e == hipSuccess) e = hipStreamCreateWithFlags(&p->side, hipStreamNonBlocking);
         if (e == hipSuccess) e = hipEventCreateWithFlags(&p->fork, hipEventDisableTiming);
@@ -982,7 +991,8 @@ template <class R> qed_status plan_step(qed_plan p, hipStream_t st)
         QS_CHECK(hipStreamWaitEvent(p->side, p->fork, 0));
         auto sk = p->fv == kFldGeneral ? k_plan_sub<R, kFldGeneral> : p->fv == kFldRotating ? k_plan_sub<R, kFldRotating>
                                                                                             : k_plan_sub<R, kFldPlain>;
-        QS_LAUNCH(K_PLAN_SUB, sk, dim3(p->nblk_lep), dim3(kBlock), p->lds, p->side, inst, P, p->T->dev);
+        QS_LAUNCH(K_PLAN_SUB, sk, dim3(p->nblk_lep * p->sub_split), dim3(kBlock), p->lds, p->side, inst, P, p->T->dev,
+                  p->sub_split);
         QS_CHECK(hipEventRecord(p->join, p->side));
     }
     if (p->nblk > p->nblk_lep) {
