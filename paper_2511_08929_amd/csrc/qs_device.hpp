@@ -182,11 +182,52 @@ __device__ inline Bessel3 bessel3_scaled(double x, const double *nodes)
     return o;
 }
 
+// Below x = 1 in FP64: the ascending series K_nu = (pi / (2 sin nu pi)) (I_-nu - I_nu), with
+// I_mu = sum_k (x/2)^(2k+mu) / (k! Gamma(k+mu+1)) and IntK_1/3(x) = pi/sqrt3 - int_0^x K_1/3 from the
+// term-wise integrals 2 (x/2)^(2k+mu+1) / ((2k+mu+1) k! Gamma(k+mu+1)), each of the three divided
+// by pi/sqrt3 (sin(pi/3) = sin(2 pi/3)).  Eleven terms: on (0, 1] the three functions and their
+// ratios are within 4e-15 relative of their values to 30 digits, where the trapezoid sum needs
+// 23 to 70 nodes with an exponential each (the collapse of most emissions is at small x).
+template <int M3> __device__ __forceinline__ void small_series64(double h, double lh, double rg, double &s, double &j)
+{
+    constexpr double mu = (double)M3 / 3.0;          // mu = M3 / 3
+    const double h2 = h * h;
+    double t = rg * exp(mu * lh);                    // (x/2)^mu / Gamma(mu + 1)
+    s = t;
+    j = t * h * (2.0 / (mu + 1.0));
+#pragma unroll
+    for (int k = 1; k < 11; ++k) {
+        t *= h2 * (1.0 / ((double)k * ((double)k + mu)));
+        s += t;
+        j += t * h * (2.0 / (2.0 * (double)k + mu + 1.0));
+    }
+}
+
+__device__ __forceinline__ void bessel_small64(double x, double &k13, double &k23, double &ik)
+{
+    const double h = 0.5 * x, lh = log(h);
+    double sm2, jm2, sm1, jm1, sp1, jp1, sp2, jp2;
+    small_series64<-2>(h, lh, 1.0 / 2.678938534707747634, sm2, jm2);      // 1 / Gamma(1/3)
+    small_series64<-1>(h, lh, 1.0 / 1.354117939426400417, sm1, jm1);      // 1 / Gamma(2/3)
+    small_series64<1>(h, lh, 1.0 / 0.8929795115692492112, sp1, jp1);      // 1 / Gamma(4/3)
+    small_series64<2>(h, lh, 1.0 / 0.9027452929509336113, sp2, jp2);      // 1 / Gamma(5/3)
+    k13 = sm1 - sp1;
+    k23 = sm2 - sp2;
+    ik = 1.0 - (jm1 - jp1);
+}
+
 // Ratios K_1/3 / K_2/3 and IntK_1/3 / K_2/3 at x: all the spin and polarization collapse needs.
 template <class R> __device__ __forceinline__ void bessel_ratios(double x, const void *nodes, R &K1, R &I);
 
 template <> __device__ __forceinline__ void bessel_ratios<double>(double x, const void *nodes, double &K1, double &I)
 {
+    if (x < 1.0) {
+        double k13, k23, ik;
+        bessel_small64(fmax(x, 1e-300), k13, k23, ik);
+        K1 = k13 / k23;
+        I = ik / k23;
+        return;
+    }
     const Bessel3 b = bessel3_scaled(x, (const double *)nodes);
     K1 = b.k13 / b.k23;
     I = b.ik / b.k23;
@@ -290,6 +331,14 @@ template <class R> __device__ __forceinline__ void bessel_abs(double x, const vo
 template <> __device__ __forceinline__ void bessel_abs<double>(double x, const void *nodes, double &K13, double &K23,
                                                                double &IK)
 {
+    if (x < 1.0) {
+        constexpr double c = 1.813799364234217851;  // pi / sqrt3
+        bessel_small64(fmax(x, 1e-300), K13, K23, IK);
+        K13 *= c;
+        K23 *= c;
+        IK *= c;
+        return;
+    }
     const Bessel3 b = bessel3_scaled(x, (const double *)nodes);
     const double e = x < 700.0 ? exp(-x) : 0.0;
     K13 = b.k13 * e;
