@@ -41,12 +41,15 @@ def gtab32(q):
     return q.Tables(precision=q.QED_F32)
 
 
-def _sim(q, tab, w, cap_e, cap_p, cap_g, flags, merged=False, k_retire=None):
+def _sim(q, tab, w, cap_e, cap_p, cap_g, flags, merged=False, k_retire=None, ppb=0):
     from paper_2511_08929_amd.sim import Simulation
     f = q.make_fields(w.field_kind, E0=w.E0, B0=w.B0, a0=w.a0, phase_len=w.phase_len)
-    return Simulation(tab, cap_e=cap_e, cap_p=cap_p, cap_g=cap_g, track=w.track, fields=f, dt=w.dt, eps_r=EPS,
-                      seed=w.seed, flags=flags, k_retire=w.k_retire if k_retire is None else k_retire,
-                      merged=merged)
+    sim = Simulation(tab, cap_e=cap_e, cap_p=cap_p, cap_g=cap_g, track=w.track, fields=f, dt=w.dt, eps_r=EPS,
+                     seed=w.seed, flags=flags, k_retire=w.k_retire if k_retire is None else k_retire,
+                     merged=merged)
+    if merged and ppb:
+        sim.set_launch_config(particles_per_block=ppb)
+    return sim
 
 
 def _workload(n, dt, seed=41, B0=(0.0, 0.0, 160.0), E0=(0.0, 40.0, 0.0)):
@@ -157,12 +160,13 @@ def test_subcycle_rejected_with_other_decisions(q, gtab64):
                 sim.step()
 
 
-def _run_both(q, tab, w, cap_e, cap_p, cap_g, flags, steps, every=0, k_retire=None):
-    """the same run through the per-species calls and through the merged step"""
+def _run_both(q, tab, w, cap_e, cap_p, cap_g, flags, steps, every=0, k_retire=None, ppb=0):
+    """the same run through the per-species calls and through the merged step (with ppb
+    particles per streaming block, 0: the library's default)"""
     import torch
     out = []
     for merged in (False, True):
-        sim = _sim(q, tab, w, cap_e, cap_p, cap_g, flags, merged=merged, k_retire=k_retire)
+        sim = _sim(q, tab, w, cap_e, cap_p, cap_g, flags, merged=merged, k_retire=k_retire, ppb=ppb)
         sim.e.load(w.x, w.p, w.s)
         for k in range(steps):
             sim.step()
@@ -174,23 +178,25 @@ def _run_both(q, tab, w, cap_e, cap_p, cap_g, flags, steps, every=0, k_retire=No
     return out
 
 
-@pytest.mark.parametrize("prec,cap_per_lepton", [("fp64", 80), ("fp32", 80), ("fp64", 1)])
-def test_plan_subcycle_equals_per_species(q, gtab64, gtab32, prec, cap_per_lepton):
+@pytest.mark.parametrize("prec,cap_per_lepton,ppb,n", [("fp64", 80, 0, 1000), ("fp32", 80, 0, 1000), ("fp64", 1, 0, 1000),
+                                                     ("fp64", 80, 1024, 1000), ("fp32", 80, 2048, 3000)])
+def test_plan_subcycle_equals_per_species(q, gtab64, gtab32, prec, cap_per_lepton, ppb, n):
     """The merged step's sub-cycling (the streaming pass flags the leptons with several sub-steps,
     the sub-step launch runs them, keeps their photons and counts them per round, the processing
     pass copies the photons to their places) equals the per-species calls (16 rounds of three
-    launches) bit for bit: 1000 leptons with 1 to 16 sub-steps, 4 steps, every photon kept; and
+    launches) bit for bit: n leptons with 1 to 16 sub-steps, 4 steps, every photon kept; and
     with a photon store of one slot per lepton, which overflows, so both drop
-    the same photons (the latest rounds' first)."""
+    the same photons (the latest rounds' first).  With 1024 and 2048 leptons per streaming block
+    the sub-step launch splits each streaming block over 4 and 6 blocks, which add their counts
+    to the streaming block's atomically."""
     tab = gtab64 if prec == "fp64" else gtab32
-    n = 1000
     w = _workload(n, dt=0.5)
     if prec == "fp32":
         w.x, w.p, w.s = (a.astype(np.float32).astype(np.float64) for a in (w.x, w.p, w.s))
     flags = (q.QED_ALL & ~q.QED_PAIR) | q.QED_SUBCYCLE
-    (a, ca), (b, cb) = _run_both(q, tab, w, n, 1, cap_per_lepton * n, flags, 4, k_retire=0.0)
-    print(prec, cap_per_lepton, "per-species", ca, "merged", cb)
-    assert ca == cb and ca["n_emit"] > 2000
+    (a, ca), (b, cb) = _run_both(q, tab, w, n, 1, cap_per_lepton * n, flags, 4, k_retire=0.0, ppb=ppb)
+    print(prec, cap_per_lepton, ppb, n, "per-species", ca, "merged", cb)
+    assert ca == cb and ca["n_emit"] > 2 * n
     if cap_per_lepton == 1:
         assert ca["n_capacity_overflow"] > 0
     else:
