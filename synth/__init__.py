@@ -114,15 +114,18 @@ def c3_grid(nx: int = 4096, ny: int = 1024, a0: float = 200.0, noise: float = 0.
 
 def c3(n: int = 1 << 26, seed: int = 3, steps: int = 1000, nx: int = 4096, ny: int = 1024,
        grid_seed: int = 3) -> Workload:
-    """Grid-interpolated fields: electrons uniform over the periodic box of the c3_grid snapshot
-    (16 per cell at full size), gamma ~ LogUniform(10, 1e4), isotropic directions and unit spins,
-    dt = dx/2, 1000 steps, both channels; photons below 21 m c^2 are retired (chi_gamma stays below
-    0.05 in fields up to about 2 a0 plus the noise).  The field array is in extra['grid']."""
+    """Grid-interpolated fields: electrons seeded cell by cell over the periodic box of the c3_grid
+    snapshot, as a PIC code creates them (electron i in cell floor(i nx ny / n) of the row-major
+    order, uniform within it: 16 per cell at full size), gamma ~ LogUniform(10, 1e4), isotropic
+    directions and unit spins, dt = dx/2, 1000 steps, both channels; photons below 21 m c^2 are
+    retired (chi_gamma stays below 0.05 in fields up to about 2 a0 plus the noise).  The field
+    array is in extra['grid']."""
     rng = np.random.default_rng(seed)
     grid, dx = c3_grid(nx, ny, seed=grid_seed)
+    cell = (np.arange(n, dtype=np.int64) * (nx * ny)) // n
     x = np.zeros((3, n))
-    x[0] = rng.uniform(0.0, nx * dx, n)
-    x[1] = rng.uniform(0.0, ny * dx, n)
+    x[0] = ((cell % nx) + rng.uniform(0.0, 1.0, n)) * dx
+    x[1] = ((cell // nx) + rng.uniform(0.0, 1.0, n)) * dx
     gam = np.exp(rng.uniform(math.log(10.0), math.log(1e4), n))
     p = random_unit_vectors(rng, n) * np.sqrt(gam * gam - 1.0)
     s = random_unit_vectors(rng, n)
