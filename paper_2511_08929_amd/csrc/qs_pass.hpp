@@ -699,10 +699,23 @@ struct GCount { unsigned chi = 0, norm = 0, ret = 0, prob = 0, step = 0, qed = 0
 // once: decisions at mask[w], branch (plus) at mask[nchunks + w].
 constexpr int kPhoTile = 1024;
 
-template <class R, int TILE = kPhoTile> struct PhoQueue {
+// What the queue keeps of a candidate for phase 2's fields (QK): its x, from which phase 2
+// evaluates the plane-wave or rotating field again at little cost (plain and rotating variants);
+// its x and y (the general variant in FP64); or, in single precision, the E and B phase 1
+// evaluated, so that phase 2 gathers no grid corners again (same values; the 16 KB more of LDS
+// per block still leave the general variant its three blocks per compute unit, which the 48 KB
+// more in FP64 would not).
+enum : int { kQueueX = 0, kQueueXY = 1, kQueueEB = 2 };
+template <class R, int FLD> constexpr int queue_kind()
+{
+    return FLD != kFldGeneral ? kQueueX : (sizeof(R) == 4 ? kQueueEB : kQueueXY);
+}
+
+template <class R, int TILE = kPhoTile, int QK = kQueueX> struct PhoQueue {
     uint32_t idx[TILE];
     uint64_t id[TILE];
-    R x[TILE], y[TILE];
+    R x[QK == kQueueEB ? 1 : TILE], y[QK == kQueueXY ? TILE : 1];
+    R eb[QK == kQueueEB ? 6 : 1][QK == kQueueEB ? TILE : 1];   // Ex, Ey, Ez, Bx, By, Bz
     R k[3][TILE];                  // the candidates' momenta, read once in phase 1
     unsigned long long bits[2][TILE / 64];
     uint32_t n;
@@ -739,7 +752,8 @@ __device__ __forceinline__ void photon_tile_load(const PhoDev<R> &G, int64_t til
 // flight during phase 2; otherwise the tile loads its own.
 template <class R, int FLD, int TILE = kPhoTile, bool PREF = false>
 __device__ __forceinline__ void photon_tile(const PhoDev<R> &G, const FieldDev &F, const StepDev &S, const TablesDev &T,
-                                            const R *lds, PhoQueue<R, TILE> &Q, int64_t tile, int64_t tend,
+                                            const R *lds, PhoQueue<R, TILE, queue_kind<R, FLD>()> &Q, int64_t tile,
+                                            int64_t tend,
                                             uint64_t *mask, int64_t nchunks, GCount &c, TileIn<R, TILE> *pre = nullptr,
                                             int64_t next = -1, int64_t next_end = -1)
 {
@@ -764,8 +778,10 @@ __device__ __forceinline__ void photon_tile(const PhoDev<R> &G, const FieldDev &
         const int64_t base = tile + (threadIdx.x & ~63) + (int64_t)u * kBlock;
         if (base >= tend) break;                      // wave-uniform
         const int64_t i = base + lane;
+        constexpr int QK = queue_kind<R, FLD>();
         bool cand = false;
         R xq = (R)0, yq = (R)0;
+        V3<R> Eq = {}, Bq = {};
         if (idv[u] != 0) {
             const V3<R> k = kv[u];
             const R k0r = sqrt_r(dot(k, k));
@@ -795,7 +811,9 @@ __device__ __forceinline__ void photon_tile(const PhoDev<R> &G, const FieldDev &
                 if (FLD != kFldGeneral || (finite3(E) && finite3(Bf))) cand = photon_candidate<R>(S, k0r, E, Bf);
                 else ++c.nonfin;                          // no QED in a non-finite grid field
                 xq = x.x;
-                if (FLD == kFldGeneral) yq = x.y;
+                yq = x.y;
+                Eq = E;
+                Bq = Bf;
             }
         }
         const uint64_t m = __ballot(cand);
@@ -806,8 +824,13 @@ __device__ __forceinline__ void photon_tile(const PhoDev<R> &G, const FieldDev &
             const uint32_t r = wbase + (uint32_t)__popcll(m & ((1ull << lane) - 1ull));
             Q.idx[r] = (uint32_t)(i - tile);
             Q.id[r] = idv[u];
-            Q.x[r] = xq;
-            if (FLD == kFldGeneral) Q.y[r] = yq;
+            if constexpr (QK == kQueueEB) {
+                Q.eb[0][r] = Eq.x; Q.eb[1][r] = Eq.y; Q.eb[2][r] = Eq.z;
+                Q.eb[3][r] = Bq.x; Q.eb[4][r] = Bq.y; Q.eb[5][r] = Bq.z;
+            } else {
+                Q.x[r] = xq;
+                if constexpr (QK == kQueueXY) Q.y[r] = yq;
+            }
             Q.k[0][r] = kv[u].x;
             Q.k[1][r] = kv[u].y;
             Q.k[2][r] = kv[u].z;
@@ -826,7 +849,13 @@ __device__ __forceinline__ void photon_tile(const PhoDev<R> &G, const FieldDev &
         const V3<R> k = {Q.k[0][j], Q.k[1][j], Q.k[2][j]};
         const double k0 = (double)sqrt_r(dot(k, k));
         V3<R> E, Bf;
-        eval_fields<R, FLD>(F, (double)Q.x[j], FLD == kFldGeneral ? (double)Q.y[j] : 0.0, S.t + S.dt, E, Bf);
+        if constexpr (queue_kind<R, FLD>() == kQueueEB) {
+            E = {Q.eb[0][j], Q.eb[1][j], Q.eb[2][j]};
+            Bf = {Q.eb[3][j], Q.eb[4][j], Q.eb[5][j]};
+        } else {
+            eval_fields<R, FLD>(F, (double)Q.x[j], queue_kind<R, FLD>() == kQueueXY ? (double)Q.y[j] : 0.0, S.t + S.dt,
+                                E, Bf);
+        }
         const PDecide<R> d = photon_decide<R>(S, T, lds, id, k, k0, P, E, Bf);
         if (!d.active) continue;
         c.nonfin += d.nonfinite;

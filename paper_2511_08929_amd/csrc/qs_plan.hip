@@ -101,7 +101,7 @@ k_plan_main(const InstDev<R> *inst, PlanDev P, TablesDev T, int b_first)
     extern __shared__ unsigned char smem_raw[];
     R *lds = reinterpret_cast<R *>(smem_raw);
     constexpr int TILE = pho_tile<PV>();
-    __shared__ PhoQueue<R, TILE> Q;
+    __shared__ PhoQueue<R, TILE, queue_kind<R, FLD>()> Q;
     __shared__ unsigned tot[kNCtr + 1];
     const int b = b_first + blockIdx.x;
     const int sj = P.bseg[b];

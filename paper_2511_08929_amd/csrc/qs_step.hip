@@ -90,7 +90,7 @@ __global__ void __launch_bounds__(kBlock) k_photon_main(PhoDev<R> G, FieldDev F,
     const StepDev S = localize(S0);
     extern __shared__ unsigned char smem_raw[];
     R *lds = reinterpret_cast<R *>(smem_raw);
-    __shared__ PhoQueue<R> Q;
+    __shared__ PhoQueue<R, kPhoTile, queue_kind<R, FLD>()> Q;
     stage_rates<R>(T, 1, lds);
     const int64_t n = *G.count_prev;
     const int64_t B = block_len(n, gridDim.x);
