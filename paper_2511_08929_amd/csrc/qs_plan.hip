@@ -213,7 +213,8 @@ __device__ __forceinline__ uint32_t mask_list(uint64_t m, uint16_t *list, uint32
 }
 
 // Sub-cycled leptons of the merged step (QED_SUBCYCLE), `split` blocks per lepton streaming block
-// (each over an equal share of its mask words, at most kBlock slots), between the streaming and
+// (each over an equal share of its mask words: kBlock slots at most, unless the launch would exceed
+// its cap on blocks), between the streaming and
 // the processing launches.  A block gathers the leptons of its share that the streaming pass
 // flagged (branch bit without a transition), runs all sub-steps of each on full waves, and books
 // their photons per round: the rounds with a photon in the lepton's sub-step word, its transition
@@ -847,11 +848,14 @@ qed_status plan_create(qed_tables T, int n, const qed_instance *in, int ppb, int
         if (e == hipSuccess) e = hipMalloc(&p->d_stage, sizeof(R) * kStage * (words > 0 ? words : 1));
         if (e == hipSuccess) e = hipMalloc((void **)&p->d_bsub, sizeof(uint32_t) * kSubRounds * (nblk_lep > 0 ? nblk_lep : 1));
         // a streaming block's slots are split over sub-step blocks of kBlock slots at most, so each
-        // thread takes the sub-steps of one flagged lepton and small sets still spread over the chip
+        // thread takes the sub-steps of one flagged lepton and small sets still spread over the chip;
+        // at most kSubGrid blocks in all (large sets: a few rounds of slots per block instead of
+        // hundreds of thousands of blocks that mostly find no flagged lepton)
+        constexpr int64_t kSubGrid = 8192;
         int64_t bmax = 64;
         for (const SegDev &sgm : seg)
             if (sgm.kind != 2) bmax = std::max<int64_t>(bmax, block_len(sgm.nchunks * 64, sgm.nb));
-        p->sub_split = (int)cdiv(bmax, kBlock);
+        p->sub_split = (int)std::max<int64_t>(1, std::min<int64_t>(cdiv(bmax, kBlock), kSubGrid / std::max<int64_t>(1, nblk_lep)));
         // default priority, like every stream of the library
         if (e == hipSuccess) e = hipStreamCreateWithFlags(&p->side, hipStreamNonBlocking);
         if (e == hipSuccess) e = hipEventCreateWithFlags(&p->fork, hipEventDisableTiming);

@@ -207,6 +207,34 @@ def test_plan_subcycle_equals_per_species(q, gtab64, gtab32, prec, cap_per_lepto
         np.testing.assert_array_equal(u, v)
 
 
+def test_plan_subcycle_capped_launch_equals_per_species(q, gtab32):
+    """2.2 million leptons at 2048 per streaming block: 1024 streaming blocks of 2176 slots, so the
+    sub-step launch's cap of 8192 blocks gives each streaming block 8 sub-step blocks of 320 slots
+    (some threads take two flagged leptons).  Two steps, every photon kept; the merged step equals
+    the per-species calls bit for bit (compared on the device)."""
+    import torch
+    n = 2_200_000
+    w = _workload(n, dt=0.5, seed=43)
+    w.x, w.p, w.s = (a.astype(np.float32).astype(np.float64) for a in (w.x, w.p, w.s))
+    flags = (q.QED_ALL & ~q.QED_PAIR) | q.QED_SUBCYCLE
+    out = []
+    for merged in (False, True):
+        sim = _sim(q, gtab32, w, n, 1, 12 * n, flags, merged=merged, k_retire=0.0, ppb=2048)
+        sim.e.load(w.x, w.p, w.s)
+        for _ in range(2):
+            sim.step()
+        torch.cuda.synchronize()
+        ng = sim.g.n()
+        t = [a for a in sim.e.x + sim.e.p + sim.e.s if a is not None]
+        t += [a[:ng] for a in sim.g.x + sim.g.k + sim.g.P if a is not None] + [sim.g.id[:ng]]
+        out.append(([a.clone() for a in t], q.counters_dict(sim.ctr)))
+        del sim
+    (a, ca), (b, cb) = out
+    print("capped sub-step launch: per-species", ca, "merged", cb)
+    assert ca == cb and ca["n_emit"] > n // 2 and ca["n_capacity_overflow"] == 0
+    assert len(a) == len(b) and all(u.shape == v.shape and torch.equal(u, v) for u, v in zip(a, b))
+
+
 def test_plan_subcycle_head_on_equals_per_species(q, gtab64):
     """Sub-cycling with pair production through the whole head-on pulse at a0 = 300 (200
     electrons, 1700 steps, compaction every 200): the merged step equals the per-species calls bit
