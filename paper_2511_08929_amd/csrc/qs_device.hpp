@@ -76,8 +76,17 @@ template <> __device__ __forceinline__ float ratio_r<float>(double num, double d
 // ------------------------------------------------------------------ Philox4x32-10
 // Salmon, Moraes, Dror, Shaw (SC'11): 10 rounds of two 32x32 -> 64 multiplies with
 // Weyl-sequence key bumps.
-__device__ __forceinline__ uint4 philox4x32_10(uint4 c, uint32_t k0, uint32_t k1)
+// PIN: the key (the step's seed, the same for every lane of a wave, so its first lane is exact)
+// is taken into scalar registers and hidden from the optimizer, so that the round keys are formed
+// by scalar adds at each call instead of once ahead of a loop; kept there, they outnumber the
+// scalar registers of the photon pass, whose hot loop then reloaded each from a vector lane.
+template <bool PIN = false> __device__ __forceinline__ uint4 philox4x32_10(uint4 c, uint32_t k0, uint32_t k1)
 {
+    if constexpr (PIN) {
+        k0 = __builtin_amdgcn_readfirstlane(k0);
+        k1 = __builtin_amdgcn_readfirstlane(k1);
+        asm volatile("" : "+s"(k0), "+s"(k1));
+    }
 #pragma unroll
     for (int r = 0; r < 10; ++r) {
         // one 32x32 -> 64-bit product per multiplier gives both halves
@@ -89,9 +98,10 @@ __device__ __forceinline__ uint4 philox4x32_10(uint4 c, uint32_t k0, uint32_t k1
     return c;
 }
 
+template <bool PIN = false>
 __device__ __forceinline__ uint4 philox_block(uint64_t seed, uint64_t id, int64_t step, uint32_t channel)
 {
-    return philox4x32_10(make_uint4((uint32_t)id, (uint32_t)(id >> 32), (uint32_t)step, channel),
+    return philox4x32_10<PIN>(make_uint4((uint32_t)id, (uint32_t)(id >> 32), (uint32_t)step, channel),
                          (uint32_t)seed, (uint32_t)(seed >> 32));
 }
 

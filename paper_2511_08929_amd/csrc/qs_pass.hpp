@@ -294,7 +294,8 @@ template <class R> struct PDecide {
     bool nonfinite;    // the P-vector is not finite: the photon is stepped as unpolarized
 };
 
-template <class R>
+// PIN: the draw's key pinned to scalar registers (philox4x32_10), in the photon pass's loop only
+template <class R, bool PIN = false>
 __device__ __forceinline__ PDecide<R> photon_decide(const StepDev &S, const TablesDev &T, const R *lds, uint64_t id,
                                                     V3<R> k, double k0, V3<R> P, V3<R> E, V3<R> B)
 {
@@ -323,7 +324,7 @@ __device__ __forceinline__ PDecide<R> photon_decide(const StepDev &S, const Tabl
     d.a = d.Wm * (R)0.5 * ((R)1 - d.x3) * dt;
     const R b = d.Wp * (R)0.5 * ((R)1 + d.x3) * dt;
     d.P = d.a + b;
-    Unif<R>::two(philox_block(S.seed, id, S.step, 2u), d.r1, d.r2);
+    Unif<R>::two(philox_block<PIN>(S.seed, id, S.step, 2u), d.r1, d.r2);
     return d;
 }
 
@@ -856,7 +857,7 @@ __device__ __forceinline__ void photon_tile(const PhoDev<R> &G, const FieldDev &
             eval_fields<R, FLD>(F, (double)Q.x[j], queue_kind<R, FLD>() == kQueueXY ? (double)Q.y[j] : 0.0, S.t + S.dt,
                                 E, Bf);
         }
-        const PDecide<R> d = photon_decide<R>(S, T, lds, id, k, k0, P, E, Bf);
+        const PDecide<R> d = photon_decide<R, true>(S, T, lds, id, k, k0, P, E, Bf);
         if (!d.active) continue;
         c.nonfin += d.nonfinite;
         ++c.qed;
