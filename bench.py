@@ -736,6 +736,9 @@ def parse_args(argv=None):
     ap.add_argument("--probe", action="store_true",
                     help="profiler run: copy calibration + one eager FP32 collision, no JSON line")
     ap.add_argument("--probe-steps", type=int, default=COLLISION_STEPS)
+    ap.add_argument("--probe-grid", action="store_true",
+                    help="profiler run: the grid workload (2^24 electrons, 200 steps, FP32) once, eagerly, "
+                         "no JSON line")
     return ap.parse_args(argv)
 
 
@@ -766,6 +769,26 @@ def probe(q, w, cfg, steps):
     log(f"probe: {steps} steps in {time.perf_counter() - t0:.2f} s, counters {q.counters_dict(sim.ctr)}")
 
 
+def probe_grid(q, n=1 << 24, steps=200):
+    """Profiler run of the grid workload as the `grid` extra sizes it, stepped eagerly."""
+    import torch
+    from paper_2511_08929_amd import autotune
+    wg = synth.c3(n=n, steps=steps)
+    fg = q.make_fields(q.QED_FIELD_GRID2D, grid=torch.as_tensor(wg.extra["grid"], device="cuda"), dx=wg.extra["dx"],
+                       dy=wg.extra["dy"])
+    col = Collision(q, q.Tables(precision=q.QED_F32), wg, autotune.DEFAULT, fields=fg, steps=steps,
+                    caps=(n + n // 2, n // 2, 24 * n))
+    sim = col.sim
+    t0 = time.perf_counter()
+    for k in range(steps):
+        sim.step()
+        if (k + 1) % COMPACT_EVERY == 0:
+            sim.compact()
+    torch.cuda.synchronize()
+    log(f"grid probe: {steps} steps in {time.perf_counter() - t0:.2f} s, counters {q.counters_dict(sim.ctr)}")
+    col.close()
+
+
 def main(argv=None):
     args = parse_args(argv)
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -789,6 +812,9 @@ def main(argv=None):
     if args.probe:
         probe(q, w, dict(autotune.DEFAULT, **({"particles_per_block": args.ppb} if args.ppb else {})),
               args.probe_steps)
+        return
+    if args.probe_grid:
+        probe_grid(q)
         return
 
     t32, t64 = q.Tables(precision=q.QED_F32), q.Tables(precision=q.QED_F64)

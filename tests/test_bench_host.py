@@ -66,6 +66,7 @@ def test_driver_argv_keeps_the_workload():
     assert bench.COLLISION_STEPS == 3000 and not hasattr(a, "time_steps")
     d = bench.parse_args([])
     assert d.steps >= 1 and d.warmup >= 0 and d.n == 1_000_000
+    assert not d.probe and not d.probe_grid and bench.parse_args(["--probe-grid"]).probe_grid
 
 
 @pytest.mark.parametrize("argv", [["--steps", "0"], ["--warmup", "-1"]])
